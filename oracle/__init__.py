@@ -1,0 +1,16 @@
+"""FP64 CPU oracle for the particle-mesh force-and-step loop.
+
+TEST INFRASTRUCTURE. Only the test suite, the package smoke check and the
+benchmark's CPU-baseline leg may import this package. The product path (the
+HIP library and its Python binding) never imports, calls or links it, and this
+package imports nothing from the product path; the two share no code.
+
+Contents
+  pm       mass assignment, exact 7-point Poisson solve, FFT solve, 5-point
+           gradient, interpolation, kick-drift-kick (paper Sects. 3.1-3.8)
+  mg       FP64 multigrid V-cycle following the paper's steps (Sects. 3.6-3.7)
+  adjoint  vector-Jacobian products of the above and the reverse leapfrog
+
+Every function is plain numpy/scipy in float64, written for readability.
+"""
+from . import pm, mg, adjoint  # noqa: F401

@@ -1,0 +1,292 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: the paper's
+worked example, closed forms, a textbook dense solve, brute force on tiny
+inputs, invariants and convergence orders.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import pm, mg
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+RNG = lambda s: np.random.Generator(np.random.PCG64(s))  # noqa: E731
+
+
+# ---------------------------------------------------------------- deposit
+
+def test_point_mass_worked_example():
+    """Paper App. D: point mass at a cell centre / cell corner."""
+    n = 8
+    rows = []
+    with open(os.path.join(GOLDEN, "point_mass_deposit.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                rows.append(line.split())
+    assert len(rows) == 4
+    for scheme, place, count, vals in rows:
+        u = np.array([[3.5, 4.5, 5.5]]) if place == "centre" else np.array([[3.0, 4.0, 5.0]])
+        rho = pm.deposit(u, n, scheme, mass=1.0)
+        nz = rho[rho != 0.0]
+        assert nz.size == int(count), (scheme, place)
+        ax = np.array([float(v) for v in vals.split(",")])
+        expect = np.sort(np.einsum("i,j,k->ijk", ax, ax, ax).ravel())
+        np.testing.assert_allclose(np.sort(nz), expect, rtol=0, atol=1e-15)
+        assert rho.sum() == pytest.approx(1.0, abs=1e-15)
+
+
+@pytest.mark.parametrize("mas", ["tsc", "cic"])
+def test_deposit_brute_force_definition(mas):
+    """Every (particle, cell) pair evaluated with the paper's piecewise window."""
+    n = 6
+    rng = RNG(11)
+    u = rng.uniform(0, n, size=(17, 3))
+    u[0] = [0.0, 5.999999, 3.0]          # on faces / near the wrap
+    u[1] = [2.5, 2.5, 2.5]               # cell centre
+    win = pm.w_tsc if mas == "tsc" else pm.w_cic
+    ref = np.zeros((n, n, n))
+    c = np.arange(n) + 0.5
+    for p in range(u.shape[0]):
+        s = [u[p, d] - c for d in range(3)]
+        s = [(x + n / 2) % n - n / 2 for x in s]     # minimum image
+        w = [win(x) for x in s]
+        ref += np.einsum("i,j,k->ijk", *w)
+    got = pm.deposit(u, n, mas, mass=1.0)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("mas", ["tsc", "cic"])
+def test_deposit_mass_conservation_and_lattice(mas):
+    n = 16
+    rng = RNG(3)
+    u = rng.uniform(0, n, size=(5000, 3))
+    rho = pm.deposit(u, n, mas)
+    assert rho.sum() == pytest.approx(n ** 3, rel=1e-12)
+    i = (np.arange(n) + 0.5)
+    lattice = np.stack(np.meshgrid(i, i, i, indexing="ij"), -1).reshape(-1, 3)
+    np.testing.assert_allclose(pm.deposit(lattice, n, mas), 1.0, atol=1e-14)
+
+
+# ---------------------------------------------------------------- interpolation
+
+@pytest.mark.parametrize("mas", ["tsc", "cic"])
+def test_interp_partition_of_unity_and_linear_exactness(mas):
+    n = 12
+    rng = RNG(5)
+    u = rng.uniform(3, 9, size=(200, 3))          # away from the periodic seam
+    const = np.full((n, n, n, 3), 2.5)
+    np.testing.assert_allclose(pm.interp(u, const, mas), 2.5, atol=1e-13)
+    c = np.arange(n) + 0.5
+    lin = np.stack(np.meshgrid(c, c, c, indexing="ij"), -1)   # g_c = cell centre
+    np.testing.assert_allclose(pm.interp(u, lin, mas), u, atol=1e-12)
+
+
+@pytest.mark.parametrize("mas", ["tsc", "cic"])
+def test_interp_is_transpose_of_deposit(mas):
+    n = 10
+    rng = RNG(7)
+    u = rng.uniform(0, n, size=(300, 3))
+    q = rng.standard_normal(300)
+    g = rng.standard_normal((n, n, n))
+    lhs = np.sum(pm.deposit_charges(u, n, q, mas) * g)
+    rhs = np.sum(q * pm.interp(u, g, mas))
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+# ---------------------------------------------------------------- Poisson
+
+def _dense_laplacian(n, h):
+    """7-point periodic Laplacian as an explicit matrix, from index arithmetic."""
+    N = n ** 3
+    A = np.zeros((N, N))
+    for i in range(n):
+        for j in range(n):
+            for k in range(n):
+                r = (i * n + j) * n + k
+                A[r, r] = -6.0 / h ** 2
+                for di, dj, dk in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+                    c = (((i + di) % n) * n + (j + dj) % n) * n + (k + dk) % n
+                    A[r, c] += 1.0 / h ** 2
+    return A
+
+
+def test_exact7_matches_dense_solve_8cubed():
+    n, h = 8, 1.0 / 8
+    f = RNG(13).standard_normal((n, n, n))
+    A = _dense_laplacian(n, h)
+    ones = np.ones((n ** 3, 1))
+    phi_dense = np.linalg.solve(A + ones @ ones.T, (f - f.mean()).ravel())
+    np.testing.assert_allclose(pm.solve_exact7(f, h).ravel(), phi_dense, rtol=0, atol=1e-12 * np.abs(phi_dense).max())
+    # the oracle's stencil is the dense operator
+    np.testing.assert_allclose(pm.laplacian7(f, h).ravel(), A @ f.ravel(), atol=1e-10)
+
+
+def test_exact7_single_mode_closed_form():
+    n, h = 32, 1.0 / 32
+    i = np.arange(n)
+    m = (3, 5, 1)
+    theta = 2 * np.pi * (m[0] * i[:, None, None] + m[1] * i[None, :, None] + m[2] * i[None, None, :]) / n
+    f = np.cos(theta)
+    lam = sum(2.0 * (np.cos(2 * np.pi * md / n) - 1.0) for md in m) / h ** 2
+    np.testing.assert_allclose(pm.solve_exact7(f, h), f / lam, atol=1e-14)
+
+
+def test_fft_solver_single_mode_closed_form():
+    """Paper Sect. 3.8: phi(k) = -f(k) / (k^2 W_TSC(k)^2), W_TSC = prod sinc^3(omega/2)."""
+    n, h = 32, 1.0 / 32
+    i = np.arange(n)
+    m = (2, -7, 4)
+    theta = 2 * np.pi * (m[0] * i[:, None, None] + m[1] * i[None, :, None] + m[2] * i[None, None, :]) / n
+    f = np.sin(theta)
+    k = [2 * np.pi * md for md in m]
+    k2 = sum(kd * kd for kd in k)
+    w = 1.0
+    for kd in k:
+        x = kd * h / 2
+        w *= (np.sin(x) / x) ** 3
+    np.testing.assert_allclose(pm.solve_fft(f, h, 3), -f / (k2 * w * w), atol=1e-15)
+    # Nyquist mode: omega = pi, sinc(pi/2) = 2/pi
+    f = np.cos(np.pi * i)[:, None, None] * np.ones((n, n, n))
+    expect = -f / ((np.pi * n) ** 2 * (2 / np.pi) ** 6)
+    np.testing.assert_allclose(pm.solve_fft(f, h, 3), expect, atol=1e-15)
+
+
+def test_multigrid_converges_to_exact7_and_rate():
+    n, h = 32, 1.0 / 32
+    f = RNG(17).standard_normal((n, n, n))
+    f -= f.mean()
+    u, hist = mg.solve(f, h, tol=1e-12, max_cycles=30)
+    ref = pm.solve_exact7(f, h)
+    assert np.linalg.norm(u - ref) / np.linalg.norm(ref) < 1e-10
+    rates = [hist[i] / hist[i + 1] for i in range(1, 5)]
+    # paper App. C: about a factor 10 per V-cycle without over-relaxation
+    assert all(4.0 < r < 60.0 for r in rates), rates
+
+
+def test_multigrid_restriction_is_scaled_prolongation_transpose():
+    rng = RNG(19)
+    r = rng.standard_normal((8, 8, 8))
+    v = rng.standard_normal((4, 4, 4))
+    assert np.sum(mg.restrict(r, "fw") * v) == pytest.approx(np.sum(r * mg.prolong(v)) / 8.0, rel=1e-13)
+    # paper's prolongation weights: a single coarse value spreads as (1,3,3,1)/4 per axis
+    e = np.zeros((4, 4, 4))
+    e[1, 1, 1] = 1.0
+    p = mg.prolong(e)
+    assert p[2, 2, 2] == pytest.approx(27 / 64)
+    assert p[1, 2, 2] == pytest.approx(9 / 64)
+    assert p[1, 1, 2] == pytest.approx(3 / 64)
+    assert p[1, 1, 1] == pytest.approx(1 / 64)
+    assert p.sum() == pytest.approx(8.0)
+
+
+# ---------------------------------------------------------------- gradient
+
+def test_gradient_single_mode_multiplier_and_identities():
+    n, h = 32, 1.0 / 32
+    i = np.arange(n)
+    m = 5
+    omega = 2 * np.pi * m / n
+    phi = np.sin(omega * i)[None, :, None] * np.ones((n, n, n))
+    g = pm.gradient(phi, h)
+    mult = ((4.0 / 3.0) * np.sin(omega) - (1.0 / 6.0) * np.sin(2 * omega)) / h
+    np.testing.assert_allclose(g[..., 1], -mult * np.cos(omega * i)[None, :, None] * np.ones((n, n, n)), atol=1e-12)
+    np.testing.assert_allclose(g[..., 0], 0.0, atol=1e-13)
+    assert np.abs(pm.gradient(np.full((n, n, n), 3.0), h)).max() < 1e-12
+    rng = RNG(23)
+    a, b = rng.standard_normal((2, n, n, n))
+    for ax in range(3):
+        assert np.sum(pm.derivative(a, h, ax) * b) == pytest.approx(-np.sum(a * pm.derivative(b, h, ax)), rel=1e-12)
+
+
+def test_gradient_fourth_order_convergence():
+    errs = []
+    for n in (16, 32):
+        h = 1.0 / n
+        x = (np.arange(n) + 0.5) * h
+        phi = np.exp(np.sin(2 * np.pi * x))[:, None, None] * np.ones((n, n, n))
+        exact = -(2 * np.pi * np.cos(2 * np.pi * x) * np.exp(np.sin(2 * np.pi * x)))
+        errs.append(np.abs(pm.gradient(phi, h)[:, 0, 0, 0] - exact).max())
+    assert 12.0 < errs[0] / errs[1] < 20.0, errs
+
+
+# ---------------------------------------------------------------- force chain
+
+@pytest.mark.parametrize("solver", ["exact7", "fft"])
+@pytest.mark.parametrize("mas", ["tsc", "cic"])
+def test_self_force_zero_and_pair_antisymmetry(solver, mas):
+    n = 16
+    rng = RNG(29)
+    one = rng.uniform(0, n, size=(1, 3))
+    a1 = pm.accel(one, n, 1.0, solver, mas, mass=1.0)
+    assert np.abs(a1).max() < 1e-12
+    two = rng.uniform(0, n, size=(2, 3))
+    a2 = pm.accel(two, n, 1.0, solver, mas, mass=1.0)
+    assert np.abs(a2).max() > 1e-6
+    np.testing.assert_allclose(a2[0], -a2[1], atol=1e-12 * np.abs(a2).max())
+    many = rng.uniform(0, n, size=(400, 3))
+    am = pm.accel(many, n, 1.0, solver, mas)
+    assert np.abs(am.sum(axis=0)).max() < 1e-10 * np.abs(am).sum()
+
+
+def test_point_mass_far_field_is_attractive():
+    """A test mass is pulled towards a point mass (paper App. D)."""
+    n = 32
+    src = np.array([[16.5, 16.5, 16.5]])
+    probe = np.array([[16.5 + 6.0, 16.5, 16.5]])
+    u = np.concatenate([src, probe])
+    acc = pm.accel(u, n, 1.0, "exact7", "tsc", mass=np.array(1.0))
+    assert acc[1, 0] < 0 and abs(acc[1, 1]) < 1e-12 and abs(acc[1, 2]) < 1e-12
+
+
+# ---------------------------------------------------------------- integrator
+
+def test_tau_closed_form_numbers():
+    assert pm.tau_eds(0.1, 0.11) == pytest.approx(0.294328, rel=2e-6)
+    a = 0.02 + 0.0196 * np.arange(51)
+    total = sum(pm.tau_eds(a0, a1) for a0, a1 in zip(a[:-1], a[1:]))
+    assert total == pytest.approx(2 * (0.02 ** -0.5 - 1.0), rel=1e-12)
+    # d^2 D / d tau^2 = 1.5 a Omega_m D for D = a: check by finite differences of a(tau)
+    a0, eps = 0.3, 1e-4
+    # a(tau) = (a0^{-1/2} - tau/2)^{-2}
+    at = lambda t: (a0 ** -0.5 - t / 2) ** -2  # noqa: E731
+    d2 = (at(eps) - 2 * at(0) + at(-eps)) / eps ** 2
+    assert d2 == pytest.approx(1.5 * a0 * a0, rel=1e-6)
+
+
+def test_kdk_time_reversal():
+    n = 16
+    rng = RNG(31)
+    x = rng.uniform(0, 1, size=(2000, 3))
+    v = 0.01 * rng.standard_normal((2000, 3))
+    a_list = [0.1, 0.12, 0.14, 0.16]
+    xf, vf, _ = pm.run(x, v, a_list, n)
+    xb, vb, _ = pm.run(xf, vf, a_list[::-1], n)
+    assert pm.periodic_distance(xb, x).max() < 1e-12
+    np.testing.assert_allclose(vb, v, atol=1e-12)
+
+
+def _plane_wave(n, a0, a1, steps):
+    """Zel'dovich plane wave x = q + a Psi0(q), Psi0 = -(1/k) sin(k q) x (shell crossing at a=1)."""
+    k = 2 * np.pi
+    c = (np.arange(n) + 0.5) / n
+    q = np.stack(np.meshgrid(c, c, c, indexing="ij"), -1).reshape(-1, 3)
+    psi0 = np.zeros_like(q)
+    psi0[:, 0] = -np.sin(k * q[:, 0]) / k
+    x = pm.wrap01(q + a0 * psi0)
+    v = np.sqrt(a0) * a0 * psi0
+    a_list = list(np.linspace(a0, a1, steps + 1))
+    xf, _, _ = pm.run(x, v, a_list, n, solver="exact7", mas="tsc")
+    exact = pm.wrap01(q + a1 * psi0)
+    d = xf - exact
+    d -= np.round(d)
+    return np.abs(d[:, 0]).max() / (a1 / k), np.abs(d[:, 1:]).max()
+
+
+def test_zeldovich_plane_wave_before_shell_crossing():
+    e16, t16 = _plane_wave(16, 0.1, 0.5, 40)
+    e32, t32 = _plane_wave(32, 0.1, 0.5, 40)
+    assert t16 < 1e-12 and t32 < 1e-12          # transverse motion is exactly zero
+    assert e32 < 1e-2                            # relative to the displacement amplitude
+    assert 2.5 < e16 / e32 < 6.0, (e16, e32)     # second order in h
