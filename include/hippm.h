@@ -1,0 +1,175 @@
+/*
+ * hippm.h -- C ABI of the MI355X (gfx950) particle-mesh force-and-step library.
+ *
+ * The library implements the particle-mesh loop of Breton, "PySCo: A fast
+ * particle-mesh N-body code for modified gravity simulations in Python"
+ * (arXiv:2410.20501): mass assignment (Sect. 3.5), the Poisson solve by
+ * multigrid (Sects. 3.6-3.7) or FFT (Sect. 3.8), the central finite-difference
+ * gradient (Sect. 3.5, gradient table), interpolation back to particles
+ * (Sect. 3.5) and the kick-drift-kick leapfrog (Sect. 3.4), in the
+ * supercomoving units of Sect. 3.1.
+ *
+ * Conventions shared by every entry point
+ *   - Periodic unit box with n cells per side, cell size h = 1/n; cell (i,j,k)
+ *     has its centre at ((i,j,k) + 1/2) h. Scalar grids are float [n][n][n]
+ *     row-major (k fastest); vector grids are float [n][n][n][3]; particle
+ *     arrays are float [np][3] (Sect. 3.2).
+ *   - Positions come in one of two forms (pm_poskind):
+ *       PM_POS_BOX     pos[np][3] in box units, [0, 1);
+ *       PM_POS_CELLOFF pos[np][3] is the in-cell offset in [0, 1) (cell units)
+ *                      and cell[np] the int32 linear index (i*n + j)*n + k.
+ *     Velocities are in box units per unit of supercomoving time in both forms.
+ *   - All array pointers are DEVICE pointers owned by the caller; the library
+ *     never frees them. Calls are asynchronous on `stream` (a hipStream_t; NULL
+ *     is the null stream); outputs are valid once the stream has reached the
+ *     call. Host pointers (params, stats) are read or written before return.
+ *   - A pm_ctx owns every scratch buffer (density and force grids, multigrid
+ *     hierarchy, FFT spectrum, sort arrays, reduction partials). Scratch is
+ *     allocated by pm_create, except the FFT spectrum and the sort arrays,
+ *     which are allocated on the first call that needs them; later calls do
+ *     not allocate. A context serves one stream at a time: calls that overlap
+ *     on different streams race on its scratch.
+ *   - Return value: PM_OK (0); a warning (> 0) when a result was produced but a
+ *     solver target was missed; an error (< 0) when nothing usable was
+ *     produced. Argument and shape errors are detected before any launch and
+ *     leave every buffer untouched. pm_last_error(ctx) describes the most
+ *     recent error or warning of that context.
+ */
+#ifndef HIPPM_H
+#define HIPPM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pm_ctx pm_ctx;
+typedef void *pm_stream; /* hipStream_t */
+
+enum pm_status {
+  PM_OK = 0,
+  PM_WARN_NOT_CONVERGED = 1, /* multigrid stopped at max_cycles above tol */
+  PM_WARN_FLOOR = 2,         /* multigrid stagnated at the FP32 rounding floor */
+  PM_ERR_ARG = -1,           /* null pointer, bad enum, negative count */
+  PM_ERR_SHAPE = -2,         /* grid size or particle count not supported */
+  PM_ERR_NOMEM = -3,         /* device allocation failed */
+  PM_ERR_HIP = -4,           /* a HIP runtime call failed (text in pm_last_error) */
+  PM_ERR_NONFINITE = -5      /* a non-finite value was found where checked */
+};
+
+enum pm_mas { PM_CIC = 2, PM_TSC = 3 };                    /* p of the window W^p */
+enum pm_order { PM_DEPOSIT_ATOMIC = 0, PM_DEPOSIT_SORTED = 1 };
+enum pm_poskind { PM_POS_BOX = 0, PM_POS_CELLOFF = 1 };
+enum pm_restrict { PM_RESTRICT_FW = 0, PM_RESTRICT_AVG = 1 };
+enum pm_solver { PM_SOLVER_MG = 0, PM_SOLVER_FFT = 1 };
+enum pm_guess { PM_GUESS_JACOBI = 0, PM_GUESS_WARM = 1 };
+
+/* Multigrid settings (paper Sect. 3.7.1). */
+typedef struct {
+  int pre;            /* pre-smoothing red-black Gauss-Seidel sweeps (>= 0) */
+  int post;           /* post-smoothing sweeps (>= 0) */
+  float omega;        /* over-relaxation factor; 1 = plain Gauss-Seidel */
+  float tol;          /* stop when ||f - L phi||_2 / ||f||_2 < tol */
+  int max_cycles;     /* at most this many V-cycles (1 .. 63) */
+  int restrict_kind;  /* pm_restrict */
+  int guess;          /* pm_guess: Jacobi step -h^2 f/6, or phi as given */
+  int fixed_cycles;   /* > 0: run exactly this many cycles, no convergence test
+                         and no host synchronisation (graph-capturable) */
+} pm_mg_params;
+
+typedef struct {
+  int cycles;         /* V-cycles run */
+  int status;         /* PM_OK, PM_WARN_NOT_CONVERGED or PM_WARN_FLOOR */
+  double relres[64];  /* relres[0] of the starting guess, relres[c] after cycle c
+                         (not filled when fixed_cycles > 0) */
+} pm_mg_stats;
+
+typedef struct {
+  int mas;            /* pm_mas for deposit and interpolation */
+  int order;          /* pm_order of the deposit */
+  int solver;         /* pm_solver */
+  int fft_deconv;     /* FFT solver: window power to deconvolve (0, 2, 3) */
+  double omega_m;     /* matter density parameter (1 = Einstein-de Sitter) */
+  pm_mg_params mg;
+  int timing;         /* 1: record per-stage times into pm_step_stats (adds events) */
+} pm_step_params;
+
+typedef struct {
+  pm_mg_stats mg;
+  float ms_drift, ms_deposit, ms_solve, ms_gradient, ms_interp; /* when timing */
+} pm_step_stats;
+
+/* Default parameters: TSC, atomic deposit, multigrid 2/2 sweeps, omega 1,
+ * tol 1e-6, 50 cycles, full-weighting restriction, Jacobi guess, Omega_m 1. */
+void pm_default_step_params(pm_step_params *p);
+
+/* Create a context for an n^3 grid and up to np_max particles.
+ * n must be even, 8 <= n <= 1024. flags: reserved, pass 0.
+ * Errors: PM_ERR_ARG, PM_ERR_SHAPE, PM_ERR_NOMEM, PM_ERR_HIP. */
+int pm_create(pm_ctx **ctx, int n, int64_t np_max, int flags);
+void pm_destroy(pm_ctx *ctx);
+const char *pm_last_error(const pm_ctx *ctx);
+
+/* Mass assignment (paper Sect. 3.5): rho[c] = w sum_p prod_d W(u_pd - (c_d + 1/2))
+ * with the CIC (8 cells) or TSC (27 cells) window, u = position in cell units,
+ * and particle weight w = n^3 / np (mean density 1, the paper's normalisation
+ * when np = n^3). rho is overwritten.
+ * order PM_DEPOSIT_ATOMIC: one thread per particle, FP32 atomic adds (the sum
+ *   order, hence the last bits, may differ between runs).
+ * order PM_DEPOSIT_SORTED: particles are bucketed by cell (a counting sort into
+ *   context scratch; the caller's arrays are not reordered), then every cell
+ *   gathers the contributions of the particles in its 27 (8) neighbour cells
+ *   with one write per cell. Contributions are summed in 64-bit fixed point,
+ *   so the result is bitwise identical for any particle order and any run. */
+int pm_deposit(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np,
+               int poskind, int mas, int order, float *rho, pm_stream stream);
+
+/* Multigrid Poisson solve of the seven-point system (Sects. 3.5-3.7, 3.9):
+ *   (sum of 6 neighbours - 6 phi) / h^2 = coef (rho - mean rho)
+ * with coef = (3/2) a Omega_m for the supercomoving Poisson equation.
+ * phi: in = starting guess when params->guess == PM_GUESS_WARM; out = the
+ * solution with its mean removed. V-cycles of red-black Gauss-Seidel
+ * smoothing, restriction to a grid twice as coarse, recursion down to at most
+ * 16 cells per side, trilinear prolongation-correction. Unless fixed_cycles is
+ * set, the residual norm is checked after every cycle (one host sync each).
+ * Returns PM_OK, or a warning if tol was not reached; stats may be NULL. */
+int pm_solve_mg(pm_ctx *ctx, const float *rho, float coef, float *phi,
+                const pm_mg_params *params, pm_mg_stats *stats, pm_stream stream);
+
+/* FFT Poisson solve (Sect. 3.8, 'FFT'): phi(k) = -coef rho(k) / (k^2 W(k)^2),
+ * W = [prod_d sinc(k_d h / 2)]^deconv with deconv = 0 (none), 2 (CIC) or 3
+ * (TSC); phi(0) = 0. n must be a power of two (16 .. 512). */
+int pm_solve_fft(pm_ctx *ctx, const float *rho, float coef, int deconv, float *phi,
+                 pm_stream stream);
+
+/* Acceleration grid g = -grad phi with the central difference of the given
+ * number of points (3, 5 or 7; paper gradient table). g is [n][n][n][3]. */
+int pm_gradient(pm_ctx *ctx, const float *phi, int points, float *g, pm_stream stream);
+
+/* Interpolation (Sect. 3.5): acc[p] = sum_c W(u_p - (c + 1/2)) g[c], same window
+ * as the deposit. acc is [np][3]. */
+int pm_interp(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, int poskind,
+              int mas, const float *g, float *acc, pm_stream stream);
+
+/* Accelerations of the particles at scale factor a: deposit, solve with
+ * coef = 1.5 a Omega_m, 5-point gradient, interpolation. phi is the potential
+ * (warm-start input when the multigrid guess is PM_GUESS_WARM; output). */
+int pm_accel(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, int poskind,
+             double a, const pm_step_params *params, float *phi, float *acc,
+             pm_step_stats *stats, pm_stream stream);
+
+/* One kick-drift-kick step (Sect. 3.4) from scale factor a0 to a1 in
+ * Einstein-de Sitter supercomoving time, tau = 2 (a0^-1/2 - a1^-1/2):
+ *   v += (tau/2) acc;  x = wrap(x + tau v);  acc = accel(x, a1);  v += (tau/2) acc.
+ * acc: in = accelerations at (x, a0); out = at (x_new, a1). pos/cell are
+ * updated in place (offsets carried into the cell index for PM_POS_CELLOFF).
+ * phi: warm start in, potential at a1 out. */
+int pm_kdk(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, int64_t np, int poskind,
+           double a0, double a1, const pm_step_params *params, float *phi, float *acc,
+           pm_step_stats *stats, pm_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HIPPM_H */

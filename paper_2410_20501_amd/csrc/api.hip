@@ -1,0 +1,322 @@
+// C ABI entry points: argument validation, context and scratch management,
+// and the orchestration of the particle-mesh stages on the caller's stream.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "internal.h"
+
+int pm_fail(pm_ctx *ctx, int code, const std::string &msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+int pm_hip_check(pm_ctx *ctx, hipError_t e, const char *what) {
+  if (e == hipSuccess) return PM_OK;
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return pm_fail(ctx, e == hipErrorOutOfMemory ? PM_ERR_NOMEM : PM_ERR_HIP, m);
+}
+
+namespace {
+
+bool valid_mas(int m) { return m == PM_CIC || m == PM_TSC; }
+bool valid_poskind(int k) { return k == PM_POS_BOX || k == PM_POS_CELLOFF; }
+
+int check_particles(pm_ctx *ctx, const void *pos, const int32_t *cell, int64_t np, int poskind) {
+  if (np < 0) return pm_fail(ctx, PM_ERR_ARG, "negative particle count");
+  if (!valid_poskind(poskind)) return pm_fail(ctx, PM_ERR_ARG, "bad poskind");
+  if (np > 0 && !pos) return pm_fail(ctx, PM_ERR_ARG, "null pos");
+  if (np > 0 && poskind == PM_POS_CELLOFF && !cell)
+    return pm_fail(ctx, PM_ERR_ARG, "null cell array with PM_POS_CELLOFF");
+  return PM_OK;
+}
+
+int check_mg(pm_ctx *ctx, const pm_mg_params *p) {
+  if (!p) return pm_fail(ctx, PM_ERR_ARG, "null multigrid params");
+  if (p->pre < 0 || p->post < 0 || p->pre > 16 || p->post > 16)
+    return pm_fail(ctx, PM_ERR_ARG, "sweep counts must be in [0, 16]");
+  if (!(p->omega > 0.0f && p->omega < 2.0f)) return pm_fail(ctx, PM_ERR_ARG, "omega must be in (0, 2)");
+  if (p->fixed_cycles < 0 || p->fixed_cycles > 1000)
+    return pm_fail(ctx, PM_ERR_ARG, "fixed_cycles must be in [0, 1000]");
+  if (p->fixed_cycles == 0 && (p->max_cycles < 1 || p->max_cycles > 63))
+    return pm_fail(ctx, PM_ERR_ARG, "max_cycles must be in [1, 63]");
+  if (p->fixed_cycles == 0 && !(p->tol >= 0.0f)) return pm_fail(ctx, PM_ERR_ARG, "bad tol");
+  if (p->restrict_kind != PM_RESTRICT_FW && p->restrict_kind != PM_RESTRICT_AVG)
+    return pm_fail(ctx, PM_ERR_ARG, "bad restrict_kind");
+  if (p->guess != PM_GUESS_JACOBI && p->guess != PM_GUESS_WARM)
+    return pm_fail(ctx, PM_ERR_ARG, "bad guess");
+  return PM_OK;
+}
+
+int check_step(pm_ctx *ctx, const pm_step_params *p) {
+  if (!p) return pm_fail(ctx, PM_ERR_ARG, "null step params");
+  if (!valid_mas(p->mas)) return pm_fail(ctx, PM_ERR_ARG, "bad mas");
+  if (p->order != PM_DEPOSIT_ATOMIC && p->order != PM_DEPOSIT_SORTED)
+    return pm_fail(ctx, PM_ERR_ARG, "bad deposit order");
+  if (p->solver != PM_SOLVER_MG && p->solver != PM_SOLVER_FFT)
+    return pm_fail(ctx, PM_ERR_ARG, "bad solver");
+  if (p->solver == PM_SOLVER_MG) return check_mg(ctx, &p->mg);
+  if (p->fft_deconv != 0 && p->fft_deconv != 2 && p->fft_deconv != 3)
+    return pm_fail(ctx, PM_ERR_ARG, "fft_deconv must be 0, 2 or 3");
+  return PM_OK;
+}
+
+int ensure_sort_scratch(pm_ctx *ctx, int64_t np) {
+  if (np > INT32_MAX) return pm_fail(ctx, PM_ERR_SHAPE, "sorted deposit supports < 2^31 particles");
+  const int64_t ncell = (int64_t)ctx->n * ctx->n * ctx->n;
+  if (!ctx->cell_count) {
+    const size_t len = (size_t)ncell + 1;
+    const int64_t nblk = scan_blocks_needed((int64_t)len);
+    if (hipMalloc(&ctx->cell_count, sizeof(int32_t) * len) != hipSuccess ||
+        hipMalloc(&ctx->cell_start, sizeof(int32_t) * len) != hipSuccess ||
+        hipMalloc(&ctx->scan_partial, sizeof(int32_t) * (size_t)nblk) != hipSuccess)
+      return pm_fail(ctx, PM_ERR_NOMEM, "sort scratch allocation failed");
+  }
+  if (ctx->sort_cap < np) {
+    if (ctx->perm) (void)hipFree(ctx->perm);
+    if (ctx->pcell) (void)hipFree(ctx->pcell);
+    ctx->perm = ctx->pcell = nullptr;
+    const int64_t cap = std::max<int64_t>(np, ctx->np_max);
+    if (hipMalloc(&ctx->perm, sizeof(int32_t) * (size_t)std::max<int64_t>(cap, 1)) != hipSuccess ||
+        hipMalloc(&ctx->pcell, sizeof(int32_t) * (size_t)std::max<int64_t>(cap, 1)) != hipSuccess)
+      return pm_fail(ctx, PM_ERR_NOMEM, "sort scratch allocation failed");
+    ctx->sort_cap = cap;
+  }
+  return PM_OK;
+}
+
+int deposit_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, int poskind,
+                 int mas, int order, float *rho, hipStream_t s) {
+  const int n = ctx->n;
+  const int64_t ncell = (int64_t)n * n * n;
+  const float mass = np > 0 ? (float)((double)ncell / (double)np) : 0.0f;
+  if (order == PM_DEPOSIT_SORTED) {
+    int st = ensure_sort_scratch(ctx, np);
+    if (st != PM_OK) return st;
+    PM_HIP(ctx, launch_sort_by_cell(ctx, pos, cell, np, poskind, s));
+    PM_HIP(ctx, launch_deposit_pull(ctx, pos, np, poskind, mas, mass, rho, s));
+    return PM_OK;
+  }
+  PM_HIP(ctx, hipMemsetAsync(rho, 0, sizeof(float) * (size_t)ncell, s));
+  PM_HIP(ctx, launch_deposit_atomic(pos, cell, np, poskind, mas, n, mass, rho, s));
+  return PM_OK;
+}
+
+int solve_impl(pm_ctx *ctx, const pm_step_params *p, const float *rho, float coef, float *phi,
+               pm_mg_stats *st, hipStream_t s) {
+  if (p->solver == PM_SOLVER_FFT) return pm_fft_solve(ctx, rho, coef, p->fft_deconv, phi, s);
+  return pm_mg_solve(ctx, rho, coef, phi, &p->mg, st, s);
+}
+
+// deposit -> solve -> gradient -> interp (+ optional kick on vel)
+int accel_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, int poskind,
+               double a, const pm_step_params *p, float *phi, float *acc, float *vel, float kick,
+               pm_step_stats *stats, hipStream_t s, bool timing) {
+  if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[1], s));
+  int st = deposit_impl(ctx, pos, cell, np, poskind, p->mas, p->order, ctx->rho, s);
+  if (st != PM_OK) return st;
+  if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[2], s));
+  const float coef = (float)(1.5 * a * p->omega_m);
+  const int sst = solve_impl(ctx, p, ctx->rho, coef, phi, stats ? &stats->mg : nullptr, s);
+  if (sst < 0) return sst;
+  if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[3], s));
+  PM_HIP(ctx, launch_gradient(phi, ctx->n, 5, ctx->g, s));
+  if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[4], s));
+  PM_HIP(ctx, launch_interp(pos, cell, np, poskind, p->mas, ctx->n, ctx->g, acc, vel, kick, s));
+  if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[5], s));
+  return sst;
+}
+
+void fill_timing(pm_ctx *ctx, pm_step_stats *stats, bool with_drift) {
+  if (!stats) return;
+  if (hipEventSynchronize(ctx->ev[5]) != hipSuccess) return;
+  float t = 0.f;
+  stats->ms_drift = 0.f;
+  if (with_drift && hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[1]) == hipSuccess) stats->ms_drift = t;
+  if (hipEventElapsedTime(&t, ctx->ev[1], ctx->ev[2]) == hipSuccess) stats->ms_deposit = t;
+  if (hipEventElapsedTime(&t, ctx->ev[2], ctx->ev[3]) == hipSuccess) stats->ms_solve = t;
+  if (hipEventElapsedTime(&t, ctx->ev[3], ctx->ev[4]) == hipSuccess) stats->ms_gradient = t;
+  if (hipEventElapsedTime(&t, ctx->ev[4], ctx->ev[5]) == hipSuccess) stats->ms_interp = t;
+}
+
+}  // namespace
+
+extern "C" {
+
+void pm_default_step_params(pm_step_params *p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->mas = PM_TSC;
+  p->order = PM_DEPOSIT_ATOMIC;
+  p->solver = PM_SOLVER_MG;
+  p->fft_deconv = 3;
+  p->omega_m = 1.0;
+  p->mg.pre = 2;
+  p->mg.post = 2;
+  p->mg.omega = 1.0f;
+  p->mg.tol = 1e-6f;
+  p->mg.max_cycles = 50;
+  p->mg.restrict_kind = PM_RESTRICT_FW;
+  p->mg.guess = PM_GUESS_JACOBI;
+  p->mg.fixed_cycles = 0;
+  p->timing = 0;
+}
+
+int pm_create(pm_ctx **out, int n, int64_t np_max, int flags) {
+  if (!out) return PM_ERR_ARG;
+  *out = nullptr;
+  (void)flags;
+  if (np_max < 0) return PM_ERR_ARG;
+  if (n < 8 || n > 1024 || (n & 1)) return PM_ERR_SHAPE;
+  pm_ctx *ctx = new pm_ctx();  // value-initialised: every pointer starts null
+  ctx->n = n;
+  ctx->np_max = np_max;
+  if (hipGetDevice(&ctx->device) != hipSuccess) {
+    delete ctx;
+    return PM_ERR_HIP;
+  }
+  const size_t ncell = (size_t)n * n * n;
+  int st = PM_OK;
+  if (hipMalloc(&ctx->rho, sizeof(float) * ncell) != hipSuccess ||
+      hipMalloc(&ctx->g, 3 * sizeof(float) * ncell) != hipSuccess ||
+      hipMalloc(&ctx->red_partial, 2 * sizeof(double) * RED_BLOCKS) != hipSuccess ||
+      hipMalloc(&ctx->red_result, 4 * sizeof(double)) != hipSuccess ||
+      hipMalloc(&ctx->mean_f, 4 * sizeof(float)) != hipSuccess ||
+      hipHostMalloc(&ctx->host_result, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+    st = PM_ERR_NOMEM;
+  if (st == PM_OK) st = pm_mg_setup(ctx);
+  for (int i = 0; st == PM_OK && i < 8; ++i)
+    if (hipEventCreate(&ctx->ev[i]) != hipSuccess) st = PM_ERR_HIP;
+  if (st != PM_OK) {
+    pm_destroy(ctx);
+    return st;
+  }
+  *out = ctx;
+  return PM_OK;
+}
+
+void pm_destroy(pm_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipDeviceSynchronize();
+  auto fr = [](void *p) {
+    if (p) (void)hipFree(p);
+  };
+  fr(ctx->rho);
+  fr(ctx->g);
+  fr(ctx->red_partial);
+  fr(ctx->red_result);
+  fr(ctx->mean_f);
+  if (ctx->host_result) (void)hipHostFree(ctx->host_result);
+  for (int l = 1; l < ctx->nlevels; ++l) {
+    fr(ctx->lev[l].u);
+    fr(ctx->lev[l].f);
+  }
+  fr(ctx->spec);
+  fr(ctx->twiddle);
+  fr(ctx->fft_tab);
+  fr(ctx->cell_count);
+  fr(ctx->cell_start);
+  fr(ctx->perm);
+  fr(ctx->pcell);
+  fr(ctx->scan_partial);
+  for (int i = 0; i < 8; ++i)
+    if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+  delete ctx;
+}
+
+const char *pm_last_error(const pm_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int pm_deposit(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, int poskind,
+               int mas, int order, float *rho, pm_stream stream) {
+  if (!ctx) return PM_ERR_ARG;
+  int st = check_particles(ctx, pos, cell, np, poskind);
+  if (st != PM_OK) return st;
+  if (!valid_mas(mas)) return pm_fail(ctx, PM_ERR_ARG, "bad mas");
+  if (order != PM_DEPOSIT_ATOMIC && order != PM_DEPOSIT_SORTED)
+    return pm_fail(ctx, PM_ERR_ARG, "bad deposit order");
+  if (!rho) return pm_fail(ctx, PM_ERR_ARG, "null rho");
+  return deposit_impl(ctx, pos, cell, np, poskind, mas, order, rho, (hipStream_t)stream);
+}
+
+int pm_solve_mg(pm_ctx *ctx, const float *rho, float coef, float *phi,
+                const pm_mg_params *params, pm_mg_stats *stats, pm_stream stream) {
+  if (!ctx) return PM_ERR_ARG;
+  if (!rho || !phi) return pm_fail(ctx, PM_ERR_ARG, "null grid");
+  int st = check_mg(ctx, params);
+  if (st != PM_OK) return st;
+  if (!std::isfinite(coef)) return pm_fail(ctx, PM_ERR_NONFINITE, "non-finite coef");
+  return pm_mg_solve(ctx, rho, coef, phi, params, stats, (hipStream_t)stream);
+}
+
+int pm_solve_fft(pm_ctx *ctx, const float *rho, float coef, int deconv, float *phi,
+                 pm_stream stream) {
+  if (!ctx) return PM_ERR_ARG;
+  if (!rho || !phi) return pm_fail(ctx, PM_ERR_ARG, "null grid");
+  if (deconv != 0 && deconv != 2 && deconv != 3)
+    return pm_fail(ctx, PM_ERR_ARG, "deconv must be 0, 2 or 3");
+  if (!std::isfinite(coef)) return pm_fail(ctx, PM_ERR_NONFINITE, "non-finite coef");
+  return pm_fft_solve(ctx, rho, coef, deconv, phi, (hipStream_t)stream);
+}
+
+int pm_gradient(pm_ctx *ctx, const float *phi, int points, float *g, pm_stream stream) {
+  if (!ctx) return PM_ERR_ARG;
+  if (!phi || !g) return pm_fail(ctx, PM_ERR_ARG, "null grid");
+  if (points != 3 && points != 5 && points != 7)
+    return pm_fail(ctx, PM_ERR_ARG, "points must be 3, 5 or 7");
+  PM_HIP(ctx, launch_gradient(phi, ctx->n, points, g, (hipStream_t)stream));
+  return PM_OK;
+}
+
+int pm_interp(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, int poskind,
+              int mas, const float *g, float *acc, pm_stream stream) {
+  if (!ctx) return PM_ERR_ARG;
+  int st = check_particles(ctx, pos, cell, np, poskind);
+  if (st != PM_OK) return st;
+  if (!valid_mas(mas)) return pm_fail(ctx, PM_ERR_ARG, "bad mas");
+  if (!g || (np > 0 && !acc)) return pm_fail(ctx, PM_ERR_ARG, "null pointer");
+  PM_HIP(ctx, launch_interp(pos, cell, np, poskind, mas, ctx->n, g, acc, nullptr, 0.f,
+                            (hipStream_t)stream));
+  return PM_OK;
+}
+
+int pm_accel(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, int poskind,
+             double a, const pm_step_params *params, float *phi, float *acc,
+             pm_step_stats *stats, pm_stream stream) {
+  if (!ctx) return PM_ERR_ARG;
+  int st = check_particles(ctx, pos, cell, np, poskind);
+  if (st != PM_OK) return st;
+  st = check_step(ctx, params);
+  if (st != PM_OK) return st;
+  if (!phi || (np > 0 && !acc)) return pm_fail(ctx, PM_ERR_ARG, "null pointer");
+  if (!(a > 0.0) || !std::isfinite(a)) return pm_fail(ctx, PM_ERR_ARG, "scale factor must be > 0");
+  hipStream_t s = (hipStream_t)stream;
+  const bool timing = params->timing && stats;
+  st = accel_impl(ctx, pos, cell, np, poskind, a, params, phi, acc, nullptr, 0.f, stats, s, timing);
+  if (st >= 0 && timing) fill_timing(ctx, stats, false);
+  return st;
+}
+
+int pm_kdk(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, int64_t np, int poskind,
+           double a0, double a1, const pm_step_params *params, float *phi, float *acc,
+           pm_step_stats *stats, pm_stream stream) {
+  if (!ctx) return PM_ERR_ARG;
+  int st = check_particles(ctx, pos, cell, np, poskind);
+  if (st != PM_OK) return st;
+  st = check_step(ctx, params);
+  if (st != PM_OK) return st;
+  if (np > 0 && (!vel || !acc)) return pm_fail(ctx, PM_ERR_ARG, "null vel or acc");
+  if (!phi) return pm_fail(ctx, PM_ERR_ARG, "null phi");
+  if (!(a0 > 0.0) || !(a1 > 0.0) || !std::isfinite(a0) || !std::isfinite(a1))
+    return pm_fail(ctx, PM_ERR_ARG, "scale factors must be > 0");
+  hipStream_t s = (hipStream_t)stream;
+  const bool timing = params->timing && stats;
+  const double tau = 2.0 * (1.0 / std::sqrt(a0) - 1.0 / std::sqrt(a1));
+  const float half = (float)(0.5 * tau);
+  if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[0], s));
+  PM_HIP(ctx, launch_kick_drift(pos, cell, vel, acc, np, poskind, ctx->n, half, (float)tau, s));
+  st = accel_impl(ctx, pos, cell, np, poskind, a1, params, phi, acc, vel, half, stats, s, timing);
+  if (st >= 0 && timing) fill_timing(ctx, stats, true);
+  return st;
+}
+
+}  // extern "C"

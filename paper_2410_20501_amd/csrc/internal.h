@@ -1,0 +1,94 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/hippm.h"
+
+#define PM_MAX_LEVELS 12
+
+struct pm_level {
+  int n;          // cells per side
+  float *u;       // solution / error (level 0: caller's phi)
+  float *f;       // right-hand side (level 0: NULL, the source is read from rho)
+};
+
+struct pm_ctx {
+  int n;
+  int64_t np_max;
+  int device;
+  std::string err;
+  // grids
+  float *rho;            // [n^3] density scratch (pm_accel / pm_kdk)
+  float *g;              // [n^3 * 3] acceleration grid scratch
+  // multigrid hierarchy (level 0 fields are the caller's)
+  int nlevels;
+  pm_level lev[PM_MAX_LEVELS];
+  // reductions
+  double *red_partial;   // [RED_MAX_BLOCKS * 2]
+  double *red_result;    // [4] device: {sum0, sum1, mean, spare}
+  double *host_result;   // pinned [4]
+  float *mean_f;         // [1] device: FP32 mean of the current source grid
+  // FFT spectrum (lazy)
+  void *spec;            // complex float [n][n][pitch]
+  int spec_pitch;
+  float2 *twiddle;       // [n] e^{-2 pi i m / n}, m = 0 .. n-1
+  float *fft_tab;        // [2n] per-axis Green's-function tables
+  int fft_tab_key;       // which kernel the tables hold
+  // counting sort (lazy)
+  int32_t *cell_count;   // [n^3 + 1]
+  int32_t *cell_start;   // [n^3 + 1]
+  int32_t *perm;         // [np_max] particle indices bucketed by cell
+  int32_t *pcell;        // [np_max] cell of each particle
+  int32_t *scan_partial; // [SCAN_MAX_BLOCKS]
+  int64_t sort_cap;
+  // timing events
+  hipEvent_t ev[8];
+};
+
+#define RED_BLOCKS 1024
+#define RED_THREADS 256
+
+// ---------------------------------------------------------------- helpers
+int pm_fail(pm_ctx *ctx, int code, const std::string &msg);
+int pm_hip_check(pm_ctx *ctx, hipError_t e, const char *what);
+#define PM_HIP(ctx, call)                                   \
+  do {                                                      \
+    hipError_t _e = (call);                                 \
+    if (_e != hipSuccess) return pm_hip_check(ctx, _e, #call); \
+  } while (0)
+
+// ---------------------------------------------------------------- launchers
+// particles.hip
+hipError_t launch_deposit_atomic(const float *pos, const int32_t *cell, int64_t np, int poskind,
+                                 int mas, int n, float mass, float *rho, hipStream_t s);
+hipError_t launch_sort_by_cell(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np,
+                               int poskind, hipStream_t s);
+hipError_t launch_deposit_pull(pm_ctx *ctx, const float *pos, int64_t np, int poskind, int mas,
+                               float mass, float *rho, hipStream_t s);
+hipError_t launch_interp(const float *pos, const int32_t *cell, int64_t np, int poskind, int mas,
+                         int n, const float *g, float *acc, float *vel, float kick,
+                         hipStream_t s);
+hipError_t launch_kick_drift(float *pos, int32_t *cell, float *vel, const float *acc, int64_t np,
+                             int poskind, int n, float kick, float dt, hipStream_t s);
+
+// grid.hip
+hipError_t launch_gradient(const float *phi, int n, int points, float *g, hipStream_t s);
+hipError_t launch_sum_moments(const float *x, int64_t count, double *partial, double *result,
+                              float *mean_out, hipStream_t s);
+
+// mg.hip
+int pm_mg_solve(pm_ctx *ctx, const float *rho, float coef, float *phi, const pm_mg_params *p,
+                pm_mg_stats *stats, hipStream_t s);
+int pm_mg_setup(pm_ctx *ctx);
+
+// fft.hip
+int pm_fft_solve(pm_ctx *ctx, const float *rho, float coef, int deconv, float *phi,
+                 hipStream_t s);
+int pm_fft_solve_kind(pm_ctx *ctx, const float *rho, float coef, int deconv, int kind, float *phi,
+                      hipStream_t s);
+int64_t scan_blocks_needed(int64_t len);

@@ -1,0 +1,462 @@
+// Linear multigrid for the periodic seven-point Poisson problem
+// (paper Sects. 3.6-3.7.1): red-black Gauss-Seidel smoothing, residual
+// restriction to a grid of spacing 2h (full weighting = transpose of the
+// prolongation / 8, or the paper's 8-child average), recursive coarse
+// correction starting from the Jacobi guess -H^2 d_H / 6, trilinear
+// prolongation-correction with the 27/64, 9/64, 3/64, 1/64 weights, and an
+// LDS-resident coarsest-level solve.
+//
+// Every kernel reads the right-hand side as  scale * (f[c] - mean), so the
+// finest level uses the density grid directly (scale = (3/2) a Omega_m,
+// mean = the density's mean computed on the device) without materialising the
+// source term.
+#include <algorithm>
+#include <cmath>
+
+#include "internal.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kCoarseThreads = 1024;
+constexpr int kCoarseMax = 8000;  // cells held in LDS by the coarsest-level solve (20^3)
+
+__device__ __forceinline__ int wrap_index(int i, int n) {
+  i += (i < 0) ? n : 0;
+  i -= (i >= n) ? n : 0;
+  return i;
+}
+
+__device__ __forceinline__ float src_mean(const float *mean) { return mean ? *mean : 0.0f; }
+
+__device__ __forceinline__ float neighbour_sum(const float *__restrict__ u, int i, int j, int k,
+                                               int n) {
+  const size_t nn = (size_t)n * n;
+  const size_t ci = (size_t)i * nn, cj = (size_t)j * n;
+  return u[(size_t)wrap_index(i + 1, n) * nn + cj + k] + u[(size_t)wrap_index(i - 1, n) * nn + cj + k] +
+         u[ci + (size_t)wrap_index(j + 1, n) * n + k] + u[ci + (size_t)wrap_index(j - 1, n) * n + k] +
+         u[ci + cj + wrap_index(k + 1, n)] + u[ci + cj + wrap_index(k - 1, n)];
+}
+
+// u = -h^2 f / 6: one Jacobi step from a zero field (paper's first guess).
+__global__ __launch_bounds__(kThreads) void k_jacobi_guess(float *__restrict__ u,
+                                                           const float *__restrict__ f,
+                                                           float scale,
+                                                           const float *__restrict__ mean,
+                                                           int64_t count, float h2) {
+  const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (c >= count) return;
+  const float m = src_mean(mean);
+  u[c] = (-h2 / 6.0f) * (scale * (f[c] - m));
+}
+
+// One colour of a red-black Gauss-Seidel sweep: cells with (i + j + k) % 2 == colour.
+__global__ __launch_bounds__(kThreads) void k_rbgs_half(float *__restrict__ u,
+                                                        const float *__restrict__ f, float scale,
+                                                        const float *__restrict__ mean, int n,
+                                                        float h2, float omega, int colour) {
+  const int half = n >> 1;
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= (int64_t)n * n * half) return;
+  const int k2 = (int)(t % half);
+  const int64_t r = t / half;
+  const int j = (int)(r % n), i = (int)(r / n);
+  const int k = 2 * k2 + ((i + j + colour) & 1);
+  const size_t c = ((size_t)i * n + j) * n + k;
+  const float fv = scale * (f[c] - src_mean(mean));
+  const float gs = (neighbour_sum(u, i, j, k, n) - h2 * fv) * (1.0f / 6.0f);
+  u[c] = (omega == 1.0f) ? gs : fmaf(omega, gs - u[c], u[c]);
+}
+
+__device__ __forceinline__ float residual_at(const float *__restrict__ u,
+                                             const float *__restrict__ f, float scale, float m,
+                                             int i, int j, int k, int n, float inv_h2) {
+  const size_t c = ((size_t)i * n + j) * n + k;
+  const float uc = u[c];
+  // sum of neighbour differences: exact for nearby values (halves the FP32 floor)
+  const size_t nn = (size_t)n * n;
+  const size_t ci = (size_t)i * nn, cj = (size_t)j * n;
+  const float lap = (u[(size_t)wrap_index(i + 1, n) * nn + cj + k] - uc) +
+                    (u[(size_t)wrap_index(i - 1, n) * nn + cj + k] - uc) +
+                    (u[ci + (size_t)wrap_index(j + 1, n) * n + k] - uc) +
+                    (u[ci + (size_t)wrap_index(j - 1, n) * n + k] - uc) +
+                    (u[ci + cj + wrap_index(k + 1, n)] - uc) +
+                    (u[ci + cj + wrap_index(k - 1, n)] - uc);
+  return scale * (f[c] - m) - lap * inv_h2;
+}
+
+// Coarse cell (I, J, K) <- restriction of the fine residual d = f - L u.
+// Full weighting: per axis fine cells 2J-1 .. 2J+2 with weights (1, 3, 3, 1) / 8.
+// Average: the 8 children 2J, 2J+1 per axis, each with weight 1/8.
+template <int KIND>
+__global__ __launch_bounds__(kThreads) void k_residual_restrict(
+    const float *__restrict__ u, const float *__restrict__ f, float scale,
+    const float *__restrict__ mean, int n, float inv_h2, float *__restrict__ fc) {
+  const int nc = n >> 1;
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= (int64_t)nc * nc * nc) return;
+  const int K = (int)(t % nc), J = (int)((t / nc) % nc), I = (int)(t / ((int64_t)nc * nc));
+  const float m = src_mean(mean);
+  float acc = 0.0f;
+  if constexpr (KIND == PM_RESTRICT_FW) {
+    const float w[4] = {1.0f, 3.0f, 3.0f, 1.0f};
+    for (int a = 0; a < 4; ++a) {
+      const int i = wrap_index(2 * I - 1 + a, n);
+      for (int b = 0; b < 4; ++b) {
+        const int j = wrap_index(2 * J - 1 + b, n);
+        const float wab = w[a] * w[b];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int k = wrap_index(2 * K - 1 + c, n);
+          acc = fmaf(wab * w[c], residual_at(u, f, scale, m, i, j, k, n, inv_h2), acc);
+        }
+      }
+    }
+    fc[t] = acc * (1.0f / 512.0f);
+  } else {
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b)
+        for (int c = 0; c < 2; ++c)
+          acc += residual_at(u, f, scale, m, 2 * I + a, 2 * J + b, 2 * K + c, n, inv_h2);
+    fc[t] = acc * 0.125f;
+  }
+}
+
+// u_fine += P v_coarse: per axis 3/4 from the nearest coarse centre and 1/4 from
+// the next one (fine cell 2J has neighbours J, J-1; fine 2J+1 has J, J+1).
+__global__ __launch_bounds__(kThreads) void k_prolong_add(float *__restrict__ u, int n,
+                                                          const float *__restrict__ v) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= (int64_t)n * n * n) return;
+  const int k = (int)(t % n), j = (int)((t / n) % n), i = (int)(t / ((int64_t)n * n));
+  const int nc = n >> 1;
+  const int ia = i >> 1, ja = j >> 1, ka = k >> 1;
+  const int ib = wrap_index(ia + ((i & 1) ? 1 : -1), nc);
+  const int jb = wrap_index(ja + ((j & 1) ? 1 : -1), nc);
+  const int kb = wrap_index(ka + ((k & 1) ? 1 : -1), nc);
+  const size_t nn = (size_t)nc * nc;
+  auto at = [&](int x, int y, int z) { return v[(size_t)x * nn + (size_t)y * nc + z]; };
+  const float near = 0.75f, far = 0.25f;
+  const float sa = near * (near * (near * at(ia, ja, ka) + far * at(ia, ja, kb)) +
+                           far * (near * at(ia, jb, ka) + far * at(ia, jb, kb)));
+  const float sb = far * (near * (near * at(ib, ja, ka) + far * at(ib, ja, kb)) +
+                          far * (near * at(ib, jb, ka) + far * at(ib, jb, kb)));
+  u[t] += sa + sb;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// Partial sums of the squared residual and squared source.
+__global__ __launch_bounds__(RED_THREADS) void k_residual_norm(const float *__restrict__ u,
+                                                               const float *__restrict__ f,
+                                                               float scale,
+                                                               const float *__restrict__ mean,
+                                                               int n, float inv_h2,
+                                                               double *__restrict__ partial) {
+  const int64_t count = (int64_t)n * n * n;
+  const float m = src_mean(mean);
+  double s1 = 0.0, s2 = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * RED_THREADS;
+  for (int64_t t = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; t < count; t += stride) {
+    const int k = (int)(t % n), j = (int)((t / n) % n), i = (int)(t / ((int64_t)n * n));
+    const double r = residual_at(u, f, scale, m, i, j, k, n, inv_h2);
+    const double fv = scale * (f[t] - m);
+    s1 += r * r;
+    s2 += fv * fv;
+  }
+  __shared__ double l1[RED_THREADS / 64], l2[RED_THREADS / 64];
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    l1[wave] = s1;
+    l2[wave] = s2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int w = 0; w < RED_THREADS / 64; ++w) {
+      a += l1[w];
+      b += l2[w];
+    }
+    partial[2 * blockIdx.x] = a;
+    partial[2 * blockIdx.x + 1] = b;
+  }
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_pair_final(const double *__restrict__ partial,
+                                                            int nblocks,
+                                                            double *__restrict__ result) {
+  double s1 = 0.0, s2 = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += RED_THREADS) {
+    s1 += partial[2 * b];
+    s2 += partial[2 * b + 1];
+  }
+  __shared__ double l1[RED_THREADS / 64], l2[RED_THREADS / 64];
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    l1[wave] = s1;
+    l2[wave] = s2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int w = 0; w < RED_THREADS / 64; ++w) {
+      a += l1[w];
+      b += l2[w];
+    }
+    result[0] = a;
+    result[1] = b;
+  }
+}
+
+// Subtract the device-resident mean from a grid.
+__global__ __launch_bounds__(kThreads) void k_subtract_mean(float *__restrict__ u, int64_t count,
+                                                            const float *__restrict__ mean) {
+  const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (c >= count) return;
+  u[c] -= *mean;
+}
+
+__device__ double block_sum_coarse(double v, double *lds) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) lds[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < kCoarseThreads / 64; ++w) s += lds[w];
+  return s;
+}
+
+// Coarsest level: red-black Gauss-Seidel sweeps in LDS until the residual has
+// dropped by `reduction` (checked every 4 sweeps), stagnates, or max_sweeps.
+// The mean of the right-hand side and of the solution are removed.
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse_solve(
+    float *__restrict__ ug, const float *__restrict__ fg, float scale,
+    const float *__restrict__ mean, int n, float h2, float reduction, int max_sweeps) {
+  __shared__ float su[kCoarseMax];
+  __shared__ float sf[kCoarseMax];
+  __shared__ double red[kCoarseThreads / 64];
+  const int count = n * n * n;
+  const float m = src_mean(mean);
+  double fs = 0.0;
+  for (int c = threadIdx.x; c < count; c += kCoarseThreads) {
+    su[c] = ug[c];
+    const float fv = scale * (fg[c] - m);
+    sf[c] = fv;
+    fs += fv;
+  }
+  const float fmean = (float)(block_sum_coarse(fs, red) / count);
+  for (int c = threadIdx.x; c < count; c += kCoarseThreads) sf[c] -= fmean;
+  __syncthreads();
+  const float inv_h2 = 1.0f / h2;
+  auto resid_norm = [&]() {
+    double s = 0.0;
+    for (int c = threadIdx.x; c < count; c += kCoarseThreads) {
+      const int k = c % n, j = (c / n) % n, i = c / (n * n);
+      const float uc = su[c];
+      const float lap = (su[(wrap_index(i + 1, n) * n + j) * n + k] - uc) +
+                        (su[(wrap_index(i - 1, n) * n + j) * n + k] - uc) +
+                        (su[(i * n + wrap_index(j + 1, n)) * n + k] - uc) +
+                        (su[(i * n + wrap_index(j - 1, n)) * n + k] - uc) +
+                        (su[(i * n + j) * n + wrap_index(k + 1, n)] - uc) +
+                        (su[(i * n + j) * n + wrap_index(k - 1, n)] - uc);
+      const double r = sf[c] - lap * inv_h2;
+      s += r * r;
+    }
+    return sqrt(block_sum_coarse(s, red));
+  };
+  const double r0 = resid_norm();
+  double prev = r0;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    for (int colour = 0; colour < 2; ++colour) {
+      for (int c = threadIdx.x; c < count; c += kCoarseThreads) {
+        const int k = c % n, j = (c / n) % n, i = c / (n * n);
+        if (((i + j + k) & 1) != colour) continue;
+        const float nb = su[(wrap_index(i + 1, n) * n + j) * n + k] +
+                         su[(wrap_index(i - 1, n) * n + j) * n + k] +
+                         su[(i * n + wrap_index(j + 1, n)) * n + k] +
+                         su[(i * n + wrap_index(j - 1, n)) * n + k] +
+                         su[(i * n + j) * n + wrap_index(k + 1, n)] +
+                         su[(i * n + j) * n + wrap_index(k - 1, n)];
+        su[c] = (nb - h2 * sf[c]) * (1.0f / 6.0f);
+      }
+      __syncthreads();
+    }
+    if ((sweep & 3) == 3) {
+      const double r = resid_norm();
+      if (r <= reduction * r0 || r > 0.98 * prev) break;
+      prev = r;
+    }
+  }
+  double us = 0.0;
+  for (int c = threadIdx.x; c < count; c += kCoarseThreads) us += su[c];
+  const float umean = (float)(block_sum_coarse(us, red) / count);
+  for (int c = threadIdx.x; c < count; c += kCoarseThreads) ug[c] = su[c] - umean;
+}
+
+inline unsigned blocks_for(int64_t count, int threads) {
+  return (unsigned)((count + threads - 1) / threads);
+}
+
+struct Src {
+  const float *f;
+  float scale;
+  const float *mean;
+};
+
+struct Solver {
+  pm_ctx *ctx;
+  hipStream_t s;
+  const pm_mg_params *p;
+  Src src0;
+
+  Src src(int l) const { return l == 0 ? src0 : Src{ctx->lev[l].f, 1.0f, nullptr}; }
+  float h2(int l) const {
+    const double h = 1.0 / ctx->lev[l].n;
+    return (float)(h * h);
+  }
+
+  void smooth(int l, int first_colour, int sweeps) {
+    const int n = ctx->lev[l].n;
+    const int64_t half = (int64_t)n * n * (n / 2);
+    const Src sr = src(l);
+    for (int sw = 0; sw < sweeps; ++sw)
+      for (int c = 0; c < 2; ++c)
+        k_rbgs_half<<<blocks_for(half, kThreads), kThreads, 0, s>>>(
+            ctx->lev[l].u, sr.f, sr.scale, sr.mean, n, h2(l), p->omega, c ^ first_colour);
+  }
+
+  void coarse(int l) {
+    const Src sr = src(l);
+    k_coarse_solve<<<1, kCoarseThreads, 0, s>>>(ctx->lev[l].u, sr.f, sr.scale, sr.mean,
+                                                ctx->lev[l].n, h2(l), 1e-3f, 500);
+  }
+
+  void vcycle(int l) {
+    if (l == ctx->nlevels - 1) {
+      coarse(l);
+      return;
+    }
+    const int n = ctx->lev[l].n;
+    const int nc = n / 2;
+    const int64_t ncount = (int64_t)nc * nc * nc;
+    smooth(l, 0, p->pre);
+    const Src sr = src(l);
+    const float inv_h2 = 1.0f / h2(l);
+    if (p->restrict_kind == PM_RESTRICT_AVG)
+      k_residual_restrict<PM_RESTRICT_AVG><<<blocks_for(ncount, kThreads), kThreads, 0, s>>>(
+          ctx->lev[l].u, sr.f, sr.scale, sr.mean, n, inv_h2, ctx->lev[l + 1].f);
+    else
+      k_residual_restrict<PM_RESTRICT_FW><<<blocks_for(ncount, kThreads), kThreads, 0, s>>>(
+          ctx->lev[l].u, sr.f, sr.scale, sr.mean, n, inv_h2, ctx->lev[l + 1].f);
+    k_jacobi_guess<<<blocks_for(ncount, kThreads), kThreads, 0, s>>>(
+        ctx->lev[l + 1].u, ctx->lev[l + 1].f, 1.0f, nullptr, ncount, h2(l + 1));
+    vcycle(l + 1);
+    k_prolong_add<<<blocks_for((int64_t)n * n * n, kThreads), kThreads, 0, s>>>(
+        ctx->lev[l].u, n, ctx->lev[l + 1].u);
+    smooth(l, 1, p->post);
+  }
+
+  // ||f - L u||^2 and ||f||^2 at level 0 into ctx->red_result[0..1]
+  void norms() {
+    const int n = ctx->lev[0].n;
+    const int64_t count = (int64_t)n * n * n;
+    const int nb = (int)std::min<int64_t>(RED_BLOCKS, (count + RED_THREADS - 1) / RED_THREADS);
+    k_residual_norm<<<nb, RED_THREADS, 0, s>>>(ctx->lev[0].u, src0.f, src0.scale, src0.mean, n,
+                                               1.0f / h2(0), ctx->red_partial);
+    k_pair_final<<<1, RED_THREADS, 0, s>>>(ctx->red_partial, nb, ctx->red_result);
+  }
+};
+
+}  // namespace
+
+int pm_mg_setup(pm_ctx *ctx) {
+  int n = ctx->n;
+  ctx->nlevels = 0;
+  ctx->lev[0] = pm_level{n, nullptr, nullptr};
+  ctx->nlevels = 1;
+  while (n > 16 && n % 4 == 0) {
+    n /= 2;
+    if (ctx->nlevels >= PM_MAX_LEVELS) return PM_ERR_SHAPE;
+    pm_level L{n, nullptr, nullptr};
+    const size_t bytes = sizeof(float) * (size_t)n * n * n;
+    if (hipMalloc(&L.u, bytes) != hipSuccess || hipMalloc(&L.f, bytes) != hipSuccess)
+      return PM_ERR_NOMEM;
+    ctx->lev[ctx->nlevels++] = L;
+  }
+  if ((int64_t)n * n * n > kCoarseMax) return PM_ERR_SHAPE;
+  return PM_OK;
+}
+
+int pm_mg_solve(pm_ctx *ctx, const float *rho, float coef, float *phi, const pm_mg_params *p,
+                pm_mg_stats *stats, hipStream_t s) {
+  const int n = ctx->n;
+  const int64_t count = (int64_t)n * n * n;
+  ctx->lev[0].u = phi;
+  // mean of the density, kept on the device
+  PM_HIP(ctx, launch_sum_moments(rho, count, ctx->red_partial, ctx->red_result, ctx->mean_f, s));
+  Solver sv{ctx, s, p, Src{rho, coef, ctx->mean_f}};
+  if (p->guess != PM_GUESS_WARM)
+    k_jacobi_guess<<<blocks_for(count, kThreads), kThreads, 0, s>>>(phi, rho, coef, ctx->mean_f,
+                                                                     count, sv.h2(0));
+  int status = PM_OK;
+  int cycles = 0;
+  if (p->fixed_cycles > 0) {
+    for (int c = 0; c < p->fixed_cycles; ++c) sv.vcycle(0);
+    cycles = p->fixed_cycles;
+  } else {
+    double rel[64];
+    sv.norms();
+    PM_HIP(ctx, hipMemcpyAsync(ctx->host_result, ctx->red_result, 2 * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+    PM_HIP(ctx, hipStreamSynchronize(s));
+    const double fnorm = sqrt(ctx->host_result[1]);
+    if (fnorm == 0.0) {
+      PM_HIP(ctx, hipMemsetAsync(phi, 0, sizeof(float) * count, s));
+      if (stats) {
+        stats->cycles = 0;
+        stats->status = PM_OK;
+        stats->relres[0] = 0.0;
+      }
+      return PM_OK;
+    }
+    rel[0] = sqrt(ctx->host_result[0]) / fnorm;
+    status = PM_WARN_NOT_CONVERGED;
+    if (rel[0] < p->tol) status = PM_OK;
+    while (status == PM_WARN_NOT_CONVERGED && cycles < p->max_cycles) {
+      sv.vcycle(0);
+      ++cycles;
+      sv.norms();
+      PM_HIP(ctx, hipMemcpyAsync(ctx->host_result, ctx->red_result, 2 * sizeof(double),
+                                 hipMemcpyDeviceToHost, s));
+      PM_HIP(ctx, hipStreamSynchronize(s));
+      rel[cycles] = sqrt(ctx->host_result[0]) / fnorm;
+      if (rel[cycles] < p->tol) {
+        status = PM_OK;
+      } else if (rel[cycles] < 1e-4 && rel[cycles - 1] < 1.5 * rel[cycles]) {
+        status = PM_WARN_FLOOR;
+      }
+    }
+    if (stats)
+      for (int c = 0; c <= cycles; ++c) stats->relres[c] = rel[c];
+  }
+  // remove the mean of phi (gauge)
+  PM_HIP(ctx, launch_sum_moments(phi, count, ctx->red_partial, ctx->red_result, ctx->mean_f + 1, s));
+  k_subtract_mean<<<blocks_for(count, kThreads), kThreads, 0, s>>>(phi, count, ctx->mean_f + 1);
+  PM_HIP(ctx, hipGetLastError());
+  if (stats) {
+    stats->cycles = cycles;
+    stats->status = status;
+  }
+  if (status == PM_WARN_NOT_CONVERGED) pm_fail(ctx, status, "multigrid: max_cycles reached above tol");
+  if (status == PM_WARN_FLOOR) pm_fail(ctx, status, "multigrid: stagnated at the FP32 floor above tol");
+  return status;
+}

@@ -1,0 +1,251 @@
+"""ctypes binding of libhippm.so (include/hippm.h): argument marshalling only.
+
+Every function takes torch tensors that live on the GPU, checks dtype, shape
+and contiguity, and passes raw device pointers and the current torch stream to
+the C entry point of the same name. No arithmetic of the method happens here.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import warnings
+from ctypes import POINTER, byref, c_char_p, c_double, c_float, c_int, c_int64, c_void_p
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhippm.so")
+
+# enums (mirror include/hippm.h)
+PM_OK, PM_WARN_NOT_CONVERGED, PM_WARN_FLOOR = 0, 1, 2
+PM_ERR_ARG, PM_ERR_SHAPE, PM_ERR_NOMEM, PM_ERR_HIP, PM_ERR_NONFINITE = -1, -2, -3, -4, -5
+PM_CIC, PM_TSC = 2, 3
+PM_DEPOSIT_ATOMIC, PM_DEPOSIT_SORTED = 0, 1
+PM_POS_BOX, PM_POS_CELLOFF = 0, 1
+PM_RESTRICT_FW, PM_RESTRICT_AVG = 0, 1
+PM_SOLVER_MG, PM_SOLVER_FFT = 0, 1
+PM_GUESS_JACOBI, PM_GUESS_WARM = 0, 1
+
+MAS = {"cic": PM_CIC, "tsc": PM_TSC}
+ORDER = {"atomic": PM_DEPOSIT_ATOMIC, "sorted": PM_DEPOSIT_SORTED}
+
+
+class PMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"hippm error {code}: {msg}")
+        self.code = code
+
+
+class PMWarning(UserWarning):
+    pass
+
+
+class MGParams(ctypes.Structure):
+    _fields_ = [("pre", c_int), ("post", c_int), ("omega", c_float), ("tol", c_float),
+                ("max_cycles", c_int), ("restrict_kind", c_int), ("guess", c_int),
+                ("fixed_cycles", c_int)]
+
+
+class MGStats(ctypes.Structure):
+    _fields_ = [("cycles", c_int), ("status", c_int), ("relres", c_double * 64)]
+
+    def history(self):
+        return [self.relres[i] for i in range(self.cycles + 1)]
+
+
+class StepParams(ctypes.Structure):
+    _fields_ = [("mas", c_int), ("order", c_int), ("solver", c_int), ("fft_deconv", c_int),
+                ("omega_m", c_double), ("mg", MGParams), ("timing", c_int)]
+
+
+class StepStats(ctypes.Structure):
+    _fields_ = [("mg", MGStats), ("ms_drift", c_float), ("ms_deposit", c_float),
+                ("ms_solve", c_float), ("ms_gradient", c_float), ("ms_interp", c_float)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2410_20501_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = c_void_p
+    sig = {
+        "pm_default_step_params": (None, [POINTER(StepParams)]),
+        "pm_create": (c_int, [POINTER(c_void_p), c_int, c_int64, c_int]),
+        "pm_destroy": (None, [P]),
+        "pm_last_error": (c_char_p, [P]),
+        "pm_deposit": (c_int, [P, P, P, c_int64, c_int, c_int, c_int, P, P]),
+        "pm_solve_mg": (c_int, [P, P, c_float, P, POINTER(MGParams), POINTER(MGStats), P]),
+        "pm_solve_fft": (c_int, [P, P, c_float, c_int, P, P]),
+        "pm_gradient": (c_int, [P, P, c_int, P, P]),
+        "pm_interp": (c_int, [P, P, P, c_int64, c_int, c_int, P, P, P]),
+        "pm_accel": (c_int, [P, P, P, c_int64, c_int, c_double, POINTER(StepParams), P, P,
+                             POINTER(StepStats), P]),
+        "pm_kdk": (c_int, [P, P, P, P, c_int64, c_int, c_double, c_double, POINTER(StepParams),
+                           P, P, POINTER(StepStats), P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib, sorted(sig)
+
+
+_lib, EXPORTED = _load()
+
+
+def default_step_params(**kw) -> StepParams:
+    p = StepParams()
+    _lib.pm_default_step_params(byref(p))
+    for k, v in kw.items():
+        if k == "mas":
+            v = MAS.get(v, v)
+        elif k == "order":
+            v = ORDER.get(v, v)
+        elif k == "solver":
+            v = {"mg": PM_SOLVER_MG, "fft": PM_SOLVER_FFT}.get(v, v)
+        elif k == "guess":
+            v = {"jacobi": PM_GUESS_JACOBI, "warm": PM_GUESS_WARM}.get(v, v)
+        elif k == "restrict_kind":
+            v = {"fw": PM_RESTRICT_FW, "avg": PM_RESTRICT_AVG}.get(v, v)
+        if hasattr(p.mg, k) and k not in ("mas",):
+            setattr(p.mg, k, v)
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def _stream():
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, dtype=torch.float32, shape=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return c_void_p(t.data_ptr())
+
+
+class Context:
+    """Owner of a pm_ctx (scratch for an n^3 grid and up to np_max particles)."""
+
+    def __init__(self, n: int, np_max: int = 0, flags: int = 0):
+        h = c_void_p()
+        st = _lib.pm_create(byref(h), int(n), int(np_max), int(flags))
+        if st != PM_OK:
+            raise PMError(st, f"pm_create(n={n}, np_max={np_max}) failed")
+        self._h = h
+        self.n = int(n)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.pm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise PMError(PM_ERR_ARG, "context closed")
+        return self._h
+
+    def _check(self, st, what):
+        if st < 0:
+            raise PMError(st, f"{what}: {_lib.pm_last_error(self._h).decode()}")
+        if st > 0:
+            warnings.warn(f"{what}: {_lib.pm_last_error(self._h).decode()}", PMWarning, stacklevel=3)
+        return st
+
+
+def pm_create(n, np_max=0, flags=0) -> Context:
+    return Context(n, np_max, flags)
+
+
+def pm_destroy(ctx: Context):
+    ctx.close()
+
+
+def _particles(pos, cell):
+    np_ = pos.shape[0]
+    if pos.dim() != 2 or pos.shape[1] != 3:
+        raise ValueError("positions must be [np, 3]")
+    kind = PM_POS_BOX if cell is None else PM_POS_CELLOFF
+    return np_, kind, _ptr(pos, shape=(np_, 3), name="pos"), _ptr(cell, torch.int32, (np_,), "cell")
+
+
+def pm_deposit(ctx: Context, pos, rho, cell=None, mas="tsc", order="atomic"):
+    n = ctx.n
+    np_, kind, pp, cp = _particles(pos, cell)
+    st = _lib.pm_deposit(ctx.handle, pp, cp, np_, kind, MAS.get(mas, mas), ORDER.get(order, order),
+                         _ptr(rho, shape=(n, n, n), name="rho"), _stream())
+    return ctx._check(st, "pm_deposit")
+
+
+def pm_solve_mg(ctx: Context, rho, coef, phi, params: MGParams | None = None, **kw):
+    n = ctx.n
+    if params is None:
+        params = default_step_params(**kw).mg
+    stats = MGStats()
+    st = _lib.pm_solve_mg(ctx.handle, _ptr(rho, shape=(n, n, n), name="rho"), float(coef),
+                          _ptr(phi, shape=(n, n, n), name="phi"), byref(params), byref(stats),
+                          _stream())
+    ctx._check(st, "pm_solve_mg")
+    return stats
+
+
+def pm_solve_fft(ctx: Context, rho, coef, phi, deconv=3):
+    n = ctx.n
+    st = _lib.pm_solve_fft(ctx.handle, _ptr(rho, shape=(n, n, n), name="rho"), float(coef),
+                           int(deconv), _ptr(phi, shape=(n, n, n), name="phi"), _stream())
+    return ctx._check(st, "pm_solve_fft")
+
+
+def pm_gradient(ctx: Context, phi, g, points=5):
+    n = ctx.n
+    st = _lib.pm_gradient(ctx.handle, _ptr(phi, shape=(n, n, n), name="phi"), int(points),
+                          _ptr(g, shape=(n, n, n, 3), name="g"), _stream())
+    return ctx._check(st, "pm_gradient")
+
+
+def pm_interp(ctx: Context, pos, g, acc, cell=None, mas="tsc"):
+    n = ctx.n
+    np_, kind, pp, cp = _particles(pos, cell)
+    st = _lib.pm_interp(ctx.handle, pp, cp, np_, kind, MAS.get(mas, mas),
+                        _ptr(g, shape=(n, n, n, 3), name="g"), _ptr(acc, shape=(np_, 3), name="acc"),
+                        _stream())
+    return ctx._check(st, "pm_interp")
+
+
+def pm_accel(ctx: Context, pos, a, phi, acc, cell=None, params: StepParams | None = None):
+    n = ctx.n
+    np_, kind, pp, cp = _particles(pos, cell)
+    params = params or default_step_params()
+    stats = StepStats()
+    st = _lib.pm_accel(ctx.handle, pp, cp, np_, kind, float(a), byref(params),
+                       _ptr(phi, shape=(n, n, n), name="phi"), _ptr(acc, shape=(np_, 3), name="acc"),
+                       byref(stats), _stream())
+    ctx._check(st, "pm_accel")
+    return stats
+
+
+def pm_kdk(ctx: Context, pos, vel, a0, a1, phi, acc, cell=None, params: StepParams | None = None):
+    n = ctx.n
+    np_, kind, pp, cp = _particles(pos, cell)
+    params = params or default_step_params()
+    stats = StepStats()
+    st = _lib.pm_kdk(ctx.handle, pp, cp, _ptr(vel, shape=(np_, 3), name="vel"), np_, kind,
+                     float(a0), float(a1), byref(params), _ptr(phi, shape=(n, n, n), name="phi"),
+                     _ptr(acc, shape=(np_, 3), name="acc"), byref(stats), _stream())
+    ctx._check(st, "pm_kdk")
+    return stats

@@ -1,0 +1,347 @@
+"""GPU parity of every stage of the particle-mesh loop against the FP64 oracle.
+
+All inputs are seeded; the FP32 arrays given to the GPU are promoted exactly to
+FP64 for the oracle. Tolerances (relative L2 unless stated): potential and
+accelerations 1e-5, positions 1e-4 box units after 10 steps; deposit and
+gradient at FP32 rounding level.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import icgen
+from oracle import pm as opm
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2410_20501_amd as pm
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return pm
+
+
+_CTX = {}
+
+
+def ctx_for(lib, n, np_max=0):
+    key = (n, np_max)
+    if key not in _CTX:
+        _CTX[key] = lib.Context(n, np_max)
+    return _CTX[key]
+
+
+def dev(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+def lattice_ics(n, ns=-2.0, rms=0.2, a=0.1, seed=1):
+    ps = icgen.zeldovich_particles(n, ns, rms, a, seed=seed)
+    return ps.pos, ps.vel
+
+
+# ------------------------------------------------------------------ deposit
+
+@pytest.mark.parametrize("order", ["atomic", "sorted"])
+@pytest.mark.parametrize("mas", ["tsc", "cic"])
+def test_point_mass_worked_example(lib, mas, order):
+    """Paper App. D: point mass at a cell centre (CIC 1 cell, TSC 27) or corner (8 cells of 1/8)."""
+    _say(f"point mass {mas} {order}")
+    n = 8
+    ctx = ctx_for(lib, n, 1)
+    rho = torch.zeros((n, n, n), device="cuda")
+    for place, u in (("centre", [3.5, 4.5, 5.5]), ("corner", [3.0, 4.0, 5.0])):
+        pos = dev(np.array([u], dtype=np.float32) / n)
+        lib.pm_deposit(ctx, pos, rho, mas=mas, order=order)
+        got = host(rho) / n ** 3   # one particle carries mass n^3 (mean density 1)
+        ref = opm.deposit(np.array([u]), n, mas, mass=1.0)
+        np.testing.assert_array_equal(got, ref)
+        nz = np.count_nonzero(got)
+        assert nz == {("cic", "centre"): 1, ("tsc", "centre"): 27}.get((mas, place), 8)
+
+
+@pytest.mark.parametrize("poskind", ["box", "celloff"])
+@pytest.mark.parametrize("order", ["atomic", "sorted"])
+@pytest.mark.parametrize("mas", ["tsc", "cic"])
+@pytest.mark.parametrize("n,npart", [(32, None), (48, None), (32, 10007)])
+def test_deposit_parity(lib, n, npart, mas, order, poskind):
+    _say(f"deposit n={n} np={npart} {mas} {order} {poskind}")
+    if npart is None:
+        pos, _ = lattice_ics(n, seed=3)
+    else:
+        rng = np.random.Generator(np.random.PCG64(4))
+        pos = rng.uniform(0, 1, size=(npart, 3)).astype(np.float32)
+        pos[0] = [0.0, np.nextafter(np.float32(1), np.float32(0)), 0.5]
+    ctx = ctx_for(lib, n, pos.shape[0])
+    rho = torch.empty((n, n, n), device="cuda")
+    if poskind == "box":
+        lib.pm_deposit(ctx, dev(pos), rho, mas=mas, order=order)
+        u = opm.cell_units(n, pos=pos)
+    else:
+        cell, off = icgen.to_cell_offset(pos, n)
+        lib.pm_deposit(ctx, dev(off), rho, cell=dev(cell, torch.int32), mas=mas, order=order)
+        u = opm.cell_units(n, cell=cell, off=off)
+    ref = opm.deposit(u, n, mas)
+    got = host(rho)
+    # FP32 rounding of the weights and sums, plus, for box units on a grid that is
+    # not a power of two, the rounding of u = x n in FP32 (|du| <= n 2^-24; the window
+    # slope is at most 1 per axis, summed over 3 axes and both sides of a cell)
+    du = 0.0 if (n & (n - 1)) == 0 or poskind == "celloff" else n * 2.0 ** -24
+    assert np.abs(got - ref).max() <= 4e-6 * max(1.0, ref.max()) + 6 * du * ref.max()
+    assert abs(got.sum() - n ** 3) <= 1e-6 * n ** 3
+
+
+def test_sorted_deposit_is_bitwise_reproducible(lib):
+    _say("sorted deposit determinism")
+    n = 32
+    pos, _ = lattice_ics(n, rms=2.0, seed=5)
+    ctx = ctx_for(lib, n, pos.shape[0])
+    perm = np.random.Generator(np.random.PCG64(6)).permutation(pos.shape[0])
+    outs = []
+    for p in (pos, pos, pos[perm]):
+        rho = torch.empty((n, n, n), device="cuda")
+        lib.pm_deposit(ctx, dev(np.ascontiguousarray(p)), rho, order="sorted")
+        outs.append(host(rho).astype(np.float32).view(np.uint32))
+    np.testing.assert_array_equal(outs[0], outs[1])
+    np.testing.assert_array_equal(outs[0], outs[2])
+
+
+def test_deposit_empty(lib):
+    _say("deposit np=0")
+    n = 16
+    ctx = ctx_for(lib, n, 0)
+    rho = torch.full((n, n, n), 7.0, device="cuda")
+    for order in ("atomic", "sorted"):
+        lib.pm_deposit(ctx, torch.empty((0, 3), device="cuda"), rho, order=order)
+        assert host(rho).max() == 0.0
+
+
+# ------------------------------------------------------------------ solvers
+
+def _density(n, seed=7, ns=-2.0, rms=0.3):
+    pos, _ = lattice_ics(n, ns=ns, rms=rms, seed=seed)
+    return opm.deposit(opm.cell_units(n, pos=pos), n, "tsc").astype(np.float32)
+
+
+@pytest.mark.parametrize("n", [8, 16, 32, 48, 64])
+def test_mg_solve_parity(lib, n):
+    _say(f"mg solve n={n}")
+    rho32 = _density(n)
+    ctx = ctx_for(lib, n)
+    phi = torch.zeros((n, n, n), device="cuda")
+    a = 0.1
+    coef = 1.5 * a
+    stats = lib.pm_solve_mg(ctx, dev(rho32), coef, phi, tol=1e-7, max_cycles=40)
+    ref = opm.solve_exact7(opm.source(rho32.astype(np.float64), a), 1.0 / n)
+    got = host(phi)
+    assert rel_l2(got, ref) <= 1e-5, (rel_l2(got, ref), stats.history())
+    assert abs(got.mean()) <= 1e-6 * np.abs(ref).max()
+    hist = stats.history()
+    if n >= 32:
+        # paper App. C: about an order of magnitude per V-cycle (omega = 1)
+        assert hist[1] / hist[2] > 4.0, hist
+
+
+def test_mg_single_mode_closed_form(lib):
+    _say("mg single mode")
+    n = 64
+    i = np.arange(n)
+    m = (1, 3, 2)
+    theta = 2 * np.pi * (m[0] * i[:, None, None] + m[1] * i[None, :, None] + m[2] * i[None, None, :]) / n
+    rho = (1.0 + 0.1 * np.cos(theta)).astype(np.float32)
+    ctx = ctx_for(lib, n)
+    phi = torch.zeros((n, n, n), device="cuda")
+    lib.pm_solve_mg(ctx, dev(rho), 1.0, phi, tol=1e-7, max_cycles=40)
+    lam = sum(2.0 * (np.cos(2 * np.pi * md / n) - 1.0) for md in m) * n * n
+    ref = (rho.astype(np.float64) - rho.astype(np.float64).mean()) / lam
+    assert rel_l2(host(phi), ref) <= 1e-5
+
+
+def test_mg_warnings_and_fixed_cycles(lib):
+    _say("mg warnings")
+    n = 32
+    rho32 = _density(n)
+    ctx = ctx_for(lib, n)
+    phi = torch.zeros((n, n, n), device="cuda")
+    with pytest.warns(lib.PMWarning):
+        st = lib.pm_solve_mg(ctx, dev(rho32), 0.15, phi, tol=1e-9, max_cycles=1)
+    assert st.status == lib.PM_WARN_NOT_CONVERGED and st.cycles == 1
+    phi2 = torch.zeros((n, n, n), device="cuda")
+    st = lib.pm_solve_mg(ctx, dev(rho32), 0.15, phi2, fixed_cycles=12)
+    ref = opm.solve_exact7(opm.source(rho32.astype(np.float64), 0.1), 1.0 / n)
+    assert st.cycles == 12 and rel_l2(host(phi2), ref) <= 1e-5
+    with pytest.raises(lib.PMError):
+        lib.pm_solve_mg(ctx, dev(rho32), 0.15, phi2, max_cycles=0)
+
+
+def test_mg_uniform_density_gives_zero(lib):
+    _say("mg uniform")
+    n = 16
+    ctx = ctx_for(lib, n)
+    phi = torch.full((n, n, n), 3.0, device="cuda")
+    st = lib.pm_solve_mg(ctx, torch.ones((n, n, n), device="cuda"), 0.5, phi, guess="warm")
+    assert st.status == 0 and np.abs(host(phi)).max() == 0.0
+
+
+@pytest.mark.parametrize("deconv", [0, 2, 3])
+@pytest.mark.parametrize("n", [8, 16, 32, 64, 128])
+def test_fft_solve_parity(lib, n, deconv):
+    _say(f"fft solve n={n} p={deconv}")
+    rho32 = _density(n, seed=8)
+    ctx = ctx_for(lib, n)
+    phi = torch.zeros((n, n, n), device="cuda")
+    lib.pm_solve_fft(ctx, dev(rho32), 0.3, phi, deconv=deconv)
+    ref = opm.solve_fft(0.3 * (rho32.astype(np.float64) - rho32.astype(np.float64).mean()), 1.0 / n, deconv)
+    assert rel_l2(host(phi), ref) <= 1e-5
+
+
+def test_fft_rejects_non_power_of_two(lib):
+    ctx = ctx_for(lib, 48)
+    rho = torch.ones((48, 48, 48), device="cuda")
+    with pytest.raises(lib.PMError) as e:
+        lib.pm_solve_fft(ctx, rho, 1.0, torch.empty_like(rho))
+    assert e.value.code == lib.PM_ERR_SHAPE
+
+
+# ------------------------------------------------------------------ gradient, interp
+
+@pytest.mark.parametrize("points", [3, 5, 7])
+@pytest.mark.parametrize("n", [16, 48])
+def test_gradient_parity(lib, n, points):
+    _say(f"gradient n={n} points={points}")
+    phi = np.random.Generator(np.random.PCG64(9)).standard_normal((n, n, n)).astype(np.float32)
+    ctx = ctx_for(lib, n)
+    g = torch.empty((n, n, n, 3), device="cuda")
+    lib.pm_gradient(ctx, dev(phi), g, points=points)
+    ref = opm.gradient(phi.astype(np.float64), 1.0 / n, points)
+    assert rel_l2(host(g), ref) <= 1e-6
+
+
+@pytest.mark.parametrize("poskind", ["box", "celloff"])
+@pytest.mark.parametrize("mas", ["tsc", "cic"])
+def test_interp_parity(lib, mas, poskind):
+    _say(f"interp {mas} {poskind}")
+    n = 32
+    rng = np.random.Generator(np.random.PCG64(10))
+    g = rng.standard_normal((n, n, n, 3)).astype(np.float32)
+    pos = rng.uniform(0, 1, size=(5001, 3)).astype(np.float32)
+    ctx = ctx_for(lib, n)
+    acc = torch.empty((5001, 3), device="cuda")
+    if poskind == "box":
+        lib.pm_interp(ctx, dev(pos), dev(g), acc, mas=mas)
+        u = opm.cell_units(n, pos=pos)
+    else:
+        cell, off = icgen.to_cell_offset(pos, n)
+        lib.pm_interp(ctx, dev(off), dev(g), acc, cell=dev(cell, torch.int32), mas=mas)
+        u = opm.cell_units(n, cell=cell, off=off)
+    ref = opm.interp(u, g.astype(np.float64), mas)
+    assert np.abs(host(acc) - ref).max() <= 2e-6 * np.abs(g).max()
+
+
+# ------------------------------------------------------------------ full step
+
+def _run_gpu(lib, n, pos, vel, a_list, solver="mg", celloff=False, order="atomic"):
+    ctx = ctx_for(lib, n, pos.shape[0])
+    params = lib.default_step_params(solver=solver, order=order, tol=1e-7, max_cycles=40)
+    phi = torch.zeros((n, n, n), device="cuda")
+    acc = torch.empty((pos.shape[0], 3), device="cuda")
+    if celloff:
+        cell_np, off = icgen.to_cell_offset(pos, n)
+        p, cell = dev(off), dev(cell_np, torch.int32)
+    else:
+        p, cell = dev(pos), None
+    v = dev(vel)
+    lib.pm_accel(ctx, p, a_list[0], phi, acc, cell=cell, params=params)
+    params.mg.guess = lib.PM_GUESS_WARM
+    for a0, a1 in zip(a_list[:-1], a_list[1:]):
+        lib.pm_kdk(ctx, p, v, a0, a1, phi, acc, cell=cell, params=params)
+    x = host(p)
+    if celloff:
+        x = icgen.from_cell_offset(host(cell).astype(np.int64), x, n)
+    return x, host(v), host(acc), host(phi)
+
+
+def test_config1_one_step(lib):
+    """32^3, P(k) ~ k^-2, rms 0.2 cell, one KDK step a = 0.1 -> 0.11, TSC, MG 2/2."""
+    _say("config 1 one step")
+    n = 32
+    pos, vel = lattice_ics(n, -2.0, 0.2, 0.1, seed=1)
+    a_list = [0.1, 0.11]
+    x, v, acc, phi = _run_gpu(lib, n, pos, vel, a_list)
+    xr, vr, accr = opm.run(pos.astype(np.float64), vel.astype(np.float64), a_list, n)
+    _, fields = opm.accel(xr * n, n, a_list[-1], return_fields=True)
+    assert rel_l2(phi, fields["phi"]) <= 1e-5
+    assert rel_l2(acc, accr) <= 1e-5
+    assert opm.periodic_distance(x, xr).max() <= 1e-6
+    assert rel_l2(v, vr) <= 1e-5
+
+
+@pytest.mark.parametrize("solver", ["mg", "fft"])
+@pytest.mark.parametrize("celloff", [False, True])
+def test_ten_steps_parity(lib, solver, celloff):
+    """10 KDK steps (a = 0.1 -> 0.2), 64^3, P(k) ~ k^-1.5, rms 0.3 cell: positions within 1e-4."""
+    _say(f"ten steps {solver} celloff={celloff}")
+    n = 64
+    pos, vel = lattice_ics(n, -1.5, 0.3, 0.1, seed=2)
+    a_list = list(np.linspace(0.1, 0.2, 11))
+    x, v, acc, phi = _run_gpu(lib, n, pos, vel, a_list, solver=solver, celloff=celloff)
+    osolver = "exact7" if solver == "mg" else "fft"
+    xr, vr, accr = opm.run(pos.astype(np.float64), vel.astype(np.float64), a_list, n, solver=osolver)
+    assert opm.periodic_distance(x, xr).max() <= 1e-4
+    assert rel_l2(acc, accr) <= 1e-5 * 10
+    assert rel_l2(v, vr) <= 1e-5 * 10
+
+
+def test_sorted_and_atomic_steps_agree(lib):
+    _say("sorted vs atomic steps")
+    n = 32
+    pos, vel = lattice_ics(n, -2.0, 0.5, 0.1, seed=11)
+    a_list = [0.1, 0.12, 0.14]
+    xa, va, aa, _ = _run_gpu(lib, n, pos, vel, a_list, order="atomic")
+    xs, vs, as_, _ = _run_gpu(lib, n, pos, vel, a_list, order="sorted")
+    assert opm.periodic_distance(xa, xs).max() <= 1e-6
+    assert rel_l2(as_, aa) <= 1e-5
+
+
+def test_wrap_edge_cases(lib):
+    _say("wrap edge cases")
+    n = 16
+    top = np.nextafter(np.float32(1), np.float32(0))
+    pos = np.array([[top, 0.5, 0.5], [-0.0, 0.25, 0.75], [0.5, 0.5, 0.5]], dtype=np.float32)
+    vel = np.array([[1e-3, 0, 0], [-1e-3, 0, 0], [0, 0, 0]], dtype=np.float32)
+    x, _, _, _ = _run_gpu(lib, n, pos, vel, [0.5, 0.51])
+    assert np.all((x >= 0) & (x < 1))
+    xr, _, _ = opm.run(pos.astype(np.float64), vel.astype(np.float64), [0.5, 0.51], n)
+    assert opm.periodic_distance(x, xr).max() <= 1e-6
+    xc, _, _, _ = _run_gpu(lib, n, pos, vel, [0.5, 0.51], celloff=True)
+    assert opm.periodic_distance(xc, xr).max() <= 1e-6
+
+
+def test_momentum_conservation_fft(lib):
+    _say("momentum")
+    n = 32
+    rng = np.random.Generator(np.random.PCG64(12))
+    pos = rng.uniform(0, 1, size=(4096, 3)).astype(np.float32)
+    ctx = ctx_for(lib, n, 4096)
+    acc = torch.empty((4096, 3), device="cuda")
+    phi = torch.zeros((n, n, n), device="cuda")
+    lib.pm_accel(ctx, dev(pos), 1.0, phi, acc, params=lib.default_step_params(solver="fft"))
+    a = host(acc)
+    assert np.abs(a.sum(0)).max() <= 1e-5 * np.abs(a).sum(0).max()
