@@ -1,0 +1,212 @@
+"""Benchmark: particle-mesh particle-steps/s on one MI355X.
+
+Workload: 512^3 particles on a 512^3 grid, P(k) ~ k^-1 exp(-k^2/k_c^2) with
+k_c = k_Nyquist / 2, rms displacement 0.25 cell at a = 0.02, 50 kick-drift-kick
+steps uniform in a up to a = 1, positions stored as FP32 in-cell offsets plus
+an int32 cell index, TSC, multigrid (2 + 2 red-black Gauss-Seidel sweeps, full
+weighting) warm-started from the previous step's potential. Inputs are seeded
+synthetic Gaussian random fields generated on the host and copied to HBM before
+the timed region. One "step" is one pm_kdk call: kick + drift, deposit,
+multigrid solve, 5-point gradient, interpolation + kick.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_inputs(n, seed=3, a0=0.02):
+    import numpy as np
+
+    import icgen
+    t = time.time()
+    cutoff = math.pi * n / 2.0                       # k_c = k_Nyquist / 2, k_Nyquist = pi n
+    ps = icgen.zeldovich_particles(n, -1.0, 0.25, a0, seed=seed, cutoff_k=cutoff, precision="f32")
+    cell, off = icgen.to_cell_offset(ps.pos, n)
+    _log(f"inputs {n}^3 generated in {time.time() - t:.1f}s")
+    return np.ascontiguousarray(off), np.ascontiguousarray(cell), np.ascontiguousarray(ps.vel)
+
+
+def cpu_baseline(n_sample=128, steps=2, seed=3):
+    """The FP64 oracle, as is, on a bounded sample of the same recipe (host cores)."""
+    import numpy as np
+
+    import icgen
+    from oracle import pm as opm
+    a = [0.02 + 0.0196 * i for i in range(steps + 1)]
+    ps = icgen.zeldovich_particles(n_sample, -1.0, 0.25, a[0], seed=seed,
+                                   cutoff_k=math.pi * n_sample / 2.0)
+    x = ps.pos.astype(np.float64)
+    v = ps.vel.astype(np.float64)
+    acc = opm.accel(x * n_sample, n_sample, a[0])
+    t = time.perf_counter()
+    for a0, a1 in zip(a[:-1], a[1:]):
+        x, v, acc = opm.kdk_step(x, v, acc, a0, a1, n_sample)
+    dt = time.perf_counter() - t
+    return {
+        "value": n_sample ** 3 * steps / dt,
+        "unit": "particle-steps/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"FP64 numpy/scipy oracle, {n_sample}^3 particles on a {n_sample}^3 grid, "
+                  f"{steps} KDK steps from a=0.02 (same recipe, exact 7-point solve), "
+                  f"{dt:.1f}s on one host thread",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=48)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--order", default="sorted", choices=["atomic", "sorted"])
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--reorder-every", type=int, default=10,
+                    help="re-sort particles by tile every this many steps (0: never)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--stage-log", action="store_true",
+                    help="record per-stage times of every timed step (adds events)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 512 MiB device copy (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2410_20501_amd as pm
+
+    if args.copy_calibration:
+        src = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4}))
+        return
+
+    n = args.n
+    total_steps = 50
+    if args.warmup + args.steps > total_steps:
+        raise SystemExit(f"warmup + steps must be <= {total_steps} (the run has 50 steps)")
+    a_list = [0.02 + (1.0 - 0.02) * i / total_steps for i in range(total_steps + 1)]
+
+    off, cell, vel = make_inputs(n)
+    npart = off.shape[0]
+    dev = torch.device("cuda", 0)
+    off_d = torch.from_numpy(off).to(dev)
+    cell_d = torch.from_numpy(cell).to(dev)
+    vel_d = torch.from_numpy(vel).to(dev)
+    del off, cell, vel
+    phi = torch.zeros((n, n, n), device=dev)
+    acc = torch.empty((npart, 3), device=dev)
+    ctx = pm.Context(n, npart)
+    params = pm.default_step_params(order=args.order, tol=args.tol, max_cycles=40)
+    torch.cuda.synchronize()
+    if args.reorder_every > 0:
+        pm.pm_reorder(ctx, off_d, vel=vel_d, cell=cell_d)
+    pm.pm_accel(ctx, off_d, a_list[0], phi, acc, cell=cell_d, params=params)
+    params.mg.guess = pm.PM_GUESS_WARM_RESCALED
+    torch.cuda.synchronize()
+
+    import warnings
+    warnings.simplefilter("ignore", pm.PMWarning)
+    step = 0
+    for _ in range(args.warmup):
+        pm.pm_kdk(ctx, off_d, vel_d, a_list[step], a_list[step + 1], phi, acc, cell=cell_d,
+                  params=params)
+        step += 1
+    torch.cuda.synchronize()
+    _log(f"warmup done ({args.warmup} steps)")
+
+    cycles = []
+    hists = []
+    stage_rows = []
+    if args.stage_log:
+        params.timing = 1
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        if args.reorder_every > 0 and step % args.reorder_every == 0:
+            pm.pm_reorder(ctx, off_d, vel=vel_d, acc=acc, cell=cell_d)
+        st = pm.pm_kdk(ctx, off_d, vel_d, a_list[step], a_list[step + 1], phi, acc, cell=cell_d,
+                       params=params)
+        cycles.append(st.mg.cycles)
+        if args.stage_log:
+            stage_rows.append((step, round(st.ms_drift, 2), round(st.ms_deposit, 2),
+                               round(st.ms_solve, 2), round(st.ms_gradient, 2),
+                               round(st.ms_interp, 2)))
+        if i in (0, args.steps // 2, args.steps - 1):
+            hists.append(["%.2e" % r for r in st.mg.history()])
+        step += 1
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    _log(f"timed {args.steps} steps in {elapsed:.3f}s; V-cycles per step {cycles}")
+    _log(f"relres histories (first, middle, last timed step): {hists}")
+    if args.stage_log:
+        _log("step: drift deposit solve gradient interp (ms)")
+        for row in stage_rows:
+            _log(str(row))
+
+    ms_per_step = 1000.0 * elapsed / max(args.steps, 1)
+    value = npart * args.steps / elapsed
+
+    # per-stage times of one extra (untimed) step with stage events
+    params.timing = 1
+    stt = pm.pm_kdk(ctx, off_d, vel_d, a_list[step], a_list[min(step + 1, total_steps)], phi, acc,
+                    cell=cell_d, params=params) if step < total_steps else None
+    stages = None
+    if stt is not None:
+        stages = {k: round(getattr(stt, k), 4) for k in
+                  ("ms_drift", "ms_deposit", "ms_solve", "ms_gradient", "ms_interp")}
+
+    out = {
+        "metric": "PM particle-steps/s at 512^3",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded power-law Gaussian random field, Zel'dovich ICs)",
+        "config": {"workload": f"{n}^3 particles on a {n}^3 grid, 50 KDK steps a=0.02->1, "
+                               f"cell-offset positions, TSC {args.order} deposit, multigrid "
+                               f"2+2 RBGS growth-rescaled warm start tol {args.tol:g}, particles re-sorted "
+                               f"by tile every {args.reorder_every} steps",
+                   "particles": npart, "grid": n, "deposit": args.order,
+                   "vcycles_per_step": cycles},
+        "stages_ms_last_step": stages,
+    }
+    if not args.no_cpu_baseline:
+        _log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

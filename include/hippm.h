@@ -63,7 +63,22 @@ enum pm_order { PM_DEPOSIT_ATOMIC = 0, PM_DEPOSIT_SORTED = 1 };
 enum pm_poskind { PM_POS_BOX = 0, PM_POS_CELLOFF = 1 };
 enum pm_restrict { PM_RESTRICT_FW = 0, PM_RESTRICT_AVG = 1 };
 enum pm_solver { PM_SOLVER_MG = 0, PM_SOLVER_FFT = 1 };
-enum pm_guess { PM_GUESS_JACOBI = 0, PM_GUESS_WARM = 1 };
+/* Starting guess of the multigrid solve (Sects. 3.7.1 and 3.9): the Jacobi step
+ * -h^2 f / 6, the potential passed in phi, or (in pm_kdk) that potential scaled
+ * by the linear growth of the supercomoving potential between the two scale
+ * factors. The paper writes the rescaling factor as (1+z1) D1 / ((1+z0) D0);
+ * with the supercomoving Poisson equation of Sect. 3.1 the potential grows as
+ * a D, so the factor used is a1 D1 / (a0 D0) = (a1 / a0)^2 in Einstein-de
+ * Sitter. pm_solve_mg and pm_accel treat PM_GUESS_WARM_RESCALED as
+ * PM_GUESS_WARM (they have no second scale factor). */
+enum pm_guess { PM_GUESS_JACOBI = 0, PM_GUESS_WARM = 1, PM_GUESS_WARM_RESCALED = 2 };
+
+/* pm_create flags */
+enum pm_create_flags {
+  /* Run every multigrid level with the plain one-kernel-per-half-sweep kernels
+   * instead of the fused streaming kernels (a reference for testing; slower). */
+  PM_CREATE_REFERENCE_KERNELS = 1
+};
 
 /* Multigrid settings (paper Sect. 3.7.1). */
 typedef struct {
@@ -105,7 +120,9 @@ typedef struct {
 void pm_default_step_params(pm_step_params *p);
 
 /* Create a context for an n^3 grid and up to np_max particles.
- * n must be even, 8 <= n <= 1024. flags: reserved, pass 0.
+ * n must be even, 8 <= n <= 1024, and halving n while it exceeds 16 and is a
+ * multiple of 4 must end at most at 20 (the coarsest multigrid level).
+ * flags: 0 or PM_CREATE_REFERENCE_KERNELS.
  * Errors: PM_ERR_ARG, PM_ERR_SHAPE, PM_ERR_NOMEM, PM_ERR_HIP. */
 int pm_create(pm_ctx **ctx, int n, int64_t np_max, int flags);
 void pm_destroy(pm_ctx *ctx);
@@ -115,8 +132,12 @@ const char *pm_last_error(const pm_ctx *ctx);
  * with the CIC (8 cells) or TSC (27 cells) window, u = position in cell units,
  * and particle weight w = n^3 / np (mean density 1, the paper's normalisation
  * when np = n^3). rho is overwritten.
- * order PM_DEPOSIT_ATOMIC: one thread per particle, FP32 atomic adds (the sum
- *   order, hence the last bits, may differ between runs).
+ * order PM_DEPOSIT_ATOMIC: chunks of 2048 consecutive particles are sorted by
+ *   cell in on-chip memory, every cell of the chunk's box sums its weights in
+ *   registers, and the box is added to rho with one FP32 atomic per cell (the
+ *   sum order across chunks, hence the last bits, may differ between runs).
+ *   Fast when neighbours in memory are neighbours in space (see pm_reorder);
+ *   chunks spread over more than 4096 cells use one atomic per weight.
  * order PM_DEPOSIT_SORTED: particles are bucketed by cell (a counting sort into
  *   context scratch; the caller's arrays are not reordered), then every cell
  *   gathers the contributions of the particles in its 27 (8) neighbour cells
@@ -158,6 +179,18 @@ int pm_interp(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, in
 int pm_accel(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, int poskind,
              double a, const pm_step_params *params, float *phi, float *acc,
              pm_step_stats *stats, pm_stream stream);
+
+/* Reorder the particle arrays in place by cell (paper Sect. 3.2 and App. E:
+ * particles are periodically re-sorted so that neighbours in memory are
+ * neighbours in space; the paper uses a Morton curve). The order is tile-major:
+ * 8^3-cell tiles in row-major order and row-major cells inside a tile (plain
+ * row-major cells when n is not a multiple of 8); particles in the same cell
+ * keep no particular order. pos (and cell for PM_POS_CELLOFF), vel, acc and ids
+ * are permuted together; vel, acc and ids may be NULL. ids is an int64 tag per
+ * particle that lets the caller follow particle identity. Scratch: 12 bytes per
+ * particle plus the sort arrays, allocated on first use. */
+int pm_reorder(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, float *acc, int64_t *ids,
+               int64_t np, int poskind, pm_stream stream);
 
 /* One kick-drift-kick step (Sect. 3.4) from scale factor a0 to a1 in
  * Einstein-de Sitter supercomoving time, tau = 2 (a0^-1/2 - a1^-1/2):

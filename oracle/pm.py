@@ -149,7 +149,7 @@ def _mode_numbers(n):
     return m[:, None, None], m[None, :, None], mh[None, None, :]
 
 
-def solve_exact7(f, h):
+def solve_exact7(f, h, workers=1):
     """Zero-mean solution of the periodic seven-point system laplacian7(phi) = f.
 
     The discrete operator is diagonal in the Fourier basis with eigenvalue
@@ -161,11 +161,11 @@ def solve_exact7(f, h):
     mx, my, mz = _mode_numbers(n)
     lam = -(4.0 / (h * h)) * (np.sin(np.pi * mx / n) ** 2 + np.sin(np.pi * my / n) ** 2
                               + np.sin(np.pi * mz / n) ** 2)
-    fk = sfft.rfftn(f)
+    fk = sfft.rfftn(f, workers=workers)
     lam[0, 0, 0] = 1.0
     phik = fk / lam
     phik[0, 0, 0] = 0.0
-    return sfft.irfftn(phik, s=f.shape)
+    return sfft.irfftn(phik, s=f.shape, workers=workers)
 
 
 def solve_fft(f, h, p=3):

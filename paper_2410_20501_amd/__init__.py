@@ -2,11 +2,11 @@
 
 The compute lives in libhippm.so (hand-written HIP kernels behind include/hippm.h);
 this package is its Python binding. Importing fails loudly if the library has
-not been built: `python -m paper_2410_20501_amd.build`.
+not been built: `python paper_2410_20501_amd/build.py`.
 """
 from .hippm import *  # noqa: F401,F403
 from .hippm import (  # noqa: F401
     Context, PMError, PMWarning, MGParams, MGStats, StepParams, StepStats, EXPORTED,
     default_step_params, pm_create, pm_destroy, pm_deposit, pm_solve_mg, pm_solve_fft,
-    pm_gradient, pm_interp, pm_accel, pm_kdk,
+    pm_gradient, pm_interp, pm_accel, pm_kdk, pm_reorder,
 )

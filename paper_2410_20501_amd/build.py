@@ -1,6 +1,6 @@
 """Build libhippm.so (the HIP library behind include/hippm.h) for gfx950, in-tree.
 
-Usage: python -m paper_2410_20501_amd.build   (or call build()).
+Usage: python paper_2410_20501_amd/build.py   (or __graft_entry__.build()).
 """
 from __future__ import annotations
 
@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhippm.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["api.hip", "particles.hip", "grid.hip", "mg.hip", "fft.hip"]
+SOURCES = ["api.hip", "particles.hip", "grid.hip", "mg.hip", "mg_stream.hip", "fft.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -43,7 +43,8 @@ int check_mg(pm_ctx *ctx, const pm_mg_params *p) {
   if (p->fixed_cycles == 0 && !(p->tol >= 0.0f)) return pm_fail(ctx, PM_ERR_ARG, "bad tol");
   if (p->restrict_kind != PM_RESTRICT_FW && p->restrict_kind != PM_RESTRICT_AVG)
     return pm_fail(ctx, PM_ERR_ARG, "bad restrict_kind");
-  if (p->guess != PM_GUESS_JACOBI && p->guess != PM_GUESS_WARM)
+  if (p->guess != PM_GUESS_JACOBI && p->guess != PM_GUESS_WARM &&
+      p->guess != PM_GUESS_WARM_RESCALED)
     return pm_fail(ctx, PM_ERR_ARG, "bad guess");
   return PM_OK;
 }
@@ -68,7 +69,6 @@ int ensure_sort_scratch(pm_ctx *ctx, int64_t np) {
     const size_t len = (size_t)ncell + 1;
     const int64_t nblk = scan_blocks_needed((int64_t)len);
     if (hipMalloc(&ctx->cell_count, sizeof(int32_t) * len) != hipSuccess ||
-        hipMalloc(&ctx->cell_start, sizeof(int32_t) * len) != hipSuccess ||
         hipMalloc(&ctx->scan_partial, sizeof(int32_t) * (size_t)nblk) != hipSuccess)
       return pm_fail(ctx, PM_ERR_NOMEM, "sort scratch allocation failed");
   }
@@ -93,7 +93,7 @@ int deposit_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np,
   if (order == PM_DEPOSIT_SORTED) {
     int st = ensure_sort_scratch(ctx, np);
     if (st != PM_OK) return st;
-    PM_HIP(ctx, launch_sort_by_cell(ctx, pos, cell, np, poskind, s));
+    PM_HIP(ctx, launch_sort_by_cell(ctx, pos, cell, np, poskind, s, false));
     PM_HIP(ctx, launch_deposit_pull(ctx, pos, np, poskind, mas, mass, rho, s));
     return PM_OK;
   }
@@ -103,21 +103,21 @@ int deposit_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np,
 }
 
 int solve_impl(pm_ctx *ctx, const pm_step_params *p, const float *rho, float coef, float *phi,
-               pm_mg_stats *st, hipStream_t s) {
+               pm_mg_stats *st, hipStream_t s, float warm_scale) {
   if (p->solver == PM_SOLVER_FFT) return pm_fft_solve(ctx, rho, coef, p->fft_deconv, phi, s);
-  return pm_mg_solve(ctx, rho, coef, phi, &p->mg, st, s);
+  return pm_mg_solve(ctx, rho, coef, phi, &p->mg, st, s, warm_scale);
 }
 
 // deposit -> solve -> gradient -> interp (+ optional kick on vel)
 int accel_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, int poskind,
                double a, const pm_step_params *p, float *phi, float *acc, float *vel, float kick,
-               pm_step_stats *stats, hipStream_t s, bool timing) {
+               pm_step_stats *stats, hipStream_t s, bool timing, float warm_scale) {
   if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[1], s));
   int st = deposit_impl(ctx, pos, cell, np, poskind, p->mas, p->order, ctx->rho, s);
   if (st != PM_OK) return st;
   if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[2], s));
   const float coef = (float)(1.5 * a * p->omega_m);
-  const int sst = solve_impl(ctx, p, ctx->rho, coef, phi, stats ? &stats->mg : nullptr, s);
+  const int sst = solve_impl(ctx, p, ctx->rho, coef, phi, stats ? &stats->mg : nullptr, s, warm_scale);
   if (sst < 0) return sst;
   if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[3], s));
   PM_HIP(ctx, launch_gradient(phi, ctx->n, 5, ctx->g, s));
@@ -165,12 +165,12 @@ void pm_default_step_params(pm_step_params *p) {
 int pm_create(pm_ctx **out, int n, int64_t np_max, int flags) {
   if (!out) return PM_ERR_ARG;
   *out = nullptr;
-  (void)flags;
   if (np_max < 0) return PM_ERR_ARG;
   if (n < 8 || n > 1024 || (n & 1)) return PM_ERR_SHAPE;
   pm_ctx *ctx = new pm_ctx();  // value-initialised: every pointer starts null
   ctx->n = n;
   ctx->np_max = np_max;
+  ctx->flags = flags;
   if (hipGetDevice(&ctx->device) != hipSuccess) {
     delete ctx;
     return PM_ERR_HIP;
@@ -179,7 +179,7 @@ int pm_create(pm_ctx **out, int n, int64_t np_max, int flags) {
   int st = PM_OK;
   if (hipMalloc(&ctx->rho, sizeof(float) * ncell) != hipSuccess ||
       hipMalloc(&ctx->g, 3 * sizeof(float) * ncell) != hipSuccess ||
-      hipMalloc(&ctx->red_partial, 2 * sizeof(double) * RED_BLOCKS) != hipSuccess ||
+      hipMalloc(&ctx->red_partial, 2 * sizeof(double) * RED_PARTIAL_CAP) != hipSuccess ||
       hipMalloc(&ctx->red_result, 4 * sizeof(double)) != hipSuccess ||
       hipMalloc(&ctx->mean_f, 4 * sizeof(float)) != hipSuccess ||
       hipHostMalloc(&ctx->host_result, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess)
@@ -207,18 +207,21 @@ void pm_destroy(pm_ctx *ctx) {
   fr(ctx->red_result);
   fr(ctx->mean_f);
   if (ctx->host_result) (void)hipHostFree(ctx->host_result);
-  for (int l = 1; l < ctx->nlevels; ++l) {
-    fr(ctx->lev[l].u);
-    fr(ctx->lev[l].f);
+  for (int l = 0; l < ctx->nlevels; ++l) {
+    if (l > 0) {
+      fr(ctx->lev[l].u);
+      fr(ctx->lev[l].f);
+    }
+    fr(ctx->lev[l].alt);
   }
   fr(ctx->spec);
   fr(ctx->twiddle);
   fr(ctx->fft_tab);
   fr(ctx->cell_count);
-  fr(ctx->cell_start);
   fr(ctx->perm);
   fr(ctx->pcell);
   fr(ctx->scan_partial);
+  fr(ctx->reorder_tmp);
   for (int i = 0; i < 8; ++i)
     if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
   delete ctx;
@@ -245,7 +248,7 @@ int pm_solve_mg(pm_ctx *ctx, const float *rho, float coef, float *phi,
   int st = check_mg(ctx, params);
   if (st != PM_OK) return st;
   if (!std::isfinite(coef)) return pm_fail(ctx, PM_ERR_NONFINITE, "non-finite coef");
-  return pm_mg_solve(ctx, rho, coef, phi, params, stats, (hipStream_t)stream);
+  return pm_mg_solve(ctx, rho, coef, phi, params, stats, (hipStream_t)stream, 1.0f);
 }
 
 int pm_solve_fft(pm_ctx *ctx, const float *rho, float coef, int deconv, float *phi,
@@ -291,9 +294,34 @@ int pm_accel(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, int
   if (!(a > 0.0) || !std::isfinite(a)) return pm_fail(ctx, PM_ERR_ARG, "scale factor must be > 0");
   hipStream_t s = (hipStream_t)stream;
   const bool timing = params->timing && stats;
-  st = accel_impl(ctx, pos, cell, np, poskind, a, params, phi, acc, nullptr, 0.f, stats, s, timing);
+  st = accel_impl(ctx, pos, cell, np, poskind, a, params, phi, acc, nullptr, 0.f, stats, s, timing,
+                  1.0f);
   if (st >= 0 && timing) fill_timing(ctx, stats, false);
   return st;
+}
+
+int pm_reorder(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, float *acc, int64_t *ids,
+               int64_t np, int poskind, pm_stream stream) {
+  if (!ctx) return PM_ERR_ARG;
+  int st = check_particles(ctx, pos, cell, np, poskind);
+  if (st != PM_OK) return st;
+  if (np == 0) return PM_OK;
+  st = ensure_sort_scratch(ctx, np);
+  if (st != PM_OK) return st;
+  if (ctx->reorder_cap < np) {
+    if (ctx->reorder_tmp) (void)hipFree(ctx->reorder_tmp);
+    ctx->reorder_tmp = nullptr;
+    const int64_t cap = std::max<int64_t>(np, ctx->np_max);
+    if (hipMalloc(&ctx->reorder_tmp, 12 * (size_t)cap) != hipSuccess)
+      return pm_fail(ctx, PM_ERR_NOMEM, "reorder scratch allocation failed");
+    ctx->reorder_cap = cap;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const bool tile_major = (ctx->n % 8) == 0;
+  PM_HIP(ctx, launch_sort_by_cell(ctx, pos, cell, np, poskind, s, tile_major));
+  PM_HIP(ctx, launch_apply_perm(ctx, pos, poskind == PM_POS_CELLOFF ? cell : nullptr, vel, acc, ids,
+                                np, s));
+  return PM_OK;
 }
 
 int pm_kdk(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, int64_t np, int poskind,
@@ -314,7 +342,11 @@ int pm_kdk(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, int64_t np, int p
   const float half = (float)(0.5 * tau);
   if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[0], s));
   PM_HIP(ctx, launch_kick_drift(pos, cell, vel, acc, np, poskind, ctx->n, half, (float)tau, s));
-  st = accel_impl(ctx, pos, cell, np, poskind, a1, params, phi, acc, vel, half, stats, s, timing);
+  // growth rescaling of the previous potential: phi~ grows as a D(a) = a^2 in EdS
+  const float warm_scale =
+      params->mg.guess == PM_GUESS_WARM_RESCALED ? (float)((a1 / a0) * (a1 / a0)) : 1.0f;
+  st = accel_impl(ctx, pos, cell, np, poskind, a1, params, phi, acc, vel, half, stats, s, timing,
+                  warm_scale);
   if (st >= 0 && timing) fill_timing(ctx, stats, true);
   return st;
 }

@@ -15,11 +15,15 @@ struct pm_level {
   int n;          // cells per side
   float *u;       // solution / error (level 0: caller's phi)
   float *f;       // right-hand side (level 0: NULL, the source is read from rho)
+  float *alt;     // second buffer for the out-of-place streaming smoother (or NULL)
 };
+
+#define PM_STREAM_MIN_N 128   // levels at least this large use the streaming kernels
 
 struct pm_ctx {
   int n;
   int64_t np_max;
+  int flags;
   int device;
   std::string err;
   // grids
@@ -40,17 +44,19 @@ struct pm_ctx {
   float *fft_tab;        // [2n] per-axis Green's-function tables
   int fft_tab_key;       // which kernel the tables hold
   // counting sort (lazy)
-  int32_t *cell_count;   // [n^3 + 1]
-  int32_t *cell_start;   // [n^3 + 1]
+  int32_t *cell_count;   // [n^3 + 1] counts -> starts -> ends (end of c = start of c + 1)
   int32_t *perm;         // [np_max] particle indices bucketed by cell
   int32_t *pcell;        // [np_max] cell of each particle
   int32_t *scan_partial; // [SCAN_MAX_BLOCKS]
   int64_t sort_cap;
+  void *reorder_tmp;     // [np_max * 12 bytes] permutation staging (lazy)
+  int64_t reorder_cap;
   // timing events
   hipEvent_t ev[8];
 };
 
 #define RED_BLOCKS 1024
+#define RED_PARTIAL_CAP 65536  // partial-sum slots (smoother blocks or reduction blocks)
 #define RED_THREADS 256
 
 // ---------------------------------------------------------------- helpers
@@ -67,7 +73,9 @@ int pm_hip_check(pm_ctx *ctx, hipError_t e, const char *what);
 hipError_t launch_deposit_atomic(const float *pos, const int32_t *cell, int64_t np, int poskind,
                                  int mas, int n, float mass, float *rho, hipStream_t s);
 hipError_t launch_sort_by_cell(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np,
-                               int poskind, hipStream_t s);
+                               int poskind, hipStream_t s, bool tile_major);
+hipError_t launch_apply_perm(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, float *acc,
+                             int64_t *ids, int64_t np, hipStream_t s);
 hipError_t launch_deposit_pull(pm_ctx *ctx, const float *pos, int64_t np, int poskind, int mas,
                                float mass, float *rho, hipStream_t s);
 hipError_t launch_interp(const float *pos, const int32_t *cell, int64_t np, int poskind, int mas,
@@ -83,8 +91,16 @@ hipError_t launch_sum_moments(const float *x, int64_t count, double *partial, do
 
 // mg.hip
 int pm_mg_solve(pm_ctx *ctx, const float *rho, float coef, float *phi, const pm_mg_params *p,
-                pm_mg_stats *stats, hipStream_t s);
+                pm_mg_stats *stats, hipStream_t s, float warm_scale = 1.0f);
 int pm_mg_setup(pm_ctx *ctx);
+
+// mg_stream.hip
+int64_t smooth_stream_blocks(int n);
+hipError_t launch_smooth_stream(const float *uin, float *uout, const float *f, float fscale,
+                                const float *fmean, const float *vc, int n, float h2, float omega,
+                                int first_colour, int half_sweeps, double *partial, hipStream_t s);
+hipError_t launch_rr_stream(const float *u, const float *f, float fscale, const float *fmean,
+                            int n, float inv_h2, int kind, float *fc, hipStream_t s);
 
 // fft.hip
 int pm_fft_solve(pm_ctx *ctx, const float *rho, float coef, int deconv, float *phi,

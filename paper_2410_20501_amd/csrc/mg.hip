@@ -216,6 +216,13 @@ __global__ __launch_bounds__(RED_THREADS) void k_pair_final(const double *__rest
   }
 }
 
+// u *= s (growth rescaling of a warm start).
+__global__ __launch_bounds__(kThreads) void k_scale(float *__restrict__ u, int64_t count, float s) {
+  const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (c >= count) return;
+  u[c] *= s;
+}
+
 // Subtract the device-resident mean from a grid.
 __global__ __launch_bounds__(kThreads) void k_subtract_mean(float *__restrict__ u, int64_t count,
                                                             const float *__restrict__ mean) {
@@ -312,65 +319,117 @@ struct Src {
   const float *mean;
 };
 
+// Host-side V-cycle driver. Levels with n >= PM_STREAM_MIN_N (and an alt buffer)
+// run the streaming kernels with ping-pong buffers: cur[l] holds the current
+// iterate, a smoothing pass writes alt and the two are swapped. Every full
+// V-cycle swaps twice, so level 0 ends in the caller's phi. Smaller levels run
+// one kernel per red-black half-sweep, in place.
 struct Solver {
   pm_ctx *ctx;
   hipStream_t s;
   const pm_mg_params *p;
   Src src0;
+  float *cur[PM_MAX_LEVELS];
+  float *alt[PM_MAX_LEVELS];
 
   Src src(int l) const { return l == 0 ? src0 : Src{ctx->lev[l].f, 1.0f, nullptr}; }
   float h2(int l) const {
     const double h = 1.0 / ctx->lev[l].n;
     return (float)(h * h);
   }
+  bool streaming(int l) const {
+    return alt[l] != nullptr && !(ctx->flags & PM_CREATE_REFERENCE_KERNELS);
+  }
 
-  void smooth(int l, int first_colour, int sweeps) {
+  hipError_t half_sweeps(int l, int first_colour, int sweeps) {
     const int n = ctx->lev[l].n;
     const int64_t half = (int64_t)n * n * (n / 2);
     const Src sr = src(l);
     for (int sw = 0; sw < sweeps; ++sw)
       for (int c = 0; c < 2; ++c)
         k_rbgs_half<<<blocks_for(half, kThreads), kThreads, 0, s>>>(
-            ctx->lev[l].u, sr.f, sr.scale, sr.mean, n, h2(l), p->omega, c ^ first_colour);
+            cur[l], sr.f, sr.scale, sr.mean, n, h2(l), p->omega, c ^ first_colour);
+    return hipGetLastError();
   }
 
-  void coarse(int l) {
+  // streaming smoothing of `sweeps` full sweeps; the first pass may add the
+  // prolongation of vc and/or sum the residual norm of its input.
+  hipError_t stream_sweeps(int l, int first_colour, int sweeps, const float *vc, double *partial) {
+    const int n = ctx->lev[l].n;
     const Src sr = src(l);
-    k_coarse_solve<<<1, kCoarseThreads, 0, s>>>(ctx->lev[l].u, sr.f, sr.scale, sr.mean,
-                                                ctx->lev[l].n, h2(l), 1e-3f, 500);
+    hipError_t e = hipSuccess;
+    while (sweeps > 0 && e == hipSuccess) {
+      const int now = sweeps >= 2 ? 2 : 1;
+      e = launch_smooth_stream(cur[l], alt[l], sr.f, sr.scale, sr.mean, vc, n, h2(l), p->omega,
+                               first_colour, 2 * now, partial, s);
+      std::swap(cur[l], alt[l]);
+      vc = nullptr;
+      partial = nullptr;
+      sweeps -= now;
+    }
+    return e;
   }
 
-  void vcycle(int l) {
-    if (l == ctx->nlevels - 1) {
-      coarse(l);
-      return;
-    }
+  hipError_t pre_smooth(int l) {
+    return streaming(l) ? stream_sweeps(l, 0, p->pre, nullptr, nullptr) : half_sweeps(l, 0, p->pre);
+  }
+
+  hipError_t restrict_residual(int l) {
     const int n = ctx->lev[l].n;
     const int nc = n / 2;
     const int64_t ncount = (int64_t)nc * nc * nc;
-    smooth(l, 0, p->pre);
     const Src sr = src(l);
     const float inv_h2 = 1.0f / h2(l);
-    if (p->restrict_kind == PM_RESTRICT_AVG)
+    if (streaming(l)) {
+      hipError_t e = launch_rr_stream(cur[l], sr.f, sr.scale, sr.mean, n, inv_h2, p->restrict_kind,
+                                      ctx->lev[l + 1].f, s);
+      if (e != hipSuccess) return e;
+    } else if (p->restrict_kind == PM_RESTRICT_AVG) {
       k_residual_restrict<PM_RESTRICT_AVG><<<blocks_for(ncount, kThreads), kThreads, 0, s>>>(
-          ctx->lev[l].u, sr.f, sr.scale, sr.mean, n, inv_h2, ctx->lev[l + 1].f);
-    else
+          cur[l], sr.f, sr.scale, sr.mean, n, inv_h2, ctx->lev[l + 1].f);
+    } else {
       k_residual_restrict<PM_RESTRICT_FW><<<blocks_for(ncount, kThreads), kThreads, 0, s>>>(
-          ctx->lev[l].u, sr.f, sr.scale, sr.mean, n, inv_h2, ctx->lev[l + 1].f);
+          cur[l], sr.f, sr.scale, sr.mean, n, inv_h2, ctx->lev[l + 1].f);
+    }
+    // coarse starting guess: one Jacobi step -H^2 d_H / 6
     k_jacobi_guess<<<blocks_for(ncount, kThreads), kThreads, 0, s>>>(
-        ctx->lev[l + 1].u, ctx->lev[l + 1].f, 1.0f, nullptr, ncount, h2(l + 1));
-    vcycle(l + 1);
-    k_prolong_add<<<blocks_for((int64_t)n * n * n, kThreads), kThreads, 0, s>>>(
-        ctx->lev[l].u, n, ctx->lev[l + 1].u);
-    smooth(l, 1, p->post);
+        cur[l + 1], ctx->lev[l + 1].f, 1.0f, nullptr, ncount, h2(l + 1));
+    return hipGetLastError();
   }
 
-  // ||f - L u||^2 and ||f||^2 at level 0 into ctx->red_result[0..1]
+  hipError_t correct_and_post_smooth(int l) {
+    const int n = ctx->lev[l].n;
+    // (the streaming smoother can also fuse the prolongation, see PROLONG; a
+    //  separate pass is faster on gfx950 because the fused variant spills)
+    k_prolong_add<<<blocks_for((int64_t)n * n * n, kThreads), kThreads, 0, s>>>(cur[l], n,
+                                                                                 cur[l + 1]);
+    if (streaming(l)) return stream_sweeps(l, 1, p->post, nullptr, nullptr);
+    return half_sweeps(l, 1, p->post);
+  }
+
+  hipError_t coarse(int l) {
+    const Src sr = src(l);
+    k_coarse_solve<<<1, kCoarseThreads, 0, s>>>(cur[l], sr.f, sr.scale, sr.mean, ctx->lev[l].n,
+                                                h2(l), 1e-3f, 500);
+    return hipGetLastError();
+  }
+
+  // V-cycle from level l; when pre_done, the pre-smoothing of level l has run.
+  hipError_t vcycle(int l, bool pre_done = false) {
+    if (l == ctx->nlevels - 1) return coarse(l);
+    hipError_t e = pre_done ? hipSuccess : pre_smooth(l);
+    if (e == hipSuccess) e = restrict_residual(l);
+    if (e == hipSuccess) e = vcycle(l + 1);
+    if (e == hipSuccess) e = correct_and_post_smooth(l);
+    return e;
+  }
+
+  // ||f - L u||^2 and ||f||^2 at level 0 into ctx->red_result[0..1] (plain kernel)
   void norms() {
     const int n = ctx->lev[0].n;
     const int64_t count = (int64_t)n * n * n;
     const int nb = (int)std::min<int64_t>(RED_BLOCKS, (count + RED_THREADS - 1) / RED_THREADS);
-    k_residual_norm<<<nb, RED_THREADS, 0, s>>>(ctx->lev[0].u, src0.f, src0.scale, src0.mean, n,
+    k_residual_norm<<<nb, RED_THREADS, 0, s>>>(cur[0], src0.f, src0.scale, src0.mean, n,
                                                1.0f / h2(0), ctx->red_partial);
     k_pair_final<<<1, RED_THREADS, 0, s>>>(ctx->red_partial, nb, ctx->red_result);
   }
@@ -381,73 +440,103 @@ struct Solver {
 int pm_mg_setup(pm_ctx *ctx) {
   int n = ctx->n;
   ctx->nlevels = 0;
-  ctx->lev[0] = pm_level{n, nullptr, nullptr};
+  ctx->lev[0] = pm_level{n, nullptr, nullptr, nullptr};
   ctx->nlevels = 1;
   while (n > 16 && n % 4 == 0) {
     n /= 2;
     if (ctx->nlevels >= PM_MAX_LEVELS) return PM_ERR_SHAPE;
-    pm_level L{n, nullptr, nullptr};
+    pm_level L{n, nullptr, nullptr, nullptr};
     const size_t bytes = sizeof(float) * (size_t)n * n * n;
     if (hipMalloc(&L.u, bytes) != hipSuccess || hipMalloc(&L.f, bytes) != hipSuccess)
       return PM_ERR_NOMEM;
     ctx->lev[ctx->nlevels++] = L;
   }
   if ((int64_t)n * n * n > kCoarseMax) return PM_ERR_SHAPE;
+  // ping-pong buffers for the streaming levels (not the coarsest)
+  for (int l = 0; l + 1 < ctx->nlevels; ++l) {
+    const int m = ctx->lev[l].n;
+    if (m < PM_STREAM_MIN_N || (ctx->flags & PM_CREATE_REFERENCE_KERNELS)) continue;
+    if (smooth_stream_blocks(m) > RED_PARTIAL_CAP) continue;
+    if (hipMalloc(&ctx->lev[l].alt, sizeof(float) * (size_t)m * m * m) != hipSuccess)
+      return PM_ERR_NOMEM;
+  }
   return PM_OK;
 }
 
 int pm_mg_solve(pm_ctx *ctx, const float *rho, float coef, float *phi, const pm_mg_params *p,
-                pm_mg_stats *stats, hipStream_t s) {
+                pm_mg_stats *stats, hipStream_t s, float warm_scale) {
   const int n = ctx->n;
   const int64_t count = (int64_t)n * n * n;
-  ctx->lev[0].u = phi;
   // mean of the density, kept on the device
   PM_HIP(ctx, launch_sum_moments(rho, count, ctx->red_partial, ctx->red_result, ctx->mean_f, s));
-  Solver sv{ctx, s, p, Src{rho, coef, ctx->mean_f}};
-  if (p->guess != PM_GUESS_WARM)
+  Solver sv{ctx, s, p, Src{rho, coef, ctx->mean_f}, {}, {}};
+  for (int l = 0; l < ctx->nlevels; ++l) {
+    sv.cur[l] = l == 0 ? phi : ctx->lev[l].u;
+    sv.alt[l] = ctx->lev[l].alt;
+  }
+  if (p->guess == PM_GUESS_JACOBI)
     k_jacobi_guess<<<blocks_for(count, kThreads), kThreads, 0, s>>>(phi, rho, coef, ctx->mean_f,
                                                                      count, sv.h2(0));
+  else if (warm_scale != 1.0f)
+    k_scale<<<blocks_for(count, kThreads), kThreads, 0, s>>>(phi, count, warm_scale);
+  const bool fused_norm = sv.streaming(0) && p->pre > 0 && ctx->nlevels > 1;
   int status = PM_OK;
   int cycles = 0;
   if (p->fixed_cycles > 0) {
-    for (int c = 0; c < p->fixed_cycles; ++c) sv.vcycle(0);
+    for (int c = 0; c < p->fixed_cycles; ++c) PM_HIP(ctx, sv.vcycle(0));
     cycles = p->fixed_cycles;
   } else {
     double rel[64];
-    sv.norms();
-    PM_HIP(ctx, hipMemcpyAsync(ctx->host_result, ctx->red_result, 2 * sizeof(double),
-                               hipMemcpyDeviceToHost, s));
-    PM_HIP(ctx, hipStreamSynchronize(s));
-    const double fnorm = sqrt(ctx->host_result[1]);
-    if (fnorm == 0.0) {
-      PM_HIP(ctx, hipMemsetAsync(phi, 0, sizeof(float) * count, s));
-      if (stats) {
-        stats->cycles = 0;
-        stats->status = PM_OK;
-        stats->relres[0] = 0.0;
-      }
-      return PM_OK;
-    }
-    rel[0] = sqrt(ctx->host_result[0]) / fnorm;
+    double fnorm = 0.0;
     status = PM_WARN_NOT_CONVERGED;
-    if (rel[0] < p->tol) status = PM_OK;
-    while (status == PM_WARN_NOT_CONVERGED && cycles < p->max_cycles) {
-      sv.vcycle(0);
-      ++cycles;
-      sv.norms();
+    for (;;) {
+      // residual norm of the current iterate: fused into the next pre-smoothing
+      // pass when streaming (its output is used only if another cycle is needed)
+      if (fused_norm) {
+        const int64_t nb = smooth_stream_blocks(n);
+        PM_HIP(ctx, sv.stream_sweeps(0, 0, std::min(p->pre, 2), nullptr, ctx->red_partial));
+        k_pair_final<<<1, RED_THREADS, 0, s>>>(ctx->red_partial, (int)nb, ctx->red_result);
+      } else {
+        sv.norms();
+      }
       PM_HIP(ctx, hipMemcpyAsync(ctx->host_result, ctx->red_result, 2 * sizeof(double),
                                  hipMemcpyDeviceToHost, s));
       PM_HIP(ctx, hipStreamSynchronize(s));
+      if (cycles == 0) fnorm = sqrt(ctx->host_result[1]);
+      if (fnorm == 0.0) {
+        if (fused_norm) std::swap(sv.cur[0], sv.alt[0]);  // drop the speculative pass
+        PM_HIP(ctx, hipMemsetAsync(phi, 0, sizeof(float) * count, s));
+        if (stats) {
+          stats->cycles = 0;
+          stats->status = PM_OK;
+          stats->relres[0] = 0.0;
+        }
+        return PM_OK;
+      }
       rel[cycles] = sqrt(ctx->host_result[0]) / fnorm;
       if (rel[cycles] < p->tol) {
         status = PM_OK;
-      } else if (rel[cycles] < 1e-4 && rel[cycles - 1] < 1.5 * rel[cycles]) {
+      } else if (cycles > 0 && rel[cycles] < 1e-4 && rel[cycles - 1] < 1.5 * rel[cycles]) {
         status = PM_WARN_FLOOR;
       }
+      if (status != PM_WARN_NOT_CONVERGED || cycles == p->max_cycles) {
+        if (fused_norm) std::swap(sv.cur[0], sv.alt[0]);  // keep the tested iterate
+        break;
+      }
+      if (fused_norm) {
+        // finish the cycle whose pre-smoothing already ran (remaining pre sweeps first)
+        if (p->pre > 2) PM_HIP(ctx, sv.stream_sweeps(0, 0, p->pre - 2, nullptr, nullptr));
+        PM_HIP(ctx, sv.vcycle(0, true));
+      } else {
+        PM_HIP(ctx, sv.vcycle(0));
+      }
+      ++cycles;
     }
     if (stats)
       for (int c = 0; c <= cycles; ++c) stats->relres[c] = rel[c];
   }
+  if (sv.cur[0] != phi)
+    PM_HIP(ctx, hipMemcpyAsync(phi, sv.cur[0], sizeof(float) * count, hipMemcpyDeviceToDevice, s));
   // remove the mean of phi (gauge)
   PM_HIP(ctx, launch_sum_moments(phi, count, ctx->red_partial, ctx->red_result, ctx->mean_f + 1, s));
   k_subtract_mean<<<blocks_for(count, kThreads), kThreads, 0, s>>>(phi, count, ctx->mean_f + 1);

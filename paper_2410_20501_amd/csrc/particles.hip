@@ -224,30 +224,319 @@ __global__ __launch_bounds__(kThreads) void k_kick_drift(float *__restrict__ pos
 
 // ------------------------------------------------------------------ counting sort
 
-// Cell containing each particle; histogram of cells.
-template <int PK>
+// Tile-major cell key: 8^3-cell tiles in row-major order, cells row-major inside
+// a tile (a bijection of [0, n^3) when n is a multiple of 8).
+__device__ __forceinline__ int tile_key(int ci, int cj, int ck, int n) {
+  const int nt = n >> 3;
+  return ((((ci >> 3) * nt + (cj >> 3)) * nt + (ck >> 3)) << 9) +
+         ((((ci & 7) << 3) + (cj & 7)) << 3) + (ck & 7);
+}
+
+// Runs of equal keys among the lanes of a wave (particles that are neighbours in
+// memory often share a cell): head lanes start a run; run length and head lane
+// of every lane come from the ballot of heads.
+struct WaveRun {
+  bool head;
+  int len;       // run length (valid on head lanes)
+  int headlane;  // lane that starts this lane's run
+};
+
+__device__ __forceinline__ WaveRun wave_runs(int key) {
+  const int lane = threadIdx.x & 63;
+  const int prev = __shfl_up(key, 1, 64);
+  WaveRun r;
+  r.head = (lane == 0) || (prev != key);
+  const unsigned long long heads = __ballot(r.head);
+  const unsigned long long above = lane == 63 ? 0ull : (heads & ~((2ull << lane) - 1ull));
+  const int next = above ? (__ffsll((long long)above) - 1) : 64;
+  r.len = next - lane;
+  const unsigned long long upto = heads & ((lane == 63) ? ~0ull : ((2ull << lane) - 1ull));
+  r.headlane = 63 - __clzll((long long)upto);
+  return r;
+}
+
+// Cell containing each particle (as a row-major or tile-major key); histogram with
+// one atomic per run of equal keys in a wave.
+template <int PK, bool TILE>
 __global__ __launch_bounds__(kThreads) void k_cell_hist(const float *__restrict__ pos,
                                                         const int32_t *__restrict__ cell,
                                                         int64_t np, int n,
                                                         int32_t *__restrict__ pcell,
                                                         int32_t *__restrict__ count) {
   const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  int c = -1;
+  if (p < np) {
+    int q[3];
+    if constexpr (PK == PM_POS_BOX) {
+      const float fn = (float)n;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) q[d] = wrap_any((int)floorf(pos[3 * p + d] * fn), n);
+    } else {
+      const int cc = wrap_any(cell[p], n * n * n);
+      q[0] = cc / (n * n);
+      q[1] = (cc / n) - q[0] * n;
+      q[2] = cc - (cc / n) * n;
+    }
+    c = TILE ? tile_key(q[0], q[1], q[2], n) : (q[0] * n + q[1]) * n + q[2];
+    pcell[p] = c;
+  }
+  const WaveRun r = wave_runs(c);
+  if (r.head && c >= 0) atomicAdd(&count[c], r.len);
+}
+
+// dst[p] = src[perm[p]] for W elements of type T per particle.
+template <typename T, int W>
+__global__ __launch_bounds__(kThreads) void k_gather_perm(const T *__restrict__ src,
+                                                          const int32_t *__restrict__ perm,
+                                                          int64_t np, T *__restrict__ dst) {
+  const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (p >= np) return;
-  int c;
+  const int64_t q = perm[p];
+#pragma unroll
+  for (int w = 0; w < W; ++w) dst[W * p + w] = src[W * q + w];
+}
+
+// ------------------------------------------------------------------ chunked gather deposit
+
+// A block deposits a chunk of 2048 consecutive particles without per-weight
+// atomics:
+//   1. the particles' cells are taken relative to the chunk's first particle
+//      (minimum image) and their bounding box P is found;
+//   2. the particles are counting-sorted by cell of P inside LDS (two integer
+//      LDS atomics per particle), keeping only their in-cell offsets;
+//   3. every cell of P grown by one cell per side (the window's reach) sums,
+//      in registers, the window values of the particles in its 27 neighbour
+//      cells of P; the separation along an axis is (q - c) + o - 1/2 with
+//      q - c in {-1, 0, 1} and o the in-cell offset;
+//   4. non-zero sums are added to the grid with one global atomic per cell.
+// Chunks whose cell box exceeds the LDS table fall back to one global atomic
+// per weight. With particles ordered by tile (pm_reorder) a chunk spans a few
+// tiles, so its box is compact.
+constexpr int kGThreads = 256;
+constexpr int kGPPT = 8;
+constexpr int kGChunk = kGThreads * kGPPT;
+constexpr int kGCells = 4096;  // max cells of the particle box P
+
+__device__ __forceinline__ int min_image(int d, int n) { return wrap_any(d + n / 2, n) - n / 2; }
+
+__device__ __forceinline__ int wave_min_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+template <int MAS>
+__device__ __forceinline__ float window_sep_g(float s) {
+  const float a = fabsf(s);
+  if constexpr (MAS == 3) {
+    if (a < 0.5f) return 0.75f - a * a;
+    const float b = 1.5f - a;
+    return a < 1.5f ? 0.5f * b * b : 0.0f;
+  } else {
+    return a < 1.0f ? 1.0f - a : 0.0f;
+  }
+}
+
+// Cell (wrapped) and in-cell offset of particle p.
+template <int PK>
+__device__ __forceinline__ void particle_cell(const float *__restrict__ pos,
+                                              const int32_t *__restrict__ cell, int64_t p, int n,
+                                              int c[3], float o[3]) {
   if constexpr (PK == PM_POS_BOX) {
     const float fn = (float)n;
-    int q[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      int i = (int)floorf(pos[3 * p + d] * fn);
-      q[d] = wrap_any(i, n);
+      const float u = pos[3 * p + d] * fn;
+      const float fl = floorf(u);
+      c[d] = wrap_any((int)fl, n);
+      o[d] = u - fl;
     }
-    c = (q[0] * n + q[1]) * n + q[2];
   } else {
-    c = wrap_any(cell[p], n * n * n);
+    const int q = wrap_any(cell[p], n * n * n);
+    c[0] = q / (n * n);
+    c[1] = (q / n) - c[0] * n;
+    c[2] = q - (q / n) * n;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) o[d] = pos[3 * p + d];
   }
-  pcell[p] = c;
-  atomicAdd(&count[c], 1);
+}
+
+template <int MAS, int PK>
+__global__ __launch_bounds__(kGThreads) void k_deposit_chunk(const float *__restrict__ pos,
+                                                             const int32_t *__restrict__ cell,
+                                                             int64_t np, int n, float mass,
+                                                             float *__restrict__ rho) {
+  __shared__ float so[3][kGChunk];        // sorted in-cell offsets
+  __shared__ int cstart[kGCells + 1];     // cell counts, then starts, then cursors
+  __shared__ int red[6][kGThreads / 64];
+  __shared__ int wsum[kGThreads / 64];
+  const int64_t base = (int64_t)blockIdx.x * kGChunk;
+  int ref[3];
+  {
+    float o[3];
+    particle_cell<PK>(pos, cell, base, n, ref, o);
+  }
+  int lc[kGPPT][3];
+  float lo_f[kGPPT][3];
+  int lo[3] = {n, n, n}, hi[3] = {-n, -n, -n};
+#pragma unroll
+  for (int m = 0; m < kGPPT; ++m) {
+    const int64_t p = base + threadIdx.x + m * kGThreads;
+    int c[3] = {0, 0, 0};
+    float o[3] = {0.f, 0.f, 0.f};
+    if (p < np) particle_cell<PK>(pos, cell, p, n, c, o);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int d = min_image(c[a] - ref[a], n);
+      lc[m][a] = d;
+      lo_f[m][a] = o[a];
+      if (p < np) {
+        lo[a] = min(lo[a], d);
+        hi[a] = max(hi[a], d);
+      }
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int l = wave_min_i(lo[a]), h = wave_max_i(hi[a]);
+    if (lane == 0) {
+      red[a][wave] = l;
+      red[3 + a][wave] = h;
+    }
+  }
+  __syncthreads();
+  int e[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    int l = red[a][0], h = red[3 + a][0];
+    for (int w = 1; w < kGThreads / 64; ++w) {
+      l = min(l, red[a][w]);
+      h = max(h, red[3 + a][w]);
+    }
+    lo[a] = l;
+    e[a] = h - l + 1;
+  }
+  const int vol = e[0] * e[1] * e[2];
+  if (vol > kGCells) {
+    // fallback: global atomics per weight
+#pragma unroll 1
+    for (int m = 0; m < kGPPT; ++m) {
+      const int64_t p = base + threadIdx.x + m * kGThreads;
+      if (p >= np) break;
+      int f[3];
+      float w[3][MAS];
+      particle_support<MAS, PK>(pos, cell, p, n, f, w);
+      for (int a = 0; a < MAS; ++a) {
+        const size_t ia = (size_t)wrap_index(f[0] + a, n) * n;
+        for (int b = 0; b < MAS; ++b) {
+          const size_t row = (ia + wrap_index(f[1] + b, n)) * n;
+          const float wab = mass * w[0][a] * w[1][b];
+          for (int c = 0; c < MAS; ++c)
+            unsafeAtomicAdd(&rho[row + wrap_index(f[2] + c, n)], wab * w[2][c]);
+        }
+      }
+    }
+    return;
+  }
+  // 2. counting sort by local cell
+  for (int i = threadIdx.x; i <= vol; i += kGThreads) cstart[i] = 0;
+  __syncthreads();
+  int key[kGPPT];
+#pragma unroll
+  for (int m = 0; m < kGPPT; ++m) {
+    const int64_t p = base + threadIdx.x + m * kGThreads;
+    key[m] = -1;
+    if (p < np) {
+      key[m] = ((lc[m][0] - lo[0]) * e[1] + (lc[m][1] - lo[1])) * e[2] + (lc[m][2] - lo[2]);
+      atomicAdd(&cstart[key[m]], 1);
+    }
+  }
+  __syncthreads();
+  // exclusive scan of cstart[0 .. vol) (kGCells / kGThreads = 16 entries per thread)
+  {
+    constexpr int PER = kGCells / kGThreads;
+    const int b0 = threadIdx.x * PER;
+    int v[PER];
+    int tot = 0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      v[i] = (b0 + i < vol) ? cstart[b0 + i] : 0;
+      tot += v[i];
+    }
+    int x = tot;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    int woff = 0;
+    for (int w = 0; w < wave; ++w) woff += wsum[w];
+    int run = x - tot + woff;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      if (b0 + i < vol) cstart[b0 + i] = run;
+      run += v[i];
+    }
+    __syncthreads();
+  }
+  // scatter offsets: the cursor of a cell is its start, advanced atomically
+#pragma unroll
+  for (int m = 0; m < kGPPT; ++m) {
+    if (key[m] < 0) continue;
+    const int slot = atomicAdd(&cstart[key[m]], 1);
+    so[0][slot] = lo_f[m][0];
+    so[1][slot] = lo_f[m][1];
+    so[2][slot] = lo_f[m][2];
+  }
+  __syncthreads();
+  // after the scatter cstart[c] is the end of cell c, i.e. the start of cell c+1;
+  // the start of cell c is cstart[c-1] (0 for c = 0)
+  // 3. gather into the grown box, 4. flush
+  const int g0 = e[0] + 2, g1 = e[1] + 2, g2 = e[2] + 2;
+  const int gvol = g0 * g1 * g2;
+  for (int t = threadIdx.x; t < gvol; t += kGThreads) {
+    const int x = t / (g1 * g2), r = t - x * (g1 * g2);
+    const int y = r / g2, z = r - y * g2;
+    // target cell in P coordinates: (x-1, y-1, z-1)
+    float acc = 0.0f;
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) {
+      const int qx = x - 1 + dx;
+      if (qx < 0 || qx >= e[0]) continue;
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy) {
+        const int qy = y - 1 + dy;
+        if (qy < 0 || qy >= e[1]) continue;
+        const int row = (qx * e[1] + qy) * e[2];
+        const float wxy_dx = (float)dx - 0.5f, wxy_dy = (float)dy - 0.5f;
+#pragma unroll
+        for (int dz = -1; dz <= 1; ++dz) {
+          const int qz = z - 1 + dz;
+          if (qz < 0 || qz >= e[2]) continue;
+          const int q = row + qz;
+          const int s0 = q > 0 ? cstart[q - 1] : 0, s1 = cstart[q];
+          for (int sidx = s0; sidx < s1; ++sidx) {
+            acc += window_sep_g<MAS>(wxy_dx + so[0][sidx]) * window_sep_g<MAS>(wxy_dy + so[1][sidx]) *
+                   window_sep_g<MAS>((float)dz - 0.5f + so[2][sidx]);
+          }
+        }
+      }
+    }
+    if (acc != 0.0f) {
+      const int gi = wrap_any(ref[0] + lo[0] + x - 1, n);
+      const int gj = wrap_any(ref[1] + lo[1] + y - 1, n);
+      const int gk = wrap_any(ref[2] + lo[2] + z - 1, n);
+      unsafeAtomicAdd(&rho[((size_t)gi * n + gj) * n + gk], mass * acc);
+    }
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void k_scatter_perm(const int32_t *__restrict__ pcell,
@@ -255,9 +544,12 @@ __global__ __launch_bounds__(kThreads) void k_scatter_perm(const int32_t *__rest
                                                            int32_t *__restrict__ cursor,
                                                            int32_t *__restrict__ perm) {
   const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (p >= np) return;
-  const int slot = atomicAdd(&cursor[pcell[p]], 1);
-  perm[slot] = (int32_t)p;
+  const int c = p < np ? pcell[p] : -1;
+  const WaveRun r = wave_runs(c);
+  int base = 0;
+  if (r.head && c >= 0) base = atomicAdd(&cursor[c], r.len);
+  base = __shfl(base, r.headlane, 64);
+  if (c >= 0) perm[base + ((int)(threadIdx.x & 63) - r.headlane)] = (int32_t)p;
 }
 
 // Exclusive scan of `count` (len entries) into `start`, in three passes.
@@ -298,7 +590,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t *__r
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
   int s = 0;
   for (int i = threadIdx.x; i < kScanTile; i += kScanThreads) {
-    int64_t idx = base + i;
+    const int64_t idx = base + i;
     if (idx < len) s += in[idx];
   }
   __shared__ int lds[kScanThreads / 64 + 1];
@@ -321,30 +613,35 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partials(int32_t *__restr
   }
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int32_t *__restrict__ in,
+// In-place exclusive scan of one tile: coalesced loads into LDS, per-thread scan of
+// kScanItems consecutive entries, block scan of the thread totals.
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(int32_t *__restrict__ data,
                                                              int64_t len,
-                                                             const int32_t *__restrict__ partial,
-                                                             int32_t *__restrict__ out,
-                                                             int32_t *__restrict__ out2) {
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-  int v[kScanItems];
-  int s = 0;
-#pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
-    v[i] = (base + i < len) ? in[base + i] : 0;
-    s += v[i];
-  }
+                                                             const int32_t *__restrict__ partial) {
+  __shared__ int tile[kScanTile + kScanTile / 32];  // padded against bank conflicts
   __shared__ int lds[kScanThreads / 64 + 1];
-  int total;
-  int ex = block_exclusive_scan(s, lds, total) + partial[blockIdx.x];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  auto pad = [](int i) { return i + (i >> 5); };
+  for (int i = threadIdx.x; i < kScanTile; i += kScanThreads)
+    tile[pad(i)] = (base + i < len) ? data[base + i] : 0;
+  __syncthreads();
+  int v[kScanItems];
+  int sum = 0;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
-    if (base + i < len) {
-      out[base + i] = ex;
-      if (out2) out2[base + i] = ex;
-    }
+    v[i] = tile[pad(threadIdx.x * kScanItems + i)];
+    sum += v[i];
+  }
+  int total;
+  int ex = block_exclusive_scan(sum, lds, total) + partial[blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    tile[pad(threadIdx.x * kScanItems + i)] = ex;
     ex += v[i];
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kScanTile; i += kScanThreads)
+    if (base + i < len) data[base + i] = tile[pad(i)];
 }
 
 // ------------------------------------------------------------------ gathered deposit
@@ -387,7 +684,7 @@ __global__ __launch_bounds__(kThreads) void k_deposit_pull(const float *__restri
       for (int dk = -1; dk <= 1; ++dk) {
         const int qk = wrap_index(ck + dk, n);
         const int q = (qi * n + qj) * n + qk;
-        const int s0 = start[q], s1 = start[q + 1];
+        const int s0 = q > 0 ? start[q - 1] : 0, s1 = start[q];  // `start` holds cell ends
         for (int s = s0; s < s1; ++s) {
           const int p = perm[s];
           float o[3];
@@ -412,6 +709,216 @@ __global__ __launch_bounds__(kThreads) void k_deposit_pull(const float *__restri
   rho[c] = (float)((double)acc * (1.0 / kFixScale) * (double)mass);
 }
 
+// ------------------------------------------------------------------ tile-owned deposit
+
+// One block owns an 8^3 tile of output cells and reads the particles of the
+// tile's 10^3 halo cells through the per-cell ranges of the counting sort. A
+// particle in cell q adds to output cell t = q - D (D in {-1,0,1}^3) the weight
+// prod_d W(D_d + o_d - 1/2), o its in-cell offset. Weights are rounded to
+// multiples of 2^-30 and summed in 64-bit integers held in LDS (integer LDS
+// atomics are an order of magnitude faster than FP32 ones on this GPU, and the
+// integer sum is exact, so the grid is bitwise reproducible):
+//   * particles of sparse halo cells (<= kDense) add their in-tile weights with
+//     one LDS atomic each;
+//   * the particles of a dense halo cell are first reduced by one wave to the
+//     cell's 27 window moments M_q[D] = sum_p prod_d W(D_d + o_pd - 1/2), which
+//     are then added to the tile (avoiding 64 lanes updating the same words).
+// Every output cell is written once: no atomics on the grid.
+constexpr int kTT = 8;                        // tile edge
+constexpr int kTThreads = kTT * kTT * kTT;    // 512
+constexpr int kTH = kTT + 2;                  // halo edge
+constexpr int kTHalo = kTH * kTH * kTH;       // 1000
+constexpr int kDense = 32;                    // particles above which a cell is dense
+constexpr float kFix30 = 1073741824.0f;       // 2^30 units per unit weight
+
+__device__ __forceinline__ unsigned long long fix30(float w) {
+  // 0 <= w <= 27/64 < 2: w 2^30 fits an int32; rounding to 2^-30 keeps every bit
+  // of the FP32 weight above 2^-30
+  return (unsigned long long)(unsigned int)rintf(w * kFix30);
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_ull(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+template <int PK>
+__device__ __forceinline__ void load_offset(const float *__restrict__ pos, int64_t p, int n,
+                                            float o[3]) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    float x = pos[3 * p + d];
+    if constexpr (PK == PM_POS_BOX) {
+      const float u = x * (float)n;
+      x = u - floorf(u);
+    }
+    o[d] = x;
+  }
+}
+
+template <int MAS, int PK>
+__global__ __launch_bounds__(kTThreads) void k_deposit_tile(const float *__restrict__ pos,
+                                                            const int32_t *__restrict__ start,
+                                                            const int32_t *__restrict__ perm,
+                                                            int n, float mass,
+                                                            float *__restrict__ rho) {
+  __shared__ unsigned long long accum[kTThreads];
+  __shared__ int lstart[kTHalo + 1];     // local starts of the sparse halo cells
+  __shared__ int gstart[kTHalo];         // global starts (in the sorted order)
+  __shared__ int gcount[kTHalo];         // particle counts
+  __shared__ short dlist[kTHalo];        // dense halo cells
+  __shared__ int wsum[kTThreads / 64];
+  __shared__ int wdense[kTThreads / 64];
+  const int nt = n / kTT;
+  const int tile = blockIdx.x;
+  const int tk = tile % nt, tj = (tile / nt) % nt, ti = tile / (nt * nt);
+  const int i0 = ti * kTT - 1, j0 = tj * kTT - 1, k0 = tk * kTT - 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  accum[threadIdx.x] = 0ull;
+
+  // 1. halo cell ranges (two per thread); sparse counts are scanned, dense cells listed
+  int cnt[2], gs[2];
+  bool dn[2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int h = threadIdx.x * 2 + r;
+    cnt[r] = 0;
+    gs[r] = 0;
+    if (h < kTHalo) {
+      const int hx = h / (kTH * kTH), hy = (h / kTH) % kTH, hz = h % kTH;
+      const int g = (wrap_index(i0 + hx, n) * n + wrap_index(j0 + hy, n)) * n + wrap_index(k0 + hz, n);
+      gs[r] = g > 0 ? start[g - 1] : 0;   // `start` holds cell ends: end[g] = start of g + 1
+      cnt[r] = start[g] - gs[r];
+      gstart[h] = gs[r];
+      gcount[h] = cnt[r];
+    }
+    dn[r] = cnt[r] > kDense;
+  }
+  const int sp0 = dn[0] ? 0 : cnt[0], sp1 = dn[1] ? 0 : cnt[1];
+  const int tot = sp0 + sp1, dtot = (int)dn[0] + (int)dn[1];
+  int x = tot, y = dtot;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int xs = __shfl_up(x, o, 64), ys = __shfl_up(y, o, 64);
+    if (lane >= o) {
+      x += xs;
+      y += ys;
+    }
+  }
+  if (lane == 63) {
+    wsum[wave] = x;
+    wdense[wave] = y;
+  }
+  __syncthreads();
+  int woff = 0, all = 0, doff = 0, ndense = 0;
+  for (int w = 0; w < kTThreads / 64; ++w) {
+    if (w < wave) {
+      woff += wsum[w];
+      doff += wdense[w];
+    }
+    all += wsum[w];
+    ndense += wdense[w];
+  }
+  {
+    const int h = threadIdx.x * 2;
+    int ex = x - tot + woff, dx = y - dtot + doff;
+    if (h < kTHalo) {
+      lstart[h] = ex;
+      if (dn[0]) dlist[dx++] = (short)h;
+    }
+    if (h + 1 < kTHalo) {
+      lstart[h + 1] = ex + sp0;
+      if (dn[1]) dlist[dx] = (short)(h + 1);
+    }
+    if (threadIdx.x == 0) lstart[kTHalo] = all;
+  }
+  __syncthreads();
+
+  // 2. sparse particles: one per thread at a time, in-tile weights added to LDS;
+  //    the slot's halo cell comes from a binary search in the local starts
+  for (int l = threadIdx.x; l < all; l += kTThreads) {
+    int lo_h = 0, hi_h = kTHalo;  // h with lstart[h] <= l < lstart[h + 1]
+    while (hi_h - lo_h > 1) {
+      const int mid = (lo_h + hi_h) >> 1;
+      if (lstart[mid] <= l) lo_h = mid; else hi_h = mid;
+    }
+    const int h = lo_h;
+    float o[3];
+    load_offset<PK>(pos, perm[gstart[h] + (l - lstart[h])], n, o);
+    const int hx = h / (kTH * kTH), hy = (h / kTH) % kTH, hz = h % kTH;
+    float wx[3], wy[3], wz[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      wx[t] = window_sep<MAS>((float)(t - 1) + o[0] - 0.5f);
+      wy[t] = window_sep<MAS>((float)(t - 1) + o[1] - 0.5f);
+      wz[t] = window_sep<MAS>((float)(t - 1) + o[2] - 0.5f);
+    }
+    // target t = q - D in tile coordinates: (hx - 1) - (a - 1) = hx - a
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int tx = hx - a;
+      if (tx < 0 || tx >= kTT) continue;
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const int ty = hy - b;
+        if (ty < 0 || ty >= kTT) continue;
+        const float wab = wx[a] * wy[b];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const int tz = hz - c;
+          if (tz < 0 || tz >= kTT) continue;
+          const unsigned long long v = fix30(wab * wz[c]);
+          if (v) atomicAdd(&accum[(tx * kTT + ty) * kTT + tz], v);
+        }
+      }
+    }
+  }
+
+  // 3. dense cells: one wave reduces a cell's particles to 27 moments, then lanes
+  //    0..26 add them to the in-tile targets
+  for (int di = wave; di < ndense; di += kTThreads / 64) {
+    const int h = dlist[di];
+    const int g0 = gstart[h], c = gcount[h];
+    unsigned long long m[27];
+#pragma unroll
+    for (int q = 0; q < 27; ++q) m[q] = 0ull;
+    for (int l = lane; l < c; l += 64) {
+      float o[3];
+      load_offset<PK>(pos, perm[g0 + l], n, o);
+      float wx[3], wy[3], wz[3];
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        wx[t] = window_sep<MAS>((float)(t - 1) + o[0] - 0.5f);
+        wy[t] = window_sep<MAS>((float)(t - 1) + o[1] - 0.5f);
+        wz[t] = window_sep<MAS>((float)(t - 1) + o[2] - 0.5f);
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          const float wab = wx[a] * wy[b];
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc) m[(a * 3 + b) * 3 + cc] += fix30(wab * wz[cc]);
+        }
+    }
+    const int hx = h / (kTH * kTH), hy = (h / kTH) % kTH, hz = h % kTH;
+#pragma unroll
+    for (int q = 0; q < 27; ++q) {
+      const unsigned long long v = wave_sum_ull(m[q]);
+      const int a = q / 9, b = (q / 3) % 3, cc = q % 3;
+      const int tx = hx - a, ty = hy - b, tz = hz - cc;
+      if (lane == 0 && tx >= 0 && tx < kTT && ty >= 0 && ty < kTT && tz >= 0 && tz < kTT)
+        atomicAdd(&accum[(tx * kTT + ty) * kTT + tz], v);
+    }
+  }
+  __syncthreads();
+  const int cx = threadIdx.x / (kTT * kTT), cy = (threadIdx.x / kTT) % kTT, cz = threadIdx.x % kTT;
+  const int gi = ti * kTT + cx, gj = tj * kTT + cy, gk = tk * kTT + cz;
+  rho[((size_t)gi * n + gj) * n + gk] =
+      (float)((double)accum[threadIdx.x] * (1.0 / 1073741824.0) * (double)mass);
+}
+
 inline unsigned blocks_for(int64_t count, int threads) {
   return (unsigned)((count + threads - 1) / threads);
 }
@@ -421,17 +928,17 @@ inline unsigned blocks_for(int64_t count, int threads) {
 hipError_t launch_deposit_atomic(const float *pos, const int32_t *cell, int64_t np, int poskind,
                                  int mas, int n, float mass, float *rho, hipStream_t s) {
   if (np == 0) return hipSuccess;
-  const unsigned nb = blocks_for(np, kThreads);
+  const unsigned nb = blocks_for(np, kGChunk);
   if (mas == PM_TSC) {
     if (poskind == PM_POS_BOX)
-      k_deposit_atomic<3, PM_POS_BOX><<<nb, kThreads, 0, s>>>(pos, cell, np, n, mass, rho);
+      k_deposit_chunk<3, PM_POS_BOX><<<nb, kGThreads, 0, s>>>(pos, cell, np, n, mass, rho);
     else
-      k_deposit_atomic<3, PM_POS_CELLOFF><<<nb, kThreads, 0, s>>>(pos, cell, np, n, mass, rho);
+      k_deposit_chunk<3, PM_POS_CELLOFF><<<nb, kGThreads, 0, s>>>(pos, cell, np, n, mass, rho);
   } else {
     if (poskind == PM_POS_BOX)
-      k_deposit_atomic<2, PM_POS_BOX><<<nb, kThreads, 0, s>>>(pos, cell, np, n, mass, rho);
+      k_deposit_chunk<2, PM_POS_BOX><<<nb, kGThreads, 0, s>>>(pos, cell, np, n, mass, rho);
     else
-      k_deposit_atomic<2, PM_POS_CELLOFF><<<nb, kThreads, 0, s>>>(pos, cell, np, n, mass, rho);
+      k_deposit_chunk<2, PM_POS_CELLOFF><<<nb, kGThreads, 0, s>>>(pos, cell, np, n, mass, rho);
   }
   return hipGetLastError();
 }
@@ -467,7 +974,7 @@ hipError_t launch_kick_drift(float *pos, int32_t *cell, float *vel, const float 
 }
 
 hipError_t launch_sort_by_cell(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np,
-                               int poskind, hipStream_t s) {
+                               int poskind, hipStream_t s, bool tile_major) {
   const int n = ctx->n;
   const int64_t ncell = (int64_t)n * n * n;
   const int64_t len = ncell + 1;
@@ -475,19 +982,28 @@ hipError_t launch_sort_by_cell(pm_ctx *ctx, const float *pos, const int32_t *cel
   if (e != hipSuccess) return e;
   if (np > 0) {
     const unsigned nb = blocks_for(np, kThreads);
-    if (poskind == PM_POS_BOX)
-      k_cell_hist<PM_POS_BOX><<<nb, kThreads, 0, s>>>(pos, cell, np, n, ctx->pcell,
-                                                        ctx->cell_count);
-    else
-      k_cell_hist<PM_POS_CELLOFF><<<nb, kThreads, 0, s>>>(pos, cell, np, n, ctx->pcell,
-                                                            ctx->cell_count);
+    if (tile_major) {
+      if (poskind == PM_POS_BOX)
+        k_cell_hist<PM_POS_BOX, true><<<nb, kThreads, 0, s>>>(pos, cell, np, n, ctx->pcell,
+                                                               ctx->cell_count);
+      else
+        k_cell_hist<PM_POS_CELLOFF, true><<<nb, kThreads, 0, s>>>(pos, cell, np, n, ctx->pcell,
+                                                                   ctx->cell_count);
+    } else {
+      if (poskind == PM_POS_BOX)
+        k_cell_hist<PM_POS_BOX, false><<<nb, kThreads, 0, s>>>(pos, cell, np, n, ctx->pcell,
+                                                                ctx->cell_count);
+      else
+        k_cell_hist<PM_POS_CELLOFF, false><<<nb, kThreads, 0, s>>>(pos, cell, np, n, ctx->pcell,
+                                                                    ctx->cell_count);
+    }
   }
   const unsigned nblk = blocks_for(len, kScanTile);
   k_scan_reduce<<<nblk, kScanThreads, 0, s>>>(ctx->cell_count, len, ctx->scan_partial);
   k_scan_partials<<<1, kScanThreads, 0, s>>>(ctx->scan_partial, (int)nblk);
-  // start = exclusive scan; count becomes the scatter cursor (a copy of start)
-  k_scan_apply<<<nblk, kScanThreads, 0, s>>>(ctx->cell_count, len, ctx->scan_partial,
-                                             ctx->cell_start, ctx->cell_count);
+  // in-place exclusive scan: cell_count[c] = start of cell c; the scatter then
+  // advances it to the end of cell c (= start of c + 1), the layout the gathers read
+  k_scan_apply<<<nblk, kScanThreads, 0, s>>>(ctx->cell_count, len, ctx->scan_partial);
   if (np > 0)
     k_scatter_perm<<<blocks_for(np, kThreads), kThreads, 0, s>>>(ctx->pcell, np,
                                                                   ctx->cell_count, ctx->perm);
@@ -501,21 +1017,65 @@ hipError_t launch_deposit_pull(pm_ctx *ctx, const float *pos, int64_t np, int po
   (void)np;
   const int n = ctx->n;
   const int64_t ncell = (int64_t)n * n * n;
+  if (n % kTT == 0) {
+    const unsigned nt = (unsigned)(ncell / kTThreads);
+    if (mas == PM_TSC) {
+      if (poskind == PM_POS_BOX)
+        k_deposit_tile<3, PM_POS_BOX><<<nt, kTThreads, 0, s>>>(pos, ctx->cell_count, ctx->perm, n,
+                                                                mass, rho);
+      else
+        k_deposit_tile<3, PM_POS_CELLOFF><<<nt, kTThreads, 0, s>>>(pos, ctx->cell_count, ctx->perm,
+                                                                    n, mass, rho);
+    } else {
+      if (poskind == PM_POS_BOX)
+        k_deposit_tile<2, PM_POS_BOX><<<nt, kTThreads, 0, s>>>(pos, ctx->cell_count, ctx->perm, n,
+                                                                mass, rho);
+      else
+        k_deposit_tile<2, PM_POS_CELLOFF><<<nt, kTThreads, 0, s>>>(pos, ctx->cell_count, ctx->perm,
+                                                                    n, mass, rho);
+    }
+    return hipGetLastError();
+  }
   const unsigned nb = blocks_for(ncell, kThreads);
   if (mas == PM_TSC) {
     if (poskind == PM_POS_BOX)
-      k_deposit_pull<3, PM_POS_BOX><<<nb, kThreads, 0, s>>>(pos, ctx->cell_start, ctx->perm, n,
+      k_deposit_pull<3, PM_POS_BOX><<<nb, kThreads, 0, s>>>(pos, ctx->cell_count, ctx->perm, n,
                                                               mass, rho);
     else
-      k_deposit_pull<3, PM_POS_CELLOFF><<<nb, kThreads, 0, s>>>(pos, ctx->cell_start, ctx->perm,
+      k_deposit_pull<3, PM_POS_CELLOFF><<<nb, kThreads, 0, s>>>(pos, ctx->cell_count, ctx->perm,
                                                                   n, mass, rho);
   } else {
     if (poskind == PM_POS_BOX)
-      k_deposit_pull<2, PM_POS_BOX><<<nb, kThreads, 0, s>>>(pos, ctx->cell_start, ctx->perm, n,
+      k_deposit_pull<2, PM_POS_BOX><<<nb, kThreads, 0, s>>>(pos, ctx->cell_count, ctx->perm, n,
                                                               mass, rho);
     else
-      k_deposit_pull<2, PM_POS_CELLOFF><<<nb, kThreads, 0, s>>>(pos, ctx->cell_start, ctx->perm,
+      k_deposit_pull<2, PM_POS_CELLOFF><<<nb, kThreads, 0, s>>>(pos, ctx->cell_count, ctx->perm,
                                                                   n, mass, rho);
   }
+  return hipGetLastError();
+}
+
+// Permute particle arrays in place through ctx->perm (the sorted order), via scratch.
+hipError_t launch_apply_perm(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, float *acc,
+                             int64_t *ids, int64_t np, hipStream_t s) {
+  if (np == 0) return hipSuccess;
+  const unsigned nb = blocks_for(np, kThreads);
+  float *tmp = (float *)ctx->reorder_tmp;
+  hipError_t e = hipSuccess;
+  float *f3[3] = {pos, vel, acc};
+  for (int a = 0; a < 3 && e == hipSuccess; ++a) {
+    if (!f3[a]) continue;
+    k_gather_perm<float, 3><<<nb, kThreads, 0, s>>>(f3[a], ctx->perm, np, tmp);
+    e = hipMemcpyAsync(f3[a], tmp, sizeof(float) * 3 * (size_t)np, hipMemcpyDeviceToDevice, s);
+  }
+  if (e == hipSuccess && cell) {
+    k_gather_perm<int32_t, 1><<<nb, kThreads, 0, s>>>(cell, ctx->perm, np, (int32_t *)tmp);
+    e = hipMemcpyAsync(cell, tmp, sizeof(int32_t) * (size_t)np, hipMemcpyDeviceToDevice, s);
+  }
+  if (e == hipSuccess && ids) {
+    k_gather_perm<int64_t, 1><<<nb, kThreads, 0, s>>>(ids, ctx->perm, np, (int64_t *)tmp);
+    e = hipMemcpyAsync(ids, tmp, sizeof(int64_t) * (size_t)np, hipMemcpyDeviceToDevice, s);
+  }
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }

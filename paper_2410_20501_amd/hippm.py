@@ -24,7 +24,8 @@ PM_DEPOSIT_ATOMIC, PM_DEPOSIT_SORTED = 0, 1
 PM_POS_BOX, PM_POS_CELLOFF = 0, 1
 PM_RESTRICT_FW, PM_RESTRICT_AVG = 0, 1
 PM_SOLVER_MG, PM_SOLVER_FFT = 0, 1
-PM_GUESS_JACOBI, PM_GUESS_WARM = 0, 1
+PM_GUESS_JACOBI, PM_GUESS_WARM, PM_GUESS_WARM_RESCALED = 0, 1, 2
+PM_CREATE_REFERENCE_KERNELS = 1
 
 MAS = {"cic": PM_CIC, "tsc": PM_TSC}
 ORDER = {"atomic": PM_DEPOSIT_ATOMIC, "sorted": PM_DEPOSIT_SORTED}
@@ -65,7 +66,7 @@ class StepStats(ctypes.Structure):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2410_20501_amd.build`")
+        raise ImportError(f"{LIB_PATH} is not built; run `python paper_2410_20501_amd/build.py`")
     lib = ctypes.CDLL(LIB_PATH)
     P = c_void_p
     sig = {
@@ -80,6 +81,7 @@ def _load():
         "pm_interp": (c_int, [P, P, P, c_int64, c_int, c_int, P, P, P]),
         "pm_accel": (c_int, [P, P, P, c_int64, c_int, c_double, POINTER(StepParams), P, P,
                              POINTER(StepStats), P]),
+        "pm_reorder": (c_int, [P, P, P, P, P, P, c_int64, c_int, P]),
         "pm_kdk": (c_int, [P, P, P, P, c_int64, c_int, c_double, c_double, POINTER(StepParams),
                            P, P, POINTER(StepStats), P]),
     }
@@ -104,7 +106,8 @@ def default_step_params(**kw) -> StepParams:
         elif k == "solver":
             v = {"mg": PM_SOLVER_MG, "fft": PM_SOLVER_FFT}.get(v, v)
         elif k == "guess":
-            v = {"jacobi": PM_GUESS_JACOBI, "warm": PM_GUESS_WARM}.get(v, v)
+            v = {"jacobi": PM_GUESS_JACOBI, "warm": PM_GUESS_WARM,
+                 "warm_rescaled": PM_GUESS_WARM_RESCALED}.get(v, v)
         elif k == "restrict_kind":
             v = {"fw": PM_RESTRICT_FW, "avg": PM_RESTRICT_AVG}.get(v, v)
         if hasattr(p.mg, k) and k not in ("mas",):
@@ -237,6 +240,14 @@ def pm_accel(ctx: Context, pos, a, phi, acc, cell=None, params: StepParams | Non
                        byref(stats), _stream())
     ctx._check(st, "pm_accel")
     return stats
+
+
+def pm_reorder(ctx: Context, pos, vel=None, acc=None, ids=None, cell=None):
+    np_, kind, pp, cp = _particles(pos, cell)
+    st = _lib.pm_reorder(ctx.handle, pp, cp, _ptr(vel, shape=(np_, 3), name="vel"),
+                         _ptr(acc, shape=(np_, 3), name="acc"),
+                         _ptr(ids, torch.int64, (np_,), "ids"), np_, kind, _stream())
+    return ctx._check(st, "pm_reorder")
 
 
 def pm_kdk(ctx: Context, pos, vel, a0, a1, phi, acc, cell=None, params: StepParams | None = None):

@@ -108,6 +108,29 @@ def test_deposit_parity(lib, n, npart, mas, order, poskind):
     assert abs(got.sum() - n ** 3) <= 1e-6 * n ** 3
 
 
+@pytest.mark.parametrize("mas", ["tsc", "cic"])
+@pytest.mark.parametrize("order", ["atomic", "sorted"])
+def test_deposit_clustered(lib, mas, order):
+    """Dense clumps (hundreds of particles per cell) next to a uniform background."""
+    _say(f"clustered deposit {mas} {order}")
+    n = 32
+    rng = np.random.Generator(np.random.PCG64(31))
+    bg = rng.uniform(0, 1, size=(20000, 3))
+    clumps = [np.array([0.5, 0.5, 0.5]), np.array([0.01, 0.99, 0.3]), np.array([0.73, 0.12, 0.88])]
+    parts = [bg] + [c + rng.normal(0, 0.6 / n, size=(6000, 3)) for c in clumps]
+    pos = np.mod(np.concatenate(parts), 1.0).astype(np.float32)
+    pos[pos >= 1.0] = 0.0
+    pos = pos[rng.permutation(pos.shape[0])]
+    ctx = ctx_for(lib, n, pos.shape[0])
+    rho = torch.empty((n, n, n), device="cuda")
+    lib.pm_deposit(ctx, dev(pos), rho, mas=mas, order=order)
+    ref = opm.deposit(opm.cell_units(n, pos=pos), n, mas)
+    got = host(rho)
+    assert ref.max() > 100.0
+    assert np.abs(got - ref).max() <= 2e-6 * ref.max()
+    assert abs(got.sum() - n ** 3) <= 1e-6 * n ** 3
+
+
 def test_sorted_deposit_is_bitwise_reproducible(lib):
     _say("sorted deposit determinism")
     n = 32
@@ -121,6 +144,50 @@ def test_sorted_deposit_is_bitwise_reproducible(lib):
         outs.append(host(rho).astype(np.float32).view(np.uint32))
     np.testing.assert_array_equal(outs[0], outs[1])
     np.testing.assert_array_equal(outs[0], outs[2])
+
+
+@pytest.mark.parametrize("celloff", [False, True])
+def test_reorder_permutes_consistently(lib, celloff):
+    """pm_reorder: same particles (followed by ids), tile-major cell order, deposit unchanged."""
+    _say(f"reorder celloff={celloff}")
+    n = 32
+    pos, vel = lattice_ics(n, rms=1.5, seed=13)
+    rng = np.random.Generator(np.random.PCG64(14))
+    order = rng.permutation(pos.shape[0])
+    pos, vel = pos[order], vel[order]
+    ctx = ctx_for(lib, n, pos.shape[0])
+    ids = torch.arange(pos.shape[0], device="cuda", dtype=torch.int64)
+    acc = dev(vel * 2.0)
+    if celloff:
+        cell_np, off = icgen.to_cell_offset(pos, n)
+        p, cell = dev(off), dev(cell_np, torch.int32)
+    else:
+        p, cell = dev(pos), None
+    v = dev(vel)
+    rho0 = torch.empty((n, n, n), device="cuda")
+    lib.pm_deposit(ctx, p, rho0, cell=cell, order="sorted")
+    lib.pm_reorder(ctx, p, vel=v, acc=acc, ids=ids, cell=cell)
+    idn = host(ids).astype(np.int64)
+    assert np.array_equal(np.sort(idn), np.arange(pos.shape[0]))
+    np.testing.assert_array_equal(host(v), vel[idn])
+    np.testing.assert_array_equal(host(acc), 2.0 * vel[idn].astype(np.float32))
+    if celloff:
+        np.testing.assert_array_equal(host(cell).astype(np.int64), cell_np[idn])
+        np.testing.assert_array_equal(host(p), off[idn])
+        c = cell_np[idn].astype(np.int64)
+    else:
+        np.testing.assert_array_equal(host(p), pos[idn])
+        q = np.floor(pos[idn].astype(np.float64) * n).astype(np.int64) % n
+        c = (q[:, 0] * n + q[:, 1]) * n + q[:, 2]
+    ci, cj, ck = c // (n * n), (c // n) % n, c % n
+    key = ((((ci >> 3) * (n // 8) + (cj >> 3)) * (n // 8) + (ck >> 3)) << 9) + (((ci & 7) << 3) + (cj & 7)) * 8 + (ck & 7)
+    assert np.all(np.diff(key) >= 0)
+    rho1 = torch.empty((n, n, n), device="cuda")
+    lib.pm_deposit(ctx, p, rho1, cell=cell, order="sorted")
+    np.testing.assert_array_equal(host(rho0), host(rho1))
+    rho2 = torch.empty((n, n, n), device="cuda")
+    lib.pm_deposit(ctx, p, rho2, cell=cell, order="atomic")      # boxed path after reorder
+    assert np.abs(host(rho2) - host(rho1)).max() <= 4e-6 * host(rho1).max()
 
 
 def test_deposit_empty(lib):
@@ -140,7 +207,7 @@ def _density(n, seed=7, ns=-2.0, rms=0.3):
     return opm.deposit(opm.cell_units(n, pos=pos), n, "tsc").astype(np.float32)
 
 
-@pytest.mark.parametrize("n", [8, 16, 32, 48, 64])
+@pytest.mark.parametrize("n", [8, 16, 32, 48, 64, 128, 256])
 def test_mg_solve_parity(lib, n):
     _say(f"mg solve n={n}")
     rho32 = _density(n)
@@ -157,6 +224,29 @@ def test_mg_solve_parity(lib, n):
     if n >= 32:
         # paper App. C: about an order of magnitude per V-cycle (omega = 1)
         assert hist[1] / hist[2] > 4.0, hist
+
+
+@pytest.mark.parametrize("pre,post", [(2, 2), (1, 1), (3, 1), (0, 2), (2, 0)])
+def test_streaming_multigrid_matches_reference_kernels(lib, pre, post):
+    """The fused streaming smoother/restriction (n >= 128) against one kernel per half-sweep."""
+    _say(f"streaming vs reference pre={pre} post={post}")
+    n = 128
+    rho32 = _density(n, seed=21)
+    fast = ctx_for(lib, n)
+    key = ("ref", n)
+    if key not in _CTX:
+        _CTX[key] = lib.Context(n, 0, lib.PM_CREATE_REFERENCE_KERNELS)
+    ref_ctx = _CTX[key]
+    out = []
+    for c in (fast, ref_ctx):
+        phi = torch.zeros((n, n, n), device="cuda")
+        lib.pm_solve_mg(c, dev(rho32), 0.15, phi, fixed_cycles=3, pre=pre, post=post)
+        out.append(host(phi))
+    assert rel_l2(out[0], out[1]) <= 2e-6
+    phi = torch.zeros((n, n, n), device="cuda")
+    st = lib.pm_solve_mg(fast, dev(rho32), 0.15, phi, tol=1e-7, max_cycles=60, pre=pre, post=post)
+    ref = opm.solve_exact7(opm.source(rho32.astype(np.float64), 0.1), 1.0 / n)
+    assert rel_l2(host(phi), ref) <= 1e-5, st.history()
 
 
 def test_mg_single_mode_closed_form(lib):
