@@ -24,7 +24,38 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published peak
+
+# HBM traffic of the roofline kernel per launch, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of this benchmark at 512^3,
+# scaled by the same counters read for a plain 512 MiB device copy (read x2.0,
+# write x1.0). Valid only for the kernel source it was measured on: the bench
+# reports null when the source file's hash differs.
+MEASURED_TRAFFIC = {
+    # kernel: (source file, sha256 of it, fetch KiB, write KiB, fetch scale, write scale)
+    "deposit": ("paper_2410_20501_amd/csrc/particles.hip",
+                "bea21cd3b277cd06ba9106044bdfa24dad16a8005e93450a9f2d336fdacd3e74",
+                1708233.0, 524500.0, 2.0, 1.0),
+    "smooth": ("paper_2410_20501_amd/csrc/mg_stream.hip",
+               "6fb24276839515befe30638caa872f63c1058d88d49935d9089f2b2aa944e505",
+               635952.0, 524304.0, 2.0, 1.0),
+}
+
+
+def _source_hash(rel):
+    import hashlib
+    with open(os.path.join(ROOT, rel), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def traffic_bytes(kernel):
+    rec = MEASURED_TRAFFIC.get(kernel)
+    if rec is None:
+        return None
+    src, digest, fkib, wkib, fs, ws = rec
+    if _source_hash(src) != digest:
+        return None
+    return (fkib * fs + wkib * ws) * 1024.0
 
 
 def _log(msg):
@@ -81,6 +112,8 @@ def main():
     ap.add_argument("--reorder-every", type=int, default=10,
                     help="re-sort particles by tile every this many steps (0: never)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--roofline-kernel", default="deposit", choices=["deposit", "smooth", "interp"],
+                    help="kernel timed with events for the roofline object")
     ap.add_argument("--stage-log", action="store_true",
                     help="record per-stage times of every timed step (adds events)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -145,6 +178,7 @@ def main():
     stage_rows = []
     if args.stage_log:
         params.timing = 1
+    pm.pm_kernel_timer(ctx, args.roofline_kernel, capacity=8192)
     t0 = time.perf_counter()
     for i in range(args.steps):
         if args.reorder_every > 0 and step % args.reorder_every == 0:
@@ -170,6 +204,22 @@ def main():
 
     ms_per_step = 1000.0 * elapsed / max(args.steps, 1)
     value = npart * args.steps / elapsed
+    k_ms, k_launches, k_bytes = pm.pm_kernel_timer_read(ctx)
+    pm.pm_kernel_timer(ctx, "none", capacity=0)
+    roofline = None
+    if k_launches > 0 and k_ms > 0:
+        per_launch_bytes = k_bytes / k_launches
+        avg_ms = k_ms / k_launches
+        achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
+        traffic = traffic_bytes(args.roofline_kernel)
+        roofline = {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": args.roofline_kernel, "launches": k_launches,
+            "avg_ms": avg_ms, "algorithmic_bytes_per_launch": per_launch_bytes,
+        }
+        _log(f"roofline {args.roofline_kernel}: {k_launches} launches, avg {avg_ms:.3f} ms, "
+             f"{achieved:.0f} GB/s algorithmic")
 
     # per-stage times of one extra (untimed) step with stage events
     params.timing = 1
@@ -200,6 +250,7 @@ def main():
                    "particles": npart, "grid": n, "deposit": args.order,
                    "vcycles_per_step": cycles},
         "stages_ms_last_step": stages,
+        "roofline": roofline,
     }
     if not args.no_cpu_baseline:
         _log("cpu baseline (oracle) ...")

@@ -202,6 +202,23 @@ int pm_kdk(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, int64_t np, int p
            double a0, double a1, const pm_step_params *params, float *phi, float *acc,
            pm_step_stats *stats, pm_stream stream);
 
+/* Per-kernel timing (measurement support). pm_kernel_timer(ctx, kernel, cap)
+ * starts recording a pair of HIP events on the caller's stream around every
+ * launch of one kernel (at most cap launches; resets the previous record):
+ *   PM_KERNEL_DEPOSIT  the deposit's gather kernel of PM_DEPOSIT_SORTED;
+ *                      algorithmic bytes 12 per particle + 4 per cell
+ *   PM_KERNEL_SMOOTH   the streaming smoother on the finest grid (n >= 128);
+ *                      algorithmic bytes 12 per cell per pass
+ *   PM_KERNEL_INTERP   interpolation (+ kick) in pm_accel/pm_kdk; algorithmic
+ *                      bytes 48 per particle (+4 with cell indices) + 12 per cell
+ * pm_kernel_timer_read synchronises on the recorded events and returns the
+ * summed elapsed time, the number of launches and the summed algorithmic
+ * bytes; PM_WARN_NOT_CONVERGED if launches exceeded the pool. */
+enum pm_kernel_id { PM_KERNEL_NONE = 0, PM_KERNEL_DEPOSIT = 1, PM_KERNEL_SMOOTH = 2,
+                    PM_KERNEL_INTERP = 3 };
+int pm_kernel_timer(pm_ctx *ctx, int kernel, int capacity);
+int pm_kernel_timer_read(pm_ctx *ctx, double *ms, int64_t *launches, double *bytes);
+
 #ifdef __cplusplus
 }
 #endif

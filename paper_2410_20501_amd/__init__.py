@@ -9,4 +9,5 @@ from .hippm import (  # noqa: F401
     Context, PMError, PMWarning, MGParams, MGStats, StepParams, StepStats, EXPORTED,
     default_step_params, pm_create, pm_destroy, pm_deposit, pm_solve_mg, pm_solve_fft,
     pm_gradient, pm_interp, pm_accel, pm_kdk, pm_reorder,
+    pm_kernel_timer, pm_kernel_timer_read,
 )

@@ -6,6 +6,22 @@
 
 #include "internal.h"
 
+void pm_kt_begin(pm_ctx *ctx, int kernel, hipStream_t s) {
+  if (ctx->kt_kernel != kernel || kernel == PM_KERNEL_NONE) return;
+  if (ctx->kt_used >= ctx->kt_cap) {
+    ++ctx->kt_dropped;
+    return;
+  }
+  (void)hipEventRecord(ctx->kt_ev[2 * ctx->kt_used], s);
+}
+
+void pm_kt_end(pm_ctx *ctx, int kernel, hipStream_t s, double bytes) {
+  if (ctx->kt_kernel != kernel || kernel == PM_KERNEL_NONE || ctx->kt_used >= ctx->kt_cap) return;
+  (void)hipEventRecord(ctx->kt_ev[2 * ctx->kt_used + 1], s);
+  ctx->kt_used++;
+  ctx->kt_bytes += bytes;
+}
+
 int pm_fail(pm_ctx *ctx, int code, const std::string &msg) {
   if (ctx) ctx->err = msg;
   return code;
@@ -94,7 +110,10 @@ int deposit_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np,
     int st = ensure_sort_scratch(ctx, np);
     if (st != PM_OK) return st;
     PM_HIP(ctx, launch_sort_by_cell(ctx, pos, cell, np, poskind, s, false));
+    pm_kt_begin(ctx, PM_KERNEL_DEPOSIT, s);
     PM_HIP(ctx, launch_deposit_pull(ctx, pos, np, poskind, mas, mass, rho, s));
+    // algorithmic bytes: in-cell offsets (12 B per particle) + the density (4 B per cell)
+    pm_kt_end(ctx, PM_KERNEL_DEPOSIT, s, 12.0 * (double)np + 4.0 * (double)ncell);
     return PM_OK;
   }
   PM_HIP(ctx, hipMemsetAsync(rho, 0, sizeof(float) * (size_t)ncell, s));
@@ -122,7 +141,13 @@ int accel_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, i
   if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[3], s));
   PM_HIP(ctx, launch_gradient(phi, ctx->n, 5, ctx->g, s));
   if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[4], s));
+  pm_kt_begin(ctx, PM_KERNEL_INTERP, s);
   PM_HIP(ctx, launch_interp(pos, cell, np, poskind, p->mas, ctx->n, ctx->g, acc, vel, kick, s));
+  // algorithmic bytes: position (12 B, + 4 B cell index), velocity in/out (24 B),
+  // acceleration out (12 B) per particle, and the force grid once (12 B per cell)
+  pm_kt_end(ctx, PM_KERNEL_INTERP, s,
+            (double)np * (48.0 + (poskind == PM_POS_CELLOFF ? 4.0 : 0.0)) +
+                12.0 * (double)ctx->n * ctx->n * ctx->n);
   if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[5], s));
   return sst;
 }
@@ -224,6 +249,8 @@ void pm_destroy(pm_ctx *ctx) {
   fr(ctx->reorder_tmp);
   for (int i = 0; i < 8; ++i)
     if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+  for (int i = 0; i < 2 * ctx->kt_cap; ++i) (void)hipEventDestroy(ctx->kt_ev[i]);
+  delete[] ctx->kt_ev;
   delete ctx;
 }
 
@@ -298,6 +325,47 @@ int pm_accel(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, int
                   1.0f);
   if (st >= 0 && timing) fill_timing(ctx, stats, false);
   return st;
+}
+
+int pm_kernel_timer(pm_ctx *ctx, int kernel, int capacity) {
+  if (!ctx) return PM_ERR_ARG;
+  if (kernel < PM_KERNEL_NONE || kernel > PM_KERNEL_INTERP)
+    return pm_fail(ctx, PM_ERR_ARG, "unknown kernel id");
+  if (capacity < 0 || capacity > (1 << 20)) return pm_fail(ctx, PM_ERR_ARG, "bad capacity");
+  if (capacity > ctx->kt_cap) {
+    hipEvent_t *ev = new hipEvent_t[2 * capacity];
+    for (int i = 0; i < 2 * ctx->kt_cap; ++i) ev[i] = ctx->kt_ev[i];
+    for (int i = 2 * ctx->kt_cap; i < 2 * capacity; ++i)
+      if (hipEventCreate(&ev[i]) != hipSuccess) {
+        for (int j = 2 * ctx->kt_cap; j < i; ++j) (void)hipEventDestroy(ev[j]);
+        delete[] ev;
+        return pm_fail(ctx, PM_ERR_HIP, "event creation failed");
+      }
+    delete[] ctx->kt_ev;
+    ctx->kt_ev = ev;
+    ctx->kt_cap = capacity;
+  }
+  ctx->kt_kernel = kernel;
+  ctx->kt_used = 0;
+  ctx->kt_bytes = 0.0;
+  ctx->kt_dropped = 0;
+  return PM_OK;
+}
+
+int pm_kernel_timer_read(pm_ctx *ctx, double *ms, int64_t *launches, double *bytes) {
+  if (!ctx || !ms || !launches || !bytes) return PM_ERR_ARG;
+  double total = 0.0;
+  for (int i = 0; i < ctx->kt_used; ++i) {
+    float t = 0.f;
+    PM_HIP(ctx, hipEventSynchronize(ctx->kt_ev[2 * i + 1]));
+    PM_HIP(ctx, hipEventElapsedTime(&t, ctx->kt_ev[2 * i], ctx->kt_ev[2 * i + 1]));
+    total += t;
+  }
+  *ms = total;
+  *launches = ctx->kt_used;
+  *bytes = ctx->kt_bytes;
+  return ctx->kt_dropped ? pm_fail(ctx, PM_WARN_NOT_CONVERGED, "kernel timer pool overflowed")
+                         : PM_OK;
 }
 
 int pm_reorder(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, float *acc, int64_t *ids,

@@ -39,9 +39,11 @@ template <int P>
 __global__ __launch_bounds__(kThreads) void k_gradient(const float *__restrict__ phi, int n,
                                                        float inv_h, float *__restrict__ g) {
   constexpr int R = Stencil<P>::R;
-  const int k = blockIdx.x * kThreads + threadIdx.x;
-  const int j = blockIdx.y;
-  const int i = blockIdx.z;
+  const unsigned lin = xcd_block(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
+                                 gridDim.x * gridDim.y * gridDim.z);
+  const int k = (lin % gridDim.x) * kThreads + threadIdx.x;
+  const int j = (lin / gridDim.x) % gridDim.y;
+  const int i = lin / (gridDim.x * gridDim.y);
   if (k >= n) return;
   const size_t nn = (size_t)n * n;
   const size_t row = ((size_t)i * n + j) * n;

@@ -53,7 +53,26 @@ struct pm_ctx {
   int64_t reorder_cap;
   // timing events
   hipEvent_t ev[8];
+  // per-kernel timer: event pairs around every launch of one kernel
+  int kt_kernel;
+  int kt_cap, kt_used;
+  hipEvent_t *kt_ev;     // [2 * kt_cap]
+  double kt_bytes;       // algorithmic bytes of the recorded launches
+  int64_t kt_dropped;    // launches beyond the pool (not timed)
 };
+
+// kernel-timer hooks (api.hip): bracket one launch of `kernel` on stream s
+void pm_kt_begin(pm_ctx *ctx, int kernel, hipStream_t s);
+void pm_kt_end(pm_ctx *ctx, int kernel, hipStream_t s, double bytes);
+
+// Workgroups are dispatched round-robin over the 8 XCDs of an MI355X, each with its
+// own L2. Remapping the block index so that every XCD walks a contiguous range of
+// logical blocks keeps spatial neighbours (shared halos, planes) in the same L2.
+__device__ __forceinline__ unsigned xcd_block(unsigned bid, unsigned nblocks) {
+  const unsigned x = bid & 7u, k = bid >> 3;
+  const unsigned per = nblocks >> 3, rem = nblocks & 7u;
+  return x * per + (x < rem ? x : rem) + k;
+}
 
 #define RED_BLOCKS 1024
 #define RED_PARTIAL_CAP 65536  // partial-sum slots (smoother blocks or reduction blocks)

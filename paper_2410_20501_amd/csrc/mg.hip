@@ -126,7 +126,7 @@ __global__ __launch_bounds__(kThreads) void k_residual_restrict(
 // the next one (fine cell 2J has neighbours J, J-1; fine 2J+1 has J, J+1).
 __global__ __launch_bounds__(kThreads) void k_prolong_add(float *__restrict__ u, int n,
                                                           const float *__restrict__ v) {
-  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
   if (t >= (int64_t)n * n * n) return;
   const int k = (int)(t % n), j = (int)((t / n) % n), i = (int)(t / ((int64_t)n * n));
   const int nc = n >> 1;
@@ -360,8 +360,12 @@ struct Solver {
     hipError_t e = hipSuccess;
     while (sweeps > 0 && e == hipSuccess) {
       const int now = sweeps >= 2 ? 2 : 1;
+      if (l == 0) pm_kt_begin(ctx, PM_KERNEL_SMOOTH, s);
       e = launch_smooth_stream(cur[l], alt[l], sr.f, sr.scale, sr.mean, vc, n, h2(l), p->omega,
                                first_colour, 2 * now, partial, s);
+      // algorithmic bytes of one pass (any number of fused sweeps): read u and f,
+      // write u, 4 B each per cell
+      if (l == 0) pm_kt_end(ctx, PM_KERNEL_SMOOTH, s, 12.0 * (double)n * n * n);
       std::swap(cur[l], alt[l]);
       vc = nullptr;
       partial = nullptr;

@@ -69,7 +69,11 @@ __global__ __launch_bounds__(ST) void k_smooth_stream(
   constexpr int PPT = (NP + ST - 1) / ST;
   __shared__ float lds[H][NP];
 
-  const int k0 = blockIdx.x * SK, j0 = blockIdx.y * SJ, i0 = blockIdx.z * ci;
+  // XCD-aware order: consecutive logical blocks are k-, then j-neighbours
+  const unsigned lin = xcd_block(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
+                                 gridDim.x * gridDim.y * gridDim.z);
+  const int bx = lin % gridDim.x, by = (lin / gridDim.x) % gridDim.y, bz = lin / (gridDim.x * gridDim.y);
+  const int k0 = bx * SK, j0 = by * SJ, i0 = bz * ci;
   const float m = fmean ? *fmean : 0.0f;
   const float inv_h2 = 1.0f / h2;
   const size_t nn = (size_t)n * n;
@@ -244,7 +248,10 @@ __global__ __launch_bounds__(RT) void k_rr_stream(const float *__restrict__ u,
   __shared__ float Lu[UNP];
   __shared__ float Lr[UNP];
   const int nc = n >> 1;
-  const int K0 = blockIdx.x * CK, J0 = blockIdx.y * CJ, I0 = blockIdx.z * cic;
+  const unsigned lin = xcd_block(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
+                                 gridDim.x * gridDim.y * gridDim.z);
+  const int bx = lin % gridDim.x, by = (lin / gridDim.x) % gridDim.y, bz = lin / (gridDim.x * gridDim.y);
+  const int K0 = bx * CK, J0 = by * CJ, I0 = bz * cic;
   // fine region origin: fine (2 J0 - 2, 2 K0 - 2)
   const int fj0 = 2 * J0 - 2, fk0 = 2 * K0 - 2;
   const float m = fmean ? *fmean : 0.0f;

@@ -128,7 +128,7 @@ __global__ __launch_bounds__(kThreads) void k_interp(const float *__restrict__ p
                                                      const float *__restrict__ g,
                                                      float *__restrict__ acc,
                                                      float *__restrict__ vel, float kick) {
-  const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
   if (p >= np) return;
   int first[3];
   float w[3][MAS];
@@ -771,7 +771,7 @@ __global__ __launch_bounds__(kTThreads) void k_deposit_tile(const float *__restr
   __shared__ int wsum[kTThreads / 64];
   __shared__ int wdense[kTThreads / 64];
   const int nt = n / kTT;
-  const int tile = blockIdx.x;
+  const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
   const int tk = tile % nt, tj = (tile / nt) % nt, ti = tile / (nt * nt);
   const int i0 = ti * kTT - 1, j0 = tj * kTT - 1, k0 = tk * kTT - 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;

@@ -26,6 +26,7 @@ PM_RESTRICT_FW, PM_RESTRICT_AVG = 0, 1
 PM_SOLVER_MG, PM_SOLVER_FFT = 0, 1
 PM_GUESS_JACOBI, PM_GUESS_WARM, PM_GUESS_WARM_RESCALED = 0, 1, 2
 PM_CREATE_REFERENCE_KERNELS = 1
+PM_KERNEL_NONE, PM_KERNEL_DEPOSIT, PM_KERNEL_SMOOTH, PM_KERNEL_INTERP = 0, 1, 2, 3
 
 MAS = {"cic": PM_CIC, "tsc": PM_TSC}
 ORDER = {"atomic": PM_DEPOSIT_ATOMIC, "sorted": PM_DEPOSIT_SORTED}
@@ -81,6 +82,8 @@ def _load():
         "pm_interp": (c_int, [P, P, P, c_int64, c_int, c_int, P, P, P]),
         "pm_accel": (c_int, [P, P, P, c_int64, c_int, c_double, POINTER(StepParams), P, P,
                              POINTER(StepStats), P]),
+        "pm_kernel_timer": (c_int, [P, c_int, c_int]),
+        "pm_kernel_timer_read": (c_int, [P, POINTER(c_double), POINTER(c_int64), POINTER(c_double)]),
         "pm_reorder": (c_int, [P, P, P, P, P, P, c_int64, c_int, P]),
         "pm_kdk": (c_int, [P, P, P, P, c_int64, c_int, c_double, c_double, POINTER(StepParams),
                            P, P, POINTER(StepStats), P]),
@@ -240,6 +243,19 @@ def pm_accel(ctx: Context, pos, a, phi, acc, cell=None, params: StepParams | Non
                        byref(stats), _stream())
     ctx._check(st, "pm_accel")
     return stats
+
+
+def pm_kernel_timer(ctx: Context, kernel, capacity=4096):
+    kid = {"none": PM_KERNEL_NONE, "deposit": PM_KERNEL_DEPOSIT, "smooth": PM_KERNEL_SMOOTH,
+           "interp": PM_KERNEL_INTERP}.get(kernel, kernel)
+    return ctx._check(_lib.pm_kernel_timer(ctx.handle, int(kid), int(capacity)), "pm_kernel_timer")
+
+
+def pm_kernel_timer_read(ctx: Context):
+    ms, n, b = c_double(), c_int64(), c_double()
+    ctx._check(_lib.pm_kernel_timer_read(ctx.handle, byref(ms), byref(n), byref(b)),
+               "pm_kernel_timer_read")
+    return ms.value, n.value, b.value
 
 
 def pm_reorder(ctx: Context, pos, vel=None, acc=None, ids=None, cell=None):
