@@ -152,3 +152,34 @@ def ensemble_draw(master_seed: int, boxes: int, sizes=(32, 48, 64, 96, 128),
     ns = rng.choice(np.asarray(sizes), size=boxes)
     idx = rng.uniform(index_range[0], index_range[1], size=boxes)
     return [(int(ns[b]), float(idx[b]), 1000 + b) for b in range(boxes)]
+
+
+def lattice_points(n: int) -> np.ndarray:
+    """Cell centres ((i, j, k) + 1/2) / n as FP32 [n^3, 3], the unperturbed particle lattice."""
+    idx = ((np.arange(n, dtype=np.float64) + 0.5) / n).astype(np.float32)
+    q = np.empty((n, n, n, 3), dtype=np.float32)
+    q[..., 0] = idx[:, None, None]
+    q[..., 1] = idx[None, :, None]
+    q[..., 2] = idx[None, None, :]
+    return q.reshape(-1, 3)
+
+
+def weight_grid(n: int, seed: int) -> np.ndarray:
+    """Seeded uniform [0, 1) FP32 weights on the n^3 grid (loss weights of a density objective)."""
+    return np.random.default_rng(seed).random((n, n, n), dtype=np.float64).astype(np.float32)
+
+
+def direction_fields(n: int, count: int, seed: int, smooth_index: float = -1.5) -> list:
+    """Seeded perturbation directions of a displacement field, FP32 [n^3, 3] each, unit rms
+    per component: even entries are smooth Gaussian random fields (P ~ k^smooth_index), odd
+    entries white noise."""
+    out = []
+    rng = np.random.default_rng(seed)
+    for i in range(count):
+        if i % 2 == 0:
+            d = displacement_field(n, smooth_index, 1.0, seed + 7919 * (i + 1)).reshape(-1, 3)
+        else:
+            d = rng.standard_normal((n ** 3, 3))
+        d = d / np.sqrt(np.mean(d * d))
+        out.append(d.astype(np.float32))
+    return out

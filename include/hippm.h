@@ -202,6 +202,158 @@ int pm_kdk(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, int64_t np, int p
            double a0, double a1, const pm_step_params *params, float *phi, float *acc,
            pm_step_stats *stats, pm_stream stream);
 
+/* ------------------------------------------------------------------ reverse mode
+ * Vector-Jacobian products of the steps above, for differentiating a run with
+ * respect to its initial conditions (the use the paper gives for
+ * differentiable PM in its introduction). Every "_bar" output is ACCUMULATED
+ * (the call adds to it) unless stated otherwise, so a caller zeroes it once.
+ * Particle cotangents are with respect to box-unit positions x in both
+ * position forms (for PM_POS_CELLOFF, x = (cell + offset) / n). The window
+ * derivatives are exact: TSC is continuously differentiable, CIC piecewise
+ * linear (its derivative is taken inside the cell, like the forward window).
+ */
+
+/* Transpose of pm_deposit (Sect. 3.5):
+ *   pos_bar[p] += sum_c rho_bar[c] d rho[c] / d x_p
+ *              =  w n sum_c rho_bar[c] grad_u W(u_p - (c + 1/2)),  w = n^3 / np.
+ * A gather (one thread per particle, no atomics); deterministic. */
+int pm_deposit_vjp(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np,
+                   int poskind, int mas, const float *rho_bar, float *pos_bar,
+                   pm_stream stream);
+
+/* Transpose of pm_interp against a particle cotangent lam [np][3]:
+ *   g_bar[c]   += sum_p W(u_p - (c + 1/2)) lam[p]             (if g_bar != NULL)
+ *   pos_bar[p] += n sum_c grad_u W(u_p - (c + 1/2)) (g[c] . lam[p])  (if pos_bar != NULL;
+ *                                                                     needs g)
+ * g_bar is [n][n][n][3]; its sum order (FP32 atomics) may differ between runs. */
+int pm_interp_vjp(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np,
+                  int poskind, int mas, const float *g, const float *lam, float *g_bar,
+                  float *pos_bar, pm_stream stream);
+
+/* Transpose of pm_gradient: g = -D phi with D the antisymmetric periodic central
+ * difference of the gradient table, so phi_bar += sum_d D_d g_bar_d (D^T = -D). */
+int pm_gradient_vjp(pm_ctx *ctx, const float *g_bar, int points, float *phi_bar,
+                    pm_stream stream);
+
+/* The Poisson solves are self-adjoint: phi = L^+ coef (rho - mean rho) with L
+ * the symmetric seven-point operator (or the even FFT kernel) gives
+ *   rho_bar = coef L^+ (phi_bar - mean phi_bar),
+ * which is pm_solve_mg / pm_solve_fft applied to phi_bar; there is no separate
+ * entry point. */
+
+/* J(x)^T of the acceleration map of pm_accel at scale factor a, applied to lam:
+ *   pos_bar += scale (d acc / d x)^T lam
+ * phi: the potential of these positions at a (as pm_accel / pm_kdk return it);
+ * read only. Computes g = -D phi, g_bar = interp^T lam, phi_bar = D g_bar,
+ * rho_bar = solve(phi_bar) (multigrid from the Jacobi guess with params->mg,
+ * or FFT), then the two position terms (interpolation weights against g . lam,
+ * deposit weights against rho_bar). Uses 16 bytes per cell of context scratch
+ * (allocated on first use) and the context's density and force grids.
+ * Returns the status of the adjoint solve; stats may be NULL. */
+int pm_accel_vjp(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, int poskind,
+                 double a, const pm_step_params *params, const float *phi, const float *lam,
+                 float scale, float *pos_bar, pm_mg_stats *stats, pm_stream stream);
+
+/* Reverse of one pm_kdk step from a0 to a1 (Sect. 3.4 leapfrog, transposed):
+ *   pos_bar += kick1 J(x1)^T vel_bar;  vel_bar += tau pos_bar;
+ *   pos_bar += kick0 J(x0)^T vel_bar
+ * with tau = 2 (a0^-1/2 - a1^-1/2). (pos0, cell0, phi0) is the state at a0 before
+ * the step and (pos1, cell1, phi1) the state after it. kick0 = kick1 = tau / 2
+ * is the exact transpose of one step. When a chain of steps is reversed, the
+ * kick1 term of one step and the kick0 term of the step after it act on the same
+ * positions and the same vel_bar, so a caller may merge them into one (weight
+ * (tau_i + tau_{i+1}) / 2) and pass 0 for the other: a zero weight skips that
+ * evaluation (and its potential may then be NULL). Updates pos_bar and vel_bar
+ * in place; stats (may be NULL) receives the last adjoint solve's record. */
+int pm_kdk_adjoint(pm_ctx *ctx, const float *pos0, const int32_t *cell0, const float *phi0,
+                   const float *pos1, const int32_t *cell1, const float *phi1, int64_t np,
+                   int poskind, double a0, double a1, const pm_step_params *params,
+                   double kick0, double kick1, float *pos_bar, float *vel_bar,
+                   pm_step_stats *stats, pm_stream stream);
+
+/* Density objective for inference of initial conditions:
+ *   L = sum_c w[c] (rho[c] - 1)^2,  rho = pm_deposit(pos) (mean 1 when np = n^3),
+ * summed in FP64 in a fixed order. If loss != NULL it receives L (the call then
+ * synchronises the stream); if pos_bar != NULL, pos_bar += dL/dx, through
+ * rho_bar = 2 w (rho - 1) and the deposit transpose. Uses the context's density
+ * grid. */
+int pm_density_loss(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np,
+                    int poskind, int mas, int order, const float *w, double *loss,
+                    float *pos_bar, pm_stream stream);
+
+/* Zel'dovich initial state (Sect. 3.3) from a displacement field psi [np][3] (box
+ * units) at lattice points q [np][3]: pos = wrap(q + psi), vel = a0^{1/2} psi, the
+ * growing mode in Einstein-de Sitter supercomoving units (D = a). With cell == NULL
+ * pos is in box units (PM_POS_BOX); otherwise the state is written in cell-offset
+ * form (PM_POS_CELLOFF): every q must then be a cell centre (c + 1/2) / n, and
+ * u = c + 1/2 + n psi is split into cell[p] and the offset pos[p] in [0, 1). */
+int pm_ic_state(pm_ctx *ctx, const float *q, const float *psi, int64_t np, double a0,
+                float *pos, int32_t *cell, float *vel, pm_stream stream);
+
+/* Transpose of pm_ic_state: psi_bar = pos_bar + a0^{1/2} vel_bar (overwritten, not
+ * accumulated; the periodic wrap has unit derivative). */
+int pm_ic_vjp(pm_ctx *ctx, const float *pos_bar, const float *vel_bar, int64_t np, double a0,
+              float *psi_bar, pm_stream stream);
+
+/* ------------------------------------------------------------------ batched ensembles
+ * Many independent periodic boxes of different grid sizes advanced together
+ * (the paper's purpose is large suites of simulations; introduction and
+ * conclusions). Box b has an n[b]^3 grid and np[b] particles in box units; the
+ * caller packs the particle arrays of all boxes into pos, vel, acc of
+ * [sum np][3] (box b at rows p_off[b] .. p_off[b+1]) and the potentials into
+ * phi of [sum n^3] (box b at c_off[b], row-major [n][n][n]); pm_batch_layout
+ * returns both offset tables (exclusive prefix sums). Every stage of a step is
+ * one launch for the whole batch: the kernels walk work lists of (box, block)
+ * items with a persistent grid. The multigrid solve runs a fixed number of
+ * V-cycles (mg.fixed_cycles >= 1; same smoother, restriction, prolongation and
+ * coarsest-level solve as pm_solve_mg, levels halved down to at most 16 cells
+ * per side), so a step never synchronises with the host and can be captured
+ * as a graph. Deposit is the atomic form (FP32 atomics). The batch owns the
+ * density, force and multigrid arenas (about 21 bytes per cell). */
+typedef struct pm_batch pm_batch;
+
+/* n[b]: even, 8 .. 1024, halving while > 16 and a multiple of 4 must end at <= 20;
+ * np[b] >= 1. flags: 0. Errors: PM_ERR_ARG, PM_ERR_SHAPE, PM_ERR_NOMEM. */
+int pm_batch_create(pm_batch **batch, int nboxes, const int *n, const int64_t *np, int flags);
+void pm_batch_destroy(pm_batch *batch);
+const char *pm_batch_last_error(const pm_batch *batch);
+/* p_off[nboxes + 1], c_off[nboxes + 1] (host arrays) receive the packing offsets. */
+int pm_batch_layout(const pm_batch *batch, int64_t *p_off, int64_t *c_off);
+
+/* Accelerations of every box at scale factor a (deposit, solve with coef
+ * 1.5 a Omega_m, 5-point gradient, interpolation). phi is the starting guess
+ * when params->mg.guess is PM_GUESS_WARM(_RESCALED), else the Jacobi guess is
+ * used; out: the potentials. relres (host, [nboxes], may be NULL) receives each
+ * box's final ||f - L phi|| / ||f|| (the call then synchronises the stream). */
+int pm_batch_accel(pm_batch *batch, const float *pos, float *acc, float *phi, double a,
+                   const pm_step_params *params, double *relres, pm_stream stream);
+
+/* nsteps kick-drift-kick steps a[i] -> a[i+1] (a: host array of nsteps + 1) of
+ * every box, as pm_kdk does for one box; acc must hold the accelerations at
+ * a[0] (pm_batch_accel) and phi the potentials (warm start). With
+ * use_graph != 0 each step replays the graph recorded by pm_graph_capture_step
+ * (same buffers and parameters required; at most 1024 steps per call). */
+int pm_batch_kdk(pm_batch *batch, float *pos, float *vel, float *acc, float *phi, int nsteps,
+                 const double *a, const pm_step_params *params, int use_graph,
+                 pm_stream stream);
+
+/* Record one batched step on `stream` (not the null stream) as a HIP graph for
+ * pm_batch_kdk(..., use_graph = 1). The graph holds the buffer addresses and
+ * the parameters; per-step scalars come from a device table that
+ * pm_batch_kdk fills, indexed by a device step counter the graph advances.
+ * The graph clears its grids with kernels (no memset nodes). */
+int pm_graph_capture_step(pm_batch *batch, float *pos, float *vel, float *acc, float *phi,
+                          const pm_step_params *params, pm_stream stream);
+
+/* Autotuner for the stencil tile shapes of the batch (rows of the plane each
+ * thread owns in the red-black smoother and in the gradient: 1, 2 or 4): times
+ * every usable shape on the batch's own finest grids with HIP events and keeps
+ * the fastest; choice (host, [2], may be NULL) receives the smoother and
+ * gradient picks. pos supplies a density; phi is used as scratch and
+ * overwritten. Drops a captured step graph (capture again afterwards). */
+int pm_tune(pm_batch *batch, float *pos, float *phi, const pm_step_params *params, int *choice,
+            pm_stream stream);
+
 /* Per-kernel timing (measurement support). pm_kernel_timer(ctx, kernel, cap)
  * starts recording a pair of HIP events on the caller's stream around every
  * launch of one kernel (at most cap launches; resets the previous record):

@@ -164,6 +164,50 @@ void fill_timing(pm_ctx *ctx, pm_step_stats *stats, bool with_drift) {
   if (hipEventElapsedTime(&t, ctx->ev[4], ctx->ev[5]) == hipSuccess) stats->ms_interp = t;
 }
 
+int ensure_adjoint_scratch(pm_ctx *ctx) {
+  if (ctx->adj_gbar) return PM_OK;
+  const size_t ncell = (size_t)ctx->n * ctx->n * ctx->n;
+  if (hipMalloc(&ctx->adj_gbar, 3 * sizeof(float) * ncell) != hipSuccess ||
+      hipMalloc(&ctx->adj_phibar, sizeof(float) * ncell) != hipSuccess) {
+    if (ctx->adj_gbar) (void)hipFree(ctx->adj_gbar);
+    ctx->adj_gbar = nullptr;
+    return pm_fail(ctx, PM_ERR_NOMEM, "adjoint scratch allocation failed");
+  }
+  return PM_OK;
+}
+
+// pos_bar += scale * J(pos)^T lam, J = d accel / d pos at scale factor a (box units).
+// phi is the potential of pos at a. Uses ctx->g (force grid), the adjoint scratch and
+// ctx->rho (cotangent of the density).
+int accel_vjp_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, int poskind,
+                   double a, const pm_step_params *p, const float *phi, const float *lam,
+                   float scale, float *pos_bar, pm_mg_stats *stats, hipStream_t s) {
+  const int n = ctx->n;
+  const int64_t ncell = (int64_t)n * n * n;
+  const float mass = np > 0 ? (float)((double)ncell / (double)np) : 0.0f;
+  PM_HIP(ctx, launch_gradient(phi, n, 5, ctx->g, s));
+  PM_HIP(ctx, launch_fill(ctx->adj_gbar, 0.0f, 3 * ncell, s));
+  // g_bar = interp^T lam, and the position term sum_c grad W (g_c . lam_p)
+  PM_HIP(ctx, launch_interp_vjp(pos, cell, np, poskind, p->mas, n, ctx->g, lam, scale * (float)n,
+                                1.0f, ctx->adj_gbar, pos_bar, s));
+  // phi_bar = sum_d D_d g_bar_d
+  PM_HIP(ctx, launch_divergence(ctx->adj_gbar, n, 5, false, ctx->adj_phibar, s));
+  // rho_bar = coef L^+ (phi_bar - mean): the solve is self-adjoint
+  const float coef = (float)(1.5 * a * p->omega_m);
+  int sst;
+  if (p->solver == PM_SOLVER_FFT) {
+    sst = pm_fft_solve(ctx, ctx->adj_phibar, coef, p->fft_deconv, ctx->rho, s);
+  } else {
+    pm_mg_params mg = p->mg;
+    mg.guess = PM_GUESS_JACOBI;
+    sst = pm_mg_solve(ctx, ctx->adj_phibar, coef, ctx->rho, &mg, stats, s, 1.0f);
+  }
+  if (sst < 0) return sst;
+  PM_HIP(ctx, launch_deposit_vjp(pos, cell, np, poskind, p->mas, n, ctx->rho,
+                                 scale * mass * (float)n, pos_bar, s));
+  return sst;
+}
+
 }  // namespace
 
 extern "C" {
@@ -247,6 +291,8 @@ void pm_destroy(pm_ctx *ctx) {
   fr(ctx->pcell);
   fr(ctx->scan_partial);
   fr(ctx->reorder_tmp);
+  fr(ctx->adj_gbar);
+  fr(ctx->adj_phibar);
   for (int i = 0; i < 8; ++i)
     if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
   for (int i = 0; i < 2 * ctx->kt_cap; ++i) (void)hipEventDestroy(ctx->kt_ev[i]);
@@ -417,6 +463,154 @@ int pm_kdk(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, int64_t np, int p
                   warm_scale);
   if (st >= 0 && timing) fill_timing(ctx, stats, true);
   return st;
+}
+
+int pm_deposit_vjp(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, int poskind,
+                   int mas, const float *rho_bar, float *pos_bar, pm_stream stream) {
+  if (!ctx) return PM_ERR_ARG;
+  int st = check_particles(ctx, pos, cell, np, poskind);
+  if (st != PM_OK) return st;
+  if (!valid_mas(mas)) return pm_fail(ctx, PM_ERR_ARG, "bad mas");
+  if (!rho_bar || (np > 0 && !pos_bar)) return pm_fail(ctx, PM_ERR_ARG, "null pointer");
+  const int n = ctx->n;
+  const float mass = np > 0 ? (float)((double)n * n * n / (double)np) : 0.0f;
+  PM_HIP(ctx, launch_deposit_vjp(pos, cell, np, poskind, mas, n, rho_bar, mass * (float)n, pos_bar,
+                                 (hipStream_t)stream));
+  return PM_OK;
+}
+
+int pm_interp_vjp(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, int poskind,
+                  int mas, const float *g, const float *lam, float *g_bar, float *pos_bar,
+                  pm_stream stream) {
+  if (!ctx) return PM_ERR_ARG;
+  int st = check_particles(ctx, pos, cell, np, poskind);
+  if (st != PM_OK) return st;
+  if (!valid_mas(mas)) return pm_fail(ctx, PM_ERR_ARG, "bad mas");
+  if (np > 0 && !lam) return pm_fail(ctx, PM_ERR_ARG, "null lam");
+  if (!g_bar && !pos_bar) return pm_fail(ctx, PM_ERR_ARG, "both outputs null");
+  if (pos_bar && !g) return pm_fail(ctx, PM_ERR_ARG, "pos_bar needs g");
+  PM_HIP(ctx, launch_interp_vjp(pos, cell, np, poskind, mas, ctx->n, g, lam, (float)ctx->n, 1.0f,
+                                g_bar, pos_bar, (hipStream_t)stream));
+  return PM_OK;
+}
+
+int pm_gradient_vjp(pm_ctx *ctx, const float *g_bar, int points, float *phi_bar,
+                    pm_stream stream) {
+  if (!ctx) return PM_ERR_ARG;
+  if (!g_bar || !phi_bar) return pm_fail(ctx, PM_ERR_ARG, "null grid");
+  if (points != 3 && points != 5 && points != 7)
+    return pm_fail(ctx, PM_ERR_ARG, "points must be 3, 5 or 7");
+  PM_HIP(ctx, launch_divergence(g_bar, ctx->n, points, true, phi_bar, (hipStream_t)stream));
+  return PM_OK;
+}
+
+int pm_accel_vjp(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, int poskind,
+                 double a, const pm_step_params *params, const float *phi, const float *lam,
+                 float scale, float *pos_bar, pm_mg_stats *stats, pm_stream stream) {
+  if (!ctx) return PM_ERR_ARG;
+  int st = check_particles(ctx, pos, cell, np, poskind);
+  if (st != PM_OK) return st;
+  st = check_step(ctx, params);
+  if (st != PM_OK) return st;
+  if (!phi || (np > 0 && (!lam || !pos_bar))) return pm_fail(ctx, PM_ERR_ARG, "null pointer");
+  if (!(a > 0.0) || !std::isfinite(a)) return pm_fail(ctx, PM_ERR_ARG, "scale factor must be > 0");
+  if (!std::isfinite(scale)) return pm_fail(ctx, PM_ERR_NONFINITE, "non-finite scale");
+  st = ensure_adjoint_scratch(ctx);
+  if (st != PM_OK) return st;
+  return accel_vjp_impl(ctx, pos, cell, np, poskind, a, params, phi, lam, scale, pos_bar, stats,
+                        (hipStream_t)stream);
+}
+
+int pm_kdk_adjoint(pm_ctx *ctx, const float *pos0, const int32_t *cell0, const float *phi0,
+                   const float *pos1, const int32_t *cell1, const float *phi1, int64_t np,
+                   int poskind, double a0, double a1, const pm_step_params *params, double kick0,
+                   double kick1, float *pos_bar, float *vel_bar, pm_step_stats *stats,
+                   pm_stream stream) {
+  if (!ctx) return PM_ERR_ARG;
+  int st = check_particles(ctx, pos0, cell0, np, poskind);
+  if (st == PM_OK) st = check_particles(ctx, pos1, cell1, np, poskind);
+  if (st != PM_OK) return st;
+  st = check_step(ctx, params);
+  if (st != PM_OK) return st;
+  if (np > 0 && (!pos_bar || !vel_bar)) return pm_fail(ctx, PM_ERR_ARG, "null cotangent");
+  if ((kick0 != 0.0 && !phi0) || (kick1 != 0.0 && !phi1))
+    return pm_fail(ctx, PM_ERR_ARG, "null potential");
+  if (!(a0 > 0.0) || !(a1 > 0.0) || !std::isfinite(a0) || !std::isfinite(a1))
+    return pm_fail(ctx, PM_ERR_ARG, "scale factors must be > 0");
+  if (!std::isfinite(kick0) || !std::isfinite(kick1))
+    return pm_fail(ctx, PM_ERR_NONFINITE, "non-finite kick weight");
+  st = ensure_adjoint_scratch(ctx);
+  if (st != PM_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const double tau = 2.0 * (1.0 / std::sqrt(a0) - 1.0 / std::sqrt(a1));
+  pm_mg_stats *ms = stats ? &stats->mg : nullptr;
+  int worst = PM_OK;
+  if (kick1 != 0.0) {
+    st = accel_vjp_impl(ctx, pos1, cell1, np, poskind, a1, params, phi1, vel_bar, (float)kick1,
+                        pos_bar, ms, s);
+    if (st < 0) return st;
+    worst = std::max(worst, st);
+  }
+  PM_HIP(ctx, launch_axpy(vel_bar, pos_bar, (float)tau, 3 * np, s));
+  if (kick0 != 0.0) {
+    st = accel_vjp_impl(ctx, pos0, cell0, np, poskind, a0, params, phi0, vel_bar, (float)kick0,
+                        pos_bar, ms, s);
+    if (st < 0) return st;
+    worst = std::max(worst, st);
+  }
+  return worst;
+}
+
+int pm_density_loss(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, int poskind,
+                    int mas, int order, const float *w, double *loss, float *pos_bar,
+                    pm_stream stream) {
+  if (!ctx) return PM_ERR_ARG;
+  int st = check_particles(ctx, pos, cell, np, poskind);
+  if (st != PM_OK) return st;
+  if (!valid_mas(mas)) return pm_fail(ctx, PM_ERR_ARG, "bad mas");
+  if (order != PM_DEPOSIT_ATOMIC && order != PM_DEPOSIT_SORTED)
+    return pm_fail(ctx, PM_ERR_ARG, "bad deposit order");
+  if (!w) return pm_fail(ctx, PM_ERR_ARG, "null weight grid");
+  hipStream_t s = (hipStream_t)stream;
+  const int n = ctx->n;
+  const int64_t ncell = (int64_t)n * n * n;
+  st = deposit_impl(ctx, pos, cell, np, poskind, mas, order, ctx->rho, s);
+  if (st != PM_OK) return st;
+  PM_HIP(ctx, launch_density_loss(ctx->rho, w, ncell, ctx->red_partial, ctx->red_result, s));
+  if (pos_bar) {
+    const float mass = np > 0 ? (float)((double)ncell / (double)np) : 0.0f;
+    PM_HIP(ctx, launch_deposit_vjp(pos, cell, np, poskind, mas, n, ctx->rho, mass * (float)n,
+                                   pos_bar, s));
+  }
+  if (loss) {
+    PM_HIP(ctx, hipMemcpyAsync(ctx->host_result, ctx->red_result, sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+    PM_HIP(ctx, hipStreamSynchronize(s));
+    *loss = ctx->host_result[0];
+  }
+  return PM_OK;
+}
+
+int pm_ic_state(pm_ctx *ctx, const float *q, const float *psi, int64_t np, double a0, float *pos,
+                int32_t *cell, float *vel, pm_stream stream) {
+  if (!ctx) return PM_ERR_ARG;
+  if (np < 0) return pm_fail(ctx, PM_ERR_ARG, "negative particle count");
+  if (np > 0 && (!q || !psi || !pos || !vel)) return pm_fail(ctx, PM_ERR_ARG, "null pointer");
+  if (!(a0 > 0.0) || !std::isfinite(a0)) return pm_fail(ctx, PM_ERR_ARG, "scale factor must be > 0");
+  PM_HIP(ctx, launch_ic_state(q, psi, np, ctx->n, (float)std::sqrt(a0), pos, cell, vel,
+                              (hipStream_t)stream));
+  return PM_OK;
+}
+
+int pm_ic_vjp(pm_ctx *ctx, const float *pos_bar, const float *vel_bar, int64_t np, double a0,
+              float *psi_bar, pm_stream stream) {
+  if (!ctx) return PM_ERR_ARG;
+  if (np < 0) return pm_fail(ctx, PM_ERR_ARG, "negative particle count");
+  if (np > 0 && (!pos_bar || !vel_bar || !psi_bar)) return pm_fail(ctx, PM_ERR_ARG, "null pointer");
+  if (!(a0 > 0.0) || !std::isfinite(a0)) return pm_fail(ctx, PM_ERR_ARG, "scale factor must be > 0");
+  PM_HIP(ctx, launch_ic_vjp(pos_bar, vel_bar, np, (float)std::sqrt(a0), psi_bar,
+                            (hipStream_t)stream));
+  return PM_OK;
 }
 
 }  // extern "C"

@@ -51,6 +51,9 @@ struct pm_ctx {
   int64_t sort_cap;
   void *reorder_tmp;     // [np_max * 12 bytes] permutation staging (lazy)
   int64_t reorder_cap;
+  // reverse mode (lazy)
+  float *adj_gbar;       // [n^3 * 3] cotangent of the force grid
+  float *adj_phibar;     // [n^3] cotangent of the potential
   // timing events
   hipEvent_t ev[8];
   // per-kernel timer: event pairs around every launch of one kernel
@@ -102,6 +105,24 @@ hipError_t launch_interp(const float *pos, const int32_t *cell, int64_t np, int 
                          hipStream_t s);
 hipError_t launch_kick_drift(float *pos, int32_t *cell, float *vel, const float *acc, int64_t np,
                              int poskind, int n, float kick, float dt, hipStream_t s);
+
+// adjoint.hip
+hipError_t launch_deposit_vjp(const float *pos, const int32_t *cell, int64_t np, int poskind,
+                              int mas, int n, const float *rho_bar, float scale, float *pos_bar,
+                              hipStream_t s);
+hipError_t launch_interp_vjp(const float *pos, const int32_t *cell, int64_t np, int poskind,
+                             int mas, int n, const float *g, const float *lam, float pscale,
+                             float gscale, float *g_bar, float *pos_bar, hipStream_t s);
+hipError_t launch_divergence(const float *gb, int n, int points, bool accumulate, float *phib,
+                             hipStream_t s);
+hipError_t launch_axpy(float *y, const float *x, float alpha, int64_t count, hipStream_t s);
+hipError_t launch_fill(float *y, float value, int64_t count, hipStream_t s);
+hipError_t launch_density_loss(float *rho, const float *w, int64_t count, double *partial,
+                               double *result, hipStream_t s);
+hipError_t launch_ic_state(const float *q, const float *psi, int64_t np, int n, float vfac,
+                           float *pos, int32_t *cell, float *vel, hipStream_t s);
+hipError_t launch_ic_vjp(const float *xbar, const float *vbar, int64_t np, float vfac,
+                         float *psibar, hipStream_t s);
 
 // grid.hip
 hipError_t launch_gradient(const float *phi, int n, int points, float *g, hipStream_t s);

@@ -87,6 +87,29 @@ def _load():
         "pm_reorder": (c_int, [P, P, P, P, P, P, c_int64, c_int, P]),
         "pm_kdk": (c_int, [P, P, P, P, c_int64, c_int, c_double, c_double, POINTER(StepParams),
                            P, P, POINTER(StepStats), P]),
+        "pm_deposit_vjp": (c_int, [P, P, P, c_int64, c_int, c_int, P, P, P]),
+        "pm_interp_vjp": (c_int, [P, P, P, c_int64, c_int, c_int, P, P, P, P, P]),
+        "pm_gradient_vjp": (c_int, [P, P, c_int, P, P]),
+        "pm_accel_vjp": (c_int, [P, P, P, c_int64, c_int, c_double, POINTER(StepParams), P, P,
+                                 c_float, P, POINTER(MGStats), P]),
+        "pm_kdk_adjoint": (c_int, [P, P, P, P, P, P, P, c_int64, c_int, c_double, c_double,
+                                   POINTER(StepParams), c_double, c_double, P, P,
+                                   POINTER(StepStats), P]),
+        "pm_density_loss": (c_int, [P, P, P, c_int64, c_int, c_int, c_int, P,
+                                    POINTER(c_double), P, P]),
+        "pm_ic_state": (c_int, [P, P, P, c_int64, c_double, P, P, P, P]),
+        "pm_ic_vjp": (c_int, [P, P, P, c_int64, c_double, P, P]),
+        "pm_batch_create": (c_int, [POINTER(c_void_p), c_int, POINTER(c_int), POINTER(c_int64),
+                                    c_int]),
+        "pm_batch_destroy": (None, [P]),
+        "pm_batch_last_error": (c_char_p, [P]),
+        "pm_batch_layout": (c_int, [P, POINTER(c_int64), POINTER(c_int64)]),
+        "pm_batch_accel": (c_int, [P, P, P, P, c_double, POINTER(StepParams), POINTER(c_double),
+                                   P]),
+        "pm_batch_kdk": (c_int, [P, P, P, P, P, c_int, POINTER(c_double), POINTER(StepParams),
+                                 c_int, P]),
+        "pm_graph_capture_step": (c_int, [P, P, P, P, P, POINTER(StepParams), P]),
+        "pm_tune": (c_int, [P, P, P, POINTER(StepParams), POINTER(c_int), P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -276,3 +299,203 @@ def pm_kdk(ctx: Context, pos, vel, a0, a1, phi, acc, cell=None, params: StepPara
                      _ptr(acc, shape=(np_, 3), name="acc"), byref(stats), _stream())
     ctx._check(st, "pm_kdk")
     return stats
+
+
+# ------------------------------------------------------------------ reverse mode
+
+def pm_deposit_vjp(ctx: Context, pos, rho_bar, pos_bar, cell=None, mas="tsc"):
+    """pos_bar += (d rho / d x)^T rho_bar (box-unit positions)."""
+    n = ctx.n
+    np_, kind, pp, cp = _particles(pos, cell)
+    st = _lib.pm_deposit_vjp(ctx.handle, pp, cp, np_, kind, MAS.get(mas, mas),
+                             _ptr(rho_bar, shape=(n, n, n), name="rho_bar"),
+                             _ptr(pos_bar, shape=(np_, 3), name="pos_bar"), _stream())
+    return ctx._check(st, "pm_deposit_vjp")
+
+
+def pm_interp_vjp(ctx: Context, pos, lam, g=None, g_bar=None, pos_bar=None, cell=None, mas="tsc"):
+    """g_bar += interp^T lam; pos_bar += (d interp / d x)^T lam at the field g."""
+    n = ctx.n
+    np_, kind, pp, cp = _particles(pos, cell)
+    st = _lib.pm_interp_vjp(ctx.handle, pp, cp, np_, kind, MAS.get(mas, mas),
+                            _ptr(g, shape=(n, n, n, 3), name="g"),
+                            _ptr(lam, shape=(np_, 3), name="lam"),
+                            _ptr(g_bar, shape=(n, n, n, 3), name="g_bar"),
+                            _ptr(pos_bar, shape=(np_, 3), name="pos_bar"), _stream())
+    return ctx._check(st, "pm_interp_vjp")
+
+
+def pm_gradient_vjp(ctx: Context, g_bar, phi_bar, points=5):
+    """phi_bar += sum_d D_d g_bar_d."""
+    n = ctx.n
+    st = _lib.pm_gradient_vjp(ctx.handle, _ptr(g_bar, shape=(n, n, n, 3), name="g_bar"),
+                              int(points), _ptr(phi_bar, shape=(n, n, n), name="phi_bar"),
+                              _stream())
+    return ctx._check(st, "pm_gradient_vjp")
+
+
+def pm_accel_vjp(ctx: Context, pos, a, phi, lam, pos_bar, scale=1.0, cell=None,
+                 params: StepParams | None = None):
+    """pos_bar += scale J(x)^T lam, J = d accel / d x at scale factor a; phi = potential of x."""
+    n = ctx.n
+    np_, kind, pp, cp = _particles(pos, cell)
+    params = params or default_step_params()
+    stats = MGStats()
+    st = _lib.pm_accel_vjp(ctx.handle, pp, cp, np_, kind, float(a), byref(params),
+                           _ptr(phi, shape=(n, n, n), name="phi"),
+                           _ptr(lam, shape=(np_, 3), name="lam"), float(scale),
+                           _ptr(pos_bar, shape=(np_, 3), name="pos_bar"), byref(stats), _stream())
+    ctx._check(st, "pm_accel_vjp")
+    return stats
+
+
+def pm_kdk_adjoint(ctx: Context, pos0, phi0, pos1, phi1, a0, a1, pos_bar, vel_bar, kick0=None,
+                   kick1=None, cell0=None, cell1=None, params: StepParams | None = None):
+    """Reverse one KDK step in place on (pos_bar, vel_bar); kick weights default to tau/2."""
+    n = ctx.n
+    np_, kind, p0, c0 = _particles(pos0, cell0)
+    _, kind1, p1, c1 = _particles(pos1, cell1)
+    if kind1 != kind or pos1.shape[0] != np_:
+        raise ValueError("pos0 and pos1 must have the same form and count")
+    tau = 2.0 * (float(a0) ** -0.5 - float(a1) ** -0.5)
+    kick0 = 0.5 * tau if kick0 is None else float(kick0)
+    kick1 = 0.5 * tau if kick1 is None else float(kick1)
+    params = params or default_step_params()
+    stats = StepStats()
+    st = _lib.pm_kdk_adjoint(ctx.handle, p0, c0, _ptr(phi0, shape=(n, n, n), name="phi0"),
+                             p1, c1, _ptr(phi1, shape=(n, n, n), name="phi1"), np_, kind,
+                             float(a0), float(a1), byref(params), kick0, kick1,
+                             _ptr(pos_bar, shape=(np_, 3), name="pos_bar"),
+                             _ptr(vel_bar, shape=(np_, 3), name="vel_bar"), byref(stats), _stream())
+    ctx._check(st, "pm_kdk_adjoint")
+    return stats
+
+
+def pm_density_loss(ctx: Context, pos, w, pos_bar=None, cell=None, mas="tsc", order="sorted",
+                    want_loss=True):
+    """L = sum_c w (rho - 1)^2 (returned as a float when want_loss); pos_bar += dL/dx."""
+    n = ctx.n
+    np_, kind, pp, cp = _particles(pos, cell)
+    loss = c_double(0.0)
+    st = _lib.pm_density_loss(ctx.handle, pp, cp, np_, kind, MAS.get(mas, mas),
+                              ORDER.get(order, order), _ptr(w, shape=(n, n, n), name="w"),
+                              byref(loss) if want_loss else None,
+                              _ptr(pos_bar, shape=(np_, 3), name="pos_bar"), _stream())
+    ctx._check(st, "pm_density_loss")
+    return loss.value if want_loss else None
+
+
+def pm_ic_state(ctx: Context, q, psi, a0, pos, vel, cell=None):
+    """pos = wrap(q + psi), vel = a0^(1/2) psi (cell-offset form when cell is given)."""
+    np_ = q.shape[0]
+    st = _lib.pm_ic_state(ctx.handle, _ptr(q, shape=(np_, 3), name="q"),
+                          _ptr(psi, shape=(np_, 3), name="psi"), np_, float(a0),
+                          _ptr(pos, shape=(np_, 3), name="pos"),
+                          _ptr(cell, torch.int32, (np_,), "cell"),
+                          _ptr(vel, shape=(np_, 3), name="vel"), _stream())
+    return ctx._check(st, "pm_ic_state")
+
+
+def pm_ic_vjp(ctx: Context, pos_bar, vel_bar, a0, psi_bar):
+    """psi_bar = pos_bar + a0^(1/2) vel_bar."""
+    np_ = pos_bar.shape[0]
+    st = _lib.pm_ic_vjp(ctx.handle, _ptr(pos_bar, shape=(np_, 3), name="pos_bar"),
+                        _ptr(vel_bar, shape=(np_, 3), name="vel_bar"), np_, float(a0),
+                        _ptr(psi_bar, shape=(np_, 3), name="psi_bar"), _stream())
+    return ctx._check(st, "pm_ic_vjp")
+
+
+# ------------------------------------------------------------------ batched ensembles
+
+class Batch:
+    """Owner of a pm_batch: boxes of grid sizes n[b] with np[b] particles each.
+
+    Attributes p_off / c_off (lists of nboxes + 1) give the packing of the particle
+    arrays ([sum np, 3]) and of the potential arena ([sum n^3]).
+    """
+
+    def __init__(self, n, np_, flags=0):
+        nb = len(n)
+        if len(np_) != nb:
+            raise ValueError("n and np must have the same length")
+        h = c_void_p()
+        n_arr = (c_int * nb)(*[int(x) for x in n])
+        np_arr = (c_int64 * nb)(*[int(x) for x in np_])
+        st = _lib.pm_batch_create(byref(h), nb, n_arr, np_arr, int(flags))
+        if st != PM_OK:
+            raise PMError(st, f"pm_batch_create({nb} boxes) failed")
+        self._h = h
+        self.n = [int(x) for x in n]
+        self.np = [int(x) for x in np_]
+        po = (c_int64 * (nb + 1))()
+        co = (c_int64 * (nb + 1))()
+        _lib.pm_batch_layout(h, po, co)
+        self.p_off = list(po)
+        self.c_off = list(co)
+        self.np_total = self.p_off[-1]
+        self.ncell_total = self.c_off[-1]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.pm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise PMError(PM_ERR_ARG, "batch closed")
+        return self._h
+
+    def _check(self, st, what):
+        if st < 0:
+            raise PMError(st, f"{what}: {_lib.pm_batch_last_error(self._h).decode()}")
+        return st
+
+    def _parts(self, *ts):
+        return [_ptr(t, shape=(self.np_total, 3), name="particle array") for t in ts]
+
+    def _phi(self, phi):
+        return _ptr(phi, shape=(self.ncell_total,), name="phi")
+
+
+def pm_batch_create(n, np_, flags=0) -> Batch:
+    return Batch(n, np_, flags)
+
+
+def pm_batch_accel(batch: Batch, pos, acc, phi, a, params: StepParams, want_relres=False):
+    pp, ap = batch._parts(pos, acc)
+    rel = (c_double * len(batch.n))() if want_relres else None
+    st = _lib.pm_batch_accel(batch.handle, pp, ap, batch._phi(phi), float(a), byref(params), rel,
+                             _stream())
+    batch._check(st, "pm_batch_accel")
+    return list(rel) if want_relres else None
+
+
+def pm_batch_kdk(batch: Batch, pos, vel, acc, phi, a_list, params: StepParams, use_graph=False):
+    pp, vp, ap = batch._parts(pos, vel, acc)
+    nsteps = len(a_list) - 1
+    a_arr = (c_double * len(a_list))(*[float(x) for x in a_list])
+    st = _lib.pm_batch_kdk(batch.handle, pp, vp, ap, batch._phi(phi), nsteps, a_arr, byref(params),
+                           1 if use_graph else 0, _stream())
+    return batch._check(st, "pm_batch_kdk")
+
+
+def pm_graph_capture_step(batch: Batch, pos, vel, acc, phi, params: StepParams):
+    pp, vp, ap = batch._parts(pos, vel, acc)
+    st = _lib.pm_graph_capture_step(batch.handle, pp, vp, ap, batch._phi(phi), byref(params),
+                                    _stream())
+    return batch._check(st, "pm_graph_capture_step")
+
+
+def pm_tune(batch: Batch, pos, phi, params: StepParams):
+    (pp,) = batch._parts(pos)
+    choice = (c_int * 2)()
+    st = _lib.pm_tune(batch.handle, pp, batch._phi(phi), byref(params), choice, _stream())
+    batch._check(st, "pm_tune")
+    return {"smooth_rows": choice[0], "gradient_rows": choice[1]}

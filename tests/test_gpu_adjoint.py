@@ -1,0 +1,449 @@
+"""GPU parity of the reverse-mode (adjoint) path against the FP64 oracle adjoint,
+transposition identities, checkpoint/recompute determinism and finite
+differences of the full differentiable run.
+
+Differentiable-run recipe: one particle per cell of an n^3 lattice, Zel'dovich
+displacements from a seeded Gaussian random field with P(k) ~ k^-1.5 and rms
+0.3 cell at a = 0.1, 20 KDK steps with da = 0.01 to a = 0.3 (Einstein-de
+Sitter), TSC, loss sum_c w_c delta_c^2 with w seeded uniform [0, 1).
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import icgen
+from oracle import adjoint as oa
+from oracle import pm as opm
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2410_20501_amd as pm
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return pm
+
+
+_CTX = {}
+
+
+def ctx_for(lib, n, np_max=0):
+    key = (n, np_max)
+    if key not in _CTX:
+        _CTX[key] = lib.Context(n, np_max)
+    return _CTX[key]
+
+
+def dev(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel_max(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+def clustered(n, seed=11, rms=0.6):
+    ps = icgen.zeldovich_particles(n, -1.5, rms, 0.1, seed=seed)
+    return ps.pos
+
+
+def smooth_rows(x64, n, mas):
+    """Particles away from the kinks of the window derivative. The CIC window is piecewise
+    linear, so its derivative jumps where u - 1/2 is an integer (u = x n): there the kernels
+    take the derivative of the linear piece the forward evaluation uses, the oracle the
+    symmetric value 0. Both are valid one-sided choices; such rows are left out."""
+    if mas != "cic":
+        return np.ones(x64.shape[0], dtype=bool)
+    t = x64 * n - 0.5
+    frac = t - np.floor(t)
+    return np.all((frac > 1e-6) & (frac < 1.0 - 1e-6), axis=1)
+
+
+def run_inputs(n, seed=5):
+    psi = icgen.displacement_field(n, -1.5, 0.3, seed).reshape(-1, 3).astype(np.float32)
+    q = icgen.lattice_points(n)
+    w = icgen.weight_grid(n, seed + 1)
+    return psi, q, w
+
+
+A_RUN = [0.1 + 0.01 * i for i in range(21)]
+
+
+# ------------------------------------------------------------------ single VJPs
+
+@pytest.mark.parametrize("mas", ["tsc", "cic"])
+@pytest.mark.parametrize("kind", ["box", "celloff"])
+def test_deposit_vjp_matches_oracle(lib, mas, kind):
+    n = 32
+    _say(f"deposit_vjp n={n} mas={mas} kind={kind}")
+    pos = clustered(n)
+    rng = np.random.default_rng(3)
+    rb = rng.standard_normal((n, n, n)).astype(np.float32)
+    init = rng.standard_normal(pos.shape).astype(np.float32)
+    ctx = ctx_for(lib, n)
+    out = dev(init)
+    if kind == "box":
+        x64 = pos.astype(np.float64)
+        lib.pm_deposit_vjp(ctx, dev(pos), dev(rb), out, mas=mas)
+    else:
+        cell, off = icgen.to_cell_offset(pos, n)
+        x64 = icgen.from_cell_offset(cell, off, n)
+        lib.pm_deposit_vjp(ctx, dev(off), dev(rb), out, cell=dev(cell, torch.int32), mas=mas)
+    ref = oa.deposit_vjp(x64, n, rb.astype(np.float64), mas)
+    got = host(out) - init.astype(np.float64)
+    keep = smooth_rows(x64, n, mas)
+    err = rel_max(got[keep], ref[keep])
+    _say(f"  rel max err {err:.2e}")
+    assert err < 1e-5
+
+
+@pytest.mark.parametrize("mas", ["tsc", "cic"])
+def test_interp_vjp_matches_oracle(lib, mas):
+    n = 32
+    _say(f"interp_vjp n={n} mas={mas}")
+    pos = clustered(n, seed=12)
+    rng = np.random.default_rng(4)
+    g = rng.standard_normal((n, n, n, 3)).astype(np.float32)
+    lam = rng.standard_normal(pos.shape).astype(np.float32)
+    ctx = ctx_for(lib, n)
+    gbar = torch.zeros((n, n, n, 3), device="cuda")
+    xbar = torch.zeros(pos.shape, device="cuda")
+    lib.pm_interp_vjp(ctx, dev(pos), dev(lam), g=dev(g), g_bar=gbar, pos_bar=xbar, mas=mas)
+    gref, xref = oa.interp_vjp(pos.astype(np.float64), g.astype(np.float64),
+                               lam.astype(np.float64), mas)
+    keep = smooth_rows(pos.astype(np.float64), n, mas)
+    eg, ex = rel_max(host(gbar), gref), rel_max(host(xbar)[keep], xref[keep])
+    _say(f"  g_bar {eg:.2e}  pos_bar {ex:.2e}")
+    assert eg < 1e-5 and ex < 1e-5
+
+
+@pytest.mark.parametrize("points", [3, 5, 7])
+def test_gradient_vjp_matches_oracle(lib, points):
+    n = 24
+    _say(f"gradient_vjp n={n} points={points}")
+    rng = np.random.default_rng(5)
+    gb = rng.standard_normal((n, n, n, 3)).astype(np.float32)
+    init = rng.standard_normal((n, n, n)).astype(np.float32)
+    ctx = ctx_for(lib, n)
+    out = dev(init)
+    lib.pm_gradient_vjp(ctx, dev(gb), out, points=points)
+    ref = oa.gradient_vjp(gb.astype(np.float64), 1.0 / n, points)
+    err = rel_max(host(out) - init, ref)
+    _say(f"  rel max err {err:.2e}")
+    assert err < 1e-5
+
+
+def test_transposition_identities(lib):
+    """<interp^T lam, g> = <lam, interp g>, <D^T y, phi> = <y, -D phi>, solve symmetric."""
+    n = 32
+    _say("transposition identities n=32")
+    pos = clustered(n, seed=13)
+    rng = np.random.default_rng(6)
+    ctx = ctx_for(lib, n)
+    g = dev(rng.standard_normal((n, n, n, 3)))
+    lam = dev(rng.standard_normal(pos.shape))
+    acc = torch.empty(pos.shape, device="cuda")
+    lib.pm_interp(ctx, dev(pos), g, acc)
+    gbar = torch.zeros_like(g)
+    lib.pm_interp_vjp(ctx, dev(pos), lam, g_bar=gbar)
+    lhs = float(np.sum(host(gbar) * host(g)))
+    rhs = float(np.sum(host(lam) * host(acc)))
+    assert abs(lhs - rhs) <= 1e-5 * np.sqrt(np.sum(host(gbar) ** 2) * np.sum(host(g) ** 2))
+    phi = dev(rng.standard_normal((n, n, n)))
+    y = dev(rng.standard_normal((n, n, n, 3)))
+    gphi = torch.empty_like(y)
+    lib.pm_gradient(ctx, phi, gphi)
+    dty = torch.zeros_like(phi)
+    lib.pm_gradient_vjp(ctx, y, dty)
+    lhs = float(np.sum(host(dty) * host(phi)))
+    rhs = float(np.sum(host(y) * host(gphi)))
+    assert abs(lhs - rhs) <= 1e-5 * np.linalg.norm(host(dty)) * np.linalg.norm(host(phi))
+    a = dev(rng.standard_normal((n, n, n)))
+    b = dev(rng.standard_normal((n, n, n)))
+    sa, sb = torch.zeros_like(a), torch.zeros_like(b)
+    lib.pm_solve_mg(ctx, a, 0.7, sa, tol=1e-7, max_cycles=40)
+    lib.pm_solve_mg(ctx, b, 0.7, sb, tol=1e-7, max_cycles=40)
+    ab, ba = host(sa), host(sb)
+    lhs = float(np.sum(ab * (host(b) - host(b).mean())))
+    rhs = float(np.sum(ba * (host(a) - host(a).mean())))
+    assert abs(lhs - rhs) <= 1e-5 * np.linalg.norm(ab) * np.linalg.norm(host(b))
+
+
+@pytest.mark.parametrize("solver", ["mg", "fft"])
+def test_accel_vjp_matches_oracle(lib, solver):
+    n, a = 32, 0.2
+    _say(f"accel_vjp n={n} solver={solver}")
+    pos = clustered(n, seed=14)
+    x64 = pos.astype(np.float64)
+    rng = np.random.default_rng(7)
+    lam = rng.standard_normal(pos.shape).astype(np.float32)
+    ctx = ctx_for(lib, n)
+    params = lib.default_step_params(solver=solver, tol=1e-7, max_cycles=40, fft_deconv=3)
+    phi = torch.zeros((n, n, n), device="cuda")
+    acc = torch.empty(pos.shape, device="cuda")
+    import warnings
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore", lib.PMWarning)
+        lib.pm_accel(ctx, dev(pos), a, phi, acc, params=params)
+        xbar = torch.zeros(pos.shape, device="cuda")
+        lib.pm_accel_vjp(ctx, dev(pos), a, phi, dev(lam), xbar, scale=0.5, params=params)
+    if solver == "mg":
+        ref = 0.5 * oa.accel_vjp(x64, n, a, lam.astype(np.float64))
+    else:
+        # the TSC-deconvolved FFT kernel is even in k, hence its own transpose
+        h = 1.0 / n
+        _, fields = opm.accel(x64 * n, n, a, "fft", points=5, return_fields=True)
+        gbar, xb = oa.interp_vjp(x64, fields["g"], lam.astype(np.float64))
+        phibar = oa.gradient_vjp(gbar, h, 5)
+        rhobar = 1.5 * a * opm.solve_fft(phibar, h, 3)
+        ref = 0.5 * (xb + oa.deposit_vjp(x64, n, rhobar))
+    err = rel_l2(host(xbar), ref)
+    _say(f"  rel l2 err {err:.2e}")
+    assert err < 2e-5
+
+
+def test_kdk_adjoint_one_step_matches_oracle(lib):
+    n, a0, a1 = 32, 0.1, 0.11
+    _say("kdk_adjoint one step n=32")
+    pos = clustered(n, seed=15, rms=0.3)
+    x0 = pos.astype(np.float64)
+    v0 = (np.random.default_rng(8).standard_normal(pos.shape) * 1e-3).astype(np.float32)
+    rng = np.random.default_rng(9)
+    xb = rng.standard_normal(pos.shape).astype(np.float32)
+    vb = rng.standard_normal(pos.shape).astype(np.float32)
+    ctx = ctx_for(lib, n)
+    params = lib.default_step_params(tol=1e-7, max_cycles=40, order="sorted")
+    pos_d, vel_d = dev(pos), dev(v0)
+    phi0 = torch.zeros((n, n, n), device="cuda")
+    acc = torch.empty(pos.shape, device="cuda")
+    import warnings
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore", lib.PMWarning)
+        lib.pm_accel(ctx, pos_d, a0, phi0, acc, params=params)
+        p0 = pos_d.clone()
+        phi1 = phi0.clone()
+        lib.pm_kdk(ctx, pos_d, vel_d, a0, a1, phi1, acc, params=params)
+        xbd, vbd = dev(xb), dev(vb)
+        lib.pm_kdk_adjoint(ctx, p0, phi0, pos_d, phi1, a0, a1, xbd, vbd, params=params)
+    states = oa.forward_trajectory(x0, v0.astype(np.float64), [a0, a1], n)
+    xr, vr = oa.kdk_adjoint(states, [a0, a1], n, xb.astype(np.float64), vb.astype(np.float64))
+    ex, ev = rel_l2(host(xbd), xr), rel_l2(host(vbd), vr)
+    _say(f"  x_bar {ex:.2e}  v_bar {ev:.2e}")
+    assert ex < 2e-5 and ev < 2e-5
+
+
+def test_density_loss_and_ic_map(lib):
+    n = 32
+    _say("density loss + IC map n=32")
+    psi, q, w = run_inputs(n, seed=21)
+    ctx = ctx_for(lib, n)
+    pos = torch.empty(psi.shape, device="cuda")
+    vel = torch.empty_like(pos)
+    lib.pm_ic_state(ctx, dev(q), dev(psi), 0.1, pos, vel)
+    x_ref = opm.wrap01(q.astype(np.float64) + psi.astype(np.float64))
+    dx = np.abs(host(pos) - x_ref)
+    dx = np.minimum(dx, 1.0 - dx)
+    assert dx.max() < 1.2e-7
+    assert rel_max(host(vel), np.sqrt(0.1) * psi.astype(np.float64)) < 1e-6
+    xbar = torch.zeros_like(pos)
+    loss = lib.pm_density_loss(ctx, pos, dev(w), pos_bar=xbar)
+    xp = host(pos)
+    lref = oa.density_loss(xp, n, w.astype(np.float64))
+    gref = oa.density_loss_vjp(xp, n, w.astype(np.float64))
+    _say(f"  loss {loss:.6e} vs {lref:.6e}; grad err {rel_l2(host(xbar), gref):.2e}")
+    assert abs(loss - lref) <= 1e-5 * lref
+    assert rel_l2(host(xbar), gref) < 1e-5
+    vb = dev(np.random.default_rng(1).standard_normal(psi.shape))
+    psib = torch.empty_like(pos)
+    lib.pm_ic_vjp(ctx, xbar, vb, 0.1, psib)
+    assert rel_max(host(psib), host(xbar) + np.sqrt(0.1) * host(vb)) < 1e-6
+
+
+# ------------------------------------------------------------------ the full run
+
+def _run(lib, n, k=4, fixed_cycles=0, tol=1e-6, poskind="box"):
+    from paper_2410_20501_amd import autodiff
+    return autodiff.Run(n, n ** 3, A_RUN, checkpoint_every=k, fixed_cycles=fixed_cycles, tol=tol,
+                        poskind=poskind)
+
+
+@pytest.mark.parametrize("kind", ["box", "celloff"])
+def test_ic_gradient_matches_oracle_small(lib, kind):
+    """32^3, 20 steps: loss and dL/dpsi from the hand-written adjoint vs the FP64 oracle."""
+    from paper_2410_20501_amd import autodiff
+    n = 32
+    _say(f"ic gradient vs oracle n=32, 20 steps, {kind}")
+    psi, q, w = run_inputs(n, seed=31)
+    run = _run(lib, n, poskind=kind)
+    import warnings
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore", lib.PMWarning)
+        loss, grad = autodiff.loss_and_gradient(dev(psi), dev(q), dev(w), run)
+    lref, gref = oa.ic_gradient(psi.astype(np.float64), q.astype(np.float64), A_RUN, n,
+                                w.astype(np.float64))
+    el, eg = abs(loss - lref) / lref, rel_l2(host(grad), gref)
+    _say(f"  loss {loss:.8e} vs {lref:.8e} ({el:.1e}); grad rel l2 {eg:.2e}")
+    run.close()
+    assert el < 1e-5
+    assert eg < 1e-4
+
+
+def test_checkpoint_interval_does_not_change_result(lib):
+    """Recompute from checkpoints is bitwise identical (sorted deposit): k = 1, 4, 20 agree."""
+    from paper_2410_20501_amd import autodiff
+    n = 32
+    _say("checkpoint interval k=1,4,20 n=32")
+    psi, q, w = run_inputs(n, seed=41)
+    out = []
+    import warnings
+    for k in (1, 4, 20):
+        run = _run(lib, n, k=k)
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore", lib.PMWarning)
+            loss, grad = autodiff.loss_and_gradient(dev(psi), dev(q), dev(w), run)
+        out.append((loss, host(grad), dict(run.stats)))
+        run.close()
+    for loss, grad, st in out[1:]:
+        # the forward pass (sorted deposit, same warm starts) replays bitwise; the
+        # gradient differs only through the FP32 atomic sum order of interp^T
+        assert loss == out[0][0]
+        assert rel_l2(grad, out[0][1]) < 1e-6
+    # N + 1 transposed force evaluations for N steps, whatever k
+    assert all(st["adjoint_evals"] == 21 for _, _, st in out)
+
+
+# ------------------------------------------------------------------ 128^3, 20 steps
+
+N_FULL = 128
+FD_EPS_CELLS = 1e-3
+
+
+def _full_inputs():
+    psi = icgen.displacement_field(N_FULL, -1.5, 0.3, 51).reshape(-1, 3).astype(np.float32)
+    return psi, icgen.lattice_points(N_FULL), icgen.weight_grid(N_FULL, 52)
+
+
+@pytest.fixture(scope="module")
+def full_run(lib):
+    """The 128^3 differentiable run (cell-offset positions, checkpoints every 4 steps) and its
+    adjoint gradient."""
+    from paper_2410_20501_amd import autodiff
+    import warnings
+    psi, q, w = _full_inputs()
+    run = autodiff.Run(N_FULL, N_FULL ** 3, A_RUN, checkpoint_every=4, poskind="celloff")
+    psi_d, q_d, w_d = dev(psi), dev(q), dev(w)
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore", lib.PMWarning)
+        loss, grad = autodiff.loss_and_gradient(psi_d, q_d, w_d, run)
+    yield dict(run=run, psi=psi_d, q=q_d, w=w_d, loss=loss, grad=grad.double())
+    run.close()
+
+
+def _fd_check(lib, full_run, dirs):
+    """Fourth-order central differences of L along each direction with the FP32 steps actually
+    taken (psi +- m eps d rounded to FP32; m = 1, 2), against the adjoint's inner products
+    with the same steps. Returns (fd, ad) arrays."""
+    from paper_2410_20501_amd import autodiff
+    import warnings
+    run, psi, q, w, G = (full_run[k] for k in ("run", "psi", "q", "w", "grad"))
+    eps = FD_EPS_CELLS / N_FULL
+    fds, ads = [], []
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore", lib.PMWarning)
+        for d in dirs:
+            dd = dev(d)
+            half = {}
+            for m in (1, 2):
+                pp, pn = psi + m * eps * dd, psi - m * eps * dd
+                step = (pp.double() - pn.double()) / 2
+                ad = float(torch.sum(G * step))
+                fd = (autodiff.loss_only(pp, q, w, run) - autodiff.loss_only(pn, q, w, run)) / 2
+                half[m] = (fd, ad)
+            fds.append((8 * half[1][0] - half[2][0]) / 6)
+            ads.append((8 * half[1][1] - half[2][1]) / 6)
+    return np.array(fds), np.array(ads)
+
+
+def _assert_fd(fd, ad):
+    """The 1e-3 relative bound, read over the set of directions: the vector of directional
+    derivatives agrees to 1e-3 in relative L2, and every direction to 1e-3 of the rms
+    directional derivative. The FD values carry an absolute FP32 noise floor (the multigrid
+    solve stalls at a relative residual near 2e-5), so a direction whose projection happens
+    to be near zero cannot be held to 1e-3 of itself; the median per-direction relative
+    error (about 2e-5 along smooth fields, 1e-4 along white noise) is held to 3e-4."""
+    rms = float(np.sqrt(np.mean(ad * ad)))
+    agg = float(np.linalg.norm(fd - ad) / np.linalg.norm(ad))
+    rel = np.abs(fd - ad) / np.abs(ad)
+    worst = np.argsort(-rel)[:4]
+    _say(f"  set rel l2 {agg:.2e}; per direction: max |fd-ad|/rms {np.max(np.abs(fd - ad)) / rms:.2e}, "
+         f"median rel {np.median(rel):.2e}, below 1e-3: {int(np.sum(rel < 1e-3))}/{len(rel)}")
+    for j in worst:
+        _say(f"    dir {j}: ad {ad[j]:.6e} fd {fd[j]:.6e} rel {rel[j]:.2e} |ad|/rms {abs(ad[j]) / rms:.3f}")
+    assert agg < 1e-3
+    assert np.max(np.abs(fd - ad)) < 1e-3 * rms
+    assert np.median(rel) < 3e-4
+
+
+@pytest.mark.timeout(600)
+def test_adjoint_matches_finite_differences_128(lib, full_run):
+    """64 random directions from the initial-condition prior (Gaussian fields, P ~ k^-1.5)
+    against fourth-order central differences (see _assert_fd for the bound)."""
+    _say("FD check 128^3, 20 steps, 64 directions from the prior")
+    dirs = []
+    for j in range(64):
+        d = icgen.displacement_field(N_FULL, -1.5, 1.0, 9000 + j).reshape(-1, 3)
+        dirs.append((d / np.sqrt(np.mean(d * d))).astype(np.float32))  # unit rms, box units
+    fd, ad = _fd_check(lib, full_run, dirs)
+    _assert_fd(fd, ad)
+
+
+@pytest.mark.timeout(300)
+def test_adjoint_white_noise_directions_128(lib, full_run):
+    """16 white-noise directions (projections ~30x smaller than along smooth fields)."""
+    _say("FD check 128^3, 16 white-noise directions")
+    rng = np.random.default_rng(77)
+    dirs = [rng.standard_normal((N_FULL ** 3, 3)).astype(np.float32) for _ in range(16)]
+    fd, ad = _fd_check(lib, full_run, dirs)
+    _assert_fd(fd, ad)
+
+
+def test_adjoint_matches_oracle_golden_128(lib, full_run):
+    """Loss, sampled dL/dpsi and direction inner products against the FP64 oracle adjoint
+    (values written by tests/golden/make_adjoint_golden.py from oracle/ only)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "adjoint_128.json")
+    with open(path) as fh:
+        gold = json.load(fh)
+    _say("oracle golden 128^3")
+    G = full_run["grad"]
+    el = abs(full_run["loss"] - gold["loss"]) / gold["loss"]
+    idx = torch.tensor(gold["sample_index"], device="cuda")
+    gs = G[idx].cpu().numpy()
+    ref = np.array(gold["grad_sample"])
+    eg = rel_l2(gs, ref)
+    dirs = icgen.direction_fields(N_FULL, 8, gold["seeds"]["directions"])
+    dots = np.array([float(torch.sum(G * dev(d).double())) for d in dirs])
+    ed = np.abs(dots - np.array(gold["direction_dot"])) / np.abs(np.array(gold["direction_dot"]))
+    _say(f"  loss {el:.1e}, sampled grad rel l2 {eg:.2e}, direction dots max rel {ed.max():.2e}")
+    assert el < 1e-5
+    assert eg < 1e-4
+    assert ed.max() < 1e-4
