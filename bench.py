@@ -101,10 +101,148 @@ def cpu_baseline(n_sample=128, steps=2, seed=3):
     }
 
 
+def bench_adjoint(n=128, steps=20, reps=3):
+    """Differentiable run (128^3, P ~ k^-1.5, 20 steps, checkpoints every 4): loss alone vs
+    loss + gradient through the hand-written adjoint, on the same GPU."""
+    import numpy as np
+    import torch
+    import warnings
+
+    import icgen
+    import paper_2410_20501_amd as pm
+    from paper_2410_20501_amd import autodiff
+    warnings.simplefilter("ignore", pm.PMWarning)
+    a_list = [0.1 + 0.01 * i for i in range(steps + 1)]
+    psi = icgen.displacement_field(n, -1.5, 0.3, 51).reshape(-1, 3).astype(np.float32)
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()  # noqa: E731
+    psi_d, q_d, w_d = dev(psi), dev(icgen.lattice_points(n)), dev(icgen.weight_grid(n, 52))
+    run = autodiff.Run(n, n ** 3, a_list, checkpoint_every=4, poskind="celloff")
+    autodiff.loss_and_gradient(psi_d, q_d, w_d, run)  # warm-up
+    tf, tb = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        autodiff.loss_only(psi_d, q_d, w_d, run)
+        torch.cuda.synchronize()
+        tf.append(time.perf_counter() - t)
+        t = time.perf_counter()
+        autodiff.loss_and_gradient(psi_d, q_d, w_d, run)
+        torch.cuda.synchronize()
+        tb.append(time.perf_counter() - t)
+    run.close()
+    f, b = min(tf), min(tb)
+    return {
+        "workload": f"{n}^3 particles, {steps} KDK steps a=0.1->0.3, TSC, multigrid tol 1e-6, "
+                    f"cell-offset positions, checkpoints every 4 steps, loss sum w delta^2",
+        "forward_ms": 1e3 * f, "forward_and_gradient_ms": 1e3 * b,
+        "gradient_over_forward": b / f,
+        "forward_particle_steps_per_s": n ** 3 * steps / f,
+        "gradient_particle_steps_per_s": n ** 3 * steps / b,
+        "transposed_force_evaluations": steps + 1,
+    }
+
+
+def bench_batched(nboxes=96, steps=20, master_seed=2024):
+    """Ensemble of 96 boxes (grids uniform in {32,48,64,96,128}^3, np = cells, n_s in
+    [-2.5,-1]), 20 steps: one captured batched step replayed vs a loop of per-box pm_kdk."""
+    import numpy as np
+    import torch
+    import warnings
+
+    import icgen
+    import paper_2410_20501_amd as pm
+    warnings.simplefilter("ignore", pm.PMWarning)
+    a_list = [0.1 + 0.01 * i for i in range(steps + 1)]
+    draws = icgen.ensemble_draw(master_seed, nboxes)
+    t = time.time()
+    pos_l, vel_l = [], []
+    for n, ns, seed in draws:
+        ps = icgen.zeldovich_particles(n, ns, 0.25, a_list[0], seed=seed, precision="f32")
+        pos_l.append(ps.pos)
+        vel_l.append(ps.vel)
+    sizes = [d[0] for d in draws]
+    _log(f"batched inputs: {nboxes} boxes generated in {time.time() - t:.1f}s")
+    pos0 = torch.from_numpy(np.concatenate(pos_l)).cuda()
+    vel0 = torch.from_numpy(np.concatenate(vel_l)).cuda()
+    del pos_l, vel_l
+    B = pm.Batch(sizes, [n ** 3 for n in sizes])
+    npart = B.np_total
+    # plain loop: one context per box, pm_kdk per box and step (tolerance-driven multigrid)
+    first = pm.default_step_params(tol=1e-6, max_cycles=40)
+    warm = pm.default_step_params(tol=1e-6, max_cycles=40, guess="warm_rescaled")
+    ctxs = {n: pm.Context(n, n ** 3) for n in sorted(set(sizes))}
+    t_loop = 0.0
+    for b, n in enumerate(sizes):
+        sl = slice(B.p_off[b], B.p_off[b + 1])
+        pb, vb = pos0[sl].clone(), vel0[sl].clone()
+        phi = torch.zeros((n, n, n), device="cuda")
+        acc = torch.empty_like(pb)
+        pm.pm_accel(ctxs[n], pb, a_list[0], phi, acc, params=first)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for i in range(steps):
+            pm.pm_kdk(ctxs[n], pb, vb, a_list[i], a_list[i + 1], phi, acc, params=warm)
+        torch.cuda.synchronize()
+        t_loop += time.perf_counter() - t
+    for c in ctxs.values():
+        c.close()
+    # batched: tune, first solve, capture one step, replay
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        p, v = pos0.clone(), vel0.clone()
+        acc = torch.zeros_like(p)
+        phi = torch.zeros(B.ncell_total, device="cuda")
+        pw = pm.default_step_params(fixed_cycles=4, guess="warm_rescaled")
+        tune = pm.pm_tune(B, p, phi, pw)
+        phi.zero_()
+        pm.pm_batch_accel(B, p, acc, phi, a_list[0], pm.default_step_params(fixed_cycles=8))
+        state = (p.clone(), v.clone(), acc.clone(), phi.clone())
+        s.synchronize()
+        t = time.perf_counter()
+        pm.pm_batch_kdk(B, p, v, acc, phi, a_list, pw)
+        s.synchronize()
+        t_eager = time.perf_counter() - t
+        for dst, src in zip((p, v, acc, phi), state):
+            dst.copy_(src)
+        pm.pm_graph_capture_step(B, p, v, acc, phi, pw)
+        s.synchronize()
+        t = time.perf_counter()
+        pm.pm_batch_kdk(B, p, v, acc, phi, a_list, pw, use_graph=True)
+        s.synchronize()
+        t_graph = time.perf_counter() - t
+    B.close()
+    best = min(t_eager, t_graph)
+    return {
+        "workload": f"{nboxes} boxes, grids {{32,48,64,96,128}}^3 (seed {master_seed}), "
+                    f"{npart} particles total, {steps} KDK steps a=0.1->0.3, TSC, multigrid "
+                    f"(batched: 4 warm-started V-cycles per step; plain: tol 1e-6)",
+        "particles": npart,
+        "batched_graph_s": t_graph, "batched_eager_s": t_eager, "per_box_loop_s": t_loop,
+        "batched_particle_steps_per_s": npart * steps / best,
+        "per_box_loop_particle_steps_per_s": npart * steps / t_loop,
+        "speedup_vs_per_box_loop": t_loop / best,
+        "tuned_rows": tune,
+    }
+
+
+def stage_bytes(npart, ncell, cycles):
+    """Algorithmic HBM bytes of each stage of one step at cell-offset positions (the
+    minimum each stage's kernels must move; multigrid: the level-0 passes of the fused
+    V-cycle, two smoothing passes of 12 B/cell, residual-restriction 8 B/cell and
+    prolongation 8 B/cell, times 8/7 for the coarser levels)."""
+    return {
+        "ms_drift": 68.0 * npart,
+        "ms_deposit": 16.0 * npart + 4.0 * ncell,
+        "ms_solve": cycles * 40.0 * ncell * 8.0 / 7.0,
+        "ms_gradient": 16.0 * ncell,
+        "ms_interp": 52.0 * npart + 12.0 * ncell,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=48)
+    ap.add_argument("--steps", type=int, default=47)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--order", default="sorted", choices=["atomic", "sorted"])
@@ -118,6 +256,10 @@ def main():
                     help="record per-stage times of every timed step (adds events)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 512 MiB device copy (HBM counter calibration)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the adjoint and batched-ensemble measurements")
+    ap.add_argument("--only", choices=["adjoint", "batched"], default=None,
+                    help="run only one of the extra measurements and print its JSON object")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -128,6 +270,11 @@ def main():
     import torch
 
     import paper_2410_20501_amd as pm
+
+    if args.only:
+        res = bench_adjoint() if args.only == "adjoint" else bench_batched()
+        print(json.dumps({args.only: res}), flush=True)
+        return
 
     if args.copy_calibration:
         src = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
@@ -143,6 +290,7 @@ def main():
     total_steps = 50
     if args.warmup + args.steps > total_steps:
         raise SystemExit(f"warmup + steps must be <= {total_steps} (the run has 50 steps)")
+    # the step after the timed ones (when warmup + steps < 50) is re-run with per-stage events
     a_list = [0.02 + (1.0 - 0.02) * i / total_steps for i in range(total_steps + 1)]
 
     off, cell, vel = make_inputs(n)
@@ -226,9 +374,16 @@ def main():
     stt = pm.pm_kdk(ctx, off_d, vel_d, a_list[step], a_list[min(step + 1, total_steps)], phi, acc,
                     cell=cell_d, params=params) if step < total_steps else None
     stages = None
+    stage_gbs = None
     if stt is not None:
         stages = {k: round(getattr(stt, k), 4) for k in
                   ("ms_drift", "ms_deposit", "ms_solve", "ms_gradient", "ms_interp")}
+        sb = stage_bytes(npart, n ** 3, stt.mg.cycles)
+        stage_gbs = {k.replace("ms_", ""): {
+            "gbs": round(sb[k] / (stages[k] * 1e-3) / 1e9, 1),
+            "frac": round(sb[k] / (stages[k] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            for k in sb if stages[k] > 0}
+        stage_gbs["solve"]["vcycles"] = stt.mg.cycles
 
     out = {
         "metric": "PM particle-steps/s at 512^3",
@@ -250,13 +405,21 @@ def main():
                    "particles": npart, "grid": n, "deposit": args.order,
                    "vcycles_per_step": cycles},
         "stages_ms_last_step": stages,
+        "stage_gbs_last_step": stage_gbs,
         "roofline": roofline,
     }
+    ctx.close()
+    del off_d, cell_d, vel_d, phi, acc
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        _log("adjoint (128^3, 20 steps) ...")
+        out["adjoint"] = bench_adjoint()
+        _log("batched ensemble (96 boxes, 20 steps) ...")
+        out["batched"] = bench_batched()
     if not args.no_cpu_baseline:
         _log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":
