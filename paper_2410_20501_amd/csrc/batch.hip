@@ -14,6 +14,8 @@
 #include <cstring>
 #include <vector>
 
+#include "coarse_solve.h"
+#include "deposit_chunk.h"
 #include "internal.h"
 
 namespace {
@@ -27,6 +29,8 @@ constexpr int kGraphSteps = 1024;  // step-table entries reserved when a step is
 struct BoxDev {
   int n;                          // cells per side of the finest level
   int nlev;                       // multigrid levels; level nlev-1 is solved in LDS
+  int lattice;                    // deposit chunks are lattice blocks (np = n^3, 16 | n)
+  int pad;
   int64_t p0, np;                 // rows of the packed particle arrays
   int64_t c0;                     // offset of the box in the level-0 arenas (rho, phi, g)
   int64_t lo[PM_MAX_LEVELS];      // offset of level l >= 1 in the level arenas (u, f)
@@ -112,37 +116,53 @@ __global__ __launch_bounds__(kThreads) void kb_kick_drift(float *__restrict__ po
   }
 }
 
-// rho_box[c] += w W(u_p - c - 1/2), w = n^3 / np of the box; one thread per particle
-template <int MAS>
-__global__ __launch_bounds__(kThreads) void kb_deposit(const float *__restrict__ pos,
-                                                       const int2 *__restrict__ items, int nitems,
-                                                       const BoxDev *__restrict__ boxes,
-                                                       float *__restrict__ rho) {
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const int2 item = items[it];
-    const BoxDev bx = boxes[item.x];
-    const int64_t lp = (int64_t)item.y * kThreads + threadIdx.x;
-    if (lp >= bx.np) continue;
-    const int64_t p = bx.p0 + lp;
-    const int n = bx.n;
-    const float fn = (float)n;
-    const float mass = (float)((double)n * n * n / (double)bx.np);
-    float w[3][MAS];
-    int f[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) f[d] = wrap_any(axis_box<MAS>(pos[3 * p + d], fn, w[d]), n);
-    float *r = rho + bx.c0;
-#pragma unroll
-    for (int a = 0; a < MAS; ++a) {
-      const size_t ia = (size_t)wrap_index(f[0] + a, n) * n;
-#pragma unroll
-      for (int b = 0; b < MAS; ++b) {
-        const size_t row = (ia + wrap_index(f[1] + b, n)) * n;
-        const float wab = mass * w[0][a] * w[1][b];
-#pragma unroll
-        for (int c = 0; c < MAS; ++c) unsafeAtomicAdd(&r[row + wrap_index(f[2] + c, n)], wab * w[2][c]);
-      }
+// Slots of one deposit chunk of a box: an 8 x 16 x 16 block of its particle lattice
+// (particles that started on the lattice stay spatially coherent for many steps), or
+// 2048 consecutive rows.
+struct BatchIndex {
+  int64_t p0, end;
+  int m, i0, j0, k0, lattice;
+  __device__ int64_t ref() const {
+    return lattice ? p0 + ((int64_t)i0 * m + j0) * m + k0 : p0;
+  }
+  __device__ int64_t operator()(int slot) const {
+    if (lattice) {
+      const int i = i0 + (slot >> 8), j = j0 + ((slot >> 4) & 15), k = k0 + (slot & 15);
+      return p0 + ((int64_t)i * m + j) * m + k;
     }
+    const int64_t p = p0 + slot;
+    return p < end ? p : -1;
+  }
+};
+
+// rho_box += w W(u_p - c - 1/2), w = n^3 / np of the box: the chunked LDS deposit
+// (deposit_chunk.h) for every (box, chunk) item
+template <int MAS>
+__global__ __launch_bounds__(pm_chunk::kGThreads) void kb_deposit(const float *__restrict__ pos,
+                                                                  const int2 *__restrict__ items,
+                                                                  int nitems,
+                                                                  const BoxDev *__restrict__ boxes,
+                                                                  float *__restrict__ rho) {
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    __syncthreads();  // the previous item's LDS tables are no longer read
+    const int2 item = items[it];
+    const BoxDev &bx = boxes[item.x];
+    BatchIndex idx;
+    idx.m = bx.n;
+    idx.lattice = bx.lattice;
+    idx.p0 = bx.p0;
+    idx.end = bx.p0 + bx.np;
+    if (bx.lattice) {
+      const int cj = bx.n >> 4;  // chunks along j and k
+      idx.i0 = 8 * (item.y / (cj * cj));
+      idx.j0 = 16 * ((item.y / cj) % cj);
+      idx.k0 = 16 * (item.y % cj);
+    } else {
+      idx.i0 = idx.j0 = idx.k0 = 0;
+      idx.p0 = bx.p0 + (int64_t)item.y * pm_chunk::kGChunk;
+    }
+    const float mass = (float)((double)bx.n * bx.n * bx.n / (double)bx.np);
+    pm_chunk::deposit_chunk<MAS, PM_POS_BOX>(pos, nullptr, idx, bx.n, mass, rho + bx.c0);
   }
 }
 
@@ -159,7 +179,7 @@ __global__ __launch_bounds__(kThreads) void kb_interp(const float *__restrict__ 
   const float half = vel ? steps[*ctr].half : 0.0f;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int2 item = items[it];
-    const BoxDev bx = boxes[item.x];
+    const BoxDev &bx = boxes[item.x];
     const int64_t lp = (int64_t)item.y * kThreads + threadIdx.x;
     if (lp >= bx.np) continue;
     const int64_t p = bx.p0 + lp;
@@ -224,7 +244,7 @@ __global__ __launch_bounds__(kThreads) void kb_sum_partial(const float *__restri
   __shared__ double lds[kThreads / 64];
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int2 item = items[it];
-    const BoxDev bx = boxes[item.x];
+    const BoxDev &bx = boxes[item.x];
     const int64_t count = (int64_t)bx.n * bx.n * bx.n;
     const int64_t c = (int64_t)item.y * kThreads + threadIdx.x;
     const double v = c < count ? (double)x[bx.c0 + c] : 0.0;
@@ -256,7 +276,7 @@ __global__ __launch_bounds__(kThreads) void kb_subtract_mean(float *__restrict__
                                                              const float *__restrict__ mean) {
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int2 item = items[it];
-    const BoxDev bx = boxes[item.x];
+    const BoxDev &bx = boxes[item.x];
     const int64_t c = (int64_t)item.y * kThreads + threadIdx.x;
     if (c < (int64_t)bx.n * bx.n * bx.n) x[bx.c0 + c] -= mean[item.x];
   }
@@ -306,7 +326,7 @@ __global__ __launch_bounds__(kThreads) void kb_jacobi0(Arenas A, const int2 *__r
   const float coef = A.steps[*A.ctr].coef;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int2 item = items[it];
-    const BoxDev bx = boxes[item.x];
+    const BoxDev &bx = boxes[item.x];
     const LevelView v = level_view(bx, 0, A.phi, A.rho, A.lu, A.lf, coef, A.rmean, item.x);
     const int64_t c = (int64_t)item.y * kThreads + threadIdx.x;
     if (c >= (int64_t)v.n * v.n * v.n) continue;
@@ -327,17 +347,17 @@ __global__ __launch_bounds__(kThreads) void kb_rbgs_half(Arenas A, const int2 *_
   const float coef = A.steps[*A.ctr].coef;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int2 item = items[it];
-    const BoxDev bx = boxes[item.x];
+    const BoxDev &bx = boxes[item.x];
     const LevelView v = level_view(bx, l, A.phi, A.rho, A.lu, A.lf, coef, A.rmean, item.x);
     const int n = v.n, half = n >> 1;
     const float h = 1.0f / (float)n, h2 = h * h;
     const size_t nn = (size_t)n * n;
-    const int64_t tid = (int64_t)item.y * kThreads + threadIdx.x;
-    const int k2 = (int)(tid % half);
-    const int64_t rg = tid / half;  // row group: CPT rows j of plane i
-    const int groups = n / CPT;
-    if (rg >= (int64_t)n * groups) continue;
-    const int i = (int)(rg / groups), j0 = (int)(rg % groups) * CPT;
+    const unsigned tid = (unsigned)item.y * kThreads + threadIdx.x;
+    const unsigned rg = tid / (unsigned)half;  // row group: CPT rows j of plane i
+    const int k2 = (int)(tid - rg * (unsigned)half);
+    const unsigned groups = (unsigned)(n / CPT);
+    if (rg >= (unsigned)n * groups) continue;
+    const int i = (int)(rg / groups), j0 = (int)(rg - (unsigned)i * groups) * CPT;
     const size_t ci = (size_t)i * nn;
     const size_t cip = (size_t)wrap_index(i + 1, n) * nn, cim = (size_t)wrap_index(i - 1, n) * nn;
 #pragma unroll
@@ -373,42 +393,78 @@ __device__ __forceinline__ float residual_at(const LevelView &v, int i, int j, i
   return v.scale * (v.f[c] - v.mean) - lap * inv_h2;
 }
 
-// Restriction of the level-l residual to level l+1 (full weighting (1,3,3,1)/8 per
-// axis, or the 8-child average), fused with the coarse starting guess -H^2 f_H / 6.
-template <int KIND>
-__global__ __launch_bounds__(kThreads) void kb_restrict(Arenas A, const int2 *__restrict__ items,
+__device__ __forceinline__ void decode3(unsigned t, unsigned n, int &i, int &j, int &k) {
+  const unsigned r = t / n;
+  k = (int)(t - r * n);
+  i = (int)(r / n);
+  j = (int)(r - (unsigned)i * n);
+}
+
+// r = f - L u on level l of every box that has a level l+1, into a scratch arena (the
+// force-grid arena, idle during the solve) at the box's level-0 offset.
+__global__ __launch_bounds__(kThreads) void kb_residual(Arenas A, const int2 *__restrict__ items,
                                                         int nitems,
-                                                        const BoxDev *__restrict__ boxes, int l) {
+                                                        const BoxDev *__restrict__ boxes, int l,
+                                                        float *__restrict__ rbuf) {
   const float coef = A.steps[*A.ctr].coef;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int2 item = items[it];
-    const BoxDev bx = boxes[item.x];
+    const BoxDev &bx = boxes[item.x];
     const LevelView v = level_view(bx, l, A.phi, A.rho, A.lu, A.lf, coef, A.rmean, item.x);
-    const int n = v.n, nc = n >> 1;
-    const int64_t t = (int64_t)item.y * kThreads + threadIdx.x;
-    if (t >= (int64_t)nc * nc * nc) continue;
-    const int K = (int)(t % nc), J = (int)((t / nc) % nc), I = (int)(t / ((int64_t)nc * nc));
-    const float inv_h2 = (float)n * (float)n;
+    const unsigned n = (unsigned)v.n;
+    const unsigned t = (unsigned)item.y * kThreads + threadIdx.x;
+    if (t >= n * n * n) continue;
+    int i, j, k;
+    decode3(t, n, i, j, k);
+    rbuf[bx.c0 + t] = residual_at(v, i, j, k, (float)n * (float)n);
+  }
+}
+
+// Restriction of the level-l residual to level l+1 (full weighting (1,3,3,1)/8 per
+// axis, or the 8-child average), with the coarse starting guess -H^2 f_H / 6.
+template <int KIND>
+__global__ __launch_bounds__(kThreads) void kb_restrict(Arenas A, const int2 *__restrict__ items,
+                                                        int nitems,
+                                                        const BoxDev *__restrict__ boxes, int l,
+                                                        const float *__restrict__ rbuf) {
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int2 item = items[it];
+    const BoxDev &bx = boxes[item.x];
+    const int n = bx.n >> l;
+    const unsigned nc = (unsigned)n >> 1;
+    const unsigned t = (unsigned)item.y * kThreads + threadIdx.x;
+    if (t >= nc * nc * nc) continue;
+    int I, J, K;
+    decode3(t, nc, I, J, K);
+    const float *r = rbuf + bx.c0;
+    const size_t nn = (size_t)n * n;
     float acc = 0.0f;
     if constexpr (KIND == PM_RESTRICT_FW) {
       const float w[4] = {1.0f, 3.0f, 3.0f, 1.0f};
-      for (int a = 0; a < 4; ++a) {
-        const int i = wrap_index(2 * I - 1 + a, n);
-        for (int b = 0; b < 4; ++b) {
-          const int j = wrap_index(2 * J - 1 + b, n);
-          const float wab = w[a] * w[b];
+      int kk[4];
 #pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            const int k = wrap_index(2 * K - 1 + c, n);
-            acc = fmaf(wab * w[c], residual_at(v, i, j, k, inv_h2), acc);
-          }
+      for (int c = 0; c < 4; ++c) kk[c] = wrap_index(2 * K - 1 + c, n);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const size_t ri = (size_t)wrap_index(2 * I - 1 + a, n) * nn;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const size_t rj = ri + (size_t)wrap_index(2 * J - 1 + b, n) * n;
+          const float wab = w[a] * w[b];
+          const float row = fmaf(w[0], r[rj + kk[0]], fmaf(w[1], r[rj + kk[1]],
+                                 fmaf(w[2], r[rj + kk[2]], w[3] * r[rj + kk[3]])));
+          acc = fmaf(wab, row, acc);
         }
       }
       acc *= (1.0f / 512.0f);
     } else {
+#pragma unroll
       for (int a = 0; a < 2; ++a)
+#pragma unroll
         for (int b = 0; b < 2; ++b)
-          for (int c = 0; c < 2; ++c) acc += residual_at(v, 2 * I + a, 2 * J + b, 2 * K + c, inv_h2);
+#pragma unroll
+          for (int c = 0; c < 2; ++c)
+            acc += r[(size_t)(2 * I + a) * nn + (size_t)(2 * J + b) * n + (2 * K + c)];
       acc *= 0.125f;
     }
     const float H = 1.0f / (float)nc;
@@ -424,13 +480,14 @@ __global__ __launch_bounds__(kThreads) void kb_prolong_add(Arenas A, const int2 
                                                            int l) {
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int2 item = items[it];
-    const BoxDev bx = boxes[item.x];
+    const BoxDev &bx = boxes[item.x];
     const int n = bx.n >> l, nc = n >> 1;
-    const int64_t t = (int64_t)item.y * kThreads + threadIdx.x;
-    if (t >= (int64_t)n * n * n) continue;
+    const unsigned t = (unsigned)item.y * kThreads + threadIdx.x;
+    if (t >= (unsigned)n * n * n) continue;
     float *u = l == 0 ? A.phi + bx.c0 : A.lu + bx.lo[l];
     const float *vc = A.lu + bx.lo[l + 1];
-    const int k = (int)(t % n), j = (int)((t / n) % n), i = (int)(t / ((int64_t)n * n));
+    int i, j, k;
+    decode3(t, (unsigned)n, i, j, k);
     const int ia = i >> 1, ja = j >> 1, ka = k >> 1;
     const int ib = wrap_index(ia + ((i & 1) ? 1 : -1), nc);
     const int jb = wrap_index(ja + ((j & 1) ? 1 : -1), nc);
@@ -446,75 +503,18 @@ __global__ __launch_bounds__(kThreads) void kb_prolong_add(Arenas A, const int2 
   }
 }
 
-// Coarsest level of every box, one workgroup per box: red-black sweeps in LDS until
-// the residual has dropped by 1e-3 (checked every 4 sweeps), stagnates, or 500 sweeps;
-// the means of the right-hand side and of the solution are removed.
+// Coarsest level of every box, one workgroup per box, in LDS (coarse_solve.h).
 __global__ __launch_bounds__(kCoarseThreads) void kb_coarse_solve(Arenas A,
                                                                   const BoxDev *__restrict__ boxes) {
   __shared__ float su[kCoarseMax];
   __shared__ float sf[kCoarseMax];
   __shared__ double red[kCoarseThreads / 64];
   const int b = blockIdx.x;
-  const BoxDev bx = boxes[b];
-  const int l = bx.nlev - 1;
+  const BoxDev &bx = boxes[b];
   const float coef = A.steps[*A.ctr].coef;
-  const LevelView v = level_view(bx, l, A.phi, A.rho, A.lu, A.lf, coef, A.rmean, b);
-  const int n = v.n;
-  const int count = n * n * n;
-  const float h = 1.0f / (float)n, h2 = h * h, inv_h2 = 1.0f / h2;
-  double fs = 0.0;
-  for (int c = threadIdx.x; c < count; c += kCoarseThreads) {
-    su[c] = v.u[c];
-    const float fv = v.scale * (v.f[c] - v.mean);
-    sf[c] = fv;
-    fs += fv;
-  }
-  const float fmean = (float)(block_sum<kCoarseThreads>(fs, red) / count);
-  for (int c = threadIdx.x; c < count; c += kCoarseThreads) sf[c] -= fmean;
-  __syncthreads();
-  auto resid_norm = [&]() {
-    double s = 0.0;
-    for (int c = threadIdx.x; c < count; c += kCoarseThreads) {
-      const int k = c % n, j = (c / n) % n, i = c / (n * n);
-      const float uc = su[c];
-      const float lap = (su[(wrap_index(i + 1, n) * n + j) * n + k] - uc) +
-                        (su[(wrap_index(i - 1, n) * n + j) * n + k] - uc) +
-                        (su[(i * n + wrap_index(j + 1, n)) * n + k] - uc) +
-                        (su[(i * n + wrap_index(j - 1, n)) * n + k] - uc) +
-                        (su[(i * n + j) * n + wrap_index(k + 1, n)] - uc) +
-                        (su[(i * n + j) * n + wrap_index(k - 1, n)] - uc);
-      const double r = sf[c] - lap * inv_h2;
-      s += r * r;
-    }
-    return sqrt(block_sum<kCoarseThreads>(s, red));
-  };
-  const double r0 = resid_norm();
-  double prev = r0;
-  for (int sweep = 0; sweep < 500; ++sweep) {
-    for (int colour = 0; colour < 2; ++colour) {
-      for (int c = threadIdx.x; c < count; c += kCoarseThreads) {
-        const int k = c % n, j = (c / n) % n, i = c / (n * n);
-        if (((i + j + k) & 1) != colour) continue;
-        const float nb = su[(wrap_index(i + 1, n) * n + j) * n + k] +
-                         su[(wrap_index(i - 1, n) * n + j) * n + k] +
-                         su[(i * n + wrap_index(j + 1, n)) * n + k] +
-                         su[(i * n + wrap_index(j - 1, n)) * n + k] +
-                         su[(i * n + j) * n + wrap_index(k + 1, n)] +
-                         su[(i * n + j) * n + wrap_index(k - 1, n)];
-        su[c] = (nb - h2 * sf[c]) * (1.0f / 6.0f);
-      }
-      __syncthreads();
-    }
-    if ((sweep & 3) == 3) {
-      const double r = resid_norm();
-      if (r <= 1e-3 * r0 || r > 0.98 * prev) break;
-      prev = r;
-    }
-  }
-  double us = 0.0;
-  for (int c = threadIdx.x; c < count; c += kCoarseThreads) us += su[c];
-  const float umean = (float)(block_sum<kCoarseThreads>(us, red) / count);
-  for (int c = threadIdx.x; c < count; c += kCoarseThreads) v.u[c] = su[c] - umean;
+  const LevelView v = level_view(bx, bx.nlev - 1, A.phi, A.rho, A.lu, A.lf, coef, A.rmean, b);
+  const float h = 1.0f / (float)v.n;
+  pm_coarse::solve_any(v.u, v.f, v.scale, v.mean, v.n, h * h, 1e-3f, 500, su, sf, red);
 }
 
 // Per-item partial sums of |f - L u|^2 and |f|^2 on level 0 (convergence records).
@@ -527,13 +527,14 @@ __global__ __launch_bounds__(kThreads) void kb_residual_partial(Arenas A,
   const float coef = A.steps[*A.ctr].coef;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int2 item = items[it];
-    const BoxDev bx = boxes[item.x];
+    const BoxDev &bx = boxes[item.x];
     const LevelView v = level_view(bx, 0, A.phi, A.rho, A.lu, A.lf, coef, A.rmean, item.x);
     const int n = v.n;
-    const int64_t t = (int64_t)item.y * kThreads + threadIdx.x;
+    const unsigned t = (unsigned)item.y * kThreads + threadIdx.x;
     double r2 = 0.0, f2 = 0.0;
-    if (t < (int64_t)n * n * n) {
-      const int k = (int)(t % n), j = (int)((t / n) % n), i = (int)(t / ((int64_t)n * n));
+    if (t < (unsigned)n * n * n) {
+      int i, j, k;
+      decode3(t, (unsigned)n, i, j, k);
       const double r = residual_at(v, i, j, k, (float)n * (float)n);
       const double fv = v.scale * (v.f[t] - v.mean);
       r2 = r * r;
@@ -574,18 +575,18 @@ __global__ __launch_bounds__(kThreads) void kb_gradient(const float *__restrict_
   const float c1 = 2.0f / 3.0f, c2 = -1.0f / 12.0f;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int2 item = items[it];
-    const BoxDev bx = boxes[item.x];
+    const BoxDev &bx = boxes[item.x];
     const int n = bx.n;
     const float inv_h = (float)n;
     const float *u = phi + bx.c0;
     float *gb = g + 3 * bx.c0;
     const size_t nn = (size_t)n * n;
-    const int64_t tid = (int64_t)item.y * kThreads + threadIdx.x;
-    const int k = (int)(tid % n);
-    const int64_t rg = tid / n;
-    const int groups = n / CPT;
-    if (rg >= (int64_t)n * groups) continue;
-    const int i = (int)(rg / groups), j0 = (int)(rg % groups) * CPT;
+    const unsigned tid = (unsigned)item.y * kThreads + threadIdx.x;
+    const unsigned rg = tid / (unsigned)n;
+    const int k = (int)(tid - rg * (unsigned)n);
+    const unsigned groups = (unsigned)(n / CPT);
+    if (rg >= (unsigned)n * groups) continue;
+    const int i = (int)(rg / groups), j0 = (int)(rg - (unsigned)i * groups) * CPT;
     const size_t ci = (size_t)i * nn;
     const size_t cp1 = (size_t)wrap_index(i + 1, n) * nn, cm1 = (size_t)wrap_index(i - 1, n) * nn;
     const size_t cp2 = (size_t)wrap_index(i + 2, n) * nn, cm2 = (size_t)wrap_index(i - 2, n) * nn;
@@ -644,6 +645,7 @@ struct pm_batch {
   std::vector<int2> items_h;
   int2 *items = nullptr;
   List part;                        // particle blocks
+  List chunks;                      // deposit chunks (lattice blocks or runs of 2048 rows)
   List cells[PM_MAX_LEVELS];        // cell blocks of level l (boxes with nlev > l)
   List halfc[PM_MAX_LEVELS][3];     // red-black half-sweep blocks of level l, per tile shape
   List finer[PM_MAX_LEVELS];        // cell blocks of level l for boxes with a level l+1
@@ -703,11 +705,11 @@ int enqueue_accel(pm_batch *B, const float *pos, float *acc, float *vel, float *
   // deposit
   kb_fill<<<flat_grid(B->ncell_total), kThreads, 0, s>>>(B->rho, B->ncell_total, 0.0f);
   if (p->mas == PM_TSC)
-    kb_deposit<3><<<persist_grid(B->part.count), kThreads, 0, s>>>(
-        pos, B->items + B->part.off, B->part.count, B->boxes, B->rho);
+    kb_deposit<3><<<persist_grid(B->chunks.count), pm_chunk::kGThreads, 0, s>>>(
+        pos, B->items + B->chunks.off, B->chunks.count, B->boxes, B->rho);
   else
-    kb_deposit<2><<<persist_grid(B->part.count), kThreads, 0, s>>>(
-        pos, B->items + B->part.off, B->part.count, B->boxes, B->rho);
+    kb_deposit<2><<<persist_grid(B->chunks.count), pm_chunk::kGThreads, 0, s>>>(
+        pos, B->items + B->chunks.off, B->chunks.count, B->boxes, B->rho);
   const pm_batch::List &c0 = B->cells[0];
   kb_sum_partial<<<persist_grid(c0.count), kThreads, 0, s>>>(B->rho, B->items + c0.off, c0.count,
                                                              B->boxes, B->partial);
@@ -740,13 +742,16 @@ int enqueue_accel(pm_batch *B, const float *pos, float *acc, float *vel, float *
     for (int l = 0; l + 1 < B->maxlev; ++l) {
       if (B->finer[l].count == 0) break;
       sweeps(l, p->mg.pre, 0);
+      const pm_batch::List &F = B->finer[l];
+      kb_residual<<<persist_grid(F.count), kThreads, 0, s>>>(A, B->items + F.off, F.count,
+                                                             B->boxes, l, B->g);
       const pm_batch::List &R = B->coarser[l];
       if (p->mg.restrict_kind == PM_RESTRICT_AVG)
         kb_restrict<PM_RESTRICT_AVG><<<persist_grid(R.count), kThreads, 0, s>>>(
-            A, B->items + R.off, R.count, B->boxes, l);
+            A, B->items + R.off, R.count, B->boxes, l, B->g);
       else
         kb_restrict<PM_RESTRICT_FW><<<persist_grid(R.count), kThreads, 0, s>>>(
-            A, B->items + R.off, R.count, B->boxes, l);
+            A, B->items + R.off, R.count, B->boxes, l, B->g);
     }
     kb_coarse_solve<<<B->nboxes, kCoarseThreads, 0, s>>>(A, B->boxes);
     for (int l = B->maxlev - 2; l >= 0; --l) {
@@ -910,6 +915,15 @@ int pm_batch_create(pm_batch **out, int nboxes, const int *n, const int64_t *np,
   // work lists
   B->part.off = (int64_t)B->items_h.size();
   for (int b = 0; b < nboxes; ++b) append_blocks(B, B->part, b, np[b]);
+  B->chunks.off = (int64_t)B->items_h.size();
+  for (int b = 0; b < nboxes; ++b) {
+    BoxDev &d = B->boxes_h[b];
+    d.lattice = (np[b] == (int64_t)n[b] * n[b] * n[b] && n[b] % 16 == 0) ? 1 : 0;
+    const int64_t nc = d.lattice ? (int64_t)(n[b] / 8) * (n[b] / 16) * (n[b] / 16)
+                                 : (np[b] + pm_chunk::kGChunk - 1) / pm_chunk::kGChunk;
+    for (int64_t k = 0; k < nc; ++k) B->items_h.push_back(int2{b, (int)k});
+    B->chunks.count += (int)nc;
+  }
   std::vector<int> range(nboxes + 1, 0);
   for (int l = 0; l < B->maxlev; ++l) {
     B->cells[l].off = (int64_t)B->items_h.size();
@@ -1118,8 +1132,8 @@ int pm_tune(pm_batch *B, float *pos, float *phi, const pm_step_params *params, i
   const Arenas A{phi, B->rho, B->lu, B->lf, B->rmean, B->steps, B->ctr};
   // a valid source: deposit the current particles and their means
   kb_fill<<<flat_grid(B->ncell_total), kThreads, 0, s>>>(B->rho, B->ncell_total, 0.0f);
-  kb_deposit<3><<<persist_grid(B->part.count), kThreads, 0, s>>>(
-      pos, B->items + B->part.off, B->part.count, B->boxes, B->rho);
+  kb_deposit<3><<<persist_grid(B->chunks.count), pm_chunk::kGThreads, 0, s>>>(
+      pos, B->items + B->chunks.off, B->chunks.count, B->boxes, B->rho);
   const pm_batch::List &c0 = B->cells[0];
   kb_sum_partial<<<persist_grid(c0.count), kThreads, 0, s>>>(B->rho, B->items + c0.off, c0.count,
                                                              B->boxes, B->partial);

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "coarse_solve.h"
 #include "internal.h"
 
 namespace {
@@ -55,12 +56,13 @@ __global__ __launch_bounds__(kThreads) void k_rbgs_half(float *__restrict__ u,
                                                         const float *__restrict__ f, float scale,
                                                         const float *__restrict__ mean, int n,
                                                         float h2, float omega, int colour) {
-  const int half = n >> 1;
-  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (t >= (int64_t)n * n * half) return;
-  const int k2 = (int)(t % half);
-  const int64_t r = t / half;
-  const int j = (int)(r % n), i = (int)(r / n);
+  // per-level index math in 32 bits: n^3 <= 2^30
+  const unsigned half = (unsigned)n >> 1;
+  const unsigned t = blockIdx.x * kThreads + threadIdx.x;
+  if (t >= (unsigned)n * n * half) return;
+  const unsigned r = t / half;
+  const int k2 = (int)(t - r * half);
+  const int i = (int)(r / (unsigned)n), j = (int)(r - (unsigned)i * n);
   const int k = 2 * k2 + ((i + j + colour) & 1);
   const size_t c = ((size_t)i * n + j) * n + k;
   const float fv = scale * (f[c] - src_mean(mean));
@@ -92,10 +94,11 @@ template <int KIND>
 __global__ __launch_bounds__(kThreads) void k_residual_restrict(
     const float *__restrict__ u, const float *__restrict__ f, float scale,
     const float *__restrict__ mean, int n, float inv_h2, float *__restrict__ fc) {
-  const int nc = n >> 1;
-  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (t >= (int64_t)nc * nc * nc) return;
-  const int K = (int)(t % nc), J = (int)((t / nc) % nc), I = (int)(t / ((int64_t)nc * nc));
+  const unsigned nc = (unsigned)n >> 1;
+  const unsigned t = blockIdx.x * kThreads + threadIdx.x;
+  if (t >= nc * nc * nc) return;
+  const unsigned r = t / nc;
+  const int K = (int)(t - r * nc), I = (int)(r / nc), J = (int)(r - (unsigned)I * nc);
   const float m = src_mean(mean);
   float acc = 0.0f;
   if constexpr (KIND == PM_RESTRICT_FW) {
@@ -126,9 +129,11 @@ __global__ __launch_bounds__(kThreads) void k_residual_restrict(
 // the next one (fine cell 2J has neighbours J, J-1; fine 2J+1 has J, J+1).
 __global__ __launch_bounds__(kThreads) void k_prolong_add(float *__restrict__ u, int n,
                                                           const float *__restrict__ v) {
-  const int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
-  if (t >= (int64_t)n * n * n) return;
-  const int k = (int)(t % n), j = (int)((t / n) % n), i = (int)(t / ((int64_t)n * n));
+  const unsigned un = (unsigned)n;
+  const unsigned t = xcd_block(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
+  if (t >= un * un * un) return;
+  const unsigned r = t / un;
+  const int k = (int)(t - r * un), i = (int)(r / un), j = (int)(r - (unsigned)i * un);
   const int nc = n >> 1;
   const int ia = i >> 1, ja = j >> 1, ka = k >> 1;
   const int ib = wrap_index(ia + ((i & 1) ? 1 : -1), nc);
@@ -162,7 +167,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_residual_norm(const float *__re
   double s1 = 0.0, s2 = 0.0;
   const int64_t stride = (int64_t)gridDim.x * RED_THREADS;
   for (int64_t t = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; t < count; t += stride) {
-    const int k = (int)(t % n), j = (int)((t / n) % n), i = (int)(t / ((int64_t)n * n));
+    const unsigned ut = (unsigned)t, un = (unsigned)n, q = ut / un;
+    const int k = (int)(ut - q * un), i = (int)(q / un), j = (int)(q - (unsigned)i * un);
     const double r = residual_at(u, f, scale, m, i, j, k, n, inv_h2);
     const double fv = scale * (f[t] - m);
     s1 += r * r;
@@ -231,82 +237,14 @@ __global__ __launch_bounds__(kThreads) void k_subtract_mean(float *__restrict__ 
   u[c] -= *mean;
 }
 
-__device__ double block_sum_coarse(double v, double *lds) {
-  v = wave_sum(v);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) lds[wave] = v;
-  __syncthreads();
-  double s = 0.0;
-  for (int w = 0; w < kCoarseThreads / 64; ++w) s += lds[w];
-  return s;
-}
-
-// Coarsest level: red-black Gauss-Seidel sweeps in LDS until the residual has
-// dropped by `reduction` (checked every 4 sweeps), stagnates, or max_sweeps.
-// The mean of the right-hand side and of the solution are removed.
+// Coarsest level: one workgroup, in LDS (coarse_solve.h).
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_solve(
     float *__restrict__ ug, const float *__restrict__ fg, float scale,
     const float *__restrict__ mean, int n, float h2, float reduction, int max_sweeps) {
   __shared__ float su[kCoarseMax];
   __shared__ float sf[kCoarseMax];
   __shared__ double red[kCoarseThreads / 64];
-  const int count = n * n * n;
-  const float m = src_mean(mean);
-  double fs = 0.0;
-  for (int c = threadIdx.x; c < count; c += kCoarseThreads) {
-    su[c] = ug[c];
-    const float fv = scale * (fg[c] - m);
-    sf[c] = fv;
-    fs += fv;
-  }
-  const float fmean = (float)(block_sum_coarse(fs, red) / count);
-  for (int c = threadIdx.x; c < count; c += kCoarseThreads) sf[c] -= fmean;
-  __syncthreads();
-  const float inv_h2 = 1.0f / h2;
-  auto resid_norm = [&]() {
-    double s = 0.0;
-    for (int c = threadIdx.x; c < count; c += kCoarseThreads) {
-      const int k = c % n, j = (c / n) % n, i = c / (n * n);
-      const float uc = su[c];
-      const float lap = (su[(wrap_index(i + 1, n) * n + j) * n + k] - uc) +
-                        (su[(wrap_index(i - 1, n) * n + j) * n + k] - uc) +
-                        (su[(i * n + wrap_index(j + 1, n)) * n + k] - uc) +
-                        (su[(i * n + wrap_index(j - 1, n)) * n + k] - uc) +
-                        (su[(i * n + j) * n + wrap_index(k + 1, n)] - uc) +
-                        (su[(i * n + j) * n + wrap_index(k - 1, n)] - uc);
-      const double r = sf[c] - lap * inv_h2;
-      s += r * r;
-    }
-    return sqrt(block_sum_coarse(s, red));
-  };
-  const double r0 = resid_norm();
-  double prev = r0;
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    for (int colour = 0; colour < 2; ++colour) {
-      for (int c = threadIdx.x; c < count; c += kCoarseThreads) {
-        const int k = c % n, j = (c / n) % n, i = c / (n * n);
-        if (((i + j + k) & 1) != colour) continue;
-        const float nb = su[(wrap_index(i + 1, n) * n + j) * n + k] +
-                         su[(wrap_index(i - 1, n) * n + j) * n + k] +
-                         su[(i * n + wrap_index(j + 1, n)) * n + k] +
-                         su[(i * n + wrap_index(j - 1, n)) * n + k] +
-                         su[(i * n + j) * n + wrap_index(k + 1, n)] +
-                         su[(i * n + j) * n + wrap_index(k - 1, n)];
-        su[c] = (nb - h2 * sf[c]) * (1.0f / 6.0f);
-      }
-      __syncthreads();
-    }
-    if ((sweep & 3) == 3) {
-      const double r = resid_norm();
-      if (r <= reduction * r0 || r > 0.98 * prev) break;
-      prev = r;
-    }
-  }
-  double us = 0.0;
-  for (int c = threadIdx.x; c < count; c += kCoarseThreads) us += su[c];
-  const float umean = (float)(block_sum_coarse(us, red) / count);
-  for (int c = threadIdx.x; c < count; c += kCoarseThreads) ug[c] = su[c] - umean;
+  pm_coarse::solve_any(ug, fg, scale, src_mean(mean), n, h2, reduction, max_sweeps, su, sf, red);
 }
 
 inline unsigned blocks_for(int64_t count, int threads) {
