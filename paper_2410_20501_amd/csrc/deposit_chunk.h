@@ -2,21 +2,21 @@
 // atomic mode and the batched ensembles, and the particle helpers it needs.
 //
 // A workgroup deposits a chunk of up to 2048 particles without per-weight
-// atomics:
+// global atomics:
 //   1. the particles' cells are taken relative to the chunk's first particle
-//      (minimum image) and their bounding box P is found;
-//   2. the particles are counting-sorted by cell of P inside LDS (two integer
-//      LDS atomics per particle), keeping only their in-cell offsets;
-//   3. every cell of P grown by one cell per side (the window's reach) sums,
-//      in registers, the window values of the particles in its 27 neighbour
-//      cells of P; the separation along an axis is (q - c) + o - 1/2 with
-//      q - c in {-1, 0, 1} and o the in-cell offset;
-//   4. non-zero sums are added to the grid with one global atomic per cell.
-// Chunks whose cell box exceeds the LDS table fall back to one global atomic
-// per weight. Which particles form a chunk is the caller's choice (an Index
-// object maps the chunk's slots to particle rows, -1 for an empty slot): runs
-// of consecutive rows after a tile-major reorder, or lattice blocks of
-// particles that started on a lattice.
+//      (minimum image) and their bounding box is found, grown by one cell per
+//      side (the window's reach);
+//   2. every particle adds its 27 (8) window weights, as 2^-30 fixed-point
+//      integers, to 64-bit accumulators of that box in LDS (integer LDS atomics
+//      run at several T ops/s on gfx950, float ones far slower; integer sums are
+//      also exact, whatever the order);
+//   3. each touched cell of the box is added to the grid with one FP32 global
+//      atomic (so the last bits may differ between runs).
+// Chunks whose box exceeds the LDS table fall back to one global atomic per
+// weight. Which particles form a chunk is the caller's choice (an Index object
+// maps the chunk's slots to particle rows, -1 for an empty slot): runs of
+// consecutive rows after a tile-major reorder, or lattice blocks of particles
+// that started on a lattice.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -113,7 +113,7 @@ __device__ __forceinline__ void particle_support(const float *__restrict__ pos,
 constexpr int kGThreads = 256;
 constexpr int kGPPT = 8;
 constexpr int kGChunk = kGThreads * kGPPT;
-constexpr int kGCells = 4096;  // max cells of the particle box P
+constexpr int kGTable = 5120;  // cells of the grown particle box held in LDS (8 B each)
 
 __device__ __forceinline__ int min_image(int d, int n) { return wrap_any(d + n / 2, n) - n / 2; }
 
@@ -192,30 +192,31 @@ struct LatticeIndex {
 template <int MAS, int PK, class Index>
 __device__ void deposit_chunk(const float *__restrict__ pos, const int32_t *__restrict__ cell,
                               const Index idx, int n, float mass, float *__restrict__ rho) {
-  __shared__ float so[3][kGChunk];        // sorted in-cell offsets
-  __shared__ int cstart[kGCells + 1];     // cell counts, then starts, then cursors
+  __shared__ unsigned long long acc[kGTable];  // 2^-30 fixed-point sums of the grown box
   __shared__ int red[6][kGThreads / 64];
-  __shared__ int wsum[kGThreads / 64];
   int ref[3];
   {
     float o[3];
     particle_cell<PK>(pos, cell, idx.ref(), n, ref, o);
   }
+  // 1. cells relative to the reference particle, and their bounding box
   int lc[kGPPT][3];
   float lo_f[kGPPT][3];
+  bool ok[kGPPT];
   int lo[3] = {n, n, n}, hi[3] = {-n, -n, -n};
 #pragma unroll
   for (int m = 0; m < kGPPT; ++m) {
     const int64_t p = idx(threadIdx.x + m * kGThreads);
+    ok[m] = p >= 0;
     int c[3] = {0, 0, 0};
     float o[3] = {0.f, 0.f, 0.f};
-    if (p >= 0) particle_cell<PK>(pos, cell, p, n, c, o);
+    if (ok[m]) particle_cell<PK>(pos, cell, p, n, c, o);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const int d = min_image(c[a] - ref[a], n);
       lc[m][a] = d;
       lo_f[m][a] = o[a];
-      if (p >= 0) {
+      if (ok[m]) {
         lo[a] = min(lo[a], d);
         hi[a] = max(hi[a], d);
       }
@@ -231,7 +232,7 @@ __device__ void deposit_chunk(const float *__restrict__ pos, const int32_t *__re
     }
   }
   __syncthreads();
-  int e[3];
+  int g[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     int l = red[a][0], h = red[3 + a][0];
@@ -240,10 +241,10 @@ __device__ void deposit_chunk(const float *__restrict__ pos, const int32_t *__re
       h = max(h, red[3 + a][w]);
     }
     lo[a] = l;
-    e[a] = h - l + 1;
+    g[a] = h - l + 3;  // grown by the window's reach of one cell per side
   }
-  const int vol = e[0] * e[1] * e[2];
-  if (vol > kGCells) {
+  const int gvol = g[0] * g[1] * g[2];
+  if (gvol > kGTable) {
     // fallback: global atomics per weight
 #pragma unroll 1
     for (int m = 0; m < kGPPT; ++m) {
@@ -264,98 +265,46 @@ __device__ void deposit_chunk(const float *__restrict__ pos, const int32_t *__re
     }
     return;
   }
-  // 2. counting sort by local cell
-  for (int i = threadIdx.x; i <= vol; i += kGThreads) cstart[i] = 0;
+  // 2. scatter the window weights into the LDS box (integer atomics: exact sums)
+  for (int i = threadIdx.x; i < gvol; i += kGThreads) acc[i] = 0ull;
   __syncthreads();
-  int key[kGPPT];
-#pragma unroll
+  const float kFix = 1073741824.0f;  // 2^30
+#pragma unroll 2
   for (int m = 0; m < kGPPT; ++m) {
-    const int64_t p = idx(threadIdx.x + m * kGThreads);
-    key[m] = -1;
-    if (p >= 0) {
-      key[m] = ((lc[m][0] - lo[0]) * e[1] + (lc[m][1] - lo[1])) * e[2] + (lc[m][2] - lo[2]);
-      atomicAdd(&cstart[key[m]], 1);
+    if (!ok[m]) continue;
+    int f[3];
+    float w[3][MAS];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      // local index of the particle's cell is lc - lo + 1; the window's first cell
+      // is one below it (TSC), or at or one below it (CIC)
+      f[a] = axis_off<MAS>(lc[m][a] - lo[a] + 1, lo_f[m][a], w[a]);
     }
-  }
-  __syncthreads();
-  // exclusive scan of cstart[0 .. vol) (kGCells / kGThreads = 16 entries per thread)
-  {
-    constexpr int PER = kGCells / kGThreads;
-    const int b0 = threadIdx.x * PER;
-    int v[PER];
-    int tot = 0;
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      v[i] = (b0 + i < vol) ? cstart[b0 + i] : 0;
-      tot += v[i];
-    }
-    int x = tot;
+    for (int a = 0; a < MAS; ++a) {
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int y = __shfl_up(x, o, 64);
-      if (lane >= o) x += y;
-    }
-    if (lane == 63) wsum[wave] = x;
-    __syncthreads();
-    int woff = 0;
-    for (int w = 0; w < wave; ++w) woff += wsum[w];
-    int run = x - tot + woff;
+      for (int b = 0; b < MAS; ++b) {
+        const int row = ((f[0] + a) * g[1] + (f[1] + b)) * g[2] + f[2];
+        const float wab = w[0][a] * w[1][b] * kFix;
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      if (b0 + i < vol) cstart[b0 + i] = run;
-      run += v[i];
-    }
-    __syncthreads();
-  }
-  // scatter offsets: the cursor of a cell is its start, advanced atomically
-#pragma unroll
-  for (int m = 0; m < kGPPT; ++m) {
-    if (key[m] < 0) continue;
-    const int slot = atomicAdd(&cstart[key[m]], 1);
-    so[0][slot] = lo_f[m][0];
-    so[1][slot] = lo_f[m][1];
-    so[2][slot] = lo_f[m][2];
-  }
-  __syncthreads();
-  // after the scatter cstart[c] is the end of cell c, i.e. the start of cell c+1;
-  // the start of cell c is cstart[c-1] (0 for c = 0)
-  // 3. gather into the grown box, 4. flush
-  const int g0 = e[0] + 2, g1 = e[1] + 2, g2 = e[2] + 2;
-  const int gvol = g0 * g1 * g2;
-  for (int t = threadIdx.x; t < gvol; t += kGThreads) {
-    const int x = t / (g1 * g2), r = t - x * (g1 * g2);
-    const int y = r / g2, z = r - y * g2;
-    // target cell in P coordinates: (x-1, y-1, z-1)
-    float acc = 0.0f;
-#pragma unroll
-    for (int dx = -1; dx <= 1; ++dx) {
-      const int qx = x - 1 + dx;
-      if (qx < 0 || qx >= e[0]) continue;
-#pragma unroll
-      for (int dy = -1; dy <= 1; ++dy) {
-        const int qy = y - 1 + dy;
-        if (qy < 0 || qy >= e[1]) continue;
-        const int row = (qx * e[1] + qy) * e[2];
-        const float wxy_dx = (float)dx - 0.5f, wxy_dy = (float)dy - 0.5f;
-#pragma unroll
-        for (int dz = -1; dz <= 1; ++dz) {
-          const int qz = z - 1 + dz;
-          if (qz < 0 || qz >= e[2]) continue;
-          const int q = row + qz;
-          const int s0 = q > 0 ? cstart[q - 1] : 0, s1 = cstart[q];
-          for (int sidx = s0; sidx < s1; ++sidx) {
-            acc += window_sep_g<MAS>(wxy_dx + so[0][sidx]) * window_sep_g<MAS>(wxy_dy + so[1][sidx]) *
-                   window_sep_g<MAS>((float)dz - 0.5f + so[2][sidx]);
-          }
-        }
+        for (int c = 0; c < MAS; ++c)
+          atomicAdd(&acc[row + c], (unsigned long long)(unsigned)rintf(wab * w[2][c]));
       }
     }
-    if (acc != 0.0f) {
-      const int gi = wrap_any(ref[0] + lo[0] + x - 1, n);
-      const int gj = wrap_any(ref[1] + lo[1] + y - 1, n);
-      const int gk = wrap_any(ref[2] + lo[2] + z - 1, n);
-      unsafeAtomicAdd(&rho[((size_t)gi * n + gj) * n + gk], mass * acc);
-    }
+  }
+  __syncthreads();
+  // 3. one global atomic per touched cell
+  const float scale = mass * (1.0f / kFix);
+  const int g12 = g[1] * g[2];
+  for (int t = threadIdx.x; t < gvol; t += kGThreads) {
+    const unsigned long long v = acc[t];
+    if (v == 0ull) continue;
+    const int x = t / g12, r = t - x * g12;
+    const int y = r / g[2], z = r - y * g[2];
+    const int gi = wrap_any(ref[0] + lo[0] - 1 + x, n);
+    const int gj = wrap_any(ref[1] + lo[1] - 1 + y, n);
+    const int gk = wrap_any(ref[2] + lo[2] - 1 + z, n);
+    unsafeAtomicAdd(&rho[((size_t)gi * n + gj) * n + gk], (float)v * scale);
   }
 }
 

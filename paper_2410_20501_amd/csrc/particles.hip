@@ -9,7 +9,6 @@ namespace {
 
 using pm_chunk::axis_box;
 using pm_chunk::axis_off;
-using pm_chunk::kGCells;
 using pm_chunk::kGChunk;
 using pm_chunk::kGPPT;
 using pm_chunk::kGThreads;
