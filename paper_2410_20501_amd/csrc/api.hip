@@ -109,9 +109,20 @@ int deposit_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np,
   if (order == PM_DEPOSIT_SORTED) {
     int st = ensure_sort_scratch(ctx, np);
     if (st != PM_OK) return st;
-    PM_HIP(ctx, launch_sort_by_cell(ctx, pos, cell, np, poskind, s, false));
+    const bool tiles = (n % 8) == 0;
+    if (tiles && !ctx->fix_grid) {
+      if (hipMalloc(&ctx->fix_grid, sizeof(unsigned long long) * (size_t)ncell) != hipSuccess) {
+        ctx->fix_grid = nullptr;
+        return pm_fail(ctx, PM_ERR_NOMEM, "fixed-point density allocation failed");
+      }
+      PM_HIP(ctx, hipMemsetAsync(ctx->fix_grid, 0, sizeof(unsigned long long) * (size_t)ncell, s));
+    }
+    PM_HIP(ctx, launch_sort_by_cell(ctx, pos, cell, np, poskind, s, tiles ? 2 : 0));
     pm_kt_begin(ctx, PM_KERNEL_DEPOSIT, s);
-    PM_HIP(ctx, launch_deposit_pull(ctx, pos, np, poskind, mas, mass, rho, s));
+    if (tiles)
+      PM_HIP(ctx, launch_deposit_own(ctx, pos, cell, poskind, mas, mass, rho, s));
+    else
+      PM_HIP(ctx, launch_deposit_pull(ctx, pos, np, poskind, mas, mass, rho, s));
     // algorithmic bytes: in-cell offsets (12 B per particle) + the density (4 B per cell)
     pm_kt_end(ctx, PM_KERNEL_DEPOSIT, s, 12.0 * (double)np + 4.0 * (double)ncell);
     return PM_OK;
@@ -291,6 +302,7 @@ void pm_destroy(pm_ctx *ctx) {
   fr(ctx->pcell);
   fr(ctx->scan_partial);
   fr(ctx->reorder_tmp);
+  fr(ctx->fix_grid);
   fr(ctx->adj_gbar);
   fr(ctx->adj_phibar);
   for (int i = 0; i < 8; ++i)
@@ -432,7 +444,7 @@ int pm_reorder(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, float *acc, i
   }
   hipStream_t s = (hipStream_t)stream;
   const bool tile_major = (ctx->n % 8) == 0;
-  PM_HIP(ctx, launch_sort_by_cell(ctx, pos, cell, np, poskind, s, tile_major));
+  PM_HIP(ctx, launch_sort_by_cell(ctx, pos, cell, np, poskind, s, tile_major ? 1 : 0));
   PM_HIP(ctx, launch_apply_perm(ctx, pos, poskind == PM_POS_CELLOFF ? cell : nullptr, vel, acc, ids,
                                 np, s));
   return PM_OK;

@@ -50,6 +50,7 @@ struct pm_ctx {
   int32_t *scan_partial; // [SCAN_MAX_BLOCKS]
   int64_t sort_cap;
   void *reorder_tmp;     // [np_max * 12 bytes] permutation staging (lazy)
+  unsigned long long *fix_grid;  // [n^3] 2^-30 fixed-point density (sorted deposit, lazy, kept zero)
   int64_t reorder_cap;
   // reverse mode (lazy)
   float *adj_gbar;       // [n^3 * 3] cotangent of the force grid
@@ -94,12 +95,15 @@ int pm_hip_check(pm_ctx *ctx, hipError_t e, const char *what);
 // particles.hip
 hipError_t launch_deposit_atomic(const float *pos, const int32_t *cell, int64_t np, int poskind,
                                  int mas, int n, float mass, float *rho, hipStream_t s);
+// keymode: 0 row-major cells, 1 tile-major cells (n % 8 == 0), 2 tiles of 8^3 cells
 hipError_t launch_sort_by_cell(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np,
-                               int poskind, hipStream_t s, bool tile_major);
+                               int poskind, hipStream_t s, int keymode);
 hipError_t launch_apply_perm(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, float *acc,
                              int64_t *ids, int64_t np, hipStream_t s);
 hipError_t launch_deposit_pull(pm_ctx *ctx, const float *pos, int64_t np, int poskind, int mas,
                                float mass, float *rho, hipStream_t s);
+hipError_t launch_deposit_own(pm_ctx *ctx, const float *pos, const int32_t *cell, int poskind,
+                              int mas, float mass, float *rho, hipStream_t s);
 hipError_t launch_interp(const float *pos, const int32_t *cell, int64_t np, int poskind, int mas,
                          int n, const float *g, float *acc, float *vel, float kick,
                          hipStream_t s);

@@ -188,9 +188,12 @@ __device__ __forceinline__ WaveRun wave_runs(int key) {
   return r;
 }
 
-// Cell containing each particle (as a row-major or tile-major key); histogram with
-// one atomic per run of equal keys in a wave.
-template <int PK, bool TILE>
+// Sort keys: 0 = row-major cell, 1 = tile-major cell, 2 = 8^3-cell tile.
+constexpr int kKeyCell = 0, kKeyTileCell = 1, kKeyTile = 2;
+
+// Key of each particle's cell; histogram with one atomic per run of equal keys in a
+// wave (particles that are neighbours in memory mostly share keys).
+template <int PK, int KEY>
 __global__ __launch_bounds__(kThreads) void k_cell_hist(const float *__restrict__ pos,
                                                         const int32_t *__restrict__ cell,
                                                         int64_t np, int n,
@@ -210,7 +213,14 @@ __global__ __launch_bounds__(kThreads) void k_cell_hist(const float *__restrict_
       q[1] = (cc / n) - q[0] * n;
       q[2] = cc - (cc / n) * n;
     }
-    c = TILE ? tile_key(q[0], q[1], q[2], n) : (q[0] * n + q[1]) * n + q[2];
+    if constexpr (KEY == kKeyTileCell) {
+      c = tile_key(q[0], q[1], q[2], n);
+    } else if constexpr (KEY == kKeyTile) {
+      const int nt = n >> 3;
+      c = ((q[0] >> 3) * nt + (q[1] >> 3)) * nt + (q[2] >> 3);
+    } else {
+      c = (q[0] * n + q[1]) * n + q[2];
+    }
     pcell[p] = c;
   }
   const WaveRun r = wave_runs(c);
@@ -411,26 +421,12 @@ __global__ __launch_bounds__(kThreads) void k_deposit_pull(const float *__restri
   rho[c] = (float)((double)acc * (1.0 / kFixScale) * (double)mass);
 }
 
-// ------------------------------------------------------------------ tile-owned deposit
+// ------------------------------------------------------------------ fixed-point helpers
 
-// One block owns an 8^3 tile of output cells and reads the particles of the
-// tile's 10^3 halo cells through the per-cell ranges of the counting sort. A
-// particle in cell q adds to output cell t = q - D (D in {-1,0,1}^3) the weight
-// prod_d W(D_d + o_d - 1/2), o its in-cell offset. Weights are rounded to
-// multiples of 2^-30 and summed in 64-bit integers held in LDS (integer LDS
-// atomics are an order of magnitude faster than FP32 ones on this GPU, and the
-// integer sum is exact, so the grid is bitwise reproducible):
-//   * particles of sparse halo cells (<= kDense) add their in-tile weights with
-//     one LDS atomic each;
-//   * the particles of a dense halo cell are first reduced by one wave to the
-//     cell's 27 window moments M_q[D] = sum_p prod_d W(D_d + o_pd - 1/2), which
-//     are then added to the tile (avoiding 64 lanes updating the same words).
-// Every output cell is written once: no atomics on the grid.
 constexpr int kTT = 8;                        // tile edge
-constexpr int kTThreads = kTT * kTT * kTT;    // 512
-constexpr int kTH = kTT + 2;                  // halo edge
+constexpr int kTThreads = kTT * kTT * kTT;    // cells per tile (512)
+constexpr int kTH = kTT + 2;                  // tile + one-cell halo
 constexpr int kTHalo = kTH * kTH * kTH;       // 1000
-constexpr int kDense = 32;                    // particles above which a cell is dense
 constexpr float kFix30 = 1073741824.0f;       // 2^30 units per unit weight
 
 __device__ __forceinline__ unsigned long long fix30(float w) {
@@ -445,184 +441,119 @@ __device__ __forceinline__ unsigned long long wave_sum_ull(unsigned long long v)
   return v;
 }
 
-template <int PK>
-__device__ __forceinline__ void load_offset(const float *__restrict__ pos, int64_t p, int n,
-                                            float o[3]) {
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    float x = pos[3 * p + d];
-    if constexpr (PK == PM_POS_BOX) {
-      const float u = x * (float)n;
-      x = u - floorf(u);
-    }
-    o[d] = x;
-  }
+inline unsigned blocks_for(int64_t count, int threads) {
+  return (unsigned)((count + threads - 1) / threads);
 }
 
+// ------------------------------------------------------------------ particle-owned tile deposit
+
+// Deterministic deposit from particles bucketed by 8^3-cell tile: one workgroup per
+// tile reads only the
+// particles of its own tile (each particle once), adds their 27 (8) window weights
+// as 2^-30 fixed-point integers to an LDS box of the tile plus a one-cell halo, and
+// adds the box to a 64-bit fixed-point grid with one integer global atomic per
+// touched cell. A conversion pass then writes rho = w 2^-30 sum and clears the
+// fixed-point grid. Every sum is an integer sum, so the result is bitwise the same
+// for any particle order, any interleaving of the atomics and any run.
+// A wave whose 64 particles share one cell (dense cells: particles kept in
+// tile-major cell order by pm_reorder stay together) first reduces its 27 window
+// moments across lanes.
+constexpr int kOThreads = 256;
+
 template <int MAS, int PK>
-__global__ __launch_bounds__(kTThreads) void k_deposit_tile(const float *__restrict__ pos,
-                                                            const int32_t *__restrict__ start,
-                                                            const int32_t *__restrict__ perm,
-                                                            int n, float mass,
-                                                            float *__restrict__ rho) {
-  __shared__ unsigned long long accum[kTThreads];
-  __shared__ int lstart[kTHalo + 1];     // local starts of the sparse halo cells
-  __shared__ int gstart[kTHalo];         // global starts (in the sorted order)
-  __shared__ int gcount[kTHalo];         // particle counts
-  __shared__ short dlist[kTHalo];        // dense halo cells
-  __shared__ int wsum[kTThreads / 64];
-  __shared__ int wdense[kTThreads / 64];
+__global__ __launch_bounds__(kOThreads) void k_deposit_own(const float *__restrict__ pos,
+                                                           const int32_t *__restrict__ cell,
+                                                           const int32_t *__restrict__ end,
+                                                           const int32_t *__restrict__ perm,
+                                                           int n,
+                                                           unsigned long long *__restrict__ acc) {
+  __shared__ unsigned long long box[kTHalo];
   const int nt = n / kTT;
   const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
   const int tk = tile % nt, tj = (tile / nt) % nt, ti = tile / (nt * nt);
-  const int i0 = ti * kTT - 1, j0 = tj * kTT - 1, k0 = tk * kTT - 1;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  accum[threadIdx.x] = 0ull;
-
-  // 1. halo cell ranges (two per thread); sparse counts are scanned, dense cells listed
-  int cnt[2], gs[2];
-  bool dn[2];
-#pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    const int h = threadIdx.x * 2 + r;
-    cnt[r] = 0;
-    gs[r] = 0;
-    if (h < kTHalo) {
-      const int hx = h / (kTH * kTH), hy = (h / kTH) % kTH, hz = h % kTH;
-      const int g = (wrap_index(i0 + hx, n) * n + wrap_index(j0 + hy, n)) * n + wrap_index(k0 + hz, n);
-      gs[r] = g > 0 ? start[g - 1] : 0;   // `start` holds cell ends: end[g] = start of g + 1
-      cnt[r] = start[g] - gs[r];
-      gstart[h] = gs[r];
-      gcount[h] = cnt[r];
-    }
-    dn[r] = cnt[r] > kDense;
-  }
-  const int sp0 = dn[0] ? 0 : cnt[0], sp1 = dn[1] ? 0 : cnt[1];
-  const int tot = sp0 + sp1, dtot = (int)dn[0] + (int)dn[1];
-  int x = tot, y = dtot;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int xs = __shfl_up(x, o, 64), ys = __shfl_up(y, o, 64);
-    if (lane >= o) {
-      x += xs;
-      y += ys;
-    }
-  }
-  if (lane == 63) {
-    wsum[wave] = x;
-    wdense[wave] = y;
-  }
+  for (int i = threadIdx.x; i < kTHalo; i += kOThreads) box[i] = 0ull;
   __syncthreads();
-  int woff = 0, all = 0, doff = 0, ndense = 0;
-  for (int w = 0; w < kTThreads / 64; ++w) {
-    if (w < wave) {
-      woff += wsum[w];
-      doff += wdense[w];
-    }
-    all += wsum[w];
-    ndense += wdense[w];
-  }
-  {
-    const int h = threadIdx.x * 2;
-    int ex = x - tot + woff, dx = y - dtot + doff;
-    if (h < kTHalo) {
-      lstart[h] = ex;
-      if (dn[0]) dlist[dx++] = (short)h;
-    }
-    if (h + 1 < kTHalo) {
-      lstart[h + 1] = ex + sp0;
-      if (dn[1]) dlist[dx] = (short)(h + 1);
-    }
-    if (threadIdx.x == 0) lstart[kTHalo] = all;
-  }
-  __syncthreads();
-
-  // 2. sparse particles: one per thread at a time, in-tile weights added to LDS;
-  //    the slot's halo cell comes from a binary search in the local starts
-  for (int l = threadIdx.x; l < all; l += kTThreads) {
-    int lo_h = 0, hi_h = kTHalo;  // h with lstart[h] <= l < lstart[h + 1]
-    while (hi_h - lo_h > 1) {
-      const int mid = (lo_h + hi_h) >> 1;
-      if (lstart[mid] <= l) lo_h = mid; else hi_h = mid;
-    }
-    const int h = lo_h;
-    float o[3];
-    load_offset<PK>(pos, perm[gstart[h] + (l - lstart[h])], n, o);
-    const int hx = h / (kTH * kTH), hy = (h / kTH) % kTH, hz = h % kTH;
-    float wx[3], wy[3], wz[3];
-#pragma unroll
-    for (int t = 0; t < 3; ++t) {
-      wx[t] = window_sep<MAS>((float)(t - 1) + o[0] - 0.5f);
-      wy[t] = window_sep<MAS>((float)(t - 1) + o[1] - 0.5f);
-      wz[t] = window_sep<MAS>((float)(t - 1) + o[2] - 0.5f);
-    }
-    // target t = q - D in tile coordinates: (hx - 1) - (a - 1) = hx - a
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const int tx = hx - a;
-      if (tx < 0 || tx >= kTT) continue;
-#pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        const int ty = hy - b;
-        if (ty < 0 || ty >= kTT) continue;
-        const float wab = wx[a] * wy[b];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const int tz = hz - c;
-          if (tz < 0 || tz >= kTT) continue;
-          const unsigned long long v = fix30(wab * wz[c]);
-          if (v) atomicAdd(&accum[(tx * kTT + ty) * kTT + tz], v);
-        }
-      }
-    }
-  }
-
-  // 3. dense cells: one wave reduces a cell's particles to 27 moments, then lanes
-  //    0..26 add them to the in-tile targets
-  for (int di = wave; di < ndense; di += kTThreads / 64) {
-    const int h = dlist[di];
-    const int g0 = gstart[h], c = gcount[h];
-    unsigned long long m[27];
-#pragma unroll
-    for (int q = 0; q < 27; ++q) m[q] = 0ull;
-    for (int l = lane; l < c; l += 64) {
-      float o[3];
-      load_offset<PK>(pos, perm[g0 + l], n, o);
-      float wx[3], wy[3], wz[3];
+  // particles bucketed by tile: end[t] is the end of tile t's bucket
+  const int p_begin = tile > 0 ? end[tile - 1] : 0;
+  const int p_end = end[tile];
+  for (int l0 = p_begin; l0 < p_end; l0 += kOThreads) {
+    const int l = l0 + threadIdx.x;
+    bool act = l < p_end;
+    int c[3] = {0, 0, 0};
+    float o[3] = {0.f, 0.f, 0.f};
+    if (act) particle_cell<PK>(pos, cell, perm[l], n, c, o);
+    const int lx = c[0] - ti * kTT, ly = c[1] - tj * kTT, lz = c[2] - tk * kTT;
+    // every particle of the bucket lies in this tile (same cell rule as the sort)
+    act = act && (unsigned)lx < (unsigned)kTT && (unsigned)ly < (unsigned)kTT &&
+          (unsigned)lz < (unsigned)kTT;
+    const int key = act ? (lx * kTT + ly) * kTT + lz : -1;
+    float wx[MAS], wy[MAS], wz[MAS];
+    // box coordinates are tile coordinates + 1; the window's first cell follows
+    const int fx = axis_off<MAS>(lx + 1, o[0], wx);
+    const int fy = axis_off<MAS>(ly + 1, o[1], wy);
+    const int fz = axis_off<MAS>(lz + 1, o[2], wz);
+    const int key_first = __shfl(key, 0, 64);
+    const bool uniform = __ballot(act && key == key_first) == __ballot(l0 + (int)threadIdx.x < p_end) &&
+                         key_first >= 0;
+    if (uniform) {
+      // one cell for the whole wave: every lane's window lies in the 3^3 cells around
+      // it (box coordinates lx .. lx + 2); reduce the 27 moments, one lane adds them
+      float ex[3], ey[3], ez[3];
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
-        wx[t] = window_sep<MAS>((float)(t - 1) + o[0] - 0.5f);
-        wy[t] = window_sep<MAS>((float)(t - 1) + o[1] - 0.5f);
-        wz[t] = window_sep<MAS>((float)(t - 1) + o[2] - 0.5f);
+        const int ax = t - (fx - lx), ay = t - (fy - ly), az = t - (fz - lz);
+        ex[t] = (ax >= 0 && ax < MAS) ? wx[ax] : 0.0f;
+        ey[t] = (ay >= 0 && ay < MAS) ? wy[ay] : 0.0f;
+        ez[t] = (az >= 0 && az < MAS) ? wz[az] : 0.0f;
       }
+      const int bx = __shfl(lx, 0, 64), by = __shfl(ly, 0, 64), bz = __shfl(lz, 0, 64);
 #pragma unroll
       for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc) {
+            unsigned long long v = act ? fix30(ex[a] * ey[b] * ez[cc]) : 0ull;
+            v = wave_sum_ull(v);
+            if ((threadIdx.x & 63) == 0 && v)
+              atomicAdd(&box[((bx + a) * kTH + (by + b)) * kTH + (bz + cc)], v);
+          }
+    } else if (act) {
+#pragma unroll
+      for (int a = 0; a < MAS; ++a)
+#pragma unroll
+        for (int b = 0; b < MAS; ++b) {
           const float wab = wx[a] * wy[b];
+          const int row = ((fx + a) * kTH + (fy + b)) * kTH + fz;
 #pragma unroll
-          for (int cc = 0; cc < 3; ++cc) m[(a * 3 + b) * 3 + cc] += fix30(wab * wz[cc]);
+          for (int cc = 0; cc < MAS; ++cc) {
+            const unsigned long long v = fix30(wab * wz[cc]);
+            if (v) atomicAdd(&box[row + cc], v);
+          }
         }
-    }
-    const int hx = h / (kTH * kTH), hy = (h / kTH) % kTH, hz = h % kTH;
-#pragma unroll
-    for (int q = 0; q < 27; ++q) {
-      const unsigned long long v = wave_sum_ull(m[q]);
-      const int a = q / 9, b = (q / 3) % 3, cc = q % 3;
-      const int tx = hx - a, ty = hy - b, tz = hz - cc;
-      if (lane == 0 && tx >= 0 && tx < kTT && ty >= 0 && ty < kTT && tz >= 0 && tz < kTT)
-        atomicAdd(&accum[(tx * kTT + ty) * kTT + tz], v);
     }
   }
   __syncthreads();
-  const int cx = threadIdx.x / (kTT * kTT), cy = (threadIdx.x / kTT) % kTT, cz = threadIdx.x % kTT;
-  const int gi = ti * kTT + cx, gj = tj * kTT + cy, gk = tk * kTT + cz;
-  rho[((size_t)gi * n + gj) * n + gk] =
-      (float)((double)accum[threadIdx.x] * (1.0 / 1073741824.0) * (double)mass);
+  const int i0 = ti * kTT - 1, j0 = tj * kTT - 1, k0 = tk * kTT - 1;
+  for (int i = threadIdx.x; i < kTHalo; i += kOThreads) {
+    const unsigned long long v = box[i];
+    if (v == 0ull) continue;
+    const int hx = i / (kTH * kTH), hy = (i / kTH) % kTH, hz = i % kTH;
+    const size_t g = ((size_t)wrap_index(i0 + hx, n) * n + wrap_index(j0 + hy, n)) * n +
+                     wrap_index(k0 + hz, n);
+    atomicAdd(&acc[g], v);
+  }
 }
 
-inline unsigned blocks_for(int64_t count, int threads) {
-  return (unsigned)((count + threads - 1) / threads);
+// rho = scale * acc (fixed point -> FP32, in FP64 so the conversion is exact to the
+// last bit of the FP32 result); acc is cleared for the next deposit
+__global__ __launch_bounds__(kThreads) void k_fix_convert(unsigned long long *__restrict__ acc,
+                                                          int64_t count, double scale,
+                                                          float *__restrict__ rho) {
+  const int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
+  if (t >= count) return;
+  rho[t] = (float)((double)acc[t] * scale);
+  acc[t] = 0ull;
 }
 
 }  // namespace
@@ -676,29 +607,27 @@ hipError_t launch_kick_drift(float *pos, int32_t *cell, float *vel, const float 
 }
 
 hipError_t launch_sort_by_cell(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np,
-                               int poskind, hipStream_t s, bool tile_major) {
+                               int poskind, hipStream_t s, int keymode) {
   const int n = ctx->n;
-  const int64_t ncell = (int64_t)n * n * n;
-  const int64_t len = ncell + 1;
+  const int64_t nkeys = keymode == kKeyTile ? (int64_t)(n / 8) * (n / 8) * (n / 8)
+                                            : (int64_t)n * n * n;
+  const int64_t len = nkeys + 1;
   hipError_t e = hipMemsetAsync(ctx->cell_count, 0, sizeof(int32_t) * len, s);
   if (e != hipSuccess) return e;
   if (np > 0) {
     const unsigned nb = blocks_for(np, kThreads);
-    if (tile_major) {
-      if (poskind == PM_POS_BOX)
-        k_cell_hist<PM_POS_BOX, true><<<nb, kThreads, 0, s>>>(pos, cell, np, n, ctx->pcell,
-                                                               ctx->cell_count);
-      else
-        k_cell_hist<PM_POS_CELLOFF, true><<<nb, kThreads, 0, s>>>(pos, cell, np, n, ctx->pcell,
-                                                                   ctx->cell_count);
+#define PM_HIST(PKV, KEYV)                                                                   \
+  k_cell_hist<PKV, KEYV><<<nb, kThreads, 0, s>>>(pos, cell, np, n, ctx->pcell, ctx->cell_count)
+    if (poskind == PM_POS_BOX) {
+      if (keymode == kKeyTile) PM_HIST(PM_POS_BOX, kKeyTile);
+      else if (keymode == kKeyTileCell) PM_HIST(PM_POS_BOX, kKeyTileCell);
+      else PM_HIST(PM_POS_BOX, kKeyCell);
     } else {
-      if (poskind == PM_POS_BOX)
-        k_cell_hist<PM_POS_BOX, false><<<nb, kThreads, 0, s>>>(pos, cell, np, n, ctx->pcell,
-                                                                ctx->cell_count);
-      else
-        k_cell_hist<PM_POS_CELLOFF, false><<<nb, kThreads, 0, s>>>(pos, cell, np, n, ctx->pcell,
-                                                                    ctx->cell_count);
+      if (keymode == kKeyTile) PM_HIST(PM_POS_CELLOFF, kKeyTile);
+      else if (keymode == kKeyTileCell) PM_HIST(PM_POS_CELLOFF, kKeyTileCell);
+      else PM_HIST(PM_POS_CELLOFF, kKeyCell);
     }
+#undef PM_HIST
   }
   const unsigned nblk = blocks_for(len, kScanTile);
   k_scan_reduce<<<nblk, kScanThreads, 0, s>>>(ctx->cell_count, len, ctx->scan_partial);
@@ -714,30 +643,37 @@ hipError_t launch_sort_by_cell(pm_ctx *ctx, const float *pos, const int32_t *cel
 
 int64_t scan_blocks_needed(int64_t len) { return (len + kScanTile - 1) / kScanTile; }
 
+hipError_t launch_deposit_own(pm_ctx *ctx, const float *pos, const int32_t *cell, int poskind,
+                              int mas, float mass, float *rho, hipStream_t s) {
+  const int n = ctx->n;
+  const int64_t ncell = (int64_t)n * n * n;
+  const unsigned nt = (unsigned)(ncell / kTThreads);
+  unsigned long long *acc = ctx->fix_grid;
+  if (mas == PM_TSC) {
+    if (poskind == PM_POS_BOX)
+      k_deposit_own<3, PM_POS_BOX><<<nt, kOThreads, 0, s>>>(pos, cell, ctx->cell_count, ctx->perm,
+                                                             n, acc);
+    else
+      k_deposit_own<3, PM_POS_CELLOFF><<<nt, kOThreads, 0, s>>>(pos, cell, ctx->cell_count,
+                                                                 ctx->perm, n, acc);
+  } else {
+    if (poskind == PM_POS_BOX)
+      k_deposit_own<2, PM_POS_BOX><<<nt, kOThreads, 0, s>>>(pos, cell, ctx->cell_count, ctx->perm,
+                                                             n, acc);
+    else
+      k_deposit_own<2, PM_POS_CELLOFF><<<nt, kOThreads, 0, s>>>(pos, cell, ctx->cell_count,
+                                                                 ctx->perm, n, acc);
+  }
+  k_fix_convert<<<blocks_for(ncell, kThreads), kThreads, 0, s>>>(acc, ncell,
+                                                                 (double)mass / 1073741824.0, rho);
+  return hipGetLastError();
+}
+
 hipError_t launch_deposit_pull(pm_ctx *ctx, const float *pos, int64_t np, int poskind, int mas,
                                float mass, float *rho, hipStream_t s) {
   (void)np;
   const int n = ctx->n;
   const int64_t ncell = (int64_t)n * n * n;
-  if (n % kTT == 0) {
-    const unsigned nt = (unsigned)(ncell / kTThreads);
-    if (mas == PM_TSC) {
-      if (poskind == PM_POS_BOX)
-        k_deposit_tile<3, PM_POS_BOX><<<nt, kTThreads, 0, s>>>(pos, ctx->cell_count, ctx->perm, n,
-                                                                mass, rho);
-      else
-        k_deposit_tile<3, PM_POS_CELLOFF><<<nt, kTThreads, 0, s>>>(pos, ctx->cell_count, ctx->perm,
-                                                                    n, mass, rho);
-    } else {
-      if (poskind == PM_POS_BOX)
-        k_deposit_tile<2, PM_POS_BOX><<<nt, kTThreads, 0, s>>>(pos, ctx->cell_count, ctx->perm, n,
-                                                                mass, rho);
-      else
-        k_deposit_tile<2, PM_POS_CELLOFF><<<nt, kTThreads, 0, s>>>(pos, ctx->cell_count, ctx->perm,
-                                                                    n, mass, rho);
-    }
-    return hipGetLastError();
-  }
   const unsigned nb = blocks_for(ncell, kThreads);
   if (mas == PM_TSC) {
     if (poskind == PM_POS_BOX)
