@@ -141,7 +141,7 @@ int pm_mg_setup(pm_ctx *ctx);
 // mg_stream.hip
 int64_t smooth_stream_blocks(int n);
 hipError_t launch_smooth_stream(const float *uin, float *uout, const float *f, float fscale,
-                                const float *fmean, const float *vc, int n, float h2, float omega,
+                                const float *fmean, int n, float h2, float omega,
                                 int first_colour, int half_sweeps, double *partial, hipStream_t s);
 hipError_t launch_rr_stream(const float *u, const float *f, float fscale, const float *fmean,
                             int n, float inv_h2, int kind, float *fc, hipStream_t s);

@@ -127,26 +127,50 @@ __global__ __launch_bounds__(kThreads) void k_residual_restrict(
 
 // u_fine += P v_coarse: per axis 3/4 from the nearest coarse centre and 1/4 from
 // the next one (fine cell 2J has neighbours J, J-1; fine 2J+1 has J, J+1).
+// One thread per coarse cell (I, J, K) reads the 27 coarse values around it once
+// and updates its 8 fine children (2I+a, 2J+b, 2K+c), writing k-pairs as float2.
 __global__ __launch_bounds__(kThreads) void k_prolong_add(float *__restrict__ u, int n,
                                                           const float *__restrict__ v) {
-  const unsigned un = (unsigned)n;
+  const unsigned nc = (unsigned)n >> 1;
   const unsigned t = xcd_block(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
-  if (t >= un * un * un) return;
-  const unsigned r = t / un;
-  const int k = (int)(t - r * un), i = (int)(r / un), j = (int)(r - (unsigned)i * un);
-  const int nc = n >> 1;
-  const int ia = i >> 1, ja = j >> 1, ka = k >> 1;
-  const int ib = wrap_index(ia + ((i & 1) ? 1 : -1), nc);
-  const int jb = wrap_index(ja + ((j & 1) ? 1 : -1), nc);
-  const int kb = wrap_index(ka + ((k & 1) ? 1 : -1), nc);
-  const size_t nn = (size_t)nc * nc;
-  auto at = [&](int x, int y, int z) { return v[(size_t)x * nn + (size_t)y * nc + z]; };
+  if (t >= nc * nc * nc) return;
+  const unsigned r = t / nc;
+  const int K = (int)(t - r * nc), I = (int)(r / nc), J = (int)(r - (unsigned)I * nc);
+  const int c = (int)nc;
+  const int ix[3] = {wrap_index(I - 1, c), I, wrap_index(I + 1, c)};
+  const int jx[3] = {wrap_index(J - 1, c), J, wrap_index(J + 1, c)};
+  const int kx[3] = {wrap_index(K - 1, c), K, wrap_index(K + 1, c)};
   const float near = 0.75f, far = 0.25f;
-  const float sa = near * (near * (near * at(ia, ja, ka) + far * at(ia, ja, kb)) +
-                           far * (near * at(ia, jb, ka) + far * at(ia, jb, kb)));
-  const float sb = far * (near * (near * at(ib, ja, ka) + far * at(ib, ja, kb)) +
-                          far * (near * at(ib, jb, ka) + far * at(ib, jb, kb)));
-  u[t] += sa + sb;
+  // along k: even child (2K) takes K-1 and K, odd child (2K+1) takes K and K+1
+  float ek[3][3], ok[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const float *row = v + ((size_t)ix[a] * nc + jx[b]) * nc;
+      const float vm = row[kx[0]], v0 = row[kx[1]], vp = row[kx[2]];
+      ek[a][b] = near * v0 + far * vm;
+      ok[a][b] = near * v0 + far * vp;
+    }
+  const size_t nn = (size_t)n * n;
+#pragma unroll
+  for (int ai = 0; ai < 2; ++ai) {       // fine plane 2I + ai
+    const int an = 1, af = ai ? 2 : 0;   // nearest and far coarse planes
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {     // fine row 2J + bj
+      const int bn = 1, bf = bj ? 2 : 0;
+      const float se = near * (near * ek[an][bn] + far * ek[an][bf]) +
+                       far * (near * ek[af][bn] + far * ek[af][bf]);
+      const float so = near * (near * ok[an][bn] + far * ok[an][bf]) +
+                       far * (near * ok[af][bn] + far * ok[af][bf]);
+      float2 *dst = reinterpret_cast<float2 *>(u + (size_t)(2 * I + ai) * nn +
+                                               (size_t)(2 * J + bj) * n + 2 * K);
+      float2 cur = *dst;
+      cur.x += se;
+      cur.y += so;
+      *dst = cur;
+    }
+  }
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -290,22 +314,21 @@ struct Solver {
     return hipGetLastError();
   }
 
-  // streaming smoothing of `sweeps` full sweeps; the first pass may add the
-  // prolongation of vc and/or sum the residual norm of its input.
-  hipError_t stream_sweeps(int l, int first_colour, int sweeps, const float *vc, double *partial) {
+  // streaming smoothing of `sweeps` full sweeps; the first pass may sum the residual
+  // norm of its input.
+  hipError_t stream_sweeps(int l, int first_colour, int sweeps, double *partial) {
     const int n = ctx->lev[l].n;
     const Src sr = src(l);
     hipError_t e = hipSuccess;
     while (sweeps > 0 && e == hipSuccess) {
       const int now = sweeps >= 2 ? 2 : 1;
       if (l == 0) pm_kt_begin(ctx, PM_KERNEL_SMOOTH, s);
-      e = launch_smooth_stream(cur[l], alt[l], sr.f, sr.scale, sr.mean, vc, n, h2(l), p->omega,
+      e = launch_smooth_stream(cur[l], alt[l], sr.f, sr.scale, sr.mean, n, h2(l), p->omega,
                                first_colour, 2 * now, partial, s);
       // algorithmic bytes of one pass (any number of fused sweeps): read u and f,
       // write u, 4 B each per cell
       if (l == 0) pm_kt_end(ctx, PM_KERNEL_SMOOTH, s, 12.0 * (double)n * n * n);
       std::swap(cur[l], alt[l]);
-      vc = nullptr;
       partial = nullptr;
       sweeps -= now;
     }
@@ -313,7 +336,7 @@ struct Solver {
   }
 
   hipError_t pre_smooth(int l) {
-    return streaming(l) ? stream_sweeps(l, 0, p->pre, nullptr, nullptr) : half_sweeps(l, 0, p->pre);
+    return streaming(l) ? stream_sweeps(l, 0, p->pre, nullptr) : half_sweeps(l, 0, p->pre);
   }
 
   hipError_t restrict_residual(int l) {
@@ -341,11 +364,11 @@ struct Solver {
 
   hipError_t correct_and_post_smooth(int l) {
     const int n = ctx->lev[l].n;
-    // (the streaming smoother can also fuse the prolongation, see PROLONG; a
-    //  separate pass is faster on gfx950 because the fused variant spills)
-    k_prolong_add<<<blocks_for((int64_t)n * n * n, kThreads), kThreads, 0, s>>>(cur[l], n,
-                                                                                 cur[l + 1]);
-    if (streaming(l)) return stream_sweeps(l, 1, p->post, nullptr, nullptr);
+    // (a prolongation fused into the post-smoother's loads needs 8 more prefetched
+    //  values per point and spilled registers on gfx950: a separate pass is faster)
+    k_prolong_add<<<blocks_for((int64_t)(n / 2) * (n / 2) * (n / 2), kThreads), kThreads, 0, s>>>(
+        cur[l], n, cur[l + 1]);
+    if (streaming(l)) return stream_sweeps(l, 1, p->post, nullptr);
     return half_sweeps(l, 1, p->post);
   }
 
@@ -436,7 +459,7 @@ int pm_mg_solve(pm_ctx *ctx, const float *rho, float coef, float *phi, const pm_
       // pass when streaming (its output is used only if another cycle is needed)
       if (fused_norm) {
         const int64_t nb = smooth_stream_blocks(n);
-        PM_HIP(ctx, sv.stream_sweeps(0, 0, std::min(p->pre, 2), nullptr, ctx->red_partial));
+        PM_HIP(ctx, sv.stream_sweeps(0, 0, std::min(p->pre, 2), ctx->red_partial));
         k_pair_final<<<1, RED_THREADS, 0, s>>>(ctx->red_partial, (int)nb, ctx->red_result);
       } else {
         sv.norms();
@@ -467,7 +490,7 @@ int pm_mg_solve(pm_ctx *ctx, const float *rho, float coef, float *phi, const pm_
       }
       if (fused_norm) {
         // finish the cycle whose pre-smoothing already ran (remaining pre sweeps first)
-        if (p->pre > 2) PM_HIP(ctx, sv.stream_sweeps(0, 0, p->pre - 2, nullptr, nullptr));
+        if (p->pre > 2) PM_HIP(ctx, sv.stream_sweeps(0, 0, p->pre - 2, nullptr));
         PM_HIP(ctx, sv.vcycle(0, true));
       } else {
         PM_HIP(ctx, sv.vcycle(0));

@@ -14,9 +14,6 @@
 // still read the old values of the shared halo. Options:
 //   NORM     sums ||f - L u||^2 and ||f||^2 of the *input* field on the block's
 //            interior (the convergence test of the previous cycle, for free);
-//   PROLONG  adds the trilinear prolongation of the coarse correction to u as it
-//            is loaded (the prolongation-correction step fused into the
-//            post-smoother).
 // k_rr_stream: residual f - L u on the fine grid, restricted to the coarse grid
 // (full weighting (1,3,3,1)/8 per axis, or the 8-child average), in one pass.
 #include "internal.h"
@@ -60,11 +57,11 @@ __device__ void block_pair_to_partial(double s1, double s2, double *partial) {
   }
 }
 
-template <int H, bool NORM, bool PROLONG>
+template <int H, bool NORM>
 __global__ __launch_bounds__(ST) void k_smooth_stream(
     const float *__restrict__ uin, float *__restrict__ uout, const float *__restrict__ f,
-    float fscale, const float *__restrict__ fmean, const float *__restrict__ vc, int n, int ci,
-    float h2, float omega, int first_colour, double *__restrict__ partial) {
+    float fscale, const float *__restrict__ fmean, int n, int ci, float h2, float omega,
+    int first_colour, double *__restrict__ partial) {
   constexpr int RJ = SJ + 2 * H, RK = SK + 2 * H, NP = RJ * RK;
   constexpr int PPT = (NP + ST - 1) / ST;
   __shared__ float lds[H][NP];
@@ -77,13 +74,10 @@ __global__ __launch_bounds__(ST) void k_smooth_stream(
   const float m = fmean ? *fmean : 0.0f;
   const float inv_h2 = 1.0f / h2;
   const size_t nn = (size_t)n * n;
-  const int nc = n >> 1;
 
   int rjv[PPT], rkv[PPT];
   uint32_t colv[PPT];
   bool inside[PPT];
-  // coarse columns for the fused prolongation: (ja, jb) rows and (ka, kb) columns
-  uint32_t cja[PPT], cjb[PPT], cka[PPT], ckb[PPT];
 #pragma unroll
   for (int t = 0; t < PPT; ++t) {
     const int e = threadIdx.x + t * ST;
@@ -91,22 +85,15 @@ __global__ __launch_bounds__(ST) void k_smooth_stream(
     rjv[t] = rj;
     rkv[t] = rk;
     const int gj = j0 - H + rj, gk = k0 - H + rk;
-    const int wjg = wrap_any(gj, n), wkg = wrap_any(gk, n);
-    colv[t] = (e < NP) ? (uint32_t)(wjg * n + wkg) : 0u;
+    colv[t] = (e < NP) ? (uint32_t)(wrap_any(gj, n) * n + wrap_any(gk, n)) : 0u;
     inside[t] = (e < NP) && rj >= H && rj < H + SJ && rk >= H && rk < H + SK && gj < n && gk < n;
-    if constexpr (PROLONG) {
-      cja[t] = (uint32_t)((wjg >> 1) * nc);
-      cjb[t] = (uint32_t)(wrap_any((wjg >> 1) + ((wjg & 1) ? 1 : -1), nc) * nc);
-      cka[t] = (uint32_t)(wkg >> 1);
-      ckb[t] = (uint32_t)wrap_any((wkg >> 1) + ((wkg & 1) ? 1 : -1), nc);
-    }
   }
 
   float ur[H + 2][PPT];   // ur[t] = plane q - (H + 1) + t
   float fr[H + 1][PPT];   // fr[t] = plane q - H + t, already scaled: fscale (f - mean)
   float uo_prev[PPT];     // original values of plane q - 2 (NORM)
-  float nu[PPT], nf[PPT]; // prefetched plane q + 1
-  float cv[PROLONG ? 8 : 1][PPT];  // prefetched coarse values for plane q + 1
+  // two prefetch slots: planes q + 1 and q + 2 are in flight while plane q is worked on
+  float pa_u[PPT], pa_f[PPT], pb_u[PPT], pb_f[PPT];
 #pragma unroll
   for (int a = 0; a < H + 2; ++a)
 #pragma unroll
@@ -116,44 +103,25 @@ __global__ __launch_bounds__(ST) void k_smooth_stream(
 #pragma unroll
     for (int t = 0; t < PPT; ++t) fr[a][t] = 0.f;
 #pragma unroll
-  for (int t = 0; t < PPT; ++t) uo_prev[t] = nu[t] = nf[t] = 0.f;
-#pragma unroll
-  for (int a = 0; a < (PROLONG ? 8 : 1); ++a)
-#pragma unroll
-    for (int t = 0; t < PPT; ++t) cv[a][t] = 0.f;
+  for (int t = 0; t < PPT; ++t) uo_prev[t] = pa_u[t] = pa_f[t] = pb_u[t] = pb_f[t] = 0.f;
 
-  auto prefetch = [&](int q) {
-    const int gq = wrap_any(q, n);
-    const size_t plane = (size_t)gq * nn;
-    size_t ca = 0, cb = 0;
-    if constexpr (PROLONG) {
-      ca = (size_t)(gq >> 1) * nc * nc;
-      cb = (size_t)wrap_any((gq >> 1) + ((gq & 1) ? 1 : -1), nc) * nc * nc;
-    }
+  auto load = [&](int q, float (&pu)[PPT], float (&pf)[PPT]) {
+    const size_t plane = (size_t)wrap_any(q, n) * nn;
 #pragma unroll
     for (int t = 0; t < PPT; ++t) {
       if (rjv[t] >= 0) {
-        nu[t] = uin[plane + colv[t]];
-        nf[t] = f[plane + colv[t]];
-        if constexpr (PROLONG) {
-          cv[0][t] = vc[ca + cja[t] + cka[t]];
-          cv[1][t] = vc[ca + cja[t] + ckb[t]];
-          cv[2][t] = vc[ca + cjb[t] + cka[t]];
-          cv[3][t] = vc[ca + cjb[t] + ckb[t]];
-          cv[4][t] = vc[cb + cja[t] + cka[t]];
-          cv[5][t] = vc[cb + cja[t] + ckb[t]];
-          cv[6][t] = vc[cb + cjb[t] + cka[t]];
-          cv[7][t] = vc[cb + cjb[t] + ckb[t]];
-        }
+        pu[t] = uin[plane + colv[t]];
+        pf[t] = f[plane + colv[t]];
       }
     }
   };
 
   double s_r = 0.0, s_f = 0.0;
   const int qbeg = i0 - H, qend = i0 + ci + H;
-  prefetch(qbeg);
-  for (int q = qbeg; q < qend; ++q) {
-    // rotate the rings and take plane q from the prefetch registers
+
+  // one plane: take plane q from its slot, refill the slot with plane q + 2, then run
+  // the H half-sweeps of the pipeline and retire plane q - H
+  auto step = [&](int q, float (&pu)[PPT], float (&pf)[PPT]) {
 #pragma unroll
     for (int a = 0; a < H + 1; ++a)
 #pragma unroll
@@ -164,19 +132,14 @@ __global__ __launch_bounds__(ST) void k_smooth_stream(
       for (int t = 0; t < PPT; ++t) fr[a][t] = fr[a + 1][t];
 #pragma unroll
     for (int t = 0; t < PPT; ++t) {
-      float uv = nu[t];
-      if constexpr (PROLONG) {
-        // trilinear weights: 3/4 for the nearest coarse centre, 1/4 for the next
-        const float near = 0.75f, far = 0.25f;
-        const float sa = near * (near * cv[0][t] + far * cv[1][t]) + far * (near * cv[2][t] + far * cv[3][t]);
-        const float sb = near * (near * cv[4][t] + far * cv[5][t]) + far * (near * cv[6][t] + far * cv[7][t]);
-        uv += near * sa + far * sb;
-      }
-      ur[H + 1][t] = uv;
-      fr[H][t] = fscale * (nf[t] - m);
+      ur[H + 1][t] = pu[t];
+      fr[H][t] = fscale * (pf[t] - m);
     }
-    if (q + 1 < qend) prefetch(q + 1);
-    // half-sweeps s = 1 .. H on planes q - s
+    if (q + 2 < qend) load(q + 2, pu, pf);
+    // Half-sweep s = 1 .. H runs on plane q - s. Its in-plane neighbours (the other
+    // colour, which half-sweep s does not change) come from LDS slot s - 1 and its
+    // i-neighbours from this thread's registers, so all H planes are published
+    // before one barrier and the stages then run back to back.
 #pragma unroll
     for (int s = 1; s <= H; ++s) {
       const int p = q - s;
@@ -185,7 +148,13 @@ __global__ __launch_bounds__(ST) void k_smooth_stream(
 #pragma unroll
       for (int t = 0; t < PPT; ++t)
         if (rjv[t] >= 0) L[rjv[t] * RK + rkv[t]] = ur[H + 1 - s][t];
-      __syncthreads();
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 1; s <= H; ++s) {
+      const int p = q - s;
+      if (p < i0 - H + s || p >= i0 + ci + H - s) continue;  // uniform across the block
+      const float *L = lds[s - 1];
       const int colour = (first_colour + s - 1) & 1;
 #pragma unroll
       for (int t = 0; t < PPT; ++t) {
@@ -225,8 +194,15 @@ __global__ __launch_bounds__(ST) void k_smooth_stream(
       for (int t = 0; t < PPT; ++t)
         if (inside[t]) uout[op + colv[t]] = ur[1][t];
     }
-    // the LDS slots are rewritten next iteration even when only stage 1 ran here
+    // the LDS slots are rewritten by the next plane
     __syncthreads();
+  };
+
+  load(qbeg, pa_u, pa_f);
+  if (qbeg + 1 < qend) load(qbeg + 1, pb_u, pb_f);
+  for (int q = qbeg; q < qend; q += 2) {
+    step(q, pa_u, pa_f);
+    if (q + 1 < qend) step(q + 1, pb_u, pb_f);
   }
   if constexpr (NORM) block_pair_to_partial<ST>(s_r, s_f, partial);
 }
@@ -385,37 +361,27 @@ int64_t smooth_stream_blocks(int n) {
 }
 
 hipError_t launch_smooth_stream(const float *uin, float *uout, const float *f, float fscale,
-                                const float *fmean, const float *vc, int n, float h2, float omega,
+                                const float *fmean, int n, float h2, float omega,
                                 int first_colour, int half_sweeps, double *partial,
                                 hipStream_t s) {
   const int tj = (n + SJ - 1) / SJ, tk = (n + SK - 1) / SK;
   const int ci = chunk_for(n, tj * tk, 1024, 16);
   dim3 grid(tk, tj, n / ci);
-  const bool norm = partial != nullptr, pro = vc != nullptr;
+  const bool norm = partial != nullptr;
   if (half_sweeps == 4) {
-    if (norm && !pro)
-      k_smooth_stream<4, true, false><<<grid, ST, 0, s>>>(uin, uout, f, fscale, fmean, vc, n, ci, h2,
-                                                          omega, first_colour, partial);
-    else if (!norm && pro)
-      k_smooth_stream<4, false, true><<<grid, ST, 0, s>>>(uin, uout, f, fscale, fmean, vc, n, ci, h2,
-                                                          omega, first_colour, partial);
-    else if (!norm && !pro)
-      k_smooth_stream<4, false, false><<<grid, ST, 0, s>>>(uin, uout, f, fscale, fmean, vc, n, ci,
-                                                           h2, omega, first_colour, partial);
+    if (norm)
+      k_smooth_stream<4, true><<<grid, ST, 0, s>>>(uin, uout, f, fscale, fmean, n, ci, h2, omega,
+                                                   first_colour, partial);
     else
-      return hipErrorInvalidValue;
+      k_smooth_stream<4, false><<<grid, ST, 0, s>>>(uin, uout, f, fscale, fmean, n, ci, h2, omega,
+                                                    first_colour, partial);
   } else if (half_sweeps == 2) {
-    if (norm && !pro)
-      k_smooth_stream<2, true, false><<<grid, ST, 0, s>>>(uin, uout, f, fscale, fmean, vc, n, ci, h2,
-                                                          omega, first_colour, partial);
-    else if (!norm && pro)
-      k_smooth_stream<2, false, true><<<grid, ST, 0, s>>>(uin, uout, f, fscale, fmean, vc, n, ci, h2,
-                                                          omega, first_colour, partial);
-    else if (!norm && !pro)
-      k_smooth_stream<2, false, false><<<grid, ST, 0, s>>>(uin, uout, f, fscale, fmean, vc, n, ci,
-                                                           h2, omega, first_colour, partial);
+    if (norm)
+      k_smooth_stream<2, true><<<grid, ST, 0, s>>>(uin, uout, f, fscale, fmean, n, ci, h2, omega,
+                                                   first_colour, partial);
     else
-      return hipErrorInvalidValue;
+      k_smooth_stream<2, false><<<grid, ST, 0, s>>>(uin, uout, f, fscale, fmean, n, ci, h2, omega,
+                                                    first_colour, partial);
   } else {
     return hipErrorInvalidValue;
   }
