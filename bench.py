@@ -62,6 +62,16 @@ def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# multigrid settings of the benchmark run (the full-size parity test uses the same)
+BENCH_ORDER = "sorted"
+BENCH_TOL = 1e-6
+BENCH_MAX_CYCLES = 40
+
+
+def bench_step_params(pm, order=BENCH_ORDER, tol=BENCH_TOL):
+    return pm.default_step_params(order=order, tol=tol, max_cycles=BENCH_MAX_CYCLES)
+
+
 def make_inputs(n, seed=3, a0=0.02):
     import numpy as np
 
@@ -245,8 +255,8 @@ def main():
     ap.add_argument("--steps", type=int, default=47)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=512)
-    ap.add_argument("--order", default="sorted", choices=["atomic", "sorted"])
-    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--order", default=BENCH_ORDER, choices=["atomic", "sorted"])
+    ap.add_argument("--tol", type=float, default=BENCH_TOL)
     ap.add_argument("--reorder-every", type=int, default=10,
                     help="re-sort particles by tile every this many steps (0: never)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -303,7 +313,7 @@ def main():
     phi = torch.zeros((n, n, n), device=dev)
     acc = torch.empty((npart, 3), device=dev)
     ctx = pm.Context(n, npart)
-    params = pm.default_step_params(order=args.order, tol=args.tol, max_cycles=40)
+    params = bench_step_params(pm, args.order, args.tol)
     torch.cuda.synchronize()
     if args.reorder_every > 0:
         pm.pm_reorder(ctx, off_d, vel=vel_d, cell=cell_d)

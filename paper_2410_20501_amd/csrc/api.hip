@@ -153,7 +153,10 @@ int accel_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, i
   PM_HIP(ctx, launch_gradient(phi, ctx->n, 5, ctx->g, s));
   if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[4], s));
   pm_kt_begin(ctx, PM_KERNEL_INTERP, s);
-  PM_HIP(ctx, launch_interp(pos, cell, np, poskind, p->mas, ctx->n, ctx->g, acc, vel, kick, s));
+  if (p->order == PM_DEPOSIT_SORTED && ctx->n % 8 == 0)  // tile buckets of these positions
+    PM_HIP(ctx, launch_interp_tile(ctx, pos, cell, poskind, p->mas, ctx->g, acc, vel, kick, s));
+  else
+    PM_HIP(ctx, launch_interp(pos, cell, np, poskind, p->mas, ctx->n, ctx->g, acc, vel, kick, s));
   // algorithmic bytes: position (12 B, + 4 B cell index), velocity in/out (24 B),
   // acceleration out (12 B) per particle, and the force grid once (12 B per cell)
   pm_kt_end(ctx, PM_KERNEL_INTERP, s,

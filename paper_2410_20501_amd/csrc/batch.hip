@@ -473,33 +473,56 @@ __global__ __launch_bounds__(kThreads) void kb_restrict(Arenas A, const int2 *__
   }
 }
 
-// u_l += P u_{l+1} (trilinear: 3/4 nearest coarse centre, 1/4 the next, per axis)
+// u_l += P u_{l+1} (trilinear: 3/4 nearest coarse centre, 1/4 the next, per axis);
+// one thread per coarse cell reads its 27 coarse neighbours once and updates its 8
+// fine children (k-pairs as float2)
 __global__ __launch_bounds__(kThreads) void kb_prolong_add(Arenas A, const int2 *__restrict__ items,
                                                            int nitems,
                                                            const BoxDev *__restrict__ boxes,
                                                            int l) {
+  const float near = 0.75f, far = 0.25f;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int2 item = items[it];
     const BoxDev &bx = boxes[item.x];
-    const int n = bx.n >> l, nc = n >> 1;
+    const int n = bx.n >> l, c = n >> 1;
     const unsigned t = (unsigned)item.y * kThreads + threadIdx.x;
-    if (t >= (unsigned)n * n * n) continue;
+    if (t >= (unsigned)c * c * c) continue;
     float *u = l == 0 ? A.phi + bx.c0 : A.lu + bx.lo[l];
     const float *vc = A.lu + bx.lo[l + 1];
-    int i, j, k;
-    decode3(t, (unsigned)n, i, j, k);
-    const int ia = i >> 1, ja = j >> 1, ka = k >> 1;
-    const int ib = wrap_index(ia + ((i & 1) ? 1 : -1), nc);
-    const int jb = wrap_index(ja + ((j & 1) ? 1 : -1), nc);
-    const int kb = wrap_index(ka + ((k & 1) ? 1 : -1), nc);
-    const size_t nn = (size_t)nc * nc;
-    auto at = [&](int x, int y, int z) { return vc[(size_t)x * nn + (size_t)y * nc + z]; };
-    const float near = 0.75f, far = 0.25f;
-    const float sa = near * (near * (near * at(ia, ja, ka) + far * at(ia, ja, kb)) +
-                             far * (near * at(ia, jb, ka) + far * at(ia, jb, kb)));
-    const float sb = far * (near * (near * at(ib, ja, ka) + far * at(ib, ja, kb)) +
-                            far * (near * at(ib, jb, ka) + far * at(ib, jb, kb)));
-    u[t] += sa + sb;
+    int I, J, K;
+    decode3(t, (unsigned)c, I, J, K);
+    const int ix[3] = {wrap_index(I - 1, c), I, wrap_index(I + 1, c)};
+    const int jx[3] = {wrap_index(J - 1, c), J, wrap_index(J + 1, c)};
+    const int kx[3] = {wrap_index(K - 1, c), K, wrap_index(K + 1, c)};
+    float ek[3][3], ok[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const float *row = vc + ((size_t)ix[a] * c + jx[b]) * c;
+        const float vm = row[kx[0]], v0 = row[kx[1]], vp = row[kx[2]];
+        ek[a][b] = near * v0 + far * vm;
+        ok[a][b] = near * v0 + far * vp;
+      }
+    const size_t nn = (size_t)n * n;
+#pragma unroll
+    for (int ai = 0; ai < 2; ++ai) {
+      const int af = ai ? 2 : 0;
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        const int bf = bj ? 2 : 0;
+        const float se = near * (near * ek[1][1] + far * ek[1][bf]) +
+                         far * (near * ek[af][1] + far * ek[af][bf]);
+        const float so = near * (near * ok[1][1] + far * ok[1][bf]) +
+                         far * (near * ok[af][1] + far * ok[af][bf]);
+        float2 *dst = reinterpret_cast<float2 *>(u + (size_t)(2 * I + ai) * nn +
+                                                 (size_t)(2 * J + bj) * n + 2 * K);
+        float2 cur = *dst;
+        cur.x += se;
+        cur.y += so;
+        *dst = cur;
+      }
+    }
   }
 }
 
@@ -757,8 +780,9 @@ int enqueue_accel(pm_batch *B, const float *pos, float *acc, float *vel, float *
     for (int l = B->maxlev - 2; l >= 0; --l) {
       const pm_batch::List &F = B->finer[l];
       if (F.count == 0) continue;
-      kb_prolong_add<<<persist_grid(F.count), kThreads, 0, s>>>(A, B->items + F.off, F.count,
-                                                                B->boxes, l);
+      const pm_batch::List &Cl = B->coarser[l];  // one thread per coarse cell
+      kb_prolong_add<<<persist_grid(Cl.count), kThreads, 0, s>>>(A, B->items + Cl.off, Cl.count,
+                                                                 B->boxes, l);
       sweeps(l, p->mg.post, 1);
     }
   }

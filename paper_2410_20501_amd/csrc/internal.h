@@ -104,6 +104,11 @@ hipError_t launch_deposit_pull(pm_ctx *ctx, const float *pos, int64_t np, int po
                                float mass, float *rho, hipStream_t s);
 hipError_t launch_deposit_own(pm_ctx *ctx, const float *pos, const int32_t *cell, int poskind,
                               int mas, float mass, float *rho, hipStream_t s);
+// interpolation (+ kick) through the tile buckets left by the sorted deposit of the
+// same positions (n % 8 == 0)
+hipError_t launch_interp_tile(pm_ctx *ctx, const float *pos, const int32_t *cell, int poskind,
+                              int mas, const float *g, float *acc, float *vel, float kick,
+                              hipStream_t s);
 hipError_t launch_interp(const float *pos, const int32_t *cell, int64_t np, int poskind, int mas,
                          int n, const float *g, float *acc, float *vel, float kick,
                          hipStream_t s);

@@ -556,6 +556,74 @@ __global__ __launch_bounds__(kThreads) void k_fix_convert(unsigned long long *__
   acc[t] = 0ull;
 }
 
+// Interpolation + kick from particles bucketed by tile (the deposit's sort of the same
+// positions): one workgroup per 8^3 tile stages the force grid of the tile plus a
+// one-cell halo in LDS, then each particle of the tile gathers its 27 (8) window
+// values from LDS instead of from the cache hierarchy.
+template <int MAS, int PK>
+__global__ __launch_bounds__(kOThreads) void k_interp_tile(const float *__restrict__ pos,
+                                                           const int32_t *__restrict__ cell,
+                                                           const int32_t *__restrict__ end,
+                                                           const int32_t *__restrict__ perm,
+                                                           int n, const float *__restrict__ g,
+                                                           float *__restrict__ acc,
+                                                           float *__restrict__ vel, float kick) {
+  __shared__ float gs[3][kTHalo];
+  const int nt = n / kTT;
+  const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
+  const int tk = tile % nt, tj = (tile / nt) % nt, ti = tile / (nt * nt);
+  const int i0 = ti * kTT - 1, j0 = tj * kTT - 1, k0 = tk * kTT - 1;
+  for (int e = threadIdx.x; e < 3 * kTHalo; e += kOThreads) {
+    const int h = e / 3, d = e - 3 * h;
+    const int hx = h / (kTH * kTH), hy = (h / kTH) % kTH, hz = h % kTH;
+    const size_t gc = ((size_t)wrap_index(i0 + hx, n) * n + wrap_index(j0 + hy, n)) * n +
+                      wrap_index(k0 + hz, n);
+    gs[d][h] = g[3 * gc + d];
+  }
+  __syncthreads();
+  const int p_begin = tile > 0 ? end[tile - 1] : 0;
+  const int p_end = end[tile];
+  for (int l = p_begin + (int)threadIdx.x; l < p_end; l += kOThreads) {
+    const int p = perm[l];
+    int c[3];
+    float o[3];
+    particle_cell<PK>(pos, cell, p, n, c, o);
+    const int lx = c[0] - ti * kTT, ly = c[1] - tj * kTT, lz = c[2] - tk * kTT;
+    if ((unsigned)lx >= (unsigned)kTT || (unsigned)ly >= (unsigned)kTT ||
+        (unsigned)lz >= (unsigned)kTT)
+      continue;  // not this tile's particle (cannot happen with the same cell rule)
+    float wx[MAS], wy[MAS], wz[MAS];
+    const int fx = axis_off<MAS>(lx + 1, o[0], wx);
+    const int fy = axis_off<MAS>(ly + 1, o[1], wy);
+    const int fz = axis_off<MAS>(lz + 1, o[2], wz);
+    float ax = 0.f, ay = 0.f, az = 0.f;
+#pragma unroll
+    for (int a = 0; a < MAS; ++a)
+#pragma unroll
+      for (int b = 0; b < MAS; ++b) {
+        const float wab = wx[a] * wy[b];
+        const int row = ((fx + a) * kTH + (fy + b)) * kTH + fz;
+#pragma unroll
+        for (int cc = 0; cc < MAS; ++cc) {
+          const float wc = wab * wz[cc];
+          ax = fmaf(wc, gs[0][row + cc], ax);
+          ay = fmaf(wc, gs[1][row + cc], ay);
+          az = fmaf(wc, gs[2][row + cc], az);
+        }
+      }
+    if (acc) {
+      acc[3 * (size_t)p + 0] = ax;
+      acc[3 * (size_t)p + 1] = ay;
+      acc[3 * (size_t)p + 2] = az;
+    }
+    if (vel) {
+      vel[3 * (size_t)p + 0] = fmaf(kick, ax, vel[3 * (size_t)p + 0]);
+      vel[3 * (size_t)p + 1] = fmaf(kick, ay, vel[3 * (size_t)p + 1]);
+      vel[3 * (size_t)p + 2] = fmaf(kick, az, vel[3 * (size_t)p + 2]);
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_deposit_atomic(const float *pos, const int32_t *cell, int64_t np, int poskind,
@@ -666,6 +734,25 @@ hipError_t launch_deposit_own(pm_ctx *ctx, const float *pos, const int32_t *cell
   }
   k_fix_convert<<<blocks_for(ncell, kThreads), kThreads, 0, s>>>(acc, ncell,
                                                                  (double)mass / 1073741824.0, rho);
+  return hipGetLastError();
+}
+
+hipError_t launch_interp_tile(pm_ctx *ctx, const float *pos, const int32_t *cell, int poskind,
+                              int mas, const float *g, float *acc, float *vel, float kick,
+                              hipStream_t s) {
+  const int n = ctx->n;
+  const unsigned nt = (unsigned)((int64_t)n * n * n / kTThreads);
+#define PM_IT(M, K)                                                                           \
+  k_interp_tile<M, K><<<nt, kOThreads, 0, s>>>(pos, cell, ctx->cell_count, ctx->perm, n, g, acc, \
+                                               vel, kick)
+  if (mas == PM_TSC) {
+    if (poskind == PM_POS_BOX) PM_IT(3, PM_POS_BOX);
+    else PM_IT(3, PM_POS_CELLOFF);
+  } else {
+    if (poskind == PM_POS_BOX) PM_IT(2, PM_POS_BOX);
+    else PM_IT(2, PM_POS_CELLOFF);
+  }
+#undef PM_IT
   return hipGetLastError();
 }
 

@@ -2,8 +2,9 @@
 
 512^3 particles on a 512^3 grid (P(k) ~ k^-1 with a Gaussian cutoff at half the
 Nyquist wavenumber, rms displacement 0.25 cell at a = 0.02), cell-offset
-positions re-sorted by tile, atomic (chunked) deposit, multigrid with the
-growth-rescaled warm start, three kick-drift-kick steps. After the last step:
+positions re-sorted by tile, the benchmark's step parameters (sorted
+deterministic deposit, tile-staged interpolation, multigrid with the
+growth-rescaled warm start), three kick-drift-kick steps. After the last step:
   * potential: whole grid against the oracle's exact seven-point solve of the
     same density (promoted to FP64): relative L2 <= 1e-5;
   * accelerations: 4096 sampled particles against the oracle's 5-point
@@ -44,7 +45,8 @@ def test_bench_configuration_512():
     ctx = pm.Context(n, npart)
     phi = torch.zeros((n, n, n), device="cuda")
     acc = torch.empty((npart, 3), device="cuda")
-    params = pm.default_step_params(max_cycles=40)
+    import bench
+    params = bench.bench_step_params(pm)
     _say("full size 512^3: GPU steps")
     pm.pm_reorder(ctx, off_d, vel=vel_d, cell=cell_d)
     pm.pm_accel(ctx, off_d, 0.02, phi, acc, cell=cell_d, params=params)
