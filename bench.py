@@ -33,12 +33,18 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published peak
 # reports null when the source file's hash differs.
 MEASURED_TRAFFIC = {
     # kernel: (source file, sha256 of it, fetch KiB, write KiB, fetch scale, write scale)
-    "deposit": ("paper_2410_20501_amd/csrc/particles.hip",
-                "bea21cd3b277cd06ba9106044bdfa24dad16a8005e93450a9f2d336fdacd3e74",
-                1708233.0, 524500.0, 2.0, 1.0),
+    # smoother: level-0 passes, mean of the pre- (with residual norm) and post-smoothing
+    # variants weighted by their counts (45 and 39 dispatches)
     "smooth": ("paper_2410_20501_amd/csrc/mg_stream.hip",
-               "6fb24276839515befe30638caa872f63c1058d88d49935d9089f2b2aa944e505",
-               635952.0, 524304.0, 2.0, 1.0),
+               "c2193ec07731a35c9da779ca45a183823c18a103175a27a0574c11df558a8f8b",
+               631973.0, 524305.0, 2.0, 1.0),
+    # deposit: the particle-owned tile kernel plus the fixed-point conversion pass
+    "deposit": ("paper_2410_20501_amd/csrc/particles.hip",
+                "a303b908dd87e96f74a4cb22906b17c8aec36458534352f821c6094d105d461f",
+                1900950.0, 4910737.0, 2.0, 1.0),
+    "interp": ("paper_2410_20501_amd/csrc/particles.hip",
+               "a303b908dd87e96f74a4cb22906b17c8aec36458534352f821c6094d105d461f",
+               3079085.0, 3178662.0, 2.0, 1.0),
 }
 
 
@@ -260,8 +266,9 @@ def main():
     ap.add_argument("--reorder-every", type=int, default=10,
                     help="re-sort particles by tile every this many steps (0: never)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--roofline-kernel", default="deposit", choices=["deposit", "smooth", "interp"],
-                    help="kernel timed with events for the roofline object")
+    ap.add_argument("--roofline-kernel", default="smooth", choices=["deposit", "smooth", "interp"],
+                    help="kernel timed with events for the roofline object (default: the "
+                         "streaming smoother on the finest grid, the largest share of kernel time)")
     ap.add_argument("--stage-log", action="store_true",
                     help="record per-stage times of every timed step (adds events)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -336,7 +343,7 @@ def main():
     stage_rows = []
     if args.stage_log:
         params.timing = 1
-    pm.pm_kernel_timer(ctx, args.roofline_kernel, capacity=8192)
+    pm.pm_kernel_timer(ctx, args.roofline_kernel, capacity=16384)
     t0 = time.perf_counter()
     for i in range(args.steps):
         if args.reorder_every > 0 and step % args.reorder_every == 0:

@@ -190,6 +190,10 @@ __device__ __forceinline__ WaveRun wave_runs(int key) {
 
 // Sort keys: 0 = row-major cell, 1 = tile-major cell, 2 = 8^3-cell tile.
 constexpr int kKeyCell = 0, kKeyTileCell = 1, kKeyTile = 2;
+// Every wave of the histogram and scatter kernels handles kSortRounds runs of 64
+// consecutive particles; the scatter issues the cursor atomics of all rounds before it
+// needs their results, so their latencies overlap.
+constexpr int kSortRounds = 4;
 
 // Key of each particle's cell; histogram with one atomic per run of equal keys in a
 // wave (particles that are neighbours in memory mostly share keys).
@@ -199,32 +203,38 @@ __global__ __launch_bounds__(kThreads) void k_cell_hist(const float *__restrict_
                                                         int64_t np, int n,
                                                         int32_t *__restrict__ pcell,
                                                         int32_t *__restrict__ count) {
-  const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  int c = -1;
-  if (p < np) {
-    int q[3];
-    if constexpr (PK == PM_POS_BOX) {
-      const float fn = (float)n;
+  const int lane = threadIdx.x & 63;
+  const int64_t wbase =
+      ((int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6)) * 64 * kSortRounds;
 #pragma unroll
-      for (int d = 0; d < 3; ++d) q[d] = wrap_any((int)floorf(pos[3 * p + d] * fn), n);
-    } else {
-      const int cc = wrap_any(cell[p], n * n * n);
-      q[0] = cc / (n * n);
-      q[1] = (cc / n) - q[0] * n;
-      q[2] = cc - (cc / n) * n;
+  for (int m = 0; m < kSortRounds; ++m) {
+    const int64_t p = wbase + m * 64 + lane;
+    int c = -1;
+    if (p < np) {
+      int q[3];
+      if constexpr (PK == PM_POS_BOX) {
+        const float fn = (float)n;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) q[d] = wrap_any((int)floorf(pos[3 * p + d] * fn), n);
+      } else {
+        const int cc = wrap_any(cell[p], n * n * n);
+        q[0] = cc / (n * n);
+        q[1] = (cc / n) - q[0] * n;
+        q[2] = cc - (cc / n) * n;
+      }
+      if constexpr (KEY == kKeyTileCell) {
+        c = tile_key(q[0], q[1], q[2], n);
+      } else if constexpr (KEY == kKeyTile) {
+        const int nt = n >> 3;
+        c = ((q[0] >> 3) * nt + (q[1] >> 3)) * nt + (q[2] >> 3);
+      } else {
+        c = (q[0] * n + q[1]) * n + q[2];
+      }
+      pcell[p] = c;
     }
-    if constexpr (KEY == kKeyTileCell) {
-      c = tile_key(q[0], q[1], q[2], n);
-    } else if constexpr (KEY == kKeyTile) {
-      const int nt = n >> 3;
-      c = ((q[0] >> 3) * nt + (q[1] >> 3)) * nt + (q[2] >> 3);
-    } else {
-      c = (q[0] * n + q[1]) * n + q[2];
-    }
-    pcell[p] = c;
+    const WaveRun r = wave_runs(c);
+    if (r.head && c >= 0) atomicAdd(&count[c], r.len);
   }
-  const WaveRun r = wave_runs(c);
-  if (r.head && c >= 0) atomicAdd(&count[c], r.len);
 }
 
 // dst[p] = src[perm[p]] for W elements of type T per particle.
@@ -255,13 +265,27 @@ __global__ __launch_bounds__(kThreads) void k_scatter_perm(const int32_t *__rest
                                                            int64_t np,
                                                            int32_t *__restrict__ cursor,
                                                            int32_t *__restrict__ perm) {
-  const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  const int c = p < np ? pcell[p] : -1;
-  const WaveRun r = wave_runs(c);
-  int base = 0;
-  if (r.head && c >= 0) base = atomicAdd(&cursor[c], r.len);
-  base = __shfl(base, r.headlane, 64);
-  if (c >= 0) perm[base + ((int)(threadIdx.x & 63) - r.headlane)] = (int32_t)p;
+  const int lane = threadIdx.x & 63;
+  const int64_t wbase =
+      ((int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6)) * 64 * kSortRounds;
+  int c[kSortRounds], base[kSortRounds], head[kSortRounds];
+#pragma unroll
+  for (int m = 0; m < kSortRounds; ++m) {
+    const int64_t p = wbase + m * 64 + lane;
+    c[m] = p < np ? pcell[p] : -1;
+  }
+#pragma unroll
+  for (int m = 0; m < kSortRounds; ++m) {
+    const WaveRun r = wave_runs(c[m]);
+    head[m] = r.headlane;
+    base[m] = 0;
+    if (r.head && c[m] >= 0) base[m] = atomicAdd(&cursor[c[m]], r.len);
+  }
+#pragma unroll
+  for (int m = 0; m < kSortRounds; ++m) {
+    const int b = __shfl(base[m], head[m], 64);
+    if (c[m] >= 0) perm[b + (lane - head[m])] = (int32_t)(wbase + m * 64 + lane);
+  }
 }
 
 // Exclusive scan of `count` (len entries) into `start`, in three passes.
@@ -683,9 +707,9 @@ hipError_t launch_sort_by_cell(pm_ctx *ctx, const float *pos, const int32_t *cel
   hipError_t e = hipMemsetAsync(ctx->cell_count, 0, sizeof(int32_t) * len, s);
   if (e != hipSuccess) return e;
   if (np > 0) {
-    const unsigned nb = blocks_for(np, kThreads);
+    const unsigned nbr = blocks_for(np, kThreads * kSortRounds);
 #define PM_HIST(PKV, KEYV)                                                                   \
-  k_cell_hist<PKV, KEYV><<<nb, kThreads, 0, s>>>(pos, cell, np, n, ctx->pcell, ctx->cell_count)
+  k_cell_hist<PKV, KEYV><<<nbr, kThreads, 0, s>>>(pos, cell, np, n, ctx->pcell, ctx->cell_count)
     if (poskind == PM_POS_BOX) {
       if (keymode == kKeyTile) PM_HIST(PM_POS_BOX, kKeyTile);
       else if (keymode == kKeyTileCell) PM_HIST(PM_POS_BOX, kKeyTileCell);
@@ -704,7 +728,7 @@ hipError_t launch_sort_by_cell(pm_ctx *ctx, const float *pos, const int32_t *cel
   // advances it to the end of cell c (= start of c + 1), the layout the gathers read
   k_scan_apply<<<nblk, kScanThreads, 0, s>>>(ctx->cell_count, len, ctx->scan_partial);
   if (np > 0)
-    k_scatter_perm<<<blocks_for(np, kThreads), kThreads, 0, s>>>(ctx->pcell, np,
+    k_scatter_perm<<<blocks_for(np, kThreads * kSortRounds), kThreads, 0, s>>>(ctx->pcell, np,
                                                                   ctx->cell_count, ctx->perm);
   return hipGetLastError();
 }

@@ -127,7 +127,11 @@ def test_deposit_clustered(lib, mas, order):
     ref = opm.deposit(opm.cell_units(n, pos=pos), n, mas)
     got = host(rho)
     assert ref.max() > 100.0
-    assert np.abs(got - ref).max() <= 2e-6 * ref.max()
+    # sorted: exact integer sums, one FP32 rounding per cell. atomic: particles in random
+    # order fall back to FP32 global atomics, and a dense cell sums k ~ 1500 weights in
+    # an arbitrary order: a statistical bound of 3 sqrt(k) u ~ 7e-6 of the cell's value
+    tol = 2e-6 if order == "sorted" else 8e-6
+    assert np.abs(got - ref).max() <= tol * ref.max()
     assert abs(got.sum() - n ** 3) <= 1e-6 * n ** 3
 
 
