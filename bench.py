@@ -245,13 +245,14 @@ def stage_bytes(npart, ncell, cycles):
     """Algorithmic HBM bytes of each stage of one step at cell-offset positions (the
     minimum each stage's kernels must move; multigrid: the level-0 passes of the fused
     V-cycle, two smoothing passes of 12 B/cell, residual-restriction 8 B/cell and
-    prolongation 8 B/cell, times 8/7 for the coarser levels)."""
+    prolongation 8 B/cell, times 8/7 for the coarser levels). With the sorted deposit
+    the gradient is formed inside the interpolation kernel, which then reads the
+    potential (4 B/cell) instead of the force grid; the gradient stage is empty."""
     return {
         "ms_drift": 68.0 * npart,
         "ms_deposit": 16.0 * npart + 4.0 * ncell,
         "ms_solve": cycles * 40.0 * ncell * 8.0 / 7.0,
-        "ms_gradient": 16.0 * ncell,
-        "ms_interp": 52.0 * npart + 12.0 * ncell,
+        "ms_interp": 52.0 * npart + 4.0 * ncell,
     }
 
 

@@ -117,7 +117,9 @@ int deposit_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np,
       }
       PM_HIP(ctx, hipMemsetAsync(ctx->fix_grid, 0, sizeof(unsigned long long) * (size_t)ncell, s));
     }
-    PM_HIP(ctx, launch_sort_by_cell(ctx, pos, cell, np, poskind, s, tiles ? 2 : 0));
+    const bool hist = tiles && ctx->hist_ready;
+    ctx->hist_ready = false;
+    PM_HIP(ctx, launch_sort_by_cell(ctx, pos, cell, np, poskind, s, tiles ? 2 : 0, hist));
     pm_kt_begin(ctx, PM_KERNEL_DEPOSIT, s);
     if (tiles)
       PM_HIP(ctx, launch_deposit_own(ctx, pos, cell, poskind, mas, mass, rho, s));
@@ -150,18 +152,22 @@ int accel_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, i
   const int sst = solve_impl(ctx, p, ctx->rho, coef, phi, stats ? &stats->mg : nullptr, s, warm_scale);
   if (sst < 0) return sst;
   if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[3], s));
-  PM_HIP(ctx, launch_gradient(phi, ctx->n, 5, ctx->g, s));
+  // with the tile buckets of these positions (sorted deposit on tiles), the gradient is
+  // formed per tile inside the interpolation kernel
+  const bool tiles = p->order == PM_DEPOSIT_SORTED && ctx->n % 8 == 0;
+  if (!tiles) PM_HIP(ctx, launch_gradient(phi, ctx->n, 5, ctx->g, s));
   if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[4], s));
   pm_kt_begin(ctx, PM_KERNEL_INTERP, s);
-  if (p->order == PM_DEPOSIT_SORTED && ctx->n % 8 == 0)  // tile buckets of these positions
-    PM_HIP(ctx, launch_interp_tile(ctx, pos, cell, poskind, p->mas, ctx->g, acc, vel, kick, s));
+  if (tiles)
+    PM_HIP(ctx, launch_interp_tile_phi(ctx, pos, cell, poskind, p->mas, phi, acc, vel, kick, s));
   else
     PM_HIP(ctx, launch_interp(pos, cell, np, poskind, p->mas, ctx->n, ctx->g, acc, vel, kick, s));
   // algorithmic bytes: position (12 B, + 4 B cell index), velocity in/out (24 B),
-  // acceleration out (12 B) per particle, and the force grid once (12 B per cell)
+  // acceleration out (12 B) per particle, and the force grid once (12 B per cell) or,
+  // with the gradient fused, the potential once (4 B per cell)
   pm_kt_end(ctx, PM_KERNEL_INTERP, s,
             (double)np * (48.0 + (poskind == PM_POS_CELLOFF ? 4.0 : 0.0)) +
-                12.0 * (double)ctx->n * ctx->n * ctx->n);
+                (tiles ? 4.0 : 12.0) * (double)ctx->n * ctx->n * ctx->n);
   if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[5], s));
   return sst;
 }
@@ -470,7 +476,21 @@ int pm_kdk(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, int64_t np, int p
   const double tau = 2.0 * (1.0 / std::sqrt(a0) - 1.0 / std::sqrt(a1));
   const float half = (float)(0.5 * tau);
   if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[0], s));
-  PM_HIP(ctx, launch_kick_drift(pos, cell, vel, acc, np, poskind, ctx->n, half, (float)tau, s));
+  // with the sorted deposit on tiles, the drift also makes the tile histogram of the new
+  // positions (the first pass of the deposit's sort)
+  const bool fuse_hist = params->order == PM_DEPOSIT_SORTED && ctx->n % 8 == 0 && np > 0;
+  int32_t *pcell = nullptr, *count = nullptr;
+  if (fuse_hist) {
+    st = ensure_sort_scratch(ctx, np);
+    if (st != PM_OK) return st;
+    const int64_t ntiles = (int64_t)(ctx->n / 8) * (ctx->n / 8) * (ctx->n / 8);
+    PM_HIP(ctx, hipMemsetAsync(ctx->cell_count, 0, sizeof(int32_t) * (size_t)(ntiles + 1), s));
+    pcell = ctx->pcell;
+    count = ctx->cell_count;
+  }
+  PM_HIP(ctx, launch_kick_drift(pos, cell, vel, acc, np, poskind, ctx->n, half, (float)tau, s,
+                                pcell, count));
+  ctx->hist_ready = fuse_hist;
   // growth rescaling of the previous potential: phi~ grows as a D(a) = a^2 in EdS
   const float warm_scale =
       params->mg.guess == PM_GUESS_WARM_RESCALED ? (float)((a1 / a0) * (a1 / a0)) : 1.0f;

@@ -51,6 +51,7 @@ struct pm_ctx {
   int64_t sort_cap;
   void *reorder_tmp;     // [np_max * 12 bytes] permutation staging (lazy)
   unsigned long long *fix_grid;  // [n^3] 2^-30 fixed-point density (sorted deposit, lazy, kept zero)
+  bool hist_ready;       // tile histogram and keys of the current positions already made
   int64_t reorder_cap;
   // reverse mode (lazy)
   float *adj_gbar;       // [n^3 * 3] cotangent of the force grid
@@ -95,9 +96,10 @@ int pm_hip_check(pm_ctx *ctx, hipError_t e, const char *what);
 // particles.hip
 hipError_t launch_deposit_atomic(const float *pos, const int32_t *cell, int64_t np, int poskind,
                                  int mas, int n, float mass, float *rho, hipStream_t s);
-// keymode: 0 row-major cells, 1 tile-major cells (n % 8 == 0), 2 tiles of 8^3 cells
+// keymode: 0 row-major cells, 1 tile-major cells (n % 8 == 0), 2 tiles of 8^3 cells;
+// hist_done: the counts and keys were already made (by the fused kick-drift)
 hipError_t launch_sort_by_cell(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np,
-                               int poskind, hipStream_t s, int keymode);
+                               int poskind, hipStream_t s, int keymode, bool hist_done = false);
 hipError_t launch_apply_perm(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, float *acc,
                              int64_t *ids, int64_t np, hipStream_t s);
 hipError_t launch_deposit_pull(pm_ctx *ctx, const float *pos, int64_t np, int poskind, int mas,
@@ -109,11 +111,16 @@ hipError_t launch_deposit_own(pm_ctx *ctx, const float *pos, const int32_t *cell
 hipError_t launch_interp_tile(pm_ctx *ctx, const float *pos, const int32_t *cell, int poskind,
                               int mas, const float *g, float *acc, float *vel, float kick,
                               hipStream_t s);
+// the same with the 5-point gradient of phi formed per tile in LDS (no force grid)
+hipError_t launch_interp_tile_phi(pm_ctx *ctx, const float *pos, const int32_t *cell,
+                                  int poskind, int mas, const float *phi, float *acc, float *vel,
+                                  float kick, hipStream_t s);
 hipError_t launch_interp(const float *pos, const int32_t *cell, int64_t np, int poskind, int mas,
                          int n, const float *g, float *acc, float *vel, float kick,
                          hipStream_t s);
 hipError_t launch_kick_drift(float *pos, int32_t *cell, float *vel, const float *acc, int64_t np,
-                             int poskind, int n, float kick, float dt, hipStream_t s);
+                             int poskind, int n, float kick, float dt, hipStream_t s,
+                             int32_t *pcell = nullptr, int32_t *count = nullptr);
 
 // adjoint.hip
 hipError_t launch_deposit_vjp(const float *pos, const int32_t *cell, int64_t np, int poskind,

@@ -108,63 +108,6 @@ __device__ __forceinline__ float wrap_unit(float x) {
   return (x >= 1.0f) ? 0.0f : x;
 }
 
-// v += kick * acc (when acc != NULL); x += dt * v, wrapped (box) or carried (cell offset).
-template <int PK>
-__global__ __launch_bounds__(kThreads) void k_kick_drift(float *__restrict__ pos,
-                                                         int32_t *__restrict__ cell,
-                                                         float *__restrict__ vel,
-                                                         const float *__restrict__ acc,
-                                                         int64_t np, int n, float kick,
-                                                         float dt) {
-  const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (p >= np) return;
-  float v[3], x[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    v[d] = vel[3 * p + d];
-    if (acc) v[d] = fmaf(kick, acc[3 * p + d], v[d]);
-    x[d] = pos[3 * p + d];
-  }
-  if constexpr (PK == PM_POS_BOX) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) x[d] = wrap_unit(fmaf(dt, v[d], x[d]));
-  } else {
-    const float scale = dt * (float)n;
-    const int c = wrap_any(cell[p], n * n * n);
-    const int nn = n * n;
-    int ci[3] = {c / nn, (c / n) - (c / nn) * n, c - (c / n) * n};
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      float o = fmaf(scale, v[d], x[d]);
-      float fl = floorf(o);
-      o -= fl;
-      if (o >= 1.0f) {
-        o = 0.0f;
-        fl += 1.0f;
-      }
-      int q = (ci[d] + (int)fl) % n;
-      ci[d] = q < 0 ? q + n : q;
-      x[d] = o;
-    }
-    cell[p] = (ci[0] * n + ci[1]) * n + ci[2];
-  }
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    vel[3 * p + d] = v[d];
-    pos[3 * p + d] = x[d];
-  }
-}
-
-// ------------------------------------------------------------------ counting sort
-
-// Tile-major cell key: 8^3-cell tiles in row-major order, cells row-major inside
-// a tile (a bijection of [0, n^3) when n is a multiple of 8).
-__device__ __forceinline__ int tile_key(int ci, int cj, int ck, int n) {
-  const int nt = n >> 3;
-  return ((((ci >> 3) * nt + (cj >> 3)) * nt + (ck >> 3)) << 9) +
-         ((((ci & 7) << 3) + (cj & 7)) << 3) + (ck & 7);
-}
-
 // Runs of equal keys among the lanes of a wave (particles that are neighbours in
 // memory often share a cell): head lanes start a run; run length and head lane
 // of every lane come from the ballot of heads.
@@ -186,6 +129,87 @@ __device__ __forceinline__ WaveRun wave_runs(int key) {
   const unsigned long long upto = heads & ((lane == 63) ? ~0ull : ((2ull << lane) - 1ull));
   r.headlane = 63 - __clzll((long long)upto);
   return r;
+}
+
+// v += kick * acc (when acc != NULL); x += dt * v, wrapped (box) or carried (cell offset).
+// With count != NULL the kernel also does the first pass of the deposit's tile sort
+// for the new positions: the particle's 8^3-tile key goes to pcell and the tile
+// histogram gets one atomic per run of equal keys in a wave (same key rule as
+// k_cell_hist), which saves that kernel's re-read of the particles.
+template <int PK>
+__global__ __launch_bounds__(kThreads) void k_kick_drift(float *__restrict__ pos,
+                                                         int32_t *__restrict__ cell,
+                                                         float *__restrict__ vel,
+                                                         const float *__restrict__ acc,
+                                                         int64_t np, int n, float kick,
+                                                         float dt, int32_t *__restrict__ pcell,
+                                                         int32_t *__restrict__ count) {
+  const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const bool live = p < np;
+  int key = -1;
+  if (live) {
+    float v[3], x[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      v[d] = vel[3 * p + d];
+      if (acc) v[d] = fmaf(kick, acc[3 * p + d], v[d]);
+      x[d] = pos[3 * p + d];
+    }
+    int ci[3];
+    if constexpr (PK == PM_POS_BOX) {
+      const float fn = (float)n;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        x[d] = wrap_unit(fmaf(dt, v[d], x[d]));
+        ci[d] = wrap_any((int)floorf(x[d] * fn), n);
+      }
+    } else {
+      const float scale = dt * (float)n;
+      const int c = wrap_any(cell[p], n * n * n);
+      const int nn = n * n;
+      ci[0] = c / nn;
+      ci[1] = (c / n) - (c / nn) * n;
+      ci[2] = c - (c / n) * n;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        float o = fmaf(scale, v[d], x[d]);
+        float fl = floorf(o);
+        o -= fl;
+        if (o >= 1.0f) {
+          o = 0.0f;
+          fl += 1.0f;
+        }
+        int q = (ci[d] + (int)fl) % n;
+        ci[d] = q < 0 ? q + n : q;
+        x[d] = o;
+      }
+      cell[p] = (ci[0] * n + ci[1]) * n + ci[2];
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      vel[3 * p + d] = v[d];
+      pos[3 * p + d] = x[d];
+    }
+    if (count) {
+      const int nt = n >> 3;
+      key = ((ci[0] >> 3) * nt + (ci[1] >> 3)) * nt + (ci[2] >> 3);
+      pcell[p] = key;
+    }
+  }
+  if (count) {  // uniform: the whole wave takes part in the run detection
+    const WaveRun r = wave_runs(key);
+    if (r.head && key >= 0) atomicAdd(&count[key], r.len);
+  }
+}
+
+// ------------------------------------------------------------------ counting sort
+
+// Tile-major cell key: 8^3-cell tiles in row-major order, cells row-major inside
+// a tile (a bijection of [0, n^3) when n is a multiple of 8).
+__device__ __forceinline__ int tile_key(int ci, int cj, int ck, int n) {
+  const int nt = n >> 3;
+  return ((((ci >> 3) * nt + (cj >> 3)) * nt + (ck >> 3)) << 9) +
+         ((((ci & 7) << 3) + (cj & 7)) << 3) + (ck & 7);
 }
 
 // Sort keys: 0 = row-major cell, 1 = tile-major cell, 2 = 8^3-cell tile.
@@ -648,6 +672,89 @@ __global__ __launch_bounds__(kOThreads) void k_interp_tile(const float *__restri
   }
 }
 
+// Gradient and interpolation in one pass: the tile's potential plus a three-cell halo
+// is staged in LDS, g = -grad phi (5-point central difference, same arithmetic as the
+// gradient kernel) is formed for the tile plus a one-cell halo, and the particles
+// gather from it; the force grid never goes to memory.
+template <int MAS, int PK>
+__global__ __launch_bounds__(kOThreads) void k_interp_tile_phi(const float *__restrict__ pos,
+                                                               const int32_t *__restrict__ cell,
+                                                               const int32_t *__restrict__ end,
+                                                               const int32_t *__restrict__ perm,
+                                                               int n,
+                                                               const float *__restrict__ phi,
+                                                               float *__restrict__ acc,
+                                                               float *__restrict__ vel,
+                                                               float kick) {
+  constexpr int PH = kTT + 6;  // tile + 3 cells per side
+  __shared__ float ps[PH * PH * PH];
+  __shared__ float gs[3][kTHalo];
+  const int nt = n / kTT;
+  const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
+  const int tk = tile % nt, tj = (tile / nt) % nt, ti = tile / (nt * nt);
+  const int i0 = ti * kTT - 3, j0 = tj * kTT - 3, k0 = tk * kTT - 3;
+  for (int e = threadIdx.x; e < PH * PH * PH; e += kOThreads) {
+    const int hx = e / (PH * PH), hy = (e / PH) % PH, hz = e % PH;
+    ps[e] = phi[((size_t)wrap_index(i0 + hx, n) * n + wrap_index(j0 + hy, n)) * n +
+                wrap_index(k0 + hz, n)];
+  }
+  __syncthreads();
+  const float c1 = 2.0f / 3.0f, c2 = -1.0f / 12.0f, inv_h = (float)n;
+  for (int h = threadIdx.x; h < kTHalo; h += kOThreads) {
+    const int cx = h / (kTH * kTH) + 2, cy = (h / kTH) % kTH + 2, cz = h % kTH + 2;
+    const int c = (cx * PH + cy) * PH + cz;
+    float gx = c1 * (ps[c + PH * PH] - ps[c - PH * PH]);
+    gx = fmaf(c2, ps[c + 2 * PH * PH] - ps[c - 2 * PH * PH], gx);
+    float gy = c1 * (ps[c + PH] - ps[c - PH]);
+    gy = fmaf(c2, ps[c + 2 * PH] - ps[c - 2 * PH], gy);
+    float gz = c1 * (ps[c + 1] - ps[c - 1]);
+    gz = fmaf(c2, ps[c + 2] - ps[c - 2], gz);
+    gs[0][h] = -inv_h * gx;
+    gs[1][h] = -inv_h * gy;
+    gs[2][h] = -inv_h * gz;
+  }
+  __syncthreads();
+  const int p_begin = tile > 0 ? end[tile - 1] : 0;
+  const int p_end = end[tile];
+  for (int l = p_begin + (int)threadIdx.x; l < p_end; l += kOThreads) {
+    const int p = perm[l];
+    int c[3];
+    float o[3];
+    particle_cell<PK>(pos, cell, p, n, c, o);
+    const int lx = c[0] - ti * kTT, ly = c[1] - tj * kTT, lz = c[2] - tk * kTT;
+    if ((unsigned)lx >= (unsigned)kTT || (unsigned)ly >= (unsigned)kTT ||
+        (unsigned)lz >= (unsigned)kTT)
+      continue;  // not this tile's particle (cannot happen with the same cell rule)
+    float wx[MAS], wy[MAS], wz[MAS];
+    const int fx = axis_off<MAS>(lx + 1, o[0], wx);
+    const int fy = axis_off<MAS>(ly + 1, o[1], wy);
+    const int fz = axis_off<MAS>(lz + 1, o[2], wz);
+    float ax = 0.f, ay = 0.f, az = 0.f;
+#pragma unroll
+    for (int a = 0; a < MAS; ++a)
+#pragma unroll
+      for (int b = 0; b < MAS; ++b) {
+        const float wab = wx[a] * wy[b];
+        const int row = ((fx + a) * kTH + (fy + b)) * kTH + fz;
+#pragma unroll
+        for (int cc = 0; cc < MAS; ++cc) {
+          const float wc = wab * wz[cc];
+          ax = fmaf(wc, gs[0][row + cc], ax);
+          ay = fmaf(wc, gs[1][row + cc], ay);
+          az = fmaf(wc, gs[2][row + cc], az);
+        }
+      }
+    acc[3 * (size_t)p + 0] = ax;
+    acc[3 * (size_t)p + 1] = ay;
+    acc[3 * (size_t)p + 2] = az;
+    if (vel) {
+      vel[3 * (size_t)p + 0] = fmaf(kick, ax, vel[3 * (size_t)p + 0]);
+      vel[3 * (size_t)p + 1] = fmaf(kick, ay, vel[3 * (size_t)p + 1]);
+      vel[3 * (size_t)p + 2] = fmaf(kick, az, vel[3 * (size_t)p + 2]);
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_deposit_atomic(const float *pos, const int32_t *cell, int64_t np, int poskind,
@@ -688,25 +795,30 @@ hipError_t launch_interp(const float *pos, const int32_t *cell, int64_t np, int 
 }
 
 hipError_t launch_kick_drift(float *pos, int32_t *cell, float *vel, const float *acc, int64_t np,
-                             int poskind, int n, float kick, float dt, hipStream_t s) {
+                             int poskind, int n, float kick, float dt, hipStream_t s,
+                             int32_t *pcell, int32_t *count) {
   if (np == 0) return hipSuccess;
   const unsigned nb = blocks_for(np, kThreads);
   if (poskind == PM_POS_BOX)
-    k_kick_drift<PM_POS_BOX><<<nb, kThreads, 0, s>>>(pos, cell, vel, acc, np, n, kick, dt);
+    k_kick_drift<PM_POS_BOX><<<nb, kThreads, 0, s>>>(pos, cell, vel, acc, np, n, kick, dt, pcell,
+                                                      count);
   else
-    k_kick_drift<PM_POS_CELLOFF><<<nb, kThreads, 0, s>>>(pos, cell, vel, acc, np, n, kick, dt);
+    k_kick_drift<PM_POS_CELLOFF><<<nb, kThreads, 0, s>>>(pos, cell, vel, acc, np, n, kick, dt,
+                                                          pcell, count);
   return hipGetLastError();
 }
 
 hipError_t launch_sort_by_cell(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np,
-                               int poskind, hipStream_t s, int keymode) {
+                               int poskind, hipStream_t s, int keymode, bool hist_done) {
   const int n = ctx->n;
   const int64_t nkeys = keymode == kKeyTile ? (int64_t)(n / 8) * (n / 8) * (n / 8)
                                             : (int64_t)n * n * n;
   const int64_t len = nkeys + 1;
-  hipError_t e = hipMemsetAsync(ctx->cell_count, 0, sizeof(int32_t) * len, s);
-  if (e != hipSuccess) return e;
-  if (np > 0) {
+  if (!hist_done) {
+    hipError_t e = hipMemsetAsync(ctx->cell_count, 0, sizeof(int32_t) * len, s);
+    if (e != hipSuccess) return e;
+  }
+  if (np > 0 && !hist_done) {
     const unsigned nbr = blocks_for(np, kThreads * kSortRounds);
 #define PM_HIST(PKV, KEYV)                                                                   \
   k_cell_hist<PKV, KEYV><<<nbr, kThreads, 0, s>>>(pos, cell, np, n, ctx->pcell, ctx->cell_count)
@@ -777,6 +889,25 @@ hipError_t launch_interp_tile(pm_ctx *ctx, const float *pos, const int32_t *cell
     else PM_IT(2, PM_POS_CELLOFF);
   }
 #undef PM_IT
+  return hipGetLastError();
+}
+
+hipError_t launch_interp_tile_phi(pm_ctx *ctx, const float *pos, const int32_t *cell,
+                                  int poskind, int mas, const float *phi, float *acc, float *vel,
+                                  float kick, hipStream_t s) {
+  const int n = ctx->n;
+  const unsigned nt = (unsigned)((int64_t)n * n * n / kTThreads);
+#define PM_ITP(M, K)                                                                          \
+  k_interp_tile_phi<M, K><<<nt, kOThreads, 0, s>>>(pos, cell, ctx->cell_count, ctx->perm, n, phi, \
+                                                   acc, vel, kick)
+  if (mas == PM_TSC) {
+    if (poskind == PM_POS_BOX) PM_ITP(3, PM_POS_BOX);
+    else PM_ITP(3, PM_POS_CELLOFF);
+  } else {
+    if (poskind == PM_POS_BOX) PM_ITP(2, PM_POS_BOX);
+    else PM_ITP(2, PM_POS_CELLOFF);
+  }
+#undef PM_ITP
   return hipGetLastError();
 }
 
