@@ -37,14 +37,15 @@ MEASURED_TRAFFIC = {
     # variants weighted by their counts (45 and 39 dispatches)
     "smooth": ("paper_2410_20501_amd/csrc/mg_stream.hip",
                "c2193ec07731a35c9da779ca45a183823c18a103175a27a0574c11df558a8f8b",
-               631973.0, 524305.0, 2.0, 1.0),
+               630995.0, 524305.0, 2.0, 1.0),
     # deposit: the particle-owned tile kernel plus the fixed-point conversion pass
     "deposit": ("paper_2410_20501_amd/csrc/particles.hip",
-                "a303b908dd87e96f74a4cb22906b17c8aec36458534352f821c6094d105d461f",
-                1900950.0, 4910737.0, 2.0, 1.0),
+                "6e5d52c671c806c62c41b16a7f5c480f0c5ce1ef786455aeb3fd0facbcbb0a9f",
+                1900958.0, 4910737.0, 2.0, 1.0),
+    # interpolation with the fused gradient (tile-staged)
     "interp": ("paper_2410_20501_amd/csrc/particles.hip",
-               "a303b908dd87e96f74a4cb22906b17c8aec36458534352f821c6094d105d461f",
-               3079085.0, 3178662.0, 2.0, 1.0),
+               "6e5d52c671c806c62c41b16a7f5c480f0c5ce1ef786455aeb3fd0facbcbb0a9f",
+               2544928.0, 3129702.0, 2.0, 1.0),
 }
 
 
