@@ -302,6 +302,7 @@ void pm_destroy(pm_ctx *ctx) {
       fr(ctx->lev[l].f);
     }
     fr(ctx->lev[l].alt);
+    fr(ctx->lev[l].res);
   }
   fr(ctx->spec);
   fr(ctx->twiddle);

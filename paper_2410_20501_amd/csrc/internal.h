@@ -16,9 +16,12 @@ struct pm_level {
   float *u;       // solution / error (level 0: caller's phi)
   float *f;       // right-hand side (level 0: NULL, the source is read from rho)
   float *alt;     // second buffer for the out-of-place streaming smoother (or NULL)
+  float *res;     // residual scratch of the two-pass restriction (levels below streaming)
 };
 
-#define PM_STREAM_MIN_N 128   // levels at least this large use the streaming kernels
+#ifndef PM_STREAM_MIN_N
+#define PM_STREAM_MIN_N 256   // levels at least this large use the streaming kernels
+#endif
 
 struct pm_ctx {
   int n;
@@ -155,8 +158,11 @@ int64_t smooth_stream_blocks(int n);
 hipError_t launch_smooth_stream(const float *uin, float *uout, const float *f, float fscale,
                                 const float *fmean, int n, float h2, float omega,
                                 int first_colour, int half_sweeps, double *partial, hipStream_t s);
+// residual + restriction in one streaming pass; with ucg != NULL also the coarse
+// starting guess ucg = gscale * fc
 hipError_t launch_rr_stream(const float *u, const float *f, float fscale, const float *fmean,
-                            int n, float inv_h2, int kind, float *fc, hipStream_t s);
+                            int n, float inv_h2, int kind, float *fc, float *ucg, float gscale,
+                            hipStream_t s);
 
 // fft.hip
 int pm_fft_solve(pm_ctx *ctx, const float *rho, float coef, int deconv, float *phi,

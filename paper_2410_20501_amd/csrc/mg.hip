@@ -87,42 +87,65 @@ __device__ __forceinline__ float residual_at(const float *__restrict__ u,
   return scale * (f[c] - m) - lap * inv_h2;
 }
 
-// Coarse cell (I, J, K) <- restriction of the fine residual d = f - L u.
+// Two-pass restriction for the small levels: r = f - L u once per fine cell, then the
+// restriction of r (a coarse cell reads 64 or 8 fine values instead of evaluating 64
+// residuals), with the coarse starting guess -H^2 f_H / 6 written alongside.
+__global__ __launch_bounds__(kThreads) void k_residual(const float *__restrict__ u,
+                                                       const float *__restrict__ f, float scale,
+                                                       const float *__restrict__ mean, int n,
+                                                       float inv_h2, float *__restrict__ r) {
+  const unsigned un = (unsigned)n;
+  const unsigned t = blockIdx.x * kThreads + threadIdx.x;
+  if (t >= un * un * un) return;
+  const unsigned q = t / un;
+  const int k = (int)(t - q * un), i = (int)(q / un), j = (int)(q - (unsigned)i * un);
+  r[t] = residual_at(u, f, scale, src_mean(mean), i, j, k, n, inv_h2);
+}
+
+// Coarse cell (I, J, K) <- restriction of the fine residual r.
 // Full weighting: per axis fine cells 2J-1 .. 2J+2 with weights (1, 3, 3, 1) / 8.
 // Average: the 8 children 2J, 2J+1 per axis, each with weight 1/8.
 template <int KIND>
-__global__ __launch_bounds__(kThreads) void k_residual_restrict(
-    const float *__restrict__ u, const float *__restrict__ f, float scale,
-    const float *__restrict__ mean, int n, float inv_h2, float *__restrict__ fc) {
+__global__ __launch_bounds__(kThreads) void k_restrict_r(const float *__restrict__ r, int n,
+                                                         float *__restrict__ fc,
+                                                         float *__restrict__ uc,
+                                                         float gscale) {
   const unsigned nc = (unsigned)n >> 1;
   const unsigned t = blockIdx.x * kThreads + threadIdx.x;
   if (t >= nc * nc * nc) return;
-  const unsigned r = t / nc;
-  const int K = (int)(t - r * nc), I = (int)(r / nc), J = (int)(r - (unsigned)I * nc);
-  const float m = src_mean(mean);
+  const unsigned q = t / nc;
+  const int K = (int)(t - q * nc), I = (int)(q / nc), J = (int)(q - (unsigned)I * nc);
+  const size_t nn = (size_t)n * n;
   float acc = 0.0f;
   if constexpr (KIND == PM_RESTRICT_FW) {
     const float w[4] = {1.0f, 3.0f, 3.0f, 1.0f};
-    for (int a = 0; a < 4; ++a) {
-      const int i = wrap_index(2 * I - 1 + a, n);
-      for (int b = 0; b < 4; ++b) {
-        const int j = wrap_index(2 * J - 1 + b, n);
-        const float wab = w[a] * w[b];
+    int kk[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int k = wrap_index(2 * K - 1 + c, n);
-          acc = fmaf(wab * w[c], residual_at(u, f, scale, m, i, j, k, n, inv_h2), acc);
-        }
+    for (int c = 0; c < 4; ++c) kk[c] = wrap_index(2 * K - 1 + c, n);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const size_t ri = (size_t)wrap_index(2 * I - 1 + a, n) * nn;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const size_t rj = ri + (size_t)wrap_index(2 * J - 1 + b, n) * n;
+        const float row = fmaf(w[0], r[rj + kk[0]],
+                               fmaf(w[1], r[rj + kk[1]], fmaf(w[2], r[rj + kk[2]], w[3] * r[rj + kk[3]])));
+        acc = fmaf(w[a] * w[b], row, acc);
       }
     }
-    fc[t] = acc * (1.0f / 512.0f);
+    acc *= (1.0f / 512.0f);
   } else {
+#pragma unroll
     for (int a = 0; a < 2; ++a)
+#pragma unroll
       for (int b = 0; b < 2; ++b)
+#pragma unroll
         for (int c = 0; c < 2; ++c)
-          acc += residual_at(u, f, scale, m, 2 * I + a, 2 * J + b, 2 * K + c, n, inv_h2);
-    fc[t] = acc * 0.125f;
+          acc += r[(size_t)(2 * I + a) * nn + (size_t)(2 * J + b) * n + (2 * K + c)];
+    acc *= 0.125f;
   }
+  fc[t] = acc;
+  uc[t] = gscale * acc;
 }
 
 // u_fine += P v_coarse: per axis 3/4 from the nearest coarse centre and 1/4 from
@@ -345,20 +368,23 @@ struct Solver {
     const int64_t ncount = (int64_t)nc * nc * nc;
     const Src sr = src(l);
     const float inv_h2 = 1.0f / h2(l);
+    // coarse starting guess: one Jacobi step -H^2 d_H / 6, written with the restriction
+    const float gscale = -h2(l + 1) / 6.0f;
     if (streaming(l)) {
       hipError_t e = launch_rr_stream(cur[l], sr.f, sr.scale, sr.mean, n, inv_h2, p->restrict_kind,
-                                      ctx->lev[l + 1].f, s);
+                                      ctx->lev[l + 1].f, cur[l + 1], gscale, s);
       if (e != hipSuccess) return e;
-    } else if (p->restrict_kind == PM_RESTRICT_AVG) {
-      k_residual_restrict<PM_RESTRICT_AVG><<<blocks_for(ncount, kThreads), kThreads, 0, s>>>(
-          cur[l], sr.f, sr.scale, sr.mean, n, inv_h2, ctx->lev[l + 1].f);
     } else {
-      k_residual_restrict<PM_RESTRICT_FW><<<blocks_for(ncount, kThreads), kThreads, 0, s>>>(
-          cur[l], sr.f, sr.scale, sr.mean, n, inv_h2, ctx->lev[l + 1].f);
+      float *r = ctx->lev[l].res;
+      k_residual<<<blocks_for((int64_t)n * n * n, kThreads), kThreads, 0, s>>>(
+          cur[l], sr.f, sr.scale, sr.mean, n, inv_h2, r);
+      if (p->restrict_kind == PM_RESTRICT_AVG)
+        k_restrict_r<PM_RESTRICT_AVG><<<blocks_for(ncount, kThreads), kThreads, 0, s>>>(
+            r, n, ctx->lev[l + 1].f, cur[l + 1], gscale);
+      else
+        k_restrict_r<PM_RESTRICT_FW><<<blocks_for(ncount, kThreads), kThreads, 0, s>>>(
+            r, n, ctx->lev[l + 1].f, cur[l + 1], gscale);
     }
-    // coarse starting guess: one Jacobi step -H^2 d_H / 6
-    k_jacobi_guess<<<blocks_for(ncount, kThreads), kThreads, 0, s>>>(
-        cur[l + 1], ctx->lev[l + 1].f, 1.0f, nullptr, ncount, h2(l + 1));
     return hipGetLastError();
   }
 
@@ -417,6 +443,15 @@ int pm_mg_setup(pm_ctx *ctx) {
     ctx->lev[ctx->nlevels++] = L;
   }
   if ((int64_t)n * n * n > kCoarseMax) return PM_ERR_SHAPE;
+  // residual scratch of the two-pass restriction (levels that do not stream)
+  for (int l = 0; l + 1 < ctx->nlevels; ++l) {
+    const int m = ctx->lev[l].n;
+    const bool streams = m >= PM_STREAM_MIN_N && !(ctx->flags & PM_CREATE_REFERENCE_KERNELS) &&
+                         smooth_stream_blocks(m) <= RED_PARTIAL_CAP;
+    if (streams) continue;
+    if (hipMalloc(&ctx->lev[l].res, sizeof(float) * (size_t)m * m * m) != hipSuccess)
+      return PM_ERR_NOMEM;
+  }
   // ping-pong buffers for the streaming levels (not the coarsest)
   for (int l = 0; l + 1 < ctx->nlevels; ++l) {
     const int m = ctx->lev[l].n;

@@ -1,4 +1,4 @@
-// Streaming multigrid kernels for the large levels (n >= 64).
+// Streaming multigrid kernels for the large levels (n >= 256).
 //
 // A block owns an SJ x SK tile of (j, k) columns and a chunk of CI consecutive
 // i-planes, and walks through the planes once. Each thread keeps a fixed set of
@@ -220,7 +220,8 @@ __global__ __launch_bounds__(RT) void k_rr_stream(const float *__restrict__ u,
                                                   const float *__restrict__ f, float fscale,
                                                   const float *__restrict__ fmean, int n,
                                                   int cic, float inv_h2,
-                                                  float *__restrict__ fc) {
+                                                  float *__restrict__ fc,
+                                                  float *__restrict__ ucg, float gscale) {
   __shared__ float Lu[UNP];
   __shared__ float Lr[UNP];
   const int nc = n >> 1;
@@ -336,7 +337,12 @@ __global__ __launch_bounds__(RT) void k_rr_stream(const float *__restrict__ u,
       for (int c = 0; c < CPPT; ++c) {
         const int cidx = threadIdx.x + c * RT;
         const int J = J0 + cidx / CK, K = K0 + cidx % CK;
-        if (J < nc && K < nc) fc[((size_t)Idone * nc + J) * nc + K] = acc[slot][c] * scale;
+        if (J < nc && K < nc) {
+          const size_t ci = ((size_t)Idone * nc + J) * nc + K;
+          const float v = acc[slot][c] * scale;
+          fc[ci] = v;
+          if (ucg) ucg[ci] = gscale * v;  // coarse starting guess -H^2 f_H / 6
+        }
         acc[slot][c] = 0.f;
       }
     }
@@ -389,14 +395,17 @@ hipError_t launch_smooth_stream(const float *uin, float *uout, const float *f, f
 }
 
 hipError_t launch_rr_stream(const float *u, const float *f, float fscale, const float *fmean,
-                            int n, float inv_h2, int kind, float *fc, hipStream_t s) {
+                            int n, float inv_h2, int kind, float *fc, float *ucg, float gscale,
+                            hipStream_t s) {
   const int nc = n / 2;
   const int tj = (nc + CJ - 1) / CJ, tk = (nc + CK - 1) / CK;
   const int cic = chunk_for(nc, tj * tk, 1024, 8);
   dim3 grid(tk, tj, nc / cic);
   if (kind == PM_RESTRICT_AVG)
-    k_rr_stream<PM_RESTRICT_AVG><<<grid, RT, 0, s>>>(u, f, fscale, fmean, n, cic, inv_h2, fc);
+    k_rr_stream<PM_RESTRICT_AVG><<<grid, RT, 0, s>>>(u, f, fscale, fmean, n, cic, inv_h2, fc, ucg,
+                                                     gscale);
   else
-    k_rr_stream<PM_RESTRICT_FW><<<grid, RT, 0, s>>>(u, f, fscale, fmean, n, cic, inv_h2, fc);
+    k_rr_stream<PM_RESTRICT_FW><<<grid, RT, 0, s>>>(u, f, fscale, fmean, n, cic, inv_h2, fc, ucg,
+                                                    gscale);
   return hipGetLastError();
 }

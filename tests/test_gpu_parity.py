@@ -232,9 +232,9 @@ def test_mg_solve_parity(lib, n):
 
 @pytest.mark.parametrize("pre,post", [(2, 2), (1, 1), (3, 1), (0, 2), (2, 0)])
 def test_streaming_multigrid_matches_reference_kernels(lib, pre, post):
-    """The fused streaming smoother/restriction (n >= 128) against one kernel per half-sweep."""
+    """The fused streaming smoother/restriction (n >= 256) against one kernel per half-sweep."""
     _say(f"streaming vs reference pre={pre} post={post}")
-    n = 128
+    n = 256
     rho32 = _density(n, seed=21)
     fast = ctx_for(lib, n)
     key = ("ref", n)
