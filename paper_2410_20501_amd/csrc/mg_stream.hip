@@ -20,8 +20,24 @@
 
 namespace {
 
-constexpr int SJ = 32, SK = 64;  // interior tile of the smoother
-constexpr int ST = 1024;         // threads per smoother block
+#ifndef PM_SMOOTH_SJ
+#define PM_SMOOTH_SJ 16
+#endif
+#ifndef PM_SMOOTH_THREADS
+#define PM_SMOOTH_THREADS 512
+#endif
+constexpr int SJ = PM_SMOOTH_SJ, SK = 64;  // interior tile of the smoother (SJ, SK even)
+constexpr int ST = PM_SMOOTH_THREADS;      // threads per smoother block
+#ifndef PM_SMOOTH_JFAST
+#define PM_SMOOTH_JFAST 0
+#endif
+#ifndef PM_SMOOTH_NT
+#define PM_SMOOTH_NT 0
+#endif
+#ifndef PM_SMOOTH_BLOCKS
+#define PM_SMOOTH_BLOCKS 2048
+#endif
+constexpr int kSmoothBlocks = PM_SMOOTH_BLOCKS;  // blocks wanted per pass (i-chunks shrink to reach it)
 
 __device__ __forceinline__ int wrap_any(int i, int n) {
   const int r = i % n;
@@ -57,154 +73,313 @@ __device__ void block_pair_to_partial(double s1, double s2, double *partial) {
   }
 }
 
+// Colour-split pairs: a thread owns pairs of k-neighbouring points (k even, k + 1)
+// of the tile plus halo; the two points of a pair have opposite colours. Plane q of
+// the pipeline receives half-sweep s on plane q - s, whose colour alternates with s
+// exactly as the plane parity does, so one plane step updates the same point of every
+// pair in all its half-sweeps: point E in steps with q even, point O with q odd (E is
+// the point with j + k + first_colour odd). Every lane does one update per pair and
+// half-sweep, with no per-lane colour test and no masked lanes; the ring of planes is
+// unrolled, so which point a step updates is known at compile time. The halo is not
+// masked either: points near the tile edge read padding or wrapped-row values and come
+// out wrong, but a wrong value moves inward by one cell per half-sweep and the halo is
+// H cells wide, so the interior is exact.
+// The norm-accumulating pass runs twice the threads with half the pairs each: at two
+// pairs per thread its extra live values spill, and a spill reload waits for the
+// plane prefetches.
 template <int H, bool NORM>
-__global__ __launch_bounds__(ST) void k_smooth_stream(
+struct SmoothShape {
+  static constexpr int NT = NORM ? 2 * ST : ST;     // threads per block
+  static constexpr int RJ = SJ + 2 * H, RK = SK + 2 * H, RK2 = RK / 2, NPAIR = RJ * RK2;
+  static constexpr int PP = (NPAIR + NT - 1) / NT;  // pairs per thread
+  // LDS: per published plane one array of E values and one of O values, each indexed
+  // by pair (consecutive lanes, consecutive banks) with padding rows around it
+  static constexpr int PAD = RK2 + 2;                // floats before and after a colour array
+  static constexpr int ARR = NPAIR + 2 * PAD;        // floats per colour array
+  static constexpr int SLOT = 2 * ARR;               // floats per published plane (E, then O)
+  static constexpr int RING = H + 2;                 // planes held in registers
+};
+
+// planes in flight from HBM (a third one measured no faster and costs registers)
+template <int H, bool NORM>
+constexpr int smooth_prefetch() {
+  return 2;
+}
+
+template <int H, bool NORM, bool OMEGA1>
+struct SmoothState {
+  using S = SmoothShape<H, NORM>;
+  // per-thread constants
+  // LDS index of the pair in a colour array (padding included); the first of the two
+  // k-neighbours of E (in the O array) is li - 1 + offe, of O (in the E array) li - offe,
+  // with offe = swp the k offset of E in its pair
+  int li[S::PP];
+  uint32_t col[S::PP];        // in-plane offset of the pair's even-k point
+  bool swp[S::PP];            // E is the odd-k point of its pair
+  bool inside[S::PP];
+  // pipeline registers: ring slot (q - d) mod RING holds plane q - d
+  float uE[S::RING][S::PP], uO[S::RING][S::PP];
+  float fE[S::RING][S::PP], fO[S::RING][S::PP];  // fscale (f - mean)
+  static constexpr int PF = smooth_prefetch<H, NORM>();
+  float2 pu[PF][S::PP], pf[PF][S::PP];            // planes in flight from HBM
+  double s_r, s_f;
+  // uniform
+  const float *uin, *f;
+  float *uout, *lds;
+  float fscale, m, h2, omega, inv_h2;
+  int n, i0, ci, qend;
+  size_t nn;
+
+  // planes of a chunk lie within one period of the grid on either side
+  __device__ __forceinline__ int wrap_plane(int q) const { return q < 0 ? q + n : (q >= n ? q - n : q); }
+
+  __device__ __forceinline__ void load(int q, float2 (&u)[S::PP], float2 (&fv)[S::PP]) {
+    const size_t plane = (size_t)wrap_plane(q) * nn;
+#pragma unroll
+    for (int t = 0; t < S::PP; ++t) {
+      u[t] = *reinterpret_cast<const float2 *>(uin + plane + col[t]);
+      fv[t] = *reinterpret_cast<const float2 *>(f + plane + col[t]);
+    }
+  }
+};
+
+// Gauss-Seidel update of one point per pair on the plane in ring slot c (neighbour
+// planes in slots cm and cp), in-plane neighbours from L.
+// L is the colour array of the other points: k-neighbours at kn, kn + 1, j-neighbours
+// one row (RK2 pairs) up and down.
+template <int c, int cm, int cp, int RING, int PP, int RK2, bool OMEGA1, bool E>
+__device__ __forceinline__ void smooth_relax(float (&u)[RING][PP], const float (&fv)[RING][PP],
+                                             const int (&li)[PP], const bool (&swp)[PP],
+                                             const float *L, float h2, float omega) {
+#pragma unroll
+  for (int t = 0; t < PP; ++t) {
+    const int e = li[t], k = E ? (swp[t] ? e : e - 1) : (swp[t] ? e - 1 : e);
+    const float nb = (L[k] + L[k + 1]) + (L[e - RK2] + L[e + RK2]) + (u[cm][t] + u[cp][t]);
+    const float gs = (nb - h2 * fv[c][t]) * (1.0f / 6.0f);
+    const float uc = u[c][t];
+    u[c][t] = OMEGA1 ? gs : fmaf(omega, gs - uc, uc);
+  }
+}
+
+// LDS slot of half-sweep s in a step with q = R mod RING. With NORM the slot of s = 1
+// alternates between slot 0 and slot H, so the input values of plane q - 2 published by
+// the previous step are still there for the residual of plane q - 1.
+template <int R, int H, bool NORM>
+constexpr int lds_slot(int s) {
+  return (NORM && s == 1 && (R & 1)) ? H : s - 1;
+}
+
+// ring slot of plane q - d in a step with q = R mod RING
+template <int R, int RING>
+constexpr int ring_slot(int d) {
+  return ((R - d) % RING + RING) % RING;
+}
+
+// Half-sweep S of a plane step: plane q - S.
+template <int R, int S, int H, bool NORM, bool OMEGA1>
+__device__ __forceinline__ void smooth_half(SmoothState<H, NORM, OMEGA1> &c, int q) {
+  using Sh = SmoothShape<H, NORM>;
+  constexpr int RING = Sh::RING, PP = Sh::PP, RK2 = Sh::RK2;
+  constexpr int c0 = ring_slot<R, RING>(0), c1 = ring_slot<R, RING>(1);
+  constexpr int cs = ring_slot<R, RING>(S), cm = ring_slot<R, RING>(S + 1),
+                cp = ring_slot<R, RING>(S - 1);
+  const int p = q - S;
+  const float *LE = c.lds + lds_slot<R, H, NORM>(S) * Sh::SLOT, *LO = LE + Sh::ARR;
+  if constexpr ((R & 1) == 0)
+    smooth_relax<cs, cm, cp, RING, PP, RK2, OMEGA1, true>(c.uE, c.fE, c.li, c.swp, LO, c.h2,
+                                                          c.omega);
+  else
+    smooth_relax<cs, cm, cp, RING, PP, RK2, OMEGA1, false>(c.uO, c.fO, c.li, c.swp, LE, c.h2,
+                                                           c.omega);
+}
+
+// NORM: residual of the input field at plane q - 1, from the values published before
+// its first update (LDS slot of s = 1), the input values of plane q - 2 (the previous
+// step's slot) and plane q (registers, not yet updated). Run after the relaxations, so
+// its live values do not add to theirs.
+template <int R, int H, bool OMEGA1>
+__device__ __forceinline__ void smooth_norm(SmoothState<H, true, OMEGA1> &c, int q) {
+  using Sh = SmoothShape<H, true>;
+  constexpr int RING = Sh::RING, PP = Sh::PP, RK2 = Sh::RK2;
+  constexpr int c0 = ring_slot<R, RING>(0), c1 = ring_slot<R, RING>(1);
+  const int p = q - 1;
+  if (p < c.i0 || p >= c.i0 + c.ci) return;  // uniform
+  const float *LE = c.lds + lds_slot<R, H, true>(1) * Sh::SLOT, *LO = LE + Sh::ARR;
+  const float *PE = c.lds + lds_slot<R + 1, H, true>(1) * Sh::SLOT, *PO = PE + Sh::ARR;
+  float sr = 0.f, sf = 0.f;  // this plane's few terms in FP32, the running sums in FP64
+#pragma unroll
+  for (int t = 0; t < PP; ++t) {
+    if (!c.inside[t]) continue;
+    const int e = c.li[t], ka = c.swp[t] ? e : e - 1, kb = c.swp[t] ? e - 1 : e;
+    const float a = LE[e], b = LO[e];
+    const float lapa = (LO[ka] - a) + (LO[ka + 1] - a) + (LO[e - RK2] - a) + (LO[e + RK2] - a) +
+                       (PE[e] - a) + (c.uE[c0][t] - a);
+    const float lapb = (LE[kb] - b) + (LE[kb + 1] - b) + (LE[e - RK2] - b) + (LE[e + RK2] - b) +
+                       (PO[e] - b) + (c.uO[c0][t] - b);
+    const float fa = c.fE[c1][t], fb = c.fO[c1][t];
+    const float ra = fa - lapa * c.inv_h2, rb = fb - lapb * c.inv_h2;
+    sr = fmaf(ra, ra, fmaf(rb, rb, sr));
+    sf = fmaf(fa, fa, fmaf(fb, fb, sf));
+  }
+  c.s_r += sr;
+  c.s_f += sf;
+}
+
+template <int R, int S, int H, bool NORM, bool OMEGA1>
+__device__ __forceinline__ void smooth_halves(SmoothState<H, NORM, OMEGA1> &c, int q) {
+  if constexpr (S <= H) {
+    smooth_half<R, S, H, NORM, OMEGA1>(c, q);
+    smooth_halves<R, S + 1, H, NORM, OMEGA1>(c, q);
+  }
+}
+
+// One plane of the pipeline, for ring position R = q mod RING (q has the parity of R).
+template <int R, int H, bool NORM, bool OMEGA1>
+__device__ __forceinline__ void smooth_step(SmoothState<H, NORM, OMEGA1> &c, int q) {
+  using Sh = SmoothShape<H, NORM>;
+  constexpr int RING = Sh::RING, PP = Sh::PP, SLOT = Sh::SLOT;
+  constexpr int PF = smooth_prefetch<H, NORM>();
+  constexpr int P = R % PF;  // prefetch slot of plane q
+  constexpr int c0 = ring_slot<R, RING>(0), cH = ring_slot<R, RING>(H);
+  // plane q enters the ring; its slot is refilled with plane q + PF
+#pragma unroll
+  for (int t = 0; t < PP; ++t) {
+    const float2 u = c.pu[P][t], fv = c.pf[P][t];
+    const float fx = c.fscale * (fv.x - c.m), fy = c.fscale * (fv.y - c.m);
+    c.uE[c0][t] = c.swp[t] ? u.y : u.x;
+    c.uO[c0][t] = c.swp[t] ? u.x : u.y;
+    c.fE[c0][t] = c.swp[t] ? fy : fx;
+    c.fO[c0][t] = c.swp[t] ? fx : fy;
+  }
+  c.load(min(q + PF, c.qend - 1), c.pu[P], c.pf[P]);  // past the end: a harmless reload
+  // Half-sweep s runs on plane q - s. Its in-plane neighbours (the points it does not
+  // change: O when it updates E and the reverse) come from LDS slot s - 1, its
+  // i-neighbours from registers, so all H planes are published before one barrier.
+  // The residual of the input (NORM, s = 1) needs both points.
+#pragma unroll
+  for (int s = 1; s <= H; ++s) {
+    float *LE = c.lds + lds_slot<R, H, NORM>(s) * SLOT, *LO = LE + Sh::ARR;
+    const int cs = ((R - s) % RING + RING) % RING;
+    const bool both = NORM && s == 1;
+#pragma unroll
+    for (int t = 0; t < PP; ++t) {
+      if (both || (R & 1) == 1) LE[c.li[t]] = c.uE[cs][t];
+      if (both || (R & 1) == 0) LO[c.li[t]] = c.uO[cs][t];
+    }
+  }
+  __syncthreads();
+  smooth_halves<R, 1, H, NORM, OMEGA1>(c, q);
+  if constexpr (NORM) {
+    __builtin_amdgcn_sched_barrier(0);
+    smooth_norm<R, H, OMEGA1>(c, q);
+  }
+  // plane q - H is final
+  const int pout = q - H;
+  if (pout >= c.i0 && pout < c.i0 + c.ci) {
+    const size_t op = (size_t)pout * c.nn;  // output planes lie in [0, n)
+#pragma unroll
+    for (int t = 0; t < PP; ++t)
+      if (c.inside[t]) {
+        const float a = c.uE[cH][t], b = c.uO[cH][t];
+#if PM_SMOOTH_NT
+        typedef float nt2 __attribute__((ext_vector_type(2)));
+        nt2 v;
+        v.x = c.swp[t] ? b : a;
+        v.y = c.swp[t] ? a : b;
+        __builtin_nontemporal_store(v, reinterpret_cast<nt2 *>(c.uout + op + c.col[t]));
+#else
+        *reinterpret_cast<float2 *>(c.uout + op + c.col[t]) =
+            c.swp[t] ? make_float2(b, a) : make_float2(a, b);
+#endif
+      }
+  }
+  // the LDS slots are rewritten by the next plane
+  __syncthreads();
+}
+
+template <int R, bool GUARD, int H, bool NORM, bool OMEGA1>
+__device__ __forceinline__ void smooth_steps(SmoothState<H, NORM, OMEGA1> &c, int q) {
+  if constexpr (R < SmoothShape<H, NORM>::RING) {
+    if (!GUARD || q + R < c.qend) smooth_step<R, H, NORM, OMEGA1>(c, q + R);
+    smooth_steps<R + 1, GUARD, H, NORM, OMEGA1>(c, q);
+  }
+}
+
+template <int H, bool NORM, bool OMEGA1>
+// at least 4 waves per SIMD: two 512-thread blocks (or one of 1024) per CU
+__global__ __launch_bounds__(NORM ? 2 * ST : ST) __attribute__((amdgpu_waves_per_eu(4))) void k_smooth_stream(
     const float *__restrict__ uin, float *__restrict__ uout, const float *__restrict__ f,
     float fscale, const float *__restrict__ fmean, int n, int ci, float h2, float omega,
     int first_colour, double *__restrict__ partial) {
-  constexpr int RJ = SJ + 2 * H, RK = SK + 2 * H, NP = RJ * RK;
-  constexpr int PPT = (NP + ST - 1) / ST;
-  __shared__ float lds[H][NP];
+  using S = SmoothShape<H, NORM>;
+  constexpr int PF = smooth_prefetch<H, NORM>();
+  static_assert(S::RING % 2 == 0 && S::RING % PF == 0,
+                "plane parity and prefetch slots repeat within one ring period");
+  constexpr int NSLOT = H + (NORM ? 1 : 0);
+  __shared__ float lds[NSLOT * S::SLOT];
 
   // XCD-aware order: consecutive logical blocks are k-, then j-neighbours
   const unsigned lin = xcd_block(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
                                  gridDim.x * gridDim.y * gridDim.z);
+#if PM_SMOOTH_JFAST
+  const int by = lin % gridDim.y, bx = (lin / gridDim.y) % gridDim.x, bz = lin / (gridDim.x * gridDim.y);
+#else
   const int bx = lin % gridDim.x, by = (lin / gridDim.x) % gridDim.y, bz = lin / (gridDim.x * gridDim.y);
-  const int k0 = bx * SK, j0 = by * SJ, i0 = bz * ci;
-  const float m = fmean ? *fmean : 0.0f;
-  const float inv_h2 = 1.0f / h2;
-  const size_t nn = (size_t)n * n;
+#endif
+  const int k0 = bx * SK, j0 = by * SJ;
 
-  int rjv[PPT], rkv[PPT];
-  uint32_t colv[PPT];
-  bool inside[PPT];
+  SmoothState<H, NORM, OMEGA1> c;
+  c.uin = uin;
+  c.f = f;
+  c.uout = uout;
+  c.lds = lds;
+  c.fscale = fscale;
+  c.m = fmean ? *fmean : 0.0f;
+  c.h2 = h2;
+  c.omega = omega;
+  c.inv_h2 = 1.0f / h2;
+  c.n = n;
+  c.i0 = bz * ci;
+  c.ci = ci;
+  c.qend = c.i0 + ci + H;
+  c.nn = (size_t)n * n;
+  c.s_r = c.s_f = 0.0;
+
+  // padding is read by edge points (and written only by slots without a pair)
+  for (int e = threadIdx.x; e < S::PAD; e += S::NT)
 #pragma unroll
-  for (int t = 0; t < PPT; ++t) {
-    const int e = threadIdx.x + t * ST;
-    const int rj = (e < NP) ? e / RK : -100, rk = (e < NP) ? e % RK : -100;
-    rjv[t] = rj;
-    rkv[t] = rk;
-    const int gj = j0 - H + rj, gk = k0 - H + rk;
-    colv[t] = (e < NP) ? (uint32_t)(wrap_any(gj, n) * n + wrap_any(gk, n)) : 0u;
-    inside[t] = (e < NP) && rj >= H && rj < H + SJ && rk >= H && rk < H + SK && gj < n && gk < n;
+    for (int a = 0; a < 2 * NSLOT; ++a) {
+      lds[a * S::ARR + e] = 0.0f;
+      lds[a * S::ARR + S::PAD + S::NPAIR + e] = 0.0f;
+    }
+#pragma unroll
+  for (int t = 0; t < S::PP; ++t) {
+    const int e = threadIdx.x + t * S::NT;
+    const bool v = e < S::NPAIR;
+    const int rj = v ? e / S::RK2 : 0, r2 = v ? e % S::RK2 : 0;
+    const int gj = j0 - H + rj, gk = k0 - H + 2 * r2;  // gk even (k0, H even)
+    c.swp[t] = ((gj + first_colour) & 1) == 0;  // E = the point with j + k + first_colour odd
+    // a slot without a pair loads column 0 and works on the trailing padding, whose
+    // values only reach halo points, so every lane runs the same code unmasked
+    const int li = v ? S::PAD + e : S::PAD + S::NPAIR + 1;
+    // E at k = 2 r2 + offe has O neighbours in pairs r2 - 1 + offe and r2 + offe; O at
+    // k = 2 r2 + 1 - offe has E neighbours in pairs r2 - offe and r2 + 1 - offe
+    c.li[t] = li;
+    c.col[t] = v ? (uint32_t)(wrap_any(gj, n) * n + wrap_any(gk, n)) : 0u;
+    c.inside[t] = v && rj >= H && rj < H + SJ && 2 * r2 >= H && 2 * r2 < H + SK && gj < n &&
+                  gk < n;
+#pragma unroll
+    for (int a = 0; a < S::RING; ++a) c.uE[a][t] = c.uO[a][t] = c.fE[a][t] = c.fO[a][t] = 0.f;
+#pragma unroll
+    for (int a = 0; a < PF; ++a) c.pu[a][t] = c.pf[a][t] = make_float2(0.f, 0.f);
   }
-
-  float ur[H + 2][PPT];   // ur[t] = plane q - (H + 1) + t
-  float fr[H + 1][PPT];   // fr[t] = plane q - H + t, already scaled: fscale (f - mean)
-  float uo_prev[PPT];     // original values of plane q - 2 (NORM)
-  // two prefetch slots: planes q + 1 and q + 2 are in flight while plane q is worked on
-  float pa_u[PPT], pa_f[PPT], pb_u[PPT], pb_f[PPT];
+  const int qbeg = c.i0 - H;  // even (ci even, H even): step R of a ring period has q = R mod 2
 #pragma unroll
-  for (int a = 0; a < H + 2; ++a)
-#pragma unroll
-    for (int t = 0; t < PPT; ++t) ur[a][t] = 0.f;
-#pragma unroll
-  for (int a = 0; a < H + 1; ++a)
-#pragma unroll
-    for (int t = 0; t < PPT; ++t) fr[a][t] = 0.f;
-#pragma unroll
-  for (int t = 0; t < PPT; ++t) uo_prev[t] = pa_u[t] = pa_f[t] = pb_u[t] = pb_f[t] = 0.f;
-
-  auto load = [&](int q, float (&pu)[PPT], float (&pf)[PPT]) {
-    const size_t plane = (size_t)wrap_any(q, n) * nn;
-#pragma unroll
-    for (int t = 0; t < PPT; ++t) {
-      if (rjv[t] >= 0) {
-        pu[t] = uin[plane + colv[t]];
-        pf[t] = f[plane + colv[t]];
-      }
-    }
-  };
-
-  double s_r = 0.0, s_f = 0.0;
-  const int qbeg = i0 - H, qend = i0 + ci + H;
-
-  // one plane: take plane q from its slot, refill the slot with plane q + 2, then run
-  // the H half-sweeps of the pipeline and retire plane q - H
-  auto step = [&](int q, float (&pu)[PPT], float (&pf)[PPT]) {
-#pragma unroll
-    for (int a = 0; a < H + 1; ++a)
-#pragma unroll
-      for (int t = 0; t < PPT; ++t) ur[a][t] = ur[a + 1][t];
-#pragma unroll
-    for (int a = 0; a < H; ++a)
-#pragma unroll
-      for (int t = 0; t < PPT; ++t) fr[a][t] = fr[a + 1][t];
-#pragma unroll
-    for (int t = 0; t < PPT; ++t) {
-      ur[H + 1][t] = pu[t];
-      fr[H][t] = fscale * (pf[t] - m);
-    }
-    if (q + 2 < qend) load(q + 2, pu, pf);
-    // Half-sweep s = 1 .. H runs on plane q - s. Its in-plane neighbours (the other
-    // colour, which half-sweep s does not change) come from LDS slot s - 1 and its
-    // i-neighbours from this thread's registers, so all H planes are published
-    // before one barrier and the stages then run back to back.
-#pragma unroll
-    for (int s = 1; s <= H; ++s) {
-      const int p = q - s;
-      if (p < i0 - H + s || p >= i0 + ci + H - s) continue;  // uniform across the block
-      float *L = lds[s - 1];
-#pragma unroll
-      for (int t = 0; t < PPT; ++t)
-        if (rjv[t] >= 0) L[rjv[t] * RK + rkv[t]] = ur[H + 1 - s][t];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int s = 1; s <= H; ++s) {
-      const int p = q - s;
-      if (p < i0 - H + s || p >= i0 + ci + H - s) continue;  // uniform across the block
-      const float *L = lds[s - 1];
-      const int colour = (first_colour + s - 1) & 1;
-#pragma unroll
-      for (int t = 0; t < PPT; ++t) {
-        const int rj = rjv[t], rk = rkv[t];
-        if (rj < s || rj >= RJ - s || rk < s || rk >= RK - s) continue;
-        const int e = rj * RK + rk;
-        const float uc = ur[H + 1 - s][t];
-        const float inpl = L[e - RK] + L[e + RK] + L[e - 1] + L[e + 1];
-        if constexpr (NORM) {
-          // residual of the input field at plane q-1 (before its first update)
-          if (s == 1 && inside[t] && p >= i0 && p < i0 + ci) {
-            const float lap = (L[e - RK] - uc) + (L[e + RK] - uc) + (L[e - 1] - uc) +
-                              (L[e + 1] - uc) + (uo_prev[t] - uc) + (ur[H + 1][t] - uc);
-            const double r = fr[H - 1][t] - lap * inv_h2;
-            s_r += r * r;
-            s_f += (double)fr[H - 1][t] * fr[H - 1][t];
-          }
-        }
-        const int gj = j0 - H + rj, gk = k0 - H + rk;
-        if (((p + gj + gk) & 1) != colour) continue;
-        const float nb = inpl + ur[H - s][t] + ur[H + 2 - s][t];
-        const float gs = (nb - h2 * fr[H - s][t]) * (1.0f / 6.0f);
-        ur[H + 1 - s][t] = (omega == 1.0f) ? gs : fmaf(omega, gs - uc, uc);
-      }
-      if constexpr (NORM) {
-        if (s == 1) {
-#pragma unroll
-          for (int t = 0; t < PPT; ++t) uo_prev[t] = L[rjv[t] >= 0 ? rjv[t] * RK + rkv[t] : 0];
-        }
-      }
-    }
-    // plane q - H is final
-    const int pout = q - H;
-    if (pout >= i0 && pout < i0 + ci) {
-      const size_t op = (size_t)wrap_any(pout, n) * nn;
-#pragma unroll
-      for (int t = 0; t < PPT; ++t)
-        if (inside[t]) uout[op + colv[t]] = ur[1][t];
-    }
-    // the LDS slots are rewritten by the next plane
-    __syncthreads();
-  };
-
-  load(qbeg, pa_u, pa_f);
-  if (qbeg + 1 < qend) load(qbeg + 1, pb_u, pb_f);
-  for (int q = qbeg; q < qend; q += 2) {
-    step(q, pa_u, pa_f);
-    if (q + 1 < qend) step(q + 1, pb_u, pb_f);
-  }
-  if constexpr (NORM) block_pair_to_partial<ST>(s_r, s_f, partial);
+  for (int a = 0; a < PF; ++a) c.load(qbeg + a, c.pu[a], c.pf[a]);
+  int q = qbeg;
+  for (; q + S::RING <= c.qend; q += S::RING) smooth_steps<0, false, H, NORM, OMEGA1>(c, q);
+  smooth_steps<0, true, H, NORM, OMEGA1>(c, q);
+  if constexpr (NORM) block_pair_to_partial<S::NT>(c.s_r, c.s_f, partial);
 }
 
 // ---------------------------------------------------------------- residual + restrict
@@ -362,7 +537,7 @@ inline int chunk_for(int n, int tiles, int want_blocks, int min_ci) {
 
 int64_t smooth_stream_blocks(int n) {
   const int tj = (n + SJ - 1) / SJ, tk = (n + SK - 1) / SK;
-  const int ci = chunk_for(n, tj * tk, 1024, 16);
+  const int ci = chunk_for(n, tj * tk, kSmoothBlocks, 16);
   return (int64_t)tj * tk * (n / ci);
 }
 
@@ -371,26 +546,29 @@ hipError_t launch_smooth_stream(const float *uin, float *uout, const float *f, f
                                 int first_colour, int half_sweeps, double *partial,
                                 hipStream_t s) {
   const int tj = (n + SJ - 1) / SJ, tk = (n + SK - 1) / SK;
-  const int ci = chunk_for(n, tj * tk, 1024, 16);
+  const int ci = chunk_for(n, tj * tk, kSmoothBlocks, 16);
   dim3 grid(tk, tj, n / ci);
   const bool norm = partial != nullptr;
+  const bool om1 = omega == 1.0f;
+#define PM_SMOOTH_LAUNCH(H_, N_, O_)                                                     \
+  k_smooth_stream<H_, N_, O_><<<grid, (SmoothShape<H_, N_>::NT), 0, s>>>(               \
+      uin, uout, f, fscale, fmean, n, ci, h2, omega, first_colour, partial)
   if (half_sweeps == 4) {
-    if (norm)
-      k_smooth_stream<4, true><<<grid, ST, 0, s>>>(uin, uout, f, fscale, fmean, n, ci, h2, omega,
-                                                   first_colour, partial);
-    else
-      k_smooth_stream<4, false><<<grid, ST, 0, s>>>(uin, uout, f, fscale, fmean, n, ci, h2, omega,
-                                                    first_colour, partial);
+    if (norm) {
+      if (om1) PM_SMOOTH_LAUNCH(4, true, true); else PM_SMOOTH_LAUNCH(4, true, false);
+    } else {
+      if (om1) PM_SMOOTH_LAUNCH(4, false, true); else PM_SMOOTH_LAUNCH(4, false, false);
+    }
   } else if (half_sweeps == 2) {
-    if (norm)
-      k_smooth_stream<2, true><<<grid, ST, 0, s>>>(uin, uout, f, fscale, fmean, n, ci, h2, omega,
-                                                   first_colour, partial);
-    else
-      k_smooth_stream<2, false><<<grid, ST, 0, s>>>(uin, uout, f, fscale, fmean, n, ci, h2, omega,
-                                                    first_colour, partial);
+    if (norm) {
+      if (om1) PM_SMOOTH_LAUNCH(2, true, true); else PM_SMOOTH_LAUNCH(2, true, false);
+    } else {
+      if (om1) PM_SMOOTH_LAUNCH(2, false, true); else PM_SMOOTH_LAUNCH(2, false, false);
+    }
   } else {
     return hipErrorInvalidValue;
   }
+#undef PM_SMOOTH_LAUNCH
   return hipGetLastError();
 }
 

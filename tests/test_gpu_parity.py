@@ -230,10 +230,14 @@ def test_mg_solve_parity(lib, n):
         assert hist[1] / hist[2] > 4.0, hist
 
 
-@pytest.mark.parametrize("pre,post", [(2, 2), (1, 1), (3, 1), (0, 2), (2, 0)])
-def test_streaming_multigrid_matches_reference_kernels(lib, pre, post):
-    """The fused streaming smoother/restriction (n >= 256) against one kernel per half-sweep."""
-    _say(f"streaming vs reference pre={pre} post={post}")
+@pytest.mark.parametrize("pre,post,omega,kind", [(2, 2, 1.0, "fw"), (1, 1, 1.0, "fw"),
+                                                 (3, 1, 1.0, "fw"), (0, 2, 1.0, "fw"),
+                                                 (2, 0, 1.0, "fw"), (2, 1, 1.25, "fw"),
+                                                 (2, 2, 1.0, "avg")])
+def test_streaming_multigrid_matches_reference_kernels(lib, pre, post, omega, kind):
+    """The fused streaming smoother/restriction (n >= 256) against one kernel per half-sweep
+    (paper Sect. 3.7.1; omega = 1.25 with 2 + 1 sweeps is the paper's own default)."""
+    _say(f"streaming vs reference pre={pre} post={post} omega={omega} restriction={kind}")
     n = 256
     rho32 = _density(n, seed=21)
     fast = ctx_for(lib, n)
@@ -244,11 +248,13 @@ def test_streaming_multigrid_matches_reference_kernels(lib, pre, post):
     out = []
     for c in (fast, ref_ctx):
         phi = torch.zeros((n, n, n), device="cuda")
-        lib.pm_solve_mg(c, dev(rho32), 0.15, phi, fixed_cycles=3, pre=pre, post=post)
+        lib.pm_solve_mg(c, dev(rho32), 0.15, phi, fixed_cycles=3, pre=pre, post=post,
+                        omega=omega, restrict_kind=kind)
         out.append(host(phi))
     assert rel_l2(out[0], out[1]) <= 2e-6
     phi = torch.zeros((n, n, n), device="cuda")
-    st = lib.pm_solve_mg(fast, dev(rho32), 0.15, phi, tol=1e-7, max_cycles=60, pre=pre, post=post)
+    st = lib.pm_solve_mg(fast, dev(rho32), 0.15, phi, tol=1e-7, max_cycles=60, pre=pre, post=post,
+                         omega=omega, restrict_kind=kind)
     ref = opm.solve_exact7(opm.source(rho32.astype(np.float64), 0.1), 1.0 / n)
     assert rel_l2(host(phi), ref) <= 1e-5, st.history()
 
