@@ -6,8 +6,11 @@ steps uniform in a up to a = 1, positions stored as FP32 in-cell offsets plus
 an int32 cell index, TSC, multigrid (2 + 2 red-black Gauss-Seidel sweeps, full
 weighting) warm-started from the previous step's potential. Inputs are seeded
 synthetic Gaussian random fields generated on the host and copied to HBM before
-the timed region. One "step" is one pm_kdk call: kick + drift, deposit,
-multigrid solve, 5-point gradient, interpolation + kick.
+the timed region. The steps run as one chain (pm_kdk_chain): one "step" is one
+call, that is deposit, multigrid solve, 5-point gradient and interpolation, with the
+closing half-kick of the step, the opening half-kick of the next and the next drift
+applied in the interpolation pass (--no-chain: one pm_kdk call per step, kick + drift
+in a pass of its own).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 Prints one JSON line.
@@ -242,18 +245,20 @@ def bench_batched(nboxes=96, steps=20, master_seed=2024):
     }
 
 
-def stage_bytes(npart, ncell, cycles):
+def stage_bytes(npart, ncell, cycles, chained=False):
     """Algorithmic HBM bytes of each stage of one step at cell-offset positions (the
     minimum each stage's kernels must move; multigrid: the level-0 passes of the fused
     V-cycle, two smoothing passes of 12 B/cell, residual-restriction 8 B/cell and
     prolongation 8 B/cell, times 8/7 for the coarser levels). With the sorted deposit
     the gradient is formed inside the interpolation kernel, which then reads the
-    potential (4 B/cell) instead of the force grid; the gradient stage is empty."""
+    potential (4 B/cell) instead of the force grid; the gradient stage is empty. In a
+    chained step the drift is part of the interpolation pass: offsets, cell index and
+    velocity in and out and the tile key out (60 B per particle), no acceleration."""
     return {
-        "ms_drift": 68.0 * npart,
+        "ms_drift": 0.0 if chained else 68.0 * npart,
         "ms_deposit": 16.0 * npart + 4.0 * ncell,
         "ms_solve": cycles * 40.0 * ncell * 8.0 / 7.0,
-        "ms_interp": 52.0 * npart + 4.0 * ncell,
+        "ms_interp": (60.0 if chained else 52.0) * npart + 4.0 * ncell,
     }
 
 
@@ -267,6 +272,8 @@ def main():
     ap.add_argument("--tol", type=float, default=BENCH_TOL)
     ap.add_argument("--reorder-every", type=int, default=10,
                     help="re-sort particles by tile every this many steps (0: never)")
+    ap.add_argument("--no-chain", action="store_true",
+                    help="one pm_kdk call per step instead of a chain of pm_kdk_chain calls")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--roofline-kernel", default="smooth", choices=["deposit", "smooth", "interp"],
                     help="kernel timed with events for the roofline object (default: the "
@@ -332,10 +339,21 @@ def main():
 
     import warnings
     warnings.simplefilter("ignore", pm.PMWarning)
+
+    def one_step(step, last=False):
+        """Step a_list[step] -> a_list[step + 1]; with the chain, `last` ends it in the
+        synchronised state (the next drift is not applied)."""
+        if args.no_chain:
+            return pm.pm_kdk(ctx, off_d, vel_d, a_list[step], a_list[step + 1], phi, acc,
+                             cell=cell_d, params=params)
+        a2 = a_list[step + 2] if (step + 2 <= total_steps and not last) else 0.0
+        stage = pm.PM_CHAIN_FIRST if step == 0 else pm.PM_CHAIN_NEXT
+        return pm.pm_kdk_chain(ctx, off_d, vel_d, a_list[step], a_list[step + 1], a2, stage, phi,
+                               acc, cell=cell_d, params=params)
+
     step = 0
     for _ in range(args.warmup):
-        pm.pm_kdk(ctx, off_d, vel_d, a_list[step], a_list[step + 1], phi, acc, cell=cell_d,
-                  params=params)
+        one_step(step)
         step += 1
     torch.cuda.synchronize()
     _log(f"warmup done ({args.warmup} steps)")
@@ -350,8 +368,7 @@ def main():
     for i in range(args.steps):
         if args.reorder_every > 0 and step % args.reorder_every == 0:
             pm.pm_reorder(ctx, off_d, vel=vel_d, acc=acc, cell=cell_d)
-        st = pm.pm_kdk(ctx, off_d, vel_d, a_list[step], a_list[step + 1], phi, acc, cell=cell_d,
-                       params=params)
+        st = one_step(step)
         cycles.append(st.mg.cycles)
         if args.stage_log:
             stage_rows.append((step, round(st.ms_drift, 2), round(st.ms_deposit, 2),
@@ -390,14 +407,16 @@ def main():
 
     # per-stage times of one extra (untimed) step with stage events
     params.timing = 1
-    stt = pm.pm_kdk(ctx, off_d, vel_d, a_list[step], a_list[min(step + 1, total_steps)], phi, acc,
-                    cell=cell_d, params=params) if step < total_steps else None
+    # (a chain that has not reached its end keeps going: this step ends it unless more
+    # steps follow, in which case it stays a chained step like the timed ones)
+    stt = one_step(step, last=step + 2 > total_steps) if step < total_steps else None
     stages = None
     stage_gbs = None
     if stt is not None:
         stages = {k: round(getattr(stt, k), 4) for k in
                   ("ms_drift", "ms_deposit", "ms_solve", "ms_gradient", "ms_interp")}
-        sb = stage_bytes(npart, n ** 3, stt.mg.cycles)
+        chained = not args.no_chain and step + 2 <= total_steps
+        sb = stage_bytes(npart, n ** 3, stt.mg.cycles, chained)
         stage_gbs = {k.replace("ms_", ""): {
             "gbs": round(sb[k] / (stages[k] * 1e-3) / 1e9, 1),
             "frac": round(sb[k] / (stages[k] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
@@ -420,7 +439,9 @@ def main():
         "config": {"workload": f"{n}^3 particles on a {n}^3 grid, 50 KDK steps a=0.02->1, "
                                f"cell-offset positions, TSC {args.order} deposit, multigrid "
                                f"2+2 RBGS growth-rescaled warm start tol {args.tol:g}, particles re-sorted "
-                               f"by tile every {args.reorder_every} steps",
+                               f"by tile every {args.reorder_every} steps, "
+                               + ("one pm_kdk call per step" if args.no_chain else
+                                  "steps chained (kick-kick-drift fused into interpolation)"),
                    "particles": npart, "grid": n, "deposit": args.order,
                    "vcycles_per_step": cycles},
         "stages_ms_last_step": stages,

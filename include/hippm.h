@@ -202,6 +202,27 @@ int pm_kdk(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, int64_t np, int p
            double a0, double a1, const pm_step_params *params, float *phi, float *acc,
            pm_step_stats *stats, pm_stream stream);
 
+/* Stages of a chain of kick-drift-kick steps (pm_kdk_chain). */
+enum { PM_CHAIN_FIRST = 0, PM_CHAIN_NEXT = 1 };
+
+/* One step a0 -> a1 of a chain of kick-drift-kick steps a0 < a1 < a2 < ... (Sect. 3.4).
+ * The closing half-kick of a step and the opening half-kick of the next one use the
+ * same accelerations (at x(a1)), so the chain applies them together with the next
+ * drift in one pass over the particles: the same arithmetic as consecutive pm_kdk
+ * calls up to FP32 rounding order.
+ *   stage PM_CHAIN_FIRST: state synchronised at a0 (x(a0), v(a0), acc at a0), as for
+ *     pm_kdk; PM_CHAIN_NEXT: the previous call of the chain left x(a1) and the
+ *     mid-step velocities of [a0, a1].
+ *   a2 > a1: the call ends with x(a2) and the mid-step velocities of [a1, a2] (the
+ *     next call passes PM_CHAIN_NEXT and a1, a2, a3); acc is not written (with the
+ *     sorted deposit on 8^3 tiles) or holds the accelerations at x(a1).
+ *   a2 <= a1 (for example 0): last step; ends synchronised at a1 with acc at x(a1).
+ * Between the calls of a chain the particle arrays must change only through
+ * pm_reorder. Arguments, ownership and errors as for pm_kdk. */
+int pm_kdk_chain(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, int64_t np, int poskind,
+                 double a0, double a1, double a2, int stage, const pm_step_params *params,
+                 float *phi, float *acc, pm_step_stats *stats, pm_stream stream);
+
 /* ------------------------------------------------------------------ reverse mode
  * Vector-Jacobian products of the steps above, for differentiating a run with
  * respect to its initial conditions (the use the paper gives for

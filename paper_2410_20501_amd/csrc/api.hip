@@ -98,6 +98,13 @@ int ensure_sort_scratch(pm_ctx *ctx, int64_t np) {
       return pm_fail(ctx, PM_ERR_NOMEM, "sort scratch allocation failed");
     ctx->sort_cap = cap;
   }
+  if (ctx->n % 8 == 0 && !ctx->cell_count2) {
+    const size_t len = (size_t)ncell / 512 + 1;
+    if (hipMalloc(&ctx->cell_count2, sizeof(int32_t) * len) != hipSuccess) {
+      ctx->cell_count2 = nullptr;
+      return pm_fail(ctx, PM_ERR_NOMEM, "sort scratch allocation failed");
+    }
+  }
   return PM_OK;
 }
 
@@ -117,8 +124,17 @@ int deposit_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np,
       }
       PM_HIP(ctx, hipMemsetAsync(ctx->fix_grid, 0, sizeof(unsigned long long) * (size_t)ncell, s));
     }
-    const bool hist = tiles && ctx->hist_ready;
+    bool hist = tiles && ctx->hist_ready;
+    if (tiles && !hist && ctx->hist_next && ctx->hist_pos == pos && ctx->hist_cell == cell &&
+        ctx->hist_np == np) {
+      // histogram and keys made by the previous chained step's fused drift
+      PM_HIP(ctx, hipMemcpyAsync(ctx->cell_count, ctx->cell_count2,
+                                 sizeof(int32_t) * (size_t)(ncell / 512 + 1),
+                                 hipMemcpyDeviceToDevice, s));
+      hist = true;
+    }
     ctx->hist_ready = false;
+    ctx->hist_next = false;
     PM_HIP(ctx, launch_sort_by_cell(ctx, pos, cell, np, poskind, s, tiles ? 2 : 0, hist));
     pm_kt_begin(ctx, PM_KERNEL_DEPOSIT, s);
     if (tiles)
@@ -141,9 +157,15 @@ int solve_impl(pm_ctx *ctx, const pm_step_params *p, const float *rho, float coe
 }
 
 // deposit -> solve -> gradient -> interp (+ optional kick on vel)
+// the next step of a chain of leapfrog steps: its opening half-kick and its drift
+struct ChainNext {
+  float kick, dt;
+};
+
 int accel_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, int poskind,
                double a, const pm_step_params *p, float *phi, float *acc, float *vel, float kick,
-               pm_step_stats *stats, hipStream_t s, bool timing, float warm_scale) {
+               pm_step_stats *stats, hipStream_t s, bool timing, float warm_scale,
+               const ChainNext *next) {
   if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[1], s));
   int st = deposit_impl(ctx, pos, cell, np, poskind, p->mas, p->order, ctx->rho, s);
   if (st != PM_OK) return st;
@@ -158,16 +180,41 @@ int accel_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, i
   if (!tiles) PM_HIP(ctx, launch_gradient(phi, ctx->n, 5, ctx->g, s));
   if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[4], s));
   pm_kt_begin(ctx, PM_KERNEL_INTERP, s);
-  if (tiles)
-    PM_HIP(ctx, launch_interp_tile_phi(ctx, pos, cell, poskind, p->mas, phi, acc, vel, kick, s));
-  else
-    PM_HIP(ctx, launch_interp(pos, cell, np, poskind, p->mas, ctx->n, ctx->g, acc, vel, kick, s));
-  // algorithmic bytes: position (12 B, + 4 B cell index), velocity in/out (24 B),
-  // acceleration out (12 B) per particle, and the force grid once (12 B per cell) or,
-  // with the gradient fused, the potential once (4 B per cell)
-  pm_kt_end(ctx, PM_KERNEL_INTERP, s,
-            (double)np * (48.0 + (poskind == PM_POS_CELLOFF ? 4.0 : 0.0)) +
-                (tiles ? 4.0 : 12.0) * (double)ctx->n * ctx->n * ctx->n);
+  double bytes;
+  if (tiles && next && np > 0) {
+    // the closing kick of this step and the opening kick and drift of the next one, in
+    // the interpolation kernel; the next sort's tile histogram comes with the drift
+    float *wpos = const_cast<float *>(pos);
+    int32_t *wcell = const_cast<int32_t *>(cell);
+    const int64_t ntiles = (int64_t)ctx->n * ctx->n * ctx->n / 512;
+    PM_HIP(ctx, hipMemsetAsync(ctx->cell_count2, 0, sizeof(int32_t) * (size_t)(ntiles + 1), s));
+    PM_HIP(ctx, launch_interp_tile_phi(ctx, wpos, wcell, poskind, p->mas, phi, nullptr, vel,
+                                       kick + next->kick, next->dt, ctx->pcell, ctx->cell_count2,
+                                       s));
+    ctx->hist_next = true;
+    ctx->hist_pos = pos;
+    ctx->hist_cell = cell;
+    ctx->hist_np = np;
+    // position (+ cell index) and velocity in and out, tile key out
+    bytes = (double)np * (2.0 * (12.0 + (poskind == PM_POS_CELLOFF ? 4.0 : 0.0)) + 24.0 + 4.0) +
+            4.0 * (double)ctx->n * ctx->n * ctx->n;
+  } else {
+    if (tiles)
+      PM_HIP(ctx, launch_interp_tile_phi(ctx, const_cast<float *>(pos), const_cast<int32_t *>(cell),
+                                         poskind, p->mas, phi, acc, vel, kick, 0.0f, nullptr,
+                                         nullptr, s));
+    else
+      PM_HIP(ctx, launch_interp(pos, cell, np, poskind, p->mas, ctx->n, ctx->g, acc, vel, kick, s));
+    // algorithmic bytes: position (12 B, + 4 B cell index), velocity in/out (24 B),
+    // acceleration out (12 B) per particle, and the force grid once (12 B per cell) or,
+    // with the gradient fused, the potential once (4 B per cell)
+    bytes = (double)np * (48.0 + (poskind == PM_POS_CELLOFF ? 4.0 : 0.0)) +
+            (tiles ? 4.0 : 12.0) * (double)ctx->n * ctx->n * ctx->n;
+  }
+  pm_kt_end(ctx, PM_KERNEL_INTERP, s, bytes);
+  if (next && !tiles && np > 0)
+    PM_HIP(ctx, launch_kick_drift(const_cast<float *>(pos), const_cast<int32_t *>(cell), vel, acc,
+                                  np, poskind, ctx->n, next->kick, next->dt, s));
   if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[5], s));
   return sst;
 }
@@ -313,6 +360,7 @@ void pm_destroy(pm_ctx *ctx) {
   fr(ctx->scan_partial);
   fr(ctx->reorder_tmp);
   fr(ctx->fix_grid);
+  fr(ctx->cell_count2);
   fr(ctx->adj_gbar);
   fr(ctx->adj_phibar);
   for (int i = 0; i < 8; ++i)
@@ -390,7 +438,7 @@ int pm_accel(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, int
   hipStream_t s = (hipStream_t)stream;
   const bool timing = params->timing && stats;
   st = accel_impl(ctx, pos, cell, np, poskind, a, params, phi, acc, nullptr, 0.f, stats, s, timing,
-                  1.0f);
+                  1.0f, nullptr);
   if (st >= 0 && timing) fill_timing(ctx, stats, false);
   return st;
 }
@@ -453,6 +501,7 @@ int pm_reorder(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, float *acc, i
     ctx->reorder_cap = cap;
   }
   hipStream_t s = (hipStream_t)stream;
+  ctx->hist_next = false;  // the particles move: a chained step's tile keys are stale
   const bool tile_major = (ctx->n % 8) == 0;
   PM_HIP(ctx, launch_sort_by_cell(ctx, pos, cell, np, poskind, s, tile_major ? 1 : 0));
   PM_HIP(ctx, launch_apply_perm(ctx, pos, poskind == PM_POS_CELLOFF ? cell : nullptr, vel, acc, ids,
@@ -496,8 +545,58 @@ int pm_kdk(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, int64_t np, int p
   const float warm_scale =
       params->mg.guess == PM_GUESS_WARM_RESCALED ? (float)((a1 / a0) * (a1 / a0)) : 1.0f;
   st = accel_impl(ctx, pos, cell, np, poskind, a1, params, phi, acc, vel, half, stats, s, timing,
-                  warm_scale);
+                  warm_scale, nullptr);
   if (st >= 0 && timing) fill_timing(ctx, stats, true);
+  return st;
+}
+
+int pm_kdk_chain(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, int64_t np, int poskind,
+                 double a0, double a1, double a2, int stage, const pm_step_params *params,
+                 float *phi, float *acc, pm_step_stats *stats, pm_stream stream) {
+  if (!ctx) return PM_ERR_ARG;
+  int st = check_particles(ctx, pos, cell, np, poskind);
+  if (st != PM_OK) return st;
+  st = check_step(ctx, params);
+  if (st != PM_OK) return st;
+  if (np > 0 && (!vel || !acc)) return pm_fail(ctx, PM_ERR_ARG, "null vel or acc");
+  if (!phi) return pm_fail(ctx, PM_ERR_ARG, "null phi");
+  if (stage != PM_CHAIN_FIRST && stage != PM_CHAIN_NEXT)
+    return pm_fail(ctx, PM_ERR_ARG, "stage must be PM_CHAIN_FIRST or PM_CHAIN_NEXT");
+  if (!(a0 > 0.0) || !(a1 > 0.0) || !std::isfinite(a0) || !std::isfinite(a1) || !std::isfinite(a2))
+    return pm_fail(ctx, PM_ERR_ARG, "scale factors must be > 0 and finite");
+  const bool more = a2 > a1;
+  hipStream_t s = (hipStream_t)stream;
+  const bool timing = params->timing && stats;
+  const double tau = 2.0 * (1.0 / std::sqrt(a0) - 1.0 / std::sqrt(a1));
+  const float half = (float)(0.5 * tau);
+  if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[0], s));
+  if (stage == PM_CHAIN_FIRST) {
+    // synchronised state at a0: the opening half-kick and the drift, as in pm_kdk
+    const bool fuse_hist = params->order == PM_DEPOSIT_SORTED && ctx->n % 8 == 0 && np > 0;
+    int32_t *pcell = nullptr, *count = nullptr;
+    if (fuse_hist) {
+      st = ensure_sort_scratch(ctx, np);
+      if (st != PM_OK) return st;
+      const int64_t ntiles = (int64_t)(ctx->n / 8) * (ctx->n / 8) * (ctx->n / 8);
+      PM_HIP(ctx, hipMemsetAsync(ctx->cell_count, 0, sizeof(int32_t) * (size_t)(ntiles + 1), s));
+      pcell = ctx->pcell;
+      count = ctx->cell_count;
+    }
+    PM_HIP(ctx, launch_kick_drift(pos, cell, vel, acc, np, poskind, ctx->n, half, (float)tau, s,
+                                  pcell, count));
+    ctx->hist_ready = fuse_hist;
+  }
+  const float warm_scale =
+      params->mg.guess == PM_GUESS_WARM_RESCALED ? (float)((a1 / a0) * (a1 / a0)) : 1.0f;
+  ChainNext next{};
+  if (more) {
+    const double tau2 = 2.0 * (1.0 / std::sqrt(a1) - 1.0 / std::sqrt(a2));
+    next.kick = (float)(0.5 * tau2);
+    next.dt = (float)tau2;
+  }
+  st = accel_impl(ctx, pos, cell, np, poskind, a1, params, phi, acc, vel, half, stats, s, timing,
+                  warm_scale, more ? &next : nullptr);
+  if (st >= 0 && timing) fill_timing(ctx, stats, stage == PM_CHAIN_FIRST);
   return st;
 }
 

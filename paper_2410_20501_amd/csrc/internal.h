@@ -55,6 +55,12 @@ struct pm_ctx {
   void *reorder_tmp;     // [np_max * 12 bytes] permutation staging (lazy)
   unsigned long long *fix_grid;  // [n^3] 2^-30 fixed-point density (sorted deposit, lazy, kept zero)
   bool hist_ready;       // tile histogram and keys of the current positions already made
+  // a chained step's fused drift leaves the next sort's tile histogram in cell_count2
+  // and its keys in pcell, valid for the particle arrays it names until they move
+  int32_t *cell_count2;  // [n^3 / 512 + 1]
+  bool hist_next;
+  const void *hist_pos, *hist_cell;
+  int64_t hist_np;
   int64_t reorder_cap;
   // reverse mode (lazy)
   float *adj_gbar;       // [n^3 * 3] cotangent of the force grid
@@ -114,10 +120,13 @@ hipError_t launch_deposit_own(pm_ctx *ctx, const float *pos, const int32_t *cell
 hipError_t launch_interp_tile(pm_ctx *ctx, const float *pos, const int32_t *cell, int poskind,
                               int mas, const float *g, float *acc, float *vel, float kick,
                               hipStream_t s);
-// the same with the 5-point gradient of phi formed per tile in LDS (no force grid)
-hipError_t launch_interp_tile_phi(pm_ctx *ctx, const float *pos, const int32_t *cell,
-                                  int poskind, int mas, const float *phi, float *acc, float *vel,
-                                  float kick, hipStream_t s);
+// the same with the 5-point gradient of phi formed per tile in LDS (no force grid);
+// with count != NULL the kicked particles also drift by dt, and their new tile keys
+// (pcell) and tile histogram (count, zeroed by the caller) are those of the next sort;
+// acc may be NULL (not written)
+hipError_t launch_interp_tile_phi(pm_ctx *ctx, float *pos, int32_t *cell, int poskind, int mas,
+                                  const float *phi, float *acc, float *vel, float kick, float dt,
+                                  int32_t *pcell, int32_t *count, hipStream_t s);
 hipError_t launch_interp(const float *pos, const int32_t *cell, int64_t np, int poskind, int mas,
                          int n, const float *g, float *acc, float *vel, float kick,
                          hipStream_t s);

@@ -28,6 +28,9 @@ namespace {
 #endif
 constexpr int SJ = PM_SMOOTH_SJ, SK = 64;  // interior tile of the smoother (SJ, SK even)
 constexpr int ST = PM_SMOOTH_THREADS;      // threads per smoother block
+#ifndef PM_SMOOTH_STAGE_FENCE
+#define PM_SMOOTH_STAGE_FENCE 0
+#endif
 #ifndef PM_SMOOTH_JFAST
 #define PM_SMOOTH_JFAST 0
 #endif
@@ -229,6 +232,7 @@ template <int R, int S, int H, bool NORM, bool OMEGA1>
 __device__ __forceinline__ void smooth_halves(SmoothState<H, NORM, OMEGA1> &c, int q) {
   if constexpr (S <= H) {
     smooth_half<R, S, H, NORM, OMEGA1>(c, q);
+    if constexpr (PM_SMOOTH_STAGE_FENCE) __builtin_amdgcn_sched_barrier(0);
     smooth_halves<R, S + 1, H, NORM, OMEGA1>(c, q);
   }
 }

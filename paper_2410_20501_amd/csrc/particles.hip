@@ -136,6 +136,50 @@ __device__ __forceinline__ WaveRun wave_runs(int key) {
 // for the new positions: the particle's 8^3-tile key goes to pcell and the tile
 // histogram gets one atomic per run of equal keys in a wave (same key rule as
 // k_cell_hist), which saves that kernel's re-read of the particles.
+// x += dt * v for particle p, wrapped (box) or carried into the cell index (cell
+// offset); writes pos (and cell) and returns the particle's 8^3-tile key.
+template <int PK>
+__device__ __forceinline__ int drift_one(float *__restrict__ pos, int32_t *__restrict__ cell,
+                                         int64_t p, int n, float dt, const float v[3]) {
+  float x[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) x[d] = pos[3 * p + d];
+  int ci[3];
+  if constexpr (PK == PM_POS_BOX) {
+    const float fn = (float)n;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      x[d] = wrap_unit(fmaf(dt, v[d], x[d]));
+      ci[d] = wrap_any((int)floorf(x[d] * fn), n);
+    }
+  } else {
+    const float scale = dt * (float)n;
+    const int c = wrap_any(cell[p], n * n * n);
+    const int nn = n * n;
+    ci[0] = c / nn;
+    ci[1] = (c / n) - (c / nn) * n;
+    ci[2] = c - (c / n) * n;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      float o = fmaf(scale, v[d], x[d]);
+      float fl = floorf(o);
+      o -= fl;
+      if (o >= 1.0f) {
+        o = 0.0f;
+        fl += 1.0f;
+      }
+      int q = (ci[d] + (int)fl) % n;
+      ci[d] = q < 0 ? q + n : q;
+      x[d] = o;
+    }
+    cell[p] = (ci[0] * n + ci[1]) * n + ci[2];
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) pos[3 * p + d] = x[d];
+  const int nt = n >> 3;
+  return ((ci[0] >> 3) * nt + (ci[1] >> 3)) * nt + (ci[2] >> 3);
+}
+
 template <int PK>
 __global__ __launch_bounds__(kThreads) void k_kick_drift(float *__restrict__ pos,
                                                          int32_t *__restrict__ cell,
@@ -148,51 +192,16 @@ __global__ __launch_bounds__(kThreads) void k_kick_drift(float *__restrict__ pos
   const bool live = p < np;
   int key = -1;
   if (live) {
-    float v[3], x[3];
+    float v[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       v[d] = vel[3 * p + d];
       if (acc) v[d] = fmaf(kick, acc[3 * p + d], v[d]);
-      x[d] = pos[3 * p + d];
-    }
-    int ci[3];
-    if constexpr (PK == PM_POS_BOX) {
-      const float fn = (float)n;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        x[d] = wrap_unit(fmaf(dt, v[d], x[d]));
-        ci[d] = wrap_any((int)floorf(x[d] * fn), n);
-      }
-    } else {
-      const float scale = dt * (float)n;
-      const int c = wrap_any(cell[p], n * n * n);
-      const int nn = n * n;
-      ci[0] = c / nn;
-      ci[1] = (c / n) - (c / nn) * n;
-      ci[2] = c - (c / n) * n;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        float o = fmaf(scale, v[d], x[d]);
-        float fl = floorf(o);
-        o -= fl;
-        if (o >= 1.0f) {
-          o = 0.0f;
-          fl += 1.0f;
-        }
-        int q = (ci[d] + (int)fl) % n;
-        ci[d] = q < 0 ? q + n : q;
-        x[d] = o;
-      }
-      cell[p] = (ci[0] * n + ci[1]) * n + ci[2];
-    }
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
       vel[3 * p + d] = v[d];
-      pos[3 * p + d] = x[d];
     }
+    const int k = drift_one<PK>(pos, cell, p, n, dt, v);
     if (count) {
-      const int nt = n >> 3;
-      key = ((ci[0] >> 3) * nt + (ci[1] >> 3)) * nt + (ci[2] >> 3);
+      key = k;
       pcell[p] = key;
     }
   }
@@ -676,16 +685,23 @@ __global__ __launch_bounds__(kOThreads) void k_interp_tile(const float *__restri
 // is staged in LDS, g = -grad phi (5-point central difference, same arithmetic as the
 // gradient kernel) is formed for the tile plus a one-cell halo, and the particles
 // gather from it; the force grid never goes to memory.
-template <int MAS, int PK>
-__global__ __launch_bounds__(kOThreads) void k_interp_tile_phi(const float *__restrict__ pos,
-                                                               const int32_t *__restrict__ cell,
+//
+// DRIFT: after the kick the particle also drifts by dt (the opening kick of the next
+// leapfrog step is folded into `kick`), and the new 8^3-tile key and histogram of the
+// next deposit's sort go to pcell and count, as in the kick-drift kernel. Each particle
+// is read and written by the one thread that owns it in its tile bucket.
+template <int MAS, int PK, bool DRIFT>
+__global__ __launch_bounds__(kOThreads) void k_interp_tile_phi(float *__restrict__ pos,
+                                                               int32_t *__restrict__ cell,
                                                                const int32_t *__restrict__ end,
                                                                const int32_t *__restrict__ perm,
                                                                int n,
                                                                const float *__restrict__ phi,
                                                                float *__restrict__ acc,
                                                                float *__restrict__ vel,
-                                                               float kick) {
+                                                               float kick, float dt,
+                                                               int32_t *__restrict__ pcell,
+                                                               int32_t *__restrict__ count) {
   constexpr int PH = kTT + 6;  // tile + 3 cells per side
   __shared__ float ps[PH * PH * PH];
   __shared__ float gs[3][kTHalo];
@@ -716,41 +732,61 @@ __global__ __launch_bounds__(kOThreads) void k_interp_tile_phi(const float *__re
   __syncthreads();
   const int p_begin = tile > 0 ? end[tile - 1] : 0;
   const int p_end = end[tile];
-  for (int l = p_begin + (int)threadIdx.x; l < p_end; l += kOThreads) {
-    const int p = perm[l];
-    int c[3];
-    float o[3];
-    particle_cell<PK>(pos, cell, p, n, c, o);
-    const int lx = c[0] - ti * kTT, ly = c[1] - tj * kTT, lz = c[2] - tk * kTT;
-    if ((unsigned)lx >= (unsigned)kTT || (unsigned)ly >= (unsigned)kTT ||
-        (unsigned)lz >= (unsigned)kTT)
-      continue;  // not this tile's particle (cannot happen with the same cell rule)
-    float wx[MAS], wy[MAS], wz[MAS];
-    const int fx = axis_off<MAS>(lx + 1, o[0], wx);
-    const int fy = axis_off<MAS>(ly + 1, o[1], wy);
-    const int fz = axis_off<MAS>(lz + 1, o[2], wz);
-    float ax = 0.f, ay = 0.f, az = 0.f;
+  // uniform trip count: with DRIFT the whole wave takes part in the histogram's run
+  // detection
+  for (int l0 = p_begin; l0 < p_end; l0 += kOThreads) {
+    const int l = l0 + (int)threadIdx.x;
+    int key = -1;
+    if (l < p_end) {
+      const int p = perm[l];
+      int c[3];
+      float o[3];
+      particle_cell<PK>(pos, cell, p, n, c, o);
+      const int lx = c[0] - ti * kTT, ly = c[1] - tj * kTT, lz = c[2] - tk * kTT;
+      // every particle of the bucket lies in this tile (same cell rule as the sort)
+      if ((unsigned)lx < (unsigned)kTT && (unsigned)ly < (unsigned)kTT &&
+          (unsigned)lz < (unsigned)kTT) {
+        float wx[MAS], wy[MAS], wz[MAS];
+        const int fx = axis_off<MAS>(lx + 1, o[0], wx);
+        const int fy = axis_off<MAS>(ly + 1, o[1], wy);
+        const int fz = axis_off<MAS>(lz + 1, o[2], wz);
+        float ax = 0.f, ay = 0.f, az = 0.f;
 #pragma unroll
-    for (int a = 0; a < MAS; ++a)
+        for (int a = 0; a < MAS; ++a)
 #pragma unroll
-      for (int b = 0; b < MAS; ++b) {
-        const float wab = wx[a] * wy[b];
-        const int row = ((fx + a) * kTH + (fy + b)) * kTH + fz;
+          for (int b = 0; b < MAS; ++b) {
+            const float wab = wx[a] * wy[b];
+            const int row = ((fx + a) * kTH + (fy + b)) * kTH + fz;
 #pragma unroll
-        for (int cc = 0; cc < MAS; ++cc) {
-          const float wc = wab * wz[cc];
-          ax = fmaf(wc, gs[0][row + cc], ax);
-          ay = fmaf(wc, gs[1][row + cc], ay);
-          az = fmaf(wc, gs[2][row + cc], az);
+            for (int cc = 0; cc < MAS; ++cc) {
+              const float wc = wab * wz[cc];
+              ax = fmaf(wc, gs[0][row + cc], ax);
+              ay = fmaf(wc, gs[1][row + cc], ay);
+              az = fmaf(wc, gs[2][row + cc], az);
+            }
+          }
+        if (acc) {
+          acc[3 * (size_t)p + 0] = ax;
+          acc[3 * (size_t)p + 1] = ay;
+          acc[3 * (size_t)p + 2] = az;
+        }
+        if (vel) {
+          float v[3];
+          v[0] = fmaf(kick, ax, vel[3 * (size_t)p + 0]);
+          v[1] = fmaf(kick, ay, vel[3 * (size_t)p + 1]);
+          v[2] = fmaf(kick, az, vel[3 * (size_t)p + 2]);
+#pragma unroll
+          for (int d = 0; d < 3; ++d) vel[3 * (size_t)p + d] = v[d];
+          if constexpr (DRIFT) {
+            key = drift_one<PK>(pos, cell, p, n, dt, v);
+            pcell[p] = key;
+          }
         }
       }
-    acc[3 * (size_t)p + 0] = ax;
-    acc[3 * (size_t)p + 1] = ay;
-    acc[3 * (size_t)p + 2] = az;
-    if (vel) {
-      vel[3 * (size_t)p + 0] = fmaf(kick, ax, vel[3 * (size_t)p + 0]);
-      vel[3 * (size_t)p + 1] = fmaf(kick, ay, vel[3 * (size_t)p + 1]);
-      vel[3 * (size_t)p + 2] = fmaf(kick, az, vel[3 * (size_t)p + 2]);
+    }
+    if constexpr (DRIFT) {
+      const WaveRun r = wave_runs(key);
+      if (r.head && key >= 0) atomicAdd(&count[key], r.len);
     }
   }
 }
@@ -892,14 +928,22 @@ hipError_t launch_interp_tile(pm_ctx *ctx, const float *pos, const int32_t *cell
   return hipGetLastError();
 }
 
-hipError_t launch_interp_tile_phi(pm_ctx *ctx, const float *pos, const int32_t *cell,
-                                  int poskind, int mas, const float *phi, float *acc, float *vel,
-                                  float kick, hipStream_t s) {
+hipError_t launch_interp_tile_phi(pm_ctx *ctx, float *pos, int32_t *cell, int poskind, int mas,
+                                  const float *phi, float *acc, float *vel, float kick, float dt,
+                                  int32_t *pcell, int32_t *count, hipStream_t s) {
   const int n = ctx->n;
   const unsigned nt = (unsigned)((int64_t)n * n * n / kTThreads);
-#define PM_ITP(M, K)                                                                          \
-  k_interp_tile_phi<M, K><<<nt, kOThreads, 0, s>>>(pos, cell, ctx->cell_count, ctx->perm, n, phi, \
-                                                   acc, vel, kick)
+  const bool drift = count != nullptr;
+  if (drift && (!vel || !pcell)) return hipErrorInvalidValue;
+#define PM_ITP(M, K)                                                                             \
+  do {                                                                                           \
+    if (drift)                                                                                   \
+      k_interp_tile_phi<M, K, true><<<nt, kOThreads, 0, s>>>(                                    \
+          pos, cell, ctx->cell_count, ctx->perm, n, phi, acc, vel, kick, dt, pcell, count);      \
+    else                                                                                         \
+      k_interp_tile_phi<M, K, false><<<nt, kOThreads, 0, s>>>(                                   \
+          pos, cell, ctx->cell_count, ctx->perm, n, phi, acc, vel, kick, dt, nullptr, nullptr);  \
+  } while (0)
   if (mas == PM_TSC) {
     if (poskind == PM_POS_BOX) PM_ITP(3, PM_POS_BOX);
     else PM_ITP(3, PM_POS_CELLOFF);

@@ -25,6 +25,7 @@ PM_POS_BOX, PM_POS_CELLOFF = 0, 1
 PM_RESTRICT_FW, PM_RESTRICT_AVG = 0, 1
 PM_SOLVER_MG, PM_SOLVER_FFT = 0, 1
 PM_GUESS_JACOBI, PM_GUESS_WARM, PM_GUESS_WARM_RESCALED = 0, 1, 2
+PM_CHAIN_FIRST, PM_CHAIN_NEXT = 0, 1
 PM_CREATE_REFERENCE_KERNELS = 1
 PM_KERNEL_NONE, PM_KERNEL_DEPOSIT, PM_KERNEL_SMOOTH, PM_KERNEL_INTERP = 0, 1, 2, 3
 
@@ -87,6 +88,8 @@ def _load():
         "pm_reorder": (c_int, [P, P, P, P, P, P, c_int64, c_int, P]),
         "pm_kdk": (c_int, [P, P, P, P, c_int64, c_int, c_double, c_double, POINTER(StepParams),
                            P, P, POINTER(StepStats), P]),
+        "pm_kdk_chain": (c_int, [P, P, P, P, c_int64, c_int, c_double, c_double, c_double, c_int,
+                                 POINTER(StepParams), P, P, POINTER(StepStats), P]),
         "pm_deposit_vjp": (c_int, [P, P, P, c_int64, c_int, c_int, P, P, P]),
         "pm_interp_vjp": (c_int, [P, P, P, c_int64, c_int, c_int, P, P, P, P, P]),
         "pm_gradient_vjp": (c_int, [P, P, c_int, P, P]),
@@ -298,6 +301,22 @@ def pm_kdk(ctx: Context, pos, vel, a0, a1, phi, acc, cell=None, params: StepPara
                      float(a0), float(a1), byref(params), _ptr(phi, shape=(n, n, n), name="phi"),
                      _ptr(acc, shape=(np_, 3), name="acc"), byref(stats), _stream())
     ctx._check(st, "pm_kdk")
+    return stats
+
+
+def pm_kdk_chain(ctx: Context, pos, vel, a0, a1, a2, stage, phi, acc, cell=None,
+                 params: StepParams | None = None):
+    """One step a0 -> a1 of a chain of KDK steps (a2 <= a1: last step); stage is
+    PM_CHAIN_FIRST or PM_CHAIN_NEXT (include/hippm.h)."""
+    n = ctx.n
+    np_, kind, pp, cp = _particles(pos, cell)
+    params = params or default_step_params()
+    stats = StepStats()
+    st = _lib.pm_kdk_chain(ctx.handle, pp, cp, _ptr(vel, shape=(np_, 3), name="vel"), np_, kind,
+                           float(a0), float(a1), float(a2), int(stage), byref(params),
+                           _ptr(phi, shape=(n, n, n), name="phi"),
+                           _ptr(acc, shape=(np_, 3), name="acc"), byref(stats), _stream())
+    ctx._check(st, "pm_kdk_chain")
     return stats
 
 
