@@ -139,11 +139,10 @@ __device__ __forceinline__ WaveRun wave_runs(int key) {
 // x += dt * v for particle p, wrapped (box) or carried into the cell index (cell
 // offset); writes pos (and cell) and returns the particle's 8^3-tile key.
 template <int PK>
-__device__ __forceinline__ int drift_one(float *__restrict__ pos, int32_t *__restrict__ cell,
-                                         int64_t p, int n, float dt, const float v[3]) {
-  float x[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) x[d] = pos[3 * p + d];
+__device__ __forceinline__ int drift_from(float *__restrict__ pos, int32_t *__restrict__ cell,
+                                          int64_t p, int n, float dt, const float v[3],
+                                          const float xin[3], int cin) {
+  float x[3] = {xin[0], xin[1], xin[2]};
   int ci[3];
   if constexpr (PK == PM_POS_BOX) {
     const float fn = (float)n;
@@ -154,7 +153,7 @@ __device__ __forceinline__ int drift_one(float *__restrict__ pos, int32_t *__res
     }
   } else {
     const float scale = dt * (float)n;
-    const int c = wrap_any(cell[p], n * n * n);
+    const int c = wrap_any(cin, n * n * n);
     const int nn = n * n;
     ci[0] = c / nn;
     ci[1] = (c / n) - (c / nn) * n;
@@ -178,6 +177,13 @@ __device__ __forceinline__ int drift_one(float *__restrict__ pos, int32_t *__res
   for (int d = 0; d < 3; ++d) pos[3 * p + d] = x[d];
   const int nt = n >> 3;
   return ((ci[0] >> 3) * nt + (ci[1] >> 3)) * nt + (ci[2] >> 3);
+}
+
+template <int PK>
+__device__ __forceinline__ int drift_one(float *__restrict__ pos, int32_t *__restrict__ cell,
+                                         int64_t p, int n, float dt, const float v[3]) {
+  const float x[3] = {pos[3 * p + 0], pos[3 * p + 1], pos[3 * p + 2]};
+  return drift_from<PK>(pos, cell, p, n, dt, v, x, PK == PM_POS_BOX ? 0 : cell[p]);
 }
 
 template <int PK>
@@ -517,6 +523,62 @@ inline unsigned blocks_for(int64_t count, int threads) {
 // moments across lanes.
 constexpr int kOThreads = 256;
 
+// One particle of a tile bucket, loaded ahead of its use.
+struct TileParticle {
+  bool live;
+  int p, c;    // particle index, cell index (cell-offset positions)
+  float x[3];  // box-unit position or in-cell offset
+  float v[3];  // velocity (when the kernel kicks)
+};
+
+template <int PK>
+__device__ __forceinline__ TileParticle load_tile_particle(const float *__restrict__ pos,
+                                                           const int32_t *__restrict__ cell,
+                                                           const int32_t *__restrict__ perm,
+                                                           const float *__restrict__ vel, int l0,
+                                                           int p_end) {
+  TileParticle t{};
+  const int l = l0 + (int)threadIdx.x;
+  t.live = l < p_end;
+  if (t.live) {
+    t.p = perm[l];
+    const size_t q = 3 * (size_t)t.p;
+    t.x[0] = pos[q];
+    t.x[1] = pos[q + 1];
+    t.x[2] = pos[q + 2];
+    t.c = PK == PM_POS_BOX ? 0 : cell[t.p];
+    if (vel) {
+      t.v[0] = vel[q];
+      t.v[1] = vel[q + 1];
+      t.v[2] = vel[q + 2];
+    }
+  }
+  return t;
+}
+
+// cell and in-cell offset of a loaded particle (the particle_cell rule)
+template <int PK>
+__device__ __forceinline__ void cell_offset_of(const float x[3], int cin, int n, int c[3],
+                                               float o[3]) {
+  if constexpr (PK == PM_POS_BOX) {
+    const float fn = (float)n;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const float u = x[d] * fn;
+      const float fl = floorf(u);
+      c[d] = wrap_any((int)fl, n);
+      o[d] = u - fl;
+    }
+  } else {
+    const int q = wrap_any(cin, n * n * n);
+    c[0] = q / (n * n);
+    c[1] = (q / n) - c[0] * n;
+    c[2] = q - (q / n) * n;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) o[d] = x[d];
+  }
+}
+
 template <int MAS, int PK>
 __global__ __launch_bounds__(kOThreads) void k_deposit_own(const float *__restrict__ pos,
                                                            const int32_t *__restrict__ cell,
@@ -528,17 +590,24 @@ __global__ __launch_bounds__(kOThreads) void k_deposit_own(const float *__restri
   const int nt = n / kTT;
   const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
   const int tk = tile % nt, tj = (tile / nt) % nt, ti = tile / (nt * nt);
-  for (int i = threadIdx.x; i < kTHalo; i += kOThreads) box[i] = 0ull;
-  __syncthreads();
-  // particles bucketed by tile: end[t] is the end of tile t's bucket
+  // particles bucketed by tile: end[t] is the end of tile t's bucket; the first pass's
+  // particles are loaded before the box is cleared, each later pass's during the one
+  // before it
   const int p_begin = tile > 0 ? end[tile - 1] : 0;
   const int p_end = end[tile];
+  TileParticle cur{};
+  if (p_begin < p_end) cur = load_tile_particle<PK>(pos, cell, perm, nullptr, p_begin, p_end);
+  for (int i = threadIdx.x; i < kTHalo; i += kOThreads) box[i] = 0ull;
+  __syncthreads();
   for (int l0 = p_begin; l0 < p_end; l0 += kOThreads) {
-    const int l = l0 + threadIdx.x;
-    bool act = l < p_end;
+    TileParticle nxt{};
+    if (l0 + kOThreads < p_end)
+      nxt = load_tile_particle<PK>(pos, cell, perm, nullptr, l0 + kOThreads, p_end);
+    bool act = cur.live;
     int c[3] = {0, 0, 0};
     float o[3] = {0.f, 0.f, 0.f};
-    if (act) particle_cell<PK>(pos, cell, perm[l], n, c, o);
+    if (act) cell_offset_of<PK>(cur.x, cur.c, n, c, o);
+    cur = nxt;
     const int lx = c[0] - ti * kTT, ly = c[1] - tj * kTT, lz = c[2] - tk * kTT;
     // every particle of the bucket lies in this tile (same cell rule as the sort)
     act = act && (unsigned)lx < (unsigned)kTT && (unsigned)ly < (unsigned)kTT &&
@@ -709,6 +778,10 @@ __global__ __launch_bounds__(kOThreads) void k_interp_tile_phi(float *__restrict
   const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
   const int tk = tile % nt, tj = (tile / nt) % nt, ti = tile / (nt * nt);
   const int i0 = ti * kTT - 3, j0 = tj * kTT - 3, k0 = tk * kTT - 3;
+  const int p_begin = tile > 0 ? end[tile - 1] : 0;
+  const int p_end = end[tile];
+  TileParticle cur{};
+  if (p_begin < p_end) cur = load_tile_particle<PK>(pos, cell, perm, vel, p_begin, p_end);
   for (int e = threadIdx.x; e < PH * PH * PH; e += kOThreads) {
     const int hx = e / (PH * PH), hy = (e / PH) % PH, hz = e % PH;
     ps[e] = phi[((size_t)wrap_index(i0 + hx, n) * n + wrap_index(j0 + hy, n)) * n +
@@ -730,18 +803,19 @@ __global__ __launch_bounds__(kOThreads) void k_interp_tile_phi(float *__restrict
     gs[2][h] = -inv_h * gz;
   }
   __syncthreads();
-  const int p_begin = tile > 0 ? end[tile - 1] : 0;
-  const int p_end = end[tile];
   // uniform trip count: with DRIFT the whole wave takes part in the histogram's run
-  // detection
+  // detection. Each pass loads the particles of the next pass before it works on its
+  // own, and the first pass's particles are loaded before the potential is staged.
   for (int l0 = p_begin; l0 < p_end; l0 += kOThreads) {
-    const int l = l0 + (int)threadIdx.x;
+    TileParticle nxt{};
+    if (l0 + kOThreads < p_end)
+      nxt = load_tile_particle<PK>(pos, cell, perm, vel, l0 + kOThreads, p_end);
     int key = -1;
-    if (l < p_end) {
-      const int p = perm[l];
+    if (cur.live) {
+      const int p = cur.p;
       int c[3];
       float o[3];
-      particle_cell<PK>(pos, cell, p, n, c, o);
+      cell_offset_of<PK>(cur.x, cur.c, n, c, o);
       const int lx = c[0] - ti * kTT, ly = c[1] - tj * kTT, lz = c[2] - tk * kTT;
       // every particle of the bucket lies in this tile (same cell rule as the sort)
       if ((unsigned)lx < (unsigned)kTT && (unsigned)ly < (unsigned)kTT &&
@@ -772,13 +846,13 @@ __global__ __launch_bounds__(kOThreads) void k_interp_tile_phi(float *__restrict
         }
         if (vel) {
           float v[3];
-          v[0] = fmaf(kick, ax, vel[3 * (size_t)p + 0]);
-          v[1] = fmaf(kick, ay, vel[3 * (size_t)p + 1]);
-          v[2] = fmaf(kick, az, vel[3 * (size_t)p + 2]);
+          v[0] = fmaf(kick, ax, cur.v[0]);
+          v[1] = fmaf(kick, ay, cur.v[1]);
+          v[2] = fmaf(kick, az, cur.v[2]);
 #pragma unroll
           for (int d = 0; d < 3; ++d) vel[3 * (size_t)p + d] = v[d];
           if constexpr (DRIFT) {
-            key = drift_one<PK>(pos, cell, p, n, dt, v);
+            key = drift_from<PK>(pos, cell, p, n, dt, v, cur.x, cur.c);
             pcell[p] = key;
           }
         }
@@ -788,8 +862,10 @@ __global__ __launch_bounds__(kOThreads) void k_interp_tile_phi(float *__restrict
       const WaveRun r = wave_runs(key);
       if (r.head && key >= 0) atomicAdd(&count[key], r.len);
     }
+    cur = nxt;
   }
 }
+
 
 }  // namespace
 
