@@ -109,7 +109,8 @@ int ensure_sort_scratch(pm_ctx *ctx, int64_t np) {
 }
 
 int deposit_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, int poskind,
-                 int mas, int order, float *rho, hipStream_t s) {
+                 int mas, int order, float *rho, hipStream_t s, bool *mean_ready = nullptr) {
+  if (mean_ready) *mean_ready = false;
   const int n = ctx->n;
   const int64_t ncell = (int64_t)n * n * n;
   const float mass = np > 0 ? (float)((double)ncell / (double)np) : 0.0f;
@@ -138,7 +139,12 @@ int deposit_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np,
     PM_HIP(ctx, launch_sort_by_cell(ctx, pos, cell, np, poskind, s, tiles ? 2 : 0, hist));
     pm_kt_begin(ctx, PM_KERNEL_DEPOSIT, s);
     if (tiles)
-      PM_HIP(ctx, launch_deposit_own(ctx, pos, cell, poskind, mas, mass, rho, s));
+    {
+      // the mean of rho comes exactly from the fixed-point sums when the caller wants it
+      PM_HIP(ctx, launch_deposit_own(ctx, pos, cell, poskind, mas, mass, rho,
+                                     mean_ready ? ctx->mean_f : nullptr, s));
+      if (mean_ready) *mean_ready = true;
+    }
     else
       PM_HIP(ctx, launch_deposit_pull(ctx, pos, np, poskind, mas, mass, rho, s));
     // algorithmic bytes: in-cell offsets (12 B per particle) + the density (4 B per cell)
@@ -151,9 +157,9 @@ int deposit_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np,
 }
 
 int solve_impl(pm_ctx *ctx, const pm_step_params *p, const float *rho, float coef, float *phi,
-               pm_mg_stats *st, hipStream_t s, float warm_scale) {
+               pm_mg_stats *st, hipStream_t s, float warm_scale, bool rho_mean_ready = false) {
   if (p->solver == PM_SOLVER_FFT) return pm_fft_solve(ctx, rho, coef, p->fft_deconv, phi, s);
-  return pm_mg_solve(ctx, rho, coef, phi, &p->mg, st, s, warm_scale);
+  return pm_mg_solve(ctx, rho, coef, phi, &p->mg, st, s, warm_scale, rho_mean_ready);
 }
 
 // deposit -> solve -> gradient -> interp (+ optional kick on vel)
@@ -167,11 +173,13 @@ int accel_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, i
                pm_step_stats *stats, hipStream_t s, bool timing, float warm_scale,
                const ChainNext *next) {
   if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[1], s));
-  int st = deposit_impl(ctx, pos, cell, np, poskind, p->mas, p->order, ctx->rho, s);
+  bool mean_ready = false;
+  int st = deposit_impl(ctx, pos, cell, np, poskind, p->mas, p->order, ctx->rho, s, &mean_ready);
   if (st != PM_OK) return st;
   if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[2], s));
   const float coef = (float)(1.5 * a * p->omega_m);
-  const int sst = solve_impl(ctx, p, ctx->rho, coef, phi, stats ? &stats->mg : nullptr, s, warm_scale);
+  const int sst = solve_impl(ctx, p, ctx->rho, coef, phi, stats ? &stats->mg : nullptr, s, warm_scale,
+                             mean_ready);
   if (sst < 0) return sst;
   if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[3], s));
   // with the tile buckets of these positions (sorted deposit on tiles), the gradient is
@@ -315,7 +323,7 @@ int pm_create(pm_ctx **out, int n, int64_t np_max, int flags) {
   int st = PM_OK;
   if (hipMalloc(&ctx->rho, sizeof(float) * ncell) != hipSuccess ||
       hipMalloc(&ctx->g, 3 * sizeof(float) * ncell) != hipSuccess ||
-      hipMalloc(&ctx->red_partial, 2 * sizeof(double) * RED_PARTIAL_CAP) != hipSuccess ||
+      hipMalloc(&ctx->red_partial, 3 * sizeof(double) * RED_PARTIAL_CAP) != hipSuccess ||
       hipMalloc(&ctx->red_result, 4 * sizeof(double)) != hipSuccess ||
       hipMalloc(&ctx->mean_f, 4 * sizeof(float)) != hipSuccess ||
       hipHostMalloc(&ctx->host_result, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess)

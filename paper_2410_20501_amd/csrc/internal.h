@@ -114,7 +114,7 @@ hipError_t launch_apply_perm(pm_ctx *ctx, float *pos, int32_t *cell, float *vel,
 hipError_t launch_deposit_pull(pm_ctx *ctx, const float *pos, int64_t np, int poskind, int mas,
                                float mass, float *rho, hipStream_t s);
 hipError_t launch_deposit_own(pm_ctx *ctx, const float *pos, const int32_t *cell, int poskind,
-                              int mas, float mass, float *rho, hipStream_t s);
+                              int mas, float mass, float *rho, float *mean, hipStream_t s);
 // interpolation (+ kick) through the tile buckets left by the sorted deposit of the
 // same positions (n % 8 == 0)
 hipError_t launch_interp_tile(pm_ctx *ctx, const float *pos, const int32_t *cell, int poskind,
@@ -158,15 +158,21 @@ hipError_t launch_sum_moments(const float *x, int64_t count, double *partial, do
                               float *mean_out, hipStream_t s);
 
 // mg.hip
+// rho_mean_ready: ctx->mean_f[0] already holds the mean of rho (the sorted deposit's
+// conversion pass sums its exact fixed-point values), so the solve does not re-read rho
 int pm_mg_solve(pm_ctx *ctx, const float *rho, float coef, float *phi, const pm_mg_params *p,
-                pm_mg_stats *stats, hipStream_t s, float warm_scale = 1.0f);
+                pm_mg_stats *stats, hipStream_t s, float warm_scale = 1.0f,
+                bool rho_mean_ready = false);
 int pm_mg_setup(pm_ctx *ctx);
 
 // mg_stream.hip
 int64_t smooth_stream_blocks(int n);
+// partial != NULL: the pass also sums ||f - L u||^2, ||f||^2 and sum u of its input,
+// three doubles per block; uscale multiplies the input as it is read
 hipError_t launch_smooth_stream(const float *uin, float *uout, const float *f, float fscale,
                                 const float *fmean, int n, float h2, float omega,
-                                int first_colour, int half_sweeps, double *partial, hipStream_t s);
+                                int first_colour, int half_sweeps, double *partial,
+                                float uscale, hipStream_t s);
 // residual + restriction in one streaming pass; with ucg != NULL also the coarse
 // starting guess ucg = gscale * fc
 hipError_t launch_rr_stream(const float *u, const float *f, float fscale, const float *fmean,

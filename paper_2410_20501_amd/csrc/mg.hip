@@ -284,6 +284,42 @@ __global__ __launch_bounds__(kThreads) void k_subtract_mean(float *__restrict__ 
   u[c] -= *mean;
 }
 
+// Totals of the three per-block sums of the norm-summing smoother pass.
+__global__ __launch_bounds__(RED_THREADS) void k_triple_final(const double *__restrict__ partial,
+                                                              int nblocks,
+                                                              double *__restrict__ result) {
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblocks; b += RED_THREADS)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) v[i] += partial[3 * b + i];
+  __shared__ double l[3][RED_THREADS / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    v[i] = wave_sum(v[i]);
+    if (lane == 0) l[i][wave] = v[i];
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double a = 0.0;
+    for (int w = 0; w < RED_THREADS / 64; ++w) a += l[threadIdx.x][w];
+    result[threadIdx.x] = a;
+  }
+}
+
+// phi = scale * u - mean, with the mean (of scale * u) from a device sum: the copy of
+// the final iterate, its warm-start rescaling (when no cycle ran) and the gauge in one
+// pass.
+__global__ __launch_bounds__(kThreads) void k_finish_phi(const float *__restrict__ u,
+                                                         float *__restrict__ phi, int64_t count,
+                                                         float scale,
+                                                         const double *__restrict__ sum) {
+  const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (c >= count) return;
+  const float mean = (float)(*sum / (double)count);
+  phi[c] = fmaf(scale, u[c], -mean);
+}
+
 // Coarsest level: one workgroup, in LDS (coarse_solve.h).
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_solve(
     float *__restrict__ ug, const float *__restrict__ fg, float scale,
@@ -339,7 +375,8 @@ struct Solver {
 
   // streaming smoothing of `sweeps` full sweeps; the first pass may sum the residual
   // norm of its input.
-  hipError_t stream_sweeps(int l, int first_colour, int sweeps, double *partial) {
+  hipError_t stream_sweeps(int l, int first_colour, int sweeps, double *partial,
+                           float uscale = 1.0f) {
     const int n = ctx->lev[l].n;
     const Src sr = src(l);
     hipError_t e = hipSuccess;
@@ -347,12 +384,13 @@ struct Solver {
       const int now = sweeps >= 2 ? 2 : 1;
       if (l == 0) pm_kt_begin(ctx, PM_KERNEL_SMOOTH, s);
       e = launch_smooth_stream(cur[l], alt[l], sr.f, sr.scale, sr.mean, n, h2(l), p->omega,
-                               first_colour, 2 * now, partial, s);
+                               first_colour, 2 * now, partial, uscale, s);
       // algorithmic bytes of one pass (any number of fused sweeps): read u and f,
       // write u, 4 B each per cell
       if (l == 0) pm_kt_end(ctx, PM_KERNEL_SMOOTH, s, 12.0 * (double)n * n * n);
       std::swap(cur[l], alt[l]);
       partial = nullptr;
+      uscale = 1.0f;
       sweeps -= now;
     }
     return e;
@@ -464,22 +502,30 @@ int pm_mg_setup(pm_ctx *ctx) {
 }
 
 int pm_mg_solve(pm_ctx *ctx, const float *rho, float coef, float *phi, const pm_mg_params *p,
-                pm_mg_stats *stats, hipStream_t s, float warm_scale) {
+                pm_mg_stats *stats, hipStream_t s, float warm_scale, bool rho_mean_ready) {
   const int n = ctx->n;
   const int64_t count = (int64_t)n * n * n;
   // mean of the density, kept on the device
-  PM_HIP(ctx, launch_sum_moments(rho, count, ctx->red_partial, ctx->red_result, ctx->mean_f, s));
+  if (!rho_mean_ready)
+    PM_HIP(ctx, launch_sum_moments(rho, count, ctx->red_partial, ctx->red_result, ctx->mean_f, s));
   Solver sv{ctx, s, p, Src{rho, coef, ctx->mean_f}, {}, {}};
   for (int l = 0; l < ctx->nlevels; ++l) {
     sv.cur[l] = l == 0 ? phi : ctx->lev[l].u;
     sv.alt[l] = ctx->lev[l].alt;
   }
+  const bool fused_norm = sv.streaming(0) && p->pre > 0 && ctx->nlevels > 1;
+  // with the fused norm, the tolerance loop's first pass reads the warm start rescaled
+  float uscale = 1.0f;
   if (p->guess == PM_GUESS_JACOBI)
     k_jacobi_guess<<<blocks_for(count, kThreads), kThreads, 0, s>>>(phi, rho, coef, ctx->mean_f,
                                                                      count, sv.h2(0));
+  else if (warm_scale != 1.0f && fused_norm && p->fixed_cycles <= 0)
+    uscale = warm_scale;
   else if (warm_scale != 1.0f)
     k_scale<<<blocks_for(count, kThreads), kThreads, 0, s>>>(phi, count, warm_scale);
-  const bool fused_norm = sv.streaming(0) && p->pre > 0 && ctx->nlevels > 1;
+  // the final iterate's sum, when a norm pass has taken it (ctx->red_result[2])
+  bool have_sum = false;
+  float final_scale = 1.0f;
   int status = PM_OK;
   int cycles = 0;
   if (p->fixed_cycles > 0) {
@@ -494,8 +540,9 @@ int pm_mg_solve(pm_ctx *ctx, const float *rho, float coef, float *phi, const pm_
       // pass when streaming (its output is used only if another cycle is needed)
       if (fused_norm) {
         const int64_t nb = smooth_stream_blocks(n);
-        PM_HIP(ctx, sv.stream_sweeps(0, 0, std::min(p->pre, 2), ctx->red_partial));
-        k_pair_final<<<1, RED_THREADS, 0, s>>>(ctx->red_partial, (int)nb, ctx->red_result);
+        PM_HIP(ctx, sv.stream_sweeps(0, 0, std::min(p->pre, 2), ctx->red_partial,
+                                     cycles == 0 ? uscale : 1.0f));
+        k_triple_final<<<1, RED_THREADS, 0, s>>>(ctx->red_partial, (int)nb, ctx->red_result);
       } else {
         sv.norms();
       }
@@ -505,7 +552,7 @@ int pm_mg_solve(pm_ctx *ctx, const float *rho, float coef, float *phi, const pm_
       if (cycles == 0) fnorm = sqrt(ctx->host_result[1]);
       if (fnorm == 0.0) {
         if (fused_norm) std::swap(sv.cur[0], sv.alt[0]);  // drop the speculative pass
-        PM_HIP(ctx, hipMemsetAsync(phi, 0, sizeof(float) * count, s));
+        PM_HIP(ctx, launch_fill(phi, 0.0f, count, s));
         if (stats) {
           stats->cycles = 0;
           stats->status = PM_OK;
@@ -520,7 +567,11 @@ int pm_mg_solve(pm_ctx *ctx, const float *rho, float coef, float *phi, const pm_
         status = PM_WARN_FLOOR;
       }
       if (status != PM_WARN_NOT_CONVERGED || cycles == p->max_cycles) {
-        if (fused_norm) std::swap(sv.cur[0], sv.alt[0]);  // keep the tested iterate
+        if (fused_norm) {
+          std::swap(sv.cur[0], sv.alt[0]);  // keep the tested iterate
+          have_sum = true;                  // its sum came with its norm
+          if (cycles == 0) final_scale = uscale;  // read rescaled, stored as it was
+        }
         break;
       }
       if (fused_norm) {
@@ -535,11 +586,18 @@ int pm_mg_solve(pm_ctx *ctx, const float *rho, float coef, float *phi, const pm_
     if (stats)
       for (int c = 0; c <= cycles; ++c) stats->relres[c] = rel[c];
   }
-  if (sv.cur[0] != phi)
-    PM_HIP(ctx, hipMemcpyAsync(phi, sv.cur[0], sizeof(float) * count, hipMemcpyDeviceToDevice, s));
-  // remove the mean of phi (gauge)
-  PM_HIP(ctx, launch_sum_moments(phi, count, ctx->red_partial, ctx->red_result, ctx->mean_f + 1, s));
-  k_subtract_mean<<<blocks_for(count, kThreads), kThreads, 0, s>>>(phi, count, ctx->mean_f + 1);
+  if (have_sum) {
+    // copy (when the iterate is in the other buffer), rescale (when no cycle ran) and
+    // remove the mean (gauge) in one pass
+    k_finish_phi<<<blocks_for(count, kThreads), kThreads, 0, s>>>(sv.cur[0], phi, count,
+                                                                   final_scale, ctx->red_result + 2);
+  } else {
+    if (sv.cur[0] != phi)
+      PM_HIP(ctx, hipMemcpyAsync(phi, sv.cur[0], sizeof(float) * count, hipMemcpyDeviceToDevice, s));
+    // remove the mean of phi (gauge)
+    PM_HIP(ctx, launch_sum_moments(phi, count, ctx->red_partial, ctx->red_result, ctx->mean_f + 1, s));
+    k_subtract_mean<<<blocks_for(count, kThreads), kThreads, 0, s>>>(phi, count, ctx->mean_f + 1);
+  }
   PM_HIP(ctx, hipGetLastError());
   if (stats) {
     stats->cycles = cycles;

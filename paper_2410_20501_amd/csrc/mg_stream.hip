@@ -54,25 +54,29 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 template <int NT>
-__device__ void block_pair_to_partial(double s1, double s2, double *partial) {
-  __shared__ double l1[NT / 64], l2[NT / 64];
+__device__ void block_triple_to_partial(double s1, double s2, double s3, double *partial) {
+  __shared__ double l1[NT / 64], l2[NT / 64], l3[NT / 64];
   s1 = wave_sum(s1);
   s2 = wave_sum(s2);
+  s3 = wave_sum(s3);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) {
     l1[wave] = s1;
     l2[wave] = s2;
+    l3[wave] = s3;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double a = 0.0, b = 0.0;
+    double a = 0.0, b = 0.0, c = 0.0;
     for (int w = 0; w < NT / 64; ++w) {
       a += l1[w];
       b += l2[w];
+      c += l3[w];
     }
     const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-    partial[2 * bid] = a;
-    partial[2 * bid + 1] = b;
+    partial[3 * bid] = a;
+    partial[3 * bid + 1] = b;
+    partial[3 * bid + 2] = c;
   }
 }
 
@@ -125,11 +129,11 @@ struct SmoothState {
   float fE[S::RING][S::PP], fO[S::RING][S::PP];  // fscale (f - mean)
   static constexpr int PF = smooth_prefetch<H, NORM>();
   float2 pu[PF][S::PP], pf[PF][S::PP];            // planes in flight from HBM
-  double s_r, s_f;
+  double s_r, s_f, s_u;  // NORM: ||f - L u||^2, ||f||^2 and sum u of the input
   // uniform
   const float *uin, *f;
   float *uout, *lds;
-  float fscale, m, h2, omega, inv_h2;
+  float fscale, m, h2, omega, inv_h2, uscale;
   int n, i0, ci, qend;
   size_t nn;
 
@@ -209,7 +213,7 @@ __device__ __forceinline__ void smooth_norm(SmoothState<H, true, OMEGA1> &c, int
   if (p < c.i0 || p >= c.i0 + c.ci) return;  // uniform
   const float *LE = c.lds + lds_slot<R, H, true>(1) * Sh::SLOT, *LO = LE + Sh::ARR;
   const float *PE = c.lds + lds_slot<R + 1, H, true>(1) * Sh::SLOT, *PO = PE + Sh::ARR;
-  float sr = 0.f, sf = 0.f;  // this plane's few terms in FP32, the running sums in FP64
+  float sr = 0.f, sf = 0.f, su = 0.f;  // this plane's few terms in FP32, the sums in FP64
 #pragma unroll
   for (int t = 0; t < PP; ++t) {
     if (!c.inside[t]) continue;
@@ -223,9 +227,11 @@ __device__ __forceinline__ void smooth_norm(SmoothState<H, true, OMEGA1> &c, int
     const float ra = fa - lapa * c.inv_h2, rb = fb - lapb * c.inv_h2;
     sr = fmaf(ra, ra, fmaf(rb, rb, sr));
     sf = fmaf(fa, fa, fmaf(fb, fb, sf));
+    su += a + b;
   }
   c.s_r += sr;
   c.s_f += sf;
+  c.s_u += su;
 }
 
 template <int R, int S, int H, bool NORM, bool OMEGA1>
@@ -250,8 +256,9 @@ __device__ __forceinline__ void smooth_step(SmoothState<H, NORM, OMEGA1> &c, int
   for (int t = 0; t < PP; ++t) {
     const float2 u = c.pu[P][t], fv = c.pf[P][t];
     const float fx = c.fscale * (fv.x - c.m), fy = c.fscale * (fv.y - c.m);
-    c.uE[c0][t] = c.swp[t] ? u.y : u.x;
-    c.uO[c0][t] = c.swp[t] ? u.x : u.y;
+    // (uscale: growth rescaling of a warm start, applied as the input is read)
+    c.uE[c0][t] = c.uscale * (c.swp[t] ? u.y : u.x);
+    c.uO[c0][t] = c.uscale * (c.swp[t] ? u.x : u.y);
     c.fE[c0][t] = c.swp[t] ? fy : fx;
     c.fO[c0][t] = c.swp[t] ? fx : fy;
   }
@@ -314,7 +321,7 @@ template <int H, bool NORM, bool OMEGA1>
 __global__ __launch_bounds__(NORM ? 2 * ST : ST) __attribute__((amdgpu_waves_per_eu(4))) void k_smooth_stream(
     const float *__restrict__ uin, float *__restrict__ uout, const float *__restrict__ f,
     float fscale, const float *__restrict__ fmean, int n, int ci, float h2, float omega,
-    int first_colour, double *__restrict__ partial) {
+    int first_colour, double *__restrict__ partial, float uscale) {
   using S = SmoothShape<H, NORM>;
   constexpr int PF = smooth_prefetch<H, NORM>();
   static_assert(S::RING % 2 == 0 && S::RING % PF == 0,
@@ -338,6 +345,7 @@ __global__ __launch_bounds__(NORM ? 2 * ST : ST) __attribute__((amdgpu_waves_per
   c.uout = uout;
   c.lds = lds;
   c.fscale = fscale;
+  c.uscale = uscale;
   c.m = fmean ? *fmean : 0.0f;
   c.h2 = h2;
   c.omega = omega;
@@ -347,7 +355,7 @@ __global__ __launch_bounds__(NORM ? 2 * ST : ST) __attribute__((amdgpu_waves_per
   c.ci = ci;
   c.qend = c.i0 + ci + H;
   c.nn = (size_t)n * n;
-  c.s_r = c.s_f = 0.0;
+  c.s_r = c.s_f = c.s_u = 0.0;
 
   // padding is read by edge points (and written only by slots without a pair)
   for (int e = threadIdx.x; e < S::PAD; e += S::NT)
@@ -383,7 +391,7 @@ __global__ __launch_bounds__(NORM ? 2 * ST : ST) __attribute__((amdgpu_waves_per
   int q = qbeg;
   for (; q + S::RING <= c.qend; q += S::RING) smooth_steps<0, false, H, NORM, OMEGA1>(c, q);
   smooth_steps<0, true, H, NORM, OMEGA1>(c, q);
-  if constexpr (NORM) block_pair_to_partial<S::NT>(c.s_r, c.s_f, partial);
+  if constexpr (NORM) block_triple_to_partial<S::NT>(c.s_r, c.s_f, c.s_u, partial);
 }
 
 // ---------------------------------------------------------------- residual + restrict
@@ -548,7 +556,7 @@ int64_t smooth_stream_blocks(int n) {
 hipError_t launch_smooth_stream(const float *uin, float *uout, const float *f, float fscale,
                                 const float *fmean, int n, float h2, float omega,
                                 int first_colour, int half_sweeps, double *partial,
-                                hipStream_t s) {
+                                float uscale, hipStream_t s) {
   const int tj = (n + SJ - 1) / SJ, tk = (n + SK - 1) / SK;
   const int ci = chunk_for(n, tj * tk, kSmoothBlocks, 16);
   dim3 grid(tk, tj, n / ci);
@@ -556,7 +564,7 @@ hipError_t launch_smooth_stream(const float *uin, float *uout, const float *f, f
   const bool om1 = omega == 1.0f;
 #define PM_SMOOTH_LAUNCH(H_, N_, O_)                                                     \
   k_smooth_stream<H_, N_, O_><<<grid, (SmoothShape<H_, N_>::NT), 0, s>>>(               \
-      uin, uout, f, fscale, fmean, n, ci, h2, omega, first_colour, partial)
+      uin, uout, f, fscale, fmean, n, ci, h2, omega, first_colour, partial, uscale)
   if (half_sweeps == 4) {
     if (norm) {
       if (om1) PM_SMOOTH_LAUNCH(4, true, true); else PM_SMOOTH_LAUNCH(4, true, false);

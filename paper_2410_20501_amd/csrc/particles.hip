@@ -673,13 +673,50 @@ __global__ __launch_bounds__(kOThreads) void k_deposit_own(const float *__restri
 
 // rho = scale * acc (fixed point -> FP32, in FP64 so the conversion is exact to the
 // last bit of the FP32 result); acc is cleared for the next deposit
+constexpr int kFixBlocks = 4096;  // grid of the conversion pass (grid-stride)
+
+// With partial != NULL the pass also adds up the fixed-point values (exact: integers),
+// one sum per block, for the mean of rho.
 __global__ __launch_bounds__(kThreads) void k_fix_convert(unsigned long long *__restrict__ acc,
                                                           int64_t count, double scale,
-                                                          float *__restrict__ rho) {
-  const int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
-  if (t >= count) return;
-  rho[t] = (float)((double)acc[t] * scale);
-  acc[t] = 0ull;
+                                                          float *__restrict__ rho,
+                                                          unsigned long long *__restrict__ partial) {
+  unsigned long long sum = 0ull;
+  for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < count;
+       t += (int64_t)gridDim.x * kThreads) {
+    const unsigned long long v = acc[t];
+    rho[t] = (float)((double)v * scale);
+    acc[t] = 0ull;
+    sum += v;
+  }
+  if (partial) {
+    __shared__ unsigned long long ws[kThreads / 64];
+    sum = wave_sum_ull(sum);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long b = 0ull;
+      for (int w = 0; w < kThreads / 64; ++w) b += ws[w];
+      partial[blockIdx.x] = b;
+    }
+  }
+}
+
+// mean = (sum of the block sums) * scale / count
+__global__ __launch_bounds__(kThreads) void k_fix_mean(const unsigned long long *__restrict__ partial,
+                                                       int nblocks, double scale, int64_t count,
+                                                       float *__restrict__ mean) {
+  unsigned long long sum = 0ull;
+  for (int b = threadIdx.x; b < nblocks; b += kThreads) sum += partial[b];
+  __shared__ unsigned long long ws[kThreads / 64];
+  sum = wave_sum_ull(sum);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0ull;
+    for (int w = 0; w < kThreads / 64; ++w) t += ws[w];
+    *mean = (float)((double)t * scale / (double)count);
+  }
 }
 
 // Interpolation + kick from particles bucketed by tile (the deposit's sort of the same
@@ -960,7 +997,7 @@ hipError_t launch_sort_by_cell(pm_ctx *ctx, const float *pos, const int32_t *cel
 int64_t scan_blocks_needed(int64_t len) { return (len + kScanTile - 1) / kScanTile; }
 
 hipError_t launch_deposit_own(pm_ctx *ctx, const float *pos, const int32_t *cell, int poskind,
-                              int mas, float mass, float *rho, hipStream_t s) {
+                              int mas, float mass, float *rho, float *mean, hipStream_t s) {
   const int n = ctx->n;
   const int64_t ncell = (int64_t)n * n * n;
   const unsigned nt = (unsigned)(ncell / kTThreads);
@@ -980,8 +1017,12 @@ hipError_t launch_deposit_own(pm_ctx *ctx, const float *pos, const int32_t *cell
       k_deposit_own<2, PM_POS_CELLOFF><<<nt, kOThreads, 0, s>>>(pos, cell, ctx->cell_count,
                                                                  ctx->perm, n, acc);
   }
-  k_fix_convert<<<blocks_for(ncell, kThreads), kThreads, 0, s>>>(acc, ncell,
-                                                                 (double)mass / 1073741824.0, rho);
+  const double scale = (double)mass / 1073741824.0;
+  // block sums go to the reduction scratch (free until the solve that follows)
+  unsigned long long *partial = reinterpret_cast<unsigned long long *>(ctx->red_partial);
+  const int nb = (int)std::min<int64_t>(kFixBlocks, blocks_for(ncell, kThreads));
+  k_fix_convert<<<nb, kThreads, 0, s>>>(acc, ncell, scale, rho, mean ? partial : nullptr);
+  if (mean) k_fix_mean<<<1, kThreads, 0, s>>>(partial, nb, scale, ncell, mean);
   return hipGetLastError();
 }
 
