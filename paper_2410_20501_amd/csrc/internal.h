@@ -168,11 +168,13 @@ int pm_mg_setup(pm_ctx *ctx);
 // mg_stream.hip
 int64_t smooth_stream_blocks(int n);
 // partial != NULL: the pass also sums ||f - L u||^2, ||f||^2 and sum u of its input,
-// three doubles per block; uscale multiplies the input as it is read
+// three doubles per block; uscale multiplies the input as it is read; ec != NULL (not
+// with partial): the input is uin + P ec, the trilinear prolongation of the coarse
+// correction ec ((n/2)^3) added as each plane is read
 hipError_t launch_smooth_stream(const float *uin, float *uout, const float *f, float fscale,
                                 const float *fmean, int n, float h2, float omega,
                                 int first_colour, int half_sweeps, double *partial,
-                                float uscale, hipStream_t s);
+                                float uscale, const float *ec, hipStream_t s);
 // residual + restriction in one streaming pass; with ucg != NULL also the coarse
 // starting guess ucg = gscale * fc
 hipError_t launch_rr_stream(const float *u, const float *f, float fscale, const float *fmean,

@@ -105,15 +105,21 @@ struct SmoothShape {
   static constexpr int ARR = NPAIR + 2 * PAD;        // floats per colour array
   static constexpr int SLOT = 2 * ARR;               // floats per published plane (E, then O)
   static constexpr int RING = H + 2;                 // planes held in registers
+  // PRO: the coarse correction's region (tile plus halo, halved, plus one coarse cell
+  // per side) staged raw in LDS, then interpolated along k to the tile's fine columns
+  // into a ring of three planes (CJR rows of RK values)
+  static constexpr int CJR = RJ / 2 + 2, CKR = RK / 2 + 2, CPLANE = CJR * CKR;
+  static constexpr int CPT = (CPLANE + NT - 1) / NT;  // coarse values loaded per thread
+  static constexpr int KPLANE = CJR * RK;             // k-interpolated plane
 };
 
 // planes in flight from HBM (a third one measured no faster and costs registers)
-template <int H, bool NORM>
+template <int H, bool NORM, bool PRO = false>
 constexpr int smooth_prefetch() {
   return 2;
 }
 
-template <int H, bool NORM, bool OMEGA1>
+template <int H, bool NORM, bool OMEGA1, bool PRO>
 struct SmoothState {
   using S = SmoothShape<H, NORM>;
   // per-thread constants
@@ -127,9 +133,17 @@ struct SmoothState {
   // pipeline registers: ring slot (q - d) mod RING holds plane q - d
   float uE[S::RING][S::PP], uO[S::RING][S::PP];
   float fE[S::RING][S::PP], fO[S::RING][S::PP];  // fscale (f - mean)
-  static constexpr int PF = smooth_prefetch<H, NORM>();
+  static constexpr int PF = smooth_prefetch<H, NORM, PRO>();
   float2 pu[PF][S::PP], pf[PF][S::PP];            // planes in flight from HBM
   double s_r, s_f, s_u;  // NORM: ||f - L u||^2, ||f||^2 and sum u of the input
+  // PRO: u += P e as each plane enters (trilinear prolongation of the coarse correction)
+  const float *ec;          // coarse grid, nc^3
+  float *craw;              // LDS: one raw coarse plane
+  float *ck;                // LDS: ring of three k-interpolated coarse planes
+  int nc, k0h, cjb, ckb;    // coarse size; first fine column of the tile; coarse origin
+  int cr[S::PP], cr2[S::PP];  // offset of the pair's values in a k-interpolated plane:
+                              // row J and row J' (its other coarse row)
+  float cpre[S::CPT];       // a coarse plane in flight
   // uniform
   const float *uin, *f;
   float *uout, *lds;
@@ -146,6 +160,40 @@ struct SmoothState {
     for (int t = 0; t < S::PP; ++t) {
       u[t] = *reinterpret_cast<const float2 *>(uin + plane + col[t]);
       fv[t] = *reinterpret_cast<const float2 *>(f + plane + col[t]);
+    }
+  }
+
+  static __device__ __forceinline__ int cslot(int I) { return ((I % 3) + 3) % 3; }
+  // coarse indices of a tile lie within one period of the coarse grid on either side
+  __device__ __forceinline__ int cwrap(int i) const { return i < 0 ? i + nc : (i >= nc ? i - nc : i); }
+  __device__ __forceinline__ void cload(int I) {
+    const float *plane = ec + (size_t)cwrap(I) * nc * nc;
+#pragma unroll
+    for (int m = 0; m < S::CPT; ++m) {
+      // (offsets recomputed here rather than held: registers are the smoother's limit;
+      // the empty asm keeps the compiler from hoisting them out of the plane loop)
+      int e = threadIdx.x + m * S::NT;
+      asm volatile("" : "+v"(e));
+      const int jj = e / S::CKR, kk = e - jj * S::CKR;
+      if (e < S::CPLANE) cpre[m] = plane[cwrap(cjb + jj) * nc + cwrap(ckb + kk)];
+    }
+  }
+  __device__ __forceinline__ void cstore_raw() {
+#pragma unroll
+    for (int m = 0; m < S::CPT; ++m) {
+      const int e = threadIdx.x + m * S::NT;
+      if (e < S::CPLANE) craw[e] = cpre[m];
+    }
+  }
+  // fine column k of the tile: 3/4 of coarse column k >> 1 and 1/4 of its neighbour
+  // on k's side (after a barrier that follows cstore_raw)
+  __device__ __forceinline__ void cinterp_k(int I) {
+    float *dst = ck + cslot(I) * S::KPLANE;
+    for (int e = threadIdx.x; e < S::KPLANE; e += S::NT) {
+      const int jj = e / S::RK, kf = e - jj * S::RK;
+      const int gk = k0h + kf;
+      const int K = (gk >> 1) - ckb, K2 = K + ((gk & 1) ? 1 : -1);
+      dst[e] = fmaf(0.75f, craw[jj * S::CKR + K], 0.25f * craw[jj * S::CKR + K2]);
     }
   }
 };
@@ -183,8 +231,8 @@ constexpr int ring_slot(int d) {
 }
 
 // Half-sweep S of a plane step: plane q - S.
-template <int R, int S, int H, bool NORM, bool OMEGA1>
-__device__ __forceinline__ void smooth_half(SmoothState<H, NORM, OMEGA1> &c, int q) {
+template <int R, int S, int H, bool NORM, bool OMEGA1, bool PRO>
+__device__ __forceinline__ void smooth_half(SmoothState<H, NORM, OMEGA1, PRO> &c, int q) {
   using Sh = SmoothShape<H, NORM>;
   constexpr int RING = Sh::RING, PP = Sh::PP, RK2 = Sh::RK2;
   constexpr int c0 = ring_slot<R, RING>(0), c1 = ring_slot<R, RING>(1);
@@ -204,8 +252,8 @@ __device__ __forceinline__ void smooth_half(SmoothState<H, NORM, OMEGA1> &c, int
 // its first update (LDS slot of s = 1), the input values of plane q - 2 (the previous
 // step's slot) and plane q (registers, not yet updated). Run after the relaxations, so
 // its live values do not add to theirs.
-template <int R, int H, bool OMEGA1>
-__device__ __forceinline__ void smooth_norm(SmoothState<H, true, OMEGA1> &c, int q) {
+template <int R, int H, bool OMEGA1, bool PRO>
+__device__ __forceinline__ void smooth_norm(SmoothState<H, true, OMEGA1, PRO> &c, int q) {
   using Sh = SmoothShape<H, true>;
   constexpr int RING = Sh::RING, PP = Sh::PP, RK2 = Sh::RK2;
   constexpr int c0 = ring_slot<R, RING>(0), c1 = ring_slot<R, RING>(1);
@@ -234,21 +282,21 @@ __device__ __forceinline__ void smooth_norm(SmoothState<H, true, OMEGA1> &c, int
   c.s_u += su;
 }
 
-template <int R, int S, int H, bool NORM, bool OMEGA1>
-__device__ __forceinline__ void smooth_halves(SmoothState<H, NORM, OMEGA1> &c, int q) {
+template <int R, int S, int H, bool NORM, bool OMEGA1, bool PRO>
+__device__ __forceinline__ void smooth_halves(SmoothState<H, NORM, OMEGA1, PRO> &c, int q) {
   if constexpr (S <= H) {
-    smooth_half<R, S, H, NORM, OMEGA1>(c, q);
+    smooth_half<R, S, H, NORM, OMEGA1, PRO>(c, q);
     if constexpr (PM_SMOOTH_STAGE_FENCE) __builtin_amdgcn_sched_barrier(0);
-    smooth_halves<R, S + 1, H, NORM, OMEGA1>(c, q);
+    smooth_halves<R, S + 1, H, NORM, OMEGA1, PRO>(c, q);
   }
 }
 
 // One plane of the pipeline, for ring position R = q mod RING (q has the parity of R).
-template <int R, int H, bool NORM, bool OMEGA1>
-__device__ __forceinline__ void smooth_step(SmoothState<H, NORM, OMEGA1> &c, int q) {
+template <int R, int H, bool NORM, bool OMEGA1, bool PRO>
+__device__ __forceinline__ void smooth_step(SmoothState<H, NORM, OMEGA1, PRO> &c, int q) {
   using Sh = SmoothShape<H, NORM>;
   constexpr int RING = Sh::RING, PP = Sh::PP, SLOT = Sh::SLOT;
-  constexpr int PF = smooth_prefetch<H, NORM>();
+  constexpr int PF = smooth_prefetch<H, NORM, PRO>();
   constexpr int P = R % PF;  // prefetch slot of plane q
   constexpr int c0 = ring_slot<R, RING>(0), cH = ring_slot<R, RING>(H);
   // plane q enters the ring; its slot is refilled with plane q + PF
@@ -278,11 +326,48 @@ __device__ __forceinline__ void smooth_step(SmoothState<H, NORM, OMEGA1> &c, int
       if (both || (R & 1) == 0) LO[c.li[t]] = c.uO[cs][t];
     }
   }
+  if constexpr (PRO) {
+    if constexpr ((R & 1) == 1) {
+      // q = 2I + 1: coarse plane I + 2 (loaded two steps ago) is staged raw; plane
+      // I + 3 goes in flight
+      c.cstore_raw();
+      c.cload((q >> 1) + 3);
+    }
+  }
   __syncthreads();
-  smooth_halves<R, 1, H, NORM, OMEGA1>(c, q);
+  if constexpr (PRO) {
+    // (scheduling fences around this block keep its LDS reads from being hoisted into
+    // the relaxations, whose live values they would add to)
+    __builtin_amdgcn_sched_barrier(0);
+    // q = 2I + 1: the staged plane I + 2 goes into the ring, in place of plane I - 1
+    // (last read at step 2I); it is first read at step 2I + 3
+    if constexpr ((R & 1) == 1) {
+      c.cinterp_k((q >> 1) + 2);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // plane q enters with the coarse correction: per axis 3/4 from the nearest coarse
+    // cell and 1/4 from the next one (planes A, B; rows J, J'; columns K, K -+ 1)
+    constexpr int KP = Sh::KPLANE;
+    const int A = q >> 1, B = (R & 1) ? A + 1 : A - 1;
+    const float *CA = c.ck + c.cslot(A) * KP, *CB = c.ck + c.cslot(B) * KP;
+#pragma unroll
+    for (int t = 0; t < PP; ++t) {
+      // (k-interpolated values of the pair's even and odd column, one float2)
+      const float2 a1 = *reinterpret_cast<const float2 *>(CA + c.cr[t]);
+      const float2 a2 = *reinterpret_cast<const float2 *>(CA + c.cr2[t]);
+      const float2 b1 = *reinterpret_cast<const float2 *>(CB + c.cr[t]);
+      const float2 b2 = *reinterpret_cast<const float2 *>(CB + c.cr2[t]);
+      const float ev = fmaf(0.5625f, a1.x, fmaf(0.1875f, a2.x + b1.x, 0.0625f * b2.x));
+      const float od = fmaf(0.5625f, a1.y, fmaf(0.1875f, a2.y + b1.y, 0.0625f * b2.y));
+      c.uE[c0][t] += c.swp[t] ? od : ev;  // E is the odd-k point when swp
+      c.uO[c0][t] += c.swp[t] ? ev : od;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  smooth_halves<R, 1, H, NORM, OMEGA1, PRO>(c, q);
   if constexpr (NORM) {
     __builtin_amdgcn_sched_barrier(0);
-    smooth_norm<R, H, OMEGA1>(c, q);
+    smooth_norm<R, H, OMEGA1, PRO>(c, q);
   }
   // plane q - H is final
   const int pout = q - H;
@@ -308,26 +393,28 @@ __device__ __forceinline__ void smooth_step(SmoothState<H, NORM, OMEGA1> &c, int
   __syncthreads();
 }
 
-template <int R, bool GUARD, int H, bool NORM, bool OMEGA1>
-__device__ __forceinline__ void smooth_steps(SmoothState<H, NORM, OMEGA1> &c, int q) {
+template <int R, bool GUARD, int H, bool NORM, bool OMEGA1, bool PRO>
+__device__ __forceinline__ void smooth_steps(SmoothState<H, NORM, OMEGA1, PRO> &c, int q) {
   if constexpr (R < SmoothShape<H, NORM>::RING) {
-    if (!GUARD || q + R < c.qend) smooth_step<R, H, NORM, OMEGA1>(c, q + R);
-    smooth_steps<R + 1, GUARD, H, NORM, OMEGA1>(c, q);
+    if (!GUARD || q + R < c.qend) smooth_step<R, H, NORM, OMEGA1, PRO>(c, q + R);
+    smooth_steps<R + 1, GUARD, H, NORM, OMEGA1, PRO>(c, q);
   }
 }
 
-template <int H, bool NORM, bool OMEGA1>
+template <int H, bool NORM, bool OMEGA1, bool PRO>
 // at least 4 waves per SIMD: two 512-thread blocks (or one of 1024) per CU
 __global__ __launch_bounds__(NORM ? 2 * ST : ST) __attribute__((amdgpu_waves_per_eu(4))) void k_smooth_stream(
     const float *__restrict__ uin, float *__restrict__ uout, const float *__restrict__ f,
     float fscale, const float *__restrict__ fmean, int n, int ci, float h2, float omega,
-    int first_colour, double *__restrict__ partial, float uscale) {
+    int first_colour, double *__restrict__ partial, float uscale, const float *__restrict__ ec) {
   using S = SmoothShape<H, NORM>;
-  constexpr int PF = smooth_prefetch<H, NORM>();
+  constexpr int PF = smooth_prefetch<H, NORM, PRO>();
   static_assert(S::RING % 2 == 0 && S::RING % PF == 0,
                 "plane parity and prefetch slots repeat within one ring period");
   constexpr int NSLOT = H + (NORM ? 1 : 0);
   __shared__ float lds[NSLOT * S::SLOT];
+  __shared__ float craw[PRO ? S::CPLANE : 1];
+  __shared__ float __align__(8) ckl[PRO ? 3 * S::KPLANE : 2];
 
   // XCD-aware order: consecutive logical blocks are k-, then j-neighbours
   const unsigned lin = xcd_block(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
@@ -339,7 +426,7 @@ __global__ __launch_bounds__(NORM ? 2 * ST : ST) __attribute__((amdgpu_waves_per
 #endif
   const int k0 = bx * SK, j0 = by * SJ;
 
-  SmoothState<H, NORM, OMEGA1> c;
+  SmoothState<H, NORM, OMEGA1, PRO> c;
   c.uin = uin;
   c.f = f;
   c.uout = uout;
@@ -386,11 +473,45 @@ __global__ __launch_bounds__(NORM ? 2 * ST : ST) __attribute__((amdgpu_waves_per
     for (int a = 0; a < PF; ++a) c.pu[a][t] = c.pf[a][t] = make_float2(0.f, 0.f);
   }
   const int qbeg = c.i0 - H;  // even (ci even, H even): step R of a ring period has q = R mod 2
+  if constexpr (PRO) {
+    c.ec = ec;
+    c.craw = craw;
+    c.ck = ckl;
+    c.nc = n >> 1;
+    const int cjb = ((j0 - H) >> 1) - 1, ckb = ((k0 - H) >> 1) - 1;  // coarse tile origin
+    c.k0h = k0 - H;
+    c.cjb = cjb;
+    c.ckb = ckb;
+#pragma unroll
+    for (int t = 0; t < S::PP; ++t) {
+      const int e = threadIdx.x + t * S::NT;
+      const bool v = e < S::NPAIR;
+      const int rj = v ? e / S::RK2 : 0, r2 = v ? e % S::RK2 : 0;
+      const int gj = j0 - H + rj, gk = k0 - H + 2 * r2;
+      // fine j -> coarse J = j >> 1 (3/4) and J' = J -+ 1 (1/4) for j even / odd;
+      // fine k = 2K, 2K + 1 -> coarse K and K - 1 / K + 1
+      const int jr = (gj >> 1) - cjb, jr2 = jr + ((gj & 1) ? 1 : -1);
+      c.cr[t] = jr * S::RK + 2 * r2;
+      c.cr2[t] = jr2 * S::RK + 2 * r2;
+      (void)gk;
+    }
+    // coarse planes of the first two steps (q even needs q/2 - 1 and q/2, q + 1 needs
+    // q/2 and q/2 + 1), and the next one in flight
+    const int I0 = qbeg >> 1;
+    for (int I = I0 - 1; I <= I0 + 1; ++I) {
+      c.cload(I);
+      c.cstore_raw();
+      __syncthreads();
+      c.cinterp_k(I);
+      __syncthreads();
+    }
+    c.cload(I0 + 2);
+  }
 #pragma unroll
   for (int a = 0; a < PF; ++a) c.load(qbeg + a, c.pu[a], c.pf[a]);
   int q = qbeg;
-  for (; q + S::RING <= c.qend; q += S::RING) smooth_steps<0, false, H, NORM, OMEGA1>(c, q);
-  smooth_steps<0, true, H, NORM, OMEGA1>(c, q);
+  for (; q + S::RING <= c.qend; q += S::RING) smooth_steps<0, false, H, NORM, OMEGA1, PRO>(c, q);
+  smooth_steps<0, true, H, NORM, OMEGA1, PRO>(c, q);
   if constexpr (NORM) block_triple_to_partial<S::NT>(c.s_r, c.s_f, c.s_u, partial);
 }
 
@@ -556,30 +677,43 @@ int64_t smooth_stream_blocks(int n) {
 hipError_t launch_smooth_stream(const float *uin, float *uout, const float *f, float fscale,
                                 const float *fmean, int n, float h2, float omega,
                                 int first_colour, int half_sweeps, double *partial,
-                                float uscale, hipStream_t s) {
+                                float uscale, const float *ec, hipStream_t s) {
   const int tj = (n + SJ - 1) / SJ, tk = (n + SK - 1) / SK;
   const int ci = chunk_for(n, tj * tk, kSmoothBlocks, 16);
   dim3 grid(tk, tj, n / ci);
   const bool norm = partial != nullptr;
   const bool om1 = omega == 1.0f;
-#define PM_SMOOTH_LAUNCH(H_, N_, O_)                                                     \
-  k_smooth_stream<H_, N_, O_><<<grid, (SmoothShape<H_, N_>::NT), 0, s>>>(               \
-      uin, uout, f, fscale, fmean, n, ci, h2, omega, first_colour, partial, uscale)
+  const bool pro = ec != nullptr;
+  if (norm && pro) return hipErrorInvalidValue;  // the norm pass is a pre-smoothing pass
+#define PM_SMOOTH_LAUNCH(H_, N_, O_, P_)                                                 \
+  k_smooth_stream<H_, N_, O_, P_><<<grid, (SmoothShape<H_, N_>::NT), 0, s>>>(           \
+      uin, uout, f, fscale, fmean, n, ci, h2, omega, first_colour, partial, uscale, ec)
+#define PM_SMOOTH_PLAIN(H_)                                                              \
+  do {                                                                                   \
+    if (pro) {                                                                           \
+      if (om1) PM_SMOOTH_LAUNCH(H_, false, true, true);                                  \
+      else PM_SMOOTH_LAUNCH(H_, false, false, true);                                     \
+    } else {                                                                             \
+      if (om1) PM_SMOOTH_LAUNCH(H_, false, true, false);                                 \
+      else PM_SMOOTH_LAUNCH(H_, false, false, false);                                    \
+    }                                                                                    \
+  } while (0)
   if (half_sweeps == 4) {
     if (norm) {
-      if (om1) PM_SMOOTH_LAUNCH(4, true, true); else PM_SMOOTH_LAUNCH(4, true, false);
+      if (om1) PM_SMOOTH_LAUNCH(4, true, true, false); else PM_SMOOTH_LAUNCH(4, true, false, false);
     } else {
-      if (om1) PM_SMOOTH_LAUNCH(4, false, true); else PM_SMOOTH_LAUNCH(4, false, false);
+      PM_SMOOTH_PLAIN(4);
     }
   } else if (half_sweeps == 2) {
     if (norm) {
-      if (om1) PM_SMOOTH_LAUNCH(2, true, true); else PM_SMOOTH_LAUNCH(2, true, false);
+      if (om1) PM_SMOOTH_LAUNCH(2, true, true, false); else PM_SMOOTH_LAUNCH(2, true, false, false);
     } else {
-      if (om1) PM_SMOOTH_LAUNCH(2, false, true); else PM_SMOOTH_LAUNCH(2, false, false);
+      PM_SMOOTH_PLAIN(2);
     }
   } else {
     return hipErrorInvalidValue;
   }
+#undef PM_SMOOTH_PLAIN
 #undef PM_SMOOTH_LAUNCH
   return hipGetLastError();
 }

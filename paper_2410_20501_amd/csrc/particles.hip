@@ -522,6 +522,17 @@ inline unsigned blocks_for(int64_t count, int threads) {
 // tile-major cell order by pm_reorder stay together) first reduces its 27 window
 // moments across lanes.
 constexpr int kOThreads = 256;
+#ifndef PM_DEPOSIT_THREADS
+#define PM_DEPOSIT_THREADS 256
+#endif
+#ifndef PM_DEPOSIT_NOGUARD
+#define PM_DEPOSIT_NOGUARD 0
+#endif
+#ifndef PM_INTERP_THREADS
+#define PM_INTERP_THREADS 256
+#endif
+constexpr int kDThreads = PM_DEPOSIT_THREADS;  // tile deposit block
+constexpr int kIThreads = PM_INTERP_THREADS;   // tile interpolation block
 
 // One particle of a tile bucket, loaded ahead of its use.
 struct TileParticle {
@@ -580,7 +591,7 @@ __device__ __forceinline__ void cell_offset_of(const float x[3], int cin, int n,
 }
 
 template <int MAS, int PK>
-__global__ __launch_bounds__(kOThreads) void k_deposit_own(const float *__restrict__ pos,
+__global__ __launch_bounds__(kDThreads) void k_deposit_own(const float *__restrict__ pos,
                                                            const int32_t *__restrict__ cell,
                                                            const int32_t *__restrict__ end,
                                                            const int32_t *__restrict__ perm,
@@ -597,12 +608,12 @@ __global__ __launch_bounds__(kOThreads) void k_deposit_own(const float *__restri
   const int p_end = end[tile];
   TileParticle cur{};
   if (p_begin < p_end) cur = load_tile_particle<PK>(pos, cell, perm, nullptr, p_begin, p_end);
-  for (int i = threadIdx.x; i < kTHalo; i += kOThreads) box[i] = 0ull;
+  for (int i = threadIdx.x; i < kTHalo; i += kDThreads) box[i] = 0ull;
   __syncthreads();
-  for (int l0 = p_begin; l0 < p_end; l0 += kOThreads) {
+  for (int l0 = p_begin; l0 < p_end; l0 += kDThreads) {
     TileParticle nxt{};
-    if (l0 + kOThreads < p_end)
-      nxt = load_tile_particle<PK>(pos, cell, perm, nullptr, l0 + kOThreads, p_end);
+    if (l0 + kDThreads < p_end)
+      nxt = load_tile_particle<PK>(pos, cell, perm, nullptr, l0 + kDThreads, p_end);
     bool act = cur.live;
     int c[3] = {0, 0, 0};
     float o[3] = {0.f, 0.f, 0.f};
@@ -654,14 +665,18 @@ __global__ __launch_bounds__(kOThreads) void k_deposit_own(const float *__restri
 #pragma unroll
           for (int cc = 0; cc < MAS; ++cc) {
             const unsigned long long v = fix30(wab * wz[cc]);
+#if PM_DEPOSIT_NOGUARD
+            atomicAdd(&box[row + cc], v);
+#else
             if (v) atomicAdd(&box[row + cc], v);
+#endif
           }
         }
     }
   }
   __syncthreads();
   const int i0 = ti * kTT - 1, j0 = tj * kTT - 1, k0 = tk * kTT - 1;
-  for (int i = threadIdx.x; i < kTHalo; i += kOThreads) {
+  for (int i = threadIdx.x; i < kTHalo; i += kDThreads) {
     const unsigned long long v = box[i];
     if (v == 0ull) continue;
     const int hx = i / (kTH * kTH), hy = (i / kTH) % kTH, hz = i % kTH;
@@ -797,7 +812,7 @@ __global__ __launch_bounds__(kOThreads) void k_interp_tile(const float *__restri
 // next deposit's sort go to pcell and count, as in the kick-drift kernel. Each particle
 // is read and written by the one thread that owns it in its tile bucket.
 template <int MAS, int PK, bool DRIFT>
-__global__ __launch_bounds__(kOThreads) void k_interp_tile_phi(float *__restrict__ pos,
+__global__ __launch_bounds__(kIThreads) void k_interp_tile_phi(float *__restrict__ pos,
                                                                int32_t *__restrict__ cell,
                                                                const int32_t *__restrict__ end,
                                                                const int32_t *__restrict__ perm,
@@ -819,14 +834,14 @@ __global__ __launch_bounds__(kOThreads) void k_interp_tile_phi(float *__restrict
   const int p_end = end[tile];
   TileParticle cur{};
   if (p_begin < p_end) cur = load_tile_particle<PK>(pos, cell, perm, vel, p_begin, p_end);
-  for (int e = threadIdx.x; e < PH * PH * PH; e += kOThreads) {
+  for (int e = threadIdx.x; e < PH * PH * PH; e += kIThreads) {
     const int hx = e / (PH * PH), hy = (e / PH) % PH, hz = e % PH;
     ps[e] = phi[((size_t)wrap_index(i0 + hx, n) * n + wrap_index(j0 + hy, n)) * n +
                 wrap_index(k0 + hz, n)];
   }
   __syncthreads();
   const float c1 = 2.0f / 3.0f, c2 = -1.0f / 12.0f, inv_h = (float)n;
-  for (int h = threadIdx.x; h < kTHalo; h += kOThreads) {
+  for (int h = threadIdx.x; h < kTHalo; h += kIThreads) {
     const int cx = h / (kTH * kTH) + 2, cy = (h / kTH) % kTH + 2, cz = h % kTH + 2;
     const int c = (cx * PH + cy) * PH + cz;
     float gx = c1 * (ps[c + PH * PH] - ps[c - PH * PH]);
@@ -843,10 +858,10 @@ __global__ __launch_bounds__(kOThreads) void k_interp_tile_phi(float *__restrict
   // uniform trip count: with DRIFT the whole wave takes part in the histogram's run
   // detection. Each pass loads the particles of the next pass before it works on its
   // own, and the first pass's particles are loaded before the potential is staged.
-  for (int l0 = p_begin; l0 < p_end; l0 += kOThreads) {
+  for (int l0 = p_begin; l0 < p_end; l0 += kIThreads) {
     TileParticle nxt{};
-    if (l0 + kOThreads < p_end)
-      nxt = load_tile_particle<PK>(pos, cell, perm, vel, l0 + kOThreads, p_end);
+    if (l0 + kIThreads < p_end)
+      nxt = load_tile_particle<PK>(pos, cell, perm, vel, l0 + kIThreads, p_end);
     int key = -1;
     if (cur.live) {
       const int p = cur.p;
@@ -1004,17 +1019,17 @@ hipError_t launch_deposit_own(pm_ctx *ctx, const float *pos, const int32_t *cell
   unsigned long long *acc = ctx->fix_grid;
   if (mas == PM_TSC) {
     if (poskind == PM_POS_BOX)
-      k_deposit_own<3, PM_POS_BOX><<<nt, kOThreads, 0, s>>>(pos, cell, ctx->cell_count, ctx->perm,
+      k_deposit_own<3, PM_POS_BOX><<<nt, kDThreads, 0, s>>>(pos, cell, ctx->cell_count, ctx->perm,
                                                              n, acc);
     else
-      k_deposit_own<3, PM_POS_CELLOFF><<<nt, kOThreads, 0, s>>>(pos, cell, ctx->cell_count,
+      k_deposit_own<3, PM_POS_CELLOFF><<<nt, kDThreads, 0, s>>>(pos, cell, ctx->cell_count,
                                                                  ctx->perm, n, acc);
   } else {
     if (poskind == PM_POS_BOX)
-      k_deposit_own<2, PM_POS_BOX><<<nt, kOThreads, 0, s>>>(pos, cell, ctx->cell_count, ctx->perm,
+      k_deposit_own<2, PM_POS_BOX><<<nt, kDThreads, 0, s>>>(pos, cell, ctx->cell_count, ctx->perm,
                                                              n, acc);
     else
-      k_deposit_own<2, PM_POS_CELLOFF><<<nt, kOThreads, 0, s>>>(pos, cell, ctx->cell_count,
+      k_deposit_own<2, PM_POS_CELLOFF><<<nt, kDThreads, 0, s>>>(pos, cell, ctx->cell_count,
                                                                  ctx->perm, n, acc);
   }
   const double scale = (double)mass / 1073741824.0;
@@ -1055,10 +1070,10 @@ hipError_t launch_interp_tile_phi(pm_ctx *ctx, float *pos, int32_t *cell, int po
 #define PM_ITP(M, K)                                                                             \
   do {                                                                                           \
     if (drift)                                                                                   \
-      k_interp_tile_phi<M, K, true><<<nt, kOThreads, 0, s>>>(                                    \
+      k_interp_tile_phi<M, K, true><<<nt, kIThreads, 0, s>>>(                                    \
           pos, cell, ctx->cell_count, ctx->perm, n, phi, acc, vel, kick, dt, pcell, count);      \
     else                                                                                         \
-      k_interp_tile_phi<M, K, false><<<nt, kOThreads, 0, s>>>(                                   \
+      k_interp_tile_phi<M, K, false><<<nt, kIThreads, 0, s>>>(                                   \
           pos, cell, ctx->cell_count, ctx->perm, n, phi, acc, vel, kick, dt, nullptr, nullptr);  \
   } while (0)
   if (mas == PM_TSC) {

@@ -259,6 +259,27 @@ def test_streaming_multigrid_matches_reference_kernels(lib, pre, post, omega, ki
     assert rel_l2(host(phi), ref) <= 1e-5, st.history()
 
 
+@pytest.mark.parametrize("pre,post,omega", [(2, 2, 1.0), (2, 1, 1.25)])
+def test_fused_prolongation_matches_reference_kernels(lib, pre, post, omega):
+    """At 512^3 the first post-smoothing pass adds the prolonged coarse correction as it
+    reads each plane (coarse planes staged in LDS); three V-cycles against the context
+    that runs one kernel per prolongation and half-sweep."""
+    _say(f"fused prolongation 512^3 pre={pre} post={post} omega={omega}")
+    n = 512
+    rng = np.random.Generator(np.random.PCG64(23))
+    rho32 = (1.0 + 0.1 * rng.standard_normal((n, n, n), dtype=np.float32)).astype(np.float32)
+    out = []
+    for flags in (0, lib.PM_CREATE_REFERENCE_KERNELS):
+        c = lib.Context(n, 0, flags)
+        phi = torch.zeros((n, n, n), device="cuda")
+        lib.pm_solve_mg(c, dev(rho32), 0.15, phi, fixed_cycles=3, pre=pre, post=post,
+                        omega=omega)
+        out.append(host(phi))
+        del phi
+        c.close()
+    assert rel_l2(out[0], out[1]) <= 2e-6
+
+
 def test_mg_single_mode_closed_form(lib):
     _say("mg single mode")
     n = 64
