@@ -529,15 +529,15 @@ __global__ __launch_bounds__(kThreads) void kb_prolong_add(Arenas A, const int2 
 // Coarsest level of every box, one workgroup per box, in LDS (coarse_solve.h).
 __global__ __launch_bounds__(kCoarseThreads) void kb_coarse_solve(Arenas A,
                                                                   const BoxDev *__restrict__ boxes) {
-  __shared__ float su[kCoarseMax];
-  __shared__ float sf[kCoarseMax];
-  __shared__ double red[kCoarseThreads / 64];
+  __shared__ float re[kCoarseMax];
+  __shared__ float im[kCoarseMax];
+  __shared__ float tc[pm_coarse::kMaxN], ts[pm_coarse::kMaxN];
   const int b = blockIdx.x;
   const BoxDev &bx = boxes[b];
   const float coef = A.steps[*A.ctr].coef;
   const LevelView v = level_view(bx, bx.nlev - 1, A.phi, A.rho, A.lu, A.lf, coef, A.rmean, b);
   const float h = 1.0f / (float)v.n;
-  pm_coarse::solve_any(v.u, v.f, v.scale, v.mean, v.n, h * h, 1e-3f, 500, su, sf, red);
+  pm_coarse::solve_any(v.u, v.f, v.scale, v.mean, v.n, h * h, re, im, tc, ts);
 }
 
 // Per-item partial sums of |f - L u|^2 and |f|^2 on level 0 (convergence records).

@@ -1,12 +1,11 @@
-// Coarsest multigrid level (at most 20^3 cells) solved by one 1024-thread
-// workgroup in LDS: red-black Gauss-Seidel sweeps until the residual has
-// dropped by `reduction` (checked every 4 sweeps), stagnates, or max_sweeps
-// (paper Sect. 3.7.1, the recursion's last level). The mean of the right-hand
-// side is removed first and the mean of the solution last (periodic problem).
-//
-// Every thread owns at most SLOTS cells of each colour; their LDS index and
-// the six neighbour indices are computed once, so a sweep is loads, one fma
-// chain and a store per cell, with no index arithmetic.
+// Coarsest multigrid level (at most 20^3 cells), solved exactly by one 1024-thread
+// workgroup in LDS (the recursion's last level, paper Sect. 3.7.1). On a periodic
+// grid the seven-point operator is diagonal in the discrete Fourier basis:
+//   L e^{i 2 pi (a i + b j + c k)/n} = lambda e^{...},
+//   lambda = (2 cos(2 pi a/n) + 2 cos(2 pi b/n) + 2 cos(2 pi c/n) - 6) / h^2,
+// so u = DFT^-1[ DFT[f] / lambda ] with the zero mode set to zero (the periodic
+// problem's mean: the right-hand side's mean is dropped, the solution has mean zero).
+// The transforms are direct DFTs along each axis (n <= 20, any n), in FP32.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -15,124 +14,81 @@ namespace pm_coarse {
 
 constexpr int kThreads = 1024;
 constexpr int kMaxCells = 8000;
+constexpr int kMaxN = 20;
+constexpr int kItems = (kMaxCells + kThreads - 1) / kThreads;  // outputs per thread and pass
 
-__device__ __forceinline__ int wrapc(int i, int n) {
-  i += (i < 0) ? n : 0;
-  i -= (i >= n) ? n : 0;
-  return i;
-}
-
-__device__ __forceinline__ double block_sum(double v, double *red) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  double s = 0.0;
-#pragma unroll
-  for (int w = 0; w < kThreads / 64; ++w) s += red[w];
-  return s;
-}
-
-// su, sf: LDS arrays of kMaxCells floats; red: LDS array of kThreads / 64 doubles.
-template <int SLOTS>
-__device__ void solve(float *__restrict__ ug, const float *__restrict__ fg, float scale,
-                      float mean, int n, float h2, float reduction, int max_sweeps, float *su,
-                      float *sf, double *red) {
+// One DFT pass along `axis` (0: i, stride n^2; 1: j, stride n; 2: k, stride 1) over the
+// planar complex grid (re, im), in place: every thread forms its outputs from the
+// line in LDS, then all write after a barrier. sgn = -1 forward, +1 inverse.
+__device__ __forceinline__ void dft_pass(float *re, float *im, const float *tc, const float *ts,
+                                         int n, int axis, float sgn) {
   const int count = n * n * n;
-  const int half = n >> 1;
-  const int hcount = count >> 1;  // cells of one colour (n even)
-  double fs = 0.0;
-  for (int c = threadIdx.x; c < count; c += kThreads) {
-    su[c] = ug[c];
-    const float fv = scale * (fg[c] - mean);
-    sf[c] = fv;
-    fs += fv;
-  }
-  const float fmean = (float)(block_sum(fs, red) / count);
-  for (int c = threadIdx.x; c < count; c += kThreads) sf[c] -= fmean;
-  // this thread's cells: half-cell t -> (i, j, k2), k = 2 k2 + ((i + j + colour) & 1)
-  int cc[2][SLOTS];
-  int nb[2][SLOTS][6];
+  const int st = axis == 0 ? n * n : (axis == 1 ? n : 1);
+  float orr[kItems], oii[kItems];
 #pragma unroll
-  for (int col = 0; col < 2; ++col) {
-#pragma unroll
-    for (int m = 0; m < SLOTS; ++m) {
-      const int t = threadIdx.x + m * kThreads;
-      cc[col][m] = -1;
-      if (t < hcount) {
-        const int k2 = t % half, r = t / half;
-        const int j = r % n, i = r / n;
-        const int k = 2 * k2 + ((i + j + col) & 1);
-        cc[col][m] = (i * n + j) * n + k;
-        nb[col][m][0] = (wrapc(i + 1, n) * n + j) * n + k;
-        nb[col][m][1] = (wrapc(i - 1, n) * n + j) * n + k;
-        nb[col][m][2] = (i * n + wrapc(j + 1, n)) * n + k;
-        nb[col][m][3] = (i * n + wrapc(j - 1, n)) * n + k;
-        nb[col][m][4] = (i * n + j) * n + wrapc(k + 1, n);
-        nb[col][m][5] = (i * n + j) * n + wrapc(k - 1, n);
+  for (int it = 0; it < kItems; ++it) {
+    const int c = threadIdx.x + it * kThreads;
+    orr[it] = oii[it] = 0.f;
+    if (c < count) {
+      const int i = c / (n * n), j = (c / n) % n, k = c % n;
+      const int p = axis == 0 ? i : (axis == 1 ? j : k);
+      const int base = c - p * st;
+      float sr = 0.f, si = 0.f;
+      int idx = 0;  // (m p) mod n
+      for (int m = 0; m < n; ++m) {
+        const float wr = tc[idx], wi = sgn * ts[idx];
+        const float xr = re[base + m * st], xi = im[base + m * st];
+        sr = fmaf(xr, wr, fmaf(-xi, wi, sr));
+        si = fmaf(xr, wi, fmaf(xi, wr, si));
+        idx += p;
+        if (idx >= n) idx -= n;
       }
+      orr[it] = sr;
+      oii[it] = si;
     }
   }
   __syncthreads();
-  const float inv_h2 = 1.0f / h2;
-  auto resid_norm = [&]() {
-    double s = 0.0;
 #pragma unroll
-    for (int col = 0; col < 2; ++col)
-#pragma unroll
-      for (int m = 0; m < SLOTS; ++m) {
-        const int c = cc[col][m];
-        if (c < 0) continue;
-        const float uc = su[c];
-        // difference form: exact for close values
-        const float lap = (su[nb[col][m][0]] - uc) + (su[nb[col][m][1]] - uc) +
-                          (su[nb[col][m][2]] - uc) + (su[nb[col][m][3]] - uc) +
-                          (su[nb[col][m][4]] - uc) + (su[nb[col][m][5]] - uc);
-        const double r = sf[c] - lap * inv_h2;
-        s += r * r;
-      }
-    return sqrt(block_sum(s, red));
-  };
-  const double r0 = resid_norm();
-  double prev = r0;
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-#pragma unroll
-    for (int col = 0; col < 2; ++col) {
-#pragma unroll
-      for (int m = 0; m < SLOTS; ++m) {
-        const int c = cc[col][m];
-        if (c < 0) continue;
-        const float s = su[nb[col][m][0]] + su[nb[col][m][1]] + su[nb[col][m][2]] +
-                        su[nb[col][m][3]] + su[nb[col][m][4]] + su[nb[col][m][5]];
-        su[c] = (s - h2 * sf[c]) * (1.0f / 6.0f);
-      }
-      __syncthreads();
-    }
-    if ((sweep & 3) == 3) {
-      const double r = resid_norm();
-      if (r <= reduction * r0 || r > 0.98 * prev) break;
-      prev = r;
+  for (int it = 0; it < kItems; ++it) {
+    const int c = threadIdx.x + it * kThreads;
+    if (c < count) {
+      re[c] = orr[it];
+      im[c] = oii[it];
     }
   }
-  double us = 0.0;
-  for (int c = threadIdx.x; c < count; c += kThreads) us += su[c];
-  const float umean = (float)(block_sum(us, red) / count);
-  for (int c = threadIdx.x; c < count; c += kThreads) ug[c] = su[c] - umean;
+  __syncthreads();
 }
 
-// Dispatch on the number of cells per colour and thread.
-__device__ __forceinline__ void solve_any(float *ug, const float *fg, float scale, float mean,
-                                          int n, float h2, float reduction, int max_sweeps,
-                                          float *su, float *sf, double *red) {
-  const int hcount = (n * n * n) >> 1;
-  if (hcount <= kThreads)
-    solve<1>(ug, fg, scale, mean, n, h2, reduction, max_sweeps, su, sf, red);
-  else if (hcount <= 2 * kThreads)
-    solve<2>(ug, fg, scale, mean, n, h2, reduction, max_sweeps, su, sf, red);
-  else
-    solve<4>(ug, fg, scale, mean, n, h2, reduction, max_sweeps, su, sf, red);
+// ug = L^-1 (scale (fg - mean)) with zero mean. re, im: LDS arrays of kMaxCells floats;
+// tc, ts: LDS arrays of kMaxN floats (cosine and sine table).
+__device__ void solve_any(float *__restrict__ ug, const float *__restrict__ fg, float scale,
+                          float mean, int n, float h2, float *re, float *im, float *tc,
+                          float *ts) {
+  const int count = n * n * n;
+  for (int c = threadIdx.x; c < count; c += kThreads) {
+    re[c] = scale * (fg[c] - mean);
+    im[c] = 0.f;
+  }
+  for (int m = threadIdx.x; m < n; m += kThreads) {
+    double s, co;
+    sincospi(2.0 * m / n, &s, &co);  // table in FP64, then rounded
+    tc[m] = (float)co;
+    ts[m] = (float)s;
+  }
+  __syncthreads();
+  for (int axis = 0; axis < 3; ++axis) dft_pass(re, im, tc, ts, n, axis, -1.0f);
+  const float inv_h2 = 1.0f / h2;
+  for (int c = threadIdx.x; c < count; c += kThreads) {
+    const int a = c / (n * n), b = (c / n) % n, k = c % n;
+    const float lam = (2.0f * (tc[a] + tc[b] + tc[k]) - 6.0f) * inv_h2;
+    const float r = c == 0 ? 0.f : 1.0f / lam;
+    re[c] *= r;
+    im[c] *= r;
+  }
+  __syncthreads();
+  for (int axis = 0; axis < 3; ++axis) dft_pass(re, im, tc, ts, n, axis, 1.0f);
+  const float inv_count = 1.0f / (float)count;
+  for (int c = threadIdx.x; c < count; c += kThreads) ug[c] = re[c] * inv_count;
 }
 
 }  // namespace pm_coarse

@@ -330,11 +330,11 @@ __global__ __launch_bounds__(kThreads) void k_finish_phi(const float *__restrict
 // Coarsest level: one workgroup, in LDS (coarse_solve.h).
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_solve(
     float *__restrict__ ug, const float *__restrict__ fg, float scale,
-    const float *__restrict__ mean, int n, float h2, float reduction, int max_sweeps) {
-  __shared__ float su[kCoarseMax];
-  __shared__ float sf[kCoarseMax];
-  __shared__ double red[kCoarseThreads / 64];
-  pm_coarse::solve_any(ug, fg, scale, src_mean(mean), n, h2, reduction, max_sweeps, su, sf, red);
+    const float *__restrict__ mean, int n, float h2) {
+  __shared__ float re[kCoarseMax];
+  __shared__ float im[kCoarseMax];
+  __shared__ float tc[pm_coarse::kMaxN], ts[pm_coarse::kMaxN];
+  pm_coarse::solve_any(ug, fg, scale, src_mean(mean), n, h2, re, im, tc, ts);
 }
 
 inline unsigned blocks_for(int64_t count, int threads) {
@@ -451,7 +451,7 @@ struct Solver {
   hipError_t coarse(int l) {
     const Src sr = src(l);
     k_coarse_solve<<<1, kCoarseThreads, 0, s>>>(cur[l], sr.f, sr.scale, sr.mean, ctx->lev[l].n,
-                                                h2(l), 1e-3f, 500);
+                                                h2(l));
     return hipGetLastError();
   }
 
