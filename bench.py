@@ -94,7 +94,7 @@ def make_inputs(n, seed=3, a0=0.02):
     return np.ascontiguousarray(off), np.ascontiguousarray(cell), np.ascontiguousarray(ps.vel)
 
 
-def cpu_baseline(n_sample=128, steps=2, seed=3):
+def cpu_baseline(n_sample=128, steps=6, seed=3):
     """The FP64 oracle, as is, on a bounded sample of the same recipe (host cores)."""
     import numpy as np
 

@@ -39,7 +39,8 @@ struct pm_ctx {
   double *red_partial;   // [RED_MAX_BLOCKS * 2]
   double *red_result;    // [4] device: {sum0, sum1, mean, spare}
   double *host_result;   // pinned [4]
-  float *mean_f;         // [1] device: FP32 mean of the current source grid
+  float *mean_f;         // [4] device: [0] FP32 mean of the current source grid,
+                         // [1] mean of the solve's final iterate (gauge)
   // FFT spectrum (lazy)
   void *spec;            // complex float [n][n][pitch]
   int spec_pitch;

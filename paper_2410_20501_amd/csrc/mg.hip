@@ -294,7 +294,9 @@ __global__ __launch_bounds__(kThreads) void k_subtract_mean(float *__restrict__ 
 // Totals of the three per-block sums of the norm-summing smoother pass.
 __global__ __launch_bounds__(RED_THREADS) void k_triple_final(const double *__restrict__ partial,
                                                               int nblocks,
-                                                              double *__restrict__ result) {
+                                                              double *__restrict__ result,
+                                                              int64_t count,
+                                                              float *__restrict__ mean) {
   double v[3] = {0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < nblocks; b += RED_THREADS)
 #pragma unroll
@@ -311,20 +313,19 @@ __global__ __launch_bounds__(RED_THREADS) void k_triple_final(const double *__re
     double a = 0.0;
     for (int w = 0; w < RED_THREADS / 64; ++w) a += l[threadIdx.x][w];
     result[threadIdx.x] = a;
+    if (threadIdx.x == 2) *mean = (float)(a / (double)count);  // mean of the input
   }
 }
 
-// phi = scale * u - mean, with the mean (of scale * u) from a device sum: the copy of
-// the final iterate, its warm-start rescaling (when no cycle ran) and the gauge in one
-// pass.
+// phi = scale * u - mean, with the device-resident mean of scale * u: the copy of the
+// final iterate, its warm-start rescaling (when no cycle ran) and the gauge in one pass.
 __global__ __launch_bounds__(kThreads) void k_finish_phi(const float *__restrict__ u,
                                                          float *__restrict__ phi, int64_t count,
                                                          float scale,
-                                                         const double *__restrict__ sum) {
+                                                         const float *__restrict__ mean) {
   const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (c >= count) return;
-  const float mean = (float)(*sum / (double)count);
-  phi[c] = fmaf(scale, u[c], -mean);
+  phi[c] = fmaf(scale, u[c], -*mean);
 }
 
 // Coarsest level: one workgroup, in LDS (coarse_solve.h).
@@ -554,7 +555,8 @@ int pm_mg_solve(pm_ctx *ctx, const float *rho, float coef, float *phi, const pm_
         const int64_t nb = smooth_stream_blocks(n);
         PM_HIP(ctx, sv.stream_sweeps(0, 0, std::min(p->pre, 2), ctx->red_partial,
                                      cycles == 0 ? uscale : 1.0f));
-        k_triple_final<<<1, RED_THREADS, 0, s>>>(ctx->red_partial, (int)nb, ctx->red_result);
+        k_triple_final<<<1, RED_THREADS, 0, s>>>(ctx->red_partial, (int)nb, ctx->red_result,
+                                                  count, ctx->mean_f + 1);
       } else {
         sv.norms();
       }
@@ -602,7 +604,7 @@ int pm_mg_solve(pm_ctx *ctx, const float *rho, float coef, float *phi, const pm_
     // copy (when the iterate is in the other buffer), rescale (when no cycle ran) and
     // remove the mean (gauge) in one pass
     k_finish_phi<<<blocks_for(count, kThreads), kThreads, 0, s>>>(sv.cur[0], phi, count,
-                                                                   final_scale, ctx->red_result + 2);
+                                                                   final_scale, ctx->mean_f + 1);
   } else {
     if (sv.cur[0] != phi)
       PM_HIP(ctx, hipMemcpyAsync(phi, sv.cur[0], sizeof(float) * count, hipMemcpyDeviceToDevice, s));

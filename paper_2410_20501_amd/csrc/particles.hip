@@ -696,9 +696,11 @@ __global__ __launch_bounds__(kThreads) void k_fix_convert(unsigned long long *__
                                                           int64_t count, double scale,
                                                           float *__restrict__ rho,
                                                           unsigned long long *__restrict__ partial) {
+  // each block converts one contiguous chunk of the grid
+  const int64_t chunk = (count + gridDim.x - 1) / gridDim.x;
+  const int64_t b0 = (int64_t)blockIdx.x * chunk, b1 = b0 + chunk < count ? b0 + chunk : count;
   unsigned long long sum = 0ull;
-  for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < count;
-       t += (int64_t)gridDim.x * kThreads) {
+  for (int64_t t = b0 + threadIdx.x; t < b1; t += kThreads) {
     const unsigned long long v = acc[t];
     rho[t] = (float)((double)v * scale);
     acc[t] = 0ull;
