@@ -36,19 +36,20 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published peak
 # reports null when the source file's hash differs.
 MEASURED_TRAFFIC = {
     # kernel: (source file, sha256 of it, fetch KiB, write KiB, fetch scale, write scale)
-    # smoother: level-0 passes, mean of the pre- (with residual norm) and post-smoothing
-    # variants weighted by their counts (45 and 39 dispatches)
+    # smoother: level-0 passes, mean of the pre-smoothing pass (with the residual norm)
+    # and the post-smoothing pass (with the prolongation) weighted by their counts (45
+    # and 39 dispatches)
     "smooth": ("paper_2410_20501_amd/csrc/mg_stream.hip",
-               "c2193ec07731a35c9da779ca45a183823c18a103175a27a0574c11df558a8f8b",
-               630995.0, 524305.0, 2.0, 1.0),
+               "2b87898978e98b927bae449e8df805f9f8512d9a2842e8dbbaed256f841e8de7",
+               743229.0, 539558.0, 2.0, 1.0),
     # deposit: the particle-owned tile kernel plus the fixed-point conversion pass
     "deposit": ("paper_2410_20501_amd/csrc/particles.hip",
-                "6e5d52c671c806c62c41b16a7f5c480f0c5ce1ef786455aeb3fd0facbcbb0a9f",
-                1900958.0, 4910737.0, 2.0, 1.0),
-    # interpolation with the fused gradient (tile-staged)
+                "e5bd27cf019f3c28999719b0bcda7bb9172aa9fb1c99eab7769b07b0f1d7ffa2",
+                1900967.0, 4910880.0, 2.0, 1.0),
+    # interpolation with the fused gradient, kicks and drift of a chained step
     "interp": ("paper_2410_20501_amd/csrc/particles.hip",
-               "6e5d52c671c806c62c41b16a7f5c480f0c5ce1ef786455aeb3fd0facbcbb0a9f",
-               2544928.0, 3129702.0, 2.0, 1.0),
+               "e5bd27cf019f3c28999719b0bcda7bb9172aa9fb1c99eab7769b07b0f1d7ffa2",
+               2935020.0, 5120295.0, 2.0, 1.0),
 }
 
 
