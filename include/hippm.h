@@ -380,10 +380,14 @@ int pm_tune(pm_batch *batch, float *pos, float *phi, const pm_step_params *param
  * launch of one kernel (at most cap launches; resets the previous record):
  *   PM_KERNEL_DEPOSIT  the deposit's gather kernel of PM_DEPOSIT_SORTED;
  *                      algorithmic bytes 12 per particle + 4 per cell
- *   PM_KERNEL_SMOOTH   the streaming smoother on the finest grid (n >= 128);
- *                      algorithmic bytes 12 per cell per pass
- *   PM_KERNEL_INTERP   interpolation (+ kick) in pm_accel/pm_kdk; algorithmic
- *                      bytes 48 per particle (+4 with cell indices) + 12 per cell
+ *   PM_KERNEL_SMOOTH   the streaming smoother on the finest grid (n >= 256);
+ *                      algorithmic bytes 12 per cell per pass, 12.5 for the
+ *                      post-smoothing pass that adds the prolongation
+ *   PM_KERNEL_INTERP   interpolation (+ kick) in pm_accel/pm_kdk/pm_kdk_chain;
+ *                      algorithmic bytes 48 per particle (+4 with cell indices)
+ *                      + 12 per cell (force grid), or + 4 per cell with the
+ *                      gradient fused (sorted deposit on 8^3 tiles); in a chain,
+ *                      52 per particle (+8 with cell indices) + 4 per cell
  * pm_kernel_timer_read synchronises on the recorded events and returns the
  * summed elapsed time, the number of launches and the summed algorithmic
  * bytes; PM_WARN_NOT_CONVERGED if launches exceeded the pool. */

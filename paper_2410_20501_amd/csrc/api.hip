@@ -118,12 +118,13 @@ int deposit_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np,
     int st = ensure_sort_scratch(ctx, np);
     if (st != PM_OK) return st;
     const bool tiles = (n % 8) == 0;
-    if (tiles && !ctx->fix_grid) {
-      if (hipMalloc(&ctx->fix_grid, sizeof(unsigned long long) * (size_t)ncell) != hipSuccess) {
-        ctx->fix_grid = nullptr;
-        return pm_fail(ctx, PM_ERR_NOMEM, "fixed-point density allocation failed");
+    if (tiles && !ctx->tile_box) {
+      // 10^3 fixed-point values per 8^3 tile (every non-empty tile overwrites its box)
+      if (hipMalloc(&ctx->tile_box, sizeof(unsigned long long) * 1000 * (size_t)(ncell / 512)) !=
+          hipSuccess) {
+        ctx->tile_box = nullptr;
+        return pm_fail(ctx, PM_ERR_NOMEM, "tile box allocation failed");
       }
-      PM_HIP(ctx, hipMemsetAsync(ctx->fix_grid, 0, sizeof(unsigned long long) * (size_t)ncell, s));
     }
     bool hist = tiles && ctx->hist_ready;
     if (tiles && !hist && ctx->hist_next && ctx->hist_pos == pos && ctx->hist_cell == cell &&
@@ -367,7 +368,7 @@ void pm_destroy(pm_ctx *ctx) {
   fr(ctx->pcell);
   fr(ctx->scan_partial);
   fr(ctx->reorder_tmp);
-  fr(ctx->fix_grid);
+  fr(ctx->tile_box);
   fr(ctx->cell_count2);
   fr(ctx->adj_gbar);
   fr(ctx->adj_phibar);

@@ -54,7 +54,7 @@ struct pm_ctx {
   int32_t *scan_partial; // [SCAN_MAX_BLOCKS]
   int64_t sort_cap;
   void *reorder_tmp;     // [np_max * 12 bytes] permutation staging (lazy)
-  unsigned long long *fix_grid;  // [n^3] 2^-30 fixed-point density (sorted deposit, lazy, kept zero)
+  unsigned long long *tile_box;  // [n^3 / 512][10^3] 2^-30 fixed-point tile boxes (sorted deposit, lazy)
   bool hist_ready;       // tile histogram and keys of the current positions already made
   // a chained step's fused drift leaves the next sort's tile histogram in cell_count2
   // and its keys in pcell, valid for the particle arrays it names until they move

@@ -3,6 +3,7 @@
 // that buckets particles by cell. Paper Sect. 3.5 (windows), Sect. 3.4 (leapfrog),
 // App. E (particle ordering for locality).
 #include "deposit_chunk.h"
+#include "tile_box.h"
 #include "internal.h"
 
 namespace {
@@ -511,13 +512,15 @@ inline unsigned blocks_for(int64_t count, int threads) {
 // ------------------------------------------------------------------ particle-owned tile deposit
 
 // Deterministic deposit from particles bucketed by 8^3-cell tile: one workgroup per
-// tile reads only the
-// particles of its own tile (each particle once), adds their 27 (8) window weights
-// as 2^-30 fixed-point integers to an LDS box of the tile plus a one-cell halo, and
-// adds the box to a 64-bit fixed-point grid with one integer global atomic per
-// touched cell. A conversion pass then writes rho = w 2^-30 sum and clears the
-// fixed-point grid. Every sum is an integer sum, so the result is bitwise the same
-// for any particle order, any interleaving of the atomics and any run.
+// tile reads only the particles of its own tile (each particle once), adds their 27
+// (8) window weights as 2^-30 fixed-point integers to an LDS box of the tile plus a
+// one-cell halo, and stores the whole box (10^3 64-bit values) with plain coalesced
+// stores to the tile's slot of a box array; an empty tile stores nothing. A gather
+// pass then forms each cell's sum from the one to eight boxes that cover it (a cell on
+// a tile face, edge or corner is also in the halo of one, three or seven neighbours),
+// skipping empty tiles, and writes rho = w 2^-30 sum. Every sum is an integer sum, so
+// the result is bitwise the same for any particle order, any interleaving of the LDS
+// atomics and any run; no global atomics, and nothing to clear between deposits.
 // A wave whose 64 particles share one cell (dense cells: particles kept in
 // tile-major cell order by pm_reorder stay together) first reduces its 27 window
 // moments across lanes.
@@ -533,6 +536,16 @@ constexpr int kOThreads = 256;
 #endif
 constexpr int kDThreads = PM_DEPOSIT_THREADS;  // tile deposit block
 constexpr int kIThreads = PM_INTERP_THREADS;   // tile interpolation block
+
+// Rank of the lane in its run of equal keys among consecutive lanes of the wave (0 for
+// the first lane of a run). Every lane of the wave takes part.
+__device__ __forceinline__ int run_rank(int key) {
+  const int lane = (int)(threadIdx.x & 63);
+  const int prev = __shfl_up(key, 1, 64);
+  const unsigned long long heads = __ballot(lane == 0 || key != prev);
+  const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+  return lane - (63 - __clzll(heads & upto));
+}
 
 // One particle of a tile bucket, loaded ahead of its use.
 struct TileParticle {
@@ -596,7 +609,7 @@ __global__ __launch_bounds__(kDThreads) void k_deposit_own(const float *__restri
                                                            const int32_t *__restrict__ end,
                                                            const int32_t *__restrict__ perm,
                                                            int n,
-                                                           unsigned long long *__restrict__ acc) {
+                                                           unsigned long long *__restrict__ tbox) {
   __shared__ unsigned long long box[kTHalo];
   const int nt = n / kTT;
   const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
@@ -606,8 +619,8 @@ __global__ __launch_bounds__(kDThreads) void k_deposit_own(const float *__restri
   // before it
   const int p_begin = tile > 0 ? end[tile - 1] : 0;
   const int p_end = end[tile];
-  TileParticle cur{};
-  if (p_begin < p_end) cur = load_tile_particle<PK>(pos, cell, perm, nullptr, p_begin, p_end);
+  if (p_begin >= p_end) return;  // empty tile: the gather pass skips its box
+  TileParticle cur = load_tile_particle<PK>(pos, cell, perm, nullptr, p_begin, p_end);
   for (int i = threadIdx.x; i < kTHalo; i += kDThreads) box[i] = 0ull;
   __syncthreads();
   for (int l0 = p_begin; l0 < p_end; l0 += kDThreads) {
@@ -624,6 +637,7 @@ __global__ __launch_bounds__(kDThreads) void k_deposit_own(const float *__restri
     act = act && (unsigned)lx < (unsigned)kTT && (unsigned)ly < (unsigned)kTT &&
           (unsigned)lz < (unsigned)kTT;
     const int key = act ? (lx * kTT + ly) * kTT + lz : -1;
+    const int rank = run_rank(key);  // all lanes of the wave
     float wx[MAS], wy[MAS], wz[MAS];
     // box coordinates are tile coordinates + 1; the window's first cell follows
     const int fx = axis_off<MAS>(lx + 1, o[0], wx);
@@ -656,64 +670,151 @@ __global__ __launch_bounds__(kDThreads) void k_deposit_own(const float *__restri
               atomicAdd(&box[((bx + a) * kTH + (by + b)) * kTH + (bz + cc)], v);
           }
     } else if (act) {
+      // the window's cells in an order rotated per axis by the base-MAS digits of the
+      // lane's rank in its run of equal cells: lanes whose particles share a cell (dense
+      // regions, particles in cell order after a re-sort) differ in at least one digit
+      // and so add to different LDS words in each instruction instead of serialising on
+      // one; lanes of distinct cells (rank 0) keep the common order (neighbouring cells,
+      // consecutive words). The rotation is applied once per particle to the three
+      // weights and offsets of each axis.
+      const int r = rank % (MAS * MAS * MAS);
+      const int ra = r / (MAS * MAS), rb = (r / MAS) % MAS, rc = r % MAS;
+      float px[MAS], py[MAS], pz[MAS];
+      int ox[MAS], oy[MAS], oz[MAS];
+#pragma unroll
+      for (int t = 0; t < MAS; ++t) {
+        const int sa = t + ra - (t + ra >= MAS ? MAS : 0);
+        const int sb = t + rb - (t + rb >= MAS ? MAS : 0);
+        const int sc = t + rc - (t + rc >= MAS ? MAS : 0);
+        px[t] = sa == 0 ? wx[0] : (sa == 1 ? wx[1] : wx[MAS - 1]);
+        py[t] = sb == 0 ? wy[0] : (sb == 1 ? wy[1] : wy[MAS - 1]);
+        pz[t] = sc == 0 ? wz[0] : (sc == 1 ? wz[1] : wz[MAS - 1]);
+        ox[t] = sa * (kTH * kTH);
+        oy[t] = sb * kTH;
+        oz[t] = sc;
+      }
+      const int base = (fx * kTH + fy) * kTH + fz;
 #pragma unroll
       for (int a = 0; a < MAS; ++a)
 #pragma unroll
         for (int b = 0; b < MAS; ++b) {
-          const float wab = wx[a] * wy[b];
-          const int row = ((fx + a) * kTH + (fy + b)) * kTH + fz;
+          const float wab = px[a] * py[b];
+          const int row = base + ox[a] + oy[b];
 #pragma unroll
           for (int cc = 0; cc < MAS; ++cc) {
-            const unsigned long long v = fix30(wab * wz[cc]);
+            const unsigned long long v = fix30(wab * pz[cc]);
 #if PM_DEPOSIT_NOGUARD
-            atomicAdd(&box[row + cc], v);
+            atomicAdd(&box[row + oz[cc]], v);
 #else
-            if (v) atomicAdd(&box[row + cc], v);
+            if (v) atomicAdd(&box[row + oz[cc]], v);
 #endif
           }
         }
     }
   }
   __syncthreads();
-  const int i0 = ti * kTT - 1, j0 = tj * kTT - 1, k0 = tk * kTT - 1;
-  for (int i = threadIdx.x; i < kTHalo; i += kDThreads) {
-    const unsigned long long v = box[i];
-    if (v == 0ull) continue;
-    const int hx = i / (kTH * kTH), hy = (i / kTH) % kTH, hz = i % kTH;
-    const size_t g = ((size_t)wrap_index(i0 + hx, n) * n + wrap_index(j0 + hy, n)) * n +
-                     wrap_index(k0 + hz, n);
-    atomicAdd(&acc[g], v);
+  // the box belongs to this tile alone: stored whole (zeros included) in the slot order
+  // of its consumers, with coalesced stores
+  static_assert(kTHalo == pm_tilebox::kSlots, "tile box shape");
+  unsigned long long *dst = tbox + (size_t)tile * kTHalo;
+  for (int o = threadIdx.x; o < kTHalo; o += kDThreads) {
+    int hx, hy, hz;
+    pm_tilebox::box_of(o, hx, hy, hz);
+    dst[o] = box[(hx * kTH + hy) * kTH + hz];
   }
 }
 
-// rho = scale * acc (fixed point -> FP32, in FP64 so the conversion is exact to the
-// last bit of the FP32 result); acc is cleared for the next deposit
-constexpr int kFixBlocks = 4096;  // grid of the conversion pass (grid-stride)
+// Gather pass of the tile deposit: one workgroup per row of up to kGRow tiles along k
+// (8 x 8 x 8 kGRow cells). A wave step covers one x, two y and 4 x 8 cells along k (half
+// the row): its loads read whole 128-byte lines of the boxes, its stores two 128-byte
+// runs of rho. Cell c of tile t sums the interior value of t's box and, on a tile
+// face, edge or corner, the halo values that the one, three or seven neighbours t + d
+// stored for it (tile_box.h). Empty tiles (no particles in their bucket) stored no box
+// and add nothing. With partial != NULL each block also adds up its fixed-point sums
+// (exact), for the mean of rho.
+constexpr int kGRow = 8;             // tiles per gather row
+constexpr int kGatherThreads = 256;  // four waves, 16 steps of 64 cells each
+constexpr int kGatherBlocks = 65536; // grid-stride above this many rows
+static_assert(kGatherThreads == 4 * 64 && kGRow * kTT == 64, "gather row shape");
 
-// With partial != NULL the pass also adds up the fixed-point values (exact: integers),
-// one sum per block, for the mean of rho.
-__global__ __launch_bounds__(kThreads) void k_fix_convert(unsigned long long *__restrict__ acc,
-                                                          int64_t count, double scale,
-                                                          float *__restrict__ rho,
-                                                          unsigned long long *__restrict__ partial) {
-  // each block converts one contiguous chunk of the grid
-  const int64_t chunk = (count + gridDim.x - 1) / gridDim.x;
-  const int64_t b0 = (int64_t)blockIdx.x * chunk, b1 = b0 + chunk < count ? b0 + chunk : count;
+__global__ __launch_bounds__(kGatherThreads) void k_tile_gather(
+    const unsigned long long *__restrict__ tbox, const int32_t *__restrict__ end, int n,
+    int64_t rows, double scale, float *__restrict__ rho,
+    unsigned long long *__restrict__ partial) {
+  using pm_tilebox::gather_slot;
+  constexpr int S = pm_tilebox::kSlots;
+  // neighbour tiles of the row: [dx + 1][dy + 1][1 + tile in row + dz], -1 when empty
+  __shared__ int s_tile[3][3][kGRow + 2];
+  __shared__ unsigned long long ws[kGatherThreads / 64];
+  const int nt = n / kTT;
+  const int nkb = (nt + kGRow - 1) / kGRow;
+  // lane: k within the tile, one of two y, one of four tiles; wave: the y pair; step it:
+  // x = it / 2 and the half of the row it % 2
+  const int zl = threadIdx.x & 7;
+  const int y = 2 * (int)(threadIdx.x >> 6) + ((threadIdx.x >> 3) & 1);
+  const int mq = (threadIdx.x >> 4) & 3;
   unsigned long long sum = 0ull;
-  for (int64_t t = b0 + threadIdx.x; t < b1; t += kThreads) {
-    const unsigned long long v = acc[t];
-    rho[t] = (float)((double)v * scale);
-    acc[t] = 0ull;
-    sum += v;
+  for (int64_t row = xcd_block(blockIdx.x, gridDim.x); row < rows; row += gridDim.x) {
+    const int tkb = (int)(row % nkb);
+    const int tj = (int)((row / nkb) % nt);
+    const int ti = (int)(row / ((int64_t)nkb * nt));
+    const int tk0 = tkb * kGRow;
+    __syncthreads();  // the previous row's table is no longer read
+    if (threadIdx.x < 9 * (kGRow + 2)) {
+      const int q = threadIdx.x / (kGRow + 2), mm = threadIdx.x % (kGRow + 2);
+      const int tt = (wrap_any(ti + q / 3 - 1, nt) * nt + wrap_any(tj + q % 3 - 1, nt)) * nt +
+                     wrap_any(tk0 - 1 + mm, nt);
+      const int cnt = end[tt] - (tt > 0 ? end[tt - 1] : 0);
+      (&s_tile[0][0][0])[threadIdx.x] = cnt > 0 ? tt : -1;
+    }
+    __syncthreads();
+    // tiles past the end of a short row (tk0 + m >= nt) are wrapped neighbours: their
+    // loads stay in bounds, their cells are not written
+    unsigned long long v[16];
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+      const int m = 4 * (it & 1) + mq;
+      const int tc = s_tile[1][1][m + 1];
+      const size_t own = (size_t)(tc >= 0 ? tc : 0) * S;  // an empty tile's box is not used
+      const unsigned long long q = tbox[own + gather_slot(0, 0, 0, it >> 1, y, zl)];
+      v[it] = tc >= 0 ? q : 0ull;
+    }
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+      const int x = it >> 1, m = 4 * (it & 1) + mq;
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        if ((dx == -1 && x != 0) || (dx == 1 && x != kTT - 1)) continue;
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+          if ((dy == -1 && y != 0) || (dy == 1 && y != kTT - 1)) continue;
+#pragma unroll
+          for (int dz = -1; dz <= 1; ++dz) {
+            if (dx == 0 && dy == 0 && dz == 0) continue;
+            if ((dz == -1 && zl != 0) || (dz == 1 && zl != kTT - 1)) continue;
+            const int t = s_tile[dx + 1][dy + 1][m + 1 + dz];
+            if (t >= 0) v[it] += tbox[(size_t)t * S + gather_slot(dx, dy, dz, x, y, zl)];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+      const int x = it >> 1, tk = tk0 + 4 * (it & 1) + mq;
+      if (tk < nt) {
+        rho[((size_t)(ti * kTT + x) * n + (tj * kTT + y)) * n + (size_t)tk * kTT + zl] =
+            (float)((double)v[it] * scale);
+        sum += v[it];
+      }
+    }
   }
   if (partial) {
-    __shared__ unsigned long long ws[kThreads / 64];
     sum = wave_sum_ull(sum);
     if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = sum;
     __syncthreads();
     if (threadIdx.x == 0) {
       unsigned long long b = 0ull;
-      for (int w = 0; w < kThreads / 64; ++w) b += ws[w];
+      for (int q = 0; q < kGatherThreads / 64; ++q) b += ws[q];
       partial[blockIdx.x] = b;
     }
   }
@@ -1018,27 +1119,25 @@ hipError_t launch_deposit_own(pm_ctx *ctx, const float *pos, const int32_t *cell
   const int n = ctx->n;
   const int64_t ncell = (int64_t)n * n * n;
   const unsigned nt = (unsigned)(ncell / kTThreads);
-  unsigned long long *acc = ctx->fix_grid;
+  unsigned long long *tbox = ctx->tile_box;
+#define PM_DO(M, K)                                                                             \
+  k_deposit_own<M, K><<<nt, kDThreads, 0, s>>>(pos, cell, ctx->cell_count, ctx->perm, n, tbox)
   if (mas == PM_TSC) {
-    if (poskind == PM_POS_BOX)
-      k_deposit_own<3, PM_POS_BOX><<<nt, kDThreads, 0, s>>>(pos, cell, ctx->cell_count, ctx->perm,
-                                                             n, acc);
-    else
-      k_deposit_own<3, PM_POS_CELLOFF><<<nt, kDThreads, 0, s>>>(pos, cell, ctx->cell_count,
-                                                                 ctx->perm, n, acc);
+    if (poskind == PM_POS_BOX) PM_DO(3, PM_POS_BOX);
+    else PM_DO(3, PM_POS_CELLOFF);
   } else {
-    if (poskind == PM_POS_BOX)
-      k_deposit_own<2, PM_POS_BOX><<<nt, kDThreads, 0, s>>>(pos, cell, ctx->cell_count, ctx->perm,
-                                                             n, acc);
-    else
-      k_deposit_own<2, PM_POS_CELLOFF><<<nt, kDThreads, 0, s>>>(pos, cell, ctx->cell_count,
-                                                                 ctx->perm, n, acc);
+    if (poskind == PM_POS_BOX) PM_DO(2, PM_POS_BOX);
+    else PM_DO(2, PM_POS_CELLOFF);
   }
+#undef PM_DO
   const double scale = (double)mass / 1073741824.0;
   // block sums go to the reduction scratch (free until the solve that follows)
   unsigned long long *partial = reinterpret_cast<unsigned long long *>(ctx->red_partial);
-  const int nb = (int)std::min<int64_t>(kFixBlocks, blocks_for(ncell, kThreads));
-  k_fix_convert<<<nb, kThreads, 0, s>>>(acc, ncell, scale, rho, mean ? partial : nullptr);
+  const int ntile = n / kTT;
+  const int64_t rows = (int64_t)ntile * ntile * ((ntile + kGRow - 1) / kGRow);
+  const int nb = (int)std::min<int64_t>(rows, kGatherBlocks);
+  k_tile_gather<<<nb, kGatherThreads, 0, s>>>(tbox, ctx->cell_count, n, rows, scale, rho,
+                                              mean ? partial : nullptr);
   if (mean) k_fix_mean<<<1, kThreads, 0, s>>>(partial, nb, scale, ncell, mean);
   return hipGetLastError();
 }

@@ -135,6 +135,30 @@ def test_deposit_clustered(lib, mas, order):
     assert abs(got.sum() - n ** 3) <= 1e-6 * n ** 3
 
 
+@pytest.mark.parametrize("mas", ["tsc", "cic"])
+def test_sorted_deposit_sparse_tiles_after_dense(lib, mas):
+    """Tile deposit with most 8^3 tiles empty, right after a deposit that filled every
+    tile: the boxes the empty tiles stored last time must be ignored, while their cells
+    still receive the window tails of particles in the neighbouring tiles (tile faces,
+    edges, corners and the periodic wrap)."""
+    _say(f"sorted deposit sparse after dense {mas}")
+    n = 32
+    dense, _ = lattice_ics(n, rms=1.0, seed=21)
+    # cell-unit positions next to tile faces / edges / corners and the box edge
+    u = np.array([[7.9, 7.9, 7.9], [8.05, 3.5, 12.2], [31.95, 0.02, 15.9],
+                  [16.0, 23.97, 24.01], [0.3, 31.6, 7.99]])
+    sparse = (u / n).astype(np.float32)
+    ctx = ctx_for(lib, n, dense.shape[0])
+    rho = torch.empty((n, n, n), device="cuda")
+    lib.pm_deposit(ctx, dev(dense), rho, mas=mas, order="sorted")
+    lib.pm_deposit(ctx, dev(sparse), rho, mas=mas, order="sorted")
+    ref = opm.deposit(opm.cell_units(n, pos=sparse), n, mas)
+    got = host(rho)
+    assert np.count_nonzero(got) == np.count_nonzero(ref)
+    assert np.abs(got - ref).max() <= 2e-6 * ref.max()
+    assert abs(got.sum() - n ** 3) <= 1e-6 * n ** 3
+
+
 def test_sorted_deposit_is_bitwise_reproducible(lib):
     _say("sorted deposit determinism")
     n = 32
