@@ -537,16 +537,6 @@ constexpr int kOThreads = 256;
 constexpr int kDThreads = PM_DEPOSIT_THREADS;  // tile deposit block
 constexpr int kIThreads = PM_INTERP_THREADS;   // tile interpolation block
 
-// Rank of the lane in its run of equal keys among consecutive lanes of the wave (0 for
-// the first lane of a run). Every lane of the wave takes part.
-__device__ __forceinline__ int run_rank(int key) {
-  const int lane = (int)(threadIdx.x & 63);
-  const int prev = __shfl_up(key, 1, 64);
-  const unsigned long long heads = __ballot(lane == 0 || key != prev);
-  const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
-  return lane - (63 - __clzll(heads & upto));
-}
-
 // One particle of a tile bucket, loaded ahead of its use.
 struct TileParticle {
   bool live;
@@ -611,6 +601,9 @@ __global__ __launch_bounds__(kDThreads) void k_deposit_own(const float *__restri
                                                            int n,
                                                            unsigned long long *__restrict__ tbox) {
   __shared__ unsigned long long box[kTHalo];
+  // per-wave particle count of each cell of the tile in the current pass (kept zero
+  // between passes): a lane's rank among the wave's lanes in its cell
+  __shared__ unsigned int s_cnt[kDThreads / 64][kTThreads];
   const int nt = n / kTT;
   const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
   const int tk = tile % nt, tj = (tile / nt) % nt, ti = tile / (nt * nt);
@@ -622,7 +615,10 @@ __global__ __launch_bounds__(kDThreads) void k_deposit_own(const float *__restri
   if (p_begin >= p_end) return;  // empty tile: the gather pass skips its box
   TileParticle cur = load_tile_particle<PK>(pos, cell, perm, nullptr, p_begin, p_end);
   for (int i = threadIdx.x; i < kTHalo; i += kDThreads) box[i] = 0ull;
+  for (int i = threadIdx.x; i < (kDThreads / 64) * kTThreads; i += kDThreads)
+    (&s_cnt[0][0])[i] = 0u;
   __syncthreads();
+  unsigned int *cnt = s_cnt[threadIdx.x >> 6];
   for (int l0 = p_begin; l0 < p_end; l0 += kDThreads) {
     TileParticle nxt{};
     if (l0 + kDThreads < p_end)
@@ -637,7 +633,8 @@ __global__ __launch_bounds__(kDThreads) void k_deposit_own(const float *__restri
     act = act && (unsigned)lx < (unsigned)kTT && (unsigned)ly < (unsigned)kTT &&
           (unsigned)lz < (unsigned)kTT;
     const int key = act ? (lx * kTT + ly) * kTT + lz : -1;
-    const int rank = run_rank(key);  // all lanes of the wave
+    const int rank = act ? (int)atomicAdd(&cnt[key], 1u) : 0;
+    const bool dup = __ballot(rank > 0) != 0ull;  // some cell holds two lanes of the wave
     float wx[MAS], wy[MAS], wz[MAS];
     // box coordinates are tile coordinates + 1; the window's first cell follows
     const int fx = axis_off<MAS>(lx + 1, o[0], wx);
@@ -669,14 +666,30 @@ __global__ __launch_bounds__(kDThreads) void k_deposit_own(const float *__restri
             if ((threadIdx.x & 63) == 0 && v)
               atomicAdd(&box[((bx + a) * kTH + (by + b)) * kTH + (bz + cc)], v);
           }
+    } else if (act && !dup) {
+#pragma unroll
+      for (int a = 0; a < MAS; ++a)
+#pragma unroll
+        for (int b = 0; b < MAS; ++b) {
+          const float wab = wx[a] * wy[b];
+          const int row = ((fx + a) * kTH + (fy + b)) * kTH + fz;
+#pragma unroll
+          for (int cc = 0; cc < MAS; ++cc) {
+            const unsigned long long v = fix30(wab * wz[cc]);
+#if PM_DEPOSIT_NOGUARD
+            atomicAdd(&box[row + cc], v);
+#else
+            if (v) atomicAdd(&box[row + cc], v);
+#endif
+          }
+        }
     } else if (act) {
-      // the window's cells in an order rotated per axis by the base-MAS digits of the
-      // lane's rank in its run of equal cells: lanes whose particles share a cell (dense
-      // regions, particles in cell order after a re-sort) differ in at least one digit
-      // and so add to different LDS words in each instruction instead of serialising on
-      // one; lanes of distinct cells (rank 0) keep the common order (neighbouring cells,
-      // consecutive words). The rotation is applied once per particle to the three
-      // weights and offsets of each axis.
+      // some lanes share a cell: the window's cells in an order rotated per axis by the
+      // base-MAS digits of the lane's rank among the wave's lanes in its cell, so that
+      // lanes of one cell (up to MAS^3 of them) add to different LDS words in each
+      // instruction instead of serialising on one (rank 0 keeps the common order). The
+      // rotation is applied once per particle to the three weights and offsets of each
+      // axis.
       const int r = rank % (MAS * MAS * MAS);
       const int ra = r / (MAS * MAS), rb = (r / MAS) % MAS, rc = r % MAS;
       float px[MAS], py[MAS], pz[MAS];
@@ -711,6 +724,7 @@ __global__ __launch_bounds__(kDThreads) void k_deposit_own(const float *__restri
           }
         }
     }
+    if (act) cnt[key] = 0u;  // counts start from zero in the next pass (same wave)
   }
   __syncthreads();
   // the box belongs to this tile alone: stored whole (zeros included) in the slot order
@@ -725,12 +739,14 @@ __global__ __launch_bounds__(kDThreads) void k_deposit_own(const float *__restri
 }
 
 // Gather pass of the tile deposit: one workgroup per row of up to kGRow tiles along k
-// (8 x 8 x 8 kGRow cells). A wave step covers one x, two y and 4 x 8 cells along k (half
-// the row): its loads read whole 128-byte lines of the boxes, its stores two 128-byte
-// runs of rho. Cell c of tile t sums the interior value of t's box and, on a tile
-// face, edge or corner, the halo values that the one, three or seven neighbours t + d
-// stored for it (tile_box.h). Empty tiles (no particles in their bucket) stored no box
-// and add nothing. With partial != NULL each block also adds up its fixed-point sums
+// (8 x 8 x 8 kGRow cells); a wave step covers one x, one y and the row's 64 cells
+// along k. Cell c of tile t sums the interior value of t's box and, on a tile face,
+// edge or corner, the halo values that the one, three or seven neighbours t + d stored
+// for it (tile_box.h). Interior, x and y faces and the edges along k are read by the
+// wave steps (64 lanes, 8 runs of 64 bytes); the pieces only the cells at k = 0 or 7
+// of a tile need (k faces, the edges along i and j, corners) are first staged in LDS
+// with whole-group loads. Empty tiles (no particles in their bucket) stored no box and
+// add nothing. With partial != NULL each block also adds up its fixed-point sums
 // (exact), for the mean of rho.
 constexpr int kGRow = 8;             // tiles per gather row
 constexpr int kGatherThreads = 256;  // four waves, 16 steps of 64 cells each
@@ -742,24 +758,33 @@ __global__ __launch_bounds__(kGatherThreads) void k_tile_gather(
     int64_t rows, double scale, float *__restrict__ rho,
     unsigned long long *__restrict__ partial) {
   using pm_tilebox::gather_slot;
+  using pm_tilebox::kCornerBase;
+  using pm_tilebox::kEdgeBase;
+  using pm_tilebox::kFaceBase;
   constexpr int S = pm_tilebox::kSlots;
   // neighbour tiles of the row: [dx + 1][dy + 1][1 + tile in row + dz], -1 when empty
   __shared__ int s_tile[3][3][kGRow + 2];
+  // staged halo: k faces [dz > 0][tile][x * 8 + y], edges along j [dx > 0][dz > 0][tile][y],
+  // edges along i [dy > 0][dz > 0][tile][x], corners [dx > 0][dy > 0][dz > 0][tile]
+  __shared__ unsigned long long s_zf[2][kGRow][64];
+  __shared__ unsigned long long s_exz[2][2][kGRow][8];
+  __shared__ unsigned long long s_eyz[2][2][kGRow][8];
+  __shared__ unsigned long long s_cr[2][2][2][kGRow];
   __shared__ unsigned long long ws[kGatherThreads / 64];
+  constexpr int kStage = 2 * kGRow * 64 + 2 * 2 * 2 * kGRow * 8 + 8 * kGRow;  // 1600
+  constexpr int kStageIt = (kStage + kGatherThreads - 1) / kGatherThreads;
   const int nt = n / kTT;
   const int nkb = (nt + kGRow - 1) / kGRow;
-  // lane: k within the tile, one of two y, one of four tiles; wave: the y pair; step it:
-  // x = it / 2 and the half of the row it % 2
-  const int zl = threadIdx.x & 7;
-  const int y = 2 * (int)(threadIdx.x >> 6) + ((threadIdx.x >> 3) & 1);
-  const int mq = (threadIdx.x >> 4) & 3;
+  const int z = threadIdx.x & 63;     // cell along k within the row
+  const int m = z >> 3, zl = z & 7;   // tile within the row, k within the tile
+  const int w = threadIdx.x >> 6;     // wave: y = w (even steps) or 4 + w (odd steps)
   unsigned long long sum = 0ull;
   for (int64_t row = xcd_block(blockIdx.x, gridDim.x); row < rows; row += gridDim.x) {
     const int tkb = (int)(row % nkb);
     const int tj = (int)((row / nkb) % nt);
     const int ti = (int)(row / ((int64_t)nkb * nt));
     const int tk0 = tkb * kGRow;
-    __syncthreads();  // the previous row's table is no longer read
+    __syncthreads();  // the previous row's table and staged halo are no longer read
     if (threadIdx.x < 9 * (kGRow + 2)) {
       const int q = threadIdx.x / (kGRow + 2), mm = threadIdx.x % (kGRow + 2);
       const int tt = (wrap_any(ti + q / 3 - 1, nt) * nt + wrap_any(tj + q % 3 - 1, nt)) * nt +
@@ -768,43 +793,73 @@ __global__ __launch_bounds__(kGatherThreads) void k_tile_gather(
       (&s_tile[0][0][0])[threadIdx.x] = cnt > 0 ? tt : -1;
     }
     __syncthreads();
-    // tiles past the end of a short row (tk0 + m >= nt) are wrapped neighbours: their
-    // loads stay in bounds, their cells are not written
-    unsigned long long v[16];
+    // halo pieces for the cells at k = 0, 7 of each tile: loaded whole (zero when empty)
+    unsigned long long st[kStageIt];
 #pragma unroll
-    for (int it = 0; it < 16; ++it) {
-      const int m = 4 * (it & 1) + mq;
-      const int tc = s_tile[1][1][m + 1];
-      const size_t own = (size_t)(tc >= 0 ? tc : 0) * S;  // an empty tile's box is not used
-      const unsigned long long q = tbox[own + gather_slot(0, 0, 0, it >> 1, y, zl)];
-      v[it] = tc >= 0 ? q : 0ull;
-    }
-#pragma unroll
-    for (int it = 0; it < 16; ++it) {
-      const int x = it >> 1, m = 4 * (it & 1) + mq;
-#pragma unroll
-      for (int dx = -1; dx <= 1; ++dx) {
-        if ((dx == -1 && x != 0) || (dx == 1 && x != kTT - 1)) continue;
-#pragma unroll
-        for (int dy = -1; dy <= 1; ++dy) {
-          if ((dy == -1 && y != 0) || (dy == 1 && y != kTT - 1)) continue;
-#pragma unroll
-          for (int dz = -1; dz <= 1; ++dz) {
-            if (dx == 0 && dy == 0 && dz == 0) continue;
-            if ((dz == -1 && zl != 0) || (dz == 1 && zl != kTT - 1)) continue;
-            const int t = s_tile[dx + 1][dy + 1][m + 1 + dz];
-            if (t >= 0) v[it] += tbox[(size_t)t * S + gather_slot(dx, dy, dz, x, y, zl)];
-          }
-        }
+    for (int u = 0; u < kStageIt; ++u) {
+      const int q = (int)threadIdx.x + u * kGatherThreads;
+      int t = -1, slot = 0;
+      if (q < 1024) {  // k faces: side 0 from tile mm - 1 (its high k face), 1 from mm + 1
+        const int sd = q >> 9, mm = (q >> 6) & 7, in = q & 63;
+        t = s_tile[1][1][mm + 2 * sd];
+        slot = kFaceBase + 64 * (5 - sd) + in;
+      } else if (q < 1280) {  // edges along j: neighbour (dx, 0, dz)
+        const int o = q - 1024, sx = o >> 7, sz = (o >> 6) & 1, mm = (o >> 3) & 7, yy = o & 7;
+        t = s_tile[2 * sx][1][mm + 2 * sz];
+        slot = kEdgeBase + 8 * (4 + 2 * (1 - sx) + (1 - sz)) + yy;
+      } else if (q < 1536) {  // edges along i: neighbour (0, dy, dz)
+        const int o = q - 1280, sy = o >> 7, sz = (o >> 6) & 1, mm = (o >> 3) & 7, xx = o & 7;
+        t = s_tile[1][2 * sy][mm + 2 * sz];
+        slot = kEdgeBase + 8 * (0 + 2 * (1 - sy) + (1 - sz)) + xx;
+      } else if (q < kStage) {  // corners: neighbour (dx, dy, dz)
+        const int o = q - 1536, sx = o >> 5, sy = (o >> 4) & 1, sz = (o >> 3) & 1, mm = o & 7;
+        t = s_tile[2 * sx][2 * sy][mm + 2 * sz];
+        slot = kCornerBase + 4 * (1 - sx) + 2 * (1 - sy) + (1 - sz);
       }
+      st[u] = t >= 0 ? tbox[(size_t)t * S + slot] : 0ull;
     }
 #pragma unroll
+    for (int u = 0; u < kStageIt; ++u) {
+      const int q = (int)threadIdx.x + u * kGatherThreads;
+      if (q < 1024) (&s_zf[0][0][0])[q] = st[u];
+      else if (q < 1280) (&s_exz[0][0][0][0])[q - 1024] = st[u];
+      else if (q < 1536) (&s_eyz[0][0][0][0])[q - 1280] = st[u];
+      else if (q < kStage) (&s_cr[0][0][0][0])[q - 1536] = st[u];
+    }
+    __syncthreads();
+    // per wave step: interior, x and y faces, edges along k from the boxes, the rest
+    // from LDS; cells of tiles past the end of a short row are not written
+    const bool live = tk0 + m < nt;
+    const int tc = s_tile[1][1][m + 1];
+    const int txm = s_tile[0][1][m + 1], txp = s_tile[2][1][m + 1];
+    const int tym = s_tile[1][0][m + 1], typ = s_tile[1][2][m + 1];
+    const size_t own = (size_t)(tc >= 0 ? tc : 0) * S;  // an empty tile's box is not used
+    const size_t kg = (size_t)tk0 * kTT + z;
+    const int sz = zl == kTT - 1;
+    const bool kedge = zl == 0 || zl == kTT - 1;
+#pragma unroll
     for (int it = 0; it < 16; ++it) {
-      const int x = it >> 1, tk = tk0 + 4 * (it & 1) + mq;
-      if (tk < nt) {
-        rho[((size_t)(ti * kTT + x) * n + (tj * kTT + y)) * n + (size_t)tk * kTT + zl] =
-            (float)((double)v[it] * scale);
-        sum += v[it];
+      const int x = it >> 1, y = 4 * (it & 1) + w;
+      const unsigned long long q = tbox[own + gather_slot(0, 0, 0, x, y, zl)];
+      unsigned long long a = tc >= 0 ? q : 0ull;
+      if (x == 0 && txm >= 0) a += tbox[(size_t)txm * S + gather_slot(-1, 0, 0, x, y, zl)];
+      if (x == kTT - 1 && txp >= 0) a += tbox[(size_t)txp * S + gather_slot(1, 0, 0, x, y, zl)];
+      if (y == 0 && tym >= 0) a += tbox[(size_t)tym * S + gather_slot(0, -1, 0, x, y, zl)];
+      if (y == kTT - 1 && typ >= 0) a += tbox[(size_t)typ * S + gather_slot(0, 1, 0, x, y, zl)];
+      if ((x == 0 || x == kTT - 1) && (y == 0 || y == kTT - 1)) {
+        const int dx = x == 0 ? -1 : 1, dy = y == 0 ? -1 : 1;
+        const int t = s_tile[dx + 1][dy + 1][m + 1];
+        if (t >= 0) a += tbox[(size_t)t * S + gather_slot(dx, dy, 0, x, y, zl)];
+      }
+      if (kedge) {
+        a += s_zf[sz][m][x * 8 + y];
+        if (x == 0 || x == kTT - 1) a += s_exz[x != 0][sz][m][y];
+        if (y == 0 || y == kTT - 1) a += s_eyz[y != 0][sz][m][x];
+        if ((x == 0 || x == kTT - 1) && (y == 0 || y == kTT - 1)) a += s_cr[x != 0][y != 0][sz][m];
+      }
+      if (live) {
+        rho[((size_t)(ti * kTT + x) * n + (tj * kTT + y)) * n + kg] = (float)((double)a * scale);
+        sum += a;
       }
     }
   }
