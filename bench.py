@@ -368,7 +368,10 @@ def main():
     t0 = time.perf_counter()
     for i in range(args.steps):
         if args.reorder_every > 0 and step % args.reorder_every == 0:
-            pm.pm_reorder(ctx, off_d, vel=vel_d, acc=acc, cell=cell_d)
+            # a chain keeps no accelerations between its steps (the next opening kick is
+            # applied with the closing one): only pm_kdk steps need acc permuted too
+            pm.pm_reorder(ctx, off_d, vel=vel_d, acc=acc if args.no_chain else None,
+                          cell=cell_d)
         st = one_step(step)
         cycles.append(st.mg.cycles)
         if args.stage_log:

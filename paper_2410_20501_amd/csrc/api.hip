@@ -510,11 +510,29 @@ int pm_reorder(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, float *acc, i
     ctx->reorder_cap = cap;
   }
   hipStream_t s = (hipStream_t)stream;
-  ctx->hist_next = false;  // the particles move: a chained step's tile keys are stale
-  const bool tile_major = (ctx->n % 8) == 0;
-  PM_HIP(ctx, launch_sort_by_cell(ctx, pos, cell, np, poskind, s, tile_major ? 1 : 0));
-  PM_HIP(ctx, launch_apply_perm(ctx, pos, poskind == PM_POS_CELLOFF ? cell : nullptr, vel, acc, ids,
-                                np, s));
+  int32_t *cell_arr = poskind == PM_POS_CELLOFF ? cell : nullptr;
+  if (ctx->n % 8 == 0) {
+    // tile-major cell order in two levels: bucket by 8^3 tile (with the tile histogram
+    // and keys a chained step's drift made for these arrays, when it did), then order
+    // each tile's bucket by cell in LDS
+    bool hist = false;
+    if (ctx->hist_next && ctx->hist_pos == pos && ctx->hist_cell == cell && ctx->hist_np == np) {
+      PM_HIP(ctx, hipMemcpyAsync(ctx->cell_count, ctx->cell_count2,
+                                 sizeof(int32_t) * (size_t)(ctx->n / 8 * (ctx->n / 8) * (ctx->n / 8) + 1),
+                                 hipMemcpyDeviceToDevice, s));
+      hist = true;
+    }
+    ctx->hist_next = false;  // the particles move: the tile keys are stale afterwards
+    ctx->hist_ready = false;
+    PM_HIP(ctx, launch_sort_by_cell(ctx, pos, cell, np, poskind, s, 2, hist));
+    PM_HIP(ctx, launch_tile_cell_sort(ctx, pos, cell, poskind, ctx->pcell, s));
+    PM_HIP(ctx, launch_apply_perm(ctx, ctx->pcell, pos, cell_arr, vel, acc, ids, np, s));
+  } else {
+    ctx->hist_next = false;
+    ctx->hist_ready = false;
+    PM_HIP(ctx, launch_sort_by_cell(ctx, pos, cell, np, poskind, s, 0));
+    PM_HIP(ctx, launch_apply_perm(ctx, ctx->perm, pos, cell_arr, vel, acc, ids, np, s));
+  }
   return PM_OK;
 }
 

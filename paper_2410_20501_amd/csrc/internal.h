@@ -110,8 +110,13 @@ hipError_t launch_deposit_atomic(const float *pos, const int32_t *cell, int64_t 
 // hist_done: the counts and keys were already made (by the fused kick-drift)
 hipError_t launch_sort_by_cell(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np,
                                int poskind, hipStream_t s, int keymode, bool hist_done = false);
-hipError_t launch_apply_perm(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, float *acc,
-                             int64_t *ids, int64_t np, hipStream_t s);
+// second level of the tile-major cell sort: the tile buckets left by keymode 2 ordered
+// by cell within each tile; out[i] = particle at place i (n % 8 == 0)
+hipError_t launch_tile_cell_sort(pm_ctx *ctx, const float *pos, const int32_t *cell,
+                                 int poskind, int32_t *out, hipStream_t s);
+// arrays[i] = arrays[order[i]] for every array given (NULL: skipped)
+hipError_t launch_apply_perm(pm_ctx *ctx, const int32_t *order, float *pos, int32_t *cell,
+                             float *vel, float *acc, int64_t *ids, int64_t np, hipStream_t s);
 hipError_t launch_deposit_pull(pm_ctx *ctx, const float *pos, int64_t np, int poskind, int mas,
                                float mass, float *rho, hipStream_t s);
 hipError_t launch_deposit_own(pm_ctx *ctx, const float *pos, const int32_t *cell, int poskind,

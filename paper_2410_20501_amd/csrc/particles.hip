@@ -234,6 +234,7 @@ constexpr int kKeyCell = 0, kKeyTileCell = 1, kKeyTile = 2;
 // consecutive particles; the scatter issues the cursor atomics of all rounds before it
 // needs their results, so their latencies overlap.
 constexpr int kSortRounds = 4;
+constexpr int kScatterHash = 2048;  // LDS hash slots of the scatter (block's distinct keys)
 
 // Key of each particle's cell; histogram with one atomic per run of equal keys in a
 // wave (particles that are neighbours in memory mostly share keys).
@@ -300,15 +301,31 @@ __global__ __launch_bounds__(kGThreads) void k_deposit_chunk(const float *__rest
   pm_chunk::deposit_chunk<MAS, PK>(pos, cell, pm_chunk::RangeIndex{base, np}, n, mass, rho);
 }
 
-
+// Scatter of the counting sort: every particle takes the next place of its key's
+// bucket (cursor[key] runs from the bucket's start to its end) and writes its index
+// there; the order within a bucket is not fixed.
 __global__ __launch_bounds__(kThreads) void k_scatter_perm(const int32_t *__restrict__ pcell,
                                                            int64_t np,
                                                            int32_t *__restrict__ cursor,
                                                            int32_t *__restrict__ perm) {
+  // the block's distinct keys in an LDS hash table (open addressing; at most
+  // kThreads * kSortRounds keys in twice as many slots, so every probe sequence ends);
+  // each run of equal keys in a wave adds its length to its key's count and takes its
+  // place from it, then one global cursor atomic per distinct key serves the block
+  constexpr int H = kScatterHash;
+  static_assert(H >= 2 * kThreads * kSortRounds && (H & (H - 1)) == 0, "scatter hash size");
+  __shared__ int s_key[H];
+  __shared__ int s_cnt[H];
+  __shared__ int s_base[H];
+  for (int i = threadIdx.x; i < H; i += kThreads) {
+    s_key[i] = -1;
+    s_cnt[i] = 0;
+  }
+  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int64_t wbase =
       ((int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6)) * 64 * kSortRounds;
-  int c[kSortRounds], base[kSortRounds], head[kSortRounds];
+  int c[kSortRounds], slot[kSortRounds], rank[kSortRounds];
 #pragma unroll
   for (int m = 0; m < kSortRounds; ++m) {
     const int64_t p = wbase + m * 64 + lane;
@@ -317,15 +334,29 @@ __global__ __launch_bounds__(kThreads) void k_scatter_perm(const int32_t *__rest
 #pragma unroll
   for (int m = 0; m < kSortRounds; ++m) {
     const WaveRun r = wave_runs(c[m]);
-    head[m] = r.headlane;
-    base[m] = 0;
-    if (r.head && c[m] >= 0) base[m] = atomicAdd(&cursor[c[m]], r.len);
+    int sl = 0, rb = 0;
+    if (r.head && c[m] >= 0) {
+      // slot = key mod H: neighbouring keys take neighbouring slots, so the cursor
+      // atomics below (thread i serves slots i, i + kThreads, ...) stay coalesced
+      unsigned h = (unsigned)c[m] & (unsigned)(H - 1);
+      for (int probe = 0; probe < H; ++probe) {
+        const int old = atomicCAS(&s_key[h], -1, c[m]);
+        if (old == -1 || old == c[m]) break;
+        h = (h + 1u) & (unsigned)(H - 1);
+      }
+      sl = (int)h;
+      rb = atomicAdd(&s_cnt[h], r.len);
+    }
+    slot[m] = __shfl(sl, r.headlane, 64);
+    rank[m] = __shfl(rb, r.headlane, 64) + (lane - r.headlane);
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i < H; i += kThreads)
+    if (s_key[i] >= 0) s_base[i] = atomicAdd(&cursor[s_key[i]], s_cnt[i]);
+  __syncthreads();
 #pragma unroll
-  for (int m = 0; m < kSortRounds; ++m) {
-    const int b = __shfl(base[m], head[m], 64);
-    if (c[m] >= 0) perm[b + (lane - head[m])] = (int32_t)(wbase + m * 64 + lane);
-  }
+  for (int m = 0; m < kSortRounds; ++m)
+    if (c[m] >= 0) perm[s_base[slot[m]] + rank[m]] = (int32_t)(wbase + m * 64 + lane);
 }
 
 // Exclusive scan of `count` (len entries) into `start`, in three passes.
@@ -735,6 +766,75 @@ __global__ __launch_bounds__(kDThreads) void k_deposit_own(const float *__restri
     int hx, hy, hz;
     pm_tilebox::box_of(o, hx, hy, hz);
     dst[o] = box[(hx * kTH + hy) * kTH + hz];
+  }
+}
+
+// Second level of the tile-major cell sort (pm_reorder): particles already bucketed by
+// 8^3 tile (perm, end) are ordered by cell within their tile, one workgroup per tile
+// with a counting sort over the tile's 512 cells in LDS (the tile-major key of a cell
+// is tile * 512 + its local index); out[i] is the particle at place i. The order within
+// a cell is not fixed.
+template <int PK>
+__device__ __forceinline__ int local_cell_of(const float *__restrict__ pos,
+                                             const int32_t *__restrict__ cell, int p, int n,
+                                             int ti, int tj, int tk) {
+  float x[3] = {0.f, 0.f, 0.f};
+  if constexpr (PK == PM_POS_BOX) {
+    x[0] = pos[3 * (size_t)p];
+    x[1] = pos[3 * (size_t)p + 1];
+    x[2] = pos[3 * (size_t)p + 2];
+  }
+  int c[3];
+  float o[3];
+  cell_offset_of<PK>(x, PK == PM_POS_BOX ? 0 : cell[p], n, c, o);
+  const int lx = c[0] - ti * 8, ly = c[1] - tj * 8, lz = c[2] - tk * 8;
+  // the bucket's particles lie in this tile (same cell rule as its key); the clamp only
+  // keeps every index in the table
+  const int l = (lx * 8 + ly) * 8 + lz;
+  return l < 0 ? 0 : (l > 511 ? 511 : l);
+}
+
+template <int PK>
+__global__ __launch_bounds__(kThreads) void k_tile_cell_sort(const float *__restrict__ pos,
+                                                             const int32_t *__restrict__ cell,
+                                                             const int32_t *__restrict__ end,
+                                                             const int32_t *__restrict__ perm,
+                                                             int n, int32_t *__restrict__ out) {
+  static_assert(2 * kThreads == 512, "two cells per thread");
+  __shared__ int s_cnt[512];
+  __shared__ int s_wave[kThreads / 64];
+  const int nt = n / 8;
+  const int tile = blockIdx.x;
+  const int tk = tile % nt, tj = (tile / nt) % nt, ti = tile / (nt * nt);
+  const int b = tile > 0 ? end[tile - 1] : 0, e = end[tile];
+  if (b >= e) return;
+  s_cnt[2 * threadIdx.x] = 0;
+  s_cnt[2 * threadIdx.x + 1] = 0;
+  __syncthreads();
+  for (int l = b + (int)threadIdx.x; l < e; l += kThreads)
+    atomicAdd(&s_cnt[local_cell_of<PK>(pos, cell, perm[l], n, ti, tj, tk)], 1);
+  __syncthreads();
+  // exclusive scan of the 512 counts (two per thread) into per-cell cursors
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c0 = s_cnt[2 * threadIdx.x], c1 = s_cnt[2 * threadIdx.x + 1];
+  int v = c0 + c1;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(v, o, 64);
+    if (lane >= o) v += u;
+  }
+  if (lane == 63) s_wave[wave] = v;
+  __syncthreads();
+  int off = 0;
+  for (int w = 0; w < wave; ++w) off += s_wave[w];
+  const int excl = off + v - (c0 + c1);
+  s_cnt[2 * threadIdx.x] = excl;
+  s_cnt[2 * threadIdx.x + 1] = excl + c0;
+  __syncthreads();
+  for (int l = b + (int)threadIdx.x; l < e; l += kThreads) {
+    const int p = perm[l];
+    const int slot = atomicAdd(&s_cnt[local_cell_of<PK>(pos, cell, p, n, ti, tj, tk)], 1);
+    out[b + slot] = p;
   }
 }
 
@@ -1268,8 +1368,21 @@ hipError_t launch_deposit_pull(pm_ctx *ctx, const float *pos, int64_t np, int po
 }
 
 // Permute particle arrays in place through ctx->perm (the sorted order), via scratch.
-hipError_t launch_apply_perm(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, float *acc,
-                             int64_t *ids, int64_t np, hipStream_t s) {
+hipError_t launch_tile_cell_sort(pm_ctx *ctx, const float *pos, const int32_t *cell,
+                                 int poskind, int32_t *out, hipStream_t s) {
+  const int n = ctx->n;
+  const unsigned nt = (unsigned)((int64_t)n * n * n / 512);
+  if (poskind == PM_POS_BOX)
+    k_tile_cell_sort<PM_POS_BOX><<<nt, kThreads, 0, s>>>(pos, cell, ctx->cell_count, ctx->perm, n,
+                                                         out);
+  else
+    k_tile_cell_sort<PM_POS_CELLOFF><<<nt, kThreads, 0, s>>>(pos, cell, ctx->cell_count,
+                                                             ctx->perm, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_perm(pm_ctx *ctx, const int32_t *order, float *pos, int32_t *cell,
+                             float *vel, float *acc, int64_t *ids, int64_t np, hipStream_t s) {
   if (np == 0) return hipSuccess;
   const unsigned nb = blocks_for(np, kThreads);
   float *tmp = (float *)ctx->reorder_tmp;
@@ -1277,15 +1390,15 @@ hipError_t launch_apply_perm(pm_ctx *ctx, float *pos, int32_t *cell, float *vel,
   float *f3[3] = {pos, vel, acc};
   for (int a = 0; a < 3 && e == hipSuccess; ++a) {
     if (!f3[a]) continue;
-    k_gather_perm<float, 3><<<nb, kThreads, 0, s>>>(f3[a], ctx->perm, np, tmp);
+    k_gather_perm<float, 3><<<nb, kThreads, 0, s>>>(f3[a], order, np, tmp);
     e = hipMemcpyAsync(f3[a], tmp, sizeof(float) * 3 * (size_t)np, hipMemcpyDeviceToDevice, s);
   }
   if (e == hipSuccess && cell) {
-    k_gather_perm<int32_t, 1><<<nb, kThreads, 0, s>>>(cell, ctx->perm, np, (int32_t *)tmp);
+    k_gather_perm<int32_t, 1><<<nb, kThreads, 0, s>>>(cell, order, np, (int32_t *)tmp);
     e = hipMemcpyAsync(cell, tmp, sizeof(int32_t) * (size_t)np, hipMemcpyDeviceToDevice, s);
   }
   if (e == hipSuccess && ids) {
-    k_gather_perm<int64_t, 1><<<nb, kThreads, 0, s>>>(ids, ctx->perm, np, (int64_t *)tmp);
+    k_gather_perm<int64_t, 1><<<nb, kThreads, 0, s>>>(ids, order, np, (int64_t *)tmp);
     e = hipMemcpyAsync(ids, tmp, sizeof(int64_t) * (size_t)np, hipMemcpyDeviceToDevice, s);
   }
   if (e != hipSuccess) return e;
