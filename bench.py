@@ -79,8 +79,11 @@ BENCH_TOL = 1e-6
 BENCH_MAX_CYCLES = 40
 
 
-def bench_step_params(pm, order=BENCH_ORDER, tol=BENCH_TOL):
-    return pm.default_step_params(order=order, tol=tol, max_cycles=BENCH_MAX_CYCLES)
+def bench_step_params(pm, order=BENCH_ORDER, tol=BENCH_TOL, omega=None):
+    p = pm.default_step_params(order=order, tol=tol, max_cycles=BENCH_MAX_CYCLES)
+    if omega is not None:
+        p.mg.omega = omega
+    return p
 
 
 def make_inputs(n, seed=3, a0=0.02):
@@ -271,6 +274,9 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--order", default=BENCH_ORDER, choices=["atomic", "sorted"])
     ap.add_argument("--tol", type=float, default=BENCH_TOL)
+    ap.add_argument("--omega", type=float, default=None,
+                    help="over-relaxation factor of the red-black sweeps (default: the "
+                         "library's)")
     ap.add_argument("--reorder-every", type=int, default=10,
                     help="re-sort particles by tile every this many steps (0: never)")
     ap.add_argument("--no-chain", action="store_true",
@@ -330,7 +336,7 @@ def main():
     phi = torch.zeros((n, n, n), device=dev)
     acc = torch.empty((npart, 3), device=dev)
     ctx = pm.Context(n, npart)
-    params = bench_step_params(pm, args.order, args.tol)
+    params = bench_step_params(pm, args.order, args.tol, args.omega)
     torch.cuda.synchronize()
     if args.reorder_every > 0:
         pm.pm_reorder(ctx, off_d, vel=vel_d, cell=cell_d)

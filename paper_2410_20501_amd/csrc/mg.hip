@@ -328,6 +328,19 @@ __global__ __launch_bounds__(kThreads) void k_finish_phi(const float *__restrict
   phi[c] = fmaf(scale, u[c], -*mean);
 }
 
+// The same, four cells per thread (16-byte aligned arrays, count % 4 == 0).
+__global__ __launch_bounds__(kThreads) void k_finish_phi4(const float4 *__restrict__ u,
+                                                          float4 *__restrict__ phi, int64_t count4,
+                                                          float scale,
+                                                          const float *__restrict__ mean) {
+  const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (c >= count4) return;
+  const float m = *mean;
+  const float4 v = u[c];
+  phi[c] = make_float4(fmaf(scale, v.x, -m), fmaf(scale, v.y, -m), fmaf(scale, v.z, -m),
+                       fmaf(scale, v.w, -m));
+}
+
 // Coarsest level: one workgroup, in LDS (coarse_solve.h).
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_solve(
     float *__restrict__ ug, const float *__restrict__ fg, float scale,
@@ -603,8 +616,15 @@ int pm_mg_solve(pm_ctx *ctx, const float *rho, float coef, float *phi, const pm_
   if (have_sum) {
     // copy (when the iterate is in the other buffer), rescale (when no cycle ran) and
     // remove the mean (gauge) in one pass
-    k_finish_phi<<<blocks_for(count, kThreads), kThreads, 0, s>>>(sv.cur[0], phi, count,
-                                                                   final_scale, ctx->mean_f + 1);
+    const bool vec = count % 4 == 0 && reinterpret_cast<uintptr_t>(sv.cur[0]) % 16 == 0 &&
+                     reinterpret_cast<uintptr_t>(phi) % 16 == 0;
+    if (vec)
+      k_finish_phi4<<<blocks_for(count / 4, kThreads), kThreads, 0, s>>>(
+          reinterpret_cast<const float4 *>(sv.cur[0]), reinterpret_cast<float4 *>(phi), count / 4,
+          final_scale, ctx->mean_f + 1);
+    else
+      k_finish_phi<<<blocks_for(count, kThreads), kThreads, 0, s>>>(sv.cur[0], phi, count,
+                                                                     final_scale, ctx->mean_f + 1);
   } else {
     if (sv.cur[0] != phi)
       PM_HIP(ctx, hipMemcpyAsync(phi, sv.cur[0], sizeof(float) * count, hipMemcpyDeviceToDevice, s));

@@ -1090,8 +1090,8 @@ __global__ __launch_bounds__(kIThreads) void k_interp_tile_phi(float *__restrict
   const int i0 = ti * kTT - 3, j0 = tj * kTT - 3, k0 = tk * kTT - 3;
   const int p_begin = tile > 0 ? end[tile - 1] : 0;
   const int p_end = end[tile];
-  TileParticle cur{};
-  if (p_begin < p_end) cur = load_tile_particle<PK>(pos, cell, perm, vel, p_begin, p_end);
+  if (p_begin >= p_end) return;  // no particles: nothing to stage (the histogram gets none)
+  TileParticle cur = load_tile_particle<PK>(pos, cell, perm, vel, p_begin, p_end);
   for (int e = threadIdx.x; e < PH * PH * PH; e += kIThreads) {
     const int hx = e / (PH * PH), hy = (e / PH) % PH, hz = e % PH;
     ps[e] = phi[((size_t)wrap_index(i0 + hx, n) * n + wrap_index(j0 + hy, n)) * n +
