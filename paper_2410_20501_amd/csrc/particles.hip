@@ -1009,12 +1009,24 @@ __global__ __launch_bounds__(kOThreads) void k_interp_tile(const float *__restri
   const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
   const int tk = tile % nt, tj = (tile / nt) % nt, ti = tile / (nt * nt);
   const int i0 = ti * kTT - 1, j0 = tj * kTT - 1, k0 = tk * kTT - 1;
-  for (int e = threadIdx.x; e < 3 * kTHalo; e += kOThreads) {
-    const int h = e / 3, d = e - 3 * h;
-    const int hx = h / (kTH * kTH), hy = (h / kTH) % kTH, hz = h % kTH;
-    const size_t gc = ((size_t)wrap_index(i0 + hx, n) * n + wrap_index(j0 + hy, n)) * n +
-                      wrap_index(k0 + hz, n);
-    gs[d][h] = g[3 * gc + d];
+  // all of a thread's loads in flight before the first LDS write
+  constexpr int kGS = 3 * kTHalo, kGSIt = (kGS + kOThreads - 1) / kOThreads;
+  float gv[kGSIt];
+#pragma unroll
+  for (int u = 0; u < kGSIt; ++u) {
+    const int e = (int)threadIdx.x + u * kOThreads;
+    if (e < kGS) {
+      const int h = e / 3, d = e - 3 * h;
+      const int hx = h / (kTH * kTH), hy = (h / kTH) % kTH, hz = h % kTH;
+      const size_t gc = ((size_t)wrap_index(i0 + hx, n) * n + wrap_index(j0 + hy, n)) * n +
+                        wrap_index(k0 + hz, n);
+      gv[u] = g[3 * gc + d];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kGSIt; ++u) {
+    const int e = (int)threadIdx.x + u * kOThreads;
+    if (e < kGS) gs[e % 3][e / 3] = gv[u];
   }
   __syncthreads();
   const int p_begin = tile > 0 ? end[tile - 1] : 0;
@@ -1092,10 +1104,22 @@ __global__ __launch_bounds__(kIThreads) void k_interp_tile_phi(float *__restrict
   const int p_end = end[tile];
   if (p_begin >= p_end) return;  // no particles: nothing to stage (the histogram gets none)
   TileParticle cur = load_tile_particle<PK>(pos, cell, perm, vel, p_begin, p_end);
-  for (int e = threadIdx.x; e < PH * PH * PH; e += kIThreads) {
-    const int hx = e / (PH * PH), hy = (e / PH) % PH, hz = e % PH;
-    ps[e] = phi[((size_t)wrap_index(i0 + hx, n) * n + wrap_index(j0 + hy, n)) * n +
-                wrap_index(k0 + hz, n)];
+  // all of a thread's loads in flight before the first LDS write
+  constexpr int kPS = PH * PH * PH, kPSIt = (kPS + kIThreads - 1) / kIThreads;
+  float pv[kPSIt];
+#pragma unroll
+  for (int u = 0; u < kPSIt; ++u) {
+    const int e = (int)threadIdx.x + u * kIThreads;
+    if (e < kPS) {
+      const int hx = e / (PH * PH), hy = (e / PH) % PH, hz = e % PH;
+      pv[u] = phi[((size_t)wrap_index(i0 + hx, n) * n + wrap_index(j0 + hy, n)) * n +
+                  wrap_index(k0 + hz, n)];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kPSIt; ++u) {
+    const int e = (int)threadIdx.x + u * kIThreads;
+    if (e < kPS) ps[e] = pv[u];
   }
   __syncthreads();
   const float c1 = 2.0f / 3.0f, c2 = -1.0f / 12.0f, inv_h = (float)n;
