@@ -576,22 +576,27 @@ struct TileParticle {
   float v[3];  // velocity (when the kernel kicks)
 };
 
-template <int PK>
-__device__ __forceinline__ TileParticle load_tile_particle(const float *__restrict__ pos,
-                                                           const int32_t *__restrict__ cell,
-                                                           const int32_t *__restrict__ perm,
-                                                           const float *__restrict__ vel, int l0,
-                                                           int p_end) {
-  TileParticle t{};
+// Index of this thread's particle in the pass of the bucket starting at l0 (-1 past
+// its end). The tile kernels load indices two passes ahead of use and particle data
+// one pass ahead, so that every wait is on loads issued a whole pass earlier.
+__device__ __forceinline__ int tile_index(const int32_t *__restrict__ perm, int l0, int p_end) {
   const int l = l0 + (int)threadIdx.x;
-  t.live = l < p_end;
+  return l < p_end ? perm[l] : -1;
+}
+
+template <int PK>
+__device__ __forceinline__ TileParticle load_particle(const float *__restrict__ pos,
+                                                      const int32_t *__restrict__ cell,
+                                                      const float *__restrict__ vel, int p) {
+  TileParticle t{};
+  t.live = p >= 0;
   if (t.live) {
-    t.p = perm[l];
-    const size_t q = 3 * (size_t)t.p;
+    t.p = p;
+    const size_t q = 3 * (size_t)p;
     t.x[0] = pos[q];
     t.x[1] = pos[q + 1];
     t.x[2] = pos[q + 2];
-    t.c = PK == PM_POS_BOX ? 0 : cell[t.p];
+    t.c = PK == PM_POS_BOX ? 0 : cell[p];
     if (vel) {
       t.v[0] = vel[q];
       t.v[1] = vel[q + 1];
@@ -639,21 +644,21 @@ __global__ __launch_bounds__(kDThreads) void k_deposit_own(const float *__restri
   const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
   const int tk = tile % nt, tj = (tile / nt) % nt, ti = tile / (nt * nt);
   // particles bucketed by tile: end[t] is the end of tile t's bucket; the first pass's
-  // particles are loaded before the box is cleared, each later pass's during the one
-  // before it
+  // particles (and the second's indices) are loaded before the box is cleared, each
+  // later pass's particles during the pass before it, their indices two passes before
   const int p_begin = tile > 0 ? end[tile - 1] : 0;
   const int p_end = end[tile];
   if (p_begin >= p_end) return;  // empty tile: the gather pass skips its box
-  TileParticle cur = load_tile_particle<PK>(pos, cell, perm, nullptr, p_begin, p_end);
+  TileParticle cur = load_particle<PK>(pos, cell, nullptr, tile_index(perm, p_begin, p_end));
+  int pnext = tile_index(perm, p_begin + kDThreads, p_end);
   for (int i = threadIdx.x; i < kTHalo; i += kDThreads) box[i] = 0ull;
   for (int i = threadIdx.x; i < (kDThreads / 64) * kTThreads; i += kDThreads)
     (&s_cnt[0][0])[i] = 0u;
   __syncthreads();
   unsigned int *cnt = s_cnt[threadIdx.x >> 6];
   for (int l0 = p_begin; l0 < p_end; l0 += kDThreads) {
-    TileParticle nxt{};
-    if (l0 + kDThreads < p_end)
-      nxt = load_tile_particle<PK>(pos, cell, perm, nullptr, l0 + kDThreads, p_end);
+    const TileParticle nxt = load_particle<PK>(pos, cell, nullptr, pnext);
+    pnext = tile_index(perm, l0 + 2 * kDThreads, p_end);
     bool act = cur.live;
     int c[3] = {0, 0, 0};
     float o[3] = {0.f, 0.f, 0.f};
@@ -1103,7 +1108,8 @@ __global__ __launch_bounds__(kIThreads) void k_interp_tile_phi(float *__restrict
   const int p_begin = tile > 0 ? end[tile - 1] : 0;
   const int p_end = end[tile];
   if (p_begin >= p_end) return;  // no particles: nothing to stage (the histogram gets none)
-  TileParticle cur = load_tile_particle<PK>(pos, cell, perm, vel, p_begin, p_end);
+  TileParticle cur = load_particle<PK>(pos, cell, vel, tile_index(perm, p_begin, p_end));
+  int pnext = tile_index(perm, p_begin + kIThreads, p_end);
   // all of a thread's loads in flight before the first LDS write
   constexpr int kPS = PH * PH * PH, kPSIt = (kPS + kIThreads - 1) / kIThreads;
   float pv[kPSIt];
@@ -1138,12 +1144,12 @@ __global__ __launch_bounds__(kIThreads) void k_interp_tile_phi(float *__restrict
   }
   __syncthreads();
   // uniform trip count: with DRIFT the whole wave takes part in the histogram's run
-  // detection. Each pass loads the particles of the next pass before it works on its
-  // own, and the first pass's particles are loaded before the potential is staged.
+  // detection. Each pass loads the particles of the next pass and the indices of the
+  // one after before it works on its own; the first pass's particles and the second's
+  // indices are loaded before the potential is staged.
   for (int l0 = p_begin; l0 < p_end; l0 += kIThreads) {
-    TileParticle nxt{};
-    if (l0 + kIThreads < p_end)
-      nxt = load_tile_particle<PK>(pos, cell, perm, vel, l0 + kIThreads, p_end);
+    const TileParticle nxt = load_particle<PK>(pos, cell, vel, pnext);
+    pnext = tile_index(perm, l0 + 2 * kIThreads, p_end);
     int key = -1;
     if (cur.live) {
       const int p = cur.p;
