@@ -41,15 +41,15 @@ MEASURED_TRAFFIC = {
     # and 39 dispatches)
     "smooth": ("paper_2410_20501_amd/csrc/mg_stream.hip",
                "2b87898978e98b927bae449e8df805f9f8512d9a2842e8dbbaed256f841e8de7",
-               743229.0, 539558.0, 2.0, 1.0),
-    # deposit: the particle-owned tile kernel plus the fixed-point conversion pass
+               740728.0, 539558.0, 2.0, 1.0),
+    # deposit: the particle-owned tile kernel plus the gather pass over the tile boxes
     "deposit": ("paper_2410_20501_amd/csrc/particles.hip",
-                "e5bd27cf019f3c28999719b0bcda7bb9172aa9fb1c99eab7769b07b0f1d7ffa2",
-                1900967.0, 4910880.0, 2.0, 1.0),
+                "63c68818acdf547f2da41b20679efd87b310ac39ea5924dc3d3f32a12a80f9b9",
+                2507804.0, 2573627.0, 2.0, 1.0),
     # interpolation with the fused gradient, kicks and drift of a chained step
     "interp": ("paper_2410_20501_amd/csrc/particles.hip",
-               "e5bd27cf019f3c28999719b0bcda7bb9172aa9fb1c99eab7769b07b0f1d7ffa2",
-               2935020.0, 5120295.0, 2.0, 1.0),
+               "63c68818acdf547f2da41b20679efd87b310ac39ea5924dc3d3f32a12a80f9b9",
+               2828121.0, 5383610.0, 2.0, 1.0),
 }
 
 
