@@ -921,7 +921,10 @@ __global__ __launch_bounds__(kGatherThreads) void k_tile_gather(
         t = s_tile[2 * sx][2 * sy][mm + 2 * sz];
         slot = kCornerBase + 4 * (1 - sx) + 2 * (1 - sy) + (1 - sz);
       }
-      st[u] = t >= 0 ? tbox[(size_t)t * S + slot] : 0ull;
+      // loaded unconditionally (an empty tile or a surplus item reads tile 0's box and
+      // is dropped), so that all of a thread's loads are in flight together
+      const unsigned long long val = tbox[(size_t)(t >= 0 ? t : 0) * S + slot];
+      st[u] = t >= 0 ? val : 0ull;
     }
 #pragma unroll
     for (int u = 0; u < kStageIt; ++u) {
@@ -942,29 +945,61 @@ __global__ __launch_bounds__(kGatherThreads) void k_tile_gather(
     const size_t kg = (size_t)tk0 * kTT + z;
     const int sz = zl == kTT - 1;
     const bool kedge = zl == 0 || zl == kTT - 1;
+    // every load of a half row (x = 4 h .. 4 h + 3) is issued unconditionally and
+    // without branches between them (a piece a cell does not take reads the cell's own
+    // interior value instead and is dropped), so that they are in flight together; the
+    // LDS pieces and the stores follow
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+      unsigned long long v[8];
 #pragma unroll
-    for (int it = 0; it < 16; ++it) {
-      const int x = it >> 1, y = 4 * (it & 1) + w;
-      const unsigned long long q = tbox[own + gather_slot(0, 0, 0, x, y, zl)];
-      unsigned long long a = tc >= 0 ? q : 0ull;
-      if (x == 0 && txm >= 0) a += tbox[(size_t)txm * S + gather_slot(-1, 0, 0, x, y, zl)];
-      if (x == kTT - 1 && txp >= 0) a += tbox[(size_t)txp * S + gather_slot(1, 0, 0, x, y, zl)];
-      if (y == 0 && tym >= 0) a += tbox[(size_t)tym * S + gather_slot(0, -1, 0, x, y, zl)];
-      if (y == kTT - 1 && typ >= 0) a += tbox[(size_t)typ * S + gather_slot(0, 1, 0, x, y, zl)];
-      if ((x == 0 || x == kTT - 1) && (y == 0 || y == kTT - 1)) {
-        const int dx = x == 0 ? -1 : 1, dy = y == 0 ? -1 : 1;
-        const int t = s_tile[dx + 1][dy + 1][m + 1];
-        if (t >= 0) a += tbox[(size_t)t * S + gather_slot(dx, dy, 0, x, y, zl)];
+      for (int j = 0; j < 8; ++j) {
+        const int x = 4 * h + (j >> 1), y = 4 * (j & 1) + w;
+        const size_t self = own + gather_slot(0, 0, 0, x, y, zl);
+        const unsigned long long q = tbox[self];
+        unsigned long long a = tc >= 0 ? q : 0ull;
+        const bool xe = x == 0 || x == kTT - 1;
+        const int tx = x == 0 ? txm : txp;
+        const bool tkx = xe && tx >= 0;
+        const unsigned long long vx =
+            tbox[tkx ? (size_t)tx * S + gather_slot(x == 0 ? -1 : 1, 0, 0, x, y, zl) : self];
+        a += tkx ? vx : 0ull;
+        const bool ye = y == 0 || y == kTT - 1;  // wave-uniform
+        const int ty = y == 0 ? tym : typ;
+        const bool tky = ye && ty >= 0;
+        const unsigned long long vy =
+            tbox[tky ? (size_t)ty * S + gather_slot(0, y == 0 ? -1 : 1, 0, x, y, zl) : self];
+        a += tky ? vy : 0ull;
+        if (j < 2 || j >= 6) {  // x = 0 or 3 (h = 0), x = 4 or 7 (h = 1): the edges along k
+          const int dx = j < 2 ? -1 : 1, dy = y == 0 ? -1 : 1;
+          const int t = s_tile[dx + 1][dy + 1][m + 1];
+          const bool te = xe && ye && t >= 0;
+          const unsigned long long ve =
+              tbox[te ? (size_t)t * S + gather_slot(dx, dy, 0, x, y, zl) : self];
+          a += te ? ve : 0ull;
+        }
+        v[j] = a;
       }
       if (kedge) {
-        a += s_zf[sz][m][x * 8 + y];
-        if (x == 0 || x == kTT - 1) a += s_exz[x != 0][sz][m][y];
-        if (y == 0 || y == kTT - 1) a += s_eyz[y != 0][sz][m][x];
-        if ((x == 0 || x == kTT - 1) && (y == 0 || y == kTT - 1)) a += s_cr[x != 0][y != 0][sz][m];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int x = 4 * h + (j >> 1), y = 4 * (j & 1) + w;
+          unsigned long long a = s_zf[sz][m][x * 8 + y];
+          if (x == 0 || x == kTT - 1) a += s_exz[x != 0][sz][m][y];
+          if (y == 0 || y == kTT - 1) a += s_eyz[y != 0][sz][m][x];
+          if ((x == 0 || x == kTT - 1) && (y == 0 || y == kTT - 1))
+            a += s_cr[x != 0][y != 0][sz][m];
+          v[j] += a;
+        }
       }
       if (live) {
-        rho[((size_t)(ti * kTT + x) * n + (tj * kTT + y)) * n + kg] = (float)((double)a * scale);
-        sum += a;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int x = 4 * h + (j >> 1), y = 4 * (j & 1) + w;
+          rho[((size_t)(ti * kTT + x) * n + (tj * kTT + y)) * n + kg] =
+              (float)((double)v[j] * scale);
+          sum += v[j];
+        }
       }
     }
   }
@@ -1086,7 +1121,7 @@ __global__ __launch_bounds__(kOThreads) void k_interp_tile(const float *__restri
 // leapfrog step is folded into `kick`), and the new 8^3-tile key and histogram of the
 // next deposit's sort go to pcell and count, as in the kick-drift kernel. Each particle
 // is read and written by the one thread that owns it in its tile bucket.
-template <int MAS, int PK, bool DRIFT>
+template <int MAS, int PK, bool DRIFT, bool VEC>
 __global__ __launch_bounds__(kIThreads) void k_interp_tile_phi(float *__restrict__ pos,
                                                                int32_t *__restrict__ cell,
                                                                const int32_t *__restrict__ end,
@@ -1098,44 +1133,67 @@ __global__ __launch_bounds__(kIThreads) void k_interp_tile_phi(float *__restrict
                                                                float kick, float dt,
                                                                int32_t *__restrict__ pcell,
                                                                int32_t *__restrict__ count) {
-  constexpr int PH = kTT + 6;  // tile + 3 cells per side
-  __shared__ float ps[PH * PH * PH];
+  // potential of the tile plus 3 cells per side along i and j; along k 16 cells from 4
+  // below the tile (rows of four aligned float4, one of them unused per side)
+  constexpr int PH = kTT + 6, PZ = kTT + 8;
+  __shared__ __align__(16) float ps[PH * PH * PZ + 4];  // + a slot for surplus staging items
   __shared__ float gs[3][kTHalo];
   const int nt = n / kTT;
   const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
   const int tk = tile % nt, tj = (tile / nt) % nt, ti = tile / (nt * nt);
-  const int i0 = ti * kTT - 3, j0 = tj * kTT - 3, k0 = tk * kTT - 3;
+  const int i0 = ti * kTT - 3, j0 = tj * kTT - 3, k0 = tk * kTT - 4;
   const int p_begin = tile > 0 ? end[tile - 1] : 0;
   const int p_end = end[tile];
   if (p_begin >= p_end) return;  // no particles: nothing to stage (the histogram gets none)
   TileParticle cur = load_particle<PK>(pos, cell, vel, tile_index(perm, p_begin, p_end));
   int pnext = tile_index(perm, p_begin + kIThreads, p_end);
   // all of a thread's loads in flight before the first LDS write
-  constexpr int kPS = PH * PH * PH, kPSIt = (kPS + kIThreads - 1) / kIThreads;
-  float pv[kPSIt];
+  if constexpr (VEC) {
+    // n % 8 == 0 and phi 16-byte aligned: every float4 of a row (k0 + 4 q, q = 0..3,
+    // wrapped) lies in one row of the grid at a multiple of four
+    constexpr int kItems = PH * PH * 4, kIt = (kItems + kIThreads - 1) / kIThreads;
+    float4 pv[kIt];
 #pragma unroll
-  for (int u = 0; u < kPSIt; ++u) {
-    const int e = (int)threadIdx.x + u * kIThreads;
-    if (e < kPS) {
-      const int hx = e / (PH * PH), hy = (e / PH) % PH, hz = e % PH;
+    for (int u = 0; u < kIt; ++u) {
+      // past the last item: a repeated load of it (every element written, so the array
+      // stays in registers and all loads are in flight together)
+      const int e = min((int)threadIdx.x + u * kIThreads, kItems - 1);
+      const int r = e >> 2, q = e & 3, hx = r / PH, hy = r % PH;
+      pv[u] = *reinterpret_cast<const float4 *>(
+          phi + ((size_t)wrap_index(i0 + hx, n) * n + wrap_index(j0 + hy, n)) * n +
+          wrap_index(k0 + 4 * q, n));
+    }
+#pragma unroll
+    for (int u = 0; u < kIt; ++u) {
+      const int e = (int)threadIdx.x + u * kIThreads;
+      const int at = e < kItems ? (e >> 2) * PZ + 4 * (e & 3) : PH * PH * PZ;
+      *reinterpret_cast<float4 *>(ps + at) = pv[u];
+    }
+  } else {
+    constexpr int kPS = PH * PH * PZ, kPSIt = (kPS + kIThreads - 1) / kIThreads;
+    float pv[kPSIt];
+#pragma unroll
+    for (int u = 0; u < kPSIt; ++u) {
+      const int e = min((int)threadIdx.x + u * kIThreads, kPS - 1);
+      const int hx = e / (PH * PZ), hy = (e / PZ) % PH, hz = e % PZ;
       pv[u] = phi[((size_t)wrap_index(i0 + hx, n) * n + wrap_index(j0 + hy, n)) * n +
                   wrap_index(k0 + hz, n)];
     }
-  }
 #pragma unroll
-  for (int u = 0; u < kPSIt; ++u) {
-    const int e = (int)threadIdx.x + u * kIThreads;
-    if (e < kPS) ps[e] = pv[u];
+    for (int u = 0; u < kPSIt; ++u) {
+      const int e = (int)threadIdx.x + u * kIThreads;
+      ps[e < kPS ? e : kPS] = pv[u];
+    }
   }
   __syncthreads();
   const float c1 = 2.0f / 3.0f, c2 = -1.0f / 12.0f, inv_h = (float)n;
   for (int h = threadIdx.x; h < kTHalo; h += kIThreads) {
-    const int cx = h / (kTH * kTH) + 2, cy = (h / kTH) % kTH + 2, cz = h % kTH + 2;
-    const int c = (cx * PH + cy) * PH + cz;
-    float gx = c1 * (ps[c + PH * PH] - ps[c - PH * PH]);
-    gx = fmaf(c2, ps[c + 2 * PH * PH] - ps[c - 2 * PH * PH], gx);
-    float gy = c1 * (ps[c + PH] - ps[c - PH]);
-    gy = fmaf(c2, ps[c + 2 * PH] - ps[c - 2 * PH], gy);
+    const int cx = h / (kTH * kTH) + 2, cy = (h / kTH) % kTH + 2, cz = h % kTH + 3;
+    const int c = (cx * PH + cy) * PZ + cz;
+    float gx = c1 * (ps[c + PH * PZ] - ps[c - PH * PZ]);
+    gx = fmaf(c2, ps[c + 2 * PH * PZ] - ps[c - 2 * PH * PZ], gx);
+    float gy = c1 * (ps[c + PZ] - ps[c - PZ]);
+    gy = fmaf(c2, ps[c + 2 * PZ] - ps[c - 2 * PZ], gy);
     float gz = c1 * (ps[c + 1] - ps[c - 1]);
     gz = fmaf(c2, ps[c + 2] - ps[c - 2], gz);
     gs[0][h] = -inv_h * gx;
@@ -1353,14 +1411,21 @@ hipError_t launch_interp_tile_phi(pm_ctx *ctx, float *pos, int32_t *cell, int po
   const unsigned nt = (unsigned)((int64_t)n * n * n / kTThreads);
   const bool drift = count != nullptr;
   if (drift && (!vel || !pcell)) return hipErrorInvalidValue;
-#define PM_ITP(M, K)                                                                             \
+  // the potential is staged with float4 loads when its rows are 16-byte aligned
+  const bool vec = reinterpret_cast<uintptr_t>(phi) % 16 == 0;
+#define PM_ITP2(M, K, V)                                                                         \
   do {                                                                                           \
     if (drift)                                                                                   \
-      k_interp_tile_phi<M, K, true><<<nt, kIThreads, 0, s>>>(                                    \
+      k_interp_tile_phi<M, K, true, V><<<nt, kIThreads, 0, s>>>(                                 \
           pos, cell, ctx->cell_count, ctx->perm, n, phi, acc, vel, kick, dt, pcell, count);      \
     else                                                                                         \
-      k_interp_tile_phi<M, K, false><<<nt, kIThreads, 0, s>>>(                                   \
+      k_interp_tile_phi<M, K, false, V><<<nt, kIThreads, 0, s>>>(                                \
           pos, cell, ctx->cell_count, ctx->perm, n, phi, acc, vel, kick, dt, nullptr, nullptr);  \
+  } while (0)
+#define PM_ITP(M, K)                                                                             \
+  do {                                                                                           \
+    if (vec) PM_ITP2(M, K, true);                                                                \
+    else PM_ITP2(M, K, false);                                                                   \
   } while (0)
   if (mas == PM_TSC) {
     if (poskind == PM_POS_BOX) PM_ITP(3, PM_POS_BOX);
@@ -1370,6 +1435,7 @@ hipError_t launch_interp_tile_phi(pm_ctx *ctx, float *pos, int32_t *cell, int po
     else PM_ITP(2, PM_POS_CELLOFF);
   }
 #undef PM_ITP
+#undef PM_ITP2
   return hipGetLastError();
 }
 

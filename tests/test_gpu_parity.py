@@ -218,6 +218,52 @@ def test_reorder_permutes_consistently(lib, celloff):
     assert np.abs(host(rho2) - host(rho1)).max() <= 4e-6 * host(rho1).max()
 
 
+@pytest.mark.parametrize("celloff", [False, True])
+def test_sorted_paths_off_tile_grid(lib, celloff):
+    """n % 8 != 0: the sorted deposit gathers through the row-major cell sort and
+    pm_reorder orders by row-major cell. Random positions spread each scatter block's
+    1024 keys over all 36^3 cells, so its key table (slot = key mod 2048) must probe."""
+    _say(f"sorted paths n=36 celloff={celloff}")
+    n = 36
+    rng = np.random.Generator(np.random.PCG64(41))
+    pos = rng.uniform(0, 1, size=(30011, 3)).astype(np.float32)
+    vel = rng.normal(0, 1, size=pos.shape).astype(np.float32)
+    ctx = ctx_for(lib, n, pos.shape[0])
+    ids = torch.arange(pos.shape[0], device="cuda", dtype=torch.int64)
+    if celloff:
+        cell_np, off = icgen.to_cell_offset(pos, n)
+        p, cell = dev(off), dev(cell_np, torch.int32)
+        u = opm.cell_units(n, cell=cell_np, off=off)
+        du = 0.0
+    else:
+        p, cell = dev(pos), None
+        u = opm.cell_units(n, pos=pos)
+        du = n * 2.0 ** -24
+    ref = opm.deposit(u, n, "tsc")
+    tol = 4e-6 * max(1.0, ref.max()) + 6 * du * ref.max()
+    rho0 = torch.empty((n, n, n), device="cuda")
+    lib.pm_deposit(ctx, p, rho0, cell=cell, order="sorted")
+    assert np.abs(host(rho0) - ref).max() <= tol
+    v = dev(vel)
+    lib.pm_reorder(ctx, p, vel=v, ids=ids, cell=cell)
+    idn = host(ids).astype(np.int64)
+    assert np.array_equal(np.sort(idn), np.arange(pos.shape[0]))
+    np.testing.assert_array_equal(host(v), vel[idn])
+    if celloff:
+        np.testing.assert_array_equal(host(cell).astype(np.int64), cell_np[idn])
+        np.testing.assert_array_equal(host(p), off[idn])
+        c = cell_np[idn].astype(np.int64)
+    else:
+        np.testing.assert_array_equal(host(p), pos[idn])
+        # the cell rule in FP32, as the kernels apply it (x n rounds before the floor)
+        q = np.floor(pos[idn] * np.float32(n)).astype(np.int64) % n
+        c = (q[:, 0] * n + q[:, 1]) * n + q[:, 2]
+    assert np.all(np.diff(c) >= 0)
+    rho1 = torch.empty((n, n, n), device="cuda")
+    lib.pm_deposit(ctx, p, rho1, cell=cell, order="sorted")
+    assert np.abs(host(rho1) - ref).max() <= tol
+
+
 def test_deposit_empty(lib):
     _say("deposit np=0")
     n = 16
