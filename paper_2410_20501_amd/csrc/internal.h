@@ -106,7 +106,7 @@ int pm_hip_check(pm_ctx *ctx, hipError_t e, const char *what);
 // particles.hip
 hipError_t launch_deposit_atomic(const float *pos, const int32_t *cell, int64_t np, int poskind,
                                  int mas, int n, float mass, float *rho, hipStream_t s);
-// keymode: 0 row-major cells, 1 tile-major cells (n % 8 == 0), 2 tiles of 8^3 cells;
+// keymode: 0 row-major cells, 2 tiles of 8^3 cells (n % 8 == 0);
 // hist_done: the counts and keys were already made (by the fused kick-drift)
 hipError_t launch_sort_by_cell(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np,
                                int poskind, hipStream_t s, int keymode, bool hist_done = false);

@@ -220,16 +220,9 @@ __global__ __launch_bounds__(kThreads) void k_kick_drift(float *__restrict__ pos
 
 // ------------------------------------------------------------------ counting sort
 
-// Tile-major cell key: 8^3-cell tiles in row-major order, cells row-major inside
-// a tile (a bijection of [0, n^3) when n is a multiple of 8).
-__device__ __forceinline__ int tile_key(int ci, int cj, int ck, int n) {
-  const int nt = n >> 3;
-  return ((((ci >> 3) * nt + (cj >> 3)) * nt + (ck >> 3)) << 9) +
-         ((((ci & 7) << 3) + (cj & 7)) << 3) + (ck & 7);
-}
-
-// Sort keys: 0 = row-major cell, 1 = tile-major cell, 2 = 8^3-cell tile.
-constexpr int kKeyCell = 0, kKeyTileCell = 1, kKeyTile = 2;
+// Sort keys: 0 = row-major cell, 2 = 8^3-cell tile (tiles row-major). The tile-major
+// cell order of pm_reorder is the tile sort followed by k_tile_cell_sort.
+constexpr int kKeyCell = 0, kKeyTile = 2;
 // Every wave of the histogram and scatter kernels handles kSortRounds runs of 64
 // consecutive particles; the scatter issues the cursor atomics of all rounds before it
 // needs their results, so their latencies overlap.
@@ -263,9 +256,7 @@ __global__ __launch_bounds__(kThreads) void k_cell_hist(const float *__restrict_
         q[1] = (cc / n) - q[0] * n;
         q[2] = cc - (cc / n) * n;
       }
-      if constexpr (KEY == kKeyTileCell) {
-        c = tile_key(q[0], q[1], q[2], n);
-      } else if constexpr (KEY == kKeyTile) {
+      if constexpr (KEY == kKeyTile) {
         const int nt = n >> 3;
         c = ((q[0] >> 3) * nt + (q[1] >> 3)) * nt + (q[2] >> 3);
       } else {
@@ -1334,11 +1325,9 @@ hipError_t launch_sort_by_cell(pm_ctx *ctx, const float *pos, const int32_t *cel
   k_cell_hist<PKV, KEYV><<<nbr, kThreads, 0, s>>>(pos, cell, np, n, ctx->pcell, ctx->cell_count)
     if (poskind == PM_POS_BOX) {
       if (keymode == kKeyTile) PM_HIST(PM_POS_BOX, kKeyTile);
-      else if (keymode == kKeyTileCell) PM_HIST(PM_POS_BOX, kKeyTileCell);
       else PM_HIST(PM_POS_BOX, kKeyCell);
     } else {
       if (keymode == kKeyTile) PM_HIST(PM_POS_CELLOFF, kKeyTile);
-      else if (keymode == kKeyTileCell) PM_HIST(PM_POS_CELLOFF, kKeyTileCell);
       else PM_HIST(PM_POS_CELLOFF, kKeyCell);
     }
 #undef PM_HIST
