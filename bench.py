@@ -41,15 +41,15 @@ MEASURED_TRAFFIC = {
     # and 39 dispatches)
     "smooth": ("paper_2410_20501_amd/csrc/mg_stream.hip",
                "2b87898978e98b927bae449e8df805f9f8512d9a2842e8dbbaed256f841e8de7",
-               740728.0, 539558.0, 2.0, 1.0),
+               743905.0, 539558.0, 2.0, 1.0),
     # deposit: the particle-owned tile kernel plus the gather pass over the tile boxes
     "deposit": ("paper_2410_20501_amd/csrc/particles.hip",
-                "63c68818acdf547f2da41b20679efd87b310ac39ea5924dc3d3f32a12a80f9b9",
-                2507804.0, 2573627.0, 2.0, 1.0),
+                "cca1acecb69ab7c83c71bd0343e048f76941900cbfe9bc91eadb7df0e6270e62",
+                2493321.0, 2573651.0, 2.0, 1.0),
     # interpolation with the fused gradient, kicks and drift of a chained step
     "interp": ("paper_2410_20501_amd/csrc/particles.hip",
-               "63c68818acdf547f2da41b20679efd87b310ac39ea5924dc3d3f32a12a80f9b9",
-               2828121.0, 5383610.0, 2.0, 1.0),
+               "cca1acecb69ab7c83c71bd0343e048f76941900cbfe9bc91eadb7df0e6270e62",
+               2750314.0, 5295974.0, 2.0, 1.0),
 }
 
 
