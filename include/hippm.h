@@ -138,11 +138,16 @@ const char *pm_last_error(const pm_ctx *ctx);
  *   sum order across chunks, hence the last bits, may differ between runs).
  *   Fast when neighbours in memory are neighbours in space (see pm_reorder);
  *   chunks spread over more than 4096 cells use one atomic per weight.
- * order PM_DEPOSIT_SORTED: particles are bucketed by cell (a counting sort into
- *   context scratch; the caller's arrays are not reordered), then every cell
- *   gathers the contributions of the particles in its 27 (8) neighbour cells
- *   with one write per cell. Contributions are summed in 64-bit fixed point,
- *   so the result is bitwise identical for any particle order and any run. */
+ * order PM_DEPOSIT_SORTED: particles are bucketed (a counting sort into context
+ *   scratch; the caller's arrays are not reordered). With n % 8 == 0 the buckets
+ *   are 8^3-cell tiles: each tile adds its particles' weights into a box of the
+ *   tile plus a one-cell halo on chip and stores the box (10^3 64-bit values per
+ *   tile of context scratch, allocated on first use); a second pass sums for
+ *   every cell the boxes that cover it, with one write per cell. Otherwise the
+ *   buckets are cells and every cell gathers the contributions of the particles
+ *   in its 27 (8) neighbour cells. Contributions are summed in 64-bit fixed
+ *   point, so the result is bitwise identical for any particle order and any
+ *   run. */
 int pm_deposit(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np,
                int poskind, int mas, int order, float *rho, pm_stream stream);
 
@@ -378,7 +383,8 @@ int pm_tune(pm_batch *batch, float *pos, float *phi, const pm_step_params *param
 /* Per-kernel timing (measurement support). pm_kernel_timer(ctx, kernel, cap)
  * starts recording a pair of HIP events on the caller's stream around every
  * launch of one kernel (at most cap launches; resets the previous record):
- *   PM_KERNEL_DEPOSIT  the deposit's gather kernel of PM_DEPOSIT_SORTED;
+ *   PM_KERNEL_DEPOSIT  the deposit kernels of PM_DEPOSIT_SORTED (the tile
+ *                      pass and the gather pass, or the cell gather);
  *                      algorithmic bytes 12 per particle + 4 per cell
  *   PM_KERNEL_SMOOTH   the streaming smoother on the finest grid (n >= 256);
  *                      algorithmic bytes 12 per cell per pass, 12.5 for the

@@ -165,7 +165,7 @@ hipError_t launch_sum_moments(const float *x, int64_t count, double *partial, do
 
 // mg.hip
 // rho_mean_ready: ctx->mean_f[0] already holds the mean of rho (the sorted deposit's
-// conversion pass sums its exact fixed-point values), so the solve does not re-read rho
+// gather pass sums its exact fixed-point values), so the solve does not re-read rho
 int pm_mg_solve(pm_ctx *ctx, const float *rho, float coef, float *phi, const pm_mg_params *p,
                 pm_mg_stats *stats, hipStream_t s, float warm_scale = 1.0f,
                 bool rho_mean_ready = false);
