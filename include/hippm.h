@@ -91,6 +91,14 @@ typedef struct {
   int guess;          /* pm_guess: Jacobi step -h^2 f/6, or phi as given */
   int fixed_cycles;   /* > 0: run exactly this many cycles, no convergence test
                          and no host synchronisation (graph-capturable) */
+  float alpha;        /* > 0: the paper's rule (Sect. 3.7.1, Eq. multigrid_threshold)
+                         instead of tol: stop when ||f - L phi||_2 (over the fine
+                         cells) < alpha ||tau||_2 (over the coarse cells), with the
+                         truncation-error estimate tau = L_H(R phi) - R(L_h phi),
+                         H = 2h and R the cycle's restriction (the paper's value is
+                         0.005); costs two extra grid passes and a host
+                         synchronisation per test; needs n > 16; 0: the tol rule.
+                         Ignored by the batched step (fixed cycles). */
 } pm_mg_params;
 
 typedef struct {
@@ -116,7 +124,8 @@ typedef struct {
 } pm_step_stats;
 
 /* Default parameters: TSC, atomic deposit, multigrid 2/2 sweeps, omega 1,
- * tol 1e-6, 50 cycles, full-weighting restriction, Jacobi guess, Omega_m 1. */
+ * tol 1e-6 (alpha 0), 50 cycles, full-weighting restriction, Jacobi guess,
+ * Omega_m 1. */
 void pm_default_step_params(pm_step_params *p);
 
 /* Create a context for an n^3 grid and up to np_max particles.

@@ -125,8 +125,19 @@ def vcycle(u, f, h, pre=2, post=2, omega=1.0, restriction="fw", coarsest=16):
     return u
 
 
-def solve(f, h, u0=None, tol=1e-10, max_cycles=50, **kw):
-    """V-cycles until ||f - L u|| / ||f|| < tol. Returns (u, list of relative residuals).
+def truncation_error(u, h, restriction="fw"):
+    """Estimate of the truncation error on the coarse grid (paper Sect. 3.7.1, the
+    estimate it takes from the literature): tau = L_H(R u) - R(L_h u), H = 2h, with R
+    the restriction of the cycle."""
+    return laplacian7(restrict(u, restriction), 2.0 * h) - restrict(laplacian7(u, h), restriction)
+
+
+def solve(f, h, u0=None, tol=1e-10, max_cycles=50, alpha=None, **kw):
+    """V-cycles until ||f - L u|| / ||f|| < tol, or, with alpha, until the residual is
+    below alpha times the truncation-error estimate (Eq. multigrid_threshold): with
+    both norms the square root of the sum of squares over their own grid (the
+    residual over the fine cells, the estimate over the coarse cells),
+    ||f - L u|| < alpha ||truncation_error(u)||. Returns (u, list of relative residuals).
 
     The starting guess is the Jacobi step u = -h^2 f / 6 (paper Sect. 3.7.1)
     unless u0 (a warm start, paper Sect. 3.9) is given.
@@ -135,10 +146,16 @@ def solve(f, h, u0=None, tol=1e-10, max_cycles=50, **kw):
     u = -(h * h) * f / 6.0 if u0 is None else np.array(u0, dtype=np.float64)
     fn = np.linalg.norm(f)
     hist = []
+    restriction = kw.get("restriction", "fw")
     for _ in range(max_cycles + 1):
-        rel = np.linalg.norm(f - laplacian7(u, h)) / fn if fn > 0 else 0.0
+        dn = np.linalg.norm(f - laplacian7(u, h))
+        rel = dn / fn if fn > 0 else 0.0
         hist.append(rel)
-        if rel < tol or len(hist) > max_cycles:
+        if alpha is not None:
+            done = dn < alpha * np.linalg.norm(truncation_error(u, h, restriction))
+        else:
+            done = rel < tol
+        if done or len(hist) > max_cycles:
             break
         vcycle(u, f, h, **kw)
     return u - u.mean(), hist

@@ -317,6 +317,80 @@ __global__ __launch_bounds__(RED_THREADS) void k_triple_final(const double *__re
   }
 }
 
+// Truncation-error estimate of the paper's alternative stopping rule (Sect. 3.7.1,
+// Eq. multigrid_threshold): tau = L_H(R u) - R(L_h u) on the coarse grid (H = 2h), with
+// R the restriction of the cycle. First pass, one thread per coarse cell: R(scale u)
+// and R(L_h scale u) over the fine cells the restriction weighs (full weighting: 4^3
+// cells with (1,3,3,1)/8 per axis; average: the 8 children).
+template <int KIND>
+__global__ __launch_bounds__(kThreads) void k_tau_restrict(const float *__restrict__ u, int n,
+                                                           float inv_h2, float scale,
+                                                           float *__restrict__ ru,
+                                                           float *__restrict__ rlu) {
+  const int nc = n >> 1;
+  const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (c >= (int64_t)nc * nc * nc) return;
+  const int K = (int)(c % nc), J = (int)((c / nc) % nc), I = (int)(c / ((int64_t)nc * nc));
+  constexpr int M = KIND == PM_RESTRICT_FW ? 4 : 2;
+  const float w[4] = {1.f, 3.f, 3.f, 1.f};
+  const size_t nn = (size_t)n * n;
+  float su = 0.f, sl = 0.f;
+  for (int a = 0; a < M; ++a)
+    for (int b = 0; b < M; ++b)
+      for (int e = 0; e < M; ++e) {
+        const int off = KIND == PM_RESTRICT_FW ? -1 : 0;
+        const int i = wrap_index(2 * I + off + a, n), j = wrap_index(2 * J + off + b, n),
+                  k = wrap_index(2 * K + off + e, n);
+        const float wt = KIND == PM_RESTRICT_FW ? w[a] * w[b] * w[e] : 1.0f;
+        const float uc = u[i * nn + (size_t)j * n + k];
+        const float lap = (u[wrap_index(i - 1, n) * nn + (size_t)j * n + k] - uc) +
+                          (u[wrap_index(i + 1, n) * nn + (size_t)j * n + k] - uc) +
+                          (u[i * nn + (size_t)wrap_index(j - 1, n) * n + k] - uc) +
+                          (u[i * nn + (size_t)wrap_index(j + 1, n) * n + k] - uc) +
+                          (u[i * nn + (size_t)j * n + wrap_index(k - 1, n)] - uc) +
+                          (u[i * nn + (size_t)j * n + wrap_index(k + 1, n)] - uc);
+        su = fmaf(wt, uc, su);
+        sl = fmaf(wt, lap * inv_h2, sl);
+      }
+  const float norm = KIND == PM_RESTRICT_FW ? scale / 512.0f : scale / 8.0f;
+  ru[c] = norm * su;
+  rlu[c] = norm * sl;
+}
+
+// Second pass: tau = L_H(R u) - R(L_h u) per coarse cell, block sums of tau^2 (the
+// second slot of each pair is zero).
+__global__ __launch_bounds__(RED_THREADS) void k_tau_norm(const float *__restrict__ ru,
+                                                          const float *__restrict__ rlu, int nc,
+                                                          float inv_H2,
+                                                          double *__restrict__ partial) {
+  const int64_t count = (int64_t)nc * nc * nc;
+  const size_t nn = (size_t)nc * nc;
+  double s1 = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * RED_THREADS;
+  for (int64_t t = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; t < count; t += stride) {
+    const int k = (int)(t % nc), j = (int)((t / nc) % nc), i = (int)(t / (int64_t)nn);
+    const float c = ru[t];
+    const float lap = (ru[wrap_index(i - 1, nc) * nn + (size_t)j * nc + k] - c) +
+                      (ru[wrap_index(i + 1, nc) * nn + (size_t)j * nc + k] - c) +
+                      (ru[i * nn + (size_t)wrap_index(j - 1, nc) * nc + k] - c) +
+                      (ru[i * nn + (size_t)wrap_index(j + 1, nc) * nc + k] - c) +
+                      (ru[i * nn + (size_t)j * nc + wrap_index(k - 1, nc)] - c) +
+                      (ru[i * nn + (size_t)j * nc + wrap_index(k + 1, nc)] - c);
+    const double tau = (double)(lap * inv_H2) - (double)rlu[t];
+    s1 += tau * tau;
+  }
+  __shared__ double l1[RED_THREADS / 64];
+  s1 = wave_sum(s1);
+  if ((threadIdx.x & 63) == 0) l1[threadIdx.x >> 6] = s1;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0;
+    for (int q = 0; q < RED_THREADS / 64; ++q) a += l1[q];
+    partial[2 * blockIdx.x] = a;
+    partial[2 * blockIdx.x + 1] = 0.0;
+  }
+}
+
 // phi = scale * u - mean, with the device-resident mean of scale * u: the copy of the
 // final iterate, its warm-start rescaling (when no cycle ran) and the gauge in one pass.
 __global__ __launch_bounds__(kThreads) void k_finish_phi(const float *__restrict__ u,
@@ -480,6 +554,28 @@ struct Solver {
   }
 
   // ||f - L u||^2 and ||f||^2 at level 0 into ctx->red_result[0..1] (plain kernel)
+  // ||tau||_2 of the iterate scale * u on the level-0 grid, with level 1's arrays as
+  // scratch (free between cycles); synchronises the stream
+  hipError_t tau_norm(const float *u, float scale, double *out) {
+    const int n = ctx->lev[0].n, nc = n / 2;
+    const int64_t ncount = (int64_t)nc * nc * nc;
+    const float inv_h2 = 1.0f / h2(0);
+    float *ru = ctx->lev[1].u, *rlu = ctx->lev[1].f;
+    const unsigned gb = (unsigned)((ncount + kThreads - 1) / kThreads);
+    if (p->restrict_kind == PM_RESTRICT_AVG)
+      k_tau_restrict<PM_RESTRICT_AVG><<<gb, kThreads, 0, s>>>(u, n, inv_h2, scale, ru, rlu);
+    else
+      k_tau_restrict<PM_RESTRICT_FW><<<gb, kThreads, 0, s>>>(u, n, inv_h2, scale, ru, rlu);
+    const int nb = (int)std::min<int64_t>(RED_BLOCKS, (ncount + RED_THREADS - 1) / RED_THREADS);
+    k_tau_norm<<<nb, RED_THREADS, 0, s>>>(ru, rlu, nc, 0.25f * inv_h2, ctx->red_partial);
+    k_pair_final<<<1, RED_THREADS, 0, s>>>(ctx->red_partial, nb, ctx->red_result);
+    hipError_t e = hipMemcpyAsync(ctx->host_result + 2, ctx->red_result, sizeof(double),
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    *out = std::sqrt(ctx->host_result[2]);
+    return e;
+  }
+
   void norms() {
     const int n = ctx->lev[0].n;
     const int64_t count = (int64_t)n * n * n;
@@ -540,6 +636,8 @@ int pm_mg_solve(pm_ctx *ctx, const float *rho, float coef, float *phi, const pm_
     sv.alt[l] = ctx->lev[l].alt;
   }
   const bool fused_norm = sv.streaming(0) && p->pre > 0 && ctx->nlevels > 1;
+  if (p->alpha > 0.0f && p->fixed_cycles <= 0 && ctx->nlevels < 2)
+    return pm_fail(ctx, PM_ERR_ARG, "alpha needs a coarser multigrid level (n > 16)");
   // with the fused norm, the tolerance loop's first pass reads the warm start rescaled
   float uscale = 1.0f;
   if (p->guess == PM_GUESS_JACOBI)
@@ -588,7 +686,17 @@ int pm_mg_solve(pm_ctx *ctx, const float *rho, float coef, float *phi, const pm_
         return PM_OK;
       }
       rel[cycles] = sqrt(ctx->host_result[0]) / fnorm;
-      if (rel[cycles] < p->tol) {
+      bool converged = rel[cycles] < p->tol;
+      if (p->alpha > 0.0f) {
+        // the paper's rule: residual below alpha times the truncation-error estimate of
+        // the same iterate (the input of the norm pass, read rescaled in the first one)
+        const double dnorm = sqrt(ctx->host_result[0]);
+        double tnorm = 0.0;
+        PM_HIP(ctx, sv.tau_norm(fused_norm ? sv.alt[0] : sv.cur[0],
+                                fused_norm && cycles == 0 ? uscale : 1.0f, &tnorm));
+        converged = dnorm < (double)p->alpha * tnorm;
+      }
+      if (converged) {
         status = PM_OK;
       } else if (cycles > 0 && rel[cycles] < 1e-4 && rel[cycles - 1] < 1.5 * rel[cycles]) {
         status = PM_WARN_FLOOR;

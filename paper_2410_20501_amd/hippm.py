@@ -46,7 +46,7 @@ class PMWarning(UserWarning):
 class MGParams(ctypes.Structure):
     _fields_ = [("pre", c_int), ("post", c_int), ("omega", c_float), ("tol", c_float),
                 ("max_cycles", c_int), ("restrict_kind", c_int), ("guess", c_int),
-                ("fixed_cycles", c_int)]
+                ("fixed_cycles", c_int), ("alpha", c_float)]
 
 
 class MGStats(ctypes.Structure):

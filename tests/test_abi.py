@@ -50,9 +50,12 @@ def test_create_rejects_negative_particle_count():
 
 def test_struct_layouts_match_header():
     import paper_2410_20501_amd as pm
-    assert ctypes.sizeof(pm.MGParams) == 32
+    assert ctypes.sizeof(pm.MGParams) == 36
+    assert pm.MGParams.alpha.offset == 32
     assert ctypes.sizeof(pm.MGStats) == 8 + 64 * 8
     assert pm.StepParams.mg.offset == 24
+    assert pm.StepParams.timing.offset == 60
     assert ctypes.sizeof(pm.StepParams) == 64
     p = pm.default_step_params()
     assert (p.mas, p.mg.pre, p.mg.post, p.mg.omega, p.mg.max_cycles) == (3, 2, 2, 1.0, 50)
+    assert p.mg.alpha == 0.0

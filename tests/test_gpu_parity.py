@@ -12,6 +12,7 @@ import pytest
 import torch
 
 import icgen
+from oracle import mg as omg
 from oracle import pm as opm
 
 pytestmark = pytest.mark.gpu
@@ -363,6 +364,45 @@ def test_mg_single_mode_closed_form(lib):
     lam = sum(2.0 * (np.cos(2 * np.pi * md / n) - 1.0) for md in m) * n * n
     ref = (rho.astype(np.float64) - rho.astype(np.float64).mean()) / lam
     assert rel_l2(host(phi), ref) <= 1e-5
+
+
+@pytest.mark.parametrize("n,kind", [(64, "fw"), (64, "avg"), (256, "fw")])
+def test_mg_truncation_error_stop_rule(lib, n, kind):
+    """alpha > 0 (the paper's rule, Eq. multigrid_threshold): the solve stops at the first
+    cycle c whose iterate has ||d|| < alpha ||tau|| by the oracle's FP64 definitions (a
+    one per cent margin for the FP32 iterate and the FP32 estimate on the GPU), and the
+    iterate after c - 1 cycles does not. n = 256 takes the fused norm pass."""
+    _say(f"mg truncation-error stop n={n} {kind}")
+    rho32 = _density(n)
+    a = 0.1
+    coef = 1.5 * a
+    h = 1.0 / n
+    f = opm.source(rho32.astype(np.float64), a)
+    alpha = 0.05
+    ctx = ctx_for(lib, n)
+
+    def crit(u):
+        d = np.linalg.norm(f - opm.laplacian7(u, h))
+        t = np.linalg.norm(omg.truncation_error(u, h, kind))
+        return d, t
+
+    phi = torch.zeros((n, n, n), device="cuda")
+    st = lib.pm_solve_mg(ctx, dev(rho32), coef, phi, alpha=alpha, tol=0.0, max_cycles=40,
+                         restrict_kind=kind)
+    c = st.cycles
+    assert st.status == lib.PM_OK and 1 <= c < 40, st.history()
+    d, t = crit(host(phi))
+    assert d < alpha * t * 1.01, (c, d, t)
+    if c > 1:
+        prev = torch.zeros((n, n, n), device="cuda")
+        lib.pm_solve_mg(ctx, dev(rho32), coef, prev, fixed_cycles=c - 1, restrict_kind=kind)
+        u_prev = host(prev)
+    else:
+        u_prev = -(h * h) * f / 6.0   # the Jacobi starting guess
+    d, t = crit(u_prev)
+    assert d >= alpha * t * 0.99, (c, d, t)
+    with pytest.raises(lib.PMError):
+        lib.pm_solve_mg(ctx, dev(rho32), coef, phi, alpha=-1.0)
 
 
 def test_mg_warnings_and_fixed_cycles(lib):

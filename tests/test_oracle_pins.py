@@ -181,6 +181,58 @@ def test_multigrid_restriction_is_scaled_prolongation_transpose():
     assert p.sum() == pytest.approx(8.0)
 
 
+@pytest.mark.parametrize("restriction", ["fw", "avg"])
+def test_truncation_error_single_mode_closed_form(restriction):
+    """tau = L_H(R u) - R(L_h u) for u = cos(k . x) sampled at cell centres: the
+    seven-point operator multiplies the mode by lambda_h = sum_d (2 cos(k_d h) - 2) / h^2
+    (lambda_H with H = 2h on the coarse grid), and the restriction by rho = prod_d of
+    (2 cos(3 k_d h / 2) + 6 cos(k_d h / 2)) / 8 (full weighting over the fine centres at
+    -3h/2 .. 3h/2 from the coarse centre) or cos(k_d h / 2) (mean of the two children),
+    so tau = (lambda_H - lambda_h) rho cos(k . X) on the coarse centres X."""
+    n = 32
+    h, H = 1.0 / n, 2.0 / n
+    for m in ([1, 0, 0], [2, 3, 1], [5, -4, 7]):
+        k = 2 * np.pi * np.array(m, dtype=np.float64)
+        x = (np.arange(n) + 0.5) * h
+        X = (np.arange(n // 2) + 0.5) * H
+        u = np.cos(k[0] * x[:, None, None] + k[1] * x[None, :, None] + k[2] * x[None, None, :])
+        lam_h = np.sum(2 * np.cos(k * h) - 2) / h ** 2
+        lam_H = np.sum(2 * np.cos(k * H) - 2) / H ** 2
+        if restriction == "fw":
+            rho = np.prod((2 * np.cos(1.5 * k * h) + 6 * np.cos(0.5 * k * h)) / 8)
+        else:
+            rho = np.prod(np.cos(0.5 * k * h))
+        expect = (lam_H - lam_h) * rho * np.cos(
+            k[0] * X[:, None, None] + k[1] * X[None, :, None] + k[2] * X[None, None, :])
+        got = mg.truncation_error(u, h, restriction)
+        np.testing.assert_allclose(got, expect, atol=1e-9 * abs(lam_h))
+
+
+def test_truncation_error_stop_rule():
+    """solve(alpha=...) stops at the first cycle whose residual norm is below alpha times
+    the norm of the truncation-error estimate of the same iterate."""
+    n, h = 32, 1.0 / 32
+    rng = RNG(23)
+    f = rng.standard_normal((n, n, n))
+    f = mg.prolong(mg.restrict(f))  # a smoother source, so that tau is well above the floor
+    f -= f.mean()
+    alpha = 0.5
+    u, hist = mg.solve(f, h, alpha=alpha, max_cycles=30)
+    c = len(hist) - 1
+    assert 1 <= c < 30
+
+    def check(cycles):
+        v = -(h * h) * f / 6.0
+        for _ in range(cycles):
+            mg.vcycle(v, f, h)
+        return np.linalg.norm(f - pm.laplacian7(v, h)), np.linalg.norm(mg.truncation_error(v, h))
+
+    d, t = check(c)
+    assert d < alpha * t
+    d, t = check(c - 1)
+    assert d >= alpha * t
+
+
 # ---------------------------------------------------------------- gradient
 
 def test_gradient_single_mode_multiplier_and_identities():
