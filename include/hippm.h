@@ -62,6 +62,10 @@ enum pm_mas { PM_CIC = 2, PM_TSC = 3 };                    /* p of the window W^
 enum pm_order { PM_DEPOSIT_ATOMIC = 0, PM_DEPOSIT_SORTED = 1 };
 enum pm_poskind { PM_POS_BOX = 0, PM_POS_CELLOFF = 1 };
 enum pm_restrict { PM_RESTRICT_FW = 0, PM_RESTRICT_AVG = 1 };
+/* Multigrid cycle shape (Sect. 3.7.1, App. C): the coarse error equation of every
+ * level is treated by one V cycle (V), by two W cycles in a row (W), or by an F
+ * cycle followed by a V cycle (F). */
+enum pm_cycle { PM_CYCLE_V = 0, PM_CYCLE_W = 1, PM_CYCLE_F = 2 };
 enum pm_solver { PM_SOLVER_MG = 0, PM_SOLVER_FFT = 1 };
 /* Starting guess of the multigrid solve (Sects. 3.7.1 and 3.9): the Jacobi step
  * -h^2 f / 6, the potential passed in phi, or (in pm_kdk) that potential scaled
@@ -99,6 +103,7 @@ typedef struct {
                          0.005); costs two extra grid passes and a host
                          synchronisation per test; needs n > 16; 0: the tol rule.
                          Ignored by the batched step (fixed cycles). */
+  int cycle;          /* pm_cycle (the batched step always runs V cycles) */
 } pm_mg_params;
 
 typedef struct {
@@ -124,7 +129,7 @@ typedef struct {
 } pm_step_stats;
 
 /* Default parameters: TSC, atomic deposit, multigrid 2/2 sweeps, omega 1,
- * tol 1e-6 (alpha 0), 50 cycles, full-weighting restriction, Jacobi guess,
+ * tol 1e-6 (alpha 0), 50 V cycles, full-weighting restriction, Jacobi guess,
  * Omega_m 1. */
 void pm_default_step_params(pm_step_params *p);
 

@@ -108,7 +108,12 @@ def coarse_solve(u, f, h, tol=1e-3, max_sweeps=500):
     return u
 
 
-def vcycle(u, f, h, pre=2, post=2, omega=1.0, restriction="fw", coarsest=16):
+def vcycle(u, f, h, pre=2, post=2, omega=1.0, restriction="fw", coarsest=16, cycle="V"):
+    """One multigrid cycle in place. The paper names V, F and W cycles (Sect. 3.7.1,
+    App. C) without spelling out F and W; they follow the usual definitions: the coarse
+    error equation is treated by one V cycle (V), by two W cycles in a row (W), or by
+    an F cycle followed by a V cycle (F), the second recursion continuing from the
+    first one's coarse iterate."""
     n = u.shape[0]
     if is_coarsest(n, coarsest):
         return coarse_solve(u, f, h)
@@ -118,7 +123,9 @@ def vcycle(u, f, h, pre=2, post=2, omega=1.0, restriction="fw", coarsest=16):
     dH = restrict(d, restriction)
     H = 2.0 * h
     vH = -(H * H) * dH / 6.0
-    vcycle(vH, dH, H, pre, post, omega, restriction, coarsest)
+    inner = {"V": ("V",), "W": ("W", "W"), "F": ("F", "V")}[cycle]
+    for kind in inner:
+        vcycle(vH, dH, H, pre, post, omega, restriction, coarsest, kind)
     u += prolong(vH)
     for _ in range(post):
         rbgs_sweep(u, f, h, omega, (1, 0))

@@ -59,6 +59,8 @@ int check_mg(pm_ctx *ctx, const pm_mg_params *p) {
   if (p->fixed_cycles == 0 && !(p->tol >= 0.0f)) return pm_fail(ctx, PM_ERR_ARG, "bad tol");
   if (!(p->alpha >= 0.0f) || !std::isfinite(p->alpha))
     return pm_fail(ctx, PM_ERR_ARG, "alpha must be finite and >= 0");
+  if (p->cycle != PM_CYCLE_V && p->cycle != PM_CYCLE_W && p->cycle != PM_CYCLE_F)
+    return pm_fail(ctx, PM_ERR_ARG, "bad cycle");
   if (p->restrict_kind != PM_RESTRICT_FW && p->restrict_kind != PM_RESTRICT_AVG)
     return pm_fail(ctx, PM_ERR_ARG, "bad restrict_kind");
   if (p->guess != PM_GUESS_JACOBI && p->guess != PM_GUESS_WARM &&
@@ -307,6 +309,7 @@ void pm_default_step_params(pm_step_params *p) {
   p->mg.guess = PM_GUESS_JACOBI;
   p->mg.fixed_cycles = 0;
   p->mg.alpha = 0.0f;
+  p->mg.cycle = PM_CYCLE_V;
   p->timing = 0;
 }
 

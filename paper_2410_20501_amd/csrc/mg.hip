@@ -543,17 +543,22 @@ struct Solver {
     return hipGetLastError();
   }
 
-  // V-cycle from level l; when pre_done, the pre-smoothing of level l has run.
-  hipError_t vcycle(int l, bool pre_done = false) {
+  // One cycle from level l (shape p->cycle unless given); when pre_done, the
+  // pre-smoothing of level l has run. The coarse error equation is treated by one V
+  // cycle (V), two W cycles in a row (W) or an F cycle and then a V cycle (F); the
+  // second recursion continues from the first one's coarse iterate.
+  hipError_t vcycle(int l, bool pre_done = false, int shape = -1) {
+    if (shape < 0) shape = p->cycle;
     if (l == ctx->nlevels - 1) return coarse(l);
     hipError_t e = pre_done ? hipSuccess : pre_smooth(l);
     if (e == hipSuccess) e = restrict_residual(l);
-    if (e == hipSuccess) e = vcycle(l + 1);
+    if (e == hipSuccess) e = vcycle(l + 1, false, shape == PM_CYCLE_V ? PM_CYCLE_V : shape);
+    if (e == hipSuccess && shape != PM_CYCLE_V)
+      e = vcycle(l + 1, false, shape == PM_CYCLE_W ? PM_CYCLE_W : PM_CYCLE_V);
     if (e == hipSuccess) e = correct_and_post_smooth(l);
     return e;
   }
 
-  // ||f - L u||^2 and ||f||^2 at level 0 into ctx->red_result[0..1] (plain kernel)
   // ||tau||_2 of the iterate scale * u on the level-0 grid, with level 1's arrays as
   // scratch (free between cycles); synchronises the stream
   hipError_t tau_norm(const float *u, float scale, double *out) {
@@ -576,6 +581,7 @@ struct Solver {
     return e;
   }
 
+  // ||f - L u||^2 and ||f||^2 at level 0 into ctx->red_result[0..1] (plain kernel)
   void norms() {
     const int n = ctx->lev[0].n;
     const int64_t count = (int64_t)n * n * n;

@@ -23,6 +23,7 @@ PM_CIC, PM_TSC = 2, 3
 PM_DEPOSIT_ATOMIC, PM_DEPOSIT_SORTED = 0, 1
 PM_POS_BOX, PM_POS_CELLOFF = 0, 1
 PM_RESTRICT_FW, PM_RESTRICT_AVG = 0, 1
+PM_CYCLE_V, PM_CYCLE_W, PM_CYCLE_F = 0, 1, 2
 PM_SOLVER_MG, PM_SOLVER_FFT = 0, 1
 PM_GUESS_JACOBI, PM_GUESS_WARM, PM_GUESS_WARM_RESCALED = 0, 1, 2
 PM_CHAIN_FIRST, PM_CHAIN_NEXT = 0, 1
@@ -46,7 +47,7 @@ class PMWarning(UserWarning):
 class MGParams(ctypes.Structure):
     _fields_ = [("pre", c_int), ("post", c_int), ("omega", c_float), ("tol", c_float),
                 ("max_cycles", c_int), ("restrict_kind", c_int), ("guess", c_int),
-                ("fixed_cycles", c_int), ("alpha", c_float)]
+                ("fixed_cycles", c_int), ("alpha", c_float), ("cycle", c_int)]
 
 
 class MGStats(ctypes.Structure):
@@ -139,6 +140,8 @@ def default_step_params(**kw) -> StepParams:
                  "warm_rescaled": PM_GUESS_WARM_RESCALED}.get(v, v)
         elif k == "restrict_kind":
             v = {"fw": PM_RESTRICT_FW, "avg": PM_RESTRICT_AVG}.get(v, v)
+        elif k == "cycle":
+            v = {"V": PM_CYCLE_V, "W": PM_CYCLE_W, "F": PM_CYCLE_F}.get(v, v)
         if hasattr(p.mg, k) and k not in ("mas",):
             setattr(p.mg, k, v)
         else:

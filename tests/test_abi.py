@@ -50,12 +50,13 @@ def test_create_rejects_negative_particle_count():
 
 def test_struct_layouts_match_header():
     import paper_2410_20501_amd as pm
-    assert ctypes.sizeof(pm.MGParams) == 36
+    assert ctypes.sizeof(pm.MGParams) == 40
     assert pm.MGParams.alpha.offset == 32
+    assert pm.MGParams.cycle.offset == 36
     assert ctypes.sizeof(pm.MGStats) == 8 + 64 * 8
     assert pm.StepParams.mg.offset == 24
-    assert pm.StepParams.timing.offset == 60
-    assert ctypes.sizeof(pm.StepParams) == 64
+    assert pm.StepParams.timing.offset == 64
+    assert ctypes.sizeof(pm.StepParams) == 72
     p = pm.default_step_params()
     assert (p.mas, p.mg.pre, p.mg.post, p.mg.omega, p.mg.max_cycles) == (3, 2, 2, 1.0, 50)
-    assert p.mg.alpha == 0.0
+    assert p.mg.alpha == 0.0 and p.mg.cycle == pm.PM_CYCLE_V

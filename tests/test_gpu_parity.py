@@ -366,6 +366,30 @@ def test_mg_single_mode_closed_form(lib):
     assert rel_l2(host(phi), ref) <= 1e-5
 
 
+@pytest.mark.parametrize("n", [64, 256])
+@pytest.mark.parametrize("cycle", ["W", "F"])
+def test_mg_w_and_f_cycles(lib, n, cycle):
+    """W and F cycles (two W, or an F and a V, on every coarse level) converge to the
+    seven-point solution within the potential tolerance, with a smaller residual than
+    V cycles after two cycles; n = 256 runs the streaming kernels on its two finest
+    levels."""
+    _say(f"mg {cycle} cycles n={n}")
+    rho32 = _density(n)
+    a = 0.1
+    coef = 1.5 * a
+    ctx = ctx_for(lib, n)
+    phi = torch.zeros((n, n, n), device="cuda")
+    st = lib.pm_solve_mg(ctx, dev(rho32), coef, phi, tol=1e-6, max_cycles=40, cycle=cycle)
+    ref = opm.solve_exact7(opm.source(rho32.astype(np.float64), a), 1.0 / n)
+    assert rel_l2(host(phi), ref) <= 1e-5, st.history()
+    phiv = torch.zeros((n, n, n), device="cuda")
+    sv = lib.pm_solve_mg(ctx, dev(rho32), coef, phiv, tol=1e-6, max_cycles=40)
+    hc, hv = st.history(), sv.history()
+    assert hc[2] < hv[2], (hc, hv)
+    with pytest.raises(lib.PMError):
+        lib.pm_solve_mg(ctx, dev(rho32), coef, phi, cycle=7)
+
+
 @pytest.mark.parametrize("n,kind", [(64, "fw"), (64, "avg"), (256, "fw")])
 def test_mg_truncation_error_stop_rule(lib, n, kind):
     """alpha > 0 (the paper's rule, Eq. multigrid_threshold): the solve stops at the first

@@ -165,6 +165,50 @@ def test_multigrid_converges_to_exact7_and_rate():
     assert all(4.0 < r < 60.0 for r in rates), rates
 
 
+@pytest.mark.parametrize("cycle", ["V", "W", "F"])
+def test_multigrid_cycle_shapes_and_convergence(cycle, monkeypatch):
+    """Cycle shapes by their textbook definitions, counted on a 64 -> 32 -> 16 hierarchy:
+    one cycle visits level l (0 the finest) once (V), 2^l times (W) or l + 1 times (F);
+    every shape converges to the exact seven-point solution, W and F at least as fast
+    per cycle as V (on three levels the coarse problem is already well solved by one V
+    cycle, so the gain is small)."""
+    n, h = 64, 1.0 / 64
+    f = RNG(29).standard_normal((n, n, n))
+    f -= f.mean()
+    visits = {}
+    real_coarse = mg.coarse_solve
+    real_sweep = mg.rbgs_sweep
+
+    def sweep(u, *a, **k):
+        key = ("sweep", u.shape[0])
+        visits[key] = visits.get(key, 0) + 1
+        return real_sweep(u, *a, **k)
+
+    def coarse(u, *a, **k):
+        visits[("coarse", u.shape[0])] = visits.get(("coarse", u.shape[0]), 0) + 1
+        monkeypatch.setattr(mg, "rbgs_sweep", real_sweep)   # its own sweeps are not visits
+        try:
+            return real_coarse(u, *a, **k)
+        finally:
+            monkeypatch.setattr(mg, "rbgs_sweep", sweep)
+
+    monkeypatch.setattr(mg, "rbgs_sweep", sweep)
+    monkeypatch.setattr(mg, "coarse_solve", coarse)
+    mg.vcycle(-(h * h) * f / 6.0, f, h, pre=2, post=2, cycle=cycle)
+    expect = {"V": (1, 1, 1), "W": (1, 2, 4), "F": (1, 2, 3)}[cycle]
+    assert visits[("sweep", 64)] == 4 * expect[0]      # pre + post sweeps per visit
+    assert visits[("sweep", 32)] == 4 * expect[1]
+    assert visits[("coarse", 16)] == expect[2]
+    monkeypatch.undo()
+    u, hist = mg.solve(f, h, tol=1e-11, max_cycles=40, cycle=cycle)
+    ref = pm.solve_exact7(f, h)
+    assert np.linalg.norm(u - ref) / np.linalg.norm(ref) < 1e-9
+    _, hv = mg.solve(f, h, tol=0.0, max_cycles=3, cycle="V")
+    _, hc = mg.solve(f, h, tol=0.0, max_cycles=3, cycle=cycle)
+    if cycle != "V":
+        assert hc[3] < hv[3], (hc, hv)
+
+
 def test_multigrid_restriction_is_scaled_prolongation_transpose():
     rng = RNG(19)
     r = rng.standard_normal((8, 8, 8))
