@@ -28,15 +28,6 @@ namespace {
 #endif
 constexpr int SJ = PM_SMOOTH_SJ, SK = 64;  // interior tile of the smoother (SJ, SK even)
 constexpr int ST = PM_SMOOTH_THREADS;      // threads per smoother block
-#ifndef PM_SMOOTH_STAGE_FENCE
-#define PM_SMOOTH_STAGE_FENCE 0
-#endif
-#ifndef PM_SMOOTH_JFAST
-#define PM_SMOOTH_JFAST 0
-#endif
-#ifndef PM_SMOOTH_NT
-#define PM_SMOOTH_NT 0
-#endif
 #ifndef PM_SMOOTH_BLOCKS
 #define PM_SMOOTH_BLOCKS 2048
 #endif
@@ -286,7 +277,6 @@ template <int R, int S, int H, bool NORM, bool OMEGA1, bool PRO>
 __device__ __forceinline__ void smooth_halves(SmoothState<H, NORM, OMEGA1, PRO> &c, int q) {
   if constexpr (S <= H) {
     smooth_half<R, S, H, NORM, OMEGA1, PRO>(c, q);
-    if constexpr (PM_SMOOTH_STAGE_FENCE) __builtin_amdgcn_sched_barrier(0);
     smooth_halves<R, S + 1, H, NORM, OMEGA1, PRO>(c, q);
   }
 }
@@ -377,16 +367,8 @@ __device__ __forceinline__ void smooth_step(SmoothState<H, NORM, OMEGA1, PRO> &c
     for (int t = 0; t < PP; ++t)
       if (c.inside[t]) {
         const float a = c.uE[cH][t], b = c.uO[cH][t];
-#if PM_SMOOTH_NT
-        typedef float nt2 __attribute__((ext_vector_type(2)));
-        nt2 v;
-        v.x = c.swp[t] ? b : a;
-        v.y = c.swp[t] ? a : b;
-        __builtin_nontemporal_store(v, reinterpret_cast<nt2 *>(c.uout + op + c.col[t]));
-#else
         *reinterpret_cast<float2 *>(c.uout + op + c.col[t]) =
             c.swp[t] ? make_float2(b, a) : make_float2(a, b);
-#endif
       }
   }
   // the LDS slots are rewritten by the next plane
@@ -419,11 +401,7 @@ __global__ __launch_bounds__(NORM ? 2 * ST : ST) __attribute__((amdgpu_waves_per
   // XCD-aware order: consecutive logical blocks are k-, then j-neighbours
   const unsigned lin = xcd_block(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
                                  gridDim.x * gridDim.y * gridDim.z);
-#if PM_SMOOTH_JFAST
-  const int by = lin % gridDim.y, bx = (lin / gridDim.y) % gridDim.x, bz = lin / (gridDim.x * gridDim.y);
-#else
   const int bx = lin % gridDim.x, by = (lin / gridDim.x) % gridDim.y, bz = lin / (gridDim.x * gridDim.y);
-#endif
   const int k0 = bx * SK, j0 = by * SJ;
 
   SmoothState<H, NORM, OMEGA1, PRO> c;

@@ -550,9 +550,6 @@ constexpr int kOThreads = 256;
 #ifndef PM_DEPOSIT_THREADS
 #define PM_DEPOSIT_THREADS 256
 #endif
-#ifndef PM_DEPOSIT_NOGUARD
-#define PM_DEPOSIT_NOGUARD 0
-#endif
 #ifndef PM_INTERP_THREADS
 #define PM_INTERP_THREADS 256
 #endif
@@ -703,11 +700,7 @@ __global__ __launch_bounds__(kDThreads) void k_deposit_own(const float *__restri
 #pragma unroll
           for (int cc = 0; cc < MAS; ++cc) {
             const unsigned long long v = fix30(wab * wz[cc]);
-#if PM_DEPOSIT_NOGUARD
-            atomicAdd(&box[row + cc], v);
-#else
             if (v) atomicAdd(&box[row + cc], v);
-#endif
           }
         }
     } else if (act) {
@@ -743,11 +736,7 @@ __global__ __launch_bounds__(kDThreads) void k_deposit_own(const float *__restri
 #pragma unroll
           for (int cc = 0; cc < MAS; ++cc) {
             const unsigned long long v = fix30(wab * pz[cc]);
-#if PM_DEPOSIT_NOGUARD
-            atomicAdd(&box[row + oz[cc]], v);
-#else
             if (v) atomicAdd(&box[row + oz[cc]], v);
-#endif
           }
         }
     }
