@@ -40,15 +40,15 @@ MEASURED_TRAFFIC = {
     # and the post-smoothing pass (with the prolongation) weighted by their counts (45
     # and 39 dispatches)
     "smooth": ("paper_2410_20501_amd/csrc/mg_stream.hip",
-               "2b87898978e98b927bae449e8df805f9f8512d9a2842e8dbbaed256f841e8de7",
+               "05d60bb6a194e21ebd3b57963895793c2f1650bdd920de3d26fb92930595c244",
                743905.0, 539558.0, 2.0, 1.0),
     # deposit: the particle-owned tile kernel plus the gather pass over the tile boxes
     "deposit": ("paper_2410_20501_amd/csrc/particles.hip",
-                "cca1acecb69ab7c83c71bd0343e048f76941900cbfe9bc91eadb7df0e6270e62",
+                "f57991d28eb5cd43cc0ee842cc95c3685c4323f22df9d44156ea54b6e5331550",
                 2493321.0, 2573651.0, 2.0, 1.0),
     # interpolation with the fused gradient, kicks and drift of a chained step
     "interp": ("paper_2410_20501_amd/csrc/particles.hip",
-               "cca1acecb69ab7c83c71bd0343e048f76941900cbfe9bc91eadb7df0e6270e62",
+               "f57991d28eb5cd43cc0ee842cc95c3685c4323f22df9d44156ea54b6e5331550",
                2750314.0, 5295974.0, 2.0, 1.0),
 }
 
