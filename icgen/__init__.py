@@ -38,6 +38,7 @@ __all__ = [
     "zeldovich_particles",
     "to_cell_offset",
     "ensemble_draw",
+    "unit_directions",
     "ParticleSet",
 ]
 
@@ -182,4 +183,15 @@ def direction_fields(n: int, count: int, seed: int, smooth_index: float = -1.5) 
             d = rng.standard_normal((n ** 3, 3))
         d = d / np.sqrt(np.mean(d * d))
         out.append(d.astype(np.float32))
+    return out
+
+
+def unit_directions(npart: int, count: int, seed: int) -> list:
+    """Seeded Gaussian white-noise directions of a displacement field, FP64 [npart, 3] each,
+    normalised to unit L2 norm over all particles and components."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(count):
+        d = rng.standard_normal((npart, 3))
+        out.append(d / np.linalg.norm(d))
     return out

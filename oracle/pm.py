@@ -18,7 +18,15 @@ import scipy.fft as sfft
 # mass-assignment weights (paper Sect. 3.5, the NGP/CIC/TSC window functions)
 # --------------------------------------------------------------------------
 
-MAS_ORDER = {"cic": 2, "tsc": 3}
+MAS_ORDER = {"ngp": 1, "cic": 2, "tsc": 3}
+
+
+def w_ngp(s):
+    """NGP window of the normalised separation s (paper Sect. 3.5): 1 inside the cell.
+    The boundary |s| = 1/2 belongs to the cell whose lower face it is (the particle's
+    cell is floor(u)), i.e. s in [-1/2, 1/2)."""
+    s = np.asarray(s, dtype=np.float64)
+    return np.where((s >= -0.5) & (s < 0.5), 1.0, 0.0)
 
 
 def w_tsc(s):
@@ -40,9 +48,13 @@ def axis_support(u, mas):
     where weights has shape [support, ...]. The support is the set of cells
     whose window value can be non-zero; the weights are the window evaluated
     at the separation between u and each cell centre (c + 1/2).
-    TSC: 3 cells starting at floor(u) - 1; CIC: 2 cells starting at floor(u - 1/2).
+    TSC: 3 cells starting at floor(u) - 1; CIC: 2 cells starting at floor(u - 1/2);
+    NGP: the cell floor(u).
     """
     u = np.asarray(u, dtype=np.float64)
+    if mas == "ngp":
+        first = np.floor(u)
+        return first.astype(np.int64), w_ngp(u[None] - (first[None] + 0.5))
     if mas == "tsc":
         first = np.floor(u) - 1.0
         cells = first[None] + np.arange(3.0).reshape((3,) + (1,) * u.ndim)
@@ -192,6 +204,54 @@ def solve_fft(f, h, p=3):
     return sfft.irfftn(sfft.rfftn(f) * green, s=f.shape)
 
 
+def solve_fft_7pt(f, h):
+    """FFT_7pt solver (paper Sect. 3.8): the Fourier-space form of the seven-point
+    Laplacian, phi(k) = -f(k) / sum_d (omega_d/h sinc(omega_d/2))^2 with omega_d = k_d h,
+    no mass-assignment compensation; phi(0) = 0. (The paper prints the factor as
+    h omega_d; the stencil it names has eigenvalue (omega_d / h)^2 sinc^2(omega_d/2)
+    = (4/h^2) sin^2(omega_d/2) per axis, which is what is used.)"""
+    f = np.asarray(f, dtype=np.float64)
+    n = f.shape[0]
+    mx, my, mz = _mode_numbers(n)
+    lam = np.zeros((n, n, n // 2 + 1))
+    for m in (mx, my, mz):
+        om = 2 * np.pi * m * h                                     # omega = k h
+        sinc = np.where(om == 0.0, 1.0, np.sin(om / 2) / np.where(om == 0.0, 1.0, om / 2))
+        lam = lam + (om / h * sinc) ** 2
+    lam[0, 0, 0] = 1.0
+    phik = -sfft.rfftn(f) / lam
+    phik[0, 0, 0] = 0.0
+    return sfft.irfftn(phik, s=f.shape)
+
+
+def force_full_fft(f, h, p=3):
+    """FULL_FFT (paper Sect. 3.8, Eq. exact_fullfft_kernel): the force g = -grad phi
+    taken directly in Fourier space, g_d(k) = i k_d f(k) / (k^2 W(k)^2) (the derivative
+    of phi(k) = -f(k) / (k^2 W^2) is i k_d phi(k), numpy's transform convention), with
+    W the deconvolution window of solve_fft. On the Nyquist plane of axis d
+    (m_d = -n/2) the derivative multiplier k_d is taken as 0: the mode is its own
+    conjugate, so an odd multiplier has no real-valued image there. Returns [n,n,n,3]."""
+    f = np.asarray(f, dtype=np.float64)
+    n = f.shape[0]
+    mx, my, mz = _mode_numbers(n)
+    kx, ky, kz = 2 * np.pi * mx, 2 * np.pi * my, 2 * np.pi * mz
+    k2 = kx * kx + ky * ky + kz * kz
+
+    def sinc_half(k):
+        w = 0.5 * k * h
+        return np.where(w == 0.0, 1.0, np.sin(w) / np.where(w == 0.0, 1.0, w))
+
+    wmas = (sinc_half(kx) * sinc_half(ky) * sinc_half(kz)) ** p
+    k2[0, 0, 0] = 1.0
+    base = sfft.rfftn(f) / (k2 * wmas * wmas)
+    base[0, 0, 0] = 0.0
+    out = np.empty(f.shape + (3,))
+    for d, (kd, md) in enumerate(((kx, mx), (ky, my), (kz, mz))):
+        mult = np.where(md == -n // 2, 0.0, kd) if d < 2 else np.where(md == n // 2, 0.0, kd)
+        out[..., d] = sfft.irfftn(1j * mult * base, s=f.shape)
+    return out
+
+
 GRAD_COEFFS = {
     # central-derivative stencils of the paper's gradient table: offsets 1, 2, 3
     3: (0.5, 0.0, 0.0),
@@ -224,19 +284,27 @@ def accel(u, n, a, solver="exact7", mas="tsc", omega_m=1.0, mass=None, points=5,
           return_fields=False):
     """Particle accelerations at scale factor a: deposit -> source -> solve -> gradient -> interp.
 
-    solver: "exact7" (the seven-point system, which multigrid solves) or
-            "fft" (mass-assignment-deconvolved FFT kernel).
+    solver: "exact7" (the seven-point system, which multigrid solves),
+            "fft" (mass-assignment-deconvolved FFT kernel), "fft_7pt" (the seven-point
+            Laplacian in Fourier space) or "full_fft" (the force in Fourier space, no
+            finite-difference gradient; the returned potential is then None).
     """
     h = 1.0 / n
     rho = deposit(u, n, mas, mass)
     f = source(rho, a, omega_m)
-    if solver == "exact7":
-        phi = solve_exact7(f, h)
-    elif solver == "fft":
-        phi = solve_fft(f, h, MAS_ORDER[mas])
+    if solver == "full_fft":
+        phi = None
+        g = force_full_fft(f, h, MAS_ORDER[mas])
     else:
-        raise ValueError(solver)
-    g = gradient(phi, h, points)
+        if solver == "exact7":
+            phi = solve_exact7(f, h)
+        elif solver == "fft":
+            phi = solve_fft(f, h, MAS_ORDER[mas])
+        elif solver == "fft_7pt":
+            phi = solve_fft_7pt(f, h)
+        else:
+            raise ValueError(solver)
+        g = gradient(phi, h, points)
     acc = interp(u, g, mas)
     if return_fields:
         return acc, dict(rho=rho, f=f, phi=phi, g=g)

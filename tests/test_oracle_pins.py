@@ -37,7 +37,7 @@ def test_point_mass_worked_example():
         assert rho.sum() == pytest.approx(1.0, abs=1e-15)
 
 
-@pytest.mark.parametrize("mas", ["tsc", "cic"])
+@pytest.mark.parametrize("mas", ["tsc", "cic", "ngp"])
 def test_deposit_brute_force_definition(mas):
     """Every (particle, cell) pair evaluated with the paper's piecewise window."""
     n = 6
@@ -45,7 +45,7 @@ def test_deposit_brute_force_definition(mas):
     u = rng.uniform(0, n, size=(17, 3))
     u[0] = [0.0, 5.999999, 3.0]          # on faces / near the wrap
     u[1] = [2.5, 2.5, 2.5]               # cell centre
-    win = pm.w_tsc if mas == "tsc" else pm.w_cic
+    win = {"tsc": pm.w_tsc, "cic": pm.w_cic, "ngp": pm.w_ngp}[mas]
     ref = np.zeros((n, n, n))
     c = np.arange(n) + 0.5
     for p in range(u.shape[0]):
@@ -57,7 +57,7 @@ def test_deposit_brute_force_definition(mas):
     np.testing.assert_allclose(got, ref, rtol=0, atol=1e-14)
 
 
-@pytest.mark.parametrize("mas", ["tsc", "cic"])
+@pytest.mark.parametrize("mas", ["tsc", "cic", "ngp"])
 def test_deposit_mass_conservation_and_lattice(mas):
     n = 16
     rng = RNG(3)
@@ -83,7 +83,7 @@ def test_interp_partition_of_unity_and_linear_exactness(mas):
     np.testing.assert_allclose(pm.interp(u, lin, mas), u, atol=1e-12)
 
 
-@pytest.mark.parametrize("mas", ["tsc", "cic"])
+@pytest.mark.parametrize("mas", ["tsc", "cic", "ngp"])
 def test_interp_is_transpose_of_deposit(mas):
     n = 10
     rng = RNG(7)
@@ -151,6 +151,72 @@ def test_fft_solver_single_mode_closed_form():
     f = np.cos(np.pi * i)[:, None, None] * np.ones((n, n, n))
     expect = -f / ((np.pi * n) ** 2 * (2 / np.pi) ** 6)
     np.testing.assert_allclose(pm.solve_fft(f, h, 3), expect, atol=1e-15)
+
+
+def test_ngp_window_cells():
+    """NGP (paper Sect. 3.5): every particle lands whole in the cell that contains it,
+    floor(u) per axis, including a particle on a cell face and one at the periodic seam."""
+    n = 5
+    u = np.array([[0.2, 3.99, 4.5], [2.0, 0.0, 1.0], [4.999999, 2.5, 0.5]])
+    rho = pm.deposit(u, n, "ngp", mass=1.0)
+    assert np.count_nonzero(rho) == 3 and rho.sum() == 3.0
+    for p in u.astype(int):
+        assert rho[p[0], p[1], p[2]] == 1.0
+    g = RNG(3).standard_normal((n, n, n))
+    np.testing.assert_array_equal(pm.interp(u, g, "ngp"), g[tuple(u.astype(int).T)])
+
+
+def _mode(n, m, fn=np.cos):
+    i = np.arange(n)
+    theta = 2 * np.pi * (m[0] * i[:, None, None] + m[1] * i[None, :, None] + m[2] * i[None, None, :]) / n
+    return fn(theta)
+
+
+def test_fft_7pt_single_mode_and_seven_point_system():
+    """FFT_7pt (paper Sect. 3.8): on a single mode, phi = f / lambda(m) with the
+    seven-point eigenvalue lambda = sum_d 2 (cos(2 pi m_d / n) - 1) / h^2 (the closed
+    form written independently of the sinc form the solver uses), and on any field the
+    result solves the seven-point system, i.e. equals the exact seven-point solve (the
+    equivalence of multigrid and FFT_7pt the paper reports)."""
+    n, h = 32, 1.0 / 32
+    m = (3, -5, 7)
+    f = _mode(n, m)
+    lam = sum(2.0 * (np.cos(2 * np.pi * md / n) - 1.0) for md in m) / h ** 2
+    np.testing.assert_allclose(pm.solve_fft_7pt(f, h), f / lam, atol=1e-14)
+    r = RNG(19).standard_normal((n, n, n))
+    r -= r.mean()
+    phi = pm.solve_fft_7pt(r, h)
+    np.testing.assert_allclose(pm.laplacian7(phi, h), r, atol=1e-10 * np.abs(r).max())
+    np.testing.assert_allclose(phi, pm.solve_exact7(r, h), atol=1e-13 * np.abs(phi).max())
+
+
+@pytest.mark.parametrize("p", [3, 2])
+def test_full_fft_force_single_mode_closed_form(p):
+    """FULL_FFT (paper Sect. 3.8, Eq. exact_fullfft_kernel): for f = cos(k . x) the
+    potential is -f / (k^2 W^2) and the force -grad phi = -k sin(k . x) / (k^2 W^2),
+    W = prod_d sinc(k_d h / 2)^p. On the Nyquist plane of an axis the derivative along
+    that axis is 0 (the self-conjugate mode has no real odd image)."""
+    n, h = 16, 1.0 / 16
+    m = (2, -3, 5)
+    f = _mode(n, m)
+    k = [2 * np.pi * md for md in m]
+    k2 = sum(kd * kd for kd in k)
+    w = 1.0
+    for kd in k:
+        w *= (np.sin(kd * h / 2) / (kd * h / 2)) ** p
+    g = pm.force_full_fft(f, h, p)
+    s = _mode(n, m, np.sin)
+    for d in range(3):
+        np.testing.assert_allclose(g[..., d], -k[d] * s / (k2 * w * w), atol=1e-15)
+    # a mode on the Nyquist plane of axis 0: no force along axis 0, the others as above
+    m = (-8, 1, 2)
+    f = _mode(n, m)
+    g = pm.force_full_fft(f, h, 0)
+    k = [2 * np.pi * md for md in m]
+    assert np.abs(g[..., 0]).max() < 1e-15
+    s = _mode(n, m, np.sin)
+    for d in (1, 2):
+        np.testing.assert_allclose(g[..., d], -k[d] * s / sum(kd * kd for kd in k), atol=1e-15)
 
 
 def test_multigrid_converges_to_exact7_and_rate():
@@ -309,7 +375,7 @@ def test_gradient_fourth_order_convergence():
 
 # ---------------------------------------------------------------- force chain
 
-@pytest.mark.parametrize("solver", ["exact7", "fft"])
+@pytest.mark.parametrize("solver", ["exact7", "fft", "fft_7pt", "full_fft"])
 @pytest.mark.parametrize("mas", ["tsc", "cic"])
 def test_self_force_zero_and_pair_antisymmetry(solver, mas):
     n = 16
@@ -386,3 +452,53 @@ def test_zeldovich_plane_wave_before_shell_crossing():
     assert t16 < 1e-12 and t32 < 1e-12          # transverse motion is exactly zero
     assert e32 < 1e-2                            # relative to the displacement amplitude
     assert 2.5 < e16 / e32 < 6.0, (e16, e32)     # second order in h
+
+
+# ---------------------------------------------------------------- position forms
+
+def test_cell_units_decodes_cell_offset_form():
+    """The cell-offset form (Sect. 3.2 layout, row-major with k fastest): the linear
+    index (i n + j) n + k built by hand from explicit, distinct (i, j, k) decodes to
+    cell units (i, j, k) + offset, axis by axis (a swapped axis or a wrong stride fails)."""
+    n = 7                                       # odd, so no axis mapping is symmetric
+    ijk = np.array([[1, 4, 2], [6, 0, 3], [0, 0, 6], [5, 6, 0], [3, 2, 1]])
+    off = np.array([[0.25, 0.5, 0.75], [0.0, 0.999, 0.125], [0.5, 0.5, 0.5],
+                    [0.875, 0.0, 0.0625], [0.3, 0.6, 0.9]])
+    lin = ijk[:, 0] * n * n + ijk[:, 1] * n + ijk[:, 2]
+    np.testing.assert_array_equal(lin, [79, 297, 6, 287, 162])   # by hand
+    got = pm.cell_units(n, cell=lin.astype(np.int32), off=off)
+    np.testing.assert_array_equal(got, ijk + off)
+    # box-unit branch: u = x n
+    np.testing.assert_array_equal(pm.cell_units(n, pos=(ijk + off) / n), (ijk + off) / n * n)
+
+
+@pytest.mark.parametrize("mas", ["tsc", "cic"])
+def test_cell_offset_deposit_equals_brute_force(mas):
+    """A deposit through the cell-offset decode equals the brute-force window sum over
+    every (particle, cell) pair of the same points given in box units."""
+    n = 6
+    rng = RNG(23)
+    ijk = rng.integers(0, n, size=(40, 3))
+    off = rng.uniform(0, 1, size=(40, 3))
+    ijk[0], off[0] = [5, 0, 2], [0.999, 0.0, 0.5]         # near the seam, on a face
+    lin = (ijk[:, 0] * n + ijk[:, 1]) * n + ijk[:, 2]
+    got = pm.deposit(pm.cell_units(n, cell=lin, off=off), n, mas, mass=1.0)
+    x = (ijk + off) / n                                     # box units
+    win = pm.w_tsc if mas == "tsc" else pm.w_cic
+    c = np.arange(n) + 0.5
+    ref = np.zeros((n, n, n))
+    for p in range(x.shape[0]):
+        s = [(x[p, d] * n - c + n / 2) % n - n / 2 for d in range(3)]
+        ref += np.einsum("i,j,k->ijk", *[win(v) for v in s])
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-14)
+
+
+def test_wrap01_edges():
+    """Periodic wrap into [0, 1): values that reduce to exactly 1.0 map to 0 (a position
+    of 1.0 is the same point as 0.0), negatives wrap from the top, and interior values
+    are unchanged."""
+    x = np.array([1.0, 0.0, -0.0, -1e-17, -0.25, 1.5, 2.0, 0.999999, -1.0, 3.25])
+    got = pm.wrap01(x)
+    expect = np.array([0.0, 0.0, 0.0, 0.0, 0.75, 0.5, 0.0, 0.999999, 0.0, 0.25])
+    np.testing.assert_array_equal(got, expect)
+    assert np.all((got >= 0.0) & (got < 1.0))
