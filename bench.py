@@ -249,6 +249,43 @@ def bench_batched(nboxes=96, steps=20, master_seed=2024):
     }
 
 
+def bench_fft(n=256, reps=20):
+    """FFT Poisson solve (Green's function with TSC deconvolution) and FFT_7pt on an n^3
+    grid (the 256^3 ten-step workload's solver), timed with HIP events on the current
+    stream. Algorithmic bytes: the five LDS-staged passes each read and write the half
+    spectrum (n^2 (n/2+1) complex, about 4 B per cell each way), the first pass reads
+    the real density (4 B/cell) instead and the last writes the real potential: about
+    8 B per cell per pass, 40 B per cell per solve."""
+    import numpy as np
+    import torch
+
+    import paper_2410_20501_amd as pm
+    rng = np.random.Generator(np.random.PCG64(8))
+    rho = torch.from_numpy((1.0 + 0.3 * rng.standard_normal((n, n, n))).astype(np.float32)).cuda()
+    phi = torch.empty_like(rho)
+    g = torch.empty((n, n, n, 3), device="cuda")
+    ctx = pm.Context(n)
+    out = {"workload": f"{n}^3 grid, FFT solve with TSC deconvolution (five passes), FFT_7pt, "
+                       f"and FULL_FFT (force grid, twelve passes)"}
+    for name, kern, dst, passes in (("fft", "green", phi, 5), ("fft_7pt", "7pt", phi, 5),
+                                    ("full_fft", "full", g, 12)):
+        for _ in range(2):
+            pm.pm_solve_fft_kernel(ctx, rho, 0.3, dst, kernel=kern, deconv=3)
+        torch.cuda.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(reps):
+            pm.pm_solve_fft_kernel(ctx, rho, 0.3, dst, kernel=kern, deconv=3)
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / reps
+        alg = 8.0 * passes * n ** 3 + (8.0 * n ** 3 if name == "full_fft" else 0.0)
+        out[name] = {"ms": ms, "algorithmic_bytes": alg, "gbs": alg / (ms * 1e-3) / 1e9,
+                     "frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    ctx.close()
+    return out
+
+
 def stage_bytes(npart, ncell, cycles, chained=False):
     """Algorithmic HBM bytes of each stage of one step at cell-offset positions (the
     minimum each stage's kernels must move; multigrid: the level-0 passes of the fused
@@ -291,7 +328,7 @@ def main():
                     help="only run a 512 MiB device copy (HBM counter calibration)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the adjoint and batched-ensemble measurements")
-    ap.add_argument("--only", choices=["adjoint", "batched"], default=None,
+    ap.add_argument("--only", choices=["adjoint", "batched", "fft"], default=None,
                     help="run only one of the extra measurements and print its JSON object")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -305,7 +342,7 @@ def main():
     import paper_2410_20501_amd as pm
 
     if args.only:
-        res = bench_adjoint() if args.only == "adjoint" else bench_batched()
+        res = {"adjoint": bench_adjoint, "batched": bench_batched, "fft": bench_fft}[args.only]()
         print(json.dumps({args.only: res}), flush=True)
         return
 

@@ -50,7 +50,8 @@ typedef void *pm_stream; /* hipStream_t */
 enum pm_status {
   PM_OK = 0,
   PM_WARN_NOT_CONVERGED = 1, /* multigrid stopped at max_cycles above tol */
-  PM_WARN_FLOOR = 2,         /* multigrid stagnated at the FP32 rounding floor */
+  PM_WARN_FLOOR = 2,         /* multigrid reached the FP32 rounding floor above tol: below
+                                a relative residual of 1e-4 a V-cycle gained less than 4x */
   PM_ERR_ARG = -1,           /* null pointer, bad enum, negative count */
   PM_ERR_SHAPE = -2,         /* grid size or particle count not supported */
   PM_ERR_NOMEM = -3,         /* device allocation failed */
@@ -58,7 +59,11 @@ enum pm_status {
   PM_ERR_NONFINITE = -5      /* a non-finite value was found where checked */
 };
 
-enum pm_mas { PM_CIC = 2, PM_TSC = 3 };                    /* p of the window W^p */
+/* Mass-assignment window (Sect. 3.5): p of the window W^p, the number of cells it
+ * covers per axis. NGP serves deposit, interpolation and the forward steps; the
+ * reverse-mode and batched entry points take CIC or TSC (NGP has no position
+ * derivative). */
+enum pm_mas { PM_NGP = 1, PM_CIC = 2, PM_TSC = 3 };
 enum pm_order { PM_DEPOSIT_ATOMIC = 0, PM_DEPOSIT_SORTED = 1 };
 enum pm_poskind { PM_POS_BOX = 0, PM_POS_CELLOFF = 1 };
 enum pm_restrict { PM_RESTRICT_FW = 0, PM_RESTRICT_AVG = 1 };
@@ -66,7 +71,15 @@ enum pm_restrict { PM_RESTRICT_FW = 0, PM_RESTRICT_AVG = 1 };
  * level is treated by one V cycle (V), by two W cycles in a row (W), or by an F
  * cycle followed by a V cycle (F). */
 enum pm_cycle { PM_CYCLE_V = 0, PM_CYCLE_W = 1, PM_CYCLE_F = 2 };
-enum pm_solver { PM_SOLVER_MG = 0, PM_SOLVER_FFT = 1 };
+/* Poisson solver of a force evaluation (Sects. 3.7, 3.8): multigrid; FFT with the
+ * Green's function -1/k^2 and window deconvolution (fft_deconv); FFT_7pt, the
+ * seven-point Laplacian's eigenvalue in Fourier space (the system multigrid
+ * solves, no deconvolution); FULL_FFT, the force itself taken in Fourier space
+ * (no finite-difference gradient; the potential is then not written). */
+enum pm_solver { PM_SOLVER_MG = 0, PM_SOLVER_FFT = 1, PM_SOLVER_FFT_7PT = 2,
+                 PM_SOLVER_FULL_FFT = 3 };
+/* Fourier-space kernels of pm_solve_fft_kernel (Sect. 3.8). */
+enum pm_fft_kernel { PM_FFT_GREEN = 0, PM_FFT_7PT = 1, PM_FFT_FULL = 2 };
 /* Starting guess of the multigrid solve (Sects. 3.7.1 and 3.9): the Jacobi step
  * -h^2 f / 6, the potential passed in phi, or (in pm_kdk) that potential scaled
  * by the linear growth of the supercomoving potential between the two scale
@@ -117,7 +130,8 @@ typedef struct {
   int mas;            /* pm_mas for deposit and interpolation */
   int order;          /* pm_order of the deposit */
   int solver;         /* pm_solver */
-  int fft_deconv;     /* FFT solver: window power to deconvolve (0, 2, 3) */
+  int fft_deconv;     /* FFT and FULL_FFT solvers: window power to deconvolve (0 none,
+                         1 NGP, 2 CIC, 3 TSC) */
   double omega_m;     /* matter density parameter (1 = Einstein-de Sitter) */
   pm_mg_params mg;
   int timing;         /* 1: record per-stage times into pm_step_stats (adds events) */
@@ -155,13 +169,13 @@ const char *pm_last_error(const pm_ctx *ctx);
  * order PM_DEPOSIT_SORTED: particles are bucketed (a counting sort into context
  *   scratch; the caller's arrays are not reordered). With n % 8 == 0 the buckets
  *   are 8^3-cell tiles: each tile adds its particles' weights into a box of the
- *   tile plus a one-cell halo on chip and stores the box (10^3 64-bit values per
- *   tile of context scratch, allocated on first use); a second pass sums for
- *   every cell the boxes that cover it, with one write per cell. Otherwise the
+ *   tile plus a one-cell halo on chip, in 64-bit fixed point, and stores the box
+ *   (10^3 values, each rounded once to FP32, per tile of context scratch,
+ *   allocated on first use); a second pass sums for every cell the boxes that
+ *   cover it in FP64 in a fixed order, with one write per cell. Otherwise the
  *   buckets are cells and every cell gathers the contributions of the particles
- *   in its 27 (8) neighbour cells. Contributions are summed in 64-bit fixed
- *   point, so the result is bitwise identical for any particle order and any
- *   run. */
+ *   in its 27 (8, 1) neighbour cells in 64-bit fixed point. Either way the result
+ *   is bitwise identical for any particle order and any run. */
 int pm_deposit(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np,
                int poskind, int mas, int order, float *rho, pm_stream stream);
 
@@ -178,10 +192,26 @@ int pm_solve_mg(pm_ctx *ctx, const float *rho, float coef, float *phi,
                 const pm_mg_params *params, pm_mg_stats *stats, pm_stream stream);
 
 /* FFT Poisson solve (Sect. 3.8, 'FFT'): phi(k) = -coef rho(k) / (k^2 W(k)^2),
- * W = [prod_d sinc(k_d h / 2)]^deconv with deconv = 0 (none), 2 (CIC) or 3
- * (TSC); phi(0) = 0. n must be a power of two (16 .. 512). */
+ * W = [prod_d sinc(k_d h / 2)]^deconv with deconv = 0 (none), 1 (NGP), 2 (CIC) or
+ * 3 (TSC), k = 2 pi m in the unit box with m in [-n/2, n/2); phi(0) = 0. n must
+ * be a power of two (8 .. 1024). Same as pm_solve_fft_kernel with PM_FFT_GREEN. */
 int pm_solve_fft(pm_ctx *ctx, const float *rho, float coef, int deconv, float *phi,
                  pm_stream stream);
+
+/* FFT solve with the Fourier-space kernel of the paper's three FFT methods (Sect. 3.8):
+ *   PM_FFT_GREEN  out = phi [n][n][n]: as pm_solve_fft (deconv 0 .. 3);
+ *   PM_FFT_7PT    out = phi: phi(k) = -coef rho(k) / lambda(k), lambda the seven-point
+ *                 Laplacian's eigenvalue (4/h^2) sum_d sin^2(k_d h / 2) (the paper's
+ *                 printed form of it is garbled; this is the eigenvalue of the stencil
+ *                 it names); no deconvolution (deconv ignored). This is the system the
+ *                 multigrid solver converges to;
+ *   PM_FFT_FULL   out = g [n][n][n][3] = -grad phi taken in Fourier space
+ *                 (Eq. exact_fullfft_kernel): g_d(k) = i k_d coef rho(k) / (k^2 W^2),
+ *                 with k_d = 0 on the Nyquist plane of axis d; deconv as for GREEN.
+ * n must be a power of two (8 .. 1024). FULL uses a second spectrum of context
+ * scratch (8 bytes per cell, allocated on first use). */
+int pm_solve_fft_kernel(pm_ctx *ctx, const float *rho, float coef, int kernel, int deconv,
+                        float *out, pm_stream stream);
 
 /* Acceleration grid g = -grad phi with the central difference of the given
  * number of points (3, 5 or 7; paper gradient table). g is [n][n][n][3]. */
@@ -294,21 +324,35 @@ int pm_accel_vjp(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np,
                  double a, const pm_step_params *params, const float *phi, const float *lam,
                  float scale, float *pos_bar, pm_mg_stats *stats, pm_stream stream);
 
-/* Reverse of one pm_kdk step from a0 to a1 (Sect. 3.4 leapfrog, transposed):
- *   pos_bar += kick1 J(x1)^T vel_bar;  vel_bar += tau pos_bar;
- *   pos_bar += kick0 J(x0)^T vel_bar
- * with tau = 2 (a0^-1/2 - a1^-1/2). (pos0, cell0, phi0) is the state at a0 before
- * the step and (pos1, cell1, phi1) the state after it. kick0 = kick1 = tau / 2
- * is the exact transpose of one step. When a chain of steps is reversed, the
- * kick1 term of one step and the kick0 term of the step after it act on the same
- * positions and the same vel_bar, so a caller may merge them into one (weight
- * (tau_i + tau_{i+1}) / 2) and pass 0 for the other: a zero weight skips that
- * evaluation (and its potential may then be NULL). Updates pos_bar and vel_bar
- * in place; stats (may be NULL) receives the last adjoint solve's record. */
+/* Flags of pm_kdk_adjoint. */
+enum pm_adjoint_flags {
+  /* The closing half-kick term of this step (at x1) was already applied, merged
+   * into the opening term of the step after it (see a_prev below): it is skipped,
+   * and pos1, cell1 and phi1 may be NULL. */
+  PM_ADJ_CLOSING_MERGED = 1
+};
+
+/* Reverse of one pm_kdk step from a0 to a1 (Sect. 3.4 leapfrog, transposed), with
+ * tau = 2 (a0^-1/2 - a1^-1/2) the step's supercomoving time:
+ *   pos_bar += (tau/2) J(x1)^T vel_bar;  vel_bar += tau pos_bar;
+ *   pos_bar += w0 J(x0)^T vel_bar
+ * where J(x) = d accel / d x at the scale factor of x. (pos0, cell0, phi0) is the
+ * state at a0 before the step and (pos1, cell1, phi1) the state after it.
+ * When a chain of steps a_prev -> a0 -> a1 is reversed, the closing term of the
+ * step a_prev -> a0 acts on the same positions (x0) and the same vel_bar as the
+ * opening term of this one, so the library merges them:
+ *   a_prev > 0 (a_prev < a0): w0 = (tau(a_prev, a0) + tau(a0, a1)) / 2, and the
+ *     caller reverses the step a_prev -> a0 next with PM_ADJ_CLOSING_MERGED;
+ *   a_prev <= 0: w0 = tau / 2 (the exact transpose of this step alone).
+ * A chain of N steps so costs N + 1 transposed force evaluations instead of 2N.
+ * flags: 0 or PM_ADJ_CLOSING_MERGED. Updates pos_bar and vel_bar in place; stats
+ * (may be NULL) receives the last adjoint solve's record.
+ * Errors: PM_ERR_ARG (null pointers, a_prev >= a0 > 0, bad scale factors, bad
+ * flags). */
 int pm_kdk_adjoint(pm_ctx *ctx, const float *pos0, const int32_t *cell0, const float *phi0,
                    const float *pos1, const int32_t *cell1, const float *phi1, int64_t np,
-                   int poskind, double a0, double a1, const pm_step_params *params,
-                   double kick0, double kick1, float *pos_bar, float *vel_bar,
+                   int poskind, double a_prev, double a0, double a1,
+                   const pm_step_params *params, int flags, float *pos_bar, float *vel_bar,
                    pm_step_stats *stats, pm_stream stream);
 
 /* Density objective for inference of initial conditions:

@@ -22,11 +22,6 @@ import torch
 from . import hippm as _pm
 
 
-def _tau(a0, a1):
-    # supercomoving time step of Einstein-de Sitter (Sect. 3.1): 2 (a0^-1/2 - a1^-1/2)
-    return 2.0 * (a0 ** -0.5 - a1 ** -0.5)
-
-
 class Run:
     """Settings of a differentiable run: context, scale factors, step parameters.
 
@@ -141,7 +136,6 @@ class Trajectory(torch.autograd.Function):
         ref = pos_bar if pos_bar is not None else vel_bar
         xbar = torch.zeros_like(ref) if pos_bar is None else pos_bar.detach().clone().contiguous()
         vbar = torch.zeros_like(ref) if vel_bar is None else vel_bar.detach().clone().contiguous()
-        taus = [_tau(a[i], a[i + 1]) for i in range(nsteps)]
         starts = sorted(cps)
         for seg, s0 in reversed(list(enumerate(starts))):
             s1 = starts[seg + 1] if seg + 1 < len(starts) else nsteps
@@ -152,14 +146,15 @@ class Trajectory(torch.autograd.Function):
                 run.stats["recomputed_steps"] += 1
                 states.append((pos.clone(), cell.clone(), phi.clone()))
             for i in reversed(range(s0, s1)):
-                kick1 = 0.5 * taus[i] if i == nsteps - 1 else 0.0
-                kick0 = 0.5 * taus[i] + (0.5 * taus[i - 1] if i > 0 else 0.0)
+                # the closing term of step i was merged into the opening term of step i + 1
+                # (same positions, same cotangent), except for the last step
+                merged = i < nsteps - 1
                 x0, c0, phi0 = states[i - s0]
                 x1, c1, phi1 = states[i + 1 - s0]
-                _pm.pm_kdk_adjoint(run.ctx, x0, phi0, x1, phi1 if kick1 else None, a[i],
-                                   a[i + 1], xbar, vbar, kick0=kick0, kick1=kick1,
+                _pm.pm_kdk_adjoint(run.ctx, x0, phi0, x1, phi1, a[i], a[i + 1], xbar, vbar,
+                                   a_prev=a[i - 1] if i > 0 else 0.0, closing_merged=merged,
                                    cell0=run._cell(c0), cell1=run._cell(c1), params=run.adj)
-                run.stats["adjoint_evals"] += 1 + (1 if kick1 else 0)
+                run.stats["adjoint_evals"] += 1 + (0 if merged else 1)
             del states
         return xbar, vbar, None, None
 

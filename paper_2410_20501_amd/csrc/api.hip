@@ -35,7 +35,12 @@ int pm_hip_check(pm_ctx *ctx, hipError_t e, const char *what) {
 
 namespace {
 
-bool valid_mas(int m) { return m == PM_CIC || m == PM_TSC; }
+bool valid_mas(int m) { return m == PM_NGP || m == PM_CIC || m == PM_TSC; }
+// reverse mode needs the window's position derivative: CIC or TSC
+bool valid_mas_vjp(int m) { return m == PM_CIC || m == PM_TSC; }
+bool is_fft(int solver) {
+  return solver == PM_SOLVER_FFT || solver == PM_SOLVER_FFT_7PT || solver == PM_SOLVER_FULL_FFT;
+}
 bool valid_poskind(int k) { return k == PM_POS_BOX || k == PM_POS_CELLOFF; }
 
 int check_particles(pm_ctx *ctx, const void *pos, const int32_t *cell, int64_t np, int poskind) {
@@ -74,11 +79,21 @@ int check_step(pm_ctx *ctx, const pm_step_params *p) {
   if (!valid_mas(p->mas)) return pm_fail(ctx, PM_ERR_ARG, "bad mas");
   if (p->order != PM_DEPOSIT_ATOMIC && p->order != PM_DEPOSIT_SORTED)
     return pm_fail(ctx, PM_ERR_ARG, "bad deposit order");
-  if (p->solver != PM_SOLVER_MG && p->solver != PM_SOLVER_FFT)
+  if (p->solver != PM_SOLVER_MG && !is_fft(p->solver))
     return pm_fail(ctx, PM_ERR_ARG, "bad solver");
   if (p->solver == PM_SOLVER_MG) return check_mg(ctx, &p->mg);
-  if (p->fft_deconv != 0 && p->fft_deconv != 2 && p->fft_deconv != 3)
-    return pm_fail(ctx, PM_ERR_ARG, "fft_deconv must be 0, 2 or 3");
+  if (p->fft_deconv < 0 || p->fft_deconv > 3)
+    return pm_fail(ctx, PM_ERR_ARG, "fft_deconv must be 0, 1, 2 or 3");
+  return PM_OK;
+}
+
+// reverse mode: the window needs a position derivative and the force a potential
+int check_step_vjp(pm_ctx *ctx, const pm_step_params *p) {
+  const int st = check_step(ctx, p);
+  if (st != PM_OK) return st;
+  if (!valid_mas_vjp(p->mas)) return pm_fail(ctx, PM_ERR_ARG, "reverse mode takes CIC or TSC");
+  if (p->solver == PM_SOLVER_FULL_FFT)
+    return pm_fail(ctx, PM_ERR_ARG, "reverse mode does not take the FULL_FFT solver");
   return PM_OK;
 }
 
@@ -123,8 +138,8 @@ int deposit_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np,
     if (st != PM_OK) return st;
     const bool tiles = (n % 8) == 0;
     if (tiles && !ctx->tile_box) {
-      // 10^3 fixed-point values per 8^3 tile (every non-empty tile overwrites its box)
-      if (hipMalloc(&ctx->tile_box, sizeof(unsigned long long) * 1000 * (size_t)(ncell / 512)) !=
+      // 10^3 values per 8^3 tile (every non-empty tile overwrites its box)
+      if (hipMalloc(&ctx->tile_box, sizeof(float) * 1000 * (size_t)(ncell / 512)) !=
           hipSuccess) {
         ctx->tile_box = nullptr;
         return pm_fail(ctx, PM_ERR_NOMEM, "tile box allocation failed");
@@ -163,7 +178,11 @@ int deposit_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np,
 
 int solve_impl(pm_ctx *ctx, const pm_step_params *p, const float *rho, float coef, float *phi,
                pm_mg_stats *st, hipStream_t s, float warm_scale, bool rho_mean_ready = false) {
-  if (p->solver == PM_SOLVER_FFT) return pm_fft_solve(ctx, rho, coef, p->fft_deconv, phi, s);
+  // the sorted deposit leaves the density's mean in mean_f[0]
+  const float *mean = rho_mean_ready ? ctx->mean_f : nullptr;
+  if (p->solver == PM_SOLVER_FFT) return pm_fft_solve(ctx, rho, coef, p->fft_deconv, phi, s, mean);
+  if (p->solver == PM_SOLVER_FFT_7PT)
+    return pm_fft_solve_kind(ctx, rho, coef, 0, PM_FFT_7PT, phi, s, mean);
   return pm_mg_solve(ctx, rho, coef, phi, &p->mg, st, s, warm_scale, rho_mean_ready);
 }
 
@@ -183,14 +202,18 @@ int accel_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, i
   if (st != PM_OK) return st;
   if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[2], s));
   const float coef = (float)(1.5 * a * p->omega_m);
-  const int sst = solve_impl(ctx, p, ctx->rho, coef, phi, stats ? &stats->mg : nullptr, s, warm_scale,
-                             mean_ready);
+  const bool full_fft = p->solver == PM_SOLVER_FULL_FFT;
+  // FULL_FFT: the force grid comes straight from Fourier space (no potential, no stencil)
+  const int sst = full_fft ? pm_fft_solve_kind(ctx, ctx->rho, coef, p->fft_deconv, PM_FFT_FULL,
+                                               ctx->g, s, mean_ready ? ctx->mean_f : nullptr)
+                           : solve_impl(ctx, p, ctx->rho, coef, phi, stats ? &stats->mg : nullptr,
+                                        s, warm_scale, mean_ready);
   if (sst < 0) return sst;
   if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[3], s));
   // with the tile buckets of these positions (sorted deposit on tiles), the gradient is
   // formed per tile inside the interpolation kernel
-  const bool tiles = p->order == PM_DEPOSIT_SORTED && ctx->n % 8 == 0;
-  if (!tiles) PM_HIP(ctx, launch_gradient(phi, ctx->n, 5, ctx->g, s));
+  const bool tiles = p->order == PM_DEPOSIT_SORTED && ctx->n % 8 == 0 && !full_fft;
+  if (!tiles && !full_fft) PM_HIP(ctx, launch_gradient(phi, ctx->n, 5, ctx->g, s));
   if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[4], s));
   pm_kt_begin(ctx, PM_KERNEL_INTERP, s);
   double bytes;
@@ -277,6 +300,8 @@ int accel_vjp_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t n
   int sst;
   if (p->solver == PM_SOLVER_FFT) {
     sst = pm_fft_solve(ctx, ctx->adj_phibar, coef, p->fft_deconv, ctx->rho, s);
+  } else if (p->solver == PM_SOLVER_FFT_7PT) {
+    sst = pm_fft_solve_kind(ctx, ctx->adj_phibar, coef, 0, PM_FFT_7PT, ctx->rho, s);
   } else {
     pm_mg_params mg = p->mg;
     mg.guess = PM_GUESS_JACOBI;
@@ -367,6 +392,7 @@ void pm_destroy(pm_ctx *ctx) {
     fr(ctx->lev[l].res);
   }
   fr(ctx->spec);
+  fr(ctx->spec2);
   fr(ctx->twiddle);
   fr(ctx->fft_tab);
   fr(ctx->cell_count);
@@ -413,10 +439,21 @@ int pm_solve_fft(pm_ctx *ctx, const float *rho, float coef, int deconv, float *p
                  pm_stream stream) {
   if (!ctx) return PM_ERR_ARG;
   if (!rho || !phi) return pm_fail(ctx, PM_ERR_ARG, "null grid");
-  if (deconv != 0 && deconv != 2 && deconv != 3)
-    return pm_fail(ctx, PM_ERR_ARG, "deconv must be 0, 2 or 3");
+  if (deconv < 0 || deconv > 3) return pm_fail(ctx, PM_ERR_ARG, "deconv must be 0, 1, 2 or 3");
   if (!std::isfinite(coef)) return pm_fail(ctx, PM_ERR_NONFINITE, "non-finite coef");
   return pm_fft_solve(ctx, rho, coef, deconv, phi, (hipStream_t)stream);
+}
+
+int pm_solve_fft_kernel(pm_ctx *ctx, const float *rho, float coef, int kernel, int deconv,
+                        float *out, pm_stream stream) {
+  if (!ctx) return PM_ERR_ARG;
+  if (!rho || !out) return pm_fail(ctx, PM_ERR_ARG, "null grid");
+  if (kernel != PM_FFT_GREEN && kernel != PM_FFT_7PT && kernel != PM_FFT_FULL)
+    return pm_fail(ctx, PM_ERR_ARG, "bad FFT kernel");
+  if (deconv < 0 || deconv > 3) return pm_fail(ctx, PM_ERR_ARG, "deconv must be 0, 1, 2 or 3");
+  if (!std::isfinite(coef)) return pm_fail(ctx, PM_ERR_NONFINITE, "non-finite coef");
+  return pm_fft_solve_kind(ctx, rho, coef, kernel == PM_FFT_7PT ? 0 : deconv, kernel, out,
+                           (hipStream_t)stream);
 }
 
 int pm_gradient(pm_ctx *ctx, const float *phi, int points, float *g, pm_stream stream) {
@@ -638,7 +675,7 @@ int pm_deposit_vjp(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t n
   if (!ctx) return PM_ERR_ARG;
   int st = check_particles(ctx, pos, cell, np, poskind);
   if (st != PM_OK) return st;
-  if (!valid_mas(mas)) return pm_fail(ctx, PM_ERR_ARG, "bad mas");
+  if (!valid_mas_vjp(mas)) return pm_fail(ctx, PM_ERR_ARG, "reverse mode takes CIC or TSC");
   if (!rho_bar || (np > 0 && !pos_bar)) return pm_fail(ctx, PM_ERR_ARG, "null pointer");
   const int n = ctx->n;
   const float mass = np > 0 ? (float)((double)n * n * n / (double)np) : 0.0f;
@@ -653,7 +690,7 @@ int pm_interp_vjp(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np
   if (!ctx) return PM_ERR_ARG;
   int st = check_particles(ctx, pos, cell, np, poskind);
   if (st != PM_OK) return st;
-  if (!valid_mas(mas)) return pm_fail(ctx, PM_ERR_ARG, "bad mas");
+  if (!valid_mas_vjp(mas)) return pm_fail(ctx, PM_ERR_ARG, "reverse mode takes CIC or TSC");
   if (np > 0 && !lam) return pm_fail(ctx, PM_ERR_ARG, "null lam");
   if (!g_bar && !pos_bar) return pm_fail(ctx, PM_ERR_ARG, "both outputs null");
   if (pos_bar && !g) return pm_fail(ctx, PM_ERR_ARG, "pos_bar needs g");
@@ -678,7 +715,7 @@ int pm_accel_vjp(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np,
   if (!ctx) return PM_ERR_ARG;
   int st = check_particles(ctx, pos, cell, np, poskind);
   if (st != PM_OK) return st;
-  st = check_step(ctx, params);
+  st = check_step_vjp(ctx, params);
   if (st != PM_OK) return st;
   if (!phi || (np > 0 && (!lam || !pos_bar))) return pm_fail(ctx, PM_ERR_ARG, "null pointer");
   if (!(a > 0.0) || !std::isfinite(a)) return pm_fail(ctx, PM_ERR_ARG, "scale factor must be > 0");
@@ -691,41 +728,43 @@ int pm_accel_vjp(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np,
 
 int pm_kdk_adjoint(pm_ctx *ctx, const float *pos0, const int32_t *cell0, const float *phi0,
                    const float *pos1, const int32_t *cell1, const float *phi1, int64_t np,
-                   int poskind, double a0, double a1, const pm_step_params *params, double kick0,
-                   double kick1, float *pos_bar, float *vel_bar, pm_step_stats *stats,
+                   int poskind, double a_prev, double a0, double a1, const pm_step_params *params,
+                   int flags, float *pos_bar, float *vel_bar, pm_step_stats *stats,
                    pm_stream stream) {
   if (!ctx) return PM_ERR_ARG;
+  if (flags & ~PM_ADJ_CLOSING_MERGED) return pm_fail(ctx, PM_ERR_ARG, "bad flags");
+  const bool closing = !(flags & PM_ADJ_CLOSING_MERGED);
   int st = check_particles(ctx, pos0, cell0, np, poskind);
-  if (st == PM_OK) st = check_particles(ctx, pos1, cell1, np, poskind);
+  if (st == PM_OK && closing) st = check_particles(ctx, pos1, cell1, np, poskind);
   if (st != PM_OK) return st;
-  st = check_step(ctx, params);
+  st = check_step_vjp(ctx, params);
   if (st != PM_OK) return st;
   if (np > 0 && (!pos_bar || !vel_bar)) return pm_fail(ctx, PM_ERR_ARG, "null cotangent");
-  if ((kick0 != 0.0 && !phi0) || (kick1 != 0.0 && !phi1))
-    return pm_fail(ctx, PM_ERR_ARG, "null potential");
-  if (!(a0 > 0.0) || !(a1 > 0.0) || !std::isfinite(a0) || !std::isfinite(a1))
-    return pm_fail(ctx, PM_ERR_ARG, "scale factors must be > 0");
-  if (!std::isfinite(kick0) || !std::isfinite(kick1))
-    return pm_fail(ctx, PM_ERR_NONFINITE, "non-finite kick weight");
+  if (!phi0 || (closing && !phi1)) return pm_fail(ctx, PM_ERR_ARG, "null potential");
+  if (!(a0 > 0.0) || !(a1 > 0.0) || !std::isfinite(a0) || !std::isfinite(a1) ||
+      !std::isfinite(a_prev))
+    return pm_fail(ctx, PM_ERR_ARG, "scale factors must be > 0 and finite");
+  if (a_prev > 0.0 && !(a_prev < a0)) return pm_fail(ctx, PM_ERR_ARG, "a_prev must be < a0");
   st = ensure_adjoint_scratch(ctx);
   if (st != PM_OK) return st;
   hipStream_t s = (hipStream_t)stream;
+  // supercomoving time of Einstein-de Sitter (Sect. 3.1): tau = 2 (a0^-1/2 - a1^-1/2)
   const double tau = 2.0 * (1.0 / std::sqrt(a0) - 1.0 / std::sqrt(a1));
+  const double tau_prev = a_prev > 0.0 ? 2.0 * (1.0 / std::sqrt(a_prev) - 1.0 / std::sqrt(a0)) : 0.0;
+  const double kick0 = 0.5 * (tau + tau_prev);
   pm_mg_stats *ms = stats ? &stats->mg : nullptr;
   int worst = PM_OK;
-  if (kick1 != 0.0) {
-    st = accel_vjp_impl(ctx, pos1, cell1, np, poskind, a1, params, phi1, vel_bar, (float)kick1,
-                        pos_bar, ms, s);
+  if (closing) {
+    st = accel_vjp_impl(ctx, pos1, cell1, np, poskind, a1, params, phi1, vel_bar,
+                        (float)(0.5 * tau), pos_bar, ms, s);
     if (st < 0) return st;
     worst = std::max(worst, st);
   }
   PM_HIP(ctx, launch_axpy(vel_bar, pos_bar, (float)tau, 3 * np, s));
-  if (kick0 != 0.0) {
-    st = accel_vjp_impl(ctx, pos0, cell0, np, poskind, a0, params, phi0, vel_bar, (float)kick0,
-                        pos_bar, ms, s);
-    if (st < 0) return st;
-    worst = std::max(worst, st);
-  }
+  st = accel_vjp_impl(ctx, pos0, cell0, np, poskind, a0, params, phi0, vel_bar, (float)kick0,
+                      pos_bar, ms, s);
+  if (st < 0) return st;
+  worst = std::max(worst, st);
   return worst;
 }
 
@@ -736,6 +775,7 @@ int pm_density_loss(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t 
   int st = check_particles(ctx, pos, cell, np, poskind);
   if (st != PM_OK) return st;
   if (!valid_mas(mas)) return pm_fail(ctx, PM_ERR_ARG, "bad mas");
+  if (pos_bar && !valid_mas_vjp(mas)) return pm_fail(ctx, PM_ERR_ARG, "reverse mode takes CIC or TSC");
   if (order != PM_DEPOSIT_ATOMIC && order != PM_DEPOSIT_SORTED)
     return pm_fail(ctx, PM_ERR_ARG, "bad deposit order");
   if (!w) return pm_fail(ctx, PM_ERR_ARG, "null weight grid");

@@ -683,6 +683,8 @@ struct pm_batch {
   StepDev *steps = nullptr;
   StepDev *steps_host = nullptr;    // pinned staging
   int steps_cap = 0;
+  hipEvent_t steps_copied = nullptr;  // recorded after the last copy out of steps_host
+  bool steps_pending = false;
   int *ctr = nullptr;
   // tuned tile shapes (rows per thread of the stencil kernels); a shape is usable only
   // when it divides the side of every level it would run on
@@ -866,20 +868,29 @@ int ensure_steps(pm_batch *B, int count) {
 // step table for a[0..nsteps]: entry i drives the step a[i] -> a[i+1]
 int upload_steps(pm_batch *B, const double *a, int nsteps, const pm_step_params *p, bool rescale,
                  hipStream_t s) {
-  int st = ensure_steps(B, nsteps);
-  if (st != PM_OK) return st;
   for (int i = 0; i < nsteps; ++i) {
     const double a0 = a[i], a1 = a[i + 1];
     if (!(a0 > 0.0) || !(a1 > 0.0) || !std::isfinite(a0) || !std::isfinite(a1))
       return bfail(B, PM_ERR_ARG, "scale factors must be > 0");
+  }
+  // the pinned staging table is reused: the previous call's copy out of it (queued on
+  // whichever stream that call used) must have finished before it is overwritten
+  if (B->steps_pending) {
+    BHIP(B, hipEventSynchronize(B->steps_copied));
+    B->steps_pending = false;
+  }
+  int st = ensure_steps(B, nsteps);
+  if (st != PM_OK) return st;
+  for (int i = 0; i < nsteps; ++i) {
+    const double a0 = a[i], a1 = a[i + 1];
     const double tau = 2.0 * (1.0 / std::sqrt(a0) - 1.0 / std::sqrt(a1));
     B->steps_host[i] = StepDev{(float)(0.5 * tau), (float)tau, (float)(1.5 * a1 * p->omega_m),
                                rescale ? (float)((a1 / a0) * (a1 / a0)) : 1.0f};
   }
-  // the staging buffer is reused: wait for earlier copies out of it
-  BHIP(B, hipStreamSynchronize(s));
   BHIP(B, hipMemcpyAsync(B->steps, B->steps_host, sizeof(StepDev) * nsteps, hipMemcpyHostToDevice,
                          s));
+  BHIP(B, hipEventRecord(B->steps_copied, s));
+  B->steps_pending = true;
   kb_set_counter<<<1, 1, 0, s>>>(B->ctr, 0);
   BHIP(B, hipGetLastError());
   return PM_OK;
@@ -1023,7 +1034,8 @@ int pm_batch_create(pm_batch **out, int nboxes, const int *n, const int64_t *np,
        hipMemcpy(B->items, B->items_h.data(), sizeof(int2) * B->items_h.size(),
                  hipMemcpyHostToDevice) != hipSuccess ||
        hipMemcpy(B->range, range.data(), sizeof(int) * (nboxes + 1), hipMemcpyHostToDevice) !=
-           hipSuccess))
+           hipSuccess ||
+       hipEventCreateWithFlags(&B->steps_copied, hipEventDisableTiming) != hipSuccess))
     st = PM_ERR_HIP;
   if (st != PM_OK) {
     pm_batch_destroy(B);
@@ -1043,6 +1055,7 @@ void pm_batch_destroy(pm_batch *B) {
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (B->steps_host) (void)hipHostFree(B->steps_host);
+  if (B->steps_copied) (void)hipEventDestroy(B->steps_copied);
   delete B;
 }
 

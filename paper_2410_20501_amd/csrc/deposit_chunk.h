@@ -44,6 +44,7 @@ __device__ __forceinline__ int wrap_any(int i, int n) {
 //   W = (1/2)(1/2 - d)^2, 3/4 - d^2, (1/2)(1/2 + d)^2.
 // CIC (MAS = 2): cells floor(u - 1/2) and the next, d = u - 1/2 - floor(u - 1/2):
 //   W = 1 - d, d.
+// NGP (MAS = 1): the cell floor(u), W = 1.
 template <int MAS>
 __device__ __forceinline__ void weights_from_frac(float d, float *w) {
   if constexpr (MAS == 3) {
@@ -51,9 +52,12 @@ __device__ __forceinline__ void weights_from_frac(float d, float *w) {
     w[0] = 0.5f * a * a;
     w[1] = 0.75f - d * d;
     w[2] = 0.5f * b * b;
-  } else {
+  } else if constexpr (MAS == 2) {
     w[0] = 1.0f - d;
     w[1] = d;
+  } else {
+    (void)d;
+    w[0] = 1.0f;
   }
 }
 
@@ -65,11 +69,14 @@ __device__ __forceinline__ int axis_box(float x, float fn, float *w) {
     const float fl = floorf(u);
     weights_from_frac<3>(u - fl - 0.5f, w);
     return (int)fl - 1;
-  } else {
+  } else if constexpr (MAS == 2) {
     const float t = u - 0.5f;
     const float fl = floorf(t);
     weights_from_frac<2>(t - fl, w);
     return (int)fl;
+  } else {
+    weights_from_frac<1>(0.0f, w);
+    return (int)floorf(u);
   }
 }
 
@@ -79,6 +86,9 @@ __device__ __forceinline__ int axis_off(int c, float o, float *w) {
   if constexpr (MAS == 3) {
     weights_from_frac<3>(o - 0.5f, w);
     return c - 1;
+  } else if constexpr (MAS == 1) {
+    weights_from_frac<1>(o, w);
+    return c;
   } else {
     if (o >= 0.5f) {
       weights_from_frac<2>(o - 0.5f, w);
@@ -128,6 +138,7 @@ __device__ __forceinline__ int wave_max_i(int v) {
   return v;
 }
 
+// Window of the separation s = u - (c + 1/2); NGP takes [-1/2, 1/2) (the cell floor(u)).
 template <int MAS>
 __device__ __forceinline__ float window_sep_g(float s) {
   const float a = fabsf(s);
@@ -135,8 +146,10 @@ __device__ __forceinline__ float window_sep_g(float s) {
     if (a < 0.5f) return 0.75f - a * a;
     const float b = 1.5f - a;
     return a < 1.5f ? 0.5f * b * b : 0.0f;
-  } else {
+  } else if constexpr (MAS == 2) {
     return a < 1.0f ? 1.0f - a : 0.0f;
+  } else {
+    return (s >= -0.5f && s < 0.5f) ? 1.0f : 0.0f;
   }
 }
 

@@ -1,7 +1,9 @@
-// FFT Poisson solver (paper Sect. 3.8, 'FFT' kernel with mass-assignment
-// deconvolution, and the seven-point eigenvalue variant).
-//
-// phi = IDFT[ G(k) DFT[rho] ] with G = -coef / (k^2 W(k)^2), W = prod_d sinc(k_d h/2)^p.
+// FFT Poisson solvers of paper Sect. 3.8:
+//   FFT      phi = IDFT[ G(k) DFT[rho] ], G = -coef / (k^2 W(k)^2), W = prod_d sinc(k_d h/2)^p;
+//   FFT_7pt  the same with the seven-point eigenvalue (4/h^2) sum_d sin^2(k_d h/2) in place
+//            of k^2 and no deconvolution;
+//   FULL_FFT the force g = -grad phi taken in Fourier space, g_d = IDFT[-i k_d G DFT[rho]]
+//            (Eq. exact_fullfft_kernel), with k_d = 0 on the Nyquist plane of axis d.
 //
 // Layout: the half spectrum is kept as complex float spec[i][j][kc],
 // kc = 0 .. n/2, row pitch P (a multiple of the column-tile width).
@@ -11,10 +13,11 @@
 //   C  columns along i: forward, multiply by G, inverse (one kernel)
 //   D  columns along j, inverse
 //   E  rows along k, half complex -> real
+// (FULL_FFT: C stores G F; then per force component the i pass multiplies by -i k_d
+// and inverts into a second spectrum, followed by D and E.)
 // The 1D transforms are Stockham autosort radix-4 (+ one radix-2) stages
-// with twiddles from an FP64-computed table.
+// with twiddles from a table computed in FP64 on the device.
 #include <cmath>
-#include <vector>
 
 #include "internal.h"
 
@@ -111,17 +114,29 @@ __device__ void lds_fft(float2 *buf, int L, int T, const float2 *__restrict__ tw
 
 // Pass A: each row x[0..n) -> X[0..n/2]. z_m = x_{2m} + i x_{2m+1}, Z = FFT_{n/2}(z),
 // E_k = (Z_k + conj Z_{n/2-k}) / 2, O_k = -i (Z_k - conj Z_{n/2-k}) / 2, X_k = E_k + w^k O_k.
+// The mean of x (mean != NULL) is subtracted as it is read: the k = 0 mode is dropped by
+// every kernel anyway, and a large mean would otherwise set the scale of the FP32
+// rounding of every other mode (a density of mean 1 with fluctuations of 0.3 loses
+// about a factor 1 / 0.3 in relative accuracy at 512^3).
 __global__ __launch_bounds__(FT) void k_rows_r2c(const float *__restrict__ x,
                                                  float2 *__restrict__ spec, int n, int P,
-                                                 const float2 *__restrict__ tw) {
+                                                 const float2 *__restrict__ tw,
+                                                 const float *__restrict__ mean) {
   __shared__ float2 buf[TL];
   const int L = n / 2, T = TL / L;
   const int64_t rows = (int64_t)n * n;
   const int64_t row0 = (int64_t)blockIdx.x * T;
+  const float mu = mean ? *mean : 0.0f;
   for (int e = threadIdx.x; e < TL; e += FT) {
     const int col = e / L, m = e % L;
     const int64_t row = row0 + col;
-    buf[e] = row < rows ? reinterpret_cast<const float2 *>(x + row * n)[m] : make_float2(0.f, 0.f);
+    float2 v = make_float2(0.f, 0.f);
+    if (row < rows) {
+      v = reinterpret_cast<const float2 *>(x + row * n)[m];
+      v.x -= mu;
+      v.y -= mu;
+    }
+    buf[e] = v;
   }
   __syncthreads();
   lds_fft<false, true>(buf, L, T, tw, 2);
@@ -140,9 +155,12 @@ __global__ __launch_bounds__(FT) void k_rows_r2c(const float *__restrict__ x,
 
 // Pass E: X[0..n/2] -> x[0..n). Z~_k = (X_k + conj X_{n/2-k}) + i conj(w^k) (X_k - conj X_{n/2-k}),
 // z = unnormalised inverse FFT_{n/2}(Z~) = n (x_{2m} + i x_{2m+1}); the 1/n^3 is in G.
+// The output element of row r and position m goes to x[(r n + m) * stride + comp]
+// (stride 1: a scalar grid; stride 3: one component of a vector grid).
 __global__ __launch_bounds__(FT) void k_rows_c2r(const float2 *__restrict__ spec,
                                                  float *__restrict__ x, int n, int P,
-                                                 const float2 *__restrict__ tw) {
+                                                 const float2 *__restrict__ tw, int stride,
+                                                 int comp) {
   __shared__ float2 buf[TL];
   const int L = n / 2, T = TL / L;
   const int64_t rows = (int64_t)n * n;
@@ -162,19 +180,35 @@ __global__ __launch_bounds__(FT) void k_rows_c2r(const float2 *__restrict__ spec
   }
   __syncthreads();
   lds_fft<true, true>(buf, L, T, tw, 2);
-  for (int e = threadIdx.x; e < TL; e += FT) {
-    const int col = e / L, m = e % L;
-    const int64_t row = row0 + col;
-    if (row < rows) reinterpret_cast<float2 *>(x + row * n)[m] = buf[e];
+  if (stride == 1) {
+    for (int e = threadIdx.x; e < TL; e += FT) {
+      const int col = e / L, m = e % L;
+      const int64_t row = row0 + col;
+      if (row < rows) reinterpret_cast<float2 *>(x + row * n)[m] = buf[e];
+    }
+  } else {
+    for (int e = threadIdx.x; e < 2 * TL; e += FT) {
+      const int col = e / n, m = e % n;   // m: real position along the row
+      const int64_t row = row0 + col;
+      if (row < rows) {
+        const float2 v = buf[col * L + (m >> 1)];
+        x[(row * n + m) * stride + comp] = (m & 1) ? v.y : v.x;
+      }
+    }
   }
 }
 
 // Passes B, C, D: length-n transforms along j (AXIS 1) or i (AXIS 0) over a tile of
-// T consecutive kc columns. MODE 0 forward, 1 forward * G then inverse, 2 inverse.
+// T consecutive kc columns, from src to dst (the same buffer, or not). MODE:
+//   0 forward; 1 forward, times G, inverse; 2 inverse; 3 forward, times G;
+//   4 times -i k_d, inverse (d = deriv: 0 the i axis, 1 the j axis, 2 the k axis).
+// G(mx, my, kz) = -scale / ((t0[mx] + t0[my] + t0[kz]) t1[mx] t1[my] t1[kz]) with the
+// per-axis tables t0 = tab[0 .. n), t1 = tab[n .. 2n); k_d = tab[2n + m_d].
 template <int AXIS, int MODE>
-__global__ __launch_bounds__(FT) void k_cols(float2 *__restrict__ spec, int n, int P,
+__global__ __launch_bounds__(FT) void k_cols(const float2 *src, float2 *dst, int n, int P,
                                              const float2 *__restrict__ tw,
-                                             const float *__restrict__ tab, float scale) {
+                                             const float *__restrict__ tab, float scale,
+                                             int deriv) {
   __shared__ float2 buf[TL];
   const int L = n, T = TL / n;
   const int kc0 = blockIdx.x * T;
@@ -187,16 +221,11 @@ __global__ __launch_bounds__(FT) void k_cols(float2 *__restrict__ spec, int n, i
   };
   for (int e = threadIdx.x; e < TL; e += FT) {
     const int idx = e / T, col = e % T;
-    buf[e] = spec[gidx(idx, col)];
+    buf[e] = src[gidx(idx, col)];
   }
   __syncthreads();
-  if constexpr (MODE == 2) {
-    lds_fft<true, false>(buf, L, T, tw, 1);
-  } else {
-    lds_fft<false, false>(buf, L, T, tw, 1);
-  }
-  if constexpr (MODE == 1) {
-    // G(mx, my, kz) = -scale / ((t0[mx] + t0[my] + t0[kz]) * t1[mx] * t1[my] * t1[kz])
+  if constexpr (MODE == 0 || MODE == 1 || MODE == 3) lds_fft<false, false>(buf, L, T, tw, 1);
+  if constexpr (MODE == 1 || MODE == 3) {
     const float *t0 = tab, *t1 = tab + n;
     const int my = outer;
     for (int e = threadIdx.x; e < TL; e += FT) {
@@ -208,86 +237,122 @@ __global__ __launch_bounds__(FT) void k_cols(float2 *__restrict__ spec, int n, i
       buf[e] = make_float2(v.x * gval, v.y * gval);
     }
     __syncthreads();
-    lds_fft<true, false>(buf, L, T, tw, 1);
   }
+  if constexpr (MODE == 4) {
+    // AXIS 0 pass: the element (idx = mx, col) sits at (mx, my = outer, kz = kc0 + col)
+    const float *kv = tab + 2 * n;
+    const int my = outer;
+    for (int e = threadIdx.x; e < TL; e += FT) {
+      const int mx = e / T, kz = kc0 + e % T;
+      const float k = kv[deriv == 0 ? mx : (deriv == 1 ? my : min(kz, n - 1))];
+      const float2 v = buf[e];
+      buf[e] = make_float2(k * v.y, -k * v.x);  // (-i k) v
+    }
+    __syncthreads();
+  }
+  if constexpr (MODE == 1 || MODE == 2 || MODE == 4) lds_fft<true, false>(buf, L, T, tw, 1);
   for (int e = threadIdx.x; e < TL; e += FT) {
     const int idx = e / T, col = e % T;
-    spec[gidx(idx, col)] = buf[e];
+    dst[gidx(idx, col)] = buf[e];
   }
+}
+
+// Twiddles tw[m] = e^{-2 pi i m / n} and the per-axis tables of the kernel, in FP64 on
+// the device and rounded once. For wavenumber index i (m = i, or i - n above n/2):
+//   kind 0 (Green's function with window deconvolution): t0 = k^2, k = 2 pi m (unit
+//     box), t1 = sinc(omega/2)^(2 deconv), omega = k h = 2 pi m / n;
+//   kind 1 (seven-point eigenvalue): t0 = (4 / h^2) sin^2(omega/2), t1 = 1;
+//   kd = k, except 0 at the Nyquist index n/2 (the derivative of a self-conjugate mode).
+__global__ void k_fft_tables(float2 *__restrict__ tw, float *__restrict__ tab, int n, int deconv,
+                             int kind) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double sn, cs;
+  sincospi(-2.0 * (double)i / (double)n, &sn, &cs);
+  tw[i] = make_float2((float)cs, (float)sn);
+  const int m = i < n / 2 ? i : i - n;
+  const double half = (double)m / (double)n;  // omega / (2 pi)
+  const double sh = sinpi(half);
+  if (kind == 1) {
+    tab[i] = (float)(4.0 * (double)n * n * sh * sh);
+    tab[n + i] = 1.0f;
+  } else {
+    const double k = 2.0 * M_PI * (double)m;
+    const double sinc = (m == 0) ? 1.0 : sh / (M_PI * half);
+    tab[i] = (float)(k * k);
+    tab[n + i] = (float)pow(sinc, 2.0 * deconv);
+  }
+  tab[2 * n + i] = (i == n / 2) ? 0.0f : (float)(2.0 * M_PI * (double)m);
 }
 
 }  // namespace
 
-// kind 0: continuous Laplacian with window power `deconv`; kind 1: seven-point eigenvalue.
-static int fft_prepare(pm_ctx *ctx, int deconv, int kind) {
-  const int n = ctx->n;
+int fft_pitch(int n) {
   const int T = TL / n;
-  if (!ctx->spec) {
-    ctx->spec_pitch = ((n / 2 + 1 + T - 1) / T) * T;
-    const size_t bytes = sizeof(float2) * (size_t)n * n * ctx->spec_pitch;
-    if (hipMalloc(&ctx->spec, bytes) != hipSuccess)
-      return pm_fail(ctx, PM_ERR_NOMEM, "FFT spectrum allocation failed");
-    if (hipMemset(ctx->spec, 0, bytes) != hipSuccess)
-      return pm_fail(ctx, PM_ERR_HIP, "FFT spectrum clear failed");
-    std::vector<float2> tw(n);
-    for (int m = 0; m < n; ++m) {
-      const double ang = -2.0 * M_PI * (double)m / (double)n;
-      tw[m] = make_float2((float)std::cos(ang), (float)std::sin(ang));
-    }
-    if (hipMalloc(&ctx->twiddle, sizeof(float2) * n) != hipSuccess ||
-        hipMalloc(&ctx->fft_tab, sizeof(float) * 2 * n) != hipSuccess)
-      return pm_fail(ctx, PM_ERR_NOMEM, "FFT table allocation failed");
-    if (hipMemcpy(ctx->twiddle, tw.data(), sizeof(float2) * n, hipMemcpyHostToDevice) != hipSuccess)
-      return pm_fail(ctx, PM_ERR_HIP, "twiddle upload failed");
-    ctx->fft_tab_key = -1;
-  }
-  const int key = kind * 16 + deconv;
-  if (ctx->fft_tab_key != key) {
-    std::vector<float> tab(2 * n);
-    for (int i = 0; i < n; ++i) {
-      const int m = i < n / 2 ? i : i - n;
-      const double half = M_PI * (double)m / (double)n;  // omega / 2
-      if (kind == 1) {
-        const double s = std::sin(half);
-        tab[i] = (float)(4.0 * (double)n * n * s * s);
-        tab[n + i] = 1.0f;
-      } else {
-        const double k = 2.0 * M_PI * (double)m;
-        const double sinc = (m == 0) ? 1.0 : std::sin(half) / half;
-        tab[i] = (float)(k * k);
-        tab[n + i] = (float)std::pow(sinc, 2.0 * deconv);
-      }
-    }
-    if (hipMemcpy(ctx->fft_tab, tab.data(), sizeof(float) * 2 * n, hipMemcpyHostToDevice) !=
-        hipSuccess)
-      return pm_fail(ctx, PM_ERR_HIP, "Green table upload failed");
-    ctx->fft_tab_key = key;
-  }
-  return PM_OK;
+  return ((n / 2 + 1 + T - 1) / T) * T;
 }
 
-int pm_fft_solve_kind(pm_ctx *ctx, const float *rho, float coef, int deconv, int kind, float *phi,
-                      hipStream_t s) {
-  const int n = ctx->n;
-  if (n < 8 || (n & (n - 1)) != 0)
-    return pm_fail(ctx, PM_ERR_SHAPE, "FFT solver needs a power-of-two grid (8 .. 1024)");
-  int st = fft_prepare(ctx, deconv, kind);
-  if (st != PM_OK) return st;
-  const int P = ctx->spec_pitch;
-  float2 *spec = (float2 *)ctx->spec;
+size_t fft_spec_elems(int n) { return (size_t)n * n * fft_pitch(n); }
+
+hipError_t fft_run(const FftBufs &b, int n, const float *rho, const float *mean, float coef,
+                   int deconv, int kind, float *out, hipStream_t s) {
+  const int P = fft_pitch(n);
   const int Trow = TL / (n / 2), Tcol = TL / n;
   const unsigned row_blocks = (unsigned)(((int64_t)n * n + Trow - 1) / Trow);
   const dim3 col_grid(P / Tcol, n);
   const float scale = (float)((double)coef / ((double)n * n * n));
-  k_rows_r2c<<<row_blocks, FT, 0, s>>>(rho, spec, n, P, ctx->twiddle);
-  k_cols<1, 0><<<col_grid, FT, 0, s>>>(spec, n, P, ctx->twiddle, ctx->fft_tab, scale);
-  k_cols<0, 1><<<col_grid, FT, 0, s>>>(spec, n, P, ctx->twiddle, ctx->fft_tab, scale);
-  k_cols<1, 2><<<col_grid, FT, 0, s>>>(spec, n, P, ctx->twiddle, ctx->fft_tab, scale);
-  k_rows_c2r<<<row_blocks, FT, 0, s>>>(spec, phi, n, P, ctx->twiddle);
-  PM_HIP(ctx, hipGetLastError());
+  float2 *spec = b.spec;
+  k_fft_tables<<<(n + 255) / 256, 256, 0, s>>>(b.twiddle, b.tab, n, deconv,
+                                               kind == PM_FFT_7PT ? 1 : 0);
+  k_rows_r2c<<<row_blocks, FT, 0, s>>>(rho, spec, n, P, b.twiddle, mean);
+  k_cols<1, 0><<<col_grid, FT, 0, s>>>(spec, spec, n, P, b.twiddle, b.tab, scale, 0);
+  if (kind != PM_FFT_FULL) {
+    k_cols<0, 1><<<col_grid, FT, 0, s>>>(spec, spec, n, P, b.twiddle, b.tab, scale, 0);
+    k_cols<1, 2><<<col_grid, FT, 0, s>>>(spec, spec, n, P, b.twiddle, b.tab, scale, 0);
+    k_rows_c2r<<<row_blocks, FT, 0, s>>>(spec, out, n, P, b.twiddle, 1, 0);
+    return hipGetLastError();
+  }
+  // force in Fourier space: spec <- G F once, then per component d the inverse of
+  // -i k_d G F into the second spectrum and one component of the force grid
+  k_cols<0, 3><<<col_grid, FT, 0, s>>>(spec, spec, n, P, b.twiddle, b.tab, scale, 0);
+  for (int d = 0; d < 3; ++d) {
+    k_cols<0, 4><<<col_grid, FT, 0, s>>>(spec, b.spec2, n, P, b.twiddle, b.tab, scale, d);
+    k_cols<1, 2><<<col_grid, FT, 0, s>>>(b.spec2, b.spec2, n, P, b.twiddle, b.tab, scale, 0);
+    k_rows_c2r<<<row_blocks, FT, 0, s>>>(b.spec2, out, n, P, b.twiddle, 3, d);
+  }
+  return hipGetLastError();
+}
+
+int pm_fft_solve_kind(pm_ctx *ctx, const float *rho, float coef, int deconv, int kind, float *out,
+                      hipStream_t s, const float *mean) {
+  const int n = ctx->n;
+  if (n < 8 || (n & (n - 1)) != 0)
+    return pm_fail(ctx, PM_ERR_SHAPE, "FFT solver needs a power-of-two grid (8 .. 1024)");
+  const size_t elems = fft_spec_elems(n);
+  if (!ctx->spec) {
+    if (hipMalloc(&ctx->spec, sizeof(float2) * elems) != hipSuccess ||
+        hipMalloc(&ctx->twiddle, sizeof(float2) * n) != hipSuccess ||
+        hipMalloc(&ctx->fft_tab, sizeof(float) * 3 * n) != hipSuccess)
+      return pm_fail(ctx, PM_ERR_NOMEM, "FFT scratch allocation failed");
+  }
+  if (kind == PM_FFT_FULL && !ctx->spec2) {
+    if (hipMalloc(&ctx->spec2, sizeof(float2) * elems) != hipSuccess) {
+      ctx->spec2 = nullptr;
+      return pm_fail(ctx, PM_ERR_NOMEM, "FFT scratch allocation failed");
+    }
+  }
+  if (!mean) {
+    // the mean of rho, subtracted before the transform
+    PM_HIP(ctx, launch_sum_moments(rho, (int64_t)n * n * n, ctx->red_partial, ctx->red_result,
+                                   ctx->mean_f + 2, s));
+    mean = ctx->mean_f + 2;
+  }
+  FftBufs b{(float2 *)ctx->spec, (float2 *)ctx->spec2, ctx->twiddle, ctx->fft_tab};
+  PM_HIP(ctx, fft_run(b, n, rho, mean, coef, deconv, kind, out, s));
   return PM_OK;
 }
 
-int pm_fft_solve(pm_ctx *ctx, const float *rho, float coef, int deconv, float *phi, hipStream_t s) {
-  return pm_fft_solve_kind(ctx, rho, coef, deconv, 0, phi, s);
+int pm_fft_solve(pm_ctx *ctx, const float *rho, float coef, int deconv, float *phi, hipStream_t s,
+                 const float *mean) {
+  return pm_fft_solve_kind(ctx, rho, coef, deconv, PM_FFT_GREEN, phi, s, mean);
 }

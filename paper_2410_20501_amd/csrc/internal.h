@@ -40,13 +40,13 @@ struct pm_ctx {
   double *red_result;    // [4] device: {sum0, sum1, mean, spare}
   double *host_result;   // pinned [4]
   float *mean_f;         // [4] device: [0] FP32 mean of the current source grid,
-                         // [1] mean of the solve's final iterate (gauge)
+                         // [1] mean of the solve's final iterate (gauge), [2] mean of the
+                         // FFT solve's input
   // FFT spectrum (lazy)
-  void *spec;            // complex float [n][n][pitch]
-  int spec_pitch;
+  void *spec;            // complex float [n][n][fft_pitch(n)]
+  void *spec2;           // second spectrum of the Fourier-space force (lazy)
   float2 *twiddle;       // [n] e^{-2 pi i m / n}, m = 0 .. n-1
-  float *fft_tab;        // [2n] per-axis Green's-function tables
-  int fft_tab_key;       // which kernel the tables hold
+  float *fft_tab;        // [3n] per-axis tables: k^2 part, window part, k_d
   // counting sort (lazy)
   int32_t *cell_count;   // [n^3 + 1] counts -> starts -> ends (end of c = start of c + 1)
   int32_t *perm;         // [np_max] particle indices bucketed by cell
@@ -54,7 +54,7 @@ struct pm_ctx {
   int32_t *scan_partial; // [SCAN_MAX_BLOCKS]
   int64_t sort_cap;
   void *reorder_tmp;     // [np_max * 12 bytes] permutation staging (lazy)
-  unsigned long long *tile_box;  // [n^3 / 512][10^3] 2^-30 fixed-point tile boxes (sorted deposit, lazy)
+  float *tile_box;       // [n^3 / 512][10^3] tile boxes of the sorted deposit (lazy)
   bool hist_ready;       // tile histogram and keys of the current positions already made
   // a chained step's fused drift leaves the next sort's tile histogram in cell_count2
   // and its keys in pcell, valid for the particle arrays it names until they move
@@ -188,8 +188,20 @@ hipError_t launch_rr_stream(const float *u, const float *f, float fscale, const 
                             hipStream_t s);
 
 // fft.hip
+struct FftBufs {
+  float2 *spec, *spec2;  // half spectra [n][n][fft_pitch(n)] (spec2: PM_FFT_FULL only)
+  float2 *twiddle;       // [n]
+  float *tab;            // [3n]
+};
+int fft_pitch(int n);
+size_t fft_spec_elems(int n);
+// kind: a pm_fft_kernel; out: phi [n^3] (PM_FFT_GREEN, PM_FFT_7PT) or g [n^3 * 3] (PM_FFT_FULL);
+// mean (device, may be NULL): subtracted from rho before the transform
+hipError_t fft_run(const FftBufs &b, int n, const float *rho, const float *mean, float coef,
+                   int deconv, int kind, float *out, hipStream_t s);
+// mean: the device mean of rho when known (the sorted deposit's), else computed here
 int pm_fft_solve(pm_ctx *ctx, const float *rho, float coef, int deconv, float *phi,
-                 hipStream_t s);
-int pm_fft_solve_kind(pm_ctx *ctx, const float *rho, float coef, int deconv, int kind, float *phi,
-                      hipStream_t s);
+                 hipStream_t s, const float *mean = nullptr);
+int pm_fft_solve_kind(pm_ctx *ctx, const float *rho, float coef, int deconv, int kind, float *out,
+                      hipStream_t s, const float *mean = nullptr);
 int64_t scan_blocks_needed(int64_t len);

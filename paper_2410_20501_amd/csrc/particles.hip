@@ -449,14 +449,7 @@ constexpr double kFixScale = 1099511627776.0;  // 2^40
 
 template <int MAS>
 __device__ __forceinline__ float window_sep(float s) {
-  const float a = fabsf(s);
-  if constexpr (MAS == 3) {
-    if (a < 0.5f) return 0.75f - a * a;
-    const float b = 1.5f - a;
-    return a < 1.5f ? 0.5f * b * b : 0.0f;
-  } else {
-    return a < 1.0f ? 1.0f - a : 0.0f;
-  }
+  return window_sep_g<MAS>(s);
 }
 
 // One thread per cell: sums the window values of the particles bucketed in the
@@ -527,6 +520,13 @@ __device__ __forceinline__ unsigned long long wave_sum_ull(unsigned long long v)
   return v;
 }
 
+// wave sum in a fixed order (the shuffle tree is the same in every run)
+__device__ __forceinline__ double wave_sum_double(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
 inline unsigned blocks_for(int64_t count, int threads) {
   return (unsigned)((count + threads - 1) / threads);
 }
@@ -536,13 +536,15 @@ inline unsigned blocks_for(int64_t count, int threads) {
 // Deterministic deposit from particles bucketed by 8^3-cell tile: one workgroup per
 // tile reads only the particles of its own tile (each particle once), adds their 27
 // (8) window weights as 2^-30 fixed-point integers to an LDS box of the tile plus a
-// one-cell halo, and stores the whole box (10^3 64-bit values) with plain coalesced
-// stores to the tile's slot of a box array; an empty tile stores nothing. A gather
-// pass then forms each cell's sum from the one to eight boxes that cover it (a cell on
-// a tile face, edge or corner is also in the halo of one, three or seven neighbours),
-// skipping empty tiles, and writes rho = w 2^-30 sum. Every sum is an integer sum, so
-// the result is bitwise the same for any particle order, any interleaving of the LDS
-// atomics and any run; no global atomics, and nothing to clear between deposits.
+// one-cell halo, and stores the whole box (10^3 values, each exact sum times the
+// particle weight rounded once to FP32) with plain coalesced stores to the tile's slot
+// of a box array; an empty tile stores nothing. A gather pass then forms each cell's
+// density from the one to eight boxes that cover it (a cell on a tile face, edge or
+// corner is also in the halo of one, three or seven neighbours), summed in FP64 in a
+// fixed order, skipping empty tiles. The LDS sums are integer sums and the gather's
+// order is fixed, so the result is bitwise the same for any particle order, any
+// interleaving of the LDS atomics and any run; no global atomics, and nothing to clear
+// between deposits.
 // A wave whose 64 particles share one cell (dense cells: particles kept in
 // tile-major cell order by pm_reorder stay together) first reduces its 27 window
 // moments across lanes.
@@ -622,8 +624,8 @@ __global__ __launch_bounds__(kDThreads) void k_deposit_own(const float *__restri
                                                            const int32_t *__restrict__ cell,
                                                            const int32_t *__restrict__ end,
                                                            const int32_t *__restrict__ perm,
-                                                           int n,
-                                                           unsigned long long *__restrict__ tbox) {
+                                                           int n, double scale,
+                                                           float *__restrict__ tbox) {
   __shared__ unsigned long long box[kTHalo];
   // per-wave particle count of each cell of the tile in the current pass (kept zero
   // between passes): a lane's rank among the wave's lanes in its cell
@@ -719,9 +721,9 @@ __global__ __launch_bounds__(kDThreads) void k_deposit_own(const float *__restri
         const int sa = t + ra - (t + ra >= MAS ? MAS : 0);
         const int sb = t + rb - (t + rb >= MAS ? MAS : 0);
         const int sc = t + rc - (t + rc >= MAS ? MAS : 0);
-        px[t] = sa == 0 ? wx[0] : (sa == 1 ? wx[1] : wx[MAS - 1]);
-        py[t] = sb == 0 ? wy[0] : (sb == 1 ? wy[1] : wy[MAS - 1]);
-        pz[t] = sc == 0 ? wz[0] : (sc == 1 ? wz[1] : wz[MAS - 1]);
+        px[t] = sa == 0 ? wx[0] : (sa == 1 ? wx[MAS > 1 ? 1 : 0] : wx[MAS - 1]);
+        py[t] = sb == 0 ? wy[0] : (sb == 1 ? wy[MAS > 1 ? 1 : 0] : wy[MAS - 1]);
+        pz[t] = sc == 0 ? wz[0] : (sc == 1 ? wz[MAS > 1 ? 1 : 0] : wz[MAS - 1]);
         ox[t] = sa * (kTH * kTH);
         oy[t] = sb * kTH;
         oz[t] = sc;
@@ -744,13 +746,14 @@ __global__ __launch_bounds__(kDThreads) void k_deposit_own(const float *__restri
   }
   __syncthreads();
   // the box belongs to this tile alone: stored whole (zeros included) in the slot order
-  // of its consumers, with coalesced stores
+  // of its consumers, with coalesced stores, each exact integer sum rounded once to FP32
+  // (times the particle weight: scale = w 2^-30)
   static_assert(kTHalo == pm_tilebox::kSlots, "tile box shape");
-  unsigned long long *dst = tbox + (size_t)tile * kTHalo;
+  float *dst = tbox + (size_t)tile * kTHalo;
   for (int o = threadIdx.x; o < kTHalo; o += kDThreads) {
     int hx, hy, hz;
     pm_tilebox::box_of(o, hx, hy, hz);
-    dst[o] = box[(hx * kTH + hy) * kTH + hz];
+    dst[o] = (float)((double)box[(hx * kTH + hy) * kTH + hz] * scale);
   }
 }
 
@@ -839,9 +842,8 @@ constexpr int kGatherBlocks = 65536; // grid-stride above this many rows
 static_assert(kGatherThreads == 4 * 64 && kGRow * kTT == 64, "gather row shape");
 
 __global__ __launch_bounds__(kGatherThreads) void k_tile_gather(
-    const unsigned long long *__restrict__ tbox, const int32_t *__restrict__ end, int n,
-    int64_t rows, double scale, float *__restrict__ rho,
-    unsigned long long *__restrict__ partial) {
+    const float *__restrict__ tbox, const int32_t *__restrict__ end, int n, int64_t rows,
+    float *__restrict__ rho, double *__restrict__ partial) {
   using pm_tilebox::gather_slot;
   using pm_tilebox::kCornerBase;
   using pm_tilebox::kEdgeBase;
@@ -851,11 +853,11 @@ __global__ __launch_bounds__(kGatherThreads) void k_tile_gather(
   __shared__ int s_tile[3][3][kGRow + 2];
   // staged halo: k faces [dz > 0][tile][x * 8 + y], edges along j [dx > 0][dz > 0][tile][y],
   // edges along i [dy > 0][dz > 0][tile][x], corners [dx > 0][dy > 0][dz > 0][tile]
-  __shared__ unsigned long long s_zf[2][kGRow][64];
-  __shared__ unsigned long long s_exz[2][2][kGRow][8];
-  __shared__ unsigned long long s_eyz[2][2][kGRow][8];
-  __shared__ unsigned long long s_cr[2][2][2][kGRow];
-  __shared__ unsigned long long ws[kGatherThreads / 64];
+  __shared__ float s_zf[2][kGRow][64];
+  __shared__ float s_exz[2][2][kGRow][8];
+  __shared__ float s_eyz[2][2][kGRow][8];
+  __shared__ float s_cr[2][2][2][kGRow];
+  __shared__ double ws[kGatherThreads / 64];
   constexpr int kStage = 2 * kGRow * 64 + 2 * 2 * 2 * kGRow * 8 + 8 * kGRow;  // 1600
   constexpr int kStageIt = (kStage + kGatherThreads - 1) / kGatherThreads;
   const int nt = n / kTT;
@@ -863,7 +865,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_tile_gather(
   const int z = threadIdx.x & 63;     // cell along k within the row
   const int m = z >> 3, zl = z & 7;   // tile within the row, k within the tile
   const int w = threadIdx.x >> 6;     // wave: y = w (even steps) or 4 + w (odd steps)
-  unsigned long long sum = 0ull;
+  double sum = 0.0;
   for (int64_t row = xcd_block(blockIdx.x, gridDim.x); row < rows; row += gridDim.x) {
     const int tkb = (int)(row % nkb);
     const int tj = (int)((row / nkb) % nt);
@@ -879,7 +881,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_tile_gather(
     }
     __syncthreads();
     // halo pieces for the cells at k = 0, 7 of each tile: loaded whole (zero when empty)
-    unsigned long long st[kStageIt];
+    float st[kStageIt];
 #pragma unroll
     for (int u = 0; u < kStageIt; ++u) {
       const int q = (int)threadIdx.x + u * kGatherThreads;
@@ -903,8 +905,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_tile_gather(
       }
       // loaded unconditionally (an empty tile or a surplus item reads tile 0's box and
       // is dropped), so that all of a thread's loads are in flight together
-      const unsigned long long val = tbox[(size_t)(t >= 0 ? t : 0) * S + slot];
-      st[u] = t >= 0 ? val : 0ull;
+      const float val = tbox[(size_t)(t >= 0 ? t : 0) * S + slot];
+      st[u] = t >= 0 ? val : 0.0f;
     }
 #pragma unroll
     for (int u = 0; u < kStageIt; ++u) {
@@ -931,32 +933,31 @@ __global__ __launch_bounds__(kGatherThreads) void k_tile_gather(
     // LDS pieces and the stores follow
 #pragma unroll 1
     for (int h = 0; h < 2; ++h) {
-      unsigned long long v[8];
+      double v[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int x = 4 * h + (j >> 1), y = 4 * (j & 1) + w;
         const size_t self = own + gather_slot(0, 0, 0, x, y, zl);
-        const unsigned long long q = tbox[self];
-        unsigned long long a = tc >= 0 ? q : 0ull;
+        const float q = tbox[self];
+        double a = tc >= 0 ? (double)q : 0.0;
         const bool xe = x == 0 || x == kTT - 1;
         const int tx = x == 0 ? txm : txp;
         const bool tkx = xe && tx >= 0;
-        const unsigned long long vx =
+        const float vx =
             tbox[tkx ? (size_t)tx * S + gather_slot(x == 0 ? -1 : 1, 0, 0, x, y, zl) : self];
-        a += tkx ? vx : 0ull;
+        a += tkx ? (double)vx : 0.0;
         const bool ye = y == 0 || y == kTT - 1;  // wave-uniform
         const int ty = y == 0 ? tym : typ;
         const bool tky = ye && ty >= 0;
-        const unsigned long long vy =
+        const float vy =
             tbox[tky ? (size_t)ty * S + gather_slot(0, y == 0 ? -1 : 1, 0, x, y, zl) : self];
-        a += tky ? vy : 0ull;
+        a += tky ? (double)vy : 0.0;
         if (j < 2 || j >= 6) {  // x = 0 or 3 (h = 0), x = 4 or 7 (h = 1): the edges along k
           const int dx = j < 2 ? -1 : 1, dy = y == 0 ? -1 : 1;
           const int t = s_tile[dx + 1][dy + 1][m + 1];
           const bool te = xe && ye && t >= 0;
-          const unsigned long long ve =
-              tbox[te ? (size_t)t * S + gather_slot(dx, dy, 0, x, y, zl) : self];
-          a += te ? ve : 0ull;
+          const float ve = tbox[te ? (size_t)t * S + gather_slot(dx, dy, 0, x, y, zl) : self];
+          a += te ? (double)ve : 0.0;
         }
         v[j] = a;
       }
@@ -964,11 +965,11 @@ __global__ __launch_bounds__(kGatherThreads) void k_tile_gather(
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           const int x = 4 * h + (j >> 1), y = 4 * (j & 1) + w;
-          unsigned long long a = s_zf[sz][m][x * 8 + y];
-          if (x == 0 || x == kTT - 1) a += s_exz[x != 0][sz][m][y];
-          if (y == 0 || y == kTT - 1) a += s_eyz[y != 0][sz][m][x];
+          double a = (double)s_zf[sz][m][x * 8 + y];
+          if (x == 0 || x == kTT - 1) a += (double)s_exz[x != 0][sz][m][y];
+          if (y == 0 || y == kTT - 1) a += (double)s_eyz[y != 0][sz][m][x];
           if ((x == 0 || x == kTT - 1) && (y == 0 || y == kTT - 1))
-            a += s_cr[x != 0][y != 0][sz][m];
+            a += (double)s_cr[x != 0][y != 0][sz][m];
           v[j] += a;
         }
       }
@@ -976,39 +977,39 @@ __global__ __launch_bounds__(kGatherThreads) void k_tile_gather(
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           const int x = 4 * h + (j >> 1), y = 4 * (j & 1) + w;
-          rho[((size_t)(ti * kTT + x) * n + (tj * kTT + y)) * n + kg] =
-              (float)((double)v[j] * scale);
-          sum += v[j];
+          const float r = (float)v[j];
+          rho[((size_t)(ti * kTT + x) * n + (tj * kTT + y)) * n + kg] = r;
+          sum += (double)r;
         }
       }
     }
   }
   if (partial) {
-    sum = wave_sum_ull(sum);
+    sum = wave_sum_double(sum);
     if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = sum;
     __syncthreads();
     if (threadIdx.x == 0) {
-      unsigned long long b = 0ull;
+      double b = 0.0;
       for (int q = 0; q < kGatherThreads / 64; ++q) b += ws[q];
       partial[blockIdx.x] = b;
     }
   }
 }
 
-// mean = (sum of the block sums) * scale / count
-__global__ __launch_bounds__(kThreads) void k_fix_mean(const unsigned long long *__restrict__ partial,
-                                                       int nblocks, double scale, int64_t count,
+// mean = (sum of the block sums of rho) / count, in FP64 in a fixed order
+__global__ __launch_bounds__(kThreads) void k_fix_mean(const double *__restrict__ partial,
+                                                       int nblocks, int64_t count,
                                                        float *__restrict__ mean) {
-  unsigned long long sum = 0ull;
+  double sum = 0.0;
   for (int b = threadIdx.x; b < nblocks; b += kThreads) sum += partial[b];
-  __shared__ unsigned long long ws[kThreads / 64];
-  sum = wave_sum_ull(sum);
+  __shared__ double ws[kThreads / 64];
+  sum = wave_sum_double(sum);
   if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = sum;
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned long long t = 0ull;
+    double t = 0.0;
     for (int w = 0; w < kThreads / 64; ++w) t += ws[w];
-    *mean = (float)((double)t * scale / (double)count);
+    *mean = (float)(t / (double)count);
   }
 }
 
@@ -1256,6 +1257,11 @@ hipError_t launch_deposit_atomic(const float *pos, const int32_t *cell, int64_t 
       k_deposit_chunk<3, PM_POS_BOX><<<nb, kGThreads, 0, s>>>(pos, cell, np, n, mass, rho);
     else
       k_deposit_chunk<3, PM_POS_CELLOFF><<<nb, kGThreads, 0, s>>>(pos, cell, np, n, mass, rho);
+  } else if (mas == PM_NGP) {
+    if (poskind == PM_POS_BOX)
+      k_deposit_chunk<1, PM_POS_BOX><<<nb, kGThreads, 0, s>>>(pos, cell, np, n, mass, rho);
+    else
+      k_deposit_chunk<1, PM_POS_CELLOFF><<<nb, kGThreads, 0, s>>>(pos, cell, np, n, mass, rho);
   } else {
     if (poskind == PM_POS_BOX)
       k_deposit_chunk<2, PM_POS_BOX><<<nb, kGThreads, 0, s>>>(pos, cell, np, n, mass, rho);
@@ -1275,6 +1281,11 @@ hipError_t launch_interp(const float *pos, const int32_t *cell, int64_t np, int 
       k_interp<3, PM_POS_BOX><<<nb, kThreads, 0, s>>>(pos, cell, np, n, g, acc, vel, kick);
     else
       k_interp<3, PM_POS_CELLOFF><<<nb, kThreads, 0, s>>>(pos, cell, np, n, g, acc, vel, kick);
+  } else if (mas == PM_NGP) {
+    if (poskind == PM_POS_BOX)
+      k_interp<1, PM_POS_BOX><<<nb, kThreads, 0, s>>>(pos, cell, np, n, g, acc, vel, kick);
+    else
+      k_interp<1, PM_POS_CELLOFF><<<nb, kThreads, 0, s>>>(pos, cell, np, n, g, acc, vel, kick);
   } else {
     if (poskind == PM_POS_BOX)
       k_interp<2, PM_POS_BOX><<<nb, kThreads, 0, s>>>(pos, cell, np, n, g, acc, vel, kick);
@@ -1340,26 +1351,31 @@ hipError_t launch_deposit_own(pm_ctx *ctx, const float *pos, const int32_t *cell
   const int n = ctx->n;
   const int64_t ncell = (int64_t)n * n * n;
   const unsigned nt = (unsigned)(ncell / kTThreads);
-  unsigned long long *tbox = ctx->tile_box;
+  float *tbox = ctx->tile_box;
+  // fixed-point unit 2^-30 times the particle weight
+  const double scale = (double)mass / 1073741824.0;
 #define PM_DO(M, K)                                                                             \
-  k_deposit_own<M, K><<<nt, kDThreads, 0, s>>>(pos, cell, ctx->cell_count, ctx->perm, n, tbox)
+  k_deposit_own<M, K><<<nt, kDThreads, 0, s>>>(pos, cell, ctx->cell_count, ctx->perm, n, scale, \
+                                               tbox)
   if (mas == PM_TSC) {
     if (poskind == PM_POS_BOX) PM_DO(3, PM_POS_BOX);
     else PM_DO(3, PM_POS_CELLOFF);
+  } else if (mas == PM_NGP) {
+    if (poskind == PM_POS_BOX) PM_DO(1, PM_POS_BOX);
+    else PM_DO(1, PM_POS_CELLOFF);
   } else {
     if (poskind == PM_POS_BOX) PM_DO(2, PM_POS_BOX);
     else PM_DO(2, PM_POS_CELLOFF);
   }
 #undef PM_DO
-  const double scale = (double)mass / 1073741824.0;
   // block sums go to the reduction scratch (free until the solve that follows)
-  unsigned long long *partial = reinterpret_cast<unsigned long long *>(ctx->red_partial);
+  double *partial = ctx->red_partial;
   const int ntile = n / kTT;
   const int64_t rows = (int64_t)ntile * ntile * ((ntile + kGRow - 1) / kGRow);
   const int nb = (int)std::min<int64_t>(rows, kGatherBlocks);
-  k_tile_gather<<<nb, kGatherThreads, 0, s>>>(tbox, ctx->cell_count, n, rows, scale, rho,
+  k_tile_gather<<<nb, kGatherThreads, 0, s>>>(tbox, ctx->cell_count, n, rows, rho,
                                               mean ? partial : nullptr);
-  if (mean) k_fix_mean<<<1, kThreads, 0, s>>>(partial, nb, scale, ncell, mean);
+  if (mean) k_fix_mean<<<1, kThreads, 0, s>>>(partial, nb, ncell, mean);
   return hipGetLastError();
 }
 
@@ -1374,6 +1390,9 @@ hipError_t launch_interp_tile(pm_ctx *ctx, const float *pos, const int32_t *cell
   if (mas == PM_TSC) {
     if (poskind == PM_POS_BOX) PM_IT(3, PM_POS_BOX);
     else PM_IT(3, PM_POS_CELLOFF);
+  } else if (mas == PM_NGP) {
+    if (poskind == PM_POS_BOX) PM_IT(1, PM_POS_BOX);
+    else PM_IT(1, PM_POS_CELLOFF);
   } else {
     if (poskind == PM_POS_BOX) PM_IT(2, PM_POS_BOX);
     else PM_IT(2, PM_POS_CELLOFF);
@@ -1408,6 +1427,9 @@ hipError_t launch_interp_tile_phi(pm_ctx *ctx, float *pos, int32_t *cell, int po
   if (mas == PM_TSC) {
     if (poskind == PM_POS_BOX) PM_ITP(3, PM_POS_BOX);
     else PM_ITP(3, PM_POS_CELLOFF);
+  } else if (mas == PM_NGP) {
+    if (poskind == PM_POS_BOX) PM_ITP(1, PM_POS_BOX);
+    else PM_ITP(1, PM_POS_CELLOFF);
   } else {
     if (poskind == PM_POS_BOX) PM_ITP(2, PM_POS_BOX);
     else PM_ITP(2, PM_POS_CELLOFF);
@@ -1429,6 +1451,13 @@ hipError_t launch_deposit_pull(pm_ctx *ctx, const float *pos, int64_t np, int po
                                                               mass, rho);
     else
       k_deposit_pull<3, PM_POS_CELLOFF><<<nb, kThreads, 0, s>>>(pos, ctx->cell_count, ctx->perm,
+                                                                  n, mass, rho);
+  } else if (mas == PM_NGP) {
+    if (poskind == PM_POS_BOX)
+      k_deposit_pull<1, PM_POS_BOX><<<nb, kThreads, 0, s>>>(pos, ctx->cell_count, ctx->perm, n,
+                                                              mass, rho);
+    else
+      k_deposit_pull<1, PM_POS_CELLOFF><<<nb, kThreads, 0, s>>>(pos, ctx->cell_count, ctx->perm,
                                                                   n, mass, rho);
   } else {
     if (poskind == PM_POS_BOX)

@@ -19,18 +19,23 @@ LIB_PATH = os.path.join(_HERE, "libhippm.so")
 # enums (mirror include/hippm.h)
 PM_OK, PM_WARN_NOT_CONVERGED, PM_WARN_FLOOR = 0, 1, 2
 PM_ERR_ARG, PM_ERR_SHAPE, PM_ERR_NOMEM, PM_ERR_HIP, PM_ERR_NONFINITE = -1, -2, -3, -4, -5
-PM_CIC, PM_TSC = 2, 3
+PM_NGP, PM_CIC, PM_TSC = 1, 2, 3
 PM_DEPOSIT_ATOMIC, PM_DEPOSIT_SORTED = 0, 1
 PM_POS_BOX, PM_POS_CELLOFF = 0, 1
 PM_RESTRICT_FW, PM_RESTRICT_AVG = 0, 1
 PM_CYCLE_V, PM_CYCLE_W, PM_CYCLE_F = 0, 1, 2
-PM_SOLVER_MG, PM_SOLVER_FFT = 0, 1
+PM_SOLVER_MG, PM_SOLVER_FFT, PM_SOLVER_FFT_7PT, PM_SOLVER_FULL_FFT = 0, 1, 2, 3
+PM_FFT_GREEN, PM_FFT_7PT, PM_FFT_FULL = 0, 1, 2
 PM_GUESS_JACOBI, PM_GUESS_WARM, PM_GUESS_WARM_RESCALED = 0, 1, 2
 PM_CHAIN_FIRST, PM_CHAIN_NEXT = 0, 1
+PM_ADJ_CLOSING_MERGED = 1
 PM_CREATE_REFERENCE_KERNELS = 1
 PM_KERNEL_NONE, PM_KERNEL_DEPOSIT, PM_KERNEL_SMOOTH, PM_KERNEL_INTERP = 0, 1, 2, 3
 
-MAS = {"cic": PM_CIC, "tsc": PM_TSC}
+MAS = {"ngp": PM_NGP, "cic": PM_CIC, "tsc": PM_TSC}
+SOLVER = {"mg": PM_SOLVER_MG, "fft": PM_SOLVER_FFT, "fft_7pt": PM_SOLVER_FFT_7PT,
+          "full_fft": PM_SOLVER_FULL_FFT}
+FFT_KERNEL = {"green": PM_FFT_GREEN, "7pt": PM_FFT_7PT, "full": PM_FFT_FULL}
 ORDER = {"atomic": PM_DEPOSIT_ATOMIC, "sorted": PM_DEPOSIT_SORTED}
 
 
@@ -80,6 +85,7 @@ def _load():
         "pm_deposit": (c_int, [P, P, P, c_int64, c_int, c_int, c_int, P, P]),
         "pm_solve_mg": (c_int, [P, P, c_float, P, POINTER(MGParams), POINTER(MGStats), P]),
         "pm_solve_fft": (c_int, [P, P, c_float, c_int, P, P]),
+        "pm_solve_fft_kernel": (c_int, [P, P, c_float, c_int, c_int, P, P]),
         "pm_gradient": (c_int, [P, P, c_int, P, P]),
         "pm_interp": (c_int, [P, P, P, c_int64, c_int, c_int, P, P, P]),
         "pm_accel": (c_int, [P, P, P, c_int64, c_int, c_double, POINTER(StepParams), P, P,
@@ -97,7 +103,7 @@ def _load():
         "pm_accel_vjp": (c_int, [P, P, P, c_int64, c_int, c_double, POINTER(StepParams), P, P,
                                  c_float, P, POINTER(MGStats), P]),
         "pm_kdk_adjoint": (c_int, [P, P, P, P, P, P, P, c_int64, c_int, c_double, c_double,
-                                   POINTER(StepParams), c_double, c_double, P, P,
+                                   c_double, POINTER(StepParams), c_int, P, P,
                                    POINTER(StepStats), P]),
         "pm_density_loss": (c_int, [P, P, P, c_int64, c_int, c_int, c_int, P,
                                     POINTER(c_double), P, P]),
@@ -134,7 +140,7 @@ def default_step_params(**kw) -> StepParams:
         elif k == "order":
             v = ORDER.get(v, v)
         elif k == "solver":
-            v = {"mg": PM_SOLVER_MG, "fft": PM_SOLVER_FFT}.get(v, v)
+            v = SOLVER.get(v, v)
         elif k == "guess":
             v = {"jacobi": PM_GUESS_JACOBI, "warm": PM_GUESS_WARM,
                  "warm_rescaled": PM_GUESS_WARM_RESCALED}.get(v, v)
@@ -244,6 +250,17 @@ def pm_solve_fft(ctx: Context, rho, coef, phi, deconv=3):
     st = _lib.pm_solve_fft(ctx.handle, _ptr(rho, shape=(n, n, n), name="rho"), float(coef),
                            int(deconv), _ptr(phi, shape=(n, n, n), name="phi"), _stream())
     return ctx._check(st, "pm_solve_fft")
+
+
+def pm_solve_fft_kernel(ctx: Context, rho, coef, out, kernel="green", deconv=3):
+    """kernel "green" / "7pt": out = phi [n, n, n]; "full": out = g [n, n, n, 3]."""
+    n = ctx.n
+    kid = FFT_KERNEL.get(kernel, kernel)
+    shape = (n, n, n, 3) if kid == PM_FFT_FULL else (n, n, n)
+    st = _lib.pm_solve_fft_kernel(ctx.handle, _ptr(rho, shape=(n, n, n), name="rho"), float(coef),
+                                  int(kid), int(deconv), _ptr(out, shape=shape, name="out"),
+                                  _stream())
+    return ctx._check(st, "pm_solve_fft_kernel")
 
 
 def pm_gradient(ctx: Context, phi, g, points=5):
@@ -371,22 +388,26 @@ def pm_accel_vjp(ctx: Context, pos, a, phi, lam, pos_bar, scale=1.0, cell=None,
     return stats
 
 
-def pm_kdk_adjoint(ctx: Context, pos0, phi0, pos1, phi1, a0, a1, pos_bar, vel_bar, kick0=None,
-                   kick1=None, cell0=None, cell1=None, params: StepParams | None = None):
-    """Reverse one KDK step in place on (pos_bar, vel_bar); kick weights default to tau/2."""
+def pm_kdk_adjoint(ctx: Context, pos0, phi0, pos1, phi1, a0, a1, pos_bar, vel_bar, a_prev=0.0,
+                   closing_merged=False, cell0=None, cell1=None,
+                   params: StepParams | None = None):
+    """Reverse one KDK step a0 -> a1 in place on (pos_bar, vel_bar). a_prev > 0 merges the
+    closing term of the step a_prev -> a0 into this step's opening term; closing_merged
+    skips this step's closing term (pos1/phi1 may then be None)."""
     n = ctx.n
     np_, kind, p0, c0 = _particles(pos0, cell0)
-    _, kind1, p1, c1 = _particles(pos1, cell1)
-    if kind1 != kind or pos1.shape[0] != np_:
-        raise ValueError("pos0 and pos1 must have the same form and count")
-    tau = 2.0 * (float(a0) ** -0.5 - float(a1) ** -0.5)
-    kick0 = 0.5 * tau if kick0 is None else float(kick0)
-    kick1 = 0.5 * tau if kick1 is None else float(kick1)
+    if closing_merged:
+        p1 = c1 = None
+    else:
+        _, kind1, p1, c1 = _particles(pos1, cell1)
+        if kind1 != kind or pos1.shape[0] != np_:
+            raise ValueError("pos0 and pos1 must have the same form and count")
     params = params or default_step_params()
     stats = StepStats()
     st = _lib.pm_kdk_adjoint(ctx.handle, p0, c0, _ptr(phi0, shape=(n, n, n), name="phi0"),
                              p1, c1, _ptr(phi1, shape=(n, n, n), name="phi1"), np_, kind,
-                             float(a0), float(a1), byref(params), kick0, kick1,
+                             float(a_prev), float(a0), float(a1), byref(params),
+                             PM_ADJ_CLOSING_MERGED if closing_merged else 0,
                              _ptr(pos_bar, shape=(np_, 3), name="pos_bar"),
                              _ptr(vel_bar, shape=(np_, 3), name="vel_bar"), byref(stats), _stream())
     ctx._check(st, "pm_kdk_adjoint")

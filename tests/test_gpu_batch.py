@@ -244,3 +244,97 @@ def test_config4_ensemble_graph_vs_per_box_loop(lib):
     _say(f"  worst box: max |dx| {worst_dx:.1e} box, acc rel at equal positions {worst_a:.1e}")
     assert worst_dx < 1e-5 and worst_a < 1e-5
     B.close()
+
+
+# ------------------------------------------------------------------ against the oracle
+
+def _batch_golden():
+    """The golden's recipe module and its stored oracle values (tests/golden/
+    batch_oracle.json, written by make_batch_golden.py from oracle/ only)."""
+    import json
+    import os
+    golden = os.path.join(os.path.dirname(__file__), "golden")
+    if golden not in sys.path:
+        sys.path.insert(0, golden)
+    import make_batch_golden as mk
+    with open(os.path.join(golden, "batch_oracle.json")) as fh:
+        return mk, json.load(fh)
+
+
+def _rel_np(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.timeout(300)
+def test_batch_against_oracle_one_box_per_size(lib):
+    """One box of each ensemble grid size (32, 48, 64, 96, 128) in one batch, against the
+    FP64 oracle box by box: potential and accelerations at the initial state (sampled,
+    relative L2 <= 1e-5), positions after 10 steps with the batched step's warm-started
+    fixed-cycle solves (sampled, within 1e-4 box units), and the accelerations after the
+    10 steps against the oracle's force chain at the batch's own final positions
+    (relative L2 <= 1e-5)."""
+    from oracle import pm as opm
+    mk, gold = _batch_golden()
+    sizes = list(mk.SIZES)
+    _say(f"batch vs oracle, sizes {sizes}")
+    ins = [mk.box_inputs(b) for b in range(len(sizes))]
+    B = lib.Batch(sizes, [n ** 3 for n in sizes])
+    p = torch.from_numpy(np.concatenate([x for x, _ in ins])).cuda()
+    v = torch.from_numpy(np.concatenate([u for _, u in ins])).cuda()
+    acc = torch.zeros_like(p)
+    phi = torch.zeros(B.ncell_total, device="cuda")
+    a = gold["a"]
+    lib.pm_batch_accel(B, p, acc, phi, a[0], batch_params(lib, True))
+    torch.cuda.synchronize()
+    acc0, phi0 = acc.cpu().numpy(), phi.cpu().numpy()
+    lib.pm_batch_kdk(B, p, v, acc, phi, a, batch_params(lib, False))
+    torch.cuda.synchronize()
+    x10, acc10 = p.cpu().numpy(), acc.cpu().numpy()
+    for b, n in enumerate(sizes):
+        ref = gold["boxes"][b]
+        cells, parts = mk.box_samples(b)
+        sl = slice(B.p_off[b], B.p_off[b + 1])
+        e_phi = _rel_np(phi0[B.c_off[b]:B.c_off[b + 1]][cells], ref["phi0"])
+        e_acc0 = _rel_np(acc0[sl][parts], ref["acc0"])
+        dx = opm.periodic_distance(x10[sl][parts].astype(np.float64), np.array(ref["x10"])).max()
+        xb = x10[sl].astype(np.float64)
+        acc_ref = opm.accel(xb * n, n, a[-1])
+        e_acc10 = _rel_np(acc10[sl], acc_ref)
+        _say(f"  box n={n}: phi0 {e_phi:.1e} acc0 {e_acc0:.1e} |dx|max {dx:.1e} box, "
+             f"acc at the final positions {e_acc10:.1e}")
+        assert e_phi <= 1e-5 and e_acc0 <= 1e-5
+        assert dx <= 1e-4
+        assert e_acc10 <= 1e-5
+    B.close()
+
+
+def test_batch_back_to_back_calls_without_host_sync(lib):
+    """Two pm_batch_kdk calls with different scale factors queued back to back (no host
+    synchronisation between them) give the same result as the same calls with a
+    synchronisation in between: the second call's step table never reaches the first."""
+    sizes, pos, vel = ensemble(4, master_seed=13)
+    _say(f"back-to-back batched calls, sizes {sizes}")
+    B = lib.Batch(sizes, [n ** 3 for n in sizes])
+    p0, v0 = torch.from_numpy(pos).cuda(), torch.from_numpy(vel).cuda()
+    a1 = [0.1, 0.11, 0.12, 0.13]
+    a2 = [0.13, 0.15, 0.17, 0.19, 0.21]
+    outs = []
+    for sync in (True, False):
+        p, v = p0.clone(), v0.clone()
+        acc = torch.zeros_like(p)
+        phi = torch.zeros(B.ncell_total, device="cuda")
+        lib.pm_batch_accel(B, p, acc, phi, a1[0], batch_params(lib, True))
+        torch.cuda.synchronize()
+        lib.pm_batch_kdk(B, p, v, acc, phi, a1, batch_params(lib, False))
+        if sync:
+            torch.cuda.synchronize()
+        lib.pm_batch_kdk(B, p, v, acc, phi, a2, batch_params(lib, False))
+        torch.cuda.synchronize()
+        outs.append((p.cpu().numpy(), v.cpu().numpy()))
+    B.close()
+    dx = periodic_maxdist(outs[0][0], outs[1][0])
+    ev = float(np.linalg.norm(outs[0][1] - outs[1][1]) / np.linalg.norm(outs[0][1]))
+    _say(f"  max |dx| {dx:.1e} box, velocities {ev:.1e}")
+    # the batched deposit sums with FP32 atomics: equal up to rounding order
+    assert dx <= 1e-6 and ev <= 1e-5
