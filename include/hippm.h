@@ -213,6 +213,20 @@ int pm_solve_fft(pm_ctx *ctx, const float *rho, float coef, int deconv, float *p
 int pm_solve_fft_kernel(pm_ctx *ctx, const float *rho, float coef, int kernel, int deconv,
                         float *out, pm_stream stream);
 
+/* pm_solve_fft without a context and without allocating, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc). The spectrum, tables and the mean's partial sums live in a
+ * statically sized device array of the library (about 12.6 MiB, held on each GPU the
+ * library runs on until the process ends); n must be a power of two, 8 .. 128
+ * (PM_ERR_SHAPE otherwise). Same kernels and result as pm_solve_fft with the same n,
+ * coef and deconv (0 .. 3). rho and phi: device arrays [n][n][n] owned by the caller.
+ * Every call on one GPU shares that array: calls that overlap on one GPU (different
+ * streams or threads) race. Errors: PM_ERR_ARG (null pointer, bad deconv),
+ * PM_ERR_NONFINITE (coef), PM_ERR_SHAPE, PM_ERR_HIP (returned as codes; there is no
+ * context for a message). */
+int pm_solve_fft_noalloc(const float *rho, int n, float coef, int deconv, float *phi,
+                         pm_stream stream);
+
 /* Acceleration grid g = -grad phi with the central difference of the given
  * number of points (3, 5 or 7; paper gradient table). g is [n][n][n][3]. */
 int pm_gradient(pm_ctx *ctx, const float *phi, int points, float *g, pm_stream stream);

@@ -86,6 +86,7 @@ def _load():
         "pm_solve_mg": (c_int, [P, P, c_float, P, POINTER(MGParams), POINTER(MGStats), P]),
         "pm_solve_fft": (c_int, [P, P, c_float, c_int, P, P]),
         "pm_solve_fft_kernel": (c_int, [P, P, c_float, c_int, c_int, P, P]),
+        "pm_solve_fft_noalloc": (c_int, [P, c_int, c_float, c_int, P, P]),
         "pm_gradient": (c_int, [P, P, c_int, P, P]),
         "pm_interp": (c_int, [P, P, P, c_int64, c_int, c_int, P, P, P]),
         "pm_accel": (c_int, [P, P, P, c_int64, c_int, c_double, POINTER(StepParams), P, P,
@@ -261,6 +262,19 @@ def pm_solve_fft_kernel(ctx: Context, rho, coef, out, kernel="green", deconv=3):
                                   int(kid), int(deconv), _ptr(out, shape=shape, name="out"),
                                   _stream())
     return ctx._check(st, "pm_solve_fft_kernel")
+
+
+def pm_solve_fft_noalloc(rho, coef, phi, deconv=3):
+    """pm_solve_fft without a context and without allocating (grids up to 128^3, the
+    library's static scratch; calls that overlap on one GPU race on it)."""
+    if rho.dim() != 3 or len(set(rho.shape)) != 1:
+        raise ValueError("rho must be [n, n, n]")
+    n = rho.shape[0]
+    st = _lib.pm_solve_fft_noalloc(_ptr(rho, shape=(n, n, n), name="rho"), int(n), float(coef),
+                                   int(deconv), _ptr(phi, shape=(n, n, n), name="phi"), _stream())
+    if st < 0:
+        raise PMError(st, f"pm_solve_fft_noalloc(n={n}) failed")
+    return st
 
 
 def pm_gradient(ctx: Context, phi, g, points=5):
