@@ -10,7 +10,9 @@ Contents
            gradient, interpolation, kick-drift-kick (paper Sects. 3.1-3.8)
   mg       FP64 multigrid V-cycle following the paper's steps (Sects. 3.6-3.7)
   adjoint  vector-Jacobian products of the above and the reverse leapfrog
+  ics      Lagrangian-perturbation-theory initial conditions (1LPT to 3LPT) and the
+           power-spectrum estimator (paper Sects. 3.3, 4)
 
 Every function is plain numpy/scipy in float64, written for readability.
 """
-from . import pm, mg, adjoint  # noqa: F401
+from . import pm, mg, adjoint, ics  # noqa: F401
