@@ -12,7 +12,9 @@ Contents
   adjoint  vector-Jacobian products of the above and the reverse leapfrog
   ics      Lagrangian-perturbation-theory initial conditions (1LPT to 3LPT) and the
            power-spectrum estimator (paper Sects. 3.3, 4)
+  gravity  background expansion with a cosmological constant, parametrised gravity
+           mu(a) and QUMOND (paper Sects. 2.3, 2.4, 3.1, 3.10)
 
 Every function is plain numpy/scipy in float64, written for readability.
 """
-from . import pm, mg, adjoint, ics  # noqa: F401
+from . import pm, mg, adjoint, ics, gravity  # noqa: F401
