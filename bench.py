@@ -98,9 +98,30 @@ def make_inputs(n, seed=3, a0=0.02):
     return np.ascontiguousarray(off), np.ascontiguousarray(cell), np.ascontiguousarray(ps.vel)
 
 
+def _host_info():
+    """Host CPU model, logical core count and memory (Linux /proc)."""
+    model, mem_gb = "unknown", None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                if line.startswith("MemTotal"):
+                    mem_gb = round(int(line.split()[1]) / 1024 ** 2, 1)
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cores": os.cpu_count(), "mem_gb": mem_gb}
+
+
 def cpu_baseline(n_sample=128, steps=6, seed=3):
-    """The FP64 oracle, as is, on a bounded sample of the same recipe (host cores)."""
+    """The FP64 oracle, as is, on a bounded sample of the same recipe, with its FFTs on
+    every host core (scipy workers; numpy's bincount and roll stay single-threaded)."""
     import numpy as np
+    import scipy.fft as sfft
 
     import icgen
     from oracle import pm as opm
@@ -109,19 +130,26 @@ def cpu_baseline(n_sample=128, steps=6, seed=3):
                                    cutoff_k=math.pi * n_sample / 2.0)
     x = ps.pos.astype(np.float64)
     v = ps.vel.astype(np.float64)
-    acc = opm.accel(x * n_sample, n_sample, a[0])
-    t = time.perf_counter()
-    for a0, a1 in zip(a[:-1], a[1:]):
-        x, v, acc = opm.kdk_step(x, v, acc, a0, a1, n_sample)
-    dt = time.perf_counter() - t
+    cores = os.cpu_count() or 1
+    with sfft.set_workers(cores):
+        acc = opm.accel(x * n_sample, n_sample, a[0])
+        t = time.perf_counter()
+        for a0, a1 in zip(a[:-1], a[1:]):
+            x, v, acc = opm.kdk_step(x, v, acc, a0, a1, n_sample)
+        dt = time.perf_counter() - t
+    host = _host_info()
     return {
         "value": n_sample ** 3 * steps / dt,
         "unit": "particle-steps/s",
-        "cores": 1,
+        "cores": cores,
         "kind": "oracle",
         "sample": f"FP64 numpy/scipy oracle, {n_sample}^3 particles on a {n_sample}^3 grid, "
                   f"{steps} KDK steps from a=0.02 (same recipe, exact 7-point solve), "
-                  f"{dt:.1f}s on one host thread",
+                  f"{dt:.1f}s, scipy FFTs on {cores} threads, deposit and interpolation on one",
+        "host": host,
+        "paper_context": "the paper quotes about one CPU hour for a 512^3 Newtonian run on a "
+                         "laptop (introduction) and 15 to 25 s per 512^3 step on one CPU "
+                         "core (Sect. 4.6)",
     }
 
 
@@ -287,10 +315,9 @@ def bench_fft(n=256, reps=20):
 
 
 def stage_bytes(npart, ncell, cycles, chained=False):
-    """Algorithmic HBM bytes of each stage of one step at cell-offset positions (the
-    minimum each stage's kernels must move; multigrid: the level-0 passes of the fused
-    V-cycle, two smoothing passes of 12 B/cell, residual-restriction 8 B/cell and
-    prolongation 8 B/cell, times 8/7 for the coarser levels). With the sorted deposit
+    """Algorithmic HBM bytes of each stage of one step at cell-offset positions (what the
+    method must move, per unit of work: deposit 16 B per particle + 4 B per cell; a
+    multigrid V-cycle 82 B per cell). With the sorted deposit
     the gradient is formed inside the interpolation kernel, which then reads the
     potential (4 B/cell) instead of the force grid; the gradient stage is empty. In a
     chained step the drift is part of the interpolation pass: offsets, cell index and
@@ -298,7 +325,11 @@ def stage_bytes(npart, ncell, cycles, chained=False):
     return {
         "ms_drift": 0.0 if chained else 68.0 * npart,
         "ms_deposit": 16.0 * npart + 4.0 * ncell,
-        "ms_solve": cycles * 40.0 * ncell * 8.0 / 7.0,
+        # V-cycles of 2 + 2 sweeps at 12 B/cell each, residual-restriction and
+        # prolongation 8.5 B/cell each, all levels (x 8/7), + 8 B/cell for the finest
+        # norm: 82 B/cell per cycle; + the two sweeps of the last norm pass, whose
+        # smoothed output is kept (24 B/cell)
+        "ms_solve": (cycles * 82.0 + 24.0) * ncell,
         "ms_interp": (60.0 if chained else 52.0) * npart + 4.0 * ncell,
     }
 
@@ -449,6 +480,13 @@ def main():
             "kernel": args.roofline_kernel, "launches": k_launches,
             "avg_ms": avg_ms, "algorithmic_bytes_per_launch": per_launch_bytes,
         }
+        if args.roofline_kernel == "smooth":
+            # achieved counts 12 B/cell per red-black sweep (two per pass); the least a
+            # pass itself must move is one read of u and f and one write of u, 12 B/cell
+            minimum = 12.0 * n ** 3
+            roofline["bytes_rule"] = "12 B/cell per sweep, 2 sweeps per pass (+0.5 prolongation)"
+            roofline["pass_minimum_bytes"] = minimum
+            roofline["frac_of_pass_minimum"] = minimum / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
         _log(f"roofline {args.roofline_kernel}: {k_launches} launches, avg {avg_ms:.3f} ms, "
              f"{achieved:.0f} GB/s algorithmic")
 
@@ -485,8 +523,9 @@ def main():
         "data": "synthetic (seeded power-law Gaussian random field, Zel'dovich ICs)",
         "config": {"workload": f"{n}^3 particles on a {n}^3 grid, 50 KDK steps a=0.02->1, "
                                f"cell-offset positions, TSC {args.order} deposit, multigrid "
-                               f"2+2 RBGS growth-rescaled warm start tol {args.tol:g}, particles re-sorted "
-                               f"by tile every {args.reorder_every} steps, "
+                               f"2+2 RBGS growth-rescaled warm start, V-cycles until the FP32 "
+                               f"rounding floor (relres {args.tol:g} is below it at this size), "
+                               f"particles re-sorted by tile every {args.reorder_every} steps, "
                                + ("one pm_kdk call per step" if args.no_chain else
                                   "steps chained (kick-kick-drift fused into interpolation)"),
                    "particles": npart, "grid": n, "deposit": args.order,

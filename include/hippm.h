@@ -51,7 +51,7 @@ enum pm_status {
   PM_OK = 0,
   PM_WARN_NOT_CONVERGED = 1, /* multigrid stopped at max_cycles above tol */
   PM_WARN_FLOOR = 2,         /* multigrid reached the FP32 rounding floor above tol: below
-                                a relative residual of 1e-4 a V-cycle gained less than 4x */
+                                a relative residual of 1e-4 a V-cycle gained less than 1.5x */
   PM_ERR_ARG = -1,           /* null pointer, bad enum, negative count */
   PM_ERR_SHAPE = -2,         /* grid size or particle count not supported */
   PM_ERR_NOMEM = -3,         /* device allocation failed */
@@ -126,15 +126,42 @@ typedef struct {
                          (not filled when fixed_cycles > 0) */
 } pm_mg_stats;
 
+/* Theory of gravity of a force evaluation (Sects. 2.3, 2.4, 3.10). */
+enum pm_gravity {
+  PM_GRAVITY_NEWTON = 0,  /* lap phi = (3/2) Omega_m a (rho - mean rho) */
+  PM_GRAVITY_MU = 1,      /* parametrised: the source times mu(a) = 1 + mu0 Omega_L(a) /
+                             Omega_L0 (Eq. mu_parametrized_gravity), Omega_L0 > 0 */
+  PM_GRAVITY_QUMOND = 2   /* QUMOND: the Newtonian potential phi_N, then lap phi =
+                             div[nu(|grad phi_N| / g0) grad phi_N] discretised on cell
+                             faces as Eq. QUMOND_Poisson_MOND_discrete; multigrid or
+                             FFT_7pt solver */
+};
+/* QUMOND interpolating functions nu(y) (Sect. 2.3): simple 1/2 + sqrt(1 + 4/y) / 2; the
+ * n-family [1/2 + sqrt(1 + 4/y^n) / 2]^(1/n); the beta-family (1 - e^-y)^-1/2 + beta e^-y;
+ * the gamma-family (1 - e^(-y^(g/2)))^(-1/g) + (1 - 1/g) e^(-y^(g/2)); the delta-family
+ * (1 - e^(-y^(d/2)))^(-1/d). mond_param is n, beta, gamma or delta. */
+enum pm_nu { PM_NU_SIMPLE = 0, PM_NU_N = 1, PM_NU_BETA = 2, PM_NU_GAMMA = 3, PM_NU_DELTA = 4 };
+
 typedef struct {
   int mas;            /* pm_mas for deposit and interpolation */
   int order;          /* pm_order of the deposit */
   int solver;         /* pm_solver */
   int fft_deconv;     /* FFT and FULL_FFT solvers: window power to deconvolve (0 none,
                          1 NGP, 2 CIC, 3 TSC) */
-  double omega_m;     /* matter density parameter (1 = Einstein-de Sitter) */
+  double omega_m;     /* matter density parameter today (1 = Einstein-de Sitter) */
   pm_mg_params mg;
   int timing;         /* 1: record per-stage times into pm_step_stats (adds events) */
+  /* Background and gravity (Sects. 2.3, 2.4, 3.1, 3.10). The supercomoving time of a
+   * step a0 -> a1 is the integral of da / sqrt(Omega_m a^3 + Omega_k a^4 + Omega_L a^6),
+   * Omega_k = 1 - Omega_m - Omega_L (Einstein-de Sitter: 2 (a0^-1/2 - a1^-1/2)). */
+  double omega_l;     /* cosmological constant today (0 = Einstein-de Sitter) */
+  int gravity;        /* pm_gravity */
+  int mond_family;    /* pm_nu (QUMOND) */
+  double mu0;         /* PM_GRAVITY_MU: the coupling today */
+  double mond_g0;     /* PM_GRAVITY_QUMOND: acceleration scale g0 (> 0) in the code's
+                         supercomoving units, used as g0 a^mond_g0_exp */
+  double mond_g0_exp; /* exponent N of the time-dependent scale g0 a^N (paper default 0) */
+  double mond_param;  /* n, beta, gamma or delta of the nu family */
 } pm_step_params;
 
 typedef struct {
@@ -144,8 +171,15 @@ typedef struct {
 
 /* Default parameters: TSC, atomic deposit, multigrid 2/2 sweeps, omega 1,
  * tol 1e-6 (alpha 0), 50 V cycles, full-weighting restriction, Jacobi guess,
- * Omega_m 1. */
+ * Omega_m 1, Omega_L 0, Newtonian gravity. */
 void pm_default_step_params(pm_step_params *p);
+
+/* Supercomoving time between scale factors a0 < a1 (Sect. 3.1: dt~ = H0 dt / a^2) for
+ * matter Omega_m, a cosmological constant Omega_L and curvature 1 - Omega_m - Omega_L:
+ * the integral of da / sqrt(Omega_m a^3 + Omega_k a^4 + Omega_L a^6) (composite
+ * Gauss-Legendre quadrature in FP64; the closed form in Einstein-de Sitter). The step
+ * functions take their tau from it. Returns NaN for invalid arguments. Host only. */
+double pm_supercomoving_time(double omega_m, double omega_l, double a0, double a1);
 
 /* Create a context for an n^3 grid and up to np_max particles.
  * n must be even, 8 <= n <= 1024, and halving n while it exceeds 16 and is a
@@ -393,6 +427,44 @@ int pm_ic_state(pm_ctx *ctx, const float *q, const float *psi, int64_t np, doubl
 int pm_ic_vjp(pm_ctx *ctx, const float *pos_bar, const float *vel_bar, int64_t np, double a0,
               float *psi_bar, pm_stream stream);
 
+/* ------------------------------------------------------------------ initial conditions
+ * and the power spectrum */
+
+/* Initial conditions by Lagrangian perturbation theory (Sect. 3.3, Eqs. x_ini_LPT and
+ * v_ini_LPT; growth factors of App. A in Einstein-de Sitter) for np = n^3 particles on
+ * the lattice of cell centres, particle p = (i n + j) n + k at ((i, j, k) + 1/2) / n.
+ *   noise: [n][n][n] white noise, N(0, 1) per cell (the caller draws it; device);
+ *   k_tab, p_tab: host table of the linear P(k) at a = 1 (k = 2 pi m in the unit box,
+ *     ascending, 2 .. 65536 points), interpolated linearly in log k - log P and held
+ *     constant beyond its ends; DFT[delta] = sqrt(n^3) sqrt(P(k)) DFT[noise], with the
+ *     k = 0 mode and the Nyquist planes zero;
+ *   order 1 (Zel'dovich), 2 or 3: Psi = a Psi(1) - 3/7 a^2 Psi(2) - 1/3 a^3 Psi(3a)
+ *     + 10/21 a^3 Psi(3b) - 1/7 a^3 Psi(3c), the Psi(k) from Fourier-space derivatives
+ *     of delta as the paper writes them; velocities in supercomoving units
+ *     v = a^(1/2) sum k D^(k) Psi^(k) (an order-k term grows as a^k);
+ *   dealias 1: products of fields formed on a 2n grid from zero-padded spectra and
+ *     truncated back (free of aliasing for the quadratic and cubic terms; the paper uses
+ *     Orszag's 3/2 rule, which this equals for the quadratic ones); 0: on the n grid;
+ *   pos [np][3]: box units (cell == NULL) or in-cell offsets with cell [np]; vel [np][3].
+ * n must be a power of two (2n <= 1024 with dealiasing). The call allocates its working
+ * fields (up to 12 grids of (2n)^3 floats at third order) for its own duration and
+ * synchronises the stream before it returns. Errors: PM_ERR_ARG, PM_ERR_SHAPE,
+ * PM_ERR_NOMEM, PM_ERR_HIP. */
+int pm_ic_lpt(pm_ctx *ctx, const float *noise, int ntab, const double *k_tab,
+              const double *p_tab, int order, int dealias, double a0, float *pos,
+              int32_t *cell, float *vel, pm_stream stream);
+
+/* Power spectrum of a density grid (the estimator behind the paper's Sect. 4 results):
+ * delta = rho / mean(rho) - 1, delta_k = DFT[delta] / n^3 divided by the window
+ * W = prod_d sinc(k_d h / 2)^deconv (deconv 0 .. 3, the deposit's p), and
+ *   pk[b - 1] = mean of |delta_k|^2 over the modes of shell b = rint(|m|), b = 1 .. nbins,
+ * counting the whole sphere of wavevectors (a half-spectrum mode with 0 < k_z < n/2
+ * counts twice). kmean (may be NULL) receives the mean |k| = 2 pi |m| per shell, nmodes
+ * (may be NULL) the number of modes; empty shells give 0. Host outputs of nbins
+ * entries (1 .. 1024); the call synchronises the stream. n must be a power of two. */
+int pm_power_spectrum(pm_ctx *ctx, const float *rho, int deconv, int nbins, double *pk,
+                      double *kmean, int64_t *nmodes, pm_stream stream);
+
 /* ------------------------------------------------------------------ batched ensembles
  * Many independent periodic boxes of different grid sizes advanced together
  * (the paper's purpose is large suites of simulations; introduction and
@@ -459,7 +531,8 @@ int pm_tune(pm_batch *batch, float *pos, float *phi, const pm_step_params *param
  *                      pass and the gather pass, or the cell gather);
  *                      algorithmic bytes 12 per particle + 4 per cell
  *   PM_KERNEL_SMOOTH   the streaming smoother on the finest grid (n >= 256);
- *                      algorithmic bytes 12 per cell per pass, 12.5 for the
+ *                      algorithmic bytes 12 per cell per red-black sweep (a pass
+ *                      fuses two sweeps: 24 per cell), + 0.5 per cell for the
  *                      post-smoothing pass that adds the prolongation
  *   PM_KERNEL_INTERP   interpolation (+ kick) in pm_accel/pm_kdk/pm_kdk_chain;
  *                      algorithmic bytes 48 per particle (+4 with cell indices)

@@ -123,52 +123,150 @@ __global__ __launch_bounds__(kThreads) void k_deposit_vjp(const float *__restric
   pos_bar[3 * p + 2] += scale * gz;
 }
 
-// pos_bar[p] += scale * n * sum_c grad_u W (g_c . lam_p)   (the position term of interp^T)
-// g_bar[c]   += W lam_p                                     (the grid term: a 3-component deposit)
+// Transpose of the interpolation, per particle p:
+//   pos_bar[p] += scale * n * sum_c grad_u W (g_c . lam_p)   (the position term)
+//   g_bar[c]   += W lam_p                                     (the grid term: a 3-component deposit)
+// for a chunk of kVChunk consecutive particles per workgroup: the grid term is first
+// summed in an LDS box of the chunk's cells (grown by the window's reach) with
+// LDS atomics, then added to g_bar with one global atomic per component and touched
+// cell (about 11 per particle for particles in lattice or cell order, instead of 81).
+// A chunk spread over more than kVTable cells adds every weight with a global atomic.
+constexpr int kVThreads = 256;
+constexpr int kVPPT = 4;                    // particles per thread
+constexpr int kVChunk = kVThreads * kVPPT;  // particles per workgroup
+constexpr int kVTable = 4096;               // cells of the chunk box in LDS (3 floats each)
+
+__device__ __forceinline__ int min_image(int d, int n) { return wrap_any(d + n / 2, n) - n / 2; }
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
 template <int MAS, int PK>
-__global__ __launch_bounds__(kThreads) void k_interp_vjp(const float *__restrict__ pos,
-                                                         const int32_t *__restrict__ cell,
-                                                         int64_t np, int n,
-                                                         const float *__restrict__ g,
-                                                         const float *__restrict__ lam,
-                                                         float pscale, float gscale,
-                                                         float *__restrict__ g_bar,
-                                                         float *__restrict__ pos_bar) {
-  const int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
-  if (p >= np) return;
-  int f[3];
-  float w[3][MAS], dw[3][MAS];
-  support_wdw<MAS, PK>(pos, cell, p, n, f, w, dw);
-  const float l0 = lam[3 * p + 0], l1 = lam[3 * p + 1], l2 = lam[3 * p + 2];
-  float gx = 0.f, gy = 0.f, gz = 0.f;
+__global__ __launch_bounds__(kVThreads) void k_interp_vjp_chunk(
+    const float *__restrict__ pos, const int32_t *__restrict__ cell, int64_t np, int n,
+    const float *__restrict__ g, const float *__restrict__ lam, float pscale, float gscale,
+    float *__restrict__ g_bar, float *__restrict__ pos_bar) {
+  __shared__ float box[3 * kVTable];
+  __shared__ int red[6][kVThreads / 64];
+  const int64_t base = (int64_t)blockIdx.x * kVChunk;
+  int ref[3];
+  {
+    float w[3][MAS], dw[3][MAS];
+    support_wdw<MAS, PK>(pos, cell, base, n, ref, w, dw);
+  }
+  // window support of each of the thread's particles, relative to the chunk's first
+  int rf[kVPPT][3];
+  float w[kVPPT][3][MAS], dw[kVPPT][3][MAS];
+  bool live[kVPPT];
+  int lo[3] = {n, n, n}, hi[3] = {-n, -n, -n};
 #pragma unroll
-  for (int a = 0; a < MAS; ++a) {
-    const size_t ia = (size_t)wrap_index(f[0] + a, n) * n;
+  for (int m = 0; m < kVPPT; ++m) {
+    const int64_t p = base + threadIdx.x + (int64_t)m * kVThreads;
+    live[m] = p < np;
+    int f[3] = {0, 0, 0};
+    if (live[m]) support_wdw<MAS, PK>(pos, cell, p, n, f, w[m], dw[m]);
 #pragma unroll
-    for (int b = 0; b < MAS; ++b) {
-      const size_t row = (ia + wrap_index(f[1] + b, n)) * n;
-#pragma unroll
-      for (int c = 0; c < MAS; ++c) {
-        const size_t cc = row + wrap_index(f[2] + c, n);
-        if (pos_bar) {
-          const float gl = g[3 * cc] * l0 + g[3 * cc + 1] * l1 + g[3 * cc + 2] * l2;
-          gx = fmaf(dw[0][a] * w[1][b] * w[2][c], gl, gx);
-          gy = fmaf(w[0][a] * dw[1][b] * w[2][c], gl, gy);
-          gz = fmaf(w[0][a] * w[1][b] * dw[2][c], gl, gz);
-        }
-        if (g_bar) {
-          const float wt = gscale * w[0][a] * w[1][b] * w[2][c];
-          unsafeAtomicAdd(&g_bar[3 * cc + 0], wt * l0);
-          unsafeAtomicAdd(&g_bar[3 * cc + 1], wt * l1);
-          unsafeAtomicAdd(&g_bar[3 * cc + 2], wt * l2);
-        }
+    for (int a = 0; a < 3; ++a) {
+      rf[m][a] = min_image(f[a] - ref[a], n);
+      if (live[m]) {
+        lo[a] = min(lo[a], rf[m][a]);
+        hi[a] = max(hi[a], rf[m][a]);
       }
     }
   }
-  if (pos_bar) {
-    pos_bar[3 * p + 0] += pscale * gx;
-    pos_bar[3 * p + 1] += pscale * gy;
-    pos_bar[3 * p + 2] += pscale * gz;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int l = wave_min(lo[a]), h = wave_max(hi[a]);
+    if (lane == 0) {
+      red[a][wave] = l;
+      red[3 + a][wave] = h;
+    }
+  }
+  __syncthreads();
+  int ext[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    int l = red[a][0], h = red[3 + a][0];
+    for (int q = 1; q < kVThreads / 64; ++q) {
+      l = min(l, red[a][q]);
+      h = max(h, red[3 + a][q]);
+    }
+    lo[a] = l;
+    ext[a] = h - l + MAS;
+  }
+  const int vol = ext[0] * ext[1] * ext[2];
+  const bool in_lds = vol <= kVTable;
+  if (in_lds) {
+    for (int i = threadIdx.x; i < 3 * vol; i += kVThreads) box[i] = 0.0f;
+    __syncthreads();
+  }
+#pragma unroll 1
+  for (int m = 0; m < kVPPT; ++m) {
+    if (!live[m]) continue;
+    const int64_t p = base + threadIdx.x + (int64_t)m * kVThreads;
+    const float l0 = lam[3 * p + 0], l1 = lam[3 * p + 1], l2 = lam[3 * p + 2];
+    float gx = 0.f, gy = 0.f, gz = 0.f;
+#pragma unroll
+    for (int a = 0; a < MAS; ++a) {
+      const size_t ia = (size_t)wrap_any(ref[0] + rf[m][0] + a, n) * n;
+#pragma unroll
+      for (int b = 0; b < MAS; ++b) {
+        const size_t row = (ia + wrap_any(ref[1] + rf[m][1] + b, n)) * n;
+        const int lrow = ((rf[m][0] - lo[0] + a) * ext[1] + (rf[m][1] - lo[1] + b)) * ext[2] +
+                         (rf[m][2] - lo[2]);
+#pragma unroll
+        for (int c = 0; c < MAS; ++c) {
+          const size_t cc = row + wrap_any(ref[2] + rf[m][2] + c, n);
+          if (pos_bar) {
+            const float gl = g[3 * cc] * l0 + g[3 * cc + 1] * l1 + g[3 * cc + 2] * l2;
+            gx = fmaf(dw[m][0][a] * w[m][1][b] * w[m][2][c], gl, gx);
+            gy = fmaf(w[m][0][a] * dw[m][1][b] * w[m][2][c], gl, gy);
+            gz = fmaf(w[m][0][a] * w[m][1][b] * dw[m][2][c], gl, gz);
+          }
+          if (g_bar) {
+            const float wt = gscale * w[m][0][a] * w[m][1][b] * w[m][2][c];
+            if (in_lds) {
+              float *bx = box + 3 * (lrow + c);
+              atomicAdd(bx + 0, wt * l0);
+              atomicAdd(bx + 1, wt * l1);
+              atomicAdd(bx + 2, wt * l2);
+            } else {
+              unsafeAtomicAdd(&g_bar[3 * cc + 0], wt * l0);
+              unsafeAtomicAdd(&g_bar[3 * cc + 1], wt * l1);
+              unsafeAtomicAdd(&g_bar[3 * cc + 2], wt * l2);
+            }
+          }
+        }
+      }
+    }
+    if (pos_bar) {
+      pos_bar[3 * p + 0] += pscale * gx;
+      pos_bar[3 * p + 1] += pscale * gy;
+      pos_bar[3 * p + 2] += pscale * gz;
+    }
+  }
+  if (!in_lds || !g_bar) return;
+  __syncthreads();
+  const int e12 = ext[1] * ext[2];
+  for (int t = threadIdx.x; t < vol; t += kVThreads) {
+    const float v0 = box[3 * t], v1 = box[3 * t + 1], v2 = box[3 * t + 2];
+    if (v0 == 0.0f && v1 == 0.0f && v2 == 0.0f) continue;
+    const int x = t / e12, r = t - x * e12;
+    const int y = r / ext[2], z = r - y * ext[2];
+    const size_t gc = ((size_t)wrap_any(ref[0] + lo[0] + x, n) * n +
+                       wrap_any(ref[1] + lo[1] + y, n)) * n + wrap_any(ref[2] + lo[2] + z, n);
+    unsafeAtomicAdd(&g_bar[3 * gc + 0], v0);
+    unsafeAtomicAdd(&g_bar[3 * gc + 1], v1);
+    unsafeAtomicAdd(&g_bar[3 * gc + 2], v2);
   }
 }
 
@@ -345,22 +443,18 @@ hipError_t launch_interp_vjp(const float *pos, const int32_t *cell, int64_t np, 
                              int mas, int n, const float *g, const float *lam, float pscale,
                              float gscale, float *g_bar, float *pos_bar, hipStream_t s) {
   if (np == 0) return hipSuccess;
-  const unsigned nb = blocks_for(np, kThreads);
+  const unsigned nb = blocks_for(np, kVChunk);
+#define PM_IV(M, K)                                                                              \
+  k_interp_vjp_chunk<M, K><<<nb, kVThreads, 0, s>>>(pos, cell, np, n, g, lam, pscale, gscale,     \
+                                                     g_bar, pos_bar)
   if (mas == PM_TSC) {
-    if (poskind == PM_POS_BOX)
-      k_interp_vjp<3, PM_POS_BOX><<<nb, kThreads, 0, s>>>(pos, cell, np, n, g, lam, pscale, gscale,
-                                                           g_bar, pos_bar);
-    else
-      k_interp_vjp<3, PM_POS_CELLOFF><<<nb, kThreads, 0, s>>>(pos, cell, np, n, g, lam, pscale,
-                                                               gscale, g_bar, pos_bar);
+    if (poskind == PM_POS_BOX) PM_IV(3, PM_POS_BOX);
+    else PM_IV(3, PM_POS_CELLOFF);
   } else {
-    if (poskind == PM_POS_BOX)
-      k_interp_vjp<2, PM_POS_BOX><<<nb, kThreads, 0, s>>>(pos, cell, np, n, g, lam, pscale, gscale,
-                                                           g_bar, pos_bar);
-    else
-      k_interp_vjp<2, PM_POS_CELLOFF><<<nb, kThreads, 0, s>>>(pos, cell, np, n, g, lam, pscale,
-                                                               gscale, g_bar, pos_bar);
+    if (poskind == PM_POS_BOX) PM_IV(2, PM_POS_BOX);
+    else PM_IV(2, PM_POS_CELLOFF);
   }
+#undef PM_IV
   return hipGetLastError();
 }
 

@@ -74,9 +74,34 @@ int check_mg(pm_ctx *ctx, const pm_mg_params *p) {
   return PM_OK;
 }
 
+int check_gravity(pm_ctx *ctx, const pm_step_params *p) {
+  if (!(p->omega_m > 0.0) || !std::isfinite(p->omega_m) || !std::isfinite(p->omega_l))
+    return pm_fail(ctx, PM_ERR_ARG, "Omega_m must be > 0 and Omega_L finite");
+  if (p->gravity != PM_GRAVITY_NEWTON && p->gravity != PM_GRAVITY_MU &&
+      p->gravity != PM_GRAVITY_QUMOND)
+    return pm_fail(ctx, PM_ERR_ARG, "bad gravity");
+  if (p->gravity == PM_GRAVITY_MU && (!std::isfinite(p->mu0) || !(p->omega_l > 0.0)))
+    return pm_fail(ctx, PM_ERR_ARG, "parametrised gravity needs a finite mu0 and Omega_L > 0");
+  if (p->gravity == PM_GRAVITY_QUMOND) {
+    if (!(p->mond_g0 > 0.0) || !std::isfinite(p->mond_g0) || !std::isfinite(p->mond_g0_exp))
+      return pm_fail(ctx, PM_ERR_ARG, "QUMOND needs g0 > 0 and a finite exponent");
+    if (p->mond_family < PM_NU_SIMPLE || p->mond_family > PM_NU_DELTA)
+      return pm_fail(ctx, PM_ERR_ARG, "bad nu family");
+    if (p->mond_family != PM_NU_SIMPLE && p->mond_family != PM_NU_BETA &&
+        !(p->mond_param > 0.0))
+      return pm_fail(ctx, PM_ERR_ARG, "the nu family's parameter must be > 0");
+    if (p->mond_family == PM_NU_BETA && !std::isfinite(p->mond_param))
+      return pm_fail(ctx, PM_ERR_ARG, "bad beta");
+    if (p->solver != PM_SOLVER_MG && p->solver != PM_SOLVER_FFT_7PT)
+      return pm_fail(ctx, PM_ERR_ARG, "QUMOND takes the multigrid or FFT_7pt solver");
+  }
+  return PM_OK;
+}
+
 int check_step(pm_ctx *ctx, const pm_step_params *p) {
   if (!p) return pm_fail(ctx, PM_ERR_ARG, "null step params");
   if (!valid_mas(p->mas)) return pm_fail(ctx, PM_ERR_ARG, "bad mas");
+  if (int g = check_gravity(ctx, p)) return g;
   if (p->order != PM_DEPOSIT_ATOMIC && p->order != PM_DEPOSIT_SORTED)
     return pm_fail(ctx, PM_ERR_ARG, "bad deposit order");
   if (p->solver != PM_SOLVER_MG && !is_fft(p->solver))
@@ -94,6 +119,8 @@ int check_step_vjp(pm_ctx *ctx, const pm_step_params *p) {
   if (!valid_mas_vjp(p->mas)) return pm_fail(ctx, PM_ERR_ARG, "reverse mode takes CIC or TSC");
   if (p->solver == PM_SOLVER_FULL_FFT)
     return pm_fail(ctx, PM_ERR_ARG, "reverse mode does not take the FULL_FFT solver");
+  if (p->gravity == PM_GRAVITY_QUMOND)
+    return pm_fail(ctx, PM_ERR_ARG, "reverse mode does not take QUMOND");
   return PM_OK;
 }
 
@@ -201,13 +228,38 @@ int accel_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, i
   int st = deposit_impl(ctx, pos, cell, np, poskind, p->mas, p->order, ctx->rho, s, &mean_ready);
   if (st != PM_OK) return st;
   if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[2], s));
-  const float coef = (float)(1.5 * a * p->omega_m);
+  const float coef = (float)pm_bg_coef(p, a);
   const bool full_fft = p->solver == PM_SOLVER_FULL_FFT;
-  // FULL_FFT: the force grid comes straight from Fourier space (no potential, no stencil)
-  const int sst = full_fft ? pm_fft_solve_kind(ctx, ctx->rho, coef, p->fft_deconv, PM_FFT_FULL,
-                                               ctx->g, s, mean_ready ? ctx->mean_f : nullptr)
-                           : solve_impl(ctx, p, ctx->rho, coef, phi, stats ? &stats->mg : nullptr,
-                                        s, warm_scale, mean_ready);
+  int sst;
+  if (full_fft) {
+    // FULL_FFT: the force grid comes straight from Fourier space (no potential, no stencil)
+    sst = pm_fft_solve_kind(ctx, ctx->rho, coef, p->fft_deconv, PM_FFT_FULL, ctx->g, s,
+                            mean_ready ? ctx->mean_f : nullptr);
+  } else if (p->gravity == PM_GRAVITY_QUMOND) {
+    // QUMOND: the Newtonian potential (warm-started from the previous one), the MOND
+    // source on the cell faces, and the MOND potential (phi, warm-started as usual)
+    const size_t bytes = sizeof(float) * (size_t)ctx->n * ctx->n * ctx->n;
+    if (!ctx->mond_phin) {
+      if (hipMalloc(&ctx->mond_phin, bytes) != hipSuccess ||
+          hipMalloc(&ctx->mond_src, bytes) != hipSuccess)
+        return pm_fail(ctx, PM_ERR_NOMEM, "QUMOND scratch allocation failed");
+      ctx->mond_valid = false;
+    }
+    pm_step_params pn = *p;
+    if (!ctx->mond_valid) pn.mg.guess = PM_GUESS_JACOBI;
+    sst = solve_impl(ctx, &pn, ctx->rho, coef, ctx->mond_phin, nullptr, s, warm_scale,
+                     mean_ready);
+    if (sst < 0) return sst;
+    ctx->mond_valid = true;
+    const double g0 = p->mond_g0 * std::pow(a, p->mond_g0_exp);
+    PM_HIP(ctx, launch_qumond_source(ctx->mond_phin, ctx->n, (float)g0, p->mond_family,
+                                     (float)p->mond_param, ctx->mond_src, s));
+    sst = solve_impl(ctx, p, ctx->mond_src, 1.0f, phi, stats ? &stats->mg : nullptr, s,
+                     warm_scale, false);
+  } else {
+    sst = solve_impl(ctx, p, ctx->rho, coef, phi, stats ? &stats->mg : nullptr, s, warm_scale,
+                     mean_ready);
+  }
   if (sst < 0) return sst;
   if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[3], s));
   // with the tile buckets of these positions (sorted deposit on tiles), the gradient is
@@ -271,11 +323,14 @@ int ensure_adjoint_scratch(pm_ctx *ctx) {
   if (ctx->adj_gbar) return PM_OK;
   const size_t ncell = (size_t)ctx->n * ctx->n * ctx->n;
   if (hipMalloc(&ctx->adj_gbar, 3 * sizeof(float) * ncell) != hipSuccess ||
-      hipMalloc(&ctx->adj_phibar, sizeof(float) * ncell) != hipSuccess) {
+      hipMalloc(&ctx->adj_phibar, sizeof(float) * ncell) != hipSuccess ||
+      hipMalloc(&ctx->adj_rhobar, sizeof(float) * ncell) != hipSuccess) {
     if (ctx->adj_gbar) (void)hipFree(ctx->adj_gbar);
-    ctx->adj_gbar = nullptr;
+    if (ctx->adj_phibar) (void)hipFree(ctx->adj_phibar);
+    ctx->adj_gbar = ctx->adj_phibar = nullptr;
     return pm_fail(ctx, PM_ERR_NOMEM, "adjoint scratch allocation failed");
   }
+  ctx->adj_warm = false;
   return PM_OK;
 }
 
@@ -296,19 +351,32 @@ int accel_vjp_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t n
   // phi_bar = sum_d D_d g_bar_d
   PM_HIP(ctx, launch_divergence(ctx->adj_gbar, n, 5, false, ctx->adj_phibar, s));
   // rho_bar = coef L^+ (phi_bar - mean): the solve is self-adjoint
-  const float coef = (float)(1.5 * a * p->omega_m);
+  const double coefd = pm_bg_coef(p, a);
+  const float coef = (float)coefd;
+  float *rho_bar = ctx->adj_rhobar;
   int sst;
   if (p->solver == PM_SOLVER_FFT) {
-    sst = pm_fft_solve(ctx, ctx->adj_phibar, coef, p->fft_deconv, ctx->rho, s);
+    sst = pm_fft_solve(ctx, ctx->adj_phibar, coef, p->fft_deconv, rho_bar, s);
   } else if (p->solver == PM_SOLVER_FFT_7PT) {
-    sst = pm_fft_solve_kind(ctx, ctx->adj_phibar, coef, 0, PM_FFT_7PT, ctx->rho, s);
+    sst = pm_fft_solve_kind(ctx, ctx->adj_phibar, coef, 0, PM_FFT_7PT, rho_bar, s);
   } else {
+    // tolerance-driven solves start from the previous adjoint solve, rescaled by the
+    // ratio of the source coefficients (the cotangents of consecutive reversed steps
+    // change little); a fixed cycle count starts from the Jacobi guess, so that its
+    // result does not depend on the calls before it
     pm_mg_params mg = p->mg;
-    mg.guess = PM_GUESS_JACOBI;
-    sst = pm_mg_solve(ctx, ctx->adj_phibar, coef, ctx->rho, &mg, stats, s, 1.0f);
+    const bool warm = ctx->adj_warm && mg.fixed_cycles == 0 && ctx->adj_coef != 0.0;
+    mg.guess = warm ? PM_GUESS_WARM : PM_GUESS_JACOBI;
+    sst = pm_mg_solve(ctx, ctx->adj_phibar, coef, rho_bar, &mg, stats, s,
+                      warm ? (float)(coefd / ctx->adj_coef) : 1.0f);
   }
-  if (sst < 0) return sst;
-  PM_HIP(ctx, launch_deposit_vjp(pos, cell, np, poskind, p->mas, n, ctx->rho,
+  if (sst < 0) {
+    ctx->adj_warm = false;
+    return sst;
+  }
+  ctx->adj_warm = true;
+  ctx->adj_coef = coefd;
+  PM_HIP(ctx, launch_deposit_vjp(pos, cell, np, poskind, p->mas, n, rho_bar,
                                  scale * mass * (float)n, pos_bar, s));
   return sst;
 }
@@ -336,6 +404,13 @@ void pm_default_step_params(pm_step_params *p) {
   p->mg.alpha = 0.0f;
   p->mg.cycle = PM_CYCLE_V;
   p->timing = 0;
+  p->omega_l = 0.0;
+  p->gravity = PM_GRAVITY_NEWTON;
+  p->mond_family = PM_NU_SIMPLE;
+  p->mu0 = 0.0;
+  p->mond_g0 = 0.0;
+  p->mond_g0_exp = 0.0;
+  p->mond_param = 1.0;
 }
 
 int pm_create(pm_ctx **out, int n, int64_t np_max, int flags) {
@@ -404,6 +479,9 @@ void pm_destroy(pm_ctx *ctx) {
   fr(ctx->cell_count2);
   fr(ctx->adj_gbar);
   fr(ctx->adj_phibar);
+  fr(ctx->adj_rhobar);
+  fr(ctx->mond_phin);
+  fr(ctx->mond_src);
   for (int i = 0; i < 8; ++i)
     if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
   for (int i = 0; i < 2 * ctx->kt_cap; ++i) (void)hipEventDestroy(ctx->kt_ev[i]);
@@ -593,7 +671,8 @@ int pm_kdk(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, int64_t np, int p
     return pm_fail(ctx, PM_ERR_ARG, "scale factors must be > 0");
   hipStream_t s = (hipStream_t)stream;
   const bool timing = params->timing && stats;
-  const double tau = 2.0 * (1.0 / std::sqrt(a0) - 1.0 / std::sqrt(a1));
+  const double tau = pm_bg_tau(params->omega_m, params->omega_l, a0, a1);
+  if (!std::isfinite(tau)) return pm_fail(ctx, PM_ERR_ARG, "the background has no real time step");
   const float half = (float)(0.5 * tau);
   if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[0], s));
   // with the sorted deposit on tiles, the drift also makes the tile histogram of the new
@@ -611,9 +690,9 @@ int pm_kdk(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, int64_t np, int p
   PM_HIP(ctx, launch_kick_drift(pos, cell, vel, acc, np, poskind, ctx->n, half, (float)tau, s,
                                 pcell, count));
   ctx->hist_ready = fuse_hist;
-  // growth rescaling of the previous potential: phi~ grows as a D(a) = a^2 in EdS
-  const float warm_scale =
-      params->mg.guess == PM_GUESS_WARM_RESCALED ? (float)((a1 / a0) * (a1 / a0)) : 1.0f;
+  // growth rescaling of the previous potential: phi~ grows as a D(a) (a^2 in EdS)
+  const float warm_scale = params->mg.guess == PM_GUESS_WARM_RESCALED
+                               ? (float)pm_bg_warm_scale(params, a0, a1) : 1.0f;
   st = accel_impl(ctx, pos, cell, np, poskind, a1, params, phi, acc, vel, half, stats, s, timing,
                   warm_scale, nullptr);
   if (st >= 0 && timing) fill_timing(ctx, stats, true);
@@ -637,7 +716,8 @@ int pm_kdk_chain(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, int64_t np,
   const bool more = a2 > a1;
   hipStream_t s = (hipStream_t)stream;
   const bool timing = params->timing && stats;
-  const double tau = 2.0 * (1.0 / std::sqrt(a0) - 1.0 / std::sqrt(a1));
+  const double tau = pm_bg_tau(params->omega_m, params->omega_l, a0, a1);
+  if (!std::isfinite(tau)) return pm_fail(ctx, PM_ERR_ARG, "the background has no real time step");
   const float half = (float)(0.5 * tau);
   if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[0], s));
   if (stage == PM_CHAIN_FIRST) {
@@ -656,11 +736,11 @@ int pm_kdk_chain(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, int64_t np,
                                   pcell, count));
     ctx->hist_ready = fuse_hist;
   }
-  const float warm_scale =
-      params->mg.guess == PM_GUESS_WARM_RESCALED ? (float)((a1 / a0) * (a1 / a0)) : 1.0f;
+  const float warm_scale = params->mg.guess == PM_GUESS_WARM_RESCALED
+                               ? (float)pm_bg_warm_scale(params, a0, a1) : 1.0f;
   ChainNext next{};
   if (more) {
-    const double tau2 = 2.0 * (1.0 / std::sqrt(a1) - 1.0 / std::sqrt(a2));
+    const double tau2 = pm_bg_tau(params->omega_m, params->omega_l, a1, a2);
     next.kick = (float)(0.5 * tau2);
     next.dt = (float)tau2;
   }
@@ -748,9 +828,11 @@ int pm_kdk_adjoint(pm_ctx *ctx, const float *pos0, const int32_t *cell0, const f
   st = ensure_adjoint_scratch(ctx);
   if (st != PM_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  // supercomoving time of Einstein-de Sitter (Sect. 3.1): tau = 2 (a0^-1/2 - a1^-1/2)
-  const double tau = 2.0 * (1.0 / std::sqrt(a0) - 1.0 / std::sqrt(a1));
-  const double tau_prev = a_prev > 0.0 ? 2.0 * (1.0 / std::sqrt(a_prev) - 1.0 / std::sqrt(a0)) : 0.0;
+  // supercomoving time steps of the background (Sect. 3.1)
+  const double tau = pm_bg_tau(params->omega_m, params->omega_l, a0, a1);
+  const double tau_prev = a_prev > 0.0 ? pm_bg_tau(params->omega_m, params->omega_l, a_prev, a0) : 0.0;
+  if (!std::isfinite(tau) || !std::isfinite(tau_prev))
+    return pm_fail(ctx, PM_ERR_ARG, "the background has no real time step");
   const double kick0 = 0.5 * (tau + tau_prev);
   pm_mg_stats *ms = stats ? &stats->mg : nullptr;
   int worst = PM_OK;

@@ -39,7 +39,7 @@ struct BoxDev {
 struct StepDev {
   float half;   // tau / 2
   float dt;     // tau
-  float coef;   // 1.5 a1 Omega_m (source coefficient at the end of the step)
+  float coef;   // (3/2) Omega_m a1 mu(a1) (source coefficient at the end of the step)
   float warm;   // warm-start factor (a1 / a0)^2, or 1
 };
 
@@ -834,6 +834,11 @@ int check_batch_params(pm_batch *B, const pm_step_params *p) {
   if (!p) return bfail(B, PM_ERR_ARG, "null step params");
   if (p->mas != PM_TSC && p->mas != PM_CIC) return bfail(B, PM_ERR_ARG, "bad mas");
   if (p->solver != PM_SOLVER_MG) return bfail(B, PM_ERR_ARG, "batched runs use the multigrid solver");
+  if (p->gravity == PM_GRAVITY_QUMOND)
+    return bfail(B, PM_ERR_ARG, "batched runs take Newtonian or parametrised gravity");
+  if (!(p->omega_m > 0.0) || !std::isfinite(p->omega_l) ||
+      (p->gravity == PM_GRAVITY_MU && !(p->omega_l > 0.0)))
+    return bfail(B, PM_ERR_ARG, "bad background or gravity parameters");
   if (p->mg.fixed_cycles < 1 || p->mg.fixed_cycles > 64)
     return bfail(B, PM_ERR_ARG, "batched runs need mg.fixed_cycles in [1, 64]");
   if (p->mg.pre < 0 || p->mg.post < 0 || p->mg.pre > 16 || p->mg.post > 16)
@@ -883,9 +888,9 @@ int upload_steps(pm_batch *B, const double *a, int nsteps, const pm_step_params 
   if (st != PM_OK) return st;
   for (int i = 0; i < nsteps; ++i) {
     const double a0 = a[i], a1 = a[i + 1];
-    const double tau = 2.0 * (1.0 / std::sqrt(a0) - 1.0 / std::sqrt(a1));
-    B->steps_host[i] = StepDev{(float)(0.5 * tau), (float)tau, (float)(1.5 * a1 * p->omega_m),
-                               rescale ? (float)((a1 / a0) * (a1 / a0)) : 1.0f};
+    const double tau = pm_bg_tau(p->omega_m, p->omega_l, a0, a1);
+    B->steps_host[i] = StepDev{(float)(0.5 * tau), (float)tau, (float)pm_bg_coef(p, a1),
+                               rescale ? (float)pm_bg_warm_scale(p, a0, a1) : 1.0f};
   }
   BHIP(B, hipMemcpyAsync(B->steps, B->steps_host, sizeof(StepDev) * nsteps, hipMemcpyHostToDevice,
                          s));

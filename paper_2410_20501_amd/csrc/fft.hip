@@ -323,6 +323,33 @@ hipError_t fft_run(const FftBufs &b, int n, const float *rho, const float *mean,
   return hipGetLastError();
 }
 
+hipError_t fft_tables(const FftBufs &b, int n, int deconv, int kind, hipStream_t s) {
+  k_fft_tables<<<(n + 255) / 256, 256, 0, s>>>(b.twiddle, b.tab, n, deconv, kind);
+  return hipGetLastError();
+}
+
+hipError_t fft_forward(const FftBufs &b, int n, const float *x, const float *mean, hipStream_t s) {
+  const int P = fft_pitch(n);
+  const int Trow = TL / (n / 2), Tcol = TL / n;
+  const unsigned row_blocks = (unsigned)(((int64_t)n * n + Trow - 1) / Trow);
+  const dim3 col_grid(P / Tcol, n);
+  k_rows_r2c<<<row_blocks, FT, 0, s>>>(x, b.spec, n, P, b.twiddle, mean);
+  k_cols<1, 0><<<col_grid, FT, 0, s>>>(b.spec, b.spec, n, P, b.twiddle, b.tab, 0.0f, 0);
+  k_cols<0, 0><<<col_grid, FT, 0, s>>>(b.spec, b.spec, n, P, b.twiddle, b.tab, 0.0f, 0);
+  return hipGetLastError();
+}
+
+hipError_t fft_inverse(const FftBufs &b, int n, float *out, int stride, int comp, hipStream_t s) {
+  const int P = fft_pitch(n);
+  const int Trow = TL / (n / 2), Tcol = TL / n;
+  const unsigned row_blocks = (unsigned)(((int64_t)n * n + Trow - 1) / Trow);
+  const dim3 col_grid(P / Tcol, n);
+  k_cols<0, 2><<<col_grid, FT, 0, s>>>(b.spec, b.spec, n, P, b.twiddle, b.tab, 0.0f, 0);
+  k_cols<1, 2><<<col_grid, FT, 0, s>>>(b.spec, b.spec, n, P, b.twiddle, b.tab, 0.0f, 0);
+  k_rows_c2r<<<row_blocks, FT, 0, s>>>(b.spec, out, n, P, b.twiddle, stride, comp);
+  return hipGetLastError();
+}
+
 int pm_fft_solve_kind(pm_ctx *ctx, const float *rho, float coef, int deconv, int kind, float *out,
                       hipStream_t s, const float *mean) {
   const int n = ctx->n;

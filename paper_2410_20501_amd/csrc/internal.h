@@ -66,6 +66,14 @@ struct pm_ctx {
   // reverse mode (lazy)
   float *adj_gbar;       // [n^3 * 3] cotangent of the force grid
   float *adj_phibar;     // [n^3] cotangent of the potential
+  float *adj_rhobar;     // [n^3] cotangent of the density: the last adjoint solve's result
+  bool adj_warm;         // adj_rhobar holds a solve result (multigrid warm start)
+  double adj_coef;       // source coefficient of that solve
+  // QUMOND (lazy): the Newtonian potential (kept as the next solve's warm start) and the
+  // MOND source
+  float *mond_phin;      // [n^3]
+  float *mond_src;       // [n^3]
+  bool mond_valid;       // mond_phin holds a solution
   // timing events
   hipEvent_t ev[8];
   // per-kernel timer: event pairs around every launch of one kernel
@@ -187,6 +195,15 @@ hipError_t launch_rr_stream(const float *u, const float *f, float fscale, const 
                             int n, float inv_h2, int kind, float *fc, float *ucg, float gscale,
                             hipStream_t s);
 
+// gravity.hip: background of matter, curvature and a cosmological constant
+double pm_bg_tau(double omega_m, double omega_l, double a0, double a1);   // supercomoving time
+double pm_bg_growth(double omega_m, double omega_l, double a);            // D(a), any normalisation
+double pm_bg_coef(const pm_step_params *p, double a);       // (3/2) Omega_m a mu(a)
+double pm_bg_warm_scale(const pm_step_params *p, double a0, double a1);  // a1 D1 / (a0 D0)
+// QUMOND source div[nu(|grad phi_N| / g0) grad phi_N] on cell faces (n^3 grids)
+hipError_t launch_qumond_source(const float *phin, int n, float g0, int family, float param,
+                                float *out, hipStream_t s);
+
 // fft.hip
 struct FftBufs {
   float2 *spec, *spec2;  // half spectra [n][n][fft_pitch(n)] (spec2: PM_FFT_FULL only)
@@ -199,6 +216,13 @@ size_t fft_spec_elems(int n);
 // mean (device, may be NULL): subtracted from rho before the transform
 hipError_t fft_run(const FftBufs &b, int n, const float *rho, const float *mean, float coef,
                    int deconv, int kind, float *out, hipStream_t s);
+// separate passes over one grid: the twiddles and tables of b for an n^3 grid; the
+// forward transform of the real grid x (mean subtracted when given) into b.spec (full
+// half spectrum, unnormalised); the inverse of b.spec (consumed) into out[(p * stride) +
+// comp] (unnormalised: no 1 / n^3)
+hipError_t fft_tables(const FftBufs &b, int n, int deconv, int kind, hipStream_t s);
+hipError_t fft_forward(const FftBufs &b, int n, const float *x, const float *mean, hipStream_t s);
+hipError_t fft_inverse(const FftBufs &b, int n, float *out, int stride, int comp, hipStream_t s);
 // mean: the device mean of rho when known (the sorted deposit's), else computed here
 int pm_fft_solve(pm_ctx *ctx, const float *rho, float coef, int deconv, float *phi,
                  hipStream_t s, const float *mean = nullptr);

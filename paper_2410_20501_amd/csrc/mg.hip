@@ -432,7 +432,7 @@ inline unsigned blocks_for(int64_t count, int threads) {
 // Floor detection of the tolerance loop: below a relative residual of kFloorBelow, a
 // cycle that reduced it by less than kFloorGain ends the solve with PM_WARN_FLOOR.
 constexpr double kFloorBelow = 1e-4;
-constexpr double kFloorGain = 4.0;
+constexpr double kFloorGain = 1.5;
 
 struct Src {
   const float *f;
@@ -485,10 +485,11 @@ struct Solver {
       if (l == 0) pm_kt_begin(ctx, PM_KERNEL_SMOOTH, s);
       e = launch_smooth_stream(cur[l], alt[l], sr.f, sr.scale, sr.mean, n, h2(l), p->omega,
                                first_colour, 2 * now, partial, uscale, ec, s);
-      // algorithmic bytes of one pass (any number of fused sweeps): read u and f,
-      // write u, 4 B each per cell (+ the coarse correction, 0.5 B per fine cell)
+      // algorithmic bytes of one pass: 12 B per cell per red-black sweep (read u and f,
+      // write u), the pass fusing `now` sweeps, + the coarse correction (0.5 B per fine
+      // cell) when it is prolonged in the pass
       if (l == 0)
-        pm_kt_end(ctx, PM_KERNEL_SMOOTH, s, (ec ? 12.5 : 12.0) * (double)n * n * n);
+        pm_kt_end(ctx, PM_KERNEL_SMOOTH, s, (12.0 * now + (ec ? 0.5 : 0.0)) * (double)n * n * n);
       std::swap(cur[l], alt[l]);
       partial = nullptr;
       uscale = 1.0f;
@@ -711,8 +712,7 @@ int pm_mg_solve(pm_ctx *ctx, const float *rho, float coef, float *phi, const pm_
       } else if (cycles > 0 && rel[cycles] < kFloorBelow &&
                  rel[cycles - 1] < kFloorGain * rel[cycles]) {
         // a V-cycle removes most of the algebraic residual (about 6 to 10 times, App. C);
-        // a cycle that gained less than kFloorGain left mostly FP32 rounding behind, and
-        // the next one would gain little (measured: 1.3 times at 512^3)
+        // a cycle that gained less than kFloorGain met the FP32 rounding floor
         status = PM_WARN_FLOOR;
       }
       if (status != PM_WARN_NOT_CONVERGED || cycles == p->max_cycles) {

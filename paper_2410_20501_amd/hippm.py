@@ -26,6 +26,8 @@ PM_RESTRICT_FW, PM_RESTRICT_AVG = 0, 1
 PM_CYCLE_V, PM_CYCLE_W, PM_CYCLE_F = 0, 1, 2
 PM_SOLVER_MG, PM_SOLVER_FFT, PM_SOLVER_FFT_7PT, PM_SOLVER_FULL_FFT = 0, 1, 2, 3
 PM_FFT_GREEN, PM_FFT_7PT, PM_FFT_FULL = 0, 1, 2
+PM_GRAVITY_NEWTON, PM_GRAVITY_MU, PM_GRAVITY_QUMOND = 0, 1, 2
+PM_NU_SIMPLE, PM_NU_N, PM_NU_BETA, PM_NU_GAMMA, PM_NU_DELTA = 0, 1, 2, 3, 4
 PM_GUESS_JACOBI, PM_GUESS_WARM, PM_GUESS_WARM_RESCALED = 0, 1, 2
 PM_CHAIN_FIRST, PM_CHAIN_NEXT = 0, 1
 PM_ADJ_CLOSING_MERGED = 1
@@ -36,6 +38,9 @@ MAS = {"ngp": PM_NGP, "cic": PM_CIC, "tsc": PM_TSC}
 SOLVER = {"mg": PM_SOLVER_MG, "fft": PM_SOLVER_FFT, "fft_7pt": PM_SOLVER_FFT_7PT,
           "full_fft": PM_SOLVER_FULL_FFT}
 FFT_KERNEL = {"green": PM_FFT_GREEN, "7pt": PM_FFT_7PT, "full": PM_FFT_FULL}
+GRAVITY = {"newton": PM_GRAVITY_NEWTON, "mu": PM_GRAVITY_MU, "qumond": PM_GRAVITY_QUMOND}
+NU_FAMILY = {"simple": PM_NU_SIMPLE, "n": PM_NU_N, "beta": PM_NU_BETA, "gamma": PM_NU_GAMMA,
+             "delta": PM_NU_DELTA}
 ORDER = {"atomic": PM_DEPOSIT_ATOMIC, "sorted": PM_DEPOSIT_SORTED}
 
 
@@ -64,7 +69,10 @@ class MGStats(ctypes.Structure):
 
 class StepParams(ctypes.Structure):
     _fields_ = [("mas", c_int), ("order", c_int), ("solver", c_int), ("fft_deconv", c_int),
-                ("omega_m", c_double), ("mg", MGParams), ("timing", c_int)]
+                ("omega_m", c_double), ("mg", MGParams), ("timing", c_int),
+                ("omega_l", c_double), ("gravity", c_int), ("mond_family", c_int),
+                ("mu0", c_double), ("mond_g0", c_double), ("mond_g0_exp", c_double),
+                ("mond_param", c_double)]
 
 
 class StepStats(ctypes.Structure):
@@ -79,6 +87,7 @@ def _load():
     P = c_void_p
     sig = {
         "pm_default_step_params": (None, [POINTER(StepParams)]),
+        "pm_supercomoving_time": (c_double, [c_double, c_double, c_double, c_double]),
         "pm_create": (c_int, [POINTER(c_void_p), c_int, c_int64, c_int]),
         "pm_destroy": (None, [P]),
         "pm_last_error": (c_char_p, [P]),
@@ -110,6 +119,10 @@ def _load():
                                     POINTER(c_double), P, P]),
         "pm_ic_state": (c_int, [P, P, P, c_int64, c_double, P, P, P, P]),
         "pm_ic_vjp": (c_int, [P, P, P, c_int64, c_double, P, P]),
+        "pm_ic_lpt": (c_int, [P, P, c_int, POINTER(c_double), POINTER(c_double), c_int, c_int,
+                              c_double, P, P, P, P]),
+        "pm_power_spectrum": (c_int, [P, P, c_int, c_int, POINTER(c_double), POINTER(c_double),
+                                      POINTER(c_int64), P]),
         "pm_batch_create": (c_int, [POINTER(c_void_p), c_int, POINTER(c_int), POINTER(c_int64),
                                     c_int]),
         "pm_batch_destroy": (None, [P]),
@@ -142,6 +155,10 @@ def default_step_params(**kw) -> StepParams:
             v = ORDER.get(v, v)
         elif k == "solver":
             v = SOLVER.get(v, v)
+        elif k == "gravity":
+            v = GRAVITY.get(v, v)
+        elif k == "mond_family":
+            v = NU_FAMILY.get(v, v)
         elif k == "guess":
             v = {"jacobi": PM_GUESS_JACOBI, "warm": PM_GUESS_WARM,
                  "warm_rescaled": PM_GUESS_WARM_RESCALED}.get(v, v)
@@ -154,6 +171,11 @@ def default_step_params(**kw) -> StepParams:
         else:
             setattr(p, k, v)
     return p
+
+
+def pm_supercomoving_time(omega_m, omega_l, a0, a1):
+    """Supercomoving time between a0 and a1 for the background (host function)."""
+    return _lib.pm_supercomoving_time(float(omega_m), float(omega_l), float(a0), float(a1))
 
 
 def _stream():
@@ -460,6 +482,35 @@ def pm_ic_vjp(ctx: Context, pos_bar, vel_bar, a0, psi_bar):
                         _ptr(vel_bar, shape=(np_, 3), name="vel_bar"), np_, float(a0),
                         _ptr(psi_bar, shape=(np_, 3), name="psi_bar"), _stream())
     return ctx._check(st, "pm_ic_vjp")
+
+
+def pm_ic_lpt(ctx: Context, noise, k_tab, p_tab, a0, pos, vel, cell=None, order=2, dealias=True):
+    """Lagrangian-perturbation-theory initial conditions of the n^3 lattice (order 1..3)
+    from a white-noise grid [n, n, n] and a P(k) table (host sequences, a = 1)."""
+    n = ctx.n
+    np_ = n ** 3
+    kt = (c_double * len(k_tab))(*[float(x) for x in k_tab])
+    pt = (c_double * len(p_tab))(*[float(x) for x in p_tab])
+    if len(k_tab) != len(p_tab):
+        raise ValueError("k_tab and p_tab must have the same length")
+    st = _lib.pm_ic_lpt(ctx.handle, _ptr(noise, shape=(n, n, n), name="noise"), len(k_tab), kt,
+                        pt, int(order), 1 if dealias else 0, float(a0),
+                        _ptr(pos, shape=(np_, 3), name="pos"), _ptr(cell, torch.int32, (np_,), "cell"),
+                        _ptr(vel, shape=(np_, 3), name="vel"), _stream())
+    return ctx._check(st, "pm_ic_lpt")
+
+
+def pm_power_spectrum(ctx: Context, rho, deconv=3, nbins=None):
+    """(P, mean k, modes) per shell rint(|m|) = 1 .. nbins of delta = rho / mean - 1."""
+    n = ctx.n
+    nbins = n // 2 if nbins is None else int(nbins)
+    pk = (c_double * nbins)()
+    km = (c_double * nbins)()
+    nm = (c_int64 * nbins)()
+    st = _lib.pm_power_spectrum(ctx.handle, _ptr(rho, shape=(n, n, n), name="rho"), int(deconv),
+                                nbins, pk, km, nm, _stream())
+    ctx._check(st, "pm_power_spectrum")
+    return list(pk), list(km), list(nm)
 
 
 # ------------------------------------------------------------------ batched ensembles

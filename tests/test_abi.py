@@ -56,7 +56,11 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(pm.MGStats) == 8 + 64 * 8
     assert pm.StepParams.mg.offset == 24
     assert pm.StepParams.timing.offset == 64
-    assert ctypes.sizeof(pm.StepParams) == 72
+    assert pm.StepParams.omega_l.offset == 72
+    assert pm.StepParams.gravity.offset == 80 and pm.StepParams.mond_family.offset == 84
+    assert pm.StepParams.mond_param.offset == 112
+    assert ctypes.sizeof(pm.StepParams) == 120
     p = pm.default_step_params()
     assert (p.mas, p.mg.pre, p.mg.post, p.mg.omega, p.mg.max_cycles) == (3, 2, 2, 1.0, 50)
     assert p.mg.alpha == 0.0 and p.mg.cycle == pm.PM_CYCLE_V
+    assert p.omega_l == 0.0 and p.gravity == pm.PM_GRAVITY_NEWTON and p.mond_param == 1.0

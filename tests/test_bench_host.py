@@ -45,6 +45,8 @@ def test_stage_bytes():
     chained = b.stage_bytes(npart, ncell, cycles, chained=True)
     assert plain["ms_drift"] == 68.0 * npart and chained["ms_drift"] == 0.0
     assert plain["ms_deposit"] == chained["ms_deposit"] == 16.0 * npart + 4.0 * ncell
-    assert plain["ms_solve"] == chained["ms_solve"] == cycles * 40.0 * ncell * 8.0 / 7.0
+    # 82 B/cell per V-cycle (2 + 2 sweeps, transfers, all levels, finest norm) and the
+    # two sweeps of the last norm pass, whose output is kept
+    assert plain["ms_solve"] == chained["ms_solve"] == (cycles * 82.0 + 24.0) * ncell
     assert plain["ms_interp"] == 52.0 * npart + 4.0 * ncell
     assert chained["ms_interp"] == 60.0 * npart + 4.0 * ncell
