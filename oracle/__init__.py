@@ -14,7 +14,9 @@ Contents
            power-spectrum estimator (paper Sects. 3.3, 4)
   gravity  background expansion with a cosmological constant, parametrised gravity
            mu(a) and QUMOND (paper Sects. 2.3, 2.4, 3.1, 3.10)
+  fr       f(R) gravity (Hu-Sawicki): the scalaron by non-linear multigrid with the
+           closed-form cubic and quartic roots (paper Sects. 2.5, 3.7.2, 3.11)
 
 Every function is plain numpy/scipy in float64, written for readability.
 """
-from . import pm, mg, adjoint, ics, gravity  # noqa: F401
+from . import pm, mg, adjoint, ics, gravity, fr  # noqa: F401
