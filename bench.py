@@ -314,6 +314,84 @@ def bench_fft(n=256, reps=20):
     return out
 
 
+def bench_fr(n=512, reps=5, n_step=256, steps=3):
+    """f(R) (Hu-Sawicki n = 1, f_R0 = -1e-5, Omega_m 0.3, Omega_L 0.7, 100 Mpc/h box):
+    (1) the scalaron's FAS F cycle (the paper's one cycle per force evaluation) on an n^3
+    clustered density (log-normal, sigma 1, seeded), each cycle starting from the last,
+    with the finest non-linear Gauss-Seidel sweep timed per launch (32 algorithmic bytes
+    per cell: FP64 u read by both colour passes, s read and u written once); (2) the cost
+    of a whole f(R) step against a Newtonian one at n_step^3 particles and cells."""
+    import warnings
+
+    import torch
+
+    import icgen
+    import paper_2410_20501_amd as pm
+    warnings.simplefilter("ignore", pm.PMWarning)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(77)
+    rho = torch.exp(torch.randn((n, n, n), device="cuda", generator=gen))
+    rho /= rho.mean()
+    box = 100.0
+    p = pm.default_step_params(omega_m=0.3, omega_l=0.7, fr_f0=-1e-5, fr_n=1,
+                               fr_c2=(2997.92458 / box) ** 2)
+    ctx = pm.Context(n)
+    u = torch.ones((n, n, n), dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        pm.pm_solve_fr(ctx, rho, 0.5, p, u)
+    torch.cuda.synchronize()
+    pm.pm_kernel_timer(ctx, "fr_sweep", 64)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        pm.pm_solve_fr(ctx, rho, 0.5, p, u)
+    t1.record()
+    torch.cuda.synchronize()
+    ms_cycle = t0.elapsed_time(t1) / reps
+    kms, launches, kbytes = pm.pm_kernel_timer_read(ctx)
+    rr = pm.pm_solve_fr(ctx, rho, 0.5, p, u, relres=True)
+    ctx.close()
+    sweep_ms = kms / max(launches, 1)
+    sweep_gbs = kbytes / max(launches, 1) / (sweep_ms * 1e-3) / 1e9
+    # one F cycle: 3 sweeps + residual (24 B/cell) + restriction (16) + prolongation (16)
+    # on the finest grid; the coarser grids add about 0.3 of that
+    alg = 1.3 * (3 * 32.0 + 56.0) * n ** 3
+    out = {"workload": f"{n}^3 log-normal density (sigma 1), f(R) n=1 f_R0=-1e-5, a=0.5, one "
+                       f"FAS F cycle (2 pre + 1 post non-linear red-black sweeps, levels "
+                       f"{n} -> 4, 32 sweeps on 4^3), from the previous cycle's result",
+           "ms_per_f_cycle": ms_cycle,
+           "cycle_gbs_estimate": alg / (ms_cycle * 1e-3) / 1e9,
+           "relres_one_more_cycle": list(rr),
+           "sweep": {"avg_ms": sweep_ms, "launches": launches, "gbs": sweep_gbs,
+                     "frac": sweep_gbs / HBM_PEAK_GBS,
+                     "bytes_rule": "32 B/cell per sweep (both colours), FP64"}}
+    # whole steps: Newtonian vs f(R), same particles, multigrid, sorted deposit
+    ps = icgen.zeldovich_particles(n_step, -2.0, 0.5, 0.5, seed=78)
+    res = {}
+    for grav in ("newton", "fr"):
+        ctx = pm.Context(n_step, n_step ** 3)
+        q = pm.default_step_params(omega_m=0.3, omega_l=0.7, gravity=grav, order="sorted",
+                                   fr_f0=-1e-5, fr_c2=(2997.92458 / box) ** 2)
+        pos, vel = torch.from_numpy(ps.pos).cuda(), torch.from_numpy(ps.vel).cuda()
+        phi = torch.zeros((n_step,) * 3, device="cuda")
+        acc = torch.empty_like(pos)
+        pm.pm_accel(ctx, pos, 0.5, phi, acc, params=q)
+        q.mg.guess = pm.PM_GUESS_WARM_RESCALED
+        a_list = [0.5 + 0.01 * i for i in range(steps + 2)]
+        pm.pm_kdk(ctx, pos, vel, a_list[0], a_list[1], phi, acc, params=q)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for a0, a1 in zip(a_list[1:-1], a_list[2:]):
+            pm.pm_kdk(ctx, pos, vel, a0, a1, phi, acc, params=q)
+        torch.cuda.synchronize()
+        res[grav] = 1e3 * (time.perf_counter() - t) / steps
+        ctx.close()
+    out["step_ms"] = {"workload": f"{n_step}^3 particles and cells, LCDM, sorted TSC deposit, "
+                                  f"multigrid tol 1e-6 warm-started", **res,
+                      "fr_over_newton": res["fr"] / res["newton"]}
+    return out
+
+
 def stage_bytes(npart, ncell, cycles, chained=False):
     """Algorithmic HBM bytes of each stage of one step at cell-offset positions (what the
     method must move, per unit of work: deposit 16 B per particle + 4 B per cell; a
@@ -359,7 +437,7 @@ def main():
                     help="only run a 512 MiB device copy (HBM counter calibration)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the adjoint and batched-ensemble measurements")
-    ap.add_argument("--only", choices=["adjoint", "batched", "fft"], default=None,
+    ap.add_argument("--only", choices=["adjoint", "batched", "fft", "fr"], default=None,
                     help="run only one of the extra measurements and print its JSON object")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -373,7 +451,8 @@ def main():
     import paper_2410_20501_amd as pm
 
     if args.only:
-        res = {"adjoint": bench_adjoint, "batched": bench_batched, "fft": bench_fft}[args.only]()
+        res = {"adjoint": bench_adjoint, "batched": bench_batched, "fft": bench_fft,
+               "fr": bench_fr}[args.only]()
         print(json.dumps({args.only: res}), flush=True)
         return
 

@@ -94,7 +94,12 @@ enum pm_guess { PM_GUESS_JACOBI = 0, PM_GUESS_WARM = 1, PM_GUESS_WARM_RESCALED =
 enum pm_create_flags {
   /* Run every multigrid level with the plain one-kernel-per-half-sweep kernels
    * instead of the fused streaming kernels (a reference for testing; slower). */
-  PM_CREATE_REFERENCE_KERNELS = 1
+  PM_CREATE_REFERENCE_KERNELS = 1,
+  /* pm_accel, pm_kdk and pm_kdk_chain first count the non-finite values of the
+   * positions (and velocities) they are given, one pass over those arrays and a host
+   * synchronisation per call, and return PM_ERR_NONFINITE before any other kernel
+   * reads them (without the flag, non-finite positions are undefined behaviour) */
+  PM_CREATE_CHECK_FINITE = 2
 };
 
 /* Multigrid settings (paper Sect. 3.7.1). */
@@ -131,10 +136,14 @@ enum pm_gravity {
   PM_GRAVITY_NEWTON = 0,  /* lap phi = (3/2) Omega_m a (rho - mean rho) */
   PM_GRAVITY_MU = 1,      /* parametrised: the source times mu(a) = 1 + mu0 Omega_L(a) /
                              Omega_L0 (Eq. mu_parametrized_gravity), Omega_L0 > 0 */
-  PM_GRAVITY_QUMOND = 2   /* QUMOND: the Newtonian potential phi_N, then lap phi =
+  PM_GRAVITY_QUMOND = 2,  /* QUMOND: the Newtonian potential phi_N, then lap phi =
                              div[nu(|grad phi_N| / g0) grad phi_N] discretised on cell
                              faces as Eq. QUMOND_Poisson_MOND_discrete; multigrid or
                              FFT_7pt solver */
+  PM_GRAVITY_FR = 3       /* f(R) (Hu-Sawicki, Sects. 2.5, 3.11): the Newtonian potential
+                             phi_N (any solver but FULL_FFT) and the scalaron f~ by
+                             non-linear multigrid (pm_solve_fr); the force is the
+                             gradient of phi_N - (c~^2 / 2) f~ (F = F_N + c~^2/2 grad f~) */
 };
 /* QUMOND interpolating functions nu(y) (Sect. 2.3): simple 1/2 + sqrt(1 + 4/y) / 2; the
  * n-family [1/2 + sqrt(1 + 4/y^n) / 2]^(1/n); the beta-family (1 - e^-y)^-1/2 + beta e^-y;
@@ -162,6 +171,18 @@ typedef struct {
                          supercomoving units, used as g0 a^mond_g0_exp */
   double mond_g0_exp; /* exponent N of the time-dependent scale g0 a^N (paper default 0) */
   double mond_param;  /* n, beta, gamma or delta of the nu family */
+  /* PM_GRAVITY_FR (Sects. 2.5, 3.7.2, 3.11). Units: curvature in H0^2 / c^2, the
+   * scalaron f~ = a^2 f_R, the speed of light c~ = c / (H0 L_box) = 2997.92458 / L_box
+   * for a box of L_box Mpc/h. */
+  double fr_f0;       /* f_R0, the scalaron today (< 0) */
+  double fr_c2;       /* c~^2 (> 0) */
+  int fr_n;           /* Hu-Sawicki exponent n: 1 (cubic) or 2 (quartic) */
+  int fr_cycles;      /* FAS cycles per force evaluation (1 .. 64; paper default 1) */
+  int fr_cycle;       /* pm_cycle of the FAS (paper default PM_CYCLE_F) */
+  int fr_pre;         /* non-linear Gauss-Seidel sweeps before the coarse correction
+                         (>= 1) */
+  int fr_post;        /* ... and after it (>= 1) */
+  int fr_coarse_sweeps; /* sweeps on the coarsest FAS grid (1 .. 4096) */
 } pm_step_params;
 
 typedef struct {
@@ -184,7 +205,7 @@ double pm_supercomoving_time(double omega_m, double omega_l, double a0, double a
 /* Create a context for an n^3 grid and up to np_max particles.
  * n must be even, 8 <= n <= 1024, and halving n while it exceeds 16 and is a
  * multiple of 4 must end at most at 20 (the coarsest multigrid level).
- * flags: 0 or PM_CREATE_REFERENCE_KERNELS.
+ * flags: 0 or a combination of pm_create_flags.
  * Errors: PM_ERR_ARG, PM_ERR_SHAPE, PM_ERR_NOMEM, PM_ERR_HIP. */
 int pm_create(pm_ctx **ctx, int n, int64_t np_max, int flags);
 void pm_destroy(pm_ctx *ctx);
@@ -261,6 +282,28 @@ int pm_solve_fft_kernel(pm_ctx *ctx, const float *rho, float coef, int kernel, i
 int pm_solve_fft_noalloc(const float *rho, int n, float coef, int deconv, float *phi,
                          pm_stream stream);
 
+/* f(R) scalaron by non-linear multigrid (Sects. 3.7.2, 3.11). With
+ * u = (f~ / f~_bar)^(1/(n+1)) (1 in the background; f~_bar = a^2 f_R_bar(a),
+ * f_R_bar = (R_bar(1) / R_bar(a))^(n+1) f_R0, R_bar = 3 (Omega_m a^-3 + 4 Omega_L)) the
+ * seven-point discretisation of Eq. fr_sim_2 is, per cell,
+ *   (f~_bar / h^2) [sum of 6 neighbours of u^(n+1) - 6 u^(n+1)] - K / u = s,
+ *   K = a^4 R_bar / (3 c~^2),  s = -(Omega_m a / c~^2)(rho - mean rho) - K,
+ * which for u given its neighbours is the depressed polynomial u^(n+2) + p u + q = 0
+ * solved by the paper's closed forms (cubic for n = 1, quartic for n = 2) in FP64.
+ * Full-approximation-storage cycles (params->fr_cycle, fr_cycles of them) of red-black
+ * non-linear Gauss-Seidel (fr_pre sweeps red first, fr_post sweeps black first),
+ * full-weighting restriction of u and of the residual, coarse problem
+ * N_H(u_H) = N_H(R u) + R d, trilinear prolongation of u_H - R u; grids are halved while
+ * the side exceeds 4 and is a multiple of 4, and the coarsest gets fr_coarse_sweeps
+ * sweeps. Uses params->omega_m, omega_l and the fr_ fields.
+ * rho: device [n][n][n] density (its mean is measured). u: device FP64 [n][n][n], in =
+ * starting guess (all ones for the background), out = the result.
+ * relres: host double[2] or NULL; when given, ||s - N(u)||_2 / ||s||_2 before and after
+ * the cycles (host synchronisation). Errors: PM_ERR_ARG (bad pointer or parameter),
+ * PM_ERR_NOMEM (first call allocates the FAS levels: 32 bytes per cell in total). */
+int pm_solve_fr(pm_ctx *ctx, const float *rho, double a, const pm_step_params *params,
+                double *u, double *relres, pm_stream stream);
+
 /* Acceleration grid g = -grad phi with the central difference of the given
  * number of points (3, 5 or 7; paper gradient table). g is [n][n][n][3]. */
 int pm_gradient(pm_ctx *ctx, const float *phi, int points, float *g, pm_stream stream);
@@ -272,7 +315,11 @@ int pm_interp(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, in
 
 /* Accelerations of the particles at scale factor a: deposit, solve with
  * coef = 1.5 a Omega_m, 5-point gradient, interpolation. phi is the potential
- * (warm-start input when the multigrid guess is PM_GUESS_WARM; output). */
+ * (warm-start input when the multigrid guess is PM_GUESS_WARM; output).
+ * With PM_GRAVITY_FR phi is the Newtonian potential; the context keeps the scalaron's
+ * u (FP64, n^3), which the next evaluation starts from unless the multigrid guess is
+ * PM_GUESS_JACOBI (then from u = 1, the background), as the paper starts each step's
+ * scalaron from the previous step's without rescaling (Sect. 3.11). */
 int pm_accel(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, int poskind,
              double a, const pm_step_params *params, float *phi, float *acc,
              pm_step_stats *stats, pm_stream stream);
@@ -539,11 +586,14 @@ int pm_tune(pm_batch *batch, float *pos, float *phi, const pm_step_params *param
  *                      + 12 per cell (force grid), or + 4 per cell with the
  *                      gradient fused (sorted deposit on 8^3 tiles); in a chain,
  *                      52 per particle (+8 with cell indices) + 4 per cell
+ *   PM_KERNEL_FR_SWEEP the f(R) non-linear Gauss-Seidel sweep on the finest grid
+ *                      (both colours, FP64): algorithmic bytes 32 per cell (u read
+ *                      by each colour's pass, s read and u written once)
  * pm_kernel_timer_read synchronises on the recorded events and returns the
  * summed elapsed time, the number of launches and the summed algorithmic
  * bytes; PM_WARN_NOT_CONVERGED if launches exceeded the pool. */
 enum pm_kernel_id { PM_KERNEL_NONE = 0, PM_KERNEL_DEPOSIT = 1, PM_KERNEL_SMOOTH = 2,
-                    PM_KERNEL_INTERP = 3 };
+                    PM_KERNEL_INTERP = 3, PM_KERNEL_FR_SWEEP = 4 };
 int pm_kernel_timer(pm_ctx *ctx, int kernel, int capacity);
 int pm_kernel_timer_read(pm_ctx *ctx, double *ms, int64_t *launches, double *bytes);
 

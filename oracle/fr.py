@@ -78,12 +78,28 @@ class Coeffs:
 
 # --------------------------------------------------------------------------- roots
 
+def _stable_root_difference(d0, d1):
+    """For Delta0 < 0: with B = (-Delta0)^(3/2), sqrt(disc) = sqrt(Delta1^2 + 4 B^2) and
+    A = (|Delta1| + sqrt(disc)) / 2, returns (A^(1/3), A^(2/3) - (-Delta0)). The difference
+    is formed as (A - B)(A + B) / (A^(4/3) + A^(2/3) B^(2/3) + B^(4/3)) with
+    A - B = |Delta1| / 2 + Delta1^2 / (2 (sqrt(disc) + 2 B)): the same number, without the
+    cancellation of subtracting two nearly equal terms."""
+    B = (-d0) ** 1.5
+    sq = np.sqrt(d1 * d1 + 4.0 * B * B)
+    ad1 = np.abs(d1)
+    A = 0.5 * (ad1 + sq)
+    Q = np.cbrt(A)
+    a_minus_b = 0.5 * ad1 + 0.5 * d1 * d1 / (sq + 2.0 * B)
+    return Q, a_minus_b * (A + B) / (Q ** 4 - d0 * Q * Q + d0 * d0)
+
+
 def root_cubic(p, q):
     """Root of u^3 + p u + q = 0 by the closed forms of Sect. 3.11 (q < 0: the largest
     real root, which is positive). Where one real root exists, the cube root C is taken
-    from (Delta1 - sqrt(disc)) / 2 when Delta1 < 0: the paper's (Delta1 + sqrt(disc)) / 2
-    gives Delta0 / C in place of C and so the same root, but loses digits to
-    cancellation when p is small."""
+    from (Delta1 - sqrt(disc)) / 2 (Delta1 < 0): the paper's (Delta1 + sqrt(disc)) / 2
+    gives Delta0 / C in place of C and so the same root. For p > 0 the root
+    -(C + Delta0 / C) / 3 = (|C|^2 + Delta0) / (3 |C|) is evaluated without cancellation
+    (_stable_root_difference); the printed form loses digits when the root is small."""
     p = np.asarray(p, dtype=np.float64)
     q = np.broadcast_to(np.asarray(q, dtype=np.float64), p.shape)
     d0 = -3.0 * p
@@ -91,13 +107,13 @@ def root_cubic(p, q):
     disc = d1 * d1 - 4.0 * d0 ** 3
     out = np.empty_like(p)
     zero = p == 0.0
-    one = (~zero) & ((p > 0.0) | (disc > 0.0))
-    three = ~(zero | one)
+    pos = p > 0.0
+    one = (~zero) & (~pos) & (disc > 0.0)
+    three = ~(zero | pos | one)
     out[zero] = np.cbrt(-q[zero])
-    # C^3 = (Delta1 +- sqrt(disc)) / 2: the two signs give C and Delta0 / C, hence the
-    # same root; the sign of Delta1 (here negative, q < 0) avoids the cancellation
-    sq = np.sqrt(disc[one])
-    c = np.cbrt(0.5 * (d1[one] + np.where(d1[one] < 0.0, -sq, sq)))
+    C, diff = _stable_root_difference(d0[pos], d1[pos])
+    out[pos] = diff / (3.0 * C)
+    c = np.cbrt(0.5 * (d1[one] - np.sqrt(disc[one])))
     out[one] = -(c + d0[one] / c) / 3.0
     cos_t = np.clip(d1[three] / (2.0 * d0[three] ** 1.5), -1.0, 1.0)
     theta = np.arccos(cos_t)
@@ -106,10 +122,12 @@ def root_cubic(p, q):
 
 
 def root_quartic(p, q):
-    """Root of u^4 + p u + q = 0 by the closed forms of Sect. 3.11; where rounding
-    leaves no real S (negative discriminant or Q + Delta0/Q <= 0) the root falls back to
-    (-q)^(1/4), as the paper prescribes, and a slightly negative square-root argument
-    is taken as zero."""
+    """Root of u^4 + p u + q = 0 by the closed forms of Sect. 3.11. Q + Delta0 / Q (Q^3 =
+    (Delta1 + sqrt(disc)) / 2, Delta0 = 12 q < 0) is formed as (Q^2 + Delta0) / Q without
+    cancellation (_stable_root_difference): the printed form loses up to 1e-2 of u where
+    p is near 0. Where no real S remains (negative discriminant or Q + Delta0/Q <= 0) the
+    root falls back to (-q)^(1/4), as the paper prescribes, and a slightly negative
+    square-root argument is taken as zero."""
     p = np.asarray(p, dtype=np.float64)
     q = np.broadcast_to(np.asarray(q, dtype=np.float64), p.shape)
     d0 = 12.0 * q
@@ -118,8 +136,8 @@ def root_quartic(p, q):
     fallback = np.sqrt(np.sqrt(-q))
     out = fallback.copy()
     ok = (p != 0.0) & (disc >= 0.0)
-    Q = np.cbrt(0.5 * (d1[ok] + np.sqrt(disc[ok])))
-    w = Q + d0[ok] / Q
+    Q, diff = _stable_root_difference(d0[ok], d1[ok])
+    w = diff / Q
     good = w > 0.0
     S = 0.5 * np.sqrt(np.where(good, w, 1.0) / 3.0)
     pp = p[ok]

@@ -15,7 +15,7 @@ LIB = os.path.join(HERE, "libhippm.so")
 OBJDIR = os.path.join(HERE, "_build")
 
 SOURCES = ["api.hip", "particles.hip", "grid.hip", "mg.hip", "mg_stream.hip", "fft.hip",
-           "adjoint.hip", "batch.hip", "ics.hip", "gravity.hip", "noalloc.hip"]
+           "adjoint.hip", "batch.hip", "ics.hip", "gravity.hip", "fr.hip", "noalloc.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -52,6 +52,23 @@ int check_particles(pm_ctx *ctx, const void *pos, const int32_t *cell, int64_t n
   return PM_OK;
 }
 
+// with PM_CREATE_CHECK_FINITE: PM_ERR_NONFINITE if a position (or velocity) is not
+// finite, found before any other kernel reads them (one pass and a host sync)
+int check_finite(pm_ctx *ctx, const float *pos, const float *vel, int64_t np, hipStream_t s) {
+  if (!(ctx->flags & PM_CREATE_CHECK_FINITE) || np == 0) return PM_OK;
+  auto *cnt = reinterpret_cast<unsigned long long *>(ctx->red_result + 3);
+  PM_HIP(ctx, hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s));
+  PM_HIP(ctx, launch_count_nonfinite(pos, 3 * np, cnt, s));
+  if (vel) PM_HIP(ctx, launch_count_nonfinite(vel, 3 * np, cnt, s));
+  PM_HIP(ctx, hipMemcpyAsync(ctx->host_result + 3, cnt, sizeof(unsigned long long),
+                             hipMemcpyDeviceToHost, s));
+  PM_HIP(ctx, hipStreamSynchronize(s));
+  unsigned long long found;
+  std::memcpy(&found, ctx->host_result + 3, sizeof(found));
+  if (found) return pm_fail(ctx, PM_ERR_NONFINITE, "non-finite particle positions or velocities");
+  return PM_OK;
+}
+
 int check_mg(pm_ctx *ctx, const pm_mg_params *p) {
   if (!p) return pm_fail(ctx, PM_ERR_ARG, "null multigrid params");
   if (p->pre < 0 || p->post < 0 || p->pre > 16 || p->post > 16)
@@ -74,12 +91,37 @@ int check_mg(pm_ctx *ctx, const pm_mg_params *p) {
   return PM_OK;
 }
 
+// the f(R) fields of the step parameters (pm_solve_fr and PM_GRAVITY_FR)
+int check_fr(pm_ctx *ctx, const pm_step_params *p) {
+  if (!(p->omega_m > 0.0) || !std::isfinite(p->omega_m) || !std::isfinite(p->omega_l))
+    return pm_fail(ctx, PM_ERR_ARG, "Omega_m must be > 0 and Omega_L finite");
+  if (!(p->fr_f0 < 0.0) || !std::isfinite(p->fr_f0))
+    return pm_fail(ctx, PM_ERR_ARG, "f(R) needs a finite f_R0 < 0");
+  if (!(p->fr_c2 > 0.0) || !std::isfinite(p->fr_c2))
+    return pm_fail(ctx, PM_ERR_ARG, "f(R) needs a finite c~^2 > 0");
+  if (p->fr_n != 1 && p->fr_n != 2) return pm_fail(ctx, PM_ERR_ARG, "Hu-Sawicki n must be 1 or 2");
+  if (p->fr_cycles < 1 || p->fr_cycles > 64)
+    return pm_fail(ctx, PM_ERR_ARG, "fr_cycles must be 1 .. 64");
+  if (p->fr_cycle != PM_CYCLE_V && p->fr_cycle != PM_CYCLE_W && p->fr_cycle != PM_CYCLE_F)
+    return pm_fail(ctx, PM_ERR_ARG, "bad FAS cycle");
+  if (p->fr_pre < 1 || p->fr_pre > 64 || p->fr_post < 1 || p->fr_post > 64)
+    return pm_fail(ctx, PM_ERR_ARG, "FAS pre- and post-smoothing must be 1 .. 64 sweeps");
+  if (p->fr_coarse_sweeps < 1 || p->fr_coarse_sweeps > 4096)
+    return pm_fail(ctx, PM_ERR_ARG, "fr_coarse_sweeps must be 1 .. 4096");
+  return PM_OK;
+}
+
 int check_gravity(pm_ctx *ctx, const pm_step_params *p) {
   if (!(p->omega_m > 0.0) || !std::isfinite(p->omega_m) || !std::isfinite(p->omega_l))
     return pm_fail(ctx, PM_ERR_ARG, "Omega_m must be > 0 and Omega_L finite");
   if (p->gravity != PM_GRAVITY_NEWTON && p->gravity != PM_GRAVITY_MU &&
-      p->gravity != PM_GRAVITY_QUMOND)
+      p->gravity != PM_GRAVITY_QUMOND && p->gravity != PM_GRAVITY_FR)
     return pm_fail(ctx, PM_ERR_ARG, "bad gravity");
+  if (p->gravity == PM_GRAVITY_FR) {
+    if (int st = check_fr(ctx, p)) return st;
+    if (p->solver == PM_SOLVER_FULL_FFT)
+      return pm_fail(ctx, PM_ERR_ARG, "f(R) needs a potential: not the FULL_FFT solver");
+  }
   if (p->gravity == PM_GRAVITY_MU && (!std::isfinite(p->mu0) || !(p->omega_l > 0.0)))
     return pm_fail(ctx, PM_ERR_ARG, "parametrised gravity needs a finite mu0 and Omega_L > 0");
   if (p->gravity == PM_GRAVITY_QUMOND) {
@@ -119,8 +161,8 @@ int check_step_vjp(pm_ctx *ctx, const pm_step_params *p) {
   if (!valid_mas_vjp(p->mas)) return pm_fail(ctx, PM_ERR_ARG, "reverse mode takes CIC or TSC");
   if (p->solver == PM_SOLVER_FULL_FFT)
     return pm_fail(ctx, PM_ERR_ARG, "reverse mode does not take the FULL_FFT solver");
-  if (p->gravity == PM_GRAVITY_QUMOND)
-    return pm_fail(ctx, PM_ERR_ARG, "reverse mode does not take QUMOND");
+  if (p->gravity == PM_GRAVITY_QUMOND || p->gravity == PM_GRAVITY_FR)
+    return pm_fail(ctx, PM_ERR_ARG, "reverse mode takes Newtonian or parametrised gravity");
   return PM_OK;
 }
 
@@ -261,11 +303,20 @@ int accel_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, i
                      mean_ready);
   }
   if (sst < 0) return sst;
+  // f(R): the scalaron (from the previous one unless the guess is Jacobi) and the force
+  // potential phi_N - (c~^2 / 2) f~; phi keeps the Newtonian potential
+  const float *phif = phi;
+  if (p->gravity == PM_GRAVITY_FR) {
+    if (int fst = pm_fr_force_potential(ctx, ctx->rho, a, p, p->mg.guess != PM_GUESS_JACOBI,
+                                        phi, s))
+      return fst;
+    phif = ctx->fr_phi;
+  }
   if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[3], s));
   // with the tile buckets of these positions (sorted deposit on tiles), the gradient is
   // formed per tile inside the interpolation kernel
   const bool tiles = p->order == PM_DEPOSIT_SORTED && ctx->n % 8 == 0 && !full_fft;
-  if (!tiles && !full_fft) PM_HIP(ctx, launch_gradient(phi, ctx->n, 5, ctx->g, s));
+  if (!tiles && !full_fft) PM_HIP(ctx, launch_gradient(phif, ctx->n, 5, ctx->g, s));
   if (timing) PM_HIP(ctx, hipEventRecord(ctx->ev[4], s));
   pm_kt_begin(ctx, PM_KERNEL_INTERP, s);
   double bytes;
@@ -276,7 +327,7 @@ int accel_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, i
     int32_t *wcell = const_cast<int32_t *>(cell);
     const int64_t ntiles = (int64_t)ctx->n * ctx->n * ctx->n / 512;
     PM_HIP(ctx, hipMemsetAsync(ctx->cell_count2, 0, sizeof(int32_t) * (size_t)(ntiles + 1), s));
-    PM_HIP(ctx, launch_interp_tile_phi(ctx, wpos, wcell, poskind, p->mas, phi, nullptr, vel,
+    PM_HIP(ctx, launch_interp_tile_phi(ctx, wpos, wcell, poskind, p->mas, phif, nullptr, vel,
                                        kick + next->kick, next->dt, ctx->pcell, ctx->cell_count2,
                                        s));
     ctx->hist_next = true;
@@ -289,7 +340,7 @@ int accel_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, i
   } else {
     if (tiles)
       PM_HIP(ctx, launch_interp_tile_phi(ctx, const_cast<float *>(pos), const_cast<int32_t *>(cell),
-                                         poskind, p->mas, phi, acc, vel, kick, 0.0f, nullptr,
+                                         poskind, p->mas, phif, acc, vel, kick, 0.0f, nullptr,
                                          nullptr, s));
     else
       PM_HIP(ctx, launch_interp(pos, cell, np, poskind, p->mas, ctx->n, ctx->g, acc, vel, kick, s));
@@ -411,6 +462,14 @@ void pm_default_step_params(pm_step_params *p) {
   p->mond_g0 = 0.0;
   p->mond_g0_exp = 0.0;
   p->mond_param = 1.0;
+  p->fr_f0 = -1e-5;
+  p->fr_c2 = 29.9792458 * 29.9792458;  // a 100 Mpc/h box
+  p->fr_n = 1;
+  p->fr_cycles = 1;
+  p->fr_cycle = PM_CYCLE_F;
+  p->fr_pre = 2;
+  p->fr_post = 1;
+  p->fr_coarse_sweeps = 32;
 }
 
 int pm_create(pm_ctx **out, int n, int64_t np_max, int flags) {
@@ -418,6 +477,7 @@ int pm_create(pm_ctx **out, int n, int64_t np_max, int flags) {
   *out = nullptr;
   if (np_max < 0) return PM_ERR_ARG;
   if (n < 8 || n > 1024 || (n & 1)) return PM_ERR_SHAPE;
+  if (flags & ~(PM_CREATE_REFERENCE_KERNELS | PM_CREATE_CHECK_FINITE)) return PM_ERR_ARG;
   pm_ctx *ctx = new pm_ctx();  // value-initialised: every pointer starts null
   ctx->n = n;
   ctx->np_max = np_max;
@@ -482,6 +542,7 @@ void pm_destroy(pm_ctx *ctx) {
   fr(ctx->adj_rhobar);
   fr(ctx->mond_phin);
   fr(ctx->mond_src);
+  pm_fr_free(ctx);
   for (int i = 0; i < 8; ++i)
     if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
   for (int i = 0; i < 2 * ctx->kt_cap; ++i) (void)hipEventDestroy(ctx->kt_ev[i]);
@@ -534,6 +595,15 @@ int pm_solve_fft_kernel(pm_ctx *ctx, const float *rho, float coef, int kernel, i
                            (hipStream_t)stream);
 }
 
+int pm_solve_fr(pm_ctx *ctx, const float *rho, double a, const pm_step_params *params,
+                double *u, double *relres, pm_stream stream) {
+  if (!ctx) return PM_ERR_ARG;
+  if (!rho || !u || !params) return pm_fail(ctx, PM_ERR_ARG, "null pointer");
+  if (!(a > 0.0) || !std::isfinite(a)) return pm_fail(ctx, PM_ERR_ARG, "a must be finite and > 0");
+  if (int st = check_fr(ctx, params)) return st;
+  return pm_fr_solve(ctx, rho, a, params, u, relres, (hipStream_t)stream);
+}
+
 int pm_gradient(pm_ctx *ctx, const float *phi, int points, float *g, pm_stream stream) {
   if (!ctx) return PM_ERR_ARG;
   if (!phi || !g) return pm_fail(ctx, PM_ERR_ARG, "null grid");
@@ -566,6 +636,7 @@ int pm_accel(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, int
   if (!phi || (np > 0 && !acc)) return pm_fail(ctx, PM_ERR_ARG, "null pointer");
   if (!(a > 0.0) || !std::isfinite(a)) return pm_fail(ctx, PM_ERR_ARG, "scale factor must be > 0");
   hipStream_t s = (hipStream_t)stream;
+  if ((st = check_finite(ctx, pos, nullptr, np, s)) != PM_OK) return st;
   const bool timing = params->timing && stats;
   st = accel_impl(ctx, pos, cell, np, poskind, a, params, phi, acc, nullptr, 0.f, stats, s, timing,
                   1.0f, nullptr);
@@ -575,7 +646,7 @@ int pm_accel(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, int
 
 int pm_kernel_timer(pm_ctx *ctx, int kernel, int capacity) {
   if (!ctx) return PM_ERR_ARG;
-  if (kernel < PM_KERNEL_NONE || kernel > PM_KERNEL_INTERP)
+  if (kernel < PM_KERNEL_NONE || kernel > PM_KERNEL_FR_SWEEP)
     return pm_fail(ctx, PM_ERR_ARG, "unknown kernel id");
   if (capacity < 0 || capacity > (1 << 20)) return pm_fail(ctx, PM_ERR_ARG, "bad capacity");
   if (capacity > ctx->kt_cap) {
@@ -670,6 +741,7 @@ int pm_kdk(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, int64_t np, int p
   if (!(a0 > 0.0) || !(a1 > 0.0) || !std::isfinite(a0) || !std::isfinite(a1))
     return pm_fail(ctx, PM_ERR_ARG, "scale factors must be > 0");
   hipStream_t s = (hipStream_t)stream;
+  if ((st = check_finite(ctx, pos, vel, np, s)) != PM_OK) return st;
   const bool timing = params->timing && stats;
   const double tau = pm_bg_tau(params->omega_m, params->omega_l, a0, a1);
   if (!std::isfinite(tau)) return pm_fail(ctx, PM_ERR_ARG, "the background has no real time step");
@@ -715,6 +787,7 @@ int pm_kdk_chain(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, int64_t np,
     return pm_fail(ctx, PM_ERR_ARG, "scale factors must be > 0 and finite");
   const bool more = a2 > a1;
   hipStream_t s = (hipStream_t)stream;
+  if ((st = check_finite(ctx, pos, vel, np, s)) != PM_OK) return st;
   const bool timing = params->timing && stats;
   const double tau = pm_bg_tau(params->omega_m, params->omega_l, a0, a1);
   if (!std::isfinite(tau)) return pm_fail(ctx, PM_ERR_ARG, "the background has no real time step");

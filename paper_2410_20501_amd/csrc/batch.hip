@@ -834,7 +834,7 @@ int check_batch_params(pm_batch *B, const pm_step_params *p) {
   if (!p) return bfail(B, PM_ERR_ARG, "null step params");
   if (p->mas != PM_TSC && p->mas != PM_CIC) return bfail(B, PM_ERR_ARG, "bad mas");
   if (p->solver != PM_SOLVER_MG) return bfail(B, PM_ERR_ARG, "batched runs use the multigrid solver");
-  if (p->gravity == PM_GRAVITY_QUMOND)
+  if (p->gravity != PM_GRAVITY_NEWTON && p->gravity != PM_GRAVITY_MU)
     return bfail(B, PM_ERR_ARG, "batched runs take Newtonian or parametrised gravity");
   if (!(p->omega_m > 0.0) || !std::isfinite(p->omega_l) ||
       (p->gravity == PM_GRAVITY_MU && !(p->omega_l > 0.0)))

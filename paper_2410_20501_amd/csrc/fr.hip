@@ -1,0 +1,513 @@
+// f(R) gravity (Hu-Sawicki): the scalaron by non-linear multigrid (paper Sects. 2.5,
+// 3.7.2, 3.11).
+//
+// The unknown is u = (f~ / f~_bar)^(1/(n+1)), 1 in the background. Per cell the seven-
+// point form of the field equation is
+//   N_h(u) = (f~_bar / h^2) [sum_nb u_nb^(n+1) - 6 u^(n+1)] - K / u = s,
+// and with the neighbours fixed it is u^(n+2) + p u + q = 0,
+//   p = -(1/6) sum_nb u_nb^(n+1) + h^2 s / (6 f~_bar),   q = h^2 K / (6 f~_bar) < 0,
+// a depressed cubic (n = 1) or quartic (n = 2) whose positive root has the closed forms
+// of Sect. 3.11. Everything here is FP64, as the paper prescribes for the root branches.
+//
+// Full approximation storage (Sect. 3.7.2): after pre-smoothing, the residual
+// d = s - N_h(u) and u are restricted (full weighting), the coarse right-hand side is
+// N_H(R u) + R d, the coarse problem starts from R u, and u += P(u_H - R u) (trilinear).
+// The coarsest grid gets a fixed number of sweeps (one workgroup in LDS when it is
+// small).
+#include <cmath>
+
+#include "internal.h"
+
+namespace {
+
+constexpr int kFrThreads = 256;
+constexpr int kFrCoarseThreads = 512;
+constexpr int kFrCoarseMax = 2048;   // coarsest cells held in LDS (two FP64 arrays)
+
+__host__ __device__ inline int wrapn(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+__device__ __forceinline__ double pow_n1(double u, int ne) { return ne == 1 ? u * u : u * u * u; }
+
+// For Delta0 < 0, with B = (-Delta0)^(3/2), sqrt(disc) = sqrt(Delta1^2 + 4 B^2) and
+// A = (|Delta1| + sqrt(disc)) / 2: Q = A^(1/3) and diff = Q^2 - (-Delta0), the latter as
+// (A - B)(A + B) / (Q^4 + Q^2 (-Delta0) + Delta0^2) with A - B = |Delta1| / 2 +
+// Delta1^2 / (2 (sqrt(disc) + 2 B)), which involves no subtraction of close numbers
+__device__ __forceinline__ void stable_root_difference(double d0, double d1, double &Q,
+                                                       double &diff) {
+  const double B = -d0 * sqrt(-d0);
+  const double sq = sqrt(d1 * d1 + 4.0 * B * B);
+  const double ad1 = fabs(d1);
+  const double A = 0.5 * (ad1 + sq);
+  Q = cbrt(A);
+  const double amb = 0.5 * ad1 + 0.5 * d1 * d1 / (sq + 2.0 * B);
+  const double Q2 = Q * Q;
+  diff = amb * (A + B) / (Q2 * Q2 - d0 * Q2 + d0 * d0);
+}
+
+// positive root of u^3 + p u + q = 0 (q < 0), the closed forms of Sect. 3.11
+__device__ double root3(double p, double q) {
+  if (p == 0.0) return cbrt(-q);
+  const double d0 = -3.0 * p, d1 = 27.0 * q;
+  if (p > 0.0) {
+    // one real root -(C + Delta0 / C) / 3 = (|C|^2 + Delta0) / (3 |C|), formed without
+    // cancellation (the root is small where p is large)
+    double C, diff;
+    stable_root_difference(d0, d1, C, diff);
+    return diff / (3.0 * C);
+  }
+  const double disc = d1 * d1 - 4.0 * d0 * d0 * d0;
+  if (disc > 0.0) {
+    // one real root; C^3 = (Delta1 - sqrt(disc)) / 2 (the other sign gives Delta0 / C
+    // and the same root); C and Delta0 / C have one sign here
+    const double c = cbrt(0.5 * (d1 - sqrt(disc)));
+    return -(c + d0 / c) / 3.0;
+  }
+  // three real roots: the largest
+  const double sd0 = sqrt(d0);
+  const double ct = fmin(1.0, fmax(-1.0, d1 / (2.0 * d0 * sd0)));
+  return -2.0 * sd0 * cos(acos(ct) / 3.0 + 2.0 * M_PI / 3.0) / 3.0;
+}
+
+// positive root of u^4 + p u + q = 0 (q < 0), the closed forms of Sect. 3.11 with
+// Q + Delta0 / Q formed without cancellation (p near 0); (-q)^(1/4) where no real S
+// remains
+__device__ double root4(double p, double q) {
+  const double fb = sqrt(sqrt(-q));
+  if (p == 0.0) return fb;
+  const double d0 = 12.0 * q, d1 = 27.0 * p * p;
+  const double disc = d1 * d1 - 4.0 * d0 * d0 * d0;
+  if (disc < 0.0) return fb;
+  double Q, diff;
+  stable_root_difference(d0, d1, Q, diff);
+  const double w = diff / Q;
+  if (!(w > 0.0)) return fb;
+  const double S = 0.5 * sqrt(w / 3.0);
+  const double arg = p > 0.0 ? -4.0 * S * S + p / S : -4.0 * S * S - p / S;
+  return (p > 0.0 ? -S : S) + 0.5 * sqrt(fmax(arg, 0.0));
+}
+
+struct FrLevel {
+  int n;
+  double h2;      // h^2
+  double q;       // h^2 K / (6 f~_bar)
+  double ps;      // h^2 / (6 f~_bar), the factor of s in p
+  double a_op;    // f~_bar / h^2
+};
+
+__device__ __forceinline__ double nb_sum(const double *__restrict__ u, int n, int i, int j, int k,
+                                         int ne) {
+  const size_t nn = (size_t)n * n;
+  const size_t ri = (size_t)i * nn, rj = (size_t)j * n;
+  const size_t im = (size_t)wrapn(i - 1, n) * nn, ip = (size_t)wrapn(i + 1, n) * nn;
+  const size_t jm = (size_t)wrapn(j - 1, n) * n, jp = (size_t)wrapn(j + 1, n) * n;
+  const int km = wrapn(k - 1, n), kp = wrapn(k + 1, n);
+  return pow_n1(u[im + rj + k], ne) + pow_n1(u[ip + rj + k], ne) + pow_n1(u[ri + jm + k], ne) +
+         pow_n1(u[ri + jp + k], ne) + pow_n1(u[ri + rj + km], ne) + pow_n1(u[ri + rj + kp], ne);
+}
+
+// one colour of the non-linear red-black Gauss-Seidel: the cells with (i+j+k) % 2 ==
+// colour take the root of their polynomial (n even)
+__global__ __launch_bounds__(kFrThreads) void k_fr_sweep(double *__restrict__ u,
+                                                         const double *__restrict__ s, FrLevel L,
+                                                         int ne, int colour) {
+  const int n = L.n, hn = n >> 1;
+  const int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kFrThreads + threadIdx.x;
+  if (t >= (int64_t)n * n * hn) return;
+  const int i = (int)(t / ((int64_t)n * hn));
+  const int r = (int)(t - (int64_t)i * n * hn);
+  const int j = r / hn;
+  const int k = 2 * (r - j * hn) + ((i + j + colour) & 1);
+  const size_t c = ((size_t)i * n + j) * n + k;
+  const double p = -nb_sum(u, n, i, j, k, ne) / 6.0 + L.ps * s[c];
+  u[c] = ne == 1 ? root3(p, L.q) : root4(p, L.q);
+}
+
+// d = s - N_h(u)
+__global__ __launch_bounds__(kFrThreads) void k_fr_residual(const double *__restrict__ u,
+                                                            const double *__restrict__ s,
+                                                            FrLevel L, double K, int ne,
+                                                            double *__restrict__ d) {
+  const int n = L.n;
+  const int64_t c = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kFrThreads + threadIdx.x;
+  if (c >= (int64_t)n * n * n) return;
+  const int i = (int)(c / ((int64_t)n * n)), j = (int)((c / n) % n), k = (int)(c % n);
+  const double uc = u[c];
+  const double op = L.a_op * (nb_sum(u, n, i, j, k, ne) - 6.0 * pow_n1(uc, ne)) - K / uc;
+  d[c] = s[c] - op;
+}
+
+// full weighting of u and d onto the grid of side n/2: per axis (1, 3, 3, 1) / 8 over the
+// fine cells 2J-1 .. 2J+2; u0 = uH = R u, sH = R d
+__global__ __launch_bounds__(kFrThreads) void k_fr_restrict(const double *__restrict__ u,
+                                                            const double *__restrict__ d, int n,
+                                                            double *__restrict__ u0,
+                                                            double *__restrict__ uH,
+                                                            double *__restrict__ sH) {
+  const int N = n >> 1;
+  const int64_t c = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kFrThreads + threadIdx.x;
+  if (c >= (int64_t)N * N * N) return;
+  const int I = (int)(c / ((int64_t)N * N)), J = (int)((c / N) % N), Kc = (int)(c % N);
+  constexpr double w[4] = {0.125, 0.375, 0.375, 0.125};
+  double su = 0.0, sd = 0.0;
+  for (int a = 0; a < 4; ++a) {
+    const size_t ra = (size_t)wrapn(2 * I - 1 + a, n) * n;
+    for (int b = 0; b < 4; ++b) {
+      const size_t rb = (ra + wrapn(2 * J - 1 + b, n)) * n;
+      const double wab = w[a] * w[b];
+      double tu = 0.0, td = 0.0;
+      for (int e = 0; e < 4; ++e) {
+        const size_t f = rb + wrapn(2 * Kc - 1 + e, n);
+        tu += w[e] * u[f];
+        td += w[e] * d[f];
+      }
+      su += wab * tu;
+      sd += wab * td;
+    }
+  }
+  u0[c] = su;
+  uH[c] = su;
+  sH[c] = sd;
+}
+
+// sH += N_H(u0): the coarse right-hand side N_H(R u) + R d
+__global__ __launch_bounds__(kFrThreads) void k_fr_coarse_rhs(const double *__restrict__ u0,
+                                                              FrLevel L, double K, int ne,
+                                                              double *__restrict__ sH) {
+  const int n = L.n;
+  const int64_t c = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kFrThreads + threadIdx.x;
+  if (c >= (int64_t)n * n * n) return;
+  const int i = (int)(c / ((int64_t)n * n)), j = (int)((c / n) % n), k = (int)(c % n);
+  const double uc = u0[c];
+  sH[c] += L.a_op * (nb_sum(u0, n, i, j, k, ne) - 6.0 * pow_n1(uc, ne)) - K / uc;
+}
+
+// u += P(uH - u0) on the fine grid of side n: per axis 3/4 of the nearest coarse centre
+// and 1/4 of the next one
+__global__ __launch_bounds__(kFrThreads) void k_fr_prolong(double *__restrict__ u, int n,
+                                                           const double *__restrict__ uH,
+                                                           const double *__restrict__ u0) {
+  const int N = n >> 1;
+  const int64_t c = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kFrThreads + threadIdx.x;
+  if (c >= (int64_t)n * n * n) return;
+  const int i = (int)(c / ((int64_t)n * n)), j = (int)((c / n) % n), k = (int)(c % n);
+  const int ci[2] = {i >> 1, wrapn((i >> 1) + ((i & 1) ? 1 : -1), N)};
+  const int cj[2] = {j >> 1, wrapn((j >> 1) + ((j & 1) ? 1 : -1), N)};
+  const int ck[2] = {k >> 1, wrapn((k >> 1) + ((k & 1) ? 1 : -1), N)};
+  constexpr double w[2] = {0.75, 0.25};
+  double v = 0.0;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      const size_t r = ((size_t)ci[a] * N + cj[b]) * N;
+      double t = 0.0;
+      for (int e = 0; e < 2; ++e) t += w[e] * (uH[r + ck[e]] - u0[r + ck[e]]);
+      v += w[a] * w[b] * t;
+    }
+  u[c] += v;
+}
+
+// the coarsest grid (n^3 <= kFrCoarseMax, n even): `sweeps` red-black sweeps in LDS
+__global__ __launch_bounds__(kFrCoarseThreads) void k_fr_coarse(double *__restrict__ u,
+                                                                const double *__restrict__ s,
+                                                                FrLevel L, int ne, int sweeps) {
+  __shared__ double su[kFrCoarseMax];
+  __shared__ double ss[kFrCoarseMax];
+  const int n = L.n, cells = n * n * n;
+  for (int c = threadIdx.x; c < cells; c += kFrCoarseThreads) {
+    su[c] = u[c];
+    ss[c] = s[c];
+  }
+  __syncthreads();
+  for (int it = 0; it < sweeps; ++it)
+    for (int colour = 0; colour < 2; ++colour) {
+      for (int c = threadIdx.x; c < cells; c += kFrCoarseThreads) {
+        const int i = c / (n * n), j = (c / n) % n, k = c % n;
+        if (((i + j + k) & 1) != colour) continue;
+        const double p = -nb_sum(su, n, i, j, k, ne) / 6.0 + L.ps * ss[c];
+        su[c] = ne == 1 ? root3(p, L.q) : root4(p, L.q);
+      }
+      __syncthreads();
+    }
+  for (int c = threadIdx.x; c < cells; c += kFrCoarseThreads) u[c] = su[c];
+}
+
+// s = -cA (rho - mean) - K
+__global__ __launch_bounds__(kFrThreads) void k_fr_source(const float *__restrict__ rho,
+                                                          const double *__restrict__ mean,
+                                                          int64_t count, double cA, double K,
+                                                          double *__restrict__ s) {
+  const int64_t c = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kFrThreads + threadIdx.x;
+  if (c >= count) return;
+  s[c] = -cA * ((double)rho[c] - mean[0]) - K;
+}
+
+__global__ __launch_bounds__(kFrThreads) void k_fill_d(double *__restrict__ x, double v,
+                                                       int64_t count) {
+  const int64_t c = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kFrThreads + threadIdx.x;
+  if (c < count) x[c] = v;
+}
+
+// the potential of the force: phi_N - (c~^2 / 2) f~_bar u^(n+1)
+__global__ __launch_bounds__(kFrThreads) void k_fr_phi(const float *__restrict__ phin,
+                                                       const double *__restrict__ u,
+                                                       int64_t count, double coef, int ne,
+                                                       float *__restrict__ out) {
+  const int64_t c = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kFrThreads + threadIdx.x;
+  if (c >= count) return;
+  out[c] = (float)((double)phin[c] - coef * pow_n1(u[c], ne));
+}
+
+// per-block sums of d^2 and s^2 (two doubles per block, grid-stride)
+__global__ __launch_bounds__(kFrThreads) void k_fr_norms(const double *__restrict__ d,
+                                                         const double *__restrict__ s,
+                                                         int64_t count,
+                                                         double *__restrict__ partial) {
+  double a = 0.0, b = 0.0;
+  for (int64_t c = (int64_t)blockIdx.x * kFrThreads + threadIdx.x; c < count;
+       c += (int64_t)gridDim.x * kFrThreads) {
+    a += d[c] * d[c];
+    b += s[c] * s[c];
+  }
+  __shared__ double la[kFrThreads], lb[kFrThreads];
+  la[threadIdx.x] = a;
+  lb[threadIdx.x] = b;
+  __syncthreads();
+  for (int o = kFrThreads / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      la[threadIdx.x] += la[threadIdx.x + o];
+      lb[threadIdx.x] += lb[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = la[0];
+    partial[2 * blockIdx.x + 1] = lb[0];
+  }
+}
+
+__global__ __launch_bounds__(kFrThreads) void k_fr_norms_final(const double *__restrict__ partial,
+                                                               int nblocks,
+                                                               double *__restrict__ out) {
+  __shared__ double la[kFrThreads], lb[kFrThreads];
+  double a = 0.0, b = 0.0;
+  for (int q = threadIdx.x; q < nblocks; q += kFrThreads) {
+    a += partial[2 * q];
+    b += partial[2 * q + 1];
+  }
+  la[threadIdx.x] = a;
+  lb[threadIdx.x] = b;
+  __syncthreads();
+  for (int o = kFrThreads / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      la[threadIdx.x] += la[threadIdx.x + o];
+      lb[threadIdx.x] += lb[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = la[0];
+    out[1] = lb[0];
+  }
+}
+
+unsigned blocks(int64_t count) { return (unsigned)((count + kFrThreads - 1) / kFrThreads); }
+
+bool fr_is_coarsest(int n) { return n <= 4 || n % 4 != 0; }
+
+struct FrRun {
+  pm_ctx *ctx;
+  const pm_step_params *p;
+  double fbar, K;
+  int ne;
+  hipStream_t s;
+
+  FrLevel level(int l) const {
+    const int n = ctx->fr_lev[l].n;
+    const double h = 1.0 / n;
+    FrLevel L;
+    L.n = n;
+    L.h2 = h * h;
+    L.q = L.h2 * K / (6.0 * fbar);
+    L.ps = L.h2 / (6.0 * fbar);
+    L.a_op = fbar / L.h2;
+    return L;
+  }
+
+  hipError_t sweep(int l, double *u, int first) {
+    const FrLevel L = level(l);
+    const int64_t half = (int64_t)L.n * L.n * L.n / 2;
+    const double *sv = ctx->fr_lev[l].s;
+    if (l == 0) pm_kt_begin(ctx, PM_KERNEL_FR_SWEEP, s);
+    k_fr_sweep<<<blocks(half), kFrThreads, 0, s>>>(u, sv, L, ne, first);
+    k_fr_sweep<<<blocks(half), kFrThreads, 0, s>>>(u, sv, L, ne, 1 - first);
+    if (l == 0) pm_kt_end(ctx, PM_KERNEL_FR_SWEEP, s, 32.0 * 2.0 * (double)half);
+    return hipGetLastError();
+  }
+
+  hipError_t coarsest(int l, double *u) {
+    const FrLevel L = level(l);
+    if ((int64_t)L.n * L.n * L.n <= kFrCoarseMax) {
+      k_fr_coarse<<<1, kFrCoarseThreads, 0, s>>>(u, ctx->fr_lev[l].s, L, ne, p->fr_coarse_sweeps);
+      return hipGetLastError();
+    }
+    for (int it = 0; it < p->fr_coarse_sweeps; ++it)
+      if (hipError_t e = sweep(l, u, 0)) return e;
+    return hipSuccess;
+  }
+
+  hipError_t cycle(int l, double *u, int kind) {
+    if (l == ctx->fr_nlev - 1) return coarsest(l, u);
+    const FrLevel L = level(l);
+    const int64_t cells = (int64_t)L.n * L.n * L.n;
+    for (int it = 0; it < p->fr_pre; ++it)
+      if (hipError_t e = sweep(l, u, 0)) return e;
+    pm_fr_level &C = ctx->fr_lev[l + 1];
+    double *d = ctx->fr_lev[l].d;
+    k_fr_residual<<<blocks(cells), kFrThreads, 0, s>>>(u, ctx->fr_lev[l].s, L, K, ne, d);
+    const int64_t cc = (int64_t)C.n * C.n * C.n;
+    k_fr_restrict<<<blocks(cc), kFrThreads, 0, s>>>(u, d, L.n, C.u0, C.u, C.s);
+    k_fr_coarse_rhs<<<blocks(cc), kFrThreads, 0, s>>>(C.u0, level(l + 1), K, ne, C.s);
+    if (hipError_t e = hipGetLastError()) return e;
+    const int inner[2] = {kind == PM_CYCLE_W ? PM_CYCLE_W : (kind == PM_CYCLE_F ? PM_CYCLE_F
+                                                                                : PM_CYCLE_V),
+                          kind == PM_CYCLE_W ? PM_CYCLE_W : PM_CYCLE_V};
+    const int visits = kind == PM_CYCLE_V ? 1 : 2;
+    for (int v = 0; v < visits; ++v)
+      if (hipError_t e = cycle(l + 1, C.u, inner[v])) return e;
+    k_fr_prolong<<<blocks(cells), kFrThreads, 0, s>>>(u, L.n, C.u, C.u0);
+    for (int it = 0; it < p->fr_post; ++it)
+      if (hipError_t e = sweep(l, u, 1)) return e;
+    return hipGetLastError();
+  }
+
+  // ||s - N(u)||^2 and ||s||^2 on the finest grid into out[0..1] (device)
+  hipError_t norms(double *u, double *out) {
+    const FrLevel L = level(0);
+    const int64_t cells = (int64_t)L.n * L.n * L.n;
+    double *d = ctx->fr_lev[0].d;
+    k_fr_residual<<<blocks(cells), kFrThreads, 0, s>>>(u, ctx->fr_lev[0].s, L, K, ne, d);
+    const int nb = (int)std::min<int64_t>(RED_BLOCKS, blocks(cells));
+    k_fr_norms<<<nb, kFrThreads, 0, s>>>(d, ctx->fr_lev[0].s, cells, ctx->red_partial);
+    k_fr_norms_final<<<1, kFrThreads, 0, s>>>(ctx->red_partial, nb, out);
+    return hipGetLastError();
+  }
+};
+
+}  // namespace
+
+// R_bar in units of H0^2 / c^2 and the scalaron background (Sect. 2.5)
+static double fr_rbar(double om, double ol, double a) { return 3.0 * (om / (a * a * a) + 4.0 * ol); }
+
+void pm_fr_constants(const pm_step_params *p, double a, double *fbar, double *K, double *cA) {
+  const double rb = fr_rbar(p->omega_m, p->omega_l, a);
+  const double f = std::pow(fr_rbar(p->omega_m, p->omega_l, 1.0) / rb, p->fr_n + 1) * p->fr_f0;
+  *fbar = a * a * f;
+  *K = a * a * a * a * rb / (3.0 * p->fr_c2);
+  *cA = p->omega_m * a / p->fr_c2;
+}
+
+int pm_fr_setup(pm_ctx *ctx) {
+  if (ctx->fr_nlev > 0) return PM_OK;
+  int n = ctx->n, nl = 0;
+  pm_fr_level lev[PM_MAX_LEVELS] = {};
+  while (true) {
+    if (nl >= PM_MAX_LEVELS) return pm_fail(ctx, PM_ERR_SHAPE, "too many FAS levels");
+    lev[nl].n = n;
+    ++nl;
+    if (fr_is_coarsest(n)) break;
+    n /= 2;
+  }
+  for (int l = 0; l < nl; ++l) {
+    const size_t bytes = sizeof(double) * (size_t)lev[l].n * lev[l].n * lev[l].n;
+    bool ok = hipMalloc(&lev[l].s, bytes) == hipSuccess && hipMalloc(&lev[l].d, bytes) == hipSuccess;
+    if (ok && l > 0)
+      ok = hipMalloc(&lev[l].u, bytes) == hipSuccess && hipMalloc(&lev[l].u0, bytes) == hipSuccess;
+    if (!ok) {
+      for (int m = 0; m <= l; ++m) {
+        for (double *q : {lev[m].s, lev[m].d, lev[m].u, lev[m].u0})
+          if (q) (void)hipFree(q);
+      }
+      (void)hipGetLastError();
+      return pm_fail(ctx, PM_ERR_NOMEM, "FAS level allocation failed");
+    }
+  }
+  for (int l = 0; l < nl; ++l) ctx->fr_lev[l] = lev[l];
+  ctx->fr_nlev = nl;
+  return PM_OK;
+}
+
+void pm_fr_free(pm_ctx *ctx) {
+  for (int l = 0; l < ctx->fr_nlev; ++l)
+    for (double *q : {ctx->fr_lev[l].s, ctx->fr_lev[l].d, ctx->fr_lev[l].u, ctx->fr_lev[l].u0})
+      if (q) (void)hipFree(q);
+  ctx->fr_nlev = 0;
+  if (ctx->fr_u) (void)hipFree(ctx->fr_u);
+  if (ctx->fr_phi) (void)hipFree(ctx->fr_phi);
+  ctx->fr_u = nullptr;
+  ctx->fr_phi = nullptr;
+}
+
+int pm_fr_solve(pm_ctx *ctx, const float *rho, double a, const pm_step_params *p, double *u,
+                double *relres, hipStream_t s) {
+  if (int st = pm_fr_setup(ctx)) return st;
+  const int n = ctx->n;
+  const int64_t cells = (int64_t)n * n * n;
+  FrRun run{ctx, p, 0.0, 0.0, p->fr_n, s};
+  double cA;
+  pm_fr_constants(p, a, &run.fbar, &run.K, &cA);
+  // the density's mean in FP64 (red_result[2])
+  PM_HIP(ctx, launch_sum_moments(rho, cells, ctx->red_partial, ctx->red_result, nullptr, s));
+  k_fr_source<<<blocks(cells), kFrThreads, 0, s>>>(rho, ctx->red_result + 2, cells, cA, run.K,
+                                                   ctx->fr_lev[0].s);
+  PM_HIP(ctx, hipGetLastError());
+  if (relres) PM_HIP(ctx, run.norms(u, ctx->red_result));
+  if (relres) PM_HIP(ctx, hipMemcpyAsync(ctx->host_result + 2, ctx->red_result, 2 * sizeof(double),
+                                         hipMemcpyDeviceToHost, s));
+  for (int c = 0; c < p->fr_cycles; ++c) PM_HIP(ctx, run.cycle(0, u, p->fr_cycle));
+  if (relres) {
+    PM_HIP(ctx, run.norms(u, ctx->red_result));
+    PM_HIP(ctx, hipMemcpyAsync(ctx->host_result, ctx->red_result, 2 * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+    PM_HIP(ctx, hipStreamSynchronize(s));
+    const double s2 = ctx->host_result[1];
+    relres[0] = s2 > 0.0 ? std::sqrt(ctx->host_result[2] / s2) : 0.0;
+    relres[1] = s2 > 0.0 ? std::sqrt(ctx->host_result[0] / s2) : 0.0;
+  }
+  return PM_OK;
+}
+
+hipError_t launch_fill_double(double *x, double v, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  k_fill_d<<<blocks(count), kFrThreads, 0, s>>>(x, v, count);
+  return hipGetLastError();
+}
+
+int pm_fr_force_potential(pm_ctx *ctx, const float *rho, double a, const pm_step_params *p,
+                          bool warm, const float *phin, hipStream_t s) {
+  const int n = ctx->n;
+  const int64_t cells = (int64_t)n * n * n;
+  if (!ctx->fr_u) {
+    if (hipMalloc(&ctx->fr_u, sizeof(double) * cells) != hipSuccess) {
+      ctx->fr_u = nullptr;
+      (void)hipGetLastError();
+      return pm_fail(ctx, PM_ERR_NOMEM, "f(R) scalaron allocation failed");
+    }
+    ctx->fr_valid = false;
+  }
+  if (!ctx->fr_phi) {
+    if (hipMalloc(&ctx->fr_phi, sizeof(float) * cells) != hipSuccess) {
+      ctx->fr_phi = nullptr;
+      (void)hipGetLastError();
+      return pm_fail(ctx, PM_ERR_NOMEM, "f(R) potential allocation failed");
+    }
+  }
+  if (!warm || !ctx->fr_valid) PM_HIP(ctx, launch_fill_double(ctx->fr_u, 1.0, cells, s));
+  ctx->fr_valid = false;
+  if (int st = pm_fr_solve(ctx, rho, a, p, ctx->fr_u, nullptr, s)) return st;
+  ctx->fr_valid = true;
+  double fbar, K, cA;
+  pm_fr_constants(p, a, &fbar, &K, &cA);
+  k_fr_phi<<<blocks(cells), kFrThreads, 0, s>>>(phin, ctx->fr_u, cells, 0.5 * p->fr_c2 * fbar,
+                                                p->fr_n, ctx->fr_phi);
+  PM_HIP(ctx, hipGetLastError());
+  return PM_OK;
+}

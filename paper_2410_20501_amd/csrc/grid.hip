@@ -133,7 +133,28 @@ __global__ __launch_bounds__(RED_THREADS) void k_moments_final(const double *__r
   }
 }
 
+// count of non-finite values (grid-stride; one atomic per wave into *out)
+__global__ __launch_bounds__(RED_THREADS) void k_count_nonfinite(const float *__restrict__ x,
+                                                                 int64_t count,
+                                                                 unsigned long long *out) {
+  unsigned long long c = 0;
+  const int64_t stride = (int64_t)gridDim.x * RED_THREADS;
+  for (int64_t i = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; i < count; i += stride)
+    c += isfinite(x[i]) ? 0ull : 1ull;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+}
+
 }  // namespace
+
+hipError_t launch_count_nonfinite(const float *x, int64_t count, unsigned long long *out,
+                                  hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const int nb = (int)std::min<int64_t>(RED_BLOCKS, (count + RED_THREADS - 1) / RED_THREADS);
+  k_count_nonfinite<<<nb, RED_THREADS, 0, s>>>(x, count, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_gradient(const float *phi, int n, int points, float *g, hipStream_t s) {
   dim3 grid((n + kThreads - 1) / kThreads, n, n);

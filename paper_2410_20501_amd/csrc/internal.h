@@ -23,6 +23,15 @@ struct pm_level {
 #define PM_STREAM_MIN_N 256   // levels at least this large use the streaming kernels
 #endif
 
+// one grid of the f(R) full-approximation-storage hierarchy (FP64)
+struct pm_fr_level {
+  int n;
+  double *u;   // iterate (level 0: the caller's or the context's scalaron)
+  double *s;   // right-hand side
+  double *u0;  // R u of the finer grid (levels > 0)
+  double *d;   // residual scratch
+};
+
 struct pm_ctx {
   int n;
   int64_t np_max;
@@ -74,6 +83,13 @@ struct pm_ctx {
   float *mond_phin;      // [n^3]
   float *mond_src;       // [n^3]
   bool mond_valid;       // mond_phin holds a solution
+  // f(R) (lazy): the FAS levels, the scalaron's u of the force evaluations (kept as the
+  // next one's starting guess) and the potential of the force
+  int fr_nlev;
+  pm_fr_level fr_lev[PM_MAX_LEVELS];
+  double *fr_u;          // [n^3]
+  float *fr_phi;         // [n^3] phi_N - (c~^2 / 2) f~
+  bool fr_valid;         // fr_u holds a result
   // timing events
   hipEvent_t ev[8];
   // per-kernel timer: event pairs around every launch of one kernel
@@ -170,6 +186,9 @@ hipError_t launch_ic_vjp(const float *xbar, const float *vbar, int64_t np, float
 hipError_t launch_gradient(const float *phi, int n, int points, float *g, hipStream_t s);
 hipError_t launch_sum_moments(const float *x, int64_t count, double *partial, double *result,
                               float *mean_out, hipStream_t s);
+// *out += number of non-finite values of x[0 .. count)
+hipError_t launch_count_nonfinite(const float *x, int64_t count, unsigned long long *out,
+                                  hipStream_t s);
 
 // mg.hip
 // rho_mean_ready: ctx->mean_f[0] already holds the mean of rho (the sorted deposit's
@@ -200,6 +219,14 @@ double pm_bg_tau(double omega_m, double omega_l, double a0, double a1);   // sup
 double pm_bg_growth(double omega_m, double omega_l, double a);            // D(a), any normalisation
 double pm_bg_coef(const pm_step_params *p, double a);       // (3/2) Omega_m a mu(a)
 double pm_bg_warm_scale(const pm_step_params *p, double a0, double a1);  // a1 D1 / (a0 D0)
+// fr.hip: f(R) scalaron by non-linear multigrid (FP64)
+int pm_fr_solve(pm_ctx *ctx, const float *rho, double a, const pm_step_params *p, double *u,
+                double *relres, hipStream_t s);
+// the scalaron of a force evaluation (ctx->fr_u, from the previous one when warm) and
+// ctx->fr_phi = phin - (c~^2 / 2) f~
+int pm_fr_force_potential(pm_ctx *ctx, const float *rho, double a, const pm_step_params *p,
+                          bool warm, const float *phin, hipStream_t s);
+void pm_fr_free(pm_ctx *ctx);
 // QUMOND source div[nu(|grad phi_N| / g0) grad phi_N] on cell faces (n^3 grids)
 hipError_t launch_qumond_source(const float *phin, int n, float g0, int family, float param,
                                 float *out, hipStream_t s);

@@ -26,19 +26,20 @@ PM_RESTRICT_FW, PM_RESTRICT_AVG = 0, 1
 PM_CYCLE_V, PM_CYCLE_W, PM_CYCLE_F = 0, 1, 2
 PM_SOLVER_MG, PM_SOLVER_FFT, PM_SOLVER_FFT_7PT, PM_SOLVER_FULL_FFT = 0, 1, 2, 3
 PM_FFT_GREEN, PM_FFT_7PT, PM_FFT_FULL = 0, 1, 2
-PM_GRAVITY_NEWTON, PM_GRAVITY_MU, PM_GRAVITY_QUMOND = 0, 1, 2
+PM_GRAVITY_NEWTON, PM_GRAVITY_MU, PM_GRAVITY_QUMOND, PM_GRAVITY_FR = 0, 1, 2, 3
 PM_NU_SIMPLE, PM_NU_N, PM_NU_BETA, PM_NU_GAMMA, PM_NU_DELTA = 0, 1, 2, 3, 4
 PM_GUESS_JACOBI, PM_GUESS_WARM, PM_GUESS_WARM_RESCALED = 0, 1, 2
 PM_CHAIN_FIRST, PM_CHAIN_NEXT = 0, 1
 PM_ADJ_CLOSING_MERGED = 1
-PM_CREATE_REFERENCE_KERNELS = 1
-PM_KERNEL_NONE, PM_KERNEL_DEPOSIT, PM_KERNEL_SMOOTH, PM_KERNEL_INTERP = 0, 1, 2, 3
+PM_CREATE_REFERENCE_KERNELS, PM_CREATE_CHECK_FINITE = 1, 2
+PM_KERNEL_NONE, PM_KERNEL_DEPOSIT, PM_KERNEL_SMOOTH, PM_KERNEL_INTERP, PM_KERNEL_FR_SWEEP = 0, 1, 2, 3, 4
 
 MAS = {"ngp": PM_NGP, "cic": PM_CIC, "tsc": PM_TSC}
 SOLVER = {"mg": PM_SOLVER_MG, "fft": PM_SOLVER_FFT, "fft_7pt": PM_SOLVER_FFT_7PT,
           "full_fft": PM_SOLVER_FULL_FFT}
 FFT_KERNEL = {"green": PM_FFT_GREEN, "7pt": PM_FFT_7PT, "full": PM_FFT_FULL}
-GRAVITY = {"newton": PM_GRAVITY_NEWTON, "mu": PM_GRAVITY_MU, "qumond": PM_GRAVITY_QUMOND}
+GRAVITY = {"newton": PM_GRAVITY_NEWTON, "mu": PM_GRAVITY_MU, "qumond": PM_GRAVITY_QUMOND,
+           "fr": PM_GRAVITY_FR}
 NU_FAMILY = {"simple": PM_NU_SIMPLE, "n": PM_NU_N, "beta": PM_NU_BETA, "gamma": PM_NU_GAMMA,
              "delta": PM_NU_DELTA}
 ORDER = {"atomic": PM_DEPOSIT_ATOMIC, "sorted": PM_DEPOSIT_SORTED}
@@ -72,7 +73,9 @@ class StepParams(ctypes.Structure):
                 ("omega_m", c_double), ("mg", MGParams), ("timing", c_int),
                 ("omega_l", c_double), ("gravity", c_int), ("mond_family", c_int),
                 ("mu0", c_double), ("mond_g0", c_double), ("mond_g0_exp", c_double),
-                ("mond_param", c_double)]
+                ("mond_param", c_double), ("fr_f0", c_double), ("fr_c2", c_double),
+                ("fr_n", c_int), ("fr_cycles", c_int), ("fr_cycle", c_int), ("fr_pre", c_int),
+                ("fr_post", c_int), ("fr_coarse_sweeps", c_int)]
 
 
 class StepStats(ctypes.Structure):
@@ -96,6 +99,7 @@ def _load():
         "pm_solve_fft": (c_int, [P, P, c_float, c_int, P, P]),
         "pm_solve_fft_kernel": (c_int, [P, P, c_float, c_int, c_int, P, P]),
         "pm_solve_fft_noalloc": (c_int, [P, c_int, c_float, c_int, P, P]),
+        "pm_solve_fr": (c_int, [P, P, c_double, POINTER(StepParams), P, POINTER(c_double), P]),
         "pm_gradient": (c_int, [P, P, c_int, P, P]),
         "pm_interp": (c_int, [P, P, P, c_int64, c_int, c_int, P, P, P]),
         "pm_accel": (c_int, [P, P, P, c_int64, c_int, c_double, POINTER(StepParams), P, P,
@@ -164,7 +168,7 @@ def default_step_params(**kw) -> StepParams:
                  "warm_rescaled": PM_GUESS_WARM_RESCALED}.get(v, v)
         elif k == "restrict_kind":
             v = {"fw": PM_RESTRICT_FW, "avg": PM_RESTRICT_AVG}.get(v, v)
-        elif k == "cycle":
+        elif k in ("cycle", "fr_cycle"):
             v = {"V": PM_CYCLE_V, "W": PM_CYCLE_W, "F": PM_CYCLE_F}.get(v, v)
         if hasattr(p.mg, k) and k not in ("mas",):
             setattr(p.mg, k, v)
@@ -286,6 +290,19 @@ def pm_solve_fft_kernel(ctx: Context, rho, coef, out, kernel="green", deconv=3):
     return ctx._check(st, "pm_solve_fft_kernel")
 
 
+def pm_solve_fr(ctx: Context, rho, a, params: StepParams, u, relres=False):
+    """f(R) scalaron u (float64 [n, n, n], in: guess, out: result) by params.fr_cycles FAS
+    cycles on the density rho. With relres=True returns the relative residual before and
+    after the cycles (host synchronisation), else None."""
+    n = ctx.n
+    rr = (c_double * 2)()
+    st = _lib.pm_solve_fr(ctx.handle, _ptr(rho, shape=(n, n, n), name="rho"), float(a),
+                          byref(params), _ptr(u, dtype=torch.float64, shape=(n, n, n), name="u"),
+                          rr if relres else None, _stream())
+    ctx._check(st, "pm_solve_fr")
+    return (rr[0], rr[1]) if relres else None
+
+
 def pm_solve_fft_noalloc(rho, coef, phi, deconv=3):
     """pm_solve_fft without a context and without allocating (grids up to 128^3, the
     library's static scratch; calls that overlap on one GPU race on it)."""
@@ -329,7 +346,7 @@ def pm_accel(ctx: Context, pos, a, phi, acc, cell=None, params: StepParams | Non
 
 def pm_kernel_timer(ctx: Context, kernel, capacity=4096):
     kid = {"none": PM_KERNEL_NONE, "deposit": PM_KERNEL_DEPOSIT, "smooth": PM_KERNEL_SMOOTH,
-           "interp": PM_KERNEL_INTERP}.get(kernel, kernel)
+           "interp": PM_KERNEL_INTERP, "fr_sweep": PM_KERNEL_FR_SWEEP}.get(kernel, kernel)
     return ctx._check(_lib.pm_kernel_timer(ctx.handle, int(kid), int(capacity)), "pm_kernel_timer")
 
 

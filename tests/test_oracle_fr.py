@@ -49,6 +49,32 @@ def test_quartic_roots_match_polynomial_roots():
     assert (np.abs(u ** 4 + p * u + q) / scale).max() < 1e-9
 
 
+def _polished_root(coeffs):
+    """Largest real root from numpy, refined by Newton steps in extended precision."""
+    x = np.longdouble(_largest_real_root(coeffs))
+    c = [np.longdouble(v) for v in coeffs]
+    deg = len(c) - 1
+    for _ in range(6):
+        f = sum(ci * x ** (deg - i) for i, ci in enumerate(c))
+        df = sum((deg - i) * ci * x ** (deg - i - 1) for i, ci in enumerate(c[:-1]))
+        x = x - f / df
+    return float(x)
+
+
+def test_roots_near_zero_and_large_p():
+    """Where the neighbour term nearly balances the source (p near 0) and in deep
+    screening (large p, small root) both closed forms keep full precision."""
+    ps = [s * 10.0 ** e for e in (-12, -9, -6, -3, 0, 2, 4) for s in (1.0, -1.0)]
+    for q in (-1e-6, -1e-3, -1.0, -70.0):
+        p = np.array(ps)
+        u3, u4 = fr.root_cubic(p, q), fr.root_quartic(p, q)
+        for i, pi in enumerate(ps):
+            r3 = _polished_root([1.0, 0.0, pi, q])
+            r4 = _polished_root([1.0, 0.0, 0.0, pi, q])
+            assert u3[i] == pytest.approx(r3, rel=1e-12), (pi, q)
+            assert u4[i] == pytest.approx(r4, rel=1e-12), (pi, q)
+
+
 def test_background_values():
     """f_R_bar(1) = f_R0; R_bar in units of H0^2/c^2 is 3 (Omega_m a^-3 + 4 Omega_L);
     c~ for a 100 Mpc/h box is c / (100 km/s/Mpc * 100 Mpc)."""
