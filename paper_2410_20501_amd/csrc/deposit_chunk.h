@@ -39,6 +39,33 @@ __device__ __forceinline__ int wrap_any(int i, int n) {
   return r < 0 ? r + n : r;
 }
 
+// Grid sides are powers of two in every usual case; then periodic wraps and the
+// decoding of row-major cell indices c = (i n + j) n + k are masks and shifts. The test
+// is on a kernel argument (wave-uniform), so the divisions of the general case run
+// only for other sides.
+__device__ __forceinline__ int log2_if_pow2(int n) {
+  return (n & (n - 1)) == 0 ? __builtin_ctz((unsigned)n) : -1;
+}
+
+__device__ __forceinline__ int wrap_fast(int i, int n, int lg) {
+  return lg >= 0 ? (i & (n - 1)) : wrap_any(i, n);
+}
+
+// (i, j, k) of any integer cell index (wrapped into [0, n^3))
+__device__ __forceinline__ void decode_cell(int q, int n, int lg, int c[3]) {
+  if (lg >= 0) {
+    const int m = n - 1;
+    c[2] = q & m;
+    c[1] = (q >> lg) & m;
+    c[0] = (q >> (2 * lg)) & m;
+  } else {
+    q = wrap_any(q, n * n * n);
+    c[0] = q / (n * n);
+    c[1] = (q / n) - c[0] * n;
+    c[2] = q - (q / n) * n;
+  }
+}
+
 // Per-axis support of the window: first cell index (unwrapped) and MAS weights.
 // TSC (MAS = 3): cells floor(u)-1 .. floor(u)+1, d = u - floor(u) - 1/2 in [-1/2, 1/2):
 //   W = (1/2)(1/2 - d)^2, 3/4 - d^2, (1/2)(1/2 + d)^2.
@@ -104,18 +131,18 @@ __device__ __forceinline__ void particle_support(const float *__restrict__ pos,
                                                  const int32_t *__restrict__ cell, int64_t p,
                                                  int n, int first[3], float w[3][MAS]) {
   const float x0 = pos[3 * p + 0], x1 = pos[3 * p + 1], x2 = pos[3 * p + 2];
+  const int lg = log2_if_pow2(n);
   if constexpr (PK == PM_POS_BOX) {
     const float fn = (float)n;
-    first[0] = wrap_any(axis_box<MAS>(x0, fn, w[0]), n);
-    first[1] = wrap_any(axis_box<MAS>(x1, fn, w[1]), n);
-    first[2] = wrap_any(axis_box<MAS>(x2, fn, w[2]), n);
+    first[0] = wrap_fast(axis_box<MAS>(x0, fn, w[0]), n, lg);
+    first[1] = wrap_fast(axis_box<MAS>(x1, fn, w[1]), n, lg);
+    first[2] = wrap_fast(axis_box<MAS>(x2, fn, w[2]), n, lg);
   } else {
-    const int c = wrap_any(cell[p], n * n * n);
-    const int nn = n * n;
-    const int ci = c / nn, cj = (c / n) - ci * n, ck = c - (c / n) * n;
-    first[0] = axis_off<MAS>(ci, x0, w[0]);
-    first[1] = axis_off<MAS>(cj, x1, w[1]);
-    first[2] = axis_off<MAS>(ck, x2, w[2]);
+    int c[3];
+    decode_cell(cell[p], n, lg, c);
+    first[0] = axis_off<MAS>(c[0], x0, w[0]);
+    first[1] = axis_off<MAS>(c[1], x1, w[1]);
+    first[2] = axis_off<MAS>(c[2], x2, w[2]);
   }
 }
 
@@ -158,20 +185,18 @@ template <int PK>
 __device__ __forceinline__ void particle_cell(const float *__restrict__ pos,
                                               const int32_t *__restrict__ cell, int64_t p, int n,
                                               int c[3], float o[3]) {
+  const int lg = log2_if_pow2(n);
   if constexpr (PK == PM_POS_BOX) {
     const float fn = (float)n;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const float u = pos[3 * p + d] * fn;
       const float fl = floorf(u);
-      c[d] = wrap_any((int)fl, n);
+      c[d] = wrap_fast((int)fl, n, lg);
       o[d] = u - fl;
     }
   } else {
-    const int q = wrap_any(cell[p], n * n * n);
-    c[0] = q / (n * n);
-    c[1] = (q / n) - c[0] * n;
-    c[2] = q - (q / n) * n;
+    decode_cell(cell[p], n, lg, c);
 #pragma unroll
     for (int d = 0; d < 3; ++d) o[d] = pos[3 * p + d];
   }

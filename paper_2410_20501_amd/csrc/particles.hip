@@ -20,7 +20,10 @@ using pm_chunk::wave_max_i;
 using pm_chunk::wave_min_i;
 using pm_chunk::weights_from_frac;
 using pm_chunk::window_sep_g;
+using pm_chunk::decode_cell;
+using pm_chunk::log2_if_pow2;
 using pm_chunk::wrap_any;
+using pm_chunk::wrap_fast;
 using pm_chunk::wrap_index;
 
 constexpr int kThreads = 256;
@@ -145,20 +148,17 @@ __device__ __forceinline__ int drift_from(float *__restrict__ pos, int32_t *__re
                                           const float xin[3], int cin) {
   float x[3] = {xin[0], xin[1], xin[2]};
   int ci[3];
+  const int lg = log2_if_pow2(n);
   if constexpr (PK == PM_POS_BOX) {
     const float fn = (float)n;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       x[d] = wrap_unit(fmaf(dt, v[d], x[d]));
-      ci[d] = wrap_any((int)floorf(x[d] * fn), n);
+      ci[d] = wrap_fast((int)floorf(x[d] * fn), n, lg);
     }
   } else {
     const float scale = dt * (float)n;
-    const int c = wrap_any(cin, n * n * n);
-    const int nn = n * n;
-    ci[0] = c / nn;
-    ci[1] = (c / n) - (c / nn) * n;
-    ci[2] = c - (c / n) * n;
+    decode_cell(cin, n, lg, ci);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       float o = fmaf(scale, v[d], x[d]);
@@ -168,8 +168,7 @@ __device__ __forceinline__ int drift_from(float *__restrict__ pos, int32_t *__re
         o = 0.0f;
         fl += 1.0f;
       }
-      int q = (ci[d] + (int)fl) % n;
-      ci[d] = q < 0 ? q + n : q;
+      ci[d] = wrap_fast(ci[d] + (int)fl, n, lg);
       x[d] = o;
     }
     cell[p] = (ci[0] * n + ci[1]) * n + ci[2];
@@ -246,15 +245,13 @@ __global__ __launch_bounds__(kThreads) void k_cell_hist(const float *__restrict_
     int c = -1;
     if (p < np) {
       int q[3];
+      const int lg = log2_if_pow2(n);
       if constexpr (PK == PM_POS_BOX) {
         const float fn = (float)n;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) q[d] = wrap_any((int)floorf(pos[3 * p + d] * fn), n);
+        for (int d = 0; d < 3; ++d) q[d] = wrap_fast((int)floorf(pos[3 * p + d] * fn), n, lg);
       } else {
-        const int cc = wrap_any(cell[p], n * n * n);
-        q[0] = cc / (n * n);
-        q[1] = (cc / n) - q[0] * n;
-        q[2] = cc - (cc / n) * n;
+        decode_cell(cell[p], n, lg, q);
       }
       if constexpr (KEY == kKeyTile) {
         const int nt = n >> 3;
@@ -508,10 +505,13 @@ constexpr int kTH = kTT + 2;                  // tile + one-cell halo
 constexpr int kTHalo = kTH * kTH * kTH;       // 1000
 constexpr float kFix30 = 1073741824.0f;       // 2^30 units per unit weight
 
-__device__ __forceinline__ unsigned long long fix30(float w) {
-  // 0 <= w <= 27/64 < 2: w 2^30 fits an int32; rounding to 2^-30 keeps every bit
-  // of the FP32 weight above 2^-30
-  return (unsigned long long)(unsigned int)rintf(w * kFix30);
+// Fixed-point unit of a weight: w 2^30, with 0 <= w <= 27/64 < 2, so it fits an
+// int32. The kernels scale one axis's weights by 2^30 (exact: a power of two) and
+// truncate the product: every bit of the FP32 weight above 2^-30 is kept, and each
+// (particle, cell) pair gives the same integer on every path, so the integer sums do
+// not depend on the order of the particles.
+__device__ __forceinline__ unsigned long long fix_scaled(float w_scaled) {
+  return (unsigned long long)(unsigned int)w_scaled;
 }
 
 __device__ __forceinline__ unsigned long long wave_sum_ull(unsigned long long v) {
@@ -600,20 +600,18 @@ __device__ __forceinline__ TileParticle load_particle(const float *__restrict__ 
 template <int PK>
 __device__ __forceinline__ void cell_offset_of(const float x[3], int cin, int n, int c[3],
                                                float o[3]) {
+  const int lg = log2_if_pow2(n);
   if constexpr (PK == PM_POS_BOX) {
     const float fn = (float)n;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const float u = x[d] * fn;
       const float fl = floorf(u);
-      c[d] = wrap_any((int)fl, n);
+      c[d] = wrap_fast((int)fl, n, lg);
       o[d] = u - fl;
     }
   } else {
-    const int q = wrap_any(cin, n * n * n);
-    c[0] = q / (n * n);
-    c[1] = (q / n) - c[0] * n;
-    c[2] = q - (q / n) * n;
+    decode_cell(cin, n, lg, c);
 #pragma unroll
     for (int d = 0; d < 3; ++d) o[d] = x[d];
   }
@@ -660,12 +658,13 @@ __global__ __launch_bounds__(kDThreads) void k_deposit_own(const float *__restri
           (unsigned)lz < (unsigned)kTT;
     const int key = act ? (lx * kTT + ly) * kTT + lz : -1;
     const int rank = act ? (int)atomicAdd(&cnt[key], 1u) : 0;
-    const bool dup = __ballot(rank > 0) != 0ull;  // some cell holds two lanes of the wave
     float wx[MAS], wy[MAS], wz[MAS];
     // box coordinates are tile coordinates + 1; the window's first cell follows
     const int fx = axis_off<MAS>(lx + 1, o[0], wx);
     const int fy = axis_off<MAS>(ly + 1, o[1], wy);
     const int fz = axis_off<MAS>(lz + 1, o[2], wz);
+#pragma unroll
+    for (int t = 0; t < MAS; ++t) wz[t] *= kFix30;
     const int key_first = __shfl(key, 0, 64);
     const bool uniform = __ballot(act && key == key_first) == __ballot(l0 + (int)threadIdx.x < p_end) &&
                          key_first >= 0;
@@ -684,34 +683,48 @@ __global__ __launch_bounds__(kDThreads) void k_deposit_own(const float *__restri
 #pragma unroll
       for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b)
+        for (int b = 0; b < 3; ++b) {
+          const float eab = ex[a] * ey[b];
 #pragma unroll
           for (int cc = 0; cc < 3; ++cc) {
-            unsigned long long v = act ? fix30(ex[a] * ey[b] * ez[cc]) : 0ull;
+            unsigned long long v = act ? fix_scaled(eab * ez[cc]) : 0ull;
             v = wave_sum_ull(v);
-            if ((threadIdx.x & 63) == 0 && v)
+            if ((threadIdx.x & 63) == 0)
               atomicAdd(&box[((bx + a) * kTH + (by + b)) * kTH + (bz + cc)], v);
           }
-    } else if (act && !dup) {
-#pragma unroll
-      for (int a = 0; a < MAS; ++a)
-#pragma unroll
-        for (int b = 0; b < MAS; ++b) {
-          const float wab = wx[a] * wy[b];
-          const int row = ((fx + a) * kTH + (fy + b)) * kTH + fz;
-#pragma unroll
-          for (int cc = 0; cc < MAS; ++cc) {
-            const unsigned long long v = fix30(wab * wz[cc]);
-            if (v) atomicAdd(&box[row + cc], v);
-          }
         }
+    } else if (__ballot(rank >= MAS) == 0ull) {
+      // at most MAS lanes of the wave share a cell: the lane of rank r walks the window's
+      // k cells rotated by r, so lanes of one cell add to different LDS words in each
+      // instruction; the rotation only changes the register part of the address (the
+      // (a, b) row is the instruction's constant offset)
+      if (act) {
+        const int base = (fx * kTH + fy) * kTH + fz;
+        float pz[MAS];
+        int oz[MAS];
+#pragma unroll
+        for (int t = 0; t < MAS; ++t) {
+          const int sc = t + rank >= MAS ? t + rank - MAS : t + rank;
+          pz[t] = sc == 0 ? wz[0] : (sc == 1 ? wz[MAS > 1 ? 1 : 0] : wz[MAS - 1]);
+          oz[t] = base + sc;
+        }
+#pragma unroll
+        for (int a = 0; a < MAS; ++a)
+#pragma unroll
+          for (int b = 0; b < MAS; ++b) {
+            const float wab = wx[a] * wy[b];
+            const int row = (a * kTH + b) * kTH;
+#pragma unroll
+            for (int cc = 0; cc < MAS; ++cc)
+              atomicAdd(&box[oz[cc] + row], fix_scaled(wab * pz[cc]));
+          }
+      }
     } else if (act) {
-      // some lanes share a cell: the window's cells in an order rotated per axis by the
+      // more lanes share a cell: the window's cells in an order rotated per axis by the
       // base-MAS digits of the lane's rank among the wave's lanes in its cell, so that
       // lanes of one cell (up to MAS^3 of them) add to different LDS words in each
-      // instruction instead of serialising on one (rank 0 keeps the common order). The
-      // rotation is applied once per particle to the three weights and offsets of each
-      // axis.
+      // instruction instead of serialising on one. The rotation is applied once per
+      // particle to the three weights and offsets of each axis.
       const int r = rank % (MAS * MAS * MAS);
       const int ra = r / (MAS * MAS), rb = (r / MAS) % MAS, rc = r % MAS;
       float px[MAS], py[MAS], pz[MAS];
@@ -736,10 +749,8 @@ __global__ __launch_bounds__(kDThreads) void k_deposit_own(const float *__restri
           const float wab = px[a] * py[b];
           const int row = base + ox[a] + oy[b];
 #pragma unroll
-          for (int cc = 0; cc < MAS; ++cc) {
-            const unsigned long long v = fix30(wab * pz[cc]);
-            if (v) atomicAdd(&box[row + oz[cc]], v);
-          }
+          for (int cc = 0; cc < MAS; ++cc)
+            atomicAdd(&box[row + oz[cc]], fix_scaled(wab * pz[cc]));
         }
     }
     if (act) cnt[key] = 0u;  // counts start from zero in the next pass (same wave)
