@@ -29,7 +29,13 @@ namespace {
 constexpr int SJ = PM_SMOOTH_SJ, SK = 64;  // interior tile of the smoother (SJ, SK even)
 constexpr int ST = PM_SMOOTH_THREADS;      // threads per smoother block
 #ifndef PM_SMOOTH_BLOCKS
-#define PM_SMOOTH_BLOCKS 2048
+#define PM_SMOOTH_BLOCKS 512
+#endif
+#ifndef PM_RR_BLOCKS
+#define PM_RR_BLOCKS 2048
+#endif
+#ifndef PM_SMOOTH_WAVES
+#define PM_SMOOTH_WAVES 4  // waves per SIMD the smoother is compiled for (VGPR budget 512 / it)
 #endif
 constexpr int kSmoothBlocks = PM_SMOOTH_BLOCKS;  // blocks wanted per pass (i-chunks shrink to reach it)
 
@@ -385,7 +391,7 @@ __device__ __forceinline__ void smooth_steps(SmoothState<H, NORM, OMEGA1, PRO> &
 
 template <int H, bool NORM, bool OMEGA1, bool PRO>
 // at least 4 waves per SIMD: two 512-thread blocks (or one of 1024) per CU
-__global__ __launch_bounds__(NORM ? 2 * ST : ST) __attribute__((amdgpu_waves_per_eu(4))) void k_smooth_stream(
+__global__ __launch_bounds__(NORM ? 2 * ST : ST) __attribute__((amdgpu_waves_per_eu(PM_SMOOTH_WAVES))) void k_smooth_stream(
     const float *__restrict__ uin, float *__restrict__ uout, const float *__restrict__ f,
     float fscale, const float *__restrict__ fmean, int n, int ci, float h2, float omega,
     int first_colour, double *__restrict__ partial, float uscale, const float *__restrict__ ec) {
@@ -701,7 +707,7 @@ hipError_t launch_rr_stream(const float *u, const float *f, float fscale, const 
                             hipStream_t s) {
   const int nc = n / 2;
   const int tj = (nc + CJ - 1) / CJ, tk = (nc + CK - 1) / CK;
-  const int cic = chunk_for(nc, tj * tk, 1024, 8);
+  const int cic = chunk_for(nc, tj * tk, PM_RR_BLOCKS, 8);
   dim3 grid(tk, tj, nc / cic);
   if (kind == PM_RESTRICT_AVG)
     k_rr_stream<PM_RESTRICT_AVG><<<grid, RT, 0, s>>>(u, f, fscale, fmean, n, cic, inv_h2, fc, ucg,
