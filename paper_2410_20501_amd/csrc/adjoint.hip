@@ -270,6 +270,112 @@ __global__ __launch_bounds__(kVThreads) void k_interp_vjp_chunk(
   }
 }
 
+// Interpolation transpose through the 8^3-tile buckets of a counting sort (the
+// deposit's sort): one workgroup per tile stages the force grid of the tile and its
+// one-cell halo in LDS (the position term's gathers) and adds the particle cotangents'
+// window weights to a 10^3 box of three components in LDS; the box is then added to
+// g_bar with one global atomic per touched cell and component (the tiles' boxes
+// overlap on their halos). A particle whose window leaves the box (not possible for a
+// bucket that matches its positions) takes the per-weight global path.
+constexpr int kVTThreads = 256;
+constexpr int kVTT = 8, kVTH = kVTT + 2, kVTHalo = kVTH * kVTH * kVTH;
+
+template <int MAS, int PK>
+__global__ __launch_bounds__(kVTThreads) void k_interp_vjp_tile(
+    const float *__restrict__ pos, const int32_t *__restrict__ cell,
+    const int32_t *__restrict__ end, const int32_t *__restrict__ perm, int n,
+    const float *__restrict__ g, const float *__restrict__ lam, float pscale, float gscale,
+    float *__restrict__ g_bar, float *__restrict__ pos_bar) {
+  __shared__ float4 gs[kVTHalo];
+  __shared__ float acc[3][kVTHalo];
+  const int nt = n / kVTT;
+  const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
+  const int p_begin = tile > 0 ? end[tile - 1] : 0, p_end = end[tile];
+  if (p_begin >= p_end) return;
+  const int t0[3] = {(tile / (nt * nt)) * kVTT, ((tile / nt) % nt) * kVTT, (tile % nt) * kVTT};
+  auto box_cell = [&](int h) -> size_t {
+    const int hx = h / (kVTH * kVTH), hy = (h / kVTH) % kVTH, hz = h % kVTH;
+    return ((size_t)wrap_index(t0[0] + hx - 1, n) * n + wrap_index(t0[1] + hy - 1, n)) * n +
+           wrap_index(t0[2] + hz - 1, n);
+  };
+  for (int h = threadIdx.x; h < kVTHalo; h += kVTThreads) {
+    if (pos_bar) {
+      const size_t gc = box_cell(h);
+      gs[h] = make_float4(g[3 * gc], g[3 * gc + 1], g[3 * gc + 2], 0.0f);
+    }
+    acc[0][h] = acc[1][h] = acc[2][h] = 0.0f;
+  }
+  __syncthreads();
+  for (int l = p_begin + (int)threadIdx.x; l < p_end; l += kVTThreads) {
+    const int p = perm[l];
+    int first[3];
+    float w[3][MAS], dw[3][MAS];
+    support_wdw<MAS, PK>(pos, cell, p, n, first, w, dw);
+    int b[3];
+    bool inbox = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      int lf = first[d] - t0[d];
+      lf += lf < -n / 2 ? n : 0;
+      lf -= lf > n / 2 ? n : 0;
+      b[d] = lf + 1;
+      inbox = inbox && b[d] >= 0 && b[d] <= kVTH - MAS;
+    }
+    const float l0 = lam[3 * (size_t)p], l1 = lam[3 * (size_t)p + 1], l2 = lam[3 * (size_t)p + 2];
+    float gx = 0.f, gy = 0.f, gz = 0.f;
+#pragma unroll
+    for (int a = 0; a < MAS; ++a)
+#pragma unroll
+      for (int bb = 0; bb < MAS; ++bb) {
+        const float wab = w[0][a] * w[1][bb];
+#pragma unroll
+        for (int c = 0; c < MAS; ++c) {
+          const int h = ((b[0] + a) * kVTH + (b[1] + bb)) * kVTH + (b[2] + c);
+          size_t gc = 0;
+          if (!inbox)
+            gc = ((size_t)wrap_index(first[0] + a, n) * n + wrap_index(first[1] + bb, n)) * n +
+                 wrap_index(first[2] + c, n);
+          if (pos_bar) {
+            float4 gv;
+            if (inbox) gv = gs[h];
+            else gv = make_float4(g[3 * gc], g[3 * gc + 1], g[3 * gc + 2], 0.0f);
+            const float gl = gv.x * l0 + gv.y * l1 + gv.z * l2;
+            gx = fmaf(dw[0][a] * w[1][bb] * w[2][c], gl, gx);
+            gy = fmaf(w[0][a] * dw[1][bb] * w[2][c], gl, gy);
+            gz = fmaf(w[0][a] * w[1][bb] * dw[2][c], gl, gz);
+          }
+          if (g_bar) {
+            const float wt = gscale * wab * w[2][c];
+            if (inbox) {
+              atomicAdd(&acc[0][h], wt * l0);
+              atomicAdd(&acc[1][h], wt * l1);
+              atomicAdd(&acc[2][h], wt * l2);
+            } else {
+              unsafeAtomicAdd(&g_bar[3 * gc + 0], wt * l0);
+              unsafeAtomicAdd(&g_bar[3 * gc + 1], wt * l1);
+              unsafeAtomicAdd(&g_bar[3 * gc + 2], wt * l2);
+            }
+          }
+        }
+      }
+    if (pos_bar) {
+      pos_bar[3 * (size_t)p + 0] += pscale * gx;
+      pos_bar[3 * (size_t)p + 1] += pscale * gy;
+      pos_bar[3 * (size_t)p + 2] += pscale * gz;
+    }
+  }
+  if (!g_bar) return;
+  __syncthreads();
+  for (int h = threadIdx.x; h < kVTHalo; h += kVTThreads) {
+    const float v0 = acc[0][h], v1 = acc[1][h], v2 = acc[2][h];
+    if (v0 == 0.0f && v1 == 0.0f && v2 == 0.0f) continue;
+    const size_t gc = box_cell(h);
+    unsafeAtomicAdd(&g_bar[3 * gc + 0], v0);
+    unsafeAtomicAdd(&g_bar[3 * gc + 1], v1);
+    unsafeAtomicAdd(&g_bar[3 * gc + 2], v2);
+  }
+}
+
 // Transpose of g = -D phi with D the central difference of the gradient table:
 // phi_bar += sum_d D_d g_bar_d  (D_d^T = -D_d for the antisymmetric stencil).
 template <int P>
@@ -455,6 +561,26 @@ hipError_t launch_interp_vjp(const float *pos, const int32_t *cell, int64_t np, 
     else PM_IV(2, PM_POS_CELLOFF);
   }
 #undef PM_IV
+  return hipGetLastError();
+}
+
+hipError_t launch_interp_vjp_tile(const float *pos, const int32_t *cell, int64_t np, int poskind,
+                                  int mas, int n, const int32_t *end, const int32_t *perm,
+                                  const float *g, const float *lam, float pscale, float gscale,
+                                  float *g_bar, float *pos_bar, hipStream_t s) {
+  if (np == 0) return hipSuccess;
+  const unsigned nt = (unsigned)((int64_t)(n / kVTT) * (n / kVTT) * (n / kVTT));
+#define PM_IVT(M, K)                                                                         \
+  k_interp_vjp_tile<M, K><<<nt, kVTThreads, 0, s>>>(pos, cell, end, perm, n, g, lam, pscale, \
+                                                    gscale, g_bar, pos_bar)
+  if (mas == PM_TSC) {
+    if (poskind == PM_POS_BOX) PM_IVT(3, PM_POS_BOX);
+    else PM_IVT(3, PM_POS_CELLOFF);
+  } else {
+    if (poskind == PM_POS_BOX) PM_IVT(2, PM_POS_BOX);
+    else PM_IVT(2, PM_POS_CELLOFF);
+  }
+#undef PM_IVT
   return hipGetLastError();
 }
 

@@ -385,6 +385,28 @@ int ensure_adjoint_scratch(pm_ctx *ctx) {
   return PM_OK;
 }
 
+// interp^T: through the tile buckets of a tile sort of the positions when the grid has
+// 8^3 tiles (the sort overwrites the deposit's sort scratch, so the histogram a fused
+// drift left there is dropped), else per chunk of consecutive particles
+int interp_vjp_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, int poskind,
+                    int mas, const float *g, const float *lam, float pscale, float gscale,
+                    float *g_bar, float *pos_bar, hipStream_t s) {
+  const int n = ctx->n;
+  if (n % 8 == 0 && np > 0 && np <= INT32_MAX) {
+    int st = ensure_sort_scratch(ctx, np);
+    if (st != PM_OK) return st;
+    ctx->hist_ready = false;
+    ctx->hist_next = false;
+    PM_HIP(ctx, launch_sort_by_cell(ctx, pos, cell, np, poskind, s, 2, false));
+    PM_HIP(ctx, launch_interp_vjp_tile(pos, cell, np, poskind, mas, n, ctx->cell_count,
+                                       ctx->perm, g, lam, pscale, gscale, g_bar, pos_bar, s));
+    return PM_OK;
+  }
+  PM_HIP(ctx, launch_interp_vjp(pos, cell, np, poskind, mas, n, g, lam, pscale, gscale, g_bar,
+                                pos_bar, s));
+  return PM_OK;
+}
+
 // pos_bar += scale * J(pos)^T lam, J = d accel / d pos at scale factor a (box units).
 // phi is the potential of pos at a. Uses ctx->g (force grid), the adjoint scratch and
 // ctx->rho (cotangent of the density).
@@ -397,8 +419,9 @@ int accel_vjp_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t n
   PM_HIP(ctx, launch_gradient(phi, n, 5, ctx->g, s));
   PM_HIP(ctx, launch_fill(ctx->adj_gbar, 0.0f, 3 * ncell, s));
   // g_bar = interp^T lam, and the position term sum_c grad W (g_c . lam_p)
-  PM_HIP(ctx, launch_interp_vjp(pos, cell, np, poskind, p->mas, n, ctx->g, lam, scale * (float)n,
-                                1.0f, ctx->adj_gbar, pos_bar, s));
+  if (int st = interp_vjp_impl(ctx, pos, cell, np, poskind, p->mas, ctx->g, lam, scale * (float)n,
+                               1.0f, ctx->adj_gbar, pos_bar, s))
+    return st;
   // phi_bar = sum_d D_d g_bar_d
   PM_HIP(ctx, launch_divergence(ctx->adj_gbar, n, 5, false, ctx->adj_phibar, s));
   // rho_bar = coef L^+ (phi_bar - mean): the solve is self-adjoint
@@ -847,9 +870,8 @@ int pm_interp_vjp(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np
   if (np > 0 && !lam) return pm_fail(ctx, PM_ERR_ARG, "null lam");
   if (!g_bar && !pos_bar) return pm_fail(ctx, PM_ERR_ARG, "both outputs null");
   if (pos_bar && !g) return pm_fail(ctx, PM_ERR_ARG, "pos_bar needs g");
-  PM_HIP(ctx, launch_interp_vjp(pos, cell, np, poskind, mas, ctx->n, g, lam, (float)ctx->n, 1.0f,
-                                g_bar, pos_bar, (hipStream_t)stream));
-  return PM_OK;
+  return interp_vjp_impl(ctx, pos, cell, np, poskind, mas, g, lam, (float)ctx->n, 1.0f, g_bar,
+                         pos_bar, (hipStream_t)stream);
 }
 
 int pm_gradient_vjp(pm_ctx *ctx, const float *g_bar, int points, float *phi_bar,

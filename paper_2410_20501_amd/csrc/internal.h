@@ -20,7 +20,7 @@ struct pm_level {
 };
 
 #ifndef PM_STREAM_MIN_N
-#define PM_STREAM_MIN_N 256   // levels at least this large use the streaming kernels
+#define PM_STREAM_MIN_N 128   // levels at least this large use the streaming kernels
 #endif
 
 // one grid of the f(R) full-approximation-storage hierarchy (FP64)
@@ -171,6 +171,12 @@ hipError_t launch_deposit_vjp(const float *pos, const int32_t *cell, int64_t np,
 hipError_t launch_interp_vjp(const float *pos, const int32_t *cell, int64_t np, int poskind,
                              int mas, int n, const float *g, const float *lam, float pscale,
                              float gscale, float *g_bar, float *pos_bar, hipStream_t s);
+// the same through the 8^3-tile buckets (end, perm) of a tile sort of these positions
+// (n % 8 == 0)
+hipError_t launch_interp_vjp_tile(const float *pos, const int32_t *cell, int64_t np, int poskind,
+                                  int mas, int n, const int32_t *end, const int32_t *perm,
+                                  const float *g, const float *lam, float pscale, float gscale,
+                                  float *g_bar, float *pos_bar, hipStream_t s);
 hipError_t launch_divergence(const float *gb, int n, int points, bool accumulate, float *phib,
                              hipStream_t s);
 hipError_t launch_axpy(float *y, const float *x, float alpha, int64_t count, hipStream_t s);
