@@ -40,16 +40,16 @@ MEASURED_TRAFFIC = {
     # and the post-smoothing pass (with the prolongation) weighted by their counts (45
     # and 39 dispatches)
     "smooth": ("paper_2410_20501_amd/csrc/mg_stream.hip",
-               "05d60bb6a194e21ebd3b57963895793c2f1650bdd920de3d26fb92930595c244",
-               743905.0, 539558.0, 2.0, 1.0),
+               "8bcfe77415275f8b65a09616b990d3926d1d216e1138cd5b3e7ffb008fd7e991",
+               868085.0, 528114.0, 2.0, 1.0),
     # deposit: the particle-owned tile kernel plus the gather pass over the tile boxes
     "deposit": ("paper_2410_20501_amd/csrc/particles.hip",
-                "f57991d28eb5cd43cc0ee842cc95c3685c4323f22df9d44156ea54b6e5331550",
-                2493321.0, 2573651.0, 2.0, 1.0),
+                "858c00d7abdcbe38589b6d15dd9ddc720ef29853cd37858ffc3bdf6709ea6f17",
+                2005610.0, 1549791.0, 2.0, 1.0),
     # interpolation with the fused gradient, kicks and drift of a chained step
     "interp": ("paper_2410_20501_amd/csrc/particles.hip",
-               "f57991d28eb5cd43cc0ee842cc95c3685c4323f22df9d44156ea54b6e5331550",
-               2750314.0, 5295974.0, 2.0, 1.0),
+               "858c00d7abdcbe38589b6d15dd9ddc720ef29853cd37858ffc3bdf6709ea6f17",
+               2749282.0, 5320506.0, 2.0, 1.0),
 }
 
 
