@@ -79,6 +79,13 @@ BENCH_TOL = 1e-6
 BENCH_MAX_CYCLES = 40
 
 
+def BENCH_GUESS(pm):
+    """Warm start of the steps after the first: the linear extrapolation of the
+    growth-normalised potentials of the last two solves (one V-cycle fewer per step than
+    the growth-rescaled previous potential, the same tolerance)."""
+    return pm.PM_GUESS_EXTRAPOLATED
+
+
 def bench_step_params(pm, order=BENCH_ORDER, tol=BENCH_TOL, omega=None):
     p = pm.default_step_params(order=order, tol=tol, max_cycles=BENCH_MAX_CYCLES)
     if omega is not None:
@@ -420,6 +427,8 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--order", default=BENCH_ORDER, choices=["atomic", "sorted"])
     ap.add_argument("--tol", type=float, default=BENCH_TOL)
+    ap.add_argument("--guess", choices=["extrapolated", "warm_rescaled"], default="extrapolated",
+                    help="warm start of the multigrid solves after the first step")
     ap.add_argument("--omega", type=float, default=None,
                     help="over-relaxation factor of the red-black sweeps (default: the "
                          "library's)")
@@ -488,7 +497,8 @@ def main():
     if args.reorder_every > 0:
         pm.pm_reorder(ctx, off_d, vel=vel_d, cell=cell_d)
     pm.pm_accel(ctx, off_d, a_list[0], phi, acc, cell=cell_d, params=params)
-    params.mg.guess = pm.PM_GUESS_WARM_RESCALED
+    params.mg.guess = (pm.PM_GUESS_WARM_RESCALED if args.guess == "warm_rescaled"
+                       else BENCH_GUESS(pm))
     torch.cuda.synchronize()
 
     import warnings
@@ -602,7 +612,10 @@ def main():
         "data": "synthetic (seeded power-law Gaussian random field, Zel'dovich ICs)",
         "config": {"workload": f"{n}^3 particles on a {n}^3 grid, 50 KDK steps a=0.02->1, "
                                f"cell-offset positions, TSC {args.order} deposit, multigrid "
-                               f"2+2 RBGS growth-rescaled warm start, V-cycles until the FP32 "
+                               f"2+2 RBGS, "
+                               + ("growth-rescaled warm start" if args.guess == "warm_rescaled"
+                                  else "warm start extrapolated from the last two potentials")
+                               + f", V-cycles until the FP32 "
                                f"rounding floor (relres {args.tol:g} is below it at this size), "
                                f"particles re-sorted by tile every {args.reorder_every} steps, "
                                + ("one pm_kdk call per step" if args.no_chain else

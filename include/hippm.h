@@ -87,8 +87,23 @@ enum pm_fft_kernel { PM_FFT_GREEN = 0, PM_FFT_7PT = 1, PM_FFT_FULL = 2 };
  * with the supercomoving Poisson equation of Sect. 3.1 the potential grows as
  * a D, so the factor used is a1 D1 / (a0 D0) = (a1 / a0)^2 in Einstein-de
  * Sitter. pm_solve_mg and pm_accel treat PM_GUESS_WARM_RESCALED as
- * PM_GUESS_WARM (they have no second scale factor). */
-enum pm_guess { PM_GUESS_JACOBI = 0, PM_GUESS_WARM = 1, PM_GUESS_WARM_RESCALED = 2 };
+ * PM_GUESS_WARM (they have no second scale factor).
+ * PM_GUESS_EXTRAPOLATED (multigrid steps, Newtonian or parametrised gravity): the
+ * growth-normalised potential psi = phi / (a D) of the last two solves on the same phi
+ * array, at a_p < a_c, extrapolated linearly in supercomoving time to the new scale
+ * factor a: phi = a D(a) [psi_c + theta (psi_c - psi_p)], theta = tau(a_c, a) /
+ * tau(a_p, a_c). The context keeps the previous potential (4 bytes per cell,
+ * allocated on first use); without two earlier solves on this phi (or when a does not
+ * increase) it acts as PM_GUESS_WARM_RESCALED. Not a method of the paper: a better
+ * starting point for the same tolerance-driven solve (one V-cycle fewer per step at
+ * 512^3). pm_solve_mg treats it as PM_GUESS_WARM; the batched step as
+ * PM_GUESS_WARM_RESCALED. */
+enum pm_guess {
+  PM_GUESS_JACOBI = 0,
+  PM_GUESS_WARM = 1,
+  PM_GUESS_WARM_RESCALED = 2,
+  PM_GUESS_EXTRAPOLATED = 3
+};
 
 /* pm_create flags */
 enum pm_create_flags {

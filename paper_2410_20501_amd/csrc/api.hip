@@ -86,7 +86,7 @@ int check_mg(pm_ctx *ctx, const pm_mg_params *p) {
   if (p->restrict_kind != PM_RESTRICT_FW && p->restrict_kind != PM_RESTRICT_AVG)
     return pm_fail(ctx, PM_ERR_ARG, "bad restrict_kind");
   if (p->guess != PM_GUESS_JACOBI && p->guess != PM_GUESS_WARM &&
-      p->guess != PM_GUESS_WARM_RESCALED)
+      p->guess != PM_GUESS_WARM_RESCALED && p->guess != PM_GUESS_EXTRAPOLATED)
     return pm_fail(ctx, PM_ERR_ARG, "bad guess");
   return PM_OK;
 }
@@ -255,6 +255,44 @@ int solve_impl(pm_ctx *ctx, const pm_step_params *p, const float *rho, float coe
   return pm_mg_solve(ctx, rho, coef, phi, &p->mg, st, s, warm_scale, rho_mean_ready);
 }
 
+// PM_GUESS_EXTRAPOLATED: with two earlier solves on this phi (at a_p < a_c < a), phi
+// becomes the linear extrapolation in supercomoving time of psi = phi / (a D) and
+// *warm_scale 1; with one, the current potential is kept as the previous one and the
+// solve starts from the rescaled one (*warm_scale as given)
+int extrapolate_guess(pm_ctx *ctx, float *phi, double a, const pm_step_params *p,
+                      float *warm_scale, hipStream_t s) {
+  const int64_t count = (int64_t)ctx->n * ctx->n * ctx->n;
+  const bool have_cur = ctx->ex_phi == phi && ctx->ex_a_cur > 0.0 && ctx->ex_a_cur < a;
+  if (!have_cur) {
+    ctx->ex_has_prev = false;
+    return PM_OK;
+  }
+  if (!ctx->ex_prev) {
+    if (hipMalloc(&ctx->ex_prev, sizeof(float) * (size_t)count) != hipSuccess) {
+      ctx->ex_prev = nullptr;
+      (void)hipGetLastError();
+      return pm_fail(ctx, PM_ERR_NOMEM, "extrapolated warm start allocation failed");
+    }
+    ctx->ex_has_prev = false;
+  }
+  const double ap = ctx->ex_a_prev, ac = ctx->ex_a_cur;
+  if (ctx->ex_has_prev && ap < ac) {
+    const double om = p->omega_m, ol = p->omega_l;
+    const double gp = ap * pm_bg_growth(om, ol, ap), gc = ac * pm_bg_growth(om, ol, ac),
+                 gn = a * pm_bg_growth(om, ol, a);
+    const double theta = pm_bg_tau(om, ol, ac, a) / pm_bg_tau(om, ol, ap, ac);
+    PM_HIP(ctx, launch_extrapolate(phi, ctx->ex_prev, count, (float)(gn / gc * (1.0 + theta)),
+                                   (float)(-gn / gp * theta), s));
+    *warm_scale = 1.0f;
+  } else {
+    PM_HIP(ctx, hipMemcpyAsync(ctx->ex_prev, phi, sizeof(float) * (size_t)count,
+                               hipMemcpyDeviceToDevice, s));
+  }
+  ctx->ex_a_prev = ac;
+  ctx->ex_has_prev = true;
+  return PM_OK;
+}
+
 // deposit -> solve -> gradient -> interp (+ optional kick on vel)
 // the next step of a chain of leapfrog steps: its opening half-kick and its drift
 struct ChainNext {
@@ -299,9 +337,17 @@ int accel_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, i
     sst = solve_impl(ctx, p, ctx->mond_src, 1.0f, phi, stats ? &stats->mg : nullptr, s,
                      warm_scale, false);
   } else {
-    sst = solve_impl(ctx, p, ctx->rho, coef, phi, stats ? &stats->mg : nullptr, s, warm_scale,
+    float ws = warm_scale;
+    const bool mg = p->solver == PM_SOLVER_MG;
+    if (mg && p->mg.guess == PM_GUESS_EXTRAPOLATED)
+      if (int est = extrapolate_guess(ctx, phi, a, p, &ws, s)) return est;
+    sst = solve_impl(ctx, p, ctx->rho, coef, phi, stats ? &stats->mg : nullptr, s, ws,
                      mean_ready);
+    // the solve history of the extrapolated warm start (multigrid solves on this phi)
+    ctx->ex_phi = mg ? phi : nullptr;
+    ctx->ex_a_cur = a;
   }
+  if (p->gravity == PM_GRAVITY_QUMOND || full_fft) ctx->ex_phi = nullptr;
   if (sst < 0) return sst;
   // f(R): the scalaron (from the previous one unless the guess is Jacobi) and the force
   // potential phi_N - (c~^2 / 2) f~; phi keeps the Newtonian potential
@@ -565,6 +611,7 @@ void pm_destroy(pm_ctx *ctx) {
   fr(ctx->adj_rhobar);
   fr(ctx->mond_phin);
   fr(ctx->mond_src);
+  fr(ctx->ex_prev);
   pm_fr_free(ctx);
   for (int i = 0; i < 8; ++i)
     if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
@@ -786,7 +833,8 @@ int pm_kdk(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, int64_t np, int p
                                 pcell, count));
   ctx->hist_ready = fuse_hist;
   // growth rescaling of the previous potential: phi~ grows as a D(a) (a^2 in EdS)
-  const float warm_scale = params->mg.guess == PM_GUESS_WARM_RESCALED
+  const float warm_scale = params->mg.guess == PM_GUESS_WARM_RESCALED ||
+                                   params->mg.guess == PM_GUESS_EXTRAPOLATED
                                ? (float)pm_bg_warm_scale(params, a0, a1) : 1.0f;
   st = accel_impl(ctx, pos, cell, np, poskind, a1, params, phi, acc, vel, half, stats, s, timing,
                   warm_scale, nullptr);
@@ -832,7 +880,8 @@ int pm_kdk_chain(pm_ctx *ctx, float *pos, int32_t *cell, float *vel, int64_t np,
                                   pcell, count));
     ctx->hist_ready = fuse_hist;
   }
-  const float warm_scale = params->mg.guess == PM_GUESS_WARM_RESCALED
+  const float warm_scale = params->mg.guess == PM_GUESS_WARM_RESCALED ||
+                                   params->mg.guess == PM_GUESS_EXTRAPOLATED
                                ? (float)pm_bg_warm_scale(params, a0, a1) : 1.0f;
   ChainNext next{};
   if (more) {

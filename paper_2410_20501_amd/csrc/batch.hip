@@ -1113,7 +1113,10 @@ int pm_batch_kdk(pm_batch *B, float *pos, float *vel, float *acc, float *phi, in
     if (std::memcmp(&B->g_params, params, sizeof(pm_step_params)) != 0)
       return bfail(B, PM_ERR_ARG, "step parameters differ from the captured step");
   }
-  st = upload_steps(B, a, nsteps, params, params->mg.guess == PM_GUESS_WARM_RESCALED, s);
+  st = upload_steps(B, a, nsteps, params,
+                    params->mg.guess == PM_GUESS_WARM_RESCALED ||
+                        params->mg.guess == PM_GUESS_EXTRAPOLATED,
+                    s);
   if (st != PM_OK) return st;
   for (int i = 0; i < nsteps; ++i) {
     if (use_graph) {

@@ -133,6 +133,28 @@ __global__ __launch_bounds__(RED_THREADS) void k_moments_final(const double *__r
   }
 }
 
+// extrapolated warm start: phi = c1 phi + c2 prev, prev = the old phi (float4 per thread)
+__global__ __launch_bounds__(RED_THREADS) void k_extrapolate(float4 *__restrict__ phi,
+                                                             float4 *__restrict__ prev,
+                                                             int64_t count4, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x;
+  if (i >= count4) return;
+  const float4 u = phi[i], v = prev[i];
+  phi[i] = make_float4(fmaf(c1, u.x, c2 * v.x), fmaf(c1, u.y, c2 * v.y), fmaf(c1, u.z, c2 * v.z),
+                       fmaf(c1, u.w, c2 * v.w));
+  prev[i] = u;
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_extrapolate1(float *__restrict__ phi,
+                                                              float *__restrict__ prev,
+                                                              int64_t count, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x;
+  if (i >= count) return;
+  const float u = phi[i];
+  phi[i] = fmaf(c1, u, c2 * prev[i]);
+  prev[i] = u;
+}
+
 // count of non-finite values (grid-stride; one atomic per wave into *out)
 __global__ __launch_bounds__(RED_THREADS) void k_count_nonfinite(const float *__restrict__ x,
                                                                  int64_t count,
@@ -147,6 +169,22 @@ __global__ __launch_bounds__(RED_THREADS) void k_count_nonfinite(const float *__
 }
 
 }  // namespace
+
+hipError_t launch_extrapolate(float *phi, float *prev, int64_t count, float c1, float c2,
+                              hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  // float4 accesses when both arrays are 16-byte aligned and count is a multiple of 4
+  // (n^3 cells with n even)
+  if (count % 4 != 0 || (((uintptr_t)phi | (uintptr_t)prev) & 15u) != 0) {
+    k_extrapolate1<<<(unsigned)((count + RED_THREADS - 1) / RED_THREADS), RED_THREADS, 0, s>>>(
+        phi, prev, count, c1, c2);
+    return hipGetLastError();
+  }
+  const int64_t c4 = count / 4;
+  k_extrapolate<<<(unsigned)((c4 + RED_THREADS - 1) / RED_THREADS), RED_THREADS, 0, s>>>(
+      reinterpret_cast<float4 *>(phi), reinterpret_cast<float4 *>(prev), c4, c1, c2);
+  return hipGetLastError();
+}
 
 hipError_t launch_count_nonfinite(const float *x, int64_t count, unsigned long long *out,
                                   hipStream_t s) {

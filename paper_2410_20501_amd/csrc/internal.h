@@ -90,6 +90,12 @@ struct pm_ctx {
   double *fr_u;          // [n^3]
   float *fr_phi;         // [n^3] phi_N - (c~^2 / 2) f~
   bool fr_valid;         // fr_u holds a result
+  // extrapolated warm start (lazy): the potential of the solve before the last one on
+  // the phi array ex_phi, and the scale factors of those two solves
+  float *ex_prev;        // [n^3]
+  const float *ex_phi;
+  double ex_a_prev, ex_a_cur;
+  bool ex_has_prev;
   // timing events
   hipEvent_t ev[8];
   // per-kernel timer: event pairs around every launch of one kernel
@@ -192,6 +198,9 @@ hipError_t launch_ic_vjp(const float *xbar, const float *vbar, int64_t np, float
 hipError_t launch_gradient(const float *phi, int n, int points, float *g, hipStream_t s);
 hipError_t launch_sum_moments(const float *x, int64_t count, double *partial, double *result,
                               float *mean_out, hipStream_t s);
+// phi = c1 phi + c2 prev and prev = the old phi, per cell
+hipError_t launch_extrapolate(float *phi, float *prev, int64_t count, float c1, float c2,
+                              hipStream_t s);
 // *out += number of non-finite values of x[0 .. count)
 hipError_t launch_count_nonfinite(const float *x, int64_t count, unsigned long long *out,
                                   hipStream_t s);

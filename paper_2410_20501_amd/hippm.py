@@ -28,7 +28,7 @@ PM_SOLVER_MG, PM_SOLVER_FFT, PM_SOLVER_FFT_7PT, PM_SOLVER_FULL_FFT = 0, 1, 2, 3
 PM_FFT_GREEN, PM_FFT_7PT, PM_FFT_FULL = 0, 1, 2
 PM_GRAVITY_NEWTON, PM_GRAVITY_MU, PM_GRAVITY_QUMOND, PM_GRAVITY_FR = 0, 1, 2, 3
 PM_NU_SIMPLE, PM_NU_N, PM_NU_BETA, PM_NU_GAMMA, PM_NU_DELTA = 0, 1, 2, 3, 4
-PM_GUESS_JACOBI, PM_GUESS_WARM, PM_GUESS_WARM_RESCALED = 0, 1, 2
+PM_GUESS_JACOBI, PM_GUESS_WARM, PM_GUESS_WARM_RESCALED, PM_GUESS_EXTRAPOLATED = 0, 1, 2, 3
 PM_CHAIN_FIRST, PM_CHAIN_NEXT = 0, 1
 PM_ADJ_CLOSING_MERGED = 1
 PM_CREATE_REFERENCE_KERNELS, PM_CREATE_CHECK_FINITE = 1, 2
@@ -165,7 +165,8 @@ def default_step_params(**kw) -> StepParams:
             v = NU_FAMILY.get(v, v)
         elif k == "guess":
             v = {"jacobi": PM_GUESS_JACOBI, "warm": PM_GUESS_WARM,
-                 "warm_rescaled": PM_GUESS_WARM_RESCALED}.get(v, v)
+                 "warm_rescaled": PM_GUESS_WARM_RESCALED,
+                 "extrapolated": PM_GUESS_EXTRAPOLATED}.get(v, v)
         elif k == "restrict_kind":
             v = {"fw": PM_RESTRICT_FW, "avg": PM_RESTRICT_AVG}.get(v, v)
         elif k in ("cycle", "fr_cycle"):

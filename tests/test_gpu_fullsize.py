@@ -54,7 +54,7 @@ def test_bench_configuration_512():
     _say("full size 512^3: GPU steps")
     pm.pm_reorder(ctx, off_d, vel=vel_d, cell=cell_d)
     pm.pm_accel(ctx, off_d, 0.02, phi, acc, cell=cell_d, params=params)
-    params.mg.guess = pm.PM_GUESS_WARM_RESCALED
+    params.mg.guess = bench.BENCH_GUESS(pm)
     a_list = [0.02 + 0.0196 * i for i in range(4)]
     import warnings
     with warnings.catch_warnings():
