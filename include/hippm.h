@@ -93,8 +93,10 @@ enum pm_fft_kernel { PM_FFT_GREEN = 0, PM_FFT_7PT = 1, PM_FFT_FULL = 2 };
  * array, at a_p < a_c, extrapolated linearly in supercomoving time to the new scale
  * factor a: phi = a D(a) [psi_c + theta (psi_c - psi_p)], theta = tau(a_c, a) /
  * tau(a_p, a_c). The context keeps the previous potential (4 bytes per cell,
- * allocated on first use); without two earlier solves on this phi (or when a does not
- * increase) it acts as PM_GUESS_WARM_RESCALED. Not a method of the paper: a better
+ * allocated on first use). The history is the last two solves on this phi array in a
+ * run of consecutive PM_GUESS_EXTRAPOLATED steps (the solve before the run may have any
+ * guess); without it, when a does not increase, or with fixed_cycles > 0, the step acts
+ * as PM_GUESS_WARM_RESCALED. Not a method of the paper: a better
  * starting point for the same tolerance-driven solve (one V-cycle fewer per step at
  * 512^3). pm_solve_mg treats it as PM_GUESS_WARM; the batched step as
  * PM_GUESS_WARM_RESCALED. */

@@ -339,8 +339,14 @@ int accel_impl(pm_ctx *ctx, const float *pos, const int32_t *cell, int64_t np, i
   } else {
     float ws = warm_scale;
     const bool mg = p->solver == PM_SOLVER_MG;
-    if (mg && p->mg.guess == PM_GUESS_EXTRAPOLATED)
+    // extrapolation only for tolerance-driven solves: a fixed cycle count must not depend
+    // on a history the caller does not see
+    const bool extrap = mg && p->mg.guess == PM_GUESS_EXTRAPOLATED && p->mg.fixed_cycles == 0;
+    if (extrap) {
       if (int est = extrapolate_guess(ctx, phi, a, p, &ws, s)) return est;
+    } else {
+      ctx->ex_has_prev = false;  // ex_prev is not this solve's predecessor
+    }
     sst = solve_impl(ctx, p, ctx->rho, coef, phi, stats ? &stats->mg : nullptr, s, ws,
                      mean_ready);
     // the solve history of the extrapolated warm start (multigrid solves on this phi)
