@@ -191,8 +191,9 @@ def bench_adjoint(n=128, steps=20, reps=3):
     run.close()
     f, b = min(tf), min(tb)
     return {
-        "workload": f"{n}^3 particles, {steps} KDK steps a=0.1->0.3, TSC, multigrid tol 1e-6, "
-                    f"cell-offset positions, checkpoints every 4 steps, loss sum w delta^2",
+        "workload": f"{n}^3 particles, {steps} KDK steps a=0.1->0.3, TSC, multigrid tol 1e-6 "
+                    f"(adjoint solves 1e-5), cell-offset positions, checkpoints every 4 steps, "
+                    f"loss sum w delta^2",
         "forward_ms": 1e3 * f, "forward_and_gradient_ms": 1e3 * b,
         "gradient_over_forward": b / f,
         "forward_particle_steps_per_s": n ** 3 * steps / f,

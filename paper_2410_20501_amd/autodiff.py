@@ -28,11 +28,21 @@ class Run:
     poskind "box" keeps box-unit FP32 positions; "celloff" keeps the in-cell offset
     and an int32 cell index (positions resolved to 2^-24 of a cell instead of 2^-24
     of the box). Gradients are with respect to box-unit quantities in both forms.
+
+    warm: the forward steps' multigrid guess. "warm_rescaled" (the default) keeps the
+    warm start inside the checkpointed state, so a recomputed segment replays the forward
+    pass bitwise; "extrapolated" also draws on the solves of earlier steps, which a
+    recomputation from a checkpoint does not see, so the replay can differ at the level of
+    the solver tolerance.
+    adj_tol: truncation-error tolerance of the transposed (adjoint) Poisson solves. The
+    forward FP32 solves leave potentials accurate to about 1e-6 relative, and the adjoint
+    source is built from them; at 1e-5 the gradient moves by about 1e-6 relative from its
+    value at 1e-6 and the adjoint solves take one to two V-cycles fewer.
     """
 
     def __init__(self, n, np_, a_list, mas="tsc", order="sorted", solver="mg", tol=1e-6,
                  max_cycles=40, fixed_cycles=0, checkpoint_every=4, warm="warm_rescaled",
-                 poskind="box"):
+                 poskind="box", adj_tol=1e-5):
         if checkpoint_every < 1:
             raise ValueError("checkpoint_every must be >= 1")
         if poskind not in ("box", "celloff"):
@@ -48,7 +58,7 @@ class Run:
                       fixed_cycles=fixed_cycles)
         self.first = _pm.default_step_params(guess="jacobi", **common)
         self.step = _pm.default_step_params(guess=warm, **common)
-        self.adj = _pm.default_step_params(guess="jacobi", **common)
+        self.adj = _pm.default_step_params(guess="jacobi", **dict(common, tol=adj_tol))
         self.stats = {"forward_steps": 0, "recomputed_steps": 0, "adjoint_evals": 0}
 
     @property
