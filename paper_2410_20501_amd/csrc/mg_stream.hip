@@ -88,12 +88,12 @@ __device__ void block_triple_to_partial(double s1, double s2, double s3, double 
 // masked either: points near the tile edge read padding or wrapped-row values and come
 // out wrong, but a wrong value moves inward by one cell per half-sweep and the halo is
 // H cells wide, so the interior is exact.
-// The norm-accumulating pass runs twice the threads with half the pairs each: at two
-// pairs per thread its extra live values spill, and a spill reload waits for the
-// plane prefetches.
-template <int H, bool NORM>
+// The norm-accumulating and the prolongating passes run twice the threads with half the
+// pairs each: at two pairs per thread their extra live values spill, and a spill reload
+// waits for the plane prefetches.
+template <int H, bool NORM, bool PRO = false>
 struct SmoothShape {
-  static constexpr int NT = NORM ? 2 * ST : ST;     // threads per block
+  static constexpr int NT = (NORM || PRO) ? 2 * ST : ST;  // threads per block
   static constexpr int RJ = SJ + 2 * H, RK = SK + 2 * H, RK2 = RK / 2, NPAIR = RJ * RK2;
   static constexpr int PP = (NPAIR + NT - 1) / NT;  // pairs per thread
   // LDS: per published plane one array of E values and one of O values, each indexed
@@ -118,7 +118,7 @@ constexpr int smooth_prefetch() {
 
 template <int H, bool NORM, bool OMEGA1, bool PRO>
 struct SmoothState {
-  using S = SmoothShape<H, NORM>;
+  using S = SmoothShape<H, NORM, PRO>;
   // per-thread constants
   // LDS index of the pair in a colour array (padding included); the first of the two
   // k-neighbours of E (in the O array) is li - 1 + offe, of O (in the E array) li - offe,
@@ -213,12 +213,41 @@ __device__ __forceinline__ void smooth_relax(float (&u)[RING][PP], const float (
   }
 }
 
-// LDS slot of half-sweep s in a step with q = R mod RING. With NORM the slot of s = 1
-// alternates between slot 0 and slot H, so the input values of plane q - 2 published by
-// the previous step are still there for the residual of plane q - 1.
+#ifndef PM_SMOOTH_LDS_SETS
+#define PM_SMOOTH_LDS_SETS 1
+#endif
+// LDS slot sets. With one set every plane step ends with a barrier before the next step
+// overwrites the slots. With rotating sets (step q publishes into set q mod sets) the
+// barrier that starts a step also guarantees that every wave has finished reading the
+// set the step after next overwrites, so a step needs one barrier. The residual of the
+// norm pass also reads the previous step's set, hence three sets; they rotate with the
+// ring of planes, whose length must then be a multiple of three.
+template <int H, bool NORM>
+constexpr int lds_sets() {
+  return PM_SMOOTH_LDS_SETS == 0 ? 1 : (NORM ? ((H + 2) % 3 == 0 ? 3 : 1) : 2);
+}
+
+// LDS slot of half-sweep s in a step with q = R mod RING. With one set and NORM the slot
+// of s = 1 alternates between slot 0 and slot H, so the input values of plane q - 2
+// published by the previous step are still there for the residual of plane q - 1.
 template <int R, int H, bool NORM>
 constexpr int lds_slot(int s) {
+  constexpr int sets = lds_sets<H, NORM>();
+  if constexpr (sets > 1) return (R % sets) * H + s - 1;
   return (NORM && s == 1 && (R & 1)) ? H : s - 1;
+}
+
+// slot of the previous step's s = 1 values (the norm pass's plane q - 2 inputs)
+template <int R, int H>
+constexpr int lds_prev_slot1() {
+  constexpr int sets = lds_sets<H, true>();
+  if constexpr (sets > 1) return ((R + sets - 1) % sets) * H;
+  return lds_slot<R + 1, H, true>(1);
+}
+
+template <int H, bool NORM>
+constexpr int lds_slots() {
+  return lds_sets<H, NORM>() > 1 ? lds_sets<H, NORM>() * H : H + (NORM ? 1 : 0);
 }
 
 // ring slot of plane q - d in a step with q = R mod RING
@@ -230,7 +259,7 @@ constexpr int ring_slot(int d) {
 // Half-sweep S of a plane step: plane q - S.
 template <int R, int S, int H, bool NORM, bool OMEGA1, bool PRO>
 __device__ __forceinline__ void smooth_half(SmoothState<H, NORM, OMEGA1, PRO> &c, int q) {
-  using Sh = SmoothShape<H, NORM>;
+  using Sh = SmoothShape<H, NORM, PRO>;
   constexpr int RING = Sh::RING, PP = Sh::PP, RK2 = Sh::RK2;
   constexpr int c0 = ring_slot<R, RING>(0), c1 = ring_slot<R, RING>(1);
   constexpr int cs = ring_slot<R, RING>(S), cm = ring_slot<R, RING>(S + 1),
@@ -257,7 +286,7 @@ __device__ __forceinline__ void smooth_norm(SmoothState<H, true, OMEGA1, PRO> &c
   const int p = q - 1;
   if (p < c.i0 || p >= c.i0 + c.ci) return;  // uniform
   const float *LE = c.lds + lds_slot<R, H, true>(1) * Sh::SLOT, *LO = LE + Sh::ARR;
-  const float *PE = c.lds + lds_slot<R + 1, H, true>(1) * Sh::SLOT, *PO = PE + Sh::ARR;
+  const float *PE = c.lds + lds_prev_slot1<R, H>() * Sh::SLOT, *PO = PE + Sh::ARR;
   float sr = 0.f, sf = 0.f, su = 0.f;  // this plane's few terms in FP32, the sums in FP64
 #pragma unroll
   for (int t = 0; t < PP; ++t) {
@@ -290,7 +319,7 @@ __device__ __forceinline__ void smooth_halves(SmoothState<H, NORM, OMEGA1, PRO> 
 // One plane of the pipeline, for ring position R = q mod RING (q has the parity of R).
 template <int R, int H, bool NORM, bool OMEGA1, bool PRO>
 __device__ __forceinline__ void smooth_step(SmoothState<H, NORM, OMEGA1, PRO> &c, int q) {
-  using Sh = SmoothShape<H, NORM>;
+  using Sh = SmoothShape<H, NORM, PRO>;
   constexpr int RING = Sh::RING, PP = Sh::PP, SLOT = Sh::SLOT;
   constexpr int PF = smooth_prefetch<H, NORM, PRO>();
   constexpr int P = R % PF;  // prefetch slot of plane q
@@ -377,29 +406,33 @@ __device__ __forceinline__ void smooth_step(SmoothState<H, NORM, OMEGA1, PRO> &c
             c.swp[t] ? make_float2(b, a) : make_float2(a, b);
       }
   }
-  // the LDS slots are rewritten by the next plane
-  __syncthreads();
+  // the LDS slots are rewritten by the next plane (rotating sets: by the one after it,
+  // behind the next step's barrier)
+  if constexpr (lds_sets<H, NORM>() == 1) __syncthreads();
 }
 
 template <int R, bool GUARD, int H, bool NORM, bool OMEGA1, bool PRO>
 __device__ __forceinline__ void smooth_steps(SmoothState<H, NORM, OMEGA1, PRO> &c, int q) {
-  if constexpr (R < SmoothShape<H, NORM>::RING) {
+  if constexpr (R < SmoothShape<H, NORM, PRO>::RING) {
     if (!GUARD || q + R < c.qend) smooth_step<R, H, NORM, OMEGA1, PRO>(c, q + R);
     smooth_steps<R + 1, GUARD, H, NORM, OMEGA1, PRO>(c, q);
   }
 }
 
 template <int H, bool NORM, bool OMEGA1, bool PRO>
-// at least 4 waves per SIMD: two 512-thread blocks (or one of 1024) per CU
-__global__ __launch_bounds__(NORM ? 2 * ST : ST) __attribute__((amdgpu_waves_per_eu(PM_SMOOTH_WAVES))) void k_smooth_stream(
+// at least 4 waves per SIMD: two 512-thread blocks (or one of 1024) per CU; with rotating
+// LDS sets (60 to 90 KB per block) that is also what the LDS holds
+__global__ __launch_bounds__((SmoothShape<H, NORM, PRO>::NT)) __attribute__((amdgpu_waves_per_eu(PM_SMOOTH_WAVES))) void k_smooth_stream(
     const float *__restrict__ uin, float *__restrict__ uout, const float *__restrict__ f,
     float fscale, const float *__restrict__ fmean, int n, int ci, float h2, float omega,
     int first_colour, double *__restrict__ partial, float uscale, const float *__restrict__ ec) {
-  using S = SmoothShape<H, NORM>;
+  using S = SmoothShape<H, NORM, PRO>;
   constexpr int PF = smooth_prefetch<H, NORM, PRO>();
   static_assert(S::RING % 2 == 0 && S::RING % PF == 0,
                 "plane parity and prefetch slots repeat within one ring period");
-  constexpr int NSLOT = H + (NORM ? 1 : 0);
+  static_assert(lds_sets<H, NORM>() == 1 || S::RING % lds_sets<H, NORM>() == 0,
+                "LDS slot sets rotate with the ring of planes");
+  constexpr int NSLOT = lds_slots<H, NORM>();
   __shared__ float lds[NSLOT * S::SLOT];
   __shared__ float craw[PRO ? S::CPLANE : 1];
   __shared__ float __align__(8) ckl[PRO ? 3 * S::KPLANE : 2];
@@ -514,8 +547,8 @@ __global__ __launch_bounds__(RT) void k_rr_stream(const float *__restrict__ u,
                                                   int cic, float inv_h2,
                                                   float *__restrict__ fc,
                                                   float *__restrict__ ucg, float gscale) {
-  __shared__ float Lu[UNP];
-  __shared__ float Lr[UNP];
+  __shared__ float Lu[2 * UNP];  // u of the last two published planes
+  __shared__ float Lr[2 * UNP];  // residual of the last two planes
   const int nc = n >> 1;
   const unsigned lin = xcd_block(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
                                  gridDim.x * gridDim.y * gridDim.z);
@@ -535,9 +568,9 @@ __global__ __launch_bounds__(RT) void k_rr_stream(const float *__restrict__ u,
     rkv[t] = e < UNP ? e % UK : -100;
     colv[t] = e < UNP ? (uint32_t)(wrap_any(fj0 + rjv[t], n) * n + wrap_any(fk0 + rkv[t], n)) : 0u;
   }
-  float um[UPPT], uc[UPPT], up[UPPT];  // planes p-1, p, p+1
-  float fcur[UPPT], fnext[UPPT];       // f of planes p and p+1
-  float nu[UPPT];                      // prefetched u of the next plane
+  float um[UPPT], uc[UPPT], up[UPPT];  // u of planes t - 2, t - 1, t
+  float fcur[UPPT], fnext[UPPT];       // f of planes t - 1 and t
+  float nu[UPPT];                      // prefetched u of plane t + 1
   float acc[3][CPPT];                  // coarse accumulators indexed by coarse plane mod 3
 #pragma unroll
   for (int a = 0; a < 3; ++a)
@@ -559,83 +592,96 @@ __global__ __launch_bounds__(RT) void k_rr_stream(const float *__restrict__ u,
         fnext[t] = f[fplane + colv[t]];
       }
   };
+  // One barrier per fine plane: iteration t publishes u of plane t (Lu), forms the
+  // residual of plane t - 1 from the previous iteration's Lu (Lr), and restricts the
+  // residual of plane t - 2 from the previous iteration's Lr. Lu and Lr alternate between
+  // two buffers by plane parity, so a buffer is rewritten two iterations after it was
+  // written, behind the barrier that ended every read of it.
   prefetch(pbeg - 1);
-  for (int q = pbeg - 1; q <= pend; ++q) {
+  for (int t = pbeg - 1; t <= pend + 1; ++t) {
 #pragma unroll
-    for (int t = 0; t < UPPT; ++t) {
-      um[t] = uc[t];
-      uc[t] = up[t];
-      up[t] = nu[t];
-      fcur[t] = fnext[t];  // f of plane q - 1
+    for (int v = 0; v < UPPT; ++v) {
+      um[v] = uc[v];
+      uc[v] = up[v];
+      up[v] = nu[v];       // u of plane t
+      fcur[v] = fnext[v];  // f of plane t - 1
     }
-    if (q < pend) prefetch(q + 1);
-    const int p = q - 1;  // residual plane
-    if (p < pbeg) continue;
+    if (t < pend) prefetch(t + 1);
+    if (t >= pbeg && t < pend) {
+      float *lu = Lu + (t & 1) * UNP;
 #pragma unroll
-    for (int t = 0; t < UPPT; ++t)
-      if (rjv[t] >= 0) Lu[rjv[t] * UK + rkv[t]] = uc[t];
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < UPPT; ++t) {
-      const int rj = rjv[t], rk = rkv[t];
-      if (rj < 1 || rj >= UJ - 1 || rk < 1 || rk >= UK - 1) continue;
-      const int e = rj * UK + rk;
-      const float c = uc[t];
-      const float lap = (Lu[e - UK] - c) + (Lu[e + UK] - c) + (Lu[e - 1] - c) + (Lu[e + 1] - c) +
-                        (um[t] - c) + (up[t] - c);
-      Lr[e] = fscale * (fcur[t] - m) - lap * inv_h2;
+      for (int v = 0; v < UPPT; ++v)
+        if (rjv[v] >= 0) lu[rjv[v] * UK + rkv[v]] = up[v];
     }
-    __syncthreads();
-    // restrict within the plane, then accumulate into the coarse planes
+    if (t - 1 >= pbeg && t - 1 < pend) {
+      // residual of plane t - 1 (centre uc, i-neighbours um and up)
+      const float *lu = Lu + ((t - 1) & 1) * UNP;
+      float *lr = Lr + ((t - 1) & 1) * UNP;
 #pragma unroll
-    for (int c = 0; c < CPPT; ++c) {
-      const int cidx = threadIdx.x + c * RT;
-      const int cj = cidx / CK, ck = cidx % CK;
-      float s = 0.f;
-      if constexpr (KIND == PM_RESTRICT_FW) {
-        // fine (2J-1 .. 2J+2) relative to the region: rj = 2 cj + 1 + b
-        const float w[4] = {1.f, 3.f, 3.f, 1.f};
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const float *row = Lr + (2 * cj + 1 + b) * UK + 2 * ck + 1;
-          s = fmaf(w[b], row[0] + 3.f * (row[1] + row[2]) + row[3], s);
-        }
-        // only coarse planes owned by this block accumulate (slots are shared mod 3)
-        const int Ip = (p >= 0) ? p / 2 : -((1 - p) / 2);
-        const bool odd = (p & 1) != 0;
-        const int Io = odd ? Ip + 1 : Ip - 1;
-        if (Ip >= I0 && Ip < I0 + cic) acc[Ip % 3][c] += 3.f * s;
-        if (Io >= I0 && Io < I0 + cic) acc[Io % 3][c] += s;
-      } else {
-        const float *row0 = Lr + (2 * cj + 2) * UK + 2 * ck + 2;
-        s = row0[0] + row0[1] + row0[UK] + row0[UK + 1];
-        acc[(p >> 1) % 3][c] += s;
+      for (int v = 0; v < UPPT; ++v) {
+        const int rj = rjv[v], rk = rkv[v];
+        if (rj < 1 || rj >= UJ - 1 || rk < 1 || rk >= UK - 1) continue;
+        const int e = rj * UK + rk;
+        const float c = uc[v];
+        const float lap = (lu[e - UK] - c) + (lu[e + UK] - c) + (lu[e - 1] - c) +
+                          (lu[e + 1] - c) + (um[v] - c) + (up[v] - c);
+        lr[e] = fscale * (fcur[v] - m) - lap * inv_h2;
       }
     }
-    // coarse plane complete: FW after fine 2 I + 2 (p even, I = p/2 - 1); AVG after 2 I + 1
-    int Idone;
-    bool done;
-    if constexpr (KIND == PM_RESTRICT_FW) {
-      done = ((p & 1) == 0) && p >= 2 * I0 + 2;
-      Idone = p / 2 - 1;
-    } else {
-      done = (p & 1) == 1;
-      Idone = p >> 1;
-    }
-    if (done) {
-      const int slot = Idone % 3;
-      const float scale = (KIND == PM_RESTRICT_FW) ? (1.0f / 512.0f) : 0.125f;
+    const int p = t - 2;  // plane restricted in this iteration
+    if (p >= pbeg && p < pend) {
+      const float *Lrp = Lr + (p & 1) * UNP;
+      // restrict within the plane, then accumulate into the coarse planes
 #pragma unroll
       for (int c = 0; c < CPPT; ++c) {
         const int cidx = threadIdx.x + c * RT;
-        const int J = J0 + cidx / CK, K = K0 + cidx % CK;
-        if (J < nc && K < nc) {
-          const size_t ci = ((size_t)Idone * nc + J) * nc + K;
-          const float v = acc[slot][c] * scale;
-          fc[ci] = v;
-          if (ucg) ucg[ci] = gscale * v;  // coarse starting guess -H^2 f_H / 6
+        const int cj = cidx / CK, ck = cidx % CK;
+        float s = 0.f;
+        if constexpr (KIND == PM_RESTRICT_FW) {
+          // fine (2J-1 .. 2J+2) relative to the region: rj = 2 cj + 1 + b
+          const float w[4] = {1.f, 3.f, 3.f, 1.f};
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const float *row = Lrp + (2 * cj + 1 + b) * UK + 2 * ck + 1;
+            s = fmaf(w[b], row[0] + 3.f * (row[1] + row[2]) + row[3], s);
+          }
+          // only coarse planes owned by this block accumulate (slots are shared mod 3)
+          const int Ip = (p >= 0) ? p / 2 : -((1 - p) / 2);
+          const bool odd = (p & 1) != 0;
+          const int Io = odd ? Ip + 1 : Ip - 1;
+          if (Ip >= I0 && Ip < I0 + cic) acc[Ip % 3][c] += 3.f * s;
+          if (Io >= I0 && Io < I0 + cic) acc[Io % 3][c] += s;
+        } else {
+          const float *row0 = Lrp + (2 * cj + 2) * UK + 2 * ck + 2;
+          s = row0[0] + row0[1] + row0[UK] + row0[UK + 1];
+          acc[(p >> 1) % 3][c] += s;
         }
-        acc[slot][c] = 0.f;
+      }
+      // coarse plane complete: FW after fine 2 I + 2 (p even, I = p/2 - 1); AVG after 2 I + 1
+      int Idone;
+      bool done;
+      if constexpr (KIND == PM_RESTRICT_FW) {
+        done = ((p & 1) == 0) && p >= 2 * I0 + 2;
+        Idone = p / 2 - 1;
+      } else {
+        done = (p & 1) == 1;
+        Idone = p >> 1;
+      }
+      if (done) {
+        const int slot = Idone % 3;
+        const float scale = (KIND == PM_RESTRICT_FW) ? (1.0f / 512.0f) : 0.125f;
+#pragma unroll
+        for (int c = 0; c < CPPT; ++c) {
+          const int cidx = threadIdx.x + c * RT;
+          const int J = J0 + cidx / CK, K = K0 + cidx % CK;
+          if (J < nc && K < nc) {
+            const size_t ci = ((size_t)Idone * nc + J) * nc + K;
+            const float v = acc[slot][c] * scale;
+            fc[ci] = v;
+            if (ucg) ucg[ci] = gscale * v;  // coarse starting guess -H^2 f_H / 6
+          }
+          acc[slot][c] = 0.f;
+        }
       }
     }
     __syncthreads();
@@ -670,7 +716,7 @@ hipError_t launch_smooth_stream(const float *uin, float *uout, const float *f, f
   const bool pro = ec != nullptr;
   if (norm && pro) return hipErrorInvalidValue;  // the norm pass is a pre-smoothing pass
 #define PM_SMOOTH_LAUNCH(H_, N_, O_, P_)                                                 \
-  k_smooth_stream<H_, N_, O_, P_><<<grid, (SmoothShape<H_, N_>::NT), 0, s>>>(           \
+  k_smooth_stream<H_, N_, O_, P_><<<grid, (SmoothShape<H_, N_, P_>::NT), 0, s>>>(       \
       uin, uout, f, fscale, fmean, n, ci, h2, omega, first_colour, partial, uscale, ec)
 #define PM_SMOOTH_PLAIN(H_)                                                              \
   do {                                                                                   \
