@@ -605,8 +605,8 @@ def test_interp_parity(lib, mas, poskind):
 # ------------------------------------------------------------------ full step
 
 def _run_gpu(lib, n, pos, vel, a_list, solver="mg", celloff=False, order="atomic",
-             guess="warm", stats=None):
-    ctx = ctx_for(lib, n, pos.shape[0])
+             guess="warm", stats=None, ctx=None):
+    ctx = ctx or ctx_for(lib, n, pos.shape[0])
     params = lib.default_step_params(solver=solver, order=order, tol=1e-7, max_cycles=40)
     phi = torch.zeros((n, n, n), device="cuda")
     acc = torch.empty((pos.shape[0], 3), device="cuda")
@@ -681,6 +681,34 @@ def test_ten_steps_extrapolated_warm_start(lib):
     assert rel_l2(acc, accr) <= 1e-5 * 10
     assert all(e[1] < r[1] for e, r in zip(se[1:], sr[1:]))
     assert sum(c for c, _ in se) <= sum(c for c, _ in sr)
+
+
+def test_extrapolated_warm_start_streaming_128(lib):
+    """At 128^3 the finest level streams (the first pass of the tolerance loop also forms
+    the residual norm of the extrapolated starting guess); with the reference kernels it
+    does not. Six steps give the same trajectory both ways (the two smoothers differ only
+    in rounding) and the same starting residual in every step, and the extrapolation
+    starts each step from a smaller residual than the growth-rescaled warm start."""
+    _say("extrapolated warm start, streaming vs reference kernels, 128^3")
+    n = 128
+    pos, vel = lattice_ics(n, -1.5, 0.3, 0.1, seed=5)
+    a_list = list(np.linspace(0.1, 0.16, 7))
+    ref_ctx = lib.Context(n, pos.shape[0], lib.PM_CREATE_REFERENCE_KERNELS)
+    sf, sr, sw = [], [], []
+    xf, vf, af, pf = _run_gpu(lib, n, pos, vel, a_list, order="sorted", guess="extrapolated",
+                              stats=sf)
+    xr, vr, ar, pr = _run_gpu(lib, n, pos, vel, a_list, order="sorted", guess="extrapolated",
+                              stats=sr, ctx=ref_ctx)
+    _run_gpu(lib, n, pos, vel, a_list, order="sorted", guess="warm_rescaled", stats=sw)
+    ref_ctx.close()
+    _say(f"  cycles streaming {[c for c, _ in sf]} reference {[c for c, _ in sr]}; first residuals "
+         f"{[f'{r:.3e}' for _, r in sf]} vs {[f'{r:.3e}' for _, r in sr]} "
+         f"(rescaled {[f'{r:.1e}' for _, r in sw]})")
+    assert opm.periodic_distance(xf, xr).max() <= 1e-6
+    assert rel_l2(af, ar) <= 1e-5
+    assert rel_l2(pf, pr) <= 1e-5
+    assert all(abs(f[1] - r[1]) <= 1e-2 * r[1] for f, r in zip(sf, sr))
+    assert all(f[1] < w[1] for f, w in zip(sf[1:], sw[1:]))
 
 
 def test_sorted_and_atomic_steps_agree(lib):
