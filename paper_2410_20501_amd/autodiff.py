@@ -7,10 +7,11 @@ A run from a displacement field psi at lattice points q is
     (x_{i+1}, v_{i+1}) = KDK(x_i, v_i; a_i -> a_{i+1})    leapfrog, Sect. 3.4
 and the gradient of a loss of the final state comes back through the
 transposed leapfrog. The forward pass keeps (x, v, acc, phi) only every
-`checkpoint_every` steps; the backward pass re-runs each segment from its
-checkpoint (bitwise identical with the sorted deposit, since the multigrid
-warm start is part of the checkpoint), keeping the positions and potentials of
-the segment, and reverses it step by step with pm_kdk_adjoint. The second kick
+`checkpoint_every` steps and at the end; the backward pass re-runs each segment
+from its checkpoint but for its last step, whose end state is the next checkpoint
+(bitwise identical with the sorted deposit, since the multigrid warm start is part
+of the checkpoint), keeping the positions and potentials of the segment, and
+reverses it step by step with pm_kdk_adjoint. The second kick
 of one reversed step and the first kick of the step before act on the same
 positions and cotangent, so they are merged: a run of N steps costs N + 1
 transposed force evaluations.
@@ -131,7 +132,9 @@ class Trajectory(torch.autograd.Function):
         for i in range(run.nsteps):
             run.advance(pos, vel, cell, phi, acc, i)
             run.stats["forward_steps"] += 1
-            if (i + 1) % run.k == 0 and i + 1 < run.nsteps:
+            # every k-th state, and the final one: the state at the end of a segment is
+            # the next checkpoint, so the backward pass recomputes k - 1 steps per segment
+            if (i + 1) % run.k == 0 or i + 1 == run.nsteps:
                 checkpoints[i + 1] = snap()
         ctx.run = run
         ctx.checkpoints = checkpoints
@@ -146,15 +149,18 @@ class Trajectory(torch.autograd.Function):
         ref = pos_bar if pos_bar is not None else vel_bar
         xbar = torch.zeros_like(ref) if pos_bar is None else pos_bar.detach().clone().contiguous()
         vbar = torch.zeros_like(ref) if vel_bar is None else vel_bar.detach().clone().contiguous()
-        starts = sorted(cps)
+        starts = sorted(t for t in cps if t < nsteps)
         for seg, s0 in reversed(list(enumerate(starts))):
             s1 = starts[seg + 1] if seg + 1 < len(starts) else nsteps
+            states = [(cps[s0][0], cps[s0][2], cps[s0][3])]  # (pos, cell, phi) at s0
             pos, vel, cell, phi, acc = (t.clone() for t in cps[s0])
-            states = [(pos.clone(), cell.clone(), phi.clone())]
-            for i in range(s0, s1):
+            for i in range(s0, s1 - 1):
                 run.advance(pos, vel, cell, phi, acc, i)
                 run.stats["recomputed_steps"] += 1
                 states.append((pos.clone(), cell.clone(), phi.clone()))
+            # the segment's last step ends at the next checkpoint (bitwise the state the
+            # recomputation would give: the sorted deposit and the warm starts replay)
+            states.append((cps[s1][0], cps[s1][2], cps[s1][3]))
             for i in reversed(range(s0, s1)):
                 # the closing term of step i was merged into the opening term of step i + 1
                 # (same positions, same cotangent), except for the last step
