@@ -542,8 +542,10 @@ int pm_power_spectrum(pm_ctx *ctx, const float *rho, int deconv, int nbins, doub
  * V-cycles (mg.fixed_cycles >= 1; same smoother, restriction, prolongation and
  * coarsest-level solve as pm_solve_mg, levels halved down to at most 16 cells
  * per side), so a step never synchronises with the host and can be captured
- * as a graph. Deposit is the atomic form (FP32 atomics). The batch owns the
- * density, force and multigrid arenas (about 21 bytes per cell). */
+ * as a graph. Deposit is the chunked form with its sums in 64-bit fixed point
+ * (integer atomics into a per-cell fixed-point arena, then one conversion pass), so a
+ * step is bitwise reproducible. The batch owns the density, fixed-point, force and
+ * multigrid arenas (about 29 bytes per cell). */
 typedef struct pm_batch pm_batch;
 
 /* n[b]: even, 8 .. 1024, halving while > 16 and a multiple of 4 must end at <= 20;

@@ -138,11 +138,9 @@ struct BatchIndex {
 // rho_box += w W(u_p - c - 1/2), w = n^3 / np of the box: the chunked LDS deposit
 // (deposit_chunk.h) for every (box, chunk) item
 template <int MAS>
-__global__ __launch_bounds__(pm_chunk::kGThreads) void kb_deposit(const float *__restrict__ pos,
-                                                                  const int2 *__restrict__ items,
-                                                                  int nitems,
-                                                                  const BoxDev *__restrict__ boxes,
-                                                                  float *__restrict__ rho) {
+__global__ __launch_bounds__(pm_chunk::kGThreads) void kb_deposit(
+    const float *__restrict__ pos, const int2 *__restrict__ items, int nitems,
+    const BoxDev *__restrict__ boxes, unsigned long long *__restrict__ fix) {
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     __syncthreads();  // the previous item's LDS tables are no longer read
     const int2 item = items[it];
@@ -161,8 +159,36 @@ __global__ __launch_bounds__(pm_chunk::kGThreads) void kb_deposit(const float *_
       idx.i0 = idx.j0 = idx.k0 = 0;
       idx.p0 = bx.p0 + (int64_t)item.y * pm_chunk::kGChunk;
     }
-    const float mass = (float)((double)bx.n * bx.n * bx.n / (double)bx.np);
-    pm_chunk::deposit_chunk<MAS, PM_POS_BOX>(pos, nullptr, idx, bx.n, mass, rho + bx.c0);
+    pm_chunk::deposit_chunk<MAS, PM_POS_BOX, BatchIndex, true>(pos, nullptr, idx, bx.n, 0.0f,
+                                                               nullptr, fix + bx.c0);
+  }
+}
+
+// rho = w 2^-30 fix (w = n^3 / np of the box), fix = 0 for the next deposit, and the
+// per-item FP64 partial sums of rho (fixed order), one item of cells at a time
+__global__ __launch_bounds__(kThreads) void kb_fix_to_rho(unsigned long long *__restrict__ fix,
+                                                          float *__restrict__ rho,
+                                                          const int2 *__restrict__ items,
+                                                          int nitems,
+                                                          const BoxDev *__restrict__ boxes,
+                                                          double *__restrict__ partial) {
+  __shared__ double lds[kThreads / 64];
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int2 item = items[it];
+    const BoxDev &bx = boxes[item.x];
+    const int64_t count = (int64_t)bx.n * bx.n * bx.n;
+    const double scale = (double)count / (double)bx.np * (1.0 / 1073741824.0);
+    const int64_t c = (int64_t)item.y * kThreads + threadIdx.x;
+    double v = 0.0;
+    if (c < count) {
+      const unsigned long long q = fix[bx.c0 + c];
+      fix[bx.c0 + c] = 0ull;
+      const float r = (float)((double)q * scale);
+      rho[bx.c0 + c] = r;
+      v = (double)r;
+    }
+    const double sum = block_sum<kThreads>(v, lds);
+    if (threadIdx.x == 0) partial[it] = sum;
   }
 }
 
@@ -677,6 +703,7 @@ struct pm_batch {
   int *range = nullptr;             // [nboxes + 1] item range of each box in cells[0]
   // arenas
   float *rho = nullptr, *g = nullptr, *lu = nullptr, *lf = nullptr;
+  unsigned long long *fix = nullptr;  // [ncell_total] fixed-point deposit, zero between steps
   float *rmean = nullptr, *pmean = nullptr;
   double *partial = nullptr;        // 2 per item of cells[0]
   double *relres = nullptr;         // [nboxes]
@@ -728,16 +755,16 @@ int enqueue_accel(pm_batch *B, const float *pos, float *acc, float *vel, float *
                   const pm_step_params *p, bool first, bool with_residual, hipStream_t s) {
   const Arenas A{phi, B->rho, B->lu, B->lf, B->rmean, B->steps, B->ctr};
   // deposit
-  kb_fill<<<flat_grid(B->ncell_total), kThreads, 0, s>>>(B->rho, B->ncell_total, 0.0f);
+  // (exact fixed-point sums: the density is the same for every run and every order)
   if (p->mas == PM_TSC)
     kb_deposit<3><<<persist_grid(B->chunks.count), pm_chunk::kGThreads, 0, s>>>(
-        pos, B->items + B->chunks.off, B->chunks.count, B->boxes, B->rho);
+        pos, B->items + B->chunks.off, B->chunks.count, B->boxes, B->fix);
   else
     kb_deposit<2><<<persist_grid(B->chunks.count), pm_chunk::kGThreads, 0, s>>>(
-        pos, B->items + B->chunks.off, B->chunks.count, B->boxes, B->rho);
+        pos, B->items + B->chunks.off, B->chunks.count, B->boxes, B->fix);
   const pm_batch::List &c0 = B->cells[0];
-  kb_sum_partial<<<persist_grid(c0.count), kThreads, 0, s>>>(B->rho, B->items + c0.off, c0.count,
-                                                             B->boxes, B->partial);
+  kb_fix_to_rho<<<persist_grid(c0.count), kThreads, 0, s>>>(B->fix, B->rho, B->items + c0.off,
+                                                            c0.count, B->boxes, B->partial);
   kb_sum_final<<<B->nboxes, kThreads, 0, s>>>(B->partial, B->range, B->boxes, B->rmean);
   // multigrid: starting guess, then a fixed number of V-cycles
   if (first)
@@ -1025,6 +1052,7 @@ int pm_batch_create(pm_batch **out, int nboxes, const int *n, const int64_t *np,
   alloc((void **)&B->items, sizeof(int2) * B->items_h.size());
   alloc((void **)&B->range, sizeof(int) * (nboxes + 1));
   alloc((void **)&B->rho, sizeof(float) * B->ncell_total);
+  alloc((void **)&B->fix, sizeof(unsigned long long) * B->ncell_total);
   alloc((void **)&B->g, 3 * sizeof(float) * B->ncell_total);
   alloc((void **)&B->lu, sizeof(float) * B->lev_total);
   alloc((void **)&B->lf, sizeof(float) * B->lev_total);
@@ -1040,6 +1068,7 @@ int pm_batch_create(pm_batch **out, int nboxes, const int *n, const int64_t *np,
                  hipMemcpyHostToDevice) != hipSuccess ||
        hipMemcpy(B->range, range.data(), sizeof(int) * (nboxes + 1), hipMemcpyHostToDevice) !=
            hipSuccess ||
+       hipMemset(B->fix, 0, sizeof(unsigned long long) * B->ncell_total) != hipSuccess ||
        hipEventCreateWithFlags(&B->steps_copied, hipEventDisableTiming) != hipSuccess))
     st = PM_ERR_HIP;
   if (st != PM_OK) {
@@ -1055,7 +1084,7 @@ void pm_batch_destroy(pm_batch *B) {
   (void)hipDeviceSynchronize();
   if (B->exec) (void)hipGraphExecDestroy(B->exec);
   if (B->graph) (void)hipGraphDestroy(B->graph);
-  void *ptrs[] = {B->boxes, B->items, B->range, B->rho, B->g, B->lu, B->lf, B->rmean,
+  void *ptrs[] = {B->boxes, B->items, B->range, B->rho, B->fix, B->g, B->lu, B->lf, B->rmean,
                   B->pmean, B->partial, B->relres, B->steps, B->ctr};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -1176,12 +1205,11 @@ int pm_tune(pm_batch *B, float *pos, float *phi, const pm_step_params *params, i
   BHIP(B, hipEventCreate(&e1));
   const Arenas A{phi, B->rho, B->lu, B->lf, B->rmean, B->steps, B->ctr};
   // a valid source: deposit the current particles and their means
-  kb_fill<<<flat_grid(B->ncell_total), kThreads, 0, s>>>(B->rho, B->ncell_total, 0.0f);
   kb_deposit<3><<<persist_grid(B->chunks.count), pm_chunk::kGThreads, 0, s>>>(
-      pos, B->items + B->chunks.off, B->chunks.count, B->boxes, B->rho);
+      pos, B->items + B->chunks.off, B->chunks.count, B->boxes, B->fix);
   const pm_batch::List &c0 = B->cells[0];
-  kb_sum_partial<<<persist_grid(c0.count), kThreads, 0, s>>>(B->rho, B->items + c0.off, c0.count,
-                                                             B->boxes, B->partial);
+  kb_fix_to_rho<<<persist_grid(c0.count), kThreads, 0, s>>>(B->fix, B->rho, B->items + c0.off,
+                                                            c0.count, B->boxes, B->partial);
   kb_sum_final<<<B->nboxes, kThreads, 0, s>>>(B->partial, B->range, B->boxes, B->rmean);
   const int cpts[3] = {1, 2, 4};
   float best_s = 1e30f, best_g = 1e30f;

@@ -11,7 +11,8 @@
 //      run at several T ops/s on gfx950, float ones far slower; integer sums are
 //      also exact, whatever the order);
 //   3. each touched cell of the box is added to the grid with one FP32 global
-//      atomic (so the last bits may differ between runs).
+//      atomic (so the last bits may differ between runs), or, for a 64-bit
+//      fixed-point grid, one integer global atomic (exact: the same in every run).
 // Chunks whose box exceeds the LDS table fall back to one global atomic per
 // weight. Which particles form a chunk is the caller's choice (an Index object
 // maps the chunk's slots to particle rows, -1 for an empty slot): runs of
@@ -227,9 +228,14 @@ struct LatticeIndex {
   }
 };
 
-template <int MAS, int PK, class Index>
+// FIXED: the sums go to a 64-bit fixed-point grid (2^-30 per unit weight, no mass) with
+// integer global atomics instead of FP32 ones, so the grid is exact and the same for
+// every order of the particles and chunks (rho and mass are then unused); each
+// (particle, cell) weight becomes the same integer on the LDS path and the fallback.
+template <int MAS, int PK, class Index, bool FIXED = false>
 __device__ void deposit_chunk(const float *__restrict__ pos, const int32_t *__restrict__ cell,
-                              const Index idx, int n, float mass, float *__restrict__ rho) {
+                              const Index idx, int n, float mass, float *__restrict__ rho,
+                              unsigned long long *__restrict__ fixg = nullptr) {
   __shared__ unsigned long long acc[kGTable];  // 2^-30 fixed-point sums of the grown box
   __shared__ int red[6][kGThreads / 64];
   int ref[3];
@@ -295,9 +301,16 @@ __device__ void deposit_chunk(const float *__restrict__ pos, const int32_t *__re
         const size_t ia = (size_t)wrap_index(f[0] + a, n) * n;
         for (int b = 0; b < MAS; ++b) {
           const size_t row = (ia + wrap_index(f[1] + b, n)) * n;
-          const float wab = mass * w[0][a] * w[1][b];
-          for (int c = 0; c < MAS; ++c)
-            unsafeAtomicAdd(&rho[row + wrap_index(f[2] + c, n)], wab * w[2][c]);
+          if constexpr (FIXED) {
+            const float wab = w[0][a] * w[1][b] * 1073741824.0f;  // 2^30, as below
+            for (int c = 0; c < MAS; ++c)
+              atomicAdd(&fixg[row + wrap_index(f[2] + c, n)],
+                        (unsigned long long)(unsigned)rintf(wab * w[2][c]));
+          } else {
+            const float wab = mass * w[0][a] * w[1][b];
+            for (int c = 0; c < MAS; ++c)
+              unsafeAtomicAdd(&rho[row + wrap_index(f[2] + c, n)], wab * w[2][c]);
+          }
         }
       }
     }
@@ -342,7 +355,10 @@ __device__ void deposit_chunk(const float *__restrict__ pos, const int32_t *__re
     const int gi = wrap_any(ref[0] + lo[0] - 1 + x, n);
     const int gj = wrap_any(ref[1] + lo[1] - 1 + y, n);
     const int gk = wrap_any(ref[2] + lo[2] - 1 + z, n);
-    unsafeAtomicAdd(&rho[((size_t)gi * n + gj) * n + gk], (float)v * scale);
+    if constexpr (FIXED)
+      atomicAdd(&fixg[((size_t)gi * n + gj) * n + gk], v);
+    else
+      unsafeAtomicAdd(&rho[((size_t)gi * n + gj) * n + gk], (float)v * scale);
   }
 }
 
