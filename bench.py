@@ -40,8 +40,8 @@ MEASURED_TRAFFIC = {
     # and the post-smoothing pass (with the prolongation) weighted by their counts (45
     # and 39 dispatches)
     "smooth": ("paper_2410_20501_amd/csrc/mg_stream.hip",
-               "8bcfe77415275f8b65a09616b990d3926d1d216e1138cd5b3e7ffb008fd7e991",
-               868085.0, 528114.0, 2.0, 1.0),
+               "4ea35171df84f337cefdd3d1146566fb9eea23ffec47a4cdf832b17cc38d203f",
+               628408.0, 524301.0, 2.0, 1.0),
     # deposit: the particle-owned tile kernel plus the gather pass over the tile boxes
     "deposit": ("paper_2410_20501_amd/csrc/particles.hip",
                 "858c00d7abdcbe38589b6d15dd9ddc720ef29853cd37858ffc3bdf6709ea6f17",
