@@ -23,8 +23,11 @@
 
 namespace {
 
-constexpr int FT = 256;   // threads per block
-constexpr int TL = 4096;  // complex elements held in LDS per block
+#ifndef PM_FFT_THREADS
+#define PM_FFT_THREADS 256
+#endif
+constexpr int FT = PM_FFT_THREADS;  // threads per block
+constexpr int TL = PM_FFT_TL;       // complex elements held in LDS per block
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -287,10 +290,7 @@ __global__ void k_fft_tables(float2 *__restrict__ tw, float *__restrict__ tab, i
 
 }  // namespace
 
-int fft_pitch(int n) {
-  const int T = TL / n;
-  return ((n / 2 + 1 + T - 1) / T) * T;
-}
+int fft_pitch(int n) { return fft_pitch_of(n); }
 
 size_t fft_spec_elems(int n) { return (size_t)n * n * fft_pitch(n); }
 

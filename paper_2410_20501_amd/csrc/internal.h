@@ -252,6 +252,14 @@ struct FftBufs {
   float2 *twiddle;       // [n]
   float *tab;            // [3n]
 };
+#ifndef PM_FFT_TL
+#define PM_FFT_TL 4096  // complex elements an FFT workgroup holds in LDS
+#endif
+// row pitch of the half spectrum: n/2 + 1 columns rounded up to a whole column tile
+// (PM_FFT_TL / n columns)
+constexpr int fft_pitch_of(int n) {
+  return ((n / 2 + 1 + PM_FFT_TL / n - 1) / (PM_FFT_TL / n)) * (PM_FFT_TL / n);
+}
 int fft_pitch(int n);
 size_t fft_spec_elems(int n);
 // kind: a pm_fft_kernel; out: phi [n^3] (PM_FFT_GREEN, PM_FFT_7PT) or g [n^3 * 3] (PM_FFT_FULL);

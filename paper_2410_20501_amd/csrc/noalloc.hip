@@ -13,11 +13,11 @@ namespace {
 
 constexpr int kNoAllocMaxN = 128;
 constexpr int kNoAllocMaxDevices = 64;
-// spectrum of the largest grid (the pitch of n = 128 is 96 columns; smaller power-of-two
-// grids need fewer elements), then n twiddles, 3n table floats, the partial sums of the
-// mean (2 doubles per reduction block) and its result (4 doubles, then the FP32 mean),
-// each part 256-byte aligned (32 float2)
-constexpr size_t kNoAllocSpec = (size_t)kNoAllocMaxN * kNoAllocMaxN * 96;
+// spectrum of the largest grid (smaller power-of-two grids need fewer elements), then n
+// twiddles, 3n table floats, the partial sums of the mean (2 doubles per reduction
+// block) and its result (4 doubles, then the FP32 mean), each part 256-byte aligned
+// (32 float2)
+constexpr size_t kNoAllocSpec = (size_t)kNoAllocMaxN * kNoAllocMaxN * fft_pitch_of(kNoAllocMaxN);
 constexpr size_t kNoAllocRed = 2 * RED_BLOCKS + 32;
 constexpr size_t kNoAllocElems = kNoAllocSpec + kNoAllocMaxN + 2 * kNoAllocMaxN + kNoAllocRed + 64;
 
