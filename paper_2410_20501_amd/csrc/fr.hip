@@ -28,6 +28,28 @@ __host__ __device__ inline int wrapn(int i, int n) { return i < 0 ? i + n : (i >
 
 __device__ __forceinline__ double pow_n1(double u, int ne) { return ne == 1 ? u * u : u * u * u; }
 
+// (i, j, k) of cell c = (i n + j) n + k in 32-bit arithmetic (n^3 <= 2^30): masks and
+// shifts for a power-of-two side (the usual case; n is uniform over the launch),
+// 32-bit divisions otherwise. (64-bit divisions, a long software sequence per cell,
+// would dominate these memory-bound kernels.)
+__device__ __forceinline__ void cell_ijk(unsigned c, int n, int &i, int &j, int &k) {
+  if ((n & (n - 1)) == 0) {
+    const int lg = __builtin_ctz((unsigned)n);
+    k = (int)(c & (unsigned)(n - 1));
+    j = (int)((c >> lg) & (unsigned)(n - 1));
+    i = (int)(c >> (2 * lg));
+  } else {
+    const unsigned un = (unsigned)n, q = c / un;
+    k = (int)(c - q * un);
+    i = (int)(q / un);
+    j = (int)(q - (unsigned)i * un);
+  }
+}
+
+__device__ __forceinline__ unsigned fr_thread() {
+  return xcd_block(blockIdx.x, gridDim.x) * kFrThreads + threadIdx.x;
+}
+
 // For Delta0 < 0, with B = (-Delta0)^(3/2), sqrt(disc) = sqrt(Delta1^2 + 4 B^2) and
 // A = (|Delta1| + sqrt(disc)) / 2: Q = A^(1/3) and diff = Q^2 - (-Delta0), the latter as
 // (A - B)(A + B) / (Q^4 + Q^2 (-Delta0) + Delta0^2) with A - B = |Delta1| / 2 +
@@ -111,12 +133,22 @@ __global__ __launch_bounds__(kFrThreads) void k_fr_sweep(double *__restrict__ u,
                                                          const double *__restrict__ s, FrLevel L,
                                                          int ne, int colour) {
   const int n = L.n, hn = n >> 1;
-  const int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kFrThreads + threadIdx.x;
-  if (t >= (int64_t)n * n * hn) return;
-  const int i = (int)(t / ((int64_t)n * hn));
-  const int r = (int)(t - (int64_t)i * n * hn);
-  const int j = r / hn;
-  const int k = 2 * (r - j * hn) + ((i + j + colour) & 1);
+  const unsigned t = fr_thread();
+  if (t >= (unsigned)n * n * hn) return;
+  // t = (i n + j) (n/2) + k/2: the same decoding as a grid of side n with n/2 columns
+  int i, j, k2;
+  if ((n & (n - 1)) == 0) {
+    const int lg = __builtin_ctz((unsigned)n);
+    k2 = (int)(t & (unsigned)(hn - 1));
+    j = (int)((t >> (lg - 1)) & (unsigned)(n - 1));
+    i = (int)(t >> (2 * lg - 1));
+  } else {
+    const unsigned q = t / (unsigned)hn;
+    k2 = (int)(t - q * (unsigned)hn);
+    i = (int)(q / (unsigned)n);
+    j = (int)(q - (unsigned)i * n);
+  }
+  const int k = 2 * k2 + ((i + j + colour) & 1);
   const size_t c = ((size_t)i * n + j) * n + k;
   const double p = -nb_sum(u, n, i, j, k, ne) / 6.0 + L.ps * s[c];
   u[c] = ne == 1 ? root3(p, L.q) : root4(p, L.q);
@@ -128,9 +160,10 @@ __global__ __launch_bounds__(kFrThreads) void k_fr_residual(const double *__rest
                                                             FrLevel L, double K, int ne,
                                                             double *__restrict__ d) {
   const int n = L.n;
-  const int64_t c = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kFrThreads + threadIdx.x;
-  if (c >= (int64_t)n * n * n) return;
-  const int i = (int)(c / ((int64_t)n * n)), j = (int)((c / n) % n), k = (int)(c % n);
+  const unsigned c = fr_thread();
+  if (c >= (unsigned)n * n * n) return;
+  int i, j, k;
+  cell_ijk(c, n, i, j, k);
   const double uc = u[c];
   const double op = L.a_op * (nb_sum(u, n, i, j, k, ne) - 6.0 * pow_n1(uc, ne)) - K / uc;
   d[c] = s[c] - op;
@@ -144,9 +177,10 @@ __global__ __launch_bounds__(kFrThreads) void k_fr_restrict(const double *__rest
                                                             double *__restrict__ uH,
                                                             double *__restrict__ sH) {
   const int N = n >> 1;
-  const int64_t c = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kFrThreads + threadIdx.x;
-  if (c >= (int64_t)N * N * N) return;
-  const int I = (int)(c / ((int64_t)N * N)), J = (int)((c / N) % N), Kc = (int)(c % N);
+  const unsigned c = fr_thread();
+  if (c >= (unsigned)N * N * N) return;
+  int I, J, Kc;
+  cell_ijk(c, N, I, J, Kc);
   constexpr double w[4] = {0.125, 0.375, 0.375, 0.125};
   double su = 0.0, sd = 0.0;
   for (int a = 0; a < 4; ++a) {
@@ -174,9 +208,10 @@ __global__ __launch_bounds__(kFrThreads) void k_fr_coarse_rhs(const double *__re
                                                               FrLevel L, double K, int ne,
                                                               double *__restrict__ sH) {
   const int n = L.n;
-  const int64_t c = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kFrThreads + threadIdx.x;
-  if (c >= (int64_t)n * n * n) return;
-  const int i = (int)(c / ((int64_t)n * n)), j = (int)((c / n) % n), k = (int)(c % n);
+  const unsigned c = fr_thread();
+  if (c >= (unsigned)n * n * n) return;
+  int i, j, k;
+  cell_ijk(c, n, i, j, k);
   const double uc = u0[c];
   sH[c] += L.a_op * (nb_sum(u0, n, i, j, k, ne) - 6.0 * pow_n1(uc, ne)) - K / uc;
 }
@@ -187,9 +222,10 @@ __global__ __launch_bounds__(kFrThreads) void k_fr_prolong(double *__restrict__ 
                                                            const double *__restrict__ uH,
                                                            const double *__restrict__ u0) {
   const int N = n >> 1;
-  const int64_t c = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kFrThreads + threadIdx.x;
-  if (c >= (int64_t)n * n * n) return;
-  const int i = (int)(c / ((int64_t)n * n)), j = (int)((c / n) % n), k = (int)(c % n);
+  const unsigned c = fr_thread();
+  if (c >= (unsigned)n * n * n) return;
+  int i, j, k;
+  cell_ijk(c, n, i, j, k);
   const int ci[2] = {i >> 1, wrapn((i >> 1) + ((i & 1) ? 1 : -1), N)};
   const int cj[2] = {j >> 1, wrapn((j >> 1) + ((j & 1) ? 1 : -1), N)};
   const int ck[2] = {k >> 1, wrapn((k >> 1) + ((k & 1) ? 1 : -1), N)};
