@@ -203,6 +203,147 @@ __global__ __launch_bounds__(kFrThreads) void k_fr_restrict(const double *__rest
   sH[c] = sd;
 }
 
+// Residual and restriction in one pass over the fine grid (levels of at least 32 cells
+// per side): u0 = uH = R u and sH = R d with d = s - N_h(u), the full weighting of
+// k_fr_restrict and the residual of k_fr_residual, without writing d. A block owns a
+// 16 x 16 tile of coarse (J, K) columns and a chunk of coarse planes, and walks through
+// the fine planes once: iteration t publishes u of plane t in LDS, forms d of plane
+// t - 1 from it (the i-neighbours in registers) and restricts u and d of plane t - 2 in
+// the plane; each fine plane adds to two coarse planes (three accumulator slots). u
+// planes rotate through three LDS buffers and d planes through two, so one barrier per
+// iteration orders every buffer's reuse.
+constexpr int kRrCJ = 16, kRrCK = 16, kRrT = 256;
+constexpr int kRrUJ = 2 * kRrCJ + 4, kRrUK = 2 * kRrCK + 4, kRrNP = kRrUJ * kRrUK;
+constexpr int kRrPer = (kRrNP + kRrT - 1) / kRrT;  // region points per thread
+static_assert(kRrCJ * kRrCK == kRrT, "one coarse column per thread");
+
+__global__ __launch_bounds__(kRrT) void k_fr_rr(const double *__restrict__ u,
+                                                const double *__restrict__ s, FrLevel L,
+                                                double K, int ne, int cic,
+                                                double *__restrict__ u0,
+                                                double *__restrict__ uH,
+                                                double *__restrict__ sH) {
+  __shared__ double Lu[3][kRrNP];
+  __shared__ double Ld[2][kRrNP];
+  const int n = L.n, N = n >> 1;
+  const unsigned lin = xcd_block(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
+                                 gridDim.x * gridDim.y * gridDim.z);
+  const int bx = lin % gridDim.x, by = (lin / gridDim.x) % gridDim.y,
+            bz = lin / (gridDim.x * gridDim.y);
+  const int K0 = bx * kRrCK, J0 = by * kRrCJ, I0 = bz * cic;
+  const int fj0 = 2 * J0 - 2, fk0 = 2 * K0 - 2;  // fine region origin
+  const size_t nn = (size_t)n * n;
+  int rj[kRrPer], rk[kRrPer];
+  unsigned col[kRrPer];
+#pragma unroll
+  for (int v = 0; v < kRrPer; ++v) {
+    const int e = threadIdx.x + v * kRrT;
+    rj[v] = e < kRrNP ? e / kRrUK : -100;
+    rk[v] = e < kRrNP ? e % kRrUK : -100;
+    col[v] = e < kRrNP ? (unsigned)(wrapn(((fj0 + rj[v]) % n + n) % n, n) * n +
+                                    ((fk0 + rk[v]) % n + n) % n)
+                       : 0u;
+  }
+  double um[kRrPer], uc[kRrPer], up[kRrPer], nu[kRrPer], sc[kRrPer], sn[kRrPer];
+#pragma unroll
+  for (int v = 0; v < kRrPer; ++v) um[v] = uc[v] = up[v] = nu[v] = sc[v] = sn[v] = 1.0;
+  double au[3] = {0.0, 0.0, 0.0}, ad[3] = {0.0, 0.0, 0.0};  // coarse planes, slot I mod 3
+  // fine planes restricted: 2 I0 - 1 .. 2 (I0 + cic), i.e. [pbeg, pend)
+  const int pbeg = 2 * I0 - 1, pend = 2 * (I0 + cic) + 1;
+  auto plane_of = [&](int q) { return (size_t)(((q % n) + n) % n) * nn; };
+  auto prefetch = [&](int q) {  // u of plane q, s of plane q - 1
+    const size_t pu = plane_of(q), ps = plane_of(q - 1);
+#pragma unroll
+    for (int v = 0; v < kRrPer; ++v)
+      if (rj[v] >= 0) {
+        nu[v] = u[pu + col[v]];
+        sn[v] = s[ps + col[v]];
+      }
+  };
+  constexpr double w[4] = {0.125, 0.375, 0.375, 0.125};
+  const int cj = threadIdx.x / kRrCK, ck = threadIdx.x % kRrCK;
+  prefetch(pbeg - 1);
+  for (int t = pbeg - 1; t <= pend + 1; ++t) {
+#pragma unroll
+    for (int v = 0; v < kRrPer; ++v) {
+      um[v] = uc[v];
+      uc[v] = up[v];
+      up[v] = nu[v];  // u of plane t
+      sc[v] = sn[v];  // s of plane t - 1
+    }
+    if (t < pend) prefetch(t + 1);
+    const int su = ((t % 3) + 3) % 3;
+    if (t >= pbeg - 1 && t < pend) {
+      // (plane pbeg - 1 too: the residual of plane pbeg needs it only through registers,
+      // but publishing it keeps the buffer rotation uniform)
+#pragma unroll
+      for (int v = 0; v < kRrPer; ++v)
+        if (rj[v] >= 0) Lu[su][rj[v] * kRrUK + rk[v]] = up[v];
+    }
+    if (t - 1 >= pbeg && t - 1 < pend) {
+      // d of plane t - 1 on the region less its outer ring (centre uc, i-neighbours um, up)
+      const double *lu = Lu[((t - 1) % 3 + 3) % 3];
+      double *ld = Ld[((t - 1) & 1)];
+#pragma unroll
+      for (int v = 0; v < kRrPer; ++v) {
+        const int a = rj[v], b = rk[v];
+        if (a < 1 || a >= kRrUJ - 1 || b < 1 || b >= kRrUK - 1) continue;
+        const int e = a * kRrUK + b;
+        const double c = uc[v];
+        const double nb = pow_n1(um[v], ne) + pow_n1(up[v], ne) + pow_n1(lu[e - kRrUK], ne) +
+                          pow_n1(lu[e + kRrUK], ne) + pow_n1(lu[e - 1], ne) +
+                          pow_n1(lu[e + 1], ne);
+        const double op = L.a_op * (nb - 6.0 * pow_n1(c, ne)) - K / c;
+        ld[e] = sc[v] - op;
+      }
+    }
+    const int p = t - 2;
+    if (p >= pbeg && p < pend) {
+      const double *lu = Lu[((p % 3) + 3) % 3];
+      const double *ld = Ld[p & 1];
+      double tu = 0.0, td = 0.0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int row = (2 * cj + 1 + b) * kRrUK + 2 * ck + 1;
+        double ru = 0.0, rd = 0.0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          ru += w[e] * lu[row + e];
+          rd += w[e] * ld[row + e];
+        }
+        tu += w[b] * ru;
+        td += w[b] * rd;
+      }
+      // fine plane p adds to coarse planes I = p/2 (weight 3/8) and the next one on its
+      // side (1/8); only coarse planes of this block accumulate
+      const int Ip = (p >= 0) ? p / 2 : -((1 - p) / 2);
+      const int Io = (p & 1) ? Ip + 1 : Ip - 1;
+      if (Ip >= I0 && Ip < I0 + cic) {
+        au[Ip % 3] += 0.375 * tu;
+        ad[Ip % 3] += 0.375 * td;
+      }
+      if (Io >= I0 && Io < I0 + cic) {
+        au[Io % 3] += 0.125 * tu;
+        ad[Io % 3] += 0.125 * td;
+      }
+      // coarse plane I complete after fine plane 2 I + 2
+      if ((p & 1) == 0 && p >= 2 * I0 + 2) {
+        const int I = p / 2 - 1, sl = I % 3;
+        const int J = J0 + cj, Kc = K0 + ck;
+        if (J < N && Kc < N) {
+          const size_t ci = ((size_t)I * N + J) * N + Kc;
+          u0[ci] = au[sl];
+          uH[ci] = au[sl];
+          sH[ci] = ad[sl];
+        }
+        au[sl] = 0.0;
+        ad[sl] = 0.0;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // sH += N_H(u0): the coarse right-hand side N_H(R u) + R d
 __global__ __launch_bounds__(kFrThreads) void k_fr_coarse_rhs(const double *__restrict__ u0,
                                                               FrLevel L, double K, int ne,
@@ -217,28 +358,59 @@ __global__ __launch_bounds__(kFrThreads) void k_fr_coarse_rhs(const double *__re
 }
 
 // u += P(uH - u0) on the fine grid of side n: per axis 3/4 of the nearest coarse centre
-// and 1/4 of the next one
+// and 1/4 of the next one. One thread per coarse cell (I, J, K) reads the 27 coarse
+// differences around it once and updates its 8 fine children (2I+a, 2J+b, 2K+c) (a
+// thread per fine cell would read 8 coarse pairs for each fine cell).
 __global__ __launch_bounds__(kFrThreads) void k_fr_prolong(double *__restrict__ u, int n,
                                                            const double *__restrict__ uH,
                                                            const double *__restrict__ u0) {
   const int N = n >> 1;
   const unsigned c = fr_thread();
-  if (c >= (unsigned)n * n * n) return;
-  int i, j, k;
-  cell_ijk(c, n, i, j, k);
-  const int ci[2] = {i >> 1, wrapn((i >> 1) + ((i & 1) ? 1 : -1), N)};
-  const int cj[2] = {j >> 1, wrapn((j >> 1) + ((j & 1) ? 1 : -1), N)};
-  const int ck[2] = {k >> 1, wrapn((k >> 1) + ((k & 1) ? 1 : -1), N)};
+  if (c >= (unsigned)N * N * N) return;
+  int I, J, K;
+  cell_ijk(c, N, I, J, K);
+  const int ix[3] = {wrapn(I - 1, N), I, wrapn(I + 1, N)};
+  const int jx[3] = {wrapn(J - 1, N), J, wrapn(J + 1, N)};
+  const int kx[3] = {wrapn(K - 1, N), K, wrapn(K + 1, N)};
   constexpr double w[2] = {0.75, 0.25};
-  double v = 0.0;
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) {
-      const size_t r = ((size_t)ci[a] * N + cj[b]) * N;
-      double t = 0.0;
-      for (int e = 0; e < 2; ++e) t += w[e] * (uH[r + ck[e]] - u0[r + ck[e]]);
-      v += w[a] * w[b] * t;
+  double e[3][3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const size_t r = ((size_t)ix[a] * N + jx[b]) * N;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) e[a][b][q] = uH[r + kx[q]] - u0[r + kx[q]];
     }
-  u[c] += v;
+  const size_t nn = (size_t)n * n;
+#pragma unroll
+  for (int ai = 0; ai < 2; ++ai) {      // fine plane 2I + ai: near coarse plane 1, far 0 or 2
+    const int af = ai ? 2 : 0;
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {    // fine row 2J + bj
+      const int bf = bj ? 2 : 0;
+      double out[2];
+#pragma unroll
+      for (int ck = 0; ck < 2; ++ck) {  // fine column 2K + ck
+        const int kf = ck ? 2 : 0;
+        // the same sum as per fine cell: planes (near, far) x rows (near, far), each the
+        // k-interpolation w0 e_near + w1 e_far
+        const int pa[2] = {1, af}, pb[2] = {1, bf};
+        double v = 0.0;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            const double t = w[0] * e[pa[a]][pb[b]][1] + w[1] * e[pa[a]][pb[b]][kf];
+            v += w[a] * w[b] * t;
+          }
+        out[ck] = v;
+      }
+      double *dst = u + (size_t)(2 * I + ai) * nn + (size_t)(2 * J + bj) * n + 2 * K;
+      dst[0] += out[0];
+      dst[1] += out[1];
+    }
+  }
 }
 
 // the coarsest grid (n^3 <= kFrCoarseMax, n even): `sweeps` red-black sweeps in LDS
@@ -397,10 +569,20 @@ struct FrRun {
     for (int it = 0; it < p->fr_pre; ++it)
       if (hipError_t e = sweep(l, u, 0)) return e;
     pm_fr_level &C = ctx->fr_lev[l + 1];
-    double *d = ctx->fr_lev[l].d;
-    k_fr_residual<<<blocks(cells), kFrThreads, 0, s>>>(u, ctx->fr_lev[l].s, L, K, ne, d);
     const int64_t cc = (int64_t)C.n * C.n * C.n;
-    k_fr_restrict<<<blocks(cc), kFrThreads, 0, s>>>(u, d, L.n, C.u0, C.u, C.s);
+    if (C.n >= kRrCJ && C.n % kRrCJ == 0) {
+      // one streaming pass: residual and restriction (chunks of coarse planes sized for
+      // about 2048 blocks)
+      const int tiles = (C.n / kRrCJ) * (C.n / kRrCK);
+      int cic = C.n;
+      while (cic / 2 >= 8 && tiles * (C.n / cic) < 2048 && C.n % (cic / 2) == 0) cic /= 2;
+      const dim3 grid(C.n / kRrCK, C.n / kRrCJ, C.n / cic);
+      k_fr_rr<<<grid, kRrT, 0, s>>>(u, ctx->fr_lev[l].s, L, K, ne, cic, C.u0, C.u, C.s);
+    } else {
+      double *d = ctx->fr_lev[l].d;
+      k_fr_residual<<<blocks(cells), kFrThreads, 0, s>>>(u, ctx->fr_lev[l].s, L, K, ne, d);
+      k_fr_restrict<<<blocks(cc), kFrThreads, 0, s>>>(u, d, L.n, C.u0, C.u, C.s);
+    }
     k_fr_coarse_rhs<<<blocks(cc), kFrThreads, 0, s>>>(C.u0, level(l + 1), K, ne, C.s);
     if (hipError_t e = hipGetLastError()) return e;
     const int inner[2] = {kind == PM_CYCLE_W ? PM_CYCLE_W : (kind == PM_CYCLE_F ? PM_CYCLE_F
@@ -409,7 +591,7 @@ struct FrRun {
     const int visits = kind == PM_CYCLE_V ? 1 : 2;
     for (int v = 0; v < visits; ++v)
       if (hipError_t e = cycle(l + 1, C.u, inner[v])) return e;
-    k_fr_prolong<<<blocks(cells), kFrThreads, 0, s>>>(u, L.n, C.u, C.u0);
+    k_fr_prolong<<<blocks(cells / 8), kFrThreads, 0, s>>>(u, L.n, C.u, C.u0);
     for (int it = 0; it < p->fr_post; ++it)
       if (hipError_t e = sweep(l, u, 1)) return e;
     return hipGetLastError();
