@@ -260,6 +260,131 @@ __global__ __launch_bounds__(FT) void k_cols(const float2 *src, float2 *dst, int
   }
 }
 
+// Length-256 column passes (n = 256) as a four-step transform in registers: a length-256
+// DFT is 16 DFTs of length 16 over the stride-16 subsequences, twiddles W_256^(j k1),
+// a transpose through LDS and 16 DFTs of length 16 again. A column is handled by 16
+// threads; thread j holds the elements j, j + 16, ... before a transform and the
+// elements j, j + 16, ... of the result after it, which is also the input order of the
+// next transform, so a pass with the kernel between the forward and the inverse
+// transform needs two transposes. The same tile of 16 columns and the same modes and
+// tables as k_cols.
+// 16-point DFT in registers, natural order in and out: a radix-4 pass over the four
+// stride-4 subsequences, twiddles W_16^(n2 k1), a radix-4 pass across them.
+__device__ __forceinline__ float2 w16(int m, bool inv) {
+  // e^{-2 pi i m / 16} (forward), its conjugate (inverse), m = 0 .. 9
+  constexpr float c[10] = {1.0f, 0.92387953251128674f, 0.70710678118654752f,
+                           0.38268343236508977f, 0.0f, -0.38268343236508977f,
+                           -0.70710678118654752f, -0.92387953251128674f, -1.0f,
+                           -0.92387953251128674f};
+  constexpr float sn[10] = {0.0f, 0.38268343236508977f, 0.70710678118654752f,
+                            0.92387953251128674f, 1.0f, 0.92387953251128674f,
+                            0.70710678118654752f, 0.38268343236508977f, 0.0f,
+                            -0.38268343236508977f};
+  return make_float2(c[m], inv ? sn[m] : -sn[m]);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft16(float2 (&x)[16]) {
+  float2 y[4][4];  // y[n2][k1]: DFT over n1 of x[4 n1 + n2]
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    float2 v[4] = {x[n2], x[4 + n2], x[8 + n2], x[12 + n2]};
+    butterfly<4, INV>(v);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) y[n2][k1] = (n2 * k1 == 0) ? v[k1] : cmul(v[k1], w16(n2 * k1, INV));
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    float2 v[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+    butterfly<4, INV>(v);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) x[k1 + 4 * k2] = v[k2];
+  }
+}
+
+constexpr int kC256Pad = 17;  // LDS row of 16 values plus one (bank spread)
+
+// x: this thread's 16 inputs (elements j + 16 n1 of its column, in order of n1); out:
+// elements j + 16 k2 of the transform (thread j of the column, c its column in the tile)
+template <bool INV>
+__device__ __forceinline__ void fft256_cols(float2 (&x)[16], float2 *lds, int c, int j,
+                                            const float2 *__restrict__ tw) {
+  dft16<INV>(x);  // x[k1] = DFT over n1 of the subsequence j
+#pragma unroll
+  for (int k1 = 1; k1 < 16; ++k1) {
+    float2 t = tw[j * k1];
+    if (INV) t.y = -t.y;
+    x[k1] = cmul(x[k1], t);
+  }
+  __syncthreads();  // the previous transpose's reads are done
+#pragma unroll
+  for (int k1 = 0; k1 < 16; ++k1) lds[(c * 16 + k1) * kC256Pad + j] = x[k1];
+  __syncthreads();
+#pragma unroll
+  for (int n2 = 0; n2 < 16; ++n2) x[n2] = lds[(c * 16 + j) * kC256Pad + n2];
+  dft16<INV>(x);  // x[k2] = element j + 16 k2
+}
+
+template <int AXIS, int MODE>
+__global__ __launch_bounds__(FT) void k_cols256(const float2 *src, float2 *dst, int P,
+                                                const float2 *__restrict__ tw,
+                                                const float *__restrict__ tab, float scale,
+                                                int deriv) {
+  constexpr int n = 256, T = 16;
+  static_assert(FT == T * 16, "16 threads per column");
+  __shared__ float2 lds[T * 16 * kC256Pad];
+  const int c = threadIdx.x & 15, j = threadIdx.x >> 4;
+  const int kc0 = blockIdx.x * T;
+  const int outer = blockIdx.y;
+  auto gidx = [&](int idx) -> int64_t {
+    if constexpr (AXIS == 1)
+      return ((int64_t)outer * n + idx) * P + kc0 + c;
+    else
+      return ((int64_t)idx * n + outer) * P + kc0 + c;
+  };
+  float2 x[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) x[q] = src[gidx(j + 16 * q)];
+  if constexpr (MODE == 4) {
+    // (-i k_d) v before the inverse transform; element j + 16 q sits at mx = j + 16 q
+    const float *kv = tab + 2 * n;
+    const int kz = kc0 + c;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int mx = j + 16 * q;
+      const float k = kv[deriv == 0 ? mx : (deriv == 1 ? outer : min(kz, n - 1))];
+      x[q] = make_float2(k * x[q].y, -k * x[q].x);
+    }
+  }
+  if constexpr (MODE == 0 || MODE == 1 || MODE == 3) fft256_cols<false>(x, lds, c, j, tw);
+  if constexpr (MODE == 1 || MODE == 3) {
+    const float *t0 = tab, *t1 = tab + n;
+    const int my = outer, kz = kc0 + c;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int mx = j + 16 * q;
+      float gval = 0.0f;
+      if (kz <= n / 2 && (mx | my | kz) != 0)
+        gval = -scale / ((t0[mx] + t0[my] + t0[kz]) * (t1[mx] * t1[my] * t1[kz]));
+      x[q] = make_float2(x[q].x * gval, x[q].y * gval);
+    }
+  }
+  if constexpr (MODE == 1 || MODE == 2 || MODE == 4) fft256_cols<true>(x, lds, c, j, tw);
+#pragma unroll
+  for (int q = 0; q < 16; ++q) dst[gidx(j + 16 * q)] = x[q];
+}
+
+// a column pass: the register four-step kernel for n = 256 (16-column tiles), the LDS
+// Stockham kernel otherwise
+template <int AXIS, int MODE>
+void launch_cols(dim3 grid, hipStream_t s, const float2 *src, float2 *dst, int n, int P,
+                 const float2 *tw, const float *tab, float scale, int deriv) {
+  if (n == 256 && TL / n == 16)
+    k_cols256<AXIS, MODE><<<grid, FT, 0, s>>>(src, dst, P, tw, tab, scale, deriv);
+  else
+    k_cols<AXIS, MODE><<<grid, FT, 0, s>>>(src, dst, n, P, tw, tab, scale, deriv);
+}
+
 // Twiddles tw[m] = e^{-2 pi i m / n} and the per-axis tables of the kernel, in FP64 on
 // the device and rounded once. For wavenumber index i (m = i, or i - n above n/2):
 //   kind 0 (Green's function with window deconvolution): t0 = k^2, k = 2 pi m (unit
@@ -305,19 +430,19 @@ hipError_t fft_run(const FftBufs &b, int n, const float *rho, const float *mean,
   k_fft_tables<<<(n + 255) / 256, 256, 0, s>>>(b.twiddle, b.tab, n, deconv,
                                                kind == PM_FFT_7PT ? 1 : 0);
   k_rows_r2c<<<row_blocks, FT, 0, s>>>(rho, spec, n, P, b.twiddle, mean);
-  k_cols<1, 0><<<col_grid, FT, 0, s>>>(spec, spec, n, P, b.twiddle, b.tab, scale, 0);
+  launch_cols<1, 0>(col_grid, s, spec, spec, n, P, b.twiddle, b.tab, scale, 0);
   if (kind != PM_FFT_FULL) {
-    k_cols<0, 1><<<col_grid, FT, 0, s>>>(spec, spec, n, P, b.twiddle, b.tab, scale, 0);
-    k_cols<1, 2><<<col_grid, FT, 0, s>>>(spec, spec, n, P, b.twiddle, b.tab, scale, 0);
+    launch_cols<0, 1>(col_grid, s, spec, spec, n, P, b.twiddle, b.tab, scale, 0);
+    launch_cols<1, 2>(col_grid, s, spec, spec, n, P, b.twiddle, b.tab, scale, 0);
     k_rows_c2r<<<row_blocks, FT, 0, s>>>(spec, out, n, P, b.twiddle, 1, 0);
     return hipGetLastError();
   }
   // force in Fourier space: spec <- G F once, then per component d the inverse of
   // -i k_d G F into the second spectrum and one component of the force grid
-  k_cols<0, 3><<<col_grid, FT, 0, s>>>(spec, spec, n, P, b.twiddle, b.tab, scale, 0);
+  launch_cols<0, 3>(col_grid, s, spec, spec, n, P, b.twiddle, b.tab, scale, 0);
   for (int d = 0; d < 3; ++d) {
-    k_cols<0, 4><<<col_grid, FT, 0, s>>>(spec, b.spec2, n, P, b.twiddle, b.tab, scale, d);
-    k_cols<1, 2><<<col_grid, FT, 0, s>>>(b.spec2, b.spec2, n, P, b.twiddle, b.tab, scale, 0);
+    launch_cols<0, 4>(col_grid, s, spec, b.spec2, n, P, b.twiddle, b.tab, scale, d);
+    launch_cols<1, 2>(col_grid, s, b.spec2, b.spec2, n, P, b.twiddle, b.tab, scale, 0);
     k_rows_c2r<<<row_blocks, FT, 0, s>>>(b.spec2, out, n, P, b.twiddle, 3, d);
   }
   return hipGetLastError();
@@ -334,8 +459,8 @@ hipError_t fft_forward(const FftBufs &b, int n, const float *x, const float *mea
   const unsigned row_blocks = (unsigned)(((int64_t)n * n + Trow - 1) / Trow);
   const dim3 col_grid(P / Tcol, n);
   k_rows_r2c<<<row_blocks, FT, 0, s>>>(x, b.spec, n, P, b.twiddle, mean);
-  k_cols<1, 0><<<col_grid, FT, 0, s>>>(b.spec, b.spec, n, P, b.twiddle, b.tab, 0.0f, 0);
-  k_cols<0, 0><<<col_grid, FT, 0, s>>>(b.spec, b.spec, n, P, b.twiddle, b.tab, 0.0f, 0);
+  launch_cols<1, 0>(col_grid, s, b.spec, b.spec, n, P, b.twiddle, b.tab, 0.0f, 0);
+  launch_cols<0, 0>(col_grid, s, b.spec, b.spec, n, P, b.twiddle, b.tab, 0.0f, 0);
   return hipGetLastError();
 }
 
@@ -344,8 +469,8 @@ hipError_t fft_inverse(const FftBufs &b, int n, float *out, int stride, int comp
   const int Trow = TL / (n / 2), Tcol = TL / n;
   const unsigned row_blocks = (unsigned)(((int64_t)n * n + Trow - 1) / Trow);
   const dim3 col_grid(P / Tcol, n);
-  k_cols<0, 2><<<col_grid, FT, 0, s>>>(b.spec, b.spec, n, P, b.twiddle, b.tab, 0.0f, 0);
-  k_cols<1, 2><<<col_grid, FT, 0, s>>>(b.spec, b.spec, n, P, b.twiddle, b.tab, 0.0f, 0);
+  launch_cols<0, 2>(col_grid, s, b.spec, b.spec, n, P, b.twiddle, b.tab, 0.0f, 0);
+  launch_cols<1, 2>(col_grid, s, b.spec, b.spec, n, P, b.twiddle, b.tab, 0.0f, 0);
   k_rows_c2r<<<row_blocks, FT, 0, s>>>(b.spec, out, n, P, b.twiddle, stride, comp);
   return hipGetLastError();
 }
