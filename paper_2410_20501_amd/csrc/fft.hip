@@ -374,6 +374,148 @@ __global__ __launch_bounds__(FT) void k_cols256(const float2 *src, float2 *dst, 
   for (int q = 0; q < 16; ++q) dst[gidx(j + 16 * q)] = x[q];
 }
 
+// 8-point DFT in registers, natural order in and out (radix 4 over the two stride-2
+// subsequences, twiddles W_8^(n2 k1), radix 2 across)
+template <bool INV>
+__device__ __forceinline__ void dft8(float2 (&x)[8]) {
+  constexpr float h = 0.70710678118654752f;
+  float2 v0[4] = {x[0], x[2], x[4], x[6]}, v1[4] = {x[1], x[3], x[5], x[7]};
+  butterfly<4, INV>(v0);
+  butterfly<4, INV>(v1);
+  // W_8^k1 for k1 = 1, 2, 3 (forward e^{-i pi k1 / 4}; inverse conjugate)
+  const float s = INV ? 1.0f : -1.0f;
+  v1[1] = cmul(v1[1], make_float2(h, s * h));
+  v1[2] = make_float2(-s * v1[2].y, s * v1[2].x);  // times (0, s)
+  v1[3] = cmul(v1[3], make_float2(-h, s * h));
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    x[k1] = cadd(v0[k1], v1[k1]);
+    x[k1 + 4] = csub(v0[k1], v1[k1]);
+  }
+}
+
+// In-place length-128 transforms of the 32 rows of buf (row r at r * kRowPitch128,
+// natural order in and out), as 16 x 8 four-step transforms: thread t = 0 .. 7 of a row
+// takes the 16-point DFT of the stride-8 subsequence t, the twiddles W_128^(t k1), and
+// after a transpose the two 8-point DFTs of k1 = t and t + 8. tw is the table of n = 256
+// (W_128^m = tw[2 m]).
+constexpr int kRowPitch128 = 132;  // 128 values plus 4 (spreads the rows over the banks)
+
+template <bool INV>
+__device__ __forceinline__ void fft128_rows(float2 *buf, const float2 *__restrict__ tw) {
+  const int r = threadIdx.x >> 3, t = threadIdx.x & 7;
+  float2 *row = buf + r * kRowPitch128;
+  float2 x[16];
+#pragma unroll
+  for (int n1 = 0; n1 < 16; ++n1) x[n1] = row[8 * n1 + t];
+  dft16<INV>(x);
+#pragma unroll
+  for (int k1 = 1; k1 < 16; ++k1) {
+    float2 w = tw[2 * t * k1];
+    if (INV) w.y = -w.y;
+    x[k1] = cmul(x[k1], w);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k1 = 0; k1 < 16; ++k1) row[k1 * 8 + t] = x[k1];
+  __syncthreads();
+  float2 a[8], b[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    a[j] = row[t * 8 + j];
+    b[j] = row[(t + 8) * 8 + j];
+  }
+  dft8<INV>(a);
+  dft8<INV>(b);
+  __syncthreads();
+#pragma unroll
+  for (int k2 = 0; k2 < 8; ++k2) {
+    row[t + 16 * k2] = a[k2];
+    row[t + 8 + 16 * k2] = b[k2];
+  }
+  __syncthreads();
+}
+
+// k_rows_r2c for n = 256 (32 rows per block) with the register transform
+__global__ __launch_bounds__(FT) void k_rows_r2c256(const float *__restrict__ x,
+                                                    float2 *__restrict__ spec, int P,
+                                                    const float2 *__restrict__ tw,
+                                                    const float *__restrict__ mean) {
+  constexpr int n = 256, L = 128, T = 32;
+  static_assert(FT == T * 8, "8 threads per row");
+  __shared__ float2 buf[T * kRowPitch128];
+  const int64_t rows = (int64_t)n * n;
+  const int64_t row0 = (int64_t)blockIdx.x * T;
+  const float mu = mean ? *mean : 0.0f;
+  for (int e = threadIdx.x; e < T * L; e += FT) {
+    const int col = e / L, m = e % L;
+    const int64_t row = row0 + col;
+    float2 v = make_float2(0.f, 0.f);
+    if (row < rows) {
+      v = reinterpret_cast<const float2 *>(x + row * n)[m];
+      v.x -= mu;
+      v.y -= mu;
+    }
+    buf[col * kRowPitch128 + m] = v;
+  }
+  __syncthreads();
+  fft128_rows<false>(buf, tw);
+  for (int e = threadIdx.x; e < T * (L + 1); e += FT) {
+    const int col = e / (L + 1), k = e % (L + 1);
+    const int64_t row = row0 + col;
+    if (row >= rows) continue;
+    const float2 *b = buf + col * kRowPitch128;
+    const float2 zk = b[k == L ? 0 : k];
+    const float2 zm = conjf2(b[k == 0 ? 0 : L - k]);
+    const float2 E = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y + zm.y));
+    const float2 D = csub(zk, zm);
+    const float2 O = make_float2(0.5f * D.y, -0.5f * D.x);  // -i D / 2
+    spec[row * P + k] = cadd(E, cmul(tw[k], O));
+  }
+}
+
+// k_rows_c2r for n = 256 with the register transform
+__global__ __launch_bounds__(FT) void k_rows_c2r256(const float2 *__restrict__ spec,
+                                                    float *__restrict__ x, int P,
+                                                    const float2 *__restrict__ tw, int stride,
+                                                    int comp) {
+  constexpr int n = 256, L = 128, T = 32;
+  __shared__ float2 buf[T * kRowPitch128];
+  const int64_t rows = (int64_t)n * n;
+  const int64_t row0 = (int64_t)blockIdx.x * T;
+  for (int e = threadIdx.x; e < T * L; e += FT) {
+    const int col = e / L, k = e % L;
+    const int64_t row = row0 + col;
+    float2 z = make_float2(0.f, 0.f);
+    if (row < rows) {
+      const float2 xk = spec[row * P + k];
+      const float2 xm = conjf2(spec[row * P + (L - k)]);
+      const float2 Et = cadd(xk, xm);
+      const float2 Ot = cmul(conjf2(tw[k]), csub(xk, xm));
+      z = make_float2(Et.x - Ot.y, Et.y + Ot.x);  // Et + i Ot
+    }
+    buf[col * kRowPitch128 + k] = z;
+  }
+  __syncthreads();
+  fft128_rows<true>(buf, tw);
+  if (stride == 1) {
+    for (int e = threadIdx.x; e < T * L; e += FT) {
+      const int col = e / L, m = e % L;
+      const int64_t row = row0 + col;
+      if (row < rows) reinterpret_cast<float2 *>(x + row * n)[m] = buf[col * kRowPitch128 + m];
+    }
+  } else {
+    for (int e = threadIdx.x; e < 2 * T * L; e += FT) {
+      const int col = e / n, m = e % n;  // m: real position along the row
+      const int64_t row = row0 + col;
+      if (row < rows) {
+        const float2 v = buf[col * kRowPitch128 + (m >> 1)];
+        x[(row * n + m) * stride + comp] = (m & 1) ? v.y : v.x;
+      }
+    }
+  }
+}
+
 // a column pass: the register four-step kernel for n = 256 (16-column tiles), the LDS
 // Stockham kernel otherwise
 template <int AXIS, int MODE>
@@ -429,12 +571,18 @@ hipError_t fft_run(const FftBufs &b, int n, const float *rho, const float *mean,
   float2 *spec = b.spec;
   k_fft_tables<<<(n + 255) / 256, 256, 0, s>>>(b.twiddle, b.tab, n, deconv,
                                                kind == PM_FFT_7PT ? 1 : 0);
-  k_rows_r2c<<<row_blocks, FT, 0, s>>>(rho, spec, n, P, b.twiddle, mean);
+  if (n == 256 && Trow == 32)
+    k_rows_r2c256<<<row_blocks, FT, 0, s>>>(rho, spec, P, b.twiddle, mean);
+  else
+    k_rows_r2c<<<row_blocks, FT, 0, s>>>(rho, spec, n, P, b.twiddle, mean);
   launch_cols<1, 0>(col_grid, s, spec, spec, n, P, b.twiddle, b.tab, scale, 0);
   if (kind != PM_FFT_FULL) {
     launch_cols<0, 1>(col_grid, s, spec, spec, n, P, b.twiddle, b.tab, scale, 0);
     launch_cols<1, 2>(col_grid, s, spec, spec, n, P, b.twiddle, b.tab, scale, 0);
-    k_rows_c2r<<<row_blocks, FT, 0, s>>>(spec, out, n, P, b.twiddle, 1, 0);
+    if (n == 256 && Trow == 32)
+      k_rows_c2r256<<<row_blocks, FT, 0, s>>>(spec, out, P, b.twiddle, 1, 0);
+    else
+      k_rows_c2r<<<row_blocks, FT, 0, s>>>(spec, out, n, P, b.twiddle, 1, 0);
     return hipGetLastError();
   }
   // force in Fourier space: spec <- G F once, then per component d the inverse of
@@ -443,7 +591,10 @@ hipError_t fft_run(const FftBufs &b, int n, const float *rho, const float *mean,
   for (int d = 0; d < 3; ++d) {
     launch_cols<0, 4>(col_grid, s, spec, b.spec2, n, P, b.twiddle, b.tab, scale, d);
     launch_cols<1, 2>(col_grid, s, b.spec2, b.spec2, n, P, b.twiddle, b.tab, scale, 0);
-    k_rows_c2r<<<row_blocks, FT, 0, s>>>(b.spec2, out, n, P, b.twiddle, 3, d);
+    if (n == 256 && Trow == 32)
+      k_rows_c2r256<<<row_blocks, FT, 0, s>>>(b.spec2, out, P, b.twiddle, 3, d);
+    else
+      k_rows_c2r<<<row_blocks, FT, 0, s>>>(b.spec2, out, n, P, b.twiddle, 3, d);
   }
   return hipGetLastError();
 }
@@ -458,7 +609,10 @@ hipError_t fft_forward(const FftBufs &b, int n, const float *x, const float *mea
   const int Trow = TL / (n / 2), Tcol = TL / n;
   const unsigned row_blocks = (unsigned)(((int64_t)n * n + Trow - 1) / Trow);
   const dim3 col_grid(P / Tcol, n);
-  k_rows_r2c<<<row_blocks, FT, 0, s>>>(x, b.spec, n, P, b.twiddle, mean);
+  if (n == 256 && Trow == 32)
+    k_rows_r2c256<<<row_blocks, FT, 0, s>>>(x, b.spec, P, b.twiddle, mean);
+  else
+    k_rows_r2c<<<row_blocks, FT, 0, s>>>(x, b.spec, n, P, b.twiddle, mean);
   launch_cols<1, 0>(col_grid, s, b.spec, b.spec, n, P, b.twiddle, b.tab, 0.0f, 0);
   launch_cols<0, 0>(col_grid, s, b.spec, b.spec, n, P, b.twiddle, b.tab, 0.0f, 0);
   return hipGetLastError();
@@ -471,7 +625,10 @@ hipError_t fft_inverse(const FftBufs &b, int n, float *out, int stride, int comp
   const dim3 col_grid(P / Tcol, n);
   launch_cols<0, 2>(col_grid, s, b.spec, b.spec, n, P, b.twiddle, b.tab, 0.0f, 0);
   launch_cols<1, 2>(col_grid, s, b.spec, b.spec, n, P, b.twiddle, b.tab, 0.0f, 0);
-  k_rows_c2r<<<row_blocks, FT, 0, s>>>(b.spec, out, n, P, b.twiddle, stride, comp);
+  if (n == 256 && Trow == 32)
+    k_rows_c2r256<<<row_blocks, FT, 0, s>>>(b.spec, out, P, b.twiddle, stride, comp);
+  else
+    k_rows_c2r<<<row_blocks, FT, 0, s>>>(b.spec, out, n, P, b.twiddle, stride, comp);
   return hipGetLastError();
 }
 
