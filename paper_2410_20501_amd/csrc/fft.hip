@@ -483,18 +483,31 @@ __global__ __launch_bounds__(FT) void k_rows_c2r256(const float2 *__restrict__ s
   __shared__ float2 buf[T * kRowPitch128];
   const int64_t rows = (int64_t)n * n;
   const int64_t row0 = (int64_t)blockIdx.x * T;
-  for (int e = threadIdx.x; e < T * L; e += FT) {
-    const int col = e / L, k = e % L;
+  // the rows' half spectra (L + 1 values each) read once, coalesced, then Z~ formed from
+  // X_k and X_{L-k} in LDS
+  for (int e = threadIdx.x; e < T * (L + 1); e += FT) {
+    const int col = e / (L + 1), k = e % (L + 1);
     const int64_t row = row0 + col;
-    float2 z = make_float2(0.f, 0.f);
-    if (row < rows) {
-      const float2 xk = spec[row * P + k];
-      const float2 xm = conjf2(spec[row * P + (L - k)]);
-      const float2 Et = cadd(xk, xm);
-      const float2 Ot = cmul(conjf2(tw[k]), csub(xk, xm));
-      z = make_float2(Et.x - Ot.y, Et.y + Ot.x);  // Et + i Ot
-    }
-    buf[col * kRowPitch128 + k] = z;
+    buf[col * kRowPitch128 + k] = row < rows ? spec[row * P + k] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  constexpr int kPer = T * L / FT;
+  float2 z[kPer];
+#pragma unroll
+  for (int it = 0; it < kPer; ++it) {
+    const int e = threadIdx.x + it * FT, col = e / L, k = e % L;
+    const float2 *b = buf + col * kRowPitch128;
+    const float2 xk = b[k];
+    const float2 xm = conjf2(b[L - k]);
+    const float2 Et = cadd(xk, xm);
+    const float2 Ot = cmul(conjf2(tw[k]), csub(xk, xm));
+    z[it] = make_float2(Et.x - Ot.y, Et.y + Ot.x);  // Et + i Ot
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < kPer; ++it) {
+    const int e = threadIdx.x + it * FT, col = e / L, k = e % L;
+    buf[col * kRowPitch128 + k] = z[it];
   }
   __syncthreads();
   fft128_rows<true>(buf, tw);
