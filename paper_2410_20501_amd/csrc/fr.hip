@@ -84,7 +84,29 @@ __device__ double root3(double p, double q) {
     const double c = cbrt(0.5 * (d1 - sqrt(disc)));
     return -(c + d0 / c) / 3.0;
   }
-  // three real roots: the largest
+  // three real roots: the largest, by the trigonometric form
+  const double ap = -p;
+  if (ap > 1e-12 && ap < 1e12) {
+    // With q < 0 this root lies in [sqrt(-p), 2 sqrt(-p/3)], where f'(u) = 3u^2 + p >=
+    // 1.5 u^2 and f'' = 6u: a Newton step on f(u) = u^3 + p u + q takes a relative error
+    // e to at most 2 e^2. The form evaluated in FP32 (e of order 1e-6) and two FP64
+    // Newton steps give the root to FP64 rounding at a fraction of the cost of the FP64
+    // arccosine and cosine, which dominate the sweep's arithmetic. The reciprocal of f'
+    // is the hardware estimate with one Newton-Raphson refinement.
+    const float pf = (float)ap;
+    const float sd0f = sqrtf(3.0f * pf);
+    const float ctf = fminf(1.0f, fmaxf(-1.0f, __fdividef((float)d1, 6.0f * pf * sd0f)));
+    double u = (double)(-0.6666667f * sd0f * __cosf(acosf(ctf) * (1.0f / 3.0f) + 2.0943952f));
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const double f = fma(fma(u, u, p), u, q);
+      const double fp = fma(3.0 * u, u, p);
+      double rc = __builtin_amdgcn_rcp(fp);
+      rc = fma(rc, fma(-fp, rc, 1.0), rc);
+      u = fma(-f, rc, u);
+    }
+    return u;
+  }
   const double sd0 = sqrt(d0);
   const double ct = fmin(1.0, fmax(-1.0, d1 / (2.0 * d0 * sd0)));
   return -2.0 * sd0 * cos(acos(ct) / 3.0 + 2.0 * M_PI / 3.0) / 3.0;
@@ -127,11 +149,26 @@ __device__ __forceinline__ double nb_sum(const double *__restrict__ u, int n, in
          pow_n1(u[ri + jp + k], ne) + pow_n1(u[ri + rj + km], ne) + pow_n1(u[ri + rj + kp], ne);
 }
 
+// the sum of u^(n+1) over the six neighbours (i-1, i+1, j-1, j+1, k-1, k+1, in this
+// order) with its multiplies and adds fused explicitly, so the compiler has no choice
+// left: every sweep kernel that calls it gets the same bits
+template <int NE>
+__device__ __forceinline__ double nb6(double a, double b, double c, double d, double e,
+                                      double f) {
+  double t = NE == 1 ? a * a : (a * a) * a;
+  t = fma(NE == 1 ? b : b * b, b, t);
+  t = fma(NE == 1 ? c : c * c, c, t);
+  t = fma(NE == 1 ? d : d * d, d, t);
+  t = fma(NE == 1 ? e : e * e, e, t);
+  return fma(NE == 1 ? f : f * f, f, t);
+}
+
 // one colour of the non-linear red-black Gauss-Seidel: the cells with (i+j+k) % 2 ==
 // colour take the root of their polynomial (n even)
+template <int NE>
 __global__ __launch_bounds__(kFrThreads) void k_fr_sweep(double *__restrict__ u,
                                                          const double *__restrict__ s, FrLevel L,
-                                                         int ne, int colour) {
+                                                         int colour) {
   const int n = L.n, hn = n >> 1;
   const unsigned t = fr_thread();
   if (t >= (unsigned)n * n * hn) return;
@@ -149,9 +186,175 @@ __global__ __launch_bounds__(kFrThreads) void k_fr_sweep(double *__restrict__ u,
     j = (int)(q - (unsigned)i * n);
   }
   const int k = 2 * k2 + ((i + j + colour) & 1);
-  const size_t c = ((size_t)i * n + j) * n + k;
-  const double p = -nb_sum(u, n, i, j, k, ne) / 6.0 + L.ps * s[c];
-  u[c] = ne == 1 ? root3(p, L.q) : root4(p, L.q);
+  const size_t nn = (size_t)n * n, ri = (size_t)i * nn, rj = (size_t)j * n;
+  const size_t c = ri + rj + k;
+  const size_t im = (size_t)wrapn(i - 1, n) * nn, ip = (size_t)wrapn(i + 1, n) * nn;
+  const size_t jm = (size_t)wrapn(j - 1, n) * n, jp = (size_t)wrapn(j + 1, n) * n;
+  const double nb = nb6<NE>(u[im + rj + k], u[ip + rj + k], u[ri + jm + k], u[ri + jp + k],
+                            u[ri + rj + wrapn(k - 1, n)], u[ri + rj + wrapn(k + 1, n)]);
+  const double p = fma(nb, -1.0 / 6.0, L.ps * s[c]);
+  u[c] = NE == 1 ? root3(p, L.q) : root4(p, L.q);
+}
+
+// One full non-linear red-black sweep per pass over HBM (grids of at least 128 cells per
+// side, n % 64 == 0): the 2.5D streaming scheme of the linear smoother, in FP64. A block
+// owns a 16 x 64 (j, k) tile plus a 2-cell halo and a chunk of i-planes; each thread holds
+// one pair of k-neighbouring points (opposite colours) of the tile plus halo in a ring of
+// four planes in registers. Step q loads plane q, applies the first colour to plane q - 1
+// and the second to plane q - 2, and writes plane q - 2; in-plane neighbours come through
+// LDS, published before one barrier (two sets of slots, used by alternate steps). With the
+// colour of a point (i + j + k) mod 2, a step updates the same point of every pair in both
+// of its half-sweeps (E, the point with j + k + first_colour odd, in steps with q even; O
+// with q odd). Halo points are computed unmasked (a wrong value moves one cell per
+// half-sweep and never reaches the tile). Out of place: neighbouring blocks still read the
+// input's halo. The root and the neighbour sum (nb6) are those of k_fr_sweep, so both
+// kernels give the same bits.
+constexpr int kFsSJ = 16, kFsSK = 64, kFsH = 2;
+constexpr int kFsRJ = kFsSJ + 2 * kFsH, kFsRK = kFsSK + 2 * kFsH, kFsRK2 = kFsRK / 2;
+constexpr int kFsNPAIR = kFsRJ * kFsRK2;              // 680
+constexpr int kFsNT = (kFsNPAIR + 63) / 64 * 64;      // 704 threads, one pair each
+constexpr int kFsPAD = kFsRK2 + 2;
+constexpr int kFsARR = kFsNPAIR + 2 * kFsPAD;         // doubles per colour array
+constexpr int kFsSLOT = 2 * kFsARR;                   // E then O
+constexpr int kFsRING = kFsH + 2;                     // planes in registers
+constexpr int kFsPF = 2;                              // planes in flight
+
+struct FrStream {
+  int li, col;
+  bool swp, inside;
+  double uE[kFsRING], uO[kFsRING], sE[kFsRING], sO[kFsRING];
+  double2 pu[kFsPF], ps[kFsPF];
+  const double *uin, *s;
+  double *uout, *lds;
+  int n, i0, ci, qend;
+  size_t nn;
+  __device__ __forceinline__ int wrap_plane(int q) const { return q < 0 ? q + n : (q >= n ? q - n : q); }
+  __device__ __forceinline__ void load(int q, double2 &u, double2 &sv) const {
+    const size_t plane = (size_t)wrap_plane(q) * nn;
+    u = *reinterpret_cast<const double2 *>(uin + plane + col);
+    sv = *reinterpret_cast<const double2 *>(s + plane + col);
+  }
+};
+
+template <int R>
+constexpr int fs_ring(int d) {
+  return ((R - d) % kFsRING + kFsRING) % kFsRING;
+}
+
+// half-sweep S (1, 2) of the step with q = R mod RING: plane q - S, in-plane neighbours
+// from the LDS slot of S (the other points of the plane, as published this step)
+template <int R, int S, int NE>
+__device__ __forceinline__ void fs_half(FrStream &c, const FrLevel &L) {
+  constexpr int cs = fs_ring<R>(S), cm = fs_ring<R>(S + 1), cp = fs_ring<R>(S - 1);
+  const double *LE = c.lds + ((R & 1) * kFsH + S - 1) * kFsSLOT, *LO = LE + kFsARR;
+  const int e = c.li;
+  if constexpr ((R & 1) == 0) {
+    // update E (k-neighbours in the O array at e - 1 + offe, e + offe)
+    const int k = c.swp ? e : e - 1;
+    const double nb =
+        nb6<NE>(c.uE[cm], c.uE[cp], LO[e - kFsRK2], LO[e + kFsRK2], LO[k], LO[k + 1]);
+    const double p = fma(nb, -1.0 / 6.0, L.ps * c.sE[cs]);
+    c.uE[cs] = NE == 1 ? root3(p, L.q) : root4(p, L.q);
+  } else {
+    const int k = c.swp ? e - 1 : e;
+    const double nb =
+        nb6<NE>(c.uO[cm], c.uO[cp], LE[e - kFsRK2], LE[e + kFsRK2], LE[k], LE[k + 1]);
+    const double p = fma(nb, -1.0 / 6.0, L.ps * c.sO[cs]);
+    c.uO[cs] = NE == 1 ? root3(p, L.q) : root4(p, L.q);
+  }
+}
+
+template <int R, int NE>
+__device__ __forceinline__ void fs_step(FrStream &c, const FrLevel &L, int q) {
+  constexpr int P = R % kFsPF, c0 = fs_ring<R>(0), cH = fs_ring<R>(kFsH);
+  {
+    const double2 u = c.pu[P], sv = c.ps[P];
+    c.uE[c0] = c.swp ? u.y : u.x;
+    c.uO[c0] = c.swp ? u.x : u.y;
+    c.sE[c0] = c.swp ? sv.y : sv.x;
+    c.sO[c0] = c.swp ? sv.x : sv.y;
+  }
+  c.load(min(q + kFsPF, c.qend - 1), c.pu[P], c.ps[P]);  // past the end: a harmless reload
+  // half-sweep S acts on plane q - S; it reads the points of that plane it does not
+  // change, published here (E values when it updates O, and the reverse)
+#pragma unroll
+  for (int S = 1; S <= kFsH; ++S) {
+    double *LE = c.lds + ((R & 1) * kFsH + S - 1) * kFsSLOT, *LO = LE + kFsARR;
+    const int cs = ((R - S) % kFsRING + kFsRING) % kFsRING;
+    if ((R & 1) == 1) LE[c.li] = c.uE[cs];
+    if ((R & 1) == 0) LO[c.li] = c.uO[cs];
+  }
+  __syncthreads();
+  fs_half<R, 1, NE>(c, L);
+  fs_half<R, 2, NE>(c, L);
+  const int pout = q - kFsH;  // final
+  if (c.inside && pout >= c.i0 && pout < c.i0 + c.ci) {
+    const double a = c.uE[cH], b = c.uO[cH];
+    *reinterpret_cast<double2 *>(c.uout + (size_t)pout * c.nn + c.col) =
+        c.swp ? make_double2(b, a) : make_double2(a, b);
+  }
+}
+
+template <int R, bool GUARD, int NE>
+__device__ __forceinline__ void fs_steps(FrStream &c, const FrLevel &L, int q) {
+  if constexpr (R < kFsRING) {
+    if (!GUARD || q + R < c.qend) fs_step<R, NE>(c, L, q + R);
+    fs_steps<R + 1, GUARD, NE>(c, L, q);
+  }
+}
+
+template <int NE>
+__global__ __launch_bounds__(kFsNT) void k_fr_sweep_stream(const double *__restrict__ uin,
+                                                           double *__restrict__ uout,
+                                                           const double *__restrict__ s,
+                                                           FrLevel L, int ci,
+                                                           int first_colour) {
+  static_assert(kFsRING % 2 == 0 && kFsRING % kFsPF == 0, "ring parity and prefetch slots");
+  // two sets (steps of even and odd q) of kFsH slots: a set is rewritten two steps after
+  // it was read, behind the barrier that ended those reads
+  __shared__ double lds[2 * kFsH * kFsSLOT];
+  const unsigned lin = xcd_block(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
+                                 gridDim.x * gridDim.y * gridDim.z);
+  const int bx = lin % gridDim.x, by = (lin / gridDim.x) % gridDim.y,
+            bz = lin / (gridDim.x * gridDim.y);
+  const int n = L.n, k0 = bx * kFsSK, j0 = by * kFsSJ;
+  FrStream c;
+  c.uin = uin;
+  c.s = s;
+  c.uout = uout;
+  c.lds = lds;
+  c.n = n;
+  c.i0 = bz * ci;
+  c.ci = ci;
+  c.qend = c.i0 + ci + kFsH;
+  c.nn = (size_t)n * n;
+  for (int e = threadIdx.x; e < kFsPAD; e += kFsNT)
+    for (int a = 0; a < 4 * kFsH; ++a) {
+      lds[a * kFsARR + e] = 1.0;
+      lds[a * kFsARR + kFsPAD + kFsNPAIR + e] = 1.0;
+    }
+  {
+    const int e = threadIdx.x;
+    const bool v = e < kFsNPAIR;
+    const int rj = v ? e / kFsRK2 : 0, r2 = v ? e % kFsRK2 : 0;
+    const int gj = j0 - kFsH + rj, gk = k0 - kFsH + 2 * r2;  // gk even
+    c.swp = ((gj + first_colour) & 1) == 0;  // E = the point with j + k + first_colour odd
+    // a thread without a pair works on the trailing padding (its values reach only halo
+    // points), so every lane runs the same code
+    c.li = v ? kFsPAD + e : kFsPAD + kFsNPAIR + 1;
+    c.col = v ? (wrapn(gj < 0 ? gj + n : (gj >= n ? gj - n : gj), n) * n +
+                 (gk < 0 ? gk + n : (gk >= n ? gk - n : gk)))
+              : 0;
+    c.inside = v && rj >= kFsH && rj < kFsH + kFsSJ && 2 * r2 >= kFsH && 2 * r2 < kFsH + kFsSK;
+#pragma unroll
+    for (int a = 0; a < kFsRING; ++a) c.uE[a] = c.uO[a] = c.sE[a] = c.sO[a] = 1.0;
+  }
+  const int qbeg = c.i0 - kFsH;  // even (ci even): step R of a ring period has q = R mod 2
+#pragma unroll
+  for (int a = 0; a < kFsPF; ++a) c.load(qbeg + a, c.pu[a], c.ps[a]);
+  int q = qbeg;
+  for (; q + kFsRING <= c.qend; q += kFsRING) fs_steps<0, false, NE>(c, L, q);
+  fs_steps<0, true, NE>(c, L, q);
 }
 
 // d = s - N_h(u)
@@ -357,58 +560,88 @@ __global__ __launch_bounds__(kFrThreads) void k_fr_coarse_rhs(const double *__re
   sH[c] += L.a_op * (nb_sum(u0, n, i, j, k, ne) - 6.0 * pow_n1(uc, ne)) - K / uc;
 }
 
-// u += P(uH - u0) on the fine grid of side n: per axis 3/4 of the nearest coarse centre
-// and 1/4 of the next one. One thread per coarse cell (I, J, K) reads the 27 coarse
-// differences around it once and updates its 8 fine children (2I+a, 2J+b, 2K+c) (a
-// thread per fine cell would read 8 coarse pairs for each fine cell).
-__global__ __launch_bounds__(kFrThreads) void k_fr_prolong(double *__restrict__ u, int n,
+// uout = uin + P(uH - u0) on the fine grid of side n: per axis 3/4 of the nearest coarse
+// centre and 1/4 of the next one. A thread owns a coarse column (J, K) over `ch`
+// consecutive coarse planes I and updates the 8 fine children (2I+a, 2J+b, 2K+c) of each;
+// the differences e = uH - u0 of the 3 x 3 (J, K) neighbourhood sit in a ring of three
+// planes (I-1, I, I+1) in registers, so each coarse value is loaded 9 times instead of
+// 27 (a thread per coarse cell) or 64 (a thread per fine cell), and the next plane is in
+// flight while the current one is written.
+// VEC: uin and uout 16-byte aligned, each pair of fine children (2K, 2K+1) loaded and
+// stored as one double2
+template <bool VEC>
+__global__ __launch_bounds__(kFrThreads) void k_fr_prolong(const double *uin, double *uout,
+                                                           int n, int ch,
                                                            const double *__restrict__ uH,
                                                            const double *__restrict__ u0) {
   const int N = n >> 1;
-  const unsigned c = fr_thread();
-  if (c >= (unsigned)N * N * N) return;
-  int I, J, K;
-  cell_ijk(c, N, I, J, K);
-  const int ix[3] = {wrapn(I - 1, N), I, wrapn(I + 1, N)};
-  const int jx[3] = {wrapn(J - 1, N), J, wrapn(J + 1, N)};
+  const unsigned t = fr_thread();
+  if (t >= (unsigned)N * N * (unsigned)(N / ch)) return;
+  int ic, J, K;
+  cell_ijk(t, N, ic, J, K);
+  const size_t NN = (size_t)N * N;
+  const size_t jr[3] = {(size_t)wrapn(J - 1, N) * N, (size_t)J * N, (size_t)wrapn(J + 1, N) * N};
   const int kx[3] = {wrapn(K - 1, N), K, wrapn(K + 1, N)};
   constexpr double w[2] = {0.75, 0.25};
-  double e[3][3][3];
+  const auto load_plane = [&](int I, double(&d)[3][3]) {
+    const size_t r0 = (size_t)wrapn(I, N) * NN;
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      const size_t r = ((size_t)ix[a] * N + jx[b]) * N;
-#pragma unroll
-      for (int q = 0; q < 3; ++q) e[a][b][q] = uH[r + kx[q]] - u0[r + kx[q]];
-    }
+      for (int q = 0; q < 3; ++q) d[b][q] = uH[r0 + jr[b] + kx[q]] - u0[r0 + jr[b] + kx[q]];
+  };
+  const int I0 = ic * ch;
+  double e[3][3][3];  // planes I - 1, I, I + 1
+  load_plane(I0 - 1, e[0]);
+  load_plane(I0, e[1]);
+  load_plane(I0 + 1, e[2]);
   const size_t nn = (size_t)n * n;
+  for (int I = I0; I < I0 + ch; ++I) {
+    double nx[3][3];
+    if (I + 1 < I0 + ch) load_plane(I + 2, nx);
 #pragma unroll
-  for (int ai = 0; ai < 2; ++ai) {      // fine plane 2I + ai: near coarse plane 1, far 0 or 2
-    const int af = ai ? 2 : 0;
+    for (int ai = 0; ai < 2; ++ai) {      // fine plane 2I + ai: near coarse plane 1, far 0 or 2
+      const int af = ai ? 2 : 0;
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {    // fine row 2J + bj
-      const int bf = bj ? 2 : 0;
-      double out[2];
+      for (int bj = 0; bj < 2; ++bj) {    // fine row 2J + bj
+        const int bf = bj ? 2 : 0;
+        double out[2];
 #pragma unroll
-      for (int ck = 0; ck < 2; ++ck) {  // fine column 2K + ck
-        const int kf = ck ? 2 : 0;
-        // the same sum as per fine cell: planes (near, far) x rows (near, far), each the
-        // k-interpolation w0 e_near + w1 e_far
-        const int pa[2] = {1, af}, pb[2] = {1, bf};
-        double v = 0.0;
+        for (int ck = 0; ck < 2; ++ck) {  // fine column 2K + ck
+          const int kf = ck ? 2 : 0;
+          // planes (near, far) x rows (near, far), each the k-interpolation
+          // w0 e_near + w1 e_far
+          const int pa[2] = {1, af}, pb[2] = {1, bf};
+          double v = 0.0;
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+          for (int a = 0; a < 2; ++a)
 #pragma unroll
-          for (int b = 0; b < 2; ++b) {
-            const double t = w[0] * e[pa[a]][pb[b]][1] + w[1] * e[pa[a]][pb[b]][kf];
-            v += w[a] * w[b] * t;
-          }
-        out[ck] = v;
+            for (int b = 0; b < 2; ++b) {
+              const double tk = w[0] * e[pa[a]][pb[b]][1] + w[1] * e[pa[a]][pb[b]][kf];
+              v += w[a] * w[b] * tk;
+            }
+          out[ck] = v;
+        }
+        const size_t o = (size_t)(2 * I + ai) * nn + (size_t)(2 * J + bj) * n + 2 * K;
+        // (in place when uout == uin)
+        if constexpr (VEC) {
+          const double2 v = *reinterpret_cast<const double2 *>(uin + o);
+          *reinterpret_cast<double2 *>(uout + o) = make_double2(v.x + out[0], v.y + out[1]);
+        } else {
+          uout[o] = uin[o] + out[0];
+          uout[o + 1] = uin[o + 1] + out[1];
+        }
       }
-      double *dst = u + (size_t)(2 * I + ai) * nn + (size_t)(2 * J + bj) * n + 2 * K;
-      dst[0] += out[0];
-      dst[1] += out[1];
+    }
+    if (I + 1 < I0 + ch) {
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          e[0][b][q] = e[1][b][q];
+          e[1][b][q] = e[2][b][q];
+          e[2][b][q] = nx[b][q];
+        }
     }
   }
 }
@@ -430,7 +663,7 @@ __global__ __launch_bounds__(kFrCoarseThreads) void k_fr_coarse(double *__restri
       for (int c = threadIdx.x; c < cells; c += kFrCoarseThreads) {
         const int i = c / (n * n), j = (c / n) % n, k = c % n;
         if (((i + j + k) & 1) != colour) continue;
-        const double p = -nb_sum(su, n, i, j, k, ne) / 6.0 + L.ps * ss[c];
+        const double p = fma(nb_sum(su, n, i, j, k, ne), -1.0 / 6.0, L.ps * ss[c]);
         su[c] = ne == 1 ? root3(p, L.q) : root4(p, L.q);
       }
       __syncthreads();
@@ -545,9 +778,52 @@ struct FrRun {
     const int64_t half = (int64_t)L.n * L.n * L.n / 2;
     const double *sv = ctx->fr_lev[l].s;
     if (l == 0) pm_kt_begin(ctx, PM_KERNEL_FR_SWEEP, s);
-    k_fr_sweep<<<blocks(half), kFrThreads, 0, s>>>(u, sv, L, ne, first);
-    k_fr_sweep<<<blocks(half), kFrThreads, 0, s>>>(u, sv, L, ne, 1 - first);
+    for (int colour : {first, 1 - first}) {
+      if (ne == 1)
+        k_fr_sweep<1><<<blocks(half), kFrThreads, 0, s>>>(u, sv, L, colour);
+      else
+        k_fr_sweep<2><<<blocks(half), kFrThreads, 0, s>>>(u, sv, L, colour);
+    }
     if (l == 0) pm_kt_end(ctx, PM_KERNEL_FR_SWEEP, s, 32.0 * 2.0 * (double)half);
+    return hipGetLastError();
+  }
+
+  // the streaming sweep (out of place) on level l: grids of at least 256 cells per side
+  // in 16 x 64 tiles, when the pre- and post-sweeps and the out-of-place prolongation
+  // leave the iterate in the caller's array (an odd pre + post count) and u is 16-byte
+  // aligned for the paired loads
+  bool streams(int l, const double *u) const {
+    const int n = ctx->fr_lev[l].n;
+    return ctx->fr_lev[l].alt && n >= 256 && n % kFsSK == 0 &&
+           (p->fr_pre + p->fr_post) % 2 == 1 && (reinterpret_cast<uintptr_t>(u) & 15) == 0;
+  }
+
+  void prolong(int l, const double *in, double *out) {
+    const FrLevel L = level(l);
+    const pm_fr_level &C = ctx->fr_lev[l + 1];
+    // coarse planes per thread: up to 16, a divisor of N, with at least 2048 workgroups
+    const int N = L.n / 2;
+    int ch = 16;
+    while (ch > 1 && (N % ch != 0 || (int64_t)N * N * (N / ch) < 2048 * kFrThreads)) ch /= 2;
+    const int64_t threads = (int64_t)N * N * (N / ch);
+    if (((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15) == 0)
+      k_fr_prolong<true><<<blocks(threads), kFrThreads, 0, s>>>(in, out, L.n, ch, C.u, C.u0);
+    else
+      k_fr_prolong<false><<<blocks(threads), kFrThreads, 0, s>>>(in, out, L.n, ch, C.u, C.u0);
+  }
+
+  hipError_t stream_sweep(int l, const double *in, double *out, int first) {
+    const FrLevel L = level(l);
+    const int n = L.n, tiles = (n / kFsSJ) * (n / kFsSK);
+    int ci = n;
+    while (ci / 2 >= 16 && tiles * (n / ci) < 512 && n % (ci / 2) == 0) ci /= 2;
+    const dim3 grid(n / kFsSK, n / kFsSJ, n / ci);
+    if (l == 0) pm_kt_begin(ctx, PM_KERNEL_FR_SWEEP, s);
+    if (ne == 1)
+      k_fr_sweep_stream<1><<<grid, kFsNT, 0, s>>>(in, out, ctx->fr_lev[l].s, L, ci, first);
+    else
+      k_fr_sweep_stream<2><<<grid, kFsNT, 0, s>>>(in, out, ctx->fr_lev[l].s, L, ci, first);
+    if (l == 0) pm_kt_end(ctx, PM_KERNEL_FR_SWEEP, s, 32.0 * (double)n * n * n);
     return hipGetLastError();
   }
 
@@ -566,8 +842,17 @@ struct FrRun {
     if (l == ctx->fr_nlev - 1) return coarsest(l, u);
     const FrLevel L = level(l);
     const int64_t cells = (int64_t)L.n * L.n * L.n;
-    for (int it = 0; it < p->fr_pre; ++it)
-      if (hipError_t e = sweep(l, u, 0)) return e;
+    // streaming levels ping-pong between u and alt (cur holds the iterate)
+    const bool st = streams(l, u);
+    double *cur = u, *oth = st ? ctx->fr_lev[l].alt : nullptr;
+    for (int it = 0; it < p->fr_pre; ++it) {
+      if (st) {
+        if (hipError_t e = stream_sweep(l, cur, oth, 0)) return e;
+        std::swap(cur, oth);
+      } else if (hipError_t e = sweep(l, u, 0)) {
+        return e;
+      }
+    }
     pm_fr_level &C = ctx->fr_lev[l + 1];
     const int64_t cc = (int64_t)C.n * C.n * C.n;
     if (C.n >= 128 && C.n % kRrCJ == 0) {
@@ -578,11 +863,11 @@ struct FrRun {
       int cic = C.n;
       while (cic / 2 >= 8 && tiles * (C.n / cic) < 2048 && C.n % (cic / 2) == 0) cic /= 2;
       const dim3 grid(C.n / kRrCK, C.n / kRrCJ, C.n / cic);
-      k_fr_rr<<<grid, kRrT, 0, s>>>(u, ctx->fr_lev[l].s, L, K, ne, cic, C.u0, C.u, C.s);
+      k_fr_rr<<<grid, kRrT, 0, s>>>(cur, ctx->fr_lev[l].s, L, K, ne, cic, C.u0, C.u, C.s);
     } else {
       double *d = ctx->fr_lev[l].d;
-      k_fr_residual<<<blocks(cells), kFrThreads, 0, s>>>(u, ctx->fr_lev[l].s, L, K, ne, d);
-      k_fr_restrict<<<blocks(cc), kFrThreads, 0, s>>>(u, d, L.n, C.u0, C.u, C.s);
+      k_fr_residual<<<blocks(cells), kFrThreads, 0, s>>>(cur, ctx->fr_lev[l].s, L, K, ne, d);
+      k_fr_restrict<<<blocks(cc), kFrThreads, 0, s>>>(cur, d, L.n, C.u0, C.u, C.s);
     }
     k_fr_coarse_rhs<<<blocks(cc), kFrThreads, 0, s>>>(C.u0, level(l + 1), K, ne, C.s);
     if (hipError_t e = hipGetLastError()) return e;
@@ -592,9 +877,21 @@ struct FrRun {
     const int visits = kind == PM_CYCLE_V ? 1 : 2;
     for (int v = 0; v < visits; ++v)
       if (hipError_t e = cycle(l + 1, C.u, inner[v])) return e;
-    k_fr_prolong<<<blocks(cells / 8), kFrThreads, 0, s>>>(u, L.n, C.u, C.u0);
-    for (int it = 0; it < p->fr_post; ++it)
-      if (hipError_t e = sweep(l, u, 1)) return e;
+    if (st) {
+      prolong(l, cur, oth);
+      std::swap(cur, oth);
+    } else {
+      prolong(l, u, u);
+    }
+    for (int it = 0; it < p->fr_post; ++it) {
+      if (st) {
+        if (hipError_t e = stream_sweep(l, cur, oth, 1)) return e;
+        std::swap(cur, oth);
+      } else if (hipError_t e = sweep(l, u, 1)) {
+        return e;
+      }
+    }
+    // (an odd pre + post count brings the iterate back to u)
     return hipGetLastError();
   }
 
@@ -640,9 +937,11 @@ int pm_fr_setup(pm_ctx *ctx) {
     bool ok = hipMalloc(&lev[l].s, bytes) == hipSuccess && hipMalloc(&lev[l].d, bytes) == hipSuccess;
     if (ok && l > 0)
       ok = hipMalloc(&lev[l].u, bytes) == hipSuccess && hipMalloc(&lev[l].u0, bytes) == hipSuccess;
+    if (ok && lev[l].n >= 256 && lev[l].n % kFsSK == 0)
+      ok = hipMalloc(&lev[l].alt, bytes) == hipSuccess;
     if (!ok) {
       for (int m = 0; m <= l; ++m) {
-        for (double *q : {lev[m].s, lev[m].d, lev[m].u, lev[m].u0})
+        for (double *q : {lev[m].s, lev[m].d, lev[m].u, lev[m].u0, lev[m].alt})
           if (q) (void)hipFree(q);
       }
       (void)hipGetLastError();
@@ -656,7 +955,8 @@ int pm_fr_setup(pm_ctx *ctx) {
 
 void pm_fr_free(pm_ctx *ctx) {
   for (int l = 0; l < ctx->fr_nlev; ++l)
-    for (double *q : {ctx->fr_lev[l].s, ctx->fr_lev[l].d, ctx->fr_lev[l].u, ctx->fr_lev[l].u0})
+    for (double *q : {ctx->fr_lev[l].s, ctx->fr_lev[l].d, ctx->fr_lev[l].u, ctx->fr_lev[l].u0,
+                      ctx->fr_lev[l].alt})
       if (q) (void)hipFree(q);
   ctx->fr_nlev = 0;
   if (ctx->fr_u) (void)hipFree(ctx->fr_u);

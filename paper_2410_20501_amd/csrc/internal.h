@@ -30,6 +30,7 @@ struct pm_fr_level {
   double *s;   // right-hand side
   double *u0;  // R u of the finer grid (levels > 0)
   double *d;   // residual scratch
+  double *alt; // second iterate buffer of the streaming sweeps (levels of >= 256 cells)
 };
 
 struct pm_ctx {

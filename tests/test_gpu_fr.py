@@ -48,7 +48,7 @@ def _fr_params(lib, f0, n_exp, box, **kw):
 @pytest.mark.parametrize("n,n_exp,cycle,cycles,f0", [
     (32, 1, "F", 1, -1e-5), (32, 2, "F", 1, -1e-5), (48, 1, "F", 2, -1e-6),
     (64, 1, "V", 2, -1e-5), (64, 2, "W", 1, -1e-6), (128, 1, "F", 1, -1e-6),
-    (128, 2, "F", 1, -1e-6), (256, 1, "F", 1, -1e-6)])
+    (128, 2, "F", 1, -1e-6), (256, 1, "F", 1, -1e-6), (256, 2, "V", 1, -1e-6)])
 def test_scalaron_solve_parity(lib, n, n_exp, cycle, cycles, f0):
     rho = _lognormal(n, 1.0, 30 + n + n_exp)
     a = 0.5
@@ -67,6 +67,29 @@ def test_scalaron_solve_parity(lib, n, n_exp, cycle, cycles, f0):
     assert du <= 1e-9
     assert rr[0] == pytest.approx(hist[0], rel=1e-6)
     assert rr[1] == pytest.approx(hist[-1], rel=1e-6)
+
+
+@pytest.mark.parametrize("n,n_exp", [(256, 1), (320, 2)])
+def test_streaming_sweep_matches_colour_passes(lib, n, n_exp):
+    """Grids of 256 cells per side and more (a multiple of 64) sweep in one streaming pass
+    per red-black sweep when u is 16-byte aligned; an 8-byte offset u takes the two colour
+    passes. Red-black Gauss-Seidel does not depend on the order of the cells within a
+    colour and both kernels evaluate the same arithmetic: the same bits."""
+    rho = torch.from_numpy(_lognormal(n, 1.0, 60 + n_exp)).cuda()
+    p = _fr_params(lib, -1e-5, n_exp, 100.0, fr_cycle="F", fr_cycles=2)
+    ctx = lib.Context(n)
+    u_al = torch.ones((n, n, n), dtype=torch.float64, device="cuda")
+    buf = torch.ones(n ** 3 + 1, dtype=torch.float64, device="cuda")
+    u_off = buf[1:].view(n, n, n)
+    assert u_al.data_ptr() % 16 == 0 and u_off.data_ptr() % 16 == 8
+    rr_al = lib.pm_solve_fr(ctx, rho, 0.5, p, u_al, relres=True)
+    rr_off = lib.pm_solve_fr(ctx, rho, 0.5, p, u_off, relres=True)
+    diff = float((u_al - u_off).abs().max())
+    _say(f"fr streaming vs colour passes n={n} nexp={n_exp}: max|du| {diff:.1e}, relres "
+         f"{rr_al[1]:.3e} / {rr_off[1]:.3e}")
+    ctx.close()
+    assert diff == 0.0 and rr_al == rr_off
+    assert rr_al[1] < rr_al[0] / 5
 
 
 def test_scalaron_background_is_fixed(lib):
