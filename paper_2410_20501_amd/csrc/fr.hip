@@ -66,13 +66,48 @@ __device__ __forceinline__ void stable_root_difference(double d0, double d1, dou
   diff = amb * (A + B) / (Q2 * Q2 - d0 * Q2 + d0 * d0);
 }
 
-// positive root of u^3 + p u + q = 0 (q < 0), the closed forms of Sect. 3.11
+// Two Newton steps on f(u) = u^3 + p u + q from an FP32 estimate u of the positive root r
+// (q < 0). In every case of root3, f'(r) = 3 r^2 + p >= 1.5 r^2 and f'' = 6u, so a step
+// takes a relative error e to at most 2 e^2: an estimate good to about 1e-6 reaches FP64
+// rounding in two steps. The reciprocal of f' is the hardware estimate with one
+// Newton-Raphson refinement.
+__device__ __forceinline__ double newton3(double u, double p, double q) {
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double f = fma(fma(u, u, p), u, q);
+    const double fp = fma(3.0 * u, u, p);
+    double rc = __builtin_amdgcn_rcp(fp);
+    rc = fma(rc, fma(-fp, rc, 1.0), rc);
+    u = fma(-f, rc, u);
+  }
+  return u;
+}
+
+// positive root of u^3 + p u + q = 0 (q < 0), the closed forms of Sect. 3.11. Where p and
+// q are in a range whose FP32 intermediates neither overflow nor underflow, the form of
+// the case is evaluated in FP32 (the cancellation-free arrangements below, the
+// discriminant in FP64) and polished by newton3: the same root to FP64 rounding at a
+// fraction of the cost of FP64 cube roots, arccosines and cosines, which would dominate
+// the sweep's arithmetic. Outside that range the forms are evaluated in FP64.
 __device__ double root3(double p, double q) {
   if (p == 0.0) return cbrt(-q);
   const double d0 = -3.0 * p, d1 = 27.0 * q;
+  const double ap = fabs(p), aq = -q;
+  const bool f32 = ap > 1e-10 && ap < 1e10 && aq > 1e-15 && aq < 1e10;
   if (p > 0.0) {
     // one real root -(C + Delta0 / C) / 3 = (|C|^2 + Delta0) / (3 |C|), formed without
-    // cancellation (the root is small where p is large)
+    // cancellation (the root is small where p is large). f' >= 3 r^2 here.
+    if (f32) {
+      const float d0f = (float)d0, d1f = (float)d1, tp = -d0f;
+      const float B = tp * sqrtf(tp);
+      const float sq = sqrtf(d1f * d1f + 4.0f * B * B);
+      const float ad1 = fabsf(d1f);
+      const float A = 0.5f * (ad1 + sq);
+      const float Q = cbrtf(A), Q2 = Q * Q;
+      const float amb = 0.5f * ad1 + __fdividef(0.5f * d1f * d1f, sq + 2.0f * B);
+      const float diff = __fdividef(amb * (A + B), Q2 * Q2 - d0f * Q2 + d0f * d0f);
+      return newton3((double)__fdividef(diff, 3.0f * Q), p, q);
+    }
     double C, diff;
     stable_root_difference(d0, d1, C, diff);
     return diff / (3.0 * C);
@@ -80,32 +115,23 @@ __device__ double root3(double p, double q) {
   const double disc = d1 * d1 - 4.0 * d0 * d0 * d0;
   if (disc > 0.0) {
     // one real root; C^3 = (Delta1 - sqrt(disc)) / 2 (the other sign gives Delta0 / C
-    // and the same root); C and Delta0 / C have one sign here
+    // and the same root); C and Delta0 / C have one sign here. The root exceeds
+    // sqrt(-p) (f(sqrt(-p)) = q < 0), so f' >= 2 r^2.
+    if (f32) {
+      const float c = cbrtf(0.5f * ((float)d1 - sqrtf((float)disc)));
+      return newton3((double)(-(c + __fdividef((float)d0, c)) * (1.0f / 3.0f)), p, q);
+    }
     const double c = cbrt(0.5 * (d1 - sqrt(disc)));
     return -(c + d0 / c) / 3.0;
   }
-  // three real roots: the largest, by the trigonometric form
-  const double ap = -p;
-  if (ap > 1e-12 && ap < 1e12) {
-    // With q < 0 this root lies in [sqrt(-p), 2 sqrt(-p/3)], where f'(u) = 3u^2 + p >=
-    // 1.5 u^2 and f'' = 6u: a Newton step on f(u) = u^3 + p u + q takes a relative error
-    // e to at most 2 e^2. The form evaluated in FP32 (e of order 1e-6) and two FP64
-    // Newton steps give the root to FP64 rounding at a fraction of the cost of the FP64
-    // arccosine and cosine, which dominate the sweep's arithmetic. The reciprocal of f'
-    // is the hardware estimate with one Newton-Raphson refinement.
+  // three real roots: the largest, by the trigonometric form. With q < 0 it lies in
+  // [sqrt(-p), 2 sqrt(-p/3)], where f' >= 1.5 r^2.
+  if (f32) {
     const float pf = (float)ap;
     const float sd0f = sqrtf(3.0f * pf);
     const float ctf = fminf(1.0f, fmaxf(-1.0f, __fdividef((float)d1, 6.0f * pf * sd0f)));
-    double u = (double)(-0.6666667f * sd0f * __cosf(acosf(ctf) * (1.0f / 3.0f) + 2.0943952f));
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-      const double f = fma(fma(u, u, p), u, q);
-      const double fp = fma(3.0 * u, u, p);
-      double rc = __builtin_amdgcn_rcp(fp);
-      rc = fma(rc, fma(-fp, rc, 1.0), rc);
-      u = fma(-f, rc, u);
-    }
-    return u;
+    return newton3(
+        (double)(-0.6666667f * sd0f * __cosf(acosf(ctf) * (1.0f / 3.0f) + 2.0943952f)), p, q);
   }
   const double sd0 = sqrt(d0);
   const double ct = fmin(1.0, fmax(-1.0, d1 / (2.0 * d0 * sd0)));
@@ -647,28 +673,52 @@ __global__ __launch_bounds__(kFrThreads) void k_fr_prolong(const double *uin, do
 }
 
 // the coarsest grid (n^3 <= kFrCoarseMax, n even): `sweeps` red-black sweeps in LDS
+template <int NE>
 __global__ __launch_bounds__(kFrCoarseThreads) void k_fr_coarse(double *__restrict__ u,
                                                                 const double *__restrict__ s,
-                                                                FrLevel L, int ne, int sweeps) {
+                                                                FrLevel L, int sweeps) {
+  constexpr int kCC = kFrCoarseMax / kFrCoarseThreads;  // cells per thread at most
   __shared__ double su[kFrCoarseMax];
   __shared__ double ss[kFrCoarseMax];
   const int n = L.n, cells = n * n * n;
-  for (int c = threadIdx.x; c < cells; c += kFrCoarseThreads) {
-    su[c] = u[c];
-    ss[c] = s[c];
+  // a thread's cells, their colours and neighbours' places, decoded once for all sweeps
+  int cell[kCC], colour_of[kCC], nbr[kCC][6];
+#pragma unroll
+  for (int m = 0; m < kCC; ++m) {
+    const int c = (int)threadIdx.x + m * kFrCoarseThreads;
+    cell[m] = c < cells ? c : -1;
+    const int cv = c < cells ? c : 0;
+    const int i = cv / (n * n), j = (cv / n) % n, k = cv % n;
+    colour_of[m] = (i + j + k) & 1;
+    const int ri = i * n * n, rj = j * n;
+    nbr[m][0] = wrapn(i - 1, n) * n * n + rj + k;
+    nbr[m][1] = wrapn(i + 1, n) * n * n + rj + k;
+    nbr[m][2] = ri + wrapn(j - 1, n) * n + k;
+    nbr[m][3] = ri + wrapn(j + 1, n) * n + k;
+    nbr[m][4] = ri + rj + wrapn(k - 1, n);
+    nbr[m][5] = ri + rj + wrapn(k + 1, n);
+    if (c < cells) {
+      su[c] = u[c];
+      ss[c] = s[c];
+    }
   }
   __syncthreads();
   for (int it = 0; it < sweeps; ++it)
     for (int colour = 0; colour < 2; ++colour) {
-      for (int c = threadIdx.x; c < cells; c += kFrCoarseThreads) {
-        const int i = c / (n * n), j = (c / n) % n, k = c % n;
-        if (((i + j + k) & 1) != colour) continue;
-        const double p = fma(nb_sum(su, n, i, j, k, ne), -1.0 / 6.0, L.ps * ss[c]);
-        su[c] = ne == 1 ? root3(p, L.q) : root4(p, L.q);
+#pragma unroll
+      for (int m = 0; m < kCC; ++m) {
+        const int c = cell[m];
+        if (c < 0 || colour_of[m] != colour) continue;
+        const double nb = nb6<NE>(su[nbr[m][0]], su[nbr[m][1]], su[nbr[m][2]], su[nbr[m][3]],
+                                  su[nbr[m][4]], su[nbr[m][5]]);
+        const double p = fma(nb, -1.0 / 6.0, L.ps * ss[c]);
+        su[c] = NE == 1 ? root3(p, L.q) : root4(p, L.q);
       }
       __syncthreads();
     }
-  for (int c = threadIdx.x; c < cells; c += kFrCoarseThreads) u[c] = su[c];
+#pragma unroll
+  for (int m = 0; m < kCC; ++m)
+    if (cell[m] >= 0) u[cell[m]] = su[cell[m]];
 }
 
 // s = -cA (rho - mean) - K
@@ -830,7 +880,10 @@ struct FrRun {
   hipError_t coarsest(int l, double *u) {
     const FrLevel L = level(l);
     if ((int64_t)L.n * L.n * L.n <= kFrCoarseMax) {
-      k_fr_coarse<<<1, kFrCoarseThreads, 0, s>>>(u, ctx->fr_lev[l].s, L, ne, p->fr_coarse_sweeps);
+      if (ne == 1)
+        k_fr_coarse<1><<<1, kFrCoarseThreads, 0, s>>>(u, ctx->fr_lev[l].s, L, p->fr_coarse_sweeps);
+      else
+        k_fr_coarse<2><<<1, kFrCoarseThreads, 0, s>>>(u, ctx->fr_lev[l].s, L, p->fr_coarse_sweeps);
       return hipGetLastError();
     }
     for (int it = 0; it < p->fr_coarse_sweeps; ++it)
