@@ -69,15 +69,16 @@ __device__ __forceinline__ void stable_root_difference(double d0, double d1, dou
 // Two Newton steps on f(u) = u^3 + p u + q from an FP32 estimate u of the positive root r
 // (q < 0). In every case of root3, f'(r) = 3 r^2 + p >= 1.5 r^2 and f'' = 6u, so a step
 // takes a relative error e to at most 2 e^2: an estimate good to about 1e-6 reaches FP64
-// rounding in two steps. The reciprocal of f' is the hardware estimate with one
-// Newton-Raphson refinement.
+// rounding in two steps. The reciprocal of f' is the hardware estimate, refined by one
+// Newton-Raphson step in the first step only: the second step's correction is of order
+// 1e-12 u, so an estimate good to 1e-4 leaves an error far below rounding.
 __device__ __forceinline__ double newton3(double u, double p, double q) {
 #pragma unroll
   for (int it = 0; it < 2; ++it) {
     const double f = fma(fma(u, u, p), u, q);
     const double fp = fma(3.0 * u, u, p);
     double rc = __builtin_amdgcn_rcp(fp);
-    rc = fma(rc, fma(-fp, rc, 1.0), rc);
+    if (it == 0) rc = fma(rc, fma(-fp, rc, 1.0), rc);
     u = fma(-f, rc, u);
   }
   return u;
@@ -125,13 +126,22 @@ __device__ double root3(double p, double q) {
     return -(c + d0 / c) / 3.0;
   }
   // three real roots: the largest, by the trigonometric form. With q < 0 it lies in
-  // [sqrt(-p), 2 sqrt(-p/3)], where f' >= 1.5 r^2.
+  // [sqrt(-p), 2 sqrt(-p/3)], where f' >= 1.5 r^2. With cos(theta) = Delta1 /
+  // (2 Delta0^(3/2)) = -s (s in [0, 1]) the form -(2/3) sqrt(Delta0) cos(theta/3 + 2pi/3)
+  // is (2/3) sqrt(Delta0) g(s), g(s) = cos(arccos(s) / 3), a smooth function from
+  // cos(pi/6) to 1; the estimate takes g from a degree-5 least-squares polynomial
+  // (fitted on Chebyshev nodes of [0, 1], relative error 7e-7).
   if (f32) {
     const float pf = (float)ap;
-    const float sd0f = sqrtf(3.0f * pf);
-    const float ctf = fminf(1.0f, fmaxf(-1.0f, __fdividef((float)d1, 6.0f * pf * sd0f)));
-    return newton3(
-        (double)(-0.6666667f * sd0f * __cosf(acosf(ctf) * (1.0f / 3.0f) + 2.0943952f)), p, q);
+    const float sd0f = __builtin_amdgcn_sqrtf(3.0f * pf);
+    const float sf = fminf(1.0f, fmaxf(0.0f, __fdividef(-(float)d1, 6.0f * pf * sd0f)));
+    float g = 0.00198191f;
+    g = fmaf(g, sf, -0.00905417f);
+    g = fmaf(g, sf, 0.02197779f);
+    g = fmaf(g, sf, -0.04755363f);
+    g = fmaf(g, sf, 0.16662256f);
+    g = fmaf(g, sf, 0.86602598f);
+    return newton3((double)(0.6666667f * sd0f * g), p, q);
   }
   const double sd0 = sqrt(d0);
   const double ct = fmin(1.0, fmax(-1.0, d1 / (2.0 * d0 * sd0)));
