@@ -28,6 +28,13 @@ __host__ __device__ inline int wrapn(int i, int n) { return i < 0 ? i + n : (i >
 
 __device__ __forceinline__ double pow_n1(double u, int ne) { return ne == 1 ? u * u : u * u * u; }
 
+// the finest grid's right-hand side from the density, s = -cA (rho - mean) - K, in one
+// fused multiply-add: k_fr_source and the finest grid's streaming kernels, which read rho
+// in place of s, get the same bits
+__device__ __forceinline__ double fr_source(float rho, double mean, double cA, double K) {
+  return fma(-cA, (double)rho - mean, -K);
+}
+
 // (i, j, k) of cell c = (i n + j) n + k in 32-bit arithmetic (n^3 <= 2^30): masks and
 // shifts for a power-of-two side (the usual case; n is uniform over the launch),
 // 32-bit divisions otherwise. (64-bit divisions, a long software sequence per cell,
@@ -260,15 +267,31 @@ struct FrStream {
   bool swp, inside;
   double uE[kFsRING], uO[kFsRING], sE[kFsRING], sO[kFsRING];
   double2 pu[kFsPF], ps[kFsPF];
+  float2 pr[kFsPF];  // the density's pairs in flight, in place of ps (RHO)
   const double *uin, *s;
+  const float *rho;  // (RHO) s formed from the density (fr_source), not read
+  double mean, cA, K;
   double *uout, *lds;
   int n, i0, ci, qend;
   size_t nn;
   __device__ __forceinline__ int wrap_plane(int q) const { return q < 0 ? q + n : (q >= n ? q - n : q); }
-  __device__ __forceinline__ void load(int q, double2 &u, double2 &sv) const {
+  // plane q into prefetch slot P; with RHO the density is kept as loaded and turned into
+  // s only when the slot is used, so the loads stay in flight
+  template <bool RHO>
+  __device__ __forceinline__ void load(int q, int P) {
     const size_t plane = (size_t)wrap_plane(q) * nn;
-    u = *reinterpret_cast<const double2 *>(uin + plane + col);
-    sv = *reinterpret_cast<const double2 *>(s + plane + col);
+    pu[P] = *reinterpret_cast<const double2 *>(uin + plane + col);
+    if constexpr (RHO)
+      pr[P] = *reinterpret_cast<const float2 *>(rho + plane + col);
+    else
+      ps[P] = *reinterpret_cast<const double2 *>(s + plane + col);
+  }
+  template <bool RHO>
+  __device__ __forceinline__ double2 source_pair(int P) const {
+    if constexpr (RHO)
+      return make_double2(fr_source(pr[P].x, mean, cA, K), fr_source(pr[P].y, mean, cA, K));
+    else
+      return ps[P];
   }
 };
 
@@ -300,17 +323,17 @@ __device__ __forceinline__ void fs_half(FrStream &c, const FrLevel &L) {
   }
 }
 
-template <int R, int NE>
+template <int R, int NE, bool RHO>
 __device__ __forceinline__ void fs_step(FrStream &c, const FrLevel &L, int q) {
   constexpr int P = R % kFsPF, c0 = fs_ring<R>(0), cH = fs_ring<R>(kFsH);
   {
-    const double2 u = c.pu[P], sv = c.ps[P];
+    const double2 u = c.pu[P], sv = c.template source_pair<RHO>(P);
     c.uE[c0] = c.swp ? u.y : u.x;
     c.uO[c0] = c.swp ? u.x : u.y;
     c.sE[c0] = c.swp ? sv.y : sv.x;
     c.sO[c0] = c.swp ? sv.x : sv.y;
   }
-  c.load(min(q + kFsPF, c.qend - 1), c.pu[P], c.ps[P]);  // past the end: a harmless reload
+  c.template load<RHO>(min(q + kFsPF, c.qend - 1), P);  // past the end: a harmless reload
   // half-sweep S acts on plane q - S; it reads the points of that plane it does not
   // change, published here (E values when it updates O, and the reverse)
 #pragma unroll
@@ -331,20 +354,22 @@ __device__ __forceinline__ void fs_step(FrStream &c, const FrLevel &L, int q) {
   }
 }
 
-template <int R, bool GUARD, int NE>
+template <int R, bool GUARD, int NE, bool RHO>
 __device__ __forceinline__ void fs_steps(FrStream &c, const FrLevel &L, int q) {
   if constexpr (R < kFsRING) {
-    if (!GUARD || q + R < c.qend) fs_step<R, NE>(c, L, q + R);
-    fs_steps<R + 1, GUARD, NE>(c, L, q);
+    if (!GUARD || q + R < c.qend) fs_step<R, NE, RHO>(c, L, q + R);
+    fs_steps<R + 1, GUARD, NE, RHO>(c, L, q);
   }
 }
 
-template <int NE>
+template <int NE, bool RHO>
 __global__ __launch_bounds__(kFsNT) void k_fr_sweep_stream(const double *__restrict__ uin,
                                                            double *__restrict__ uout,
                                                            const double *__restrict__ s,
-                                                           FrLevel L, int ci,
-                                                           int first_colour) {
+                                                           const float *__restrict__ rho,
+                                                           const double *__restrict__ mean,
+                                                           double cA, double K, FrLevel L,
+                                                           int ci, int first_colour) {
   static_assert(kFsRING % 2 == 0 && kFsRING % kFsPF == 0, "ring parity and prefetch slots");
   // two sets (steps of even and odd q) of kFsH slots: a set is rewritten two steps after
   // it was read, behind the barrier that ended those reads
@@ -357,6 +382,10 @@ __global__ __launch_bounds__(kFsNT) void k_fr_sweep_stream(const double *__restr
   FrStream c;
   c.uin = uin;
   c.s = s;
+  c.rho = rho;
+  c.mean = RHO ? mean[0] : 0.0;
+  c.cA = cA;
+  c.K = K;
   c.uout = uout;
   c.lds = lds;
   c.n = n;
@@ -387,10 +416,10 @@ __global__ __launch_bounds__(kFsNT) void k_fr_sweep_stream(const double *__restr
   }
   const int qbeg = c.i0 - kFsH;  // even (ci even): step R of a ring period has q = R mod 2
 #pragma unroll
-  for (int a = 0; a < kFsPF; ++a) c.load(qbeg + a, c.pu[a], c.ps[a]);
+  for (int a = 0; a < kFsPF; ++a) c.template load<RHO>(qbeg + a, a);
   int q = qbeg;
-  for (; q + kFsRING <= c.qend; q += kFsRING) fs_steps<0, false, NE>(c, L, q);
-  fs_steps<0, true, NE>(c, L, q);
+  for (; q + kFsRING <= c.qend; q += kFsRING) fs_steps<0, false, NE, RHO>(c, L, q);
+  fs_steps<0, true, NE, RHO>(c, L, q);
 }
 
 // d = s - N_h(u)
@@ -456,9 +485,12 @@ constexpr int kRrUJ = 2 * kRrCJ + 4, kRrUK = 2 * kRrCK + 4, kRrNP = kRrUJ * kRrU
 constexpr int kRrPer = (kRrNP + kRrT - 1) / kRrT;  // region points per thread
 static_assert(kRrCJ * kRrCK == kRrT, "one coarse column per thread");
 
+template <bool RHO>
 __global__ __launch_bounds__(kRrT) void k_fr_rr(const double *__restrict__ u,
-                                                const double *__restrict__ s, FrLevel L,
-                                                double K, int ne, int cic,
+                                                const double *__restrict__ s,
+                                                const float *__restrict__ rho,
+                                                const double *__restrict__ mean, double cA,
+                                                FrLevel L, double K, int ne, int cic,
                                                 double *__restrict__ u0,
                                                 double *__restrict__ uH,
                                                 double *__restrict__ sH) {
@@ -489,6 +521,12 @@ __global__ __launch_bounds__(kRrT) void k_fr_rr(const double *__restrict__ u,
   double au[3] = {0.0, 0.0, 0.0}, ad[3] = {0.0, 0.0, 0.0};  // coarse planes, slot I mod 3
   // fine planes restricted: 2 I0 - 1 .. 2 (I0 + cic), i.e. [pbeg, pend)
   const int pbeg = 2 * I0 - 1, pend = 2 * (I0 + cic) + 1;
+  // RHO: the finest grid's s formed from the density (fr_source) when a plane moves into
+  // place, the loads kept in flight as loaded
+  const double mv = RHO ? mean[0] : 0.0;
+  float rn[kRrPer];
+#pragma unroll
+  for (int v = 0; v < kRrPer; ++v) rn[v] = 0.0f;
   auto plane_of = [&](int q) { return (size_t)(((q % n) + n) % n) * nn; };
   auto prefetch = [&](int q) {  // u of plane q, s of plane q - 1
     const size_t pu = plane_of(q), ps = plane_of(q - 1);
@@ -496,7 +534,10 @@ __global__ __launch_bounds__(kRrT) void k_fr_rr(const double *__restrict__ u,
     for (int v = 0; v < kRrPer; ++v)
       if (rj[v] >= 0) {
         nu[v] = u[pu + col[v]];
-        sn[v] = s[ps + col[v]];
+        if constexpr (RHO)
+          rn[v] = rho[ps + col[v]];
+        else
+          sn[v] = s[ps + col[v]];
       }
   };
   constexpr double w[4] = {0.125, 0.375, 0.375, 0.125};
@@ -508,7 +549,7 @@ __global__ __launch_bounds__(kRrT) void k_fr_rr(const double *__restrict__ u,
       um[v] = uc[v];
       uc[v] = up[v];
       up[v] = nu[v];  // u of plane t
-      sc[v] = sn[v];  // s of plane t - 1
+      sc[v] = RHO ? fr_source(rn[v], mv, cA, K) : sn[v];  // s of plane t - 1
     }
     if (t < pend) prefetch(t + 1);
     const int su = ((t % 3) + 3) % 3;
@@ -738,7 +779,7 @@ __global__ __launch_bounds__(kFrThreads) void k_fr_source(const float *__restric
                                                           double *__restrict__ s) {
   const int64_t c = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kFrThreads + threadIdx.x;
   if (c >= count) return;
-  s[c] = -cA * ((double)rho[c] - mean[0]) - K;
+  s[c] = fr_source(rho[c], mean[0], cA, K);
 }
 
 __global__ __launch_bounds__(kFrThreads) void k_fill_d(double *__restrict__ x, double v,
@@ -820,6 +861,10 @@ struct FrRun {
   double fbar, K;
   int ne;
   hipStream_t s;
+  // non-null: the finest grid reads the density in place of its s (streaming levels)
+  const float *rho0 = nullptr;
+  const double *mean0 = nullptr;
+  double cA = 0.0;
 
   FrLevel level(int l) const {
     const int n = ctx->fr_lev[l].n;
@@ -878,11 +923,17 @@ struct FrRun {
     int ci = n;
     while (ci / 2 >= 16 && tiles * (n / ci) < 512 && n % (ci / 2) == 0) ci /= 2;
     const dim3 grid(n / kFsSK, n / kFsSJ, n / ci);
+    const float *src = l == 0 ? rho0 : nullptr;
     if (l == 0) pm_kt_begin(ctx, PM_KERNEL_FR_SWEEP, s);
-    if (ne == 1)
-      k_fr_sweep_stream<1><<<grid, kFsNT, 0, s>>>(in, out, ctx->fr_lev[l].s, L, ci, first);
+    const double *sv = ctx->fr_lev[l].s;
+    if (ne == 1 && src)
+      k_fr_sweep_stream<1, true><<<grid, kFsNT, 0, s>>>(in, out, sv, src, mean0, cA, K, L, ci, first);
+    else if (ne == 1)
+      k_fr_sweep_stream<1, false><<<grid, kFsNT, 0, s>>>(in, out, sv, src, mean0, cA, K, L, ci, first);
+    else if (src)
+      k_fr_sweep_stream<2, true><<<grid, kFsNT, 0, s>>>(in, out, sv, src, mean0, cA, K, L, ci, first);
     else
-      k_fr_sweep_stream<2><<<grid, kFsNT, 0, s>>>(in, out, ctx->fr_lev[l].s, L, ci, first);
+      k_fr_sweep_stream<2, false><<<grid, kFsNT, 0, s>>>(in, out, sv, src, mean0, cA, K, L, ci, first);
     if (l == 0) pm_kt_end(ctx, PM_KERNEL_FR_SWEEP, s, 32.0 * (double)n * n * n);
     return hipGetLastError();
   }
@@ -926,7 +977,12 @@ struct FrRun {
       int cic = C.n;
       while (cic / 2 >= 8 && tiles * (C.n / cic) < 2048 && C.n % (cic / 2) == 0) cic /= 2;
       const dim3 grid(C.n / kRrCK, C.n / kRrCJ, C.n / cic);
-      k_fr_rr<<<grid, kRrT, 0, s>>>(cur, ctx->fr_lev[l].s, L, K, ne, cic, C.u0, C.u, C.s);
+      if (l == 0 && rho0)
+        k_fr_rr<true><<<grid, kRrT, 0, s>>>(cur, ctx->fr_lev[l].s, rho0, mean0, cA, L, K, ne, cic,
+                                            C.u0, C.u, C.s);
+      else
+        k_fr_rr<false><<<grid, kRrT, 0, s>>>(cur, ctx->fr_lev[l].s, nullptr, mean0, cA, L, K, ne,
+                                             cic, C.u0, C.u, C.s);
     } else {
       double *d = ctx->fr_lev[l].d;
       k_fr_residual<<<blocks(cells), kFrThreads, 0, s>>>(cur, ctx->fr_lev[l].s, L, K, ne, d);
@@ -1038,9 +1094,19 @@ int pm_fr_solve(pm_ctx *ctx, const float *rho, double a, const pm_step_params *p
   pm_fr_constants(p, a, &run.fbar, &run.K, &cA);
   // the density's mean in FP64 (red_result[2])
   PM_HIP(ctx, launch_sum_moments(rho, cells, ctx->red_partial, ctx->red_result, nullptr, s));
-  k_fr_source<<<blocks(cells), kFrThreads, 0, s>>>(rho, ctx->red_result + 2, cells, cA, run.K,
-                                                   ctx->fr_lev[0].s);
-  PM_HIP(ctx, hipGetLastError());
+  // a streaming finest grid (its passes read rho in pairs: 8-byte aligned) forms s from
+  // the density where it needs it; s itself is written only for the other passes and for
+  // the residual norms
+  if (run.streams(0, u) && (reinterpret_cast<uintptr_t>(rho) & 7) == 0) {
+    run.rho0 = rho;
+    run.mean0 = ctx->red_result + 2;
+    run.cA = cA;
+  }
+  if (!run.rho0 || relres) {
+    k_fr_source<<<blocks(cells), kFrThreads, 0, s>>>(rho, ctx->red_result + 2, cells, cA, run.K,
+                                                     ctx->fr_lev[0].s);
+    PM_HIP(ctx, hipGetLastError());
+  }
   if (relres) PM_HIP(ctx, run.norms(u, ctx->red_result));
   if (relres) PM_HIP(ctx, hipMemcpyAsync(ctx->host_result + 2, ctx->red_result, 2 * sizeof(double),
                                          hipMemcpyDeviceToHost, s));

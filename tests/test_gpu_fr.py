@@ -48,7 +48,10 @@ def _fr_params(lib, f0, n_exp, box, **kw):
 @pytest.mark.parametrize("n,n_exp,cycle,cycles,f0", [
     (32, 1, "F", 1, -1e-5), (32, 2, "F", 1, -1e-5), (48, 1, "F", 2, -1e-6),
     (64, 1, "V", 2, -1e-5), (64, 2, "W", 1, -1e-6), (128, 1, "F", 1, -1e-6),
-    (128, 2, "F", 1, -1e-6), (256, 1, "F", 1, -1e-6), (256, 2, "V", 1, -1e-6)])
+    (128, 2, "F", 1, -1e-6), (256, 1, "F", 1, -1e-6), (256, 2, "V", 1, -1e-6),
+    # f_R0 = -1e-8: q of order -66 and p > 0 in every cell (the cubic's one-real-root
+    # form with a positive p)
+    (32, 1, "F", 1, -1e-8), (32, 2, "F", 1, -1e-8)])
 def test_scalaron_solve_parity(lib, n, n_exp, cycle, cycles, f0):
     rho = _lognormal(n, 1.0, 30 + n + n_exp)
     a = 0.5
