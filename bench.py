@@ -446,7 +446,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 512 MiB device copy (HBM counter calibration)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the adjoint and batched-ensemble measurements")
+                    help="skip the adjoint, batched-ensemble, FFT and f(R) measurements")
     ap.add_argument("--only", choices=["adjoint", "batched", "fft", "fr"], default=None,
                     help="run only one of the extra measurements and print its JSON object")
     args = ap.parse_args()
@@ -635,6 +635,10 @@ def main():
         out["adjoint"] = bench_adjoint()
         _log("batched ensemble (96 boxes, 20 steps) ...")
         out["batched"] = bench_batched()
+        _log("FFT solvers (256^3) ...")
+        out["fft"] = bench_fft()
+        _log("f(R) scalaron (512^3 FAS F cycle, 256^3 steps) ...")
+        out["fr"] = bench_fr()
     if not args.no_cpu_baseline:
         _log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline()
