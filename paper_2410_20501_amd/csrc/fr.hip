@@ -485,12 +485,12 @@ constexpr int kRrUJ = 2 * kRrCJ + 4, kRrUK = 2 * kRrCK + 4, kRrNP = kRrUJ * kRrU
 constexpr int kRrPer = (kRrNP + kRrT - 1) / kRrT;  // region points per thread
 static_assert(kRrCJ * kRrCK == kRrT, "one coarse column per thread");
 
-template <bool RHO>
+template <int NE, bool RHO>
 __global__ __launch_bounds__(kRrT) void k_fr_rr(const double *__restrict__ u,
                                                 const double *__restrict__ s,
                                                 const float *__restrict__ rho,
                                                 const double *__restrict__ mean, double cA,
-                                                FrLevel L, double K, int ne, int cic,
+                                                FrLevel L, double K, int cic,
                                                 double *__restrict__ u0,
                                                 double *__restrict__ uH,
                                                 double *__restrict__ sH) {
@@ -570,10 +570,10 @@ __global__ __launch_bounds__(kRrT) void k_fr_rr(const double *__restrict__ u,
         if (a < 1 || a >= kRrUJ - 1 || b < 1 || b >= kRrUK - 1) continue;
         const int e = a * kRrUK + b;
         const double c = uc[v];
-        const double nb = pow_n1(um[v], ne) + pow_n1(up[v], ne) + pow_n1(lu[e - kRrUK], ne) +
-                          pow_n1(lu[e + kRrUK], ne) + pow_n1(lu[e - 1], ne) +
-                          pow_n1(lu[e + 1], ne);
-        const double op = L.a_op * (nb - 6.0 * pow_n1(c, ne)) - K / c;
+        const double nb = pow_n1(um[v], NE) + pow_n1(up[v], NE) + pow_n1(lu[e - kRrUK], NE) +
+                          pow_n1(lu[e + kRrUK], NE) + pow_n1(lu[e - 1], NE) +
+                          pow_n1(lu[e + 1], NE);
+        const double op = L.a_op * (nb - 6.0 * pow_n1(c, NE)) - K / c;
         ld[e] = sc[v] - op;
       }
     }
@@ -977,12 +977,16 @@ struct FrRun {
       int cic = C.n;
       while (cic / 2 >= 8 && tiles * (C.n / cic) < 2048 && C.n % (cic / 2) == 0) cic /= 2;
       const dim3 grid(C.n / kRrCK, C.n / kRrCJ, C.n / cic);
-      if (l == 0 && rho0)
-        k_fr_rr<true><<<grid, kRrT, 0, s>>>(cur, ctx->fr_lev[l].s, rho0, mean0, cA, L, K, ne, cic,
-                                            C.u0, C.u, C.s);
+      const double *sv = ctx->fr_lev[l].s;
+      const float *src = l == 0 ? rho0 : nullptr;
+      if (ne == 1 && src)
+        k_fr_rr<1, true><<<grid, kRrT, 0, s>>>(cur, sv, src, mean0, cA, L, K, cic, C.u0, C.u, C.s);
+      else if (ne == 1)
+        k_fr_rr<1, false><<<grid, kRrT, 0, s>>>(cur, sv, src, mean0, cA, L, K, cic, C.u0, C.u, C.s);
+      else if (src)
+        k_fr_rr<2, true><<<grid, kRrT, 0, s>>>(cur, sv, src, mean0, cA, L, K, cic, C.u0, C.u, C.s);
       else
-        k_fr_rr<false><<<grid, kRrT, 0, s>>>(cur, ctx->fr_lev[l].s, nullptr, mean0, cA, L, K, ne,
-                                             cic, C.u0, C.u, C.s);
+        k_fr_rr<2, false><<<grid, kRrT, 0, s>>>(cur, sv, src, mean0, cA, L, K, cic, C.u0, C.u, C.s);
     } else {
       double *d = ctx->fr_lev[l].d;
       k_fr_residual<<<blocks(cells), kFrThreads, 0, s>>>(cur, ctx->fr_lev[l].s, L, K, ne, d);
