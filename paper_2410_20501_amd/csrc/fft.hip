@@ -14,7 +14,8 @@
 //   D  columns along j, inverse
 //   E  rows along k, half complex -> real
 // (FULL_FFT: C stores G F; then per force component the i pass multiplies by -i k_d
-// and inverts into a second spectrum, followed by D and E.)
+// and inverts into a spectrum of its own, followed by D; one E pass over the three
+// spectra writes whole (x, y, z) cells.)
 // The 1D transforms are Stockham autosort radix-4 (+ one radix-2) stages
 // with twiddles from a table computed in FP64 on the device.
 #include <cmath>
@@ -159,43 +160,51 @@ __global__ __launch_bounds__(FT) void k_rows_r2c(const float *__restrict__ x,
 // Pass E: X[0..n/2] -> x[0..n). Z~_k = (X_k + conj X_{n/2-k}) + i conj(w^k) (X_k - conj X_{n/2-k}),
 // z = unnormalised inverse FFT_{n/2}(Z~) = n (x_{2m} + i x_{2m+1}); the 1/n^3 is in G.
 // The output element of row r and position m goes to x[(r n + m) * stride + comp]
-// (stride 1: a scalar grid; stride 3: one component of a vector grid).
-__global__ __launch_bounds__(FT) void k_rows_c2r(const float2 *__restrict__ spec,
+// (stride 1: a scalar grid; stride 3: one component of a vector grid). With ncomp > 1
+// the block also takes the same rows of the next spectra (cstride elements apart) into
+// components comp + 1 ..: the components of a cell are written close together in time,
+// so the interleaved grid's cache lines are whole when they leave L2.
+__global__ __launch_bounds__(FT) void k_rows_c2r(const float2 *__restrict__ spec0,
                                                  float *__restrict__ x, int n, int P,
                                                  const float2 *__restrict__ tw, int stride,
-                                                 int comp) {
+                                                 int comp0, int ncomp, int64_t cstride) {
   __shared__ float2 buf[TL];
   const int L = n / 2, T = TL / L;
   const int64_t rows = (int64_t)n * n;
   const int64_t row0 = (int64_t)blockIdx.x * T;
-  for (int e = threadIdx.x; e < TL; e += FT) {
-    const int col = e / L, k = e % L;
-    const int64_t row = row0 + col;
-    float2 z = make_float2(0.f, 0.f);
-    if (row < rows) {
-      const float2 xk = spec[row * P + k];
-      const float2 xm = conjf2(spec[row * P + (L - k)]);
-      const float2 Et = cadd(xk, xm);
-      const float2 Ot = cmul(conjf2(tw[k]), csub(xk, xm));
-      z = make_float2(Et.x - Ot.y, Et.y + Ot.x);  // Et + i Ot
-    }
-    buf[e] = z;
-  }
-  __syncthreads();
-  lds_fft<true, true>(buf, L, T, tw, 2);
-  if (stride == 1) {
+  for (int d = 0; d < ncomp; ++d) {
+    const float2 *__restrict__ spec = spec0 + d * cstride;
+    const int comp = comp0 + d;
+    if (d > 0) __syncthreads();  // the previous component's reads of buf are done
     for (int e = threadIdx.x; e < TL; e += FT) {
-      const int col = e / L, m = e % L;
+      const int col = e / L, k = e % L;
       const int64_t row = row0 + col;
-      if (row < rows) reinterpret_cast<float2 *>(x + row * n)[m] = buf[e];
-    }
-  } else {
-    for (int e = threadIdx.x; e < 2 * TL; e += FT) {
-      const int col = e / n, m = e % n;   // m: real position along the row
-      const int64_t row = row0 + col;
+      float2 z = make_float2(0.f, 0.f);
       if (row < rows) {
-        const float2 v = buf[col * L + (m >> 1)];
-        x[(row * n + m) * stride + comp] = (m & 1) ? v.y : v.x;
+        const float2 xk = spec[row * P + k];
+        const float2 xm = conjf2(spec[row * P + (L - k)]);
+        const float2 Et = cadd(xk, xm);
+        const float2 Ot = cmul(conjf2(tw[k]), csub(xk, xm));
+        z = make_float2(Et.x - Ot.y, Et.y + Ot.x);  // Et + i Ot
+      }
+      buf[e] = z;
+    }
+    __syncthreads();
+    lds_fft<true, true>(buf, L, T, tw, 2);
+    if (stride == 1) {
+      for (int e = threadIdx.x; e < TL; e += FT) {
+        const int col = e / L, m = e % L;
+        const int64_t row = row0 + col;
+        if (row < rows) reinterpret_cast<float2 *>(x + row * n)[m] = buf[e];
+      }
+    } else {
+      for (int e = threadIdx.x; e < 2 * TL; e += FT) {
+        const int col = e / n, m = e % n;   // m: real position along the row
+        const int64_t row = row0 + col;
+        if (row < rows) {
+          const float2 v = buf[col * L + (m >> 1)];
+          x[(row * n + m) * stride + comp] = (m & 1) ? v.y : v.x;
+        }
       }
     }
   }
@@ -475,55 +484,60 @@ __global__ __launch_bounds__(FT) void k_rows_r2c256(const float *__restrict__ x,
 }
 
 // k_rows_c2r for n = 256 with the register transform
-__global__ __launch_bounds__(FT) void k_rows_c2r256(const float2 *__restrict__ spec,
+__global__ __launch_bounds__(FT) void k_rows_c2r256(const float2 *__restrict__ spec0,
                                                     float *__restrict__ x, int P,
                                                     const float2 *__restrict__ tw, int stride,
-                                                    int comp) {
+                                                    int comp0, int ncomp, int64_t cstride) {
   constexpr int n = 256, L = 128, T = 32;
   __shared__ float2 buf[T * kRowPitch128];
   const int64_t rows = (int64_t)n * n;
   const int64_t row0 = (int64_t)blockIdx.x * T;
-  // the rows' half spectra (L + 1 values each) read once, coalesced, then Z~ formed from
-  // X_k and X_{L-k} in LDS
-  for (int e = threadIdx.x; e < T * (L + 1); e += FT) {
-    const int col = e / (L + 1), k = e % (L + 1);
-    const int64_t row = row0 + col;
-    buf[col * kRowPitch128 + k] = row < rows ? spec[row * P + k] : make_float2(0.f, 0.f);
-  }
-  __syncthreads();
-  constexpr int kPer = T * L / FT;
-  float2 z[kPer];
-#pragma unroll
-  for (int it = 0; it < kPer; ++it) {
-    const int e = threadIdx.x + it * FT, col = e / L, k = e % L;
-    const float2 *b = buf + col * kRowPitch128;
-    const float2 xk = b[k];
-    const float2 xm = conjf2(b[L - k]);
-    const float2 Et = cadd(xk, xm);
-    const float2 Ot = cmul(conjf2(tw[k]), csub(xk, xm));
-    z[it] = make_float2(Et.x - Ot.y, Et.y + Ot.x);  // Et + i Ot
-  }
-  __syncthreads();
-#pragma unroll
-  for (int it = 0; it < kPer; ++it) {
-    const int e = threadIdx.x + it * FT, col = e / L, k = e % L;
-    buf[col * kRowPitch128 + k] = z[it];
-  }
-  __syncthreads();
-  fft128_rows<true>(buf, tw);
-  if (stride == 1) {
-    for (int e = threadIdx.x; e < T * L; e += FT) {
-      const int col = e / L, m = e % L;
+  for (int d = 0; d < ncomp; ++d) {
+    const float2 *__restrict__ spec = spec0 + d * cstride;
+    const int comp = comp0 + d;
+    if (d > 0) __syncthreads();  // the previous component's reads of buf are done
+    // the rows' half spectra (L + 1 values each) read once, coalesced, then Z~ formed from
+    // X_k and X_{L-k} in LDS
+    for (int e = threadIdx.x; e < T * (L + 1); e += FT) {
+      const int col = e / (L + 1), k = e % (L + 1);
       const int64_t row = row0 + col;
-      if (row < rows) reinterpret_cast<float2 *>(x + row * n)[m] = buf[col * kRowPitch128 + m];
+      buf[col * kRowPitch128 + k] = row < rows ? spec[row * P + k] : make_float2(0.f, 0.f);
     }
-  } else {
-    for (int e = threadIdx.x; e < 2 * T * L; e += FT) {
-      const int col = e / n, m = e % n;  // m: real position along the row
-      const int64_t row = row0 + col;
-      if (row < rows) {
-        const float2 v = buf[col * kRowPitch128 + (m >> 1)];
-        x[(row * n + m) * stride + comp] = (m & 1) ? v.y : v.x;
+    __syncthreads();
+    constexpr int kPer = T * L / FT;
+    float2 z[kPer];
+  #pragma unroll
+    for (int it = 0; it < kPer; ++it) {
+      const int e = threadIdx.x + it * FT, col = e / L, k = e % L;
+      const float2 *b = buf + col * kRowPitch128;
+      const float2 xk = b[k];
+      const float2 xm = conjf2(b[L - k]);
+      const float2 Et = cadd(xk, xm);
+      const float2 Ot = cmul(conjf2(tw[k]), csub(xk, xm));
+      z[it] = make_float2(Et.x - Ot.y, Et.y + Ot.x);  // Et + i Ot
+    }
+    __syncthreads();
+  #pragma unroll
+    for (int it = 0; it < kPer; ++it) {
+      const int e = threadIdx.x + it * FT, col = e / L, k = e % L;
+      buf[col * kRowPitch128 + k] = z[it];
+    }
+    __syncthreads();
+    fft128_rows<true>(buf, tw);
+    if (stride == 1) {
+      for (int e = threadIdx.x; e < T * L; e += FT) {
+        const int col = e / L, m = e % L;
+        const int64_t row = row0 + col;
+        if (row < rows) reinterpret_cast<float2 *>(x + row * n)[m] = buf[col * kRowPitch128 + m];
+      }
+    } else {
+      for (int e = threadIdx.x; e < 2 * T * L; e += FT) {
+        const int col = e / n, m = e % n;  // m: real position along the row
+        const int64_t row = row0 + col;
+        if (row < rows) {
+          const float2 v = buf[col * kRowPitch128 + (m >> 1)];
+          x[(row * n + m) * stride + comp] = (m & 1) ? v.y : v.x;
+        }
       }
     }
   }
@@ -593,22 +607,25 @@ hipError_t fft_run(const FftBufs &b, int n, const float *rho, const float *mean,
     launch_cols<0, 1>(col_grid, s, spec, spec, n, P, b.twiddle, b.tab, scale, 0);
     launch_cols<1, 2>(col_grid, s, spec, spec, n, P, b.twiddle, b.tab, scale, 0);
     if (n == 256 && Trow == 32)
-      k_rows_c2r256<<<row_blocks, FT, 0, s>>>(spec, out, P, b.twiddle, 1, 0);
+      k_rows_c2r256<<<row_blocks, FT, 0, s>>>(spec, out, P, b.twiddle, 1, 0, 1, 0);
     else
-      k_rows_c2r<<<row_blocks, FT, 0, s>>>(spec, out, n, P, b.twiddle, 1, 0);
+      k_rows_c2r<<<row_blocks, FT, 0, s>>>(spec, out, n, P, b.twiddle, 1, 0, 1, 0);
     return hipGetLastError();
   }
   // force in Fourier space: spec <- G F once, then per component d the inverse of
-  // -i k_d G F into the second spectrum and one component of the force grid
+  // -i k_d G F along i and j into spectrum d of spec2 (three spectra), and one row pass
+  // over the three writing whole (x, y, z) cells of the force grid
   launch_cols<0, 3>(col_grid, s, spec, spec, n, P, b.twiddle, b.tab, scale, 0);
+  const int64_t elems = (int64_t)fft_spec_elems(n);
   for (int d = 0; d < 3; ++d) {
-    launch_cols<0, 4>(col_grid, s, spec, b.spec2, n, P, b.twiddle, b.tab, scale, d);
-    launch_cols<1, 2>(col_grid, s, b.spec2, b.spec2, n, P, b.twiddle, b.tab, scale, 0);
-    if (n == 256 && Trow == 32)
-      k_rows_c2r256<<<row_blocks, FT, 0, s>>>(b.spec2, out, P, b.twiddle, 3, d);
-    else
-      k_rows_c2r<<<row_blocks, FT, 0, s>>>(b.spec2, out, n, P, b.twiddle, 3, d);
+    float2 *sd = b.spec2 + d * elems;
+    launch_cols<0, 4>(col_grid, s, spec, sd, n, P, b.twiddle, b.tab, scale, d);
+    launch_cols<1, 2>(col_grid, s, sd, sd, n, P, b.twiddle, b.tab, scale, 0);
   }
+  if (n == 256 && Trow == 32)
+    k_rows_c2r256<<<row_blocks, FT, 0, s>>>(b.spec2, out, P, b.twiddle, 3, 0, 3, elems);
+  else
+    k_rows_c2r<<<row_blocks, FT, 0, s>>>(b.spec2, out, n, P, b.twiddle, 3, 0, 3, elems);
   return hipGetLastError();
 }
 
@@ -639,9 +656,9 @@ hipError_t fft_inverse(const FftBufs &b, int n, float *out, int stride, int comp
   launch_cols<0, 2>(col_grid, s, b.spec, b.spec, n, P, b.twiddle, b.tab, 0.0f, 0);
   launch_cols<1, 2>(col_grid, s, b.spec, b.spec, n, P, b.twiddle, b.tab, 0.0f, 0);
   if (n == 256 && Trow == 32)
-    k_rows_c2r256<<<row_blocks, FT, 0, s>>>(b.spec, out, P, b.twiddle, stride, comp);
+    k_rows_c2r256<<<row_blocks, FT, 0, s>>>(b.spec, out, P, b.twiddle, stride, comp, 1, 0);
   else
-    k_rows_c2r<<<row_blocks, FT, 0, s>>>(b.spec, out, n, P, b.twiddle, stride, comp);
+    k_rows_c2r<<<row_blocks, FT, 0, s>>>(b.spec, out, n, P, b.twiddle, stride, comp, 1, 0);
   return hipGetLastError();
 }
 
@@ -658,7 +675,8 @@ int pm_fft_solve_kind(pm_ctx *ctx, const float *rho, float coef, int deconv, int
       return pm_fail(ctx, PM_ERR_NOMEM, "FFT scratch allocation failed");
   }
   if (kind == PM_FFT_FULL && !ctx->spec2) {
-    if (hipMalloc(&ctx->spec2, sizeof(float2) * elems) != hipSuccess) {
+    // three spectra: one per force component
+    if (hipMalloc(&ctx->spec2, 3 * sizeof(float2) * elems) != hipSuccess) {
       ctx->spec2 = nullptr;
       return pm_fail(ctx, PM_ERR_NOMEM, "FFT scratch allocation failed");
     }

@@ -54,7 +54,7 @@ struct pm_ctx {
                          // FFT solve's input
   // FFT spectrum (lazy)
   void *spec;            // complex float [n][n][fft_pitch(n)]
-  void *spec2;           // second spectrum of the Fourier-space force (lazy)
+  void *spec2;           // three spectra of the Fourier-space force (lazy)
   float2 *twiddle;       // [n] e^{-2 pi i m / n}, m = 0 .. n-1
   float *fft_tab;        // [3n] per-axis tables: k^2 part, window part, k_d
   // counting sort (lazy)
@@ -249,7 +249,7 @@ hipError_t launch_qumond_source(const float *phin, int n, float g0, int family, 
 
 // fft.hip
 struct FftBufs {
-  float2 *spec, *spec2;  // half spectra [n][n][fft_pitch(n)] (spec2: PM_FFT_FULL only)
+  float2 *spec, *spec2;  // half spectra [n][n][fft_pitch(n)] (spec2: three, PM_FFT_FULL only)
   float2 *twiddle;       // [n]
   float *tab;            // [3n]
 };
