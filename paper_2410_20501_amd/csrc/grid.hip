@@ -71,16 +71,47 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Block partials of sum x and sum x^2 over a fixed grid (deterministic order).
+// Block partials of sum x and sum x^2 over a fixed grid (deterministic order). VEC: x
+// 16-byte aligned, read as float4 two at a time (the loads of a thread in flight
+// together); the count % 4 trailing values go to the first threads.
+template <bool VEC>
 __global__ __launch_bounds__(RED_THREADS) void k_moments_partial(const float *__restrict__ x,
                                                                  int64_t count,
                                                                  double *__restrict__ partial) {
   double s1 = 0.0, s2 = 0.0;
   const int64_t stride = (int64_t)gridDim.x * RED_THREADS;
-  for (int64_t i = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; i < count; i += stride) {
-    const double v = x[i];
-    s1 += v;
-    s2 += v * v;
+  const int64_t t = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x;
+  if constexpr (VEC) {
+    const float4 *x4 = reinterpret_cast<const float4 *>(x);
+    const int64_t c4 = count / 4;
+    int64_t i = t;
+    for (; i + stride < c4; i += 2 * stride) {
+      const float4 a = x4[i], b = x4[i + stride];
+      for (const float v : {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w}) {
+        const double d = v;
+        s1 += d;
+        s2 += d * d;
+      }
+    }
+    if (i < c4) {
+      const float4 a = x4[i];
+      for (const float v : {a.x, a.y, a.z, a.w}) {
+        const double d = v;
+        s1 += d;
+        s2 += d * d;
+      }
+    }
+    if (t < count % 4) {
+      const double d = x[4 * c4 + t];
+      s1 += d;
+      s2 += d * d;
+    }
+  } else {
+    for (int64_t i = t; i < count; i += stride) {
+      const double v = x[i];
+      s1 += v;
+      s2 += v * v;
+    }
   }
   __shared__ double l1[RED_THREADS / 64], l2[RED_THREADS / 64];
   s1 = wave_sum(s1);
@@ -209,7 +240,10 @@ hipError_t launch_sum_moments(const float *x, int64_t count, double *partial, do
                               float *mean_out, hipStream_t s) {
   int nb = (int)std::min<int64_t>(RED_BLOCKS, (count + RED_THREADS - 1) / RED_THREADS);
   if (nb < 1) nb = 1;
-  k_moments_partial<<<nb, RED_THREADS, 0, s>>>(x, count, partial);
+  if ((reinterpret_cast<uintptr_t>(x) & 15) == 0)
+    k_moments_partial<true><<<nb, RED_THREADS, 0, s>>>(x, count, partial);
+  else
+    k_moments_partial<false><<<nb, RED_THREADS, 0, s>>>(x, count, partial);
   k_moments_final<<<1, RED_THREADS, 0, s>>>(partial, nb, count, result, mean_out);
   return hipGetLastError();
 }
