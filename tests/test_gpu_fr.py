@@ -73,7 +73,8 @@ def test_scalaron_solve_parity(lib, n, n_exp, cycle, cycles, f0):
 
 
 @pytest.mark.parametrize("n,n_exp,cycle,pre,post,relres", [
-    (256, 1, "F", 2, 1, True), (320, 2, "F", 2, 1, True), (256, 1, "W", 1, 2, False)])
+    (256, 1, "F", 2, 1, True), (320, 2, "F", 2, 1, True), (256, 1, "W", 1, 2, False),
+    (512, 1, "F", 2, 1, True)])  # the benchmark's size, where no oracle run fits
 def test_streaming_sweep_matches_colour_passes(lib, n, n_exp, cycle, pre, post, relres):
     """Grids of 256 cells per side and more (a multiple of 64) sweep in one streaming pass
     per red-black sweep when u is 16-byte aligned (the finest grid then forms its s from
