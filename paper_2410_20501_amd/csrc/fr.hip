@@ -239,7 +239,7 @@ __global__ __launch_bounds__(kFrThreads) void k_fr_sweep(double *__restrict__ u,
   u[c] = NE == 1 ? root3(p, L.q) : root4(p, L.q);
 }
 
-// One full non-linear red-black sweep per pass over HBM (grids of at least 128 cells per
+// One full non-linear red-black sweep per pass over HBM (grids of at least 256 cells per
 // side, n % 64 == 0): the 2.5D streaming scheme of the linear smoother, in FP64. A block
 // owns a 16 x 64 (j, k) tile plus a 2-cell halo and a chunk of i-planes; each thread holds
 // one pair of k-neighbouring points (opposite colours) of the tile plus halo in a ring of
@@ -471,8 +471,8 @@ __global__ __launch_bounds__(kFrThreads) void k_fr_restrict(const double *__rest
   sH[c] = sd;
 }
 
-// Residual and restriction in one pass over the fine grid (levels of at least 32 cells
-// per side): u0 = uH = R u and sH = R d with d = s - N_h(u), the full weighting of
+// Residual and restriction in one pass over the fine grid (fine grids of at least 256
+// cells per side, the coarse side a multiple of 16): u0 = uH = R u and sH = R d with d = s - N_h(u), the full weighting of
 // k_fr_restrict and the residual of k_fr_residual, without writing d. A block owns a
 // 16 x 16 tile of coarse (J, K) columns and a chunk of coarse planes, and walks through
 // the fine planes once: iteration t publishes u of plane t in LDS, forms d of plane
