@@ -306,7 +306,8 @@ int pm_solve_fft_noalloc(const float *rho, int n, float coef, int deconv, float 
  *   (f~_bar / h^2) [sum of 6 neighbours of u^(n+1) - 6 u^(n+1)] - K / u = s,
  *   K = a^4 R_bar / (3 c~^2),  s = -(Omega_m a / c~^2)(rho - mean rho) - K,
  * which for u given its neighbours is the depressed polynomial u^(n+2) + p u + q = 0
- * solved by the paper's closed forms (cubic for n = 1, quartic for n = 2) in FP64.
+ * solved by the paper's closed forms (cubic for n = 1, quartic for n = 2) in FP64 (the
+ * cubic's forms evaluated in FP32 and polished to FP64 rounding by two Newton steps).
  * Full-approximation-storage cycles (params->fr_cycle, fr_cycles of them) of red-black
  * non-linear Gauss-Seidel (fr_pre sweeps red first, fr_post sweeps black first),
  * full-weighting restriction of u and of the residual, coarse problem
@@ -314,10 +315,14 @@ int pm_solve_fft_noalloc(const float *rho, int n, float coef, int deconv, float 
  * the side exceeds 4 and is a multiple of 4, and the coarsest gets fr_coarse_sweeps
  * sweeps. Uses params->omega_m, omega_l and the fr_ fields.
  * rho: device [n][n][n] density (its mean is measured). u: device FP64 [n][n][n], in =
- * starting guess (all ones for the background), out = the result.
+ * starting guess (all ones for the background), out = the result. Grids of 256 cells per
+ * side and more (a multiple of 64) sweep in one streaming pass per sweep when u is
+ * 16-byte aligned and fr_pre + fr_post is odd, the iterate alternating with a buffer of
+ * the context; otherwise in two colour passes; both give the same bits.
  * relres: host double[2] or NULL; when given, ||s - N(u)||_2 / ||s||_2 before and after
  * the cycles (host synchronisation). Errors: PM_ERR_ARG (bad pointer or parameter),
- * PM_ERR_NOMEM (first call allocates the FAS levels: 32 bytes per cell in total). */
+ * PM_ERR_NOMEM (first call allocates the FAS levels: 32 bytes per cell in total, and
+ * 9 more per cell for the streaming grids' second buffers). */
 int pm_solve_fr(pm_ctx *ctx, const float *rho, double a, const pm_step_params *params,
                 double *u, double *relres, pm_stream stream);
 
