@@ -280,8 +280,9 @@ int pm_solve_fft(pm_ctx *ctx, const float *rho, float coef, int deconv, float *p
  *   PM_FFT_FULL   out = g [n][n][n][3] = -grad phi taken in Fourier space
  *                 (Eq. exact_fullfft_kernel): g_d(k) = i k_d coef rho(k) / (k^2 W^2),
  *                 with k_d = 0 on the Nyquist plane of axis d; deconv as for GREEN.
- * n must be a power of two (8 .. 1024). FULL uses a second spectrum of context
- * scratch (8 bytes per cell, allocated on first use). */
+ * n must be a power of two (8 .. 1024). FULL uses three more spectra of context
+ * scratch (one per force component, about 14 bytes per cell in all, allocated on first
+ * use). */
 int pm_solve_fft_kernel(pm_ctx *ctx, const float *rho, float coef, int kernel, int deconv,
                         float *out, pm_stream stream);
 
